@@ -1,0 +1,222 @@
+"""Oracle for the FSMP sampler: a plain, slow FP64 CPU implementation.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` import this package.  It shares no code with the
+HIP path (``paper_2403_03156_amd``) and never imports it.
+
+* ``fsmp_oracle.c`` (loaded through ctypes): SER evaluation, light curve, the
+  grid prior normaliser, the from-scratch likelihood of App. A (eq. mgauss), the
+  acceptances of Sec. 2.4 and the chain driver with its own Philox4x32-10.
+* ``brute.py``: dense-normal likelihood, the paper's Woodbury form of delta-nu
+  (App. A, eqs. 11-18) and the exact posterior by enumeration on tiny grids.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+PHI_EXP = 0
+PHI_BIEXP = 1
+MOVE_BIRTH, MOVE_DEATH, MOVE_UPDATE = 1, 2, 3
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("ser_mu", ctypes.c_double),
+        ("ser_sigma", ctypes.c_double),
+        ("ser_tau", ctypes.c_double),
+        ("ser_amp", ctypes.c_double),
+        ("ser_support", ctypes.c_int32),
+        ("sub", ctypes.c_int32),
+        ("sigma_eps", ctypes.c_double),
+        ("mu_q", ctypes.c_double),
+        ("sigma_q", ctypes.c_double),
+        ("phi_kind", ctypes.c_int32),
+        ("tau_rise", ctypes.c_double),
+        ("tau_decay", ctypes.c_double),
+        ("t0_min", ctypes.c_double),
+        ("t0_max", ctypes.c_double),
+        ("J", ctypes.c_double),
+        ("t0_sd", ctypes.c_double),
+        ("shift_sd", ctypes.c_double),
+    ]
+
+
+LOGREC_DTYPE = np.dtype(
+    [("move", "<i4"), ("flags", "<i4"), ("j", "<i4"), ("g", "<i4"),
+     ("t0", "<f8"), ("dnu", "<f8"), ("log_alpha", "<f8")], align=True)
+assert LOGREC_DTYPE.itemsize == 40
+
+
+def make_params(ser=(8.0, 1.5, 6.0), ser_amp=1.0, ser_support=0, sub=4, sigma_eps=0.1, mu_q=1.0, sigma_q=0.3,
+                phi_kind=PHI_EXP, tau_rise=0.0, tau_decay=20.0, t0_min=50.0, t0_max=100.0, J=0.25,
+                t0_sd=1.0, shift_sd=1.0) -> Params:
+    return Params(ser[0], ser[1], ser[2], ser_amp, ser_support, sub, sigma_eps, mu_q, sigma_q, phi_kind,
+                  tau_rise, tau_decay, t0_min, t0_max, J, t0_sd, shift_sd)
+
+
+_lib = None
+
+_P = ctypes.POINTER
+_d, _i32, _i64, _u64, _u32 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32
+_vp = ctypes.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build()
+        L = ctypes.CDLL(path)
+        L.ora_philox4x32_10.argtypes = [_vp, _vp, _vp]
+        L.ora_ser_peak_time.argtypes = [_d, _d, _d]
+        L.ora_ser_peak_time.restype = _d
+        L.ora_ser_support_auto.argtypes = [_d, _d, _d]
+        L.ora_ser_support_auto.restype = ctypes.c_int
+        L.ora_ser_value.argtypes = [_P(Params), _d]
+        L.ora_ser_value.restype = _d
+        L.ora_ser_table.argtypes = [_P(Params), _vp, _i32]
+        L.ora_ser_table.restype = _i32
+        L.ora_phi.argtypes = [_P(Params), _d]
+        L.ora_phi.restype = _d
+        L.ora_log_phi.argtypes = [_P(Params), _d]
+        L.ora_log_phi.restype = _d
+        L.ora_phi_sum.argtypes = [_P(Params), _d, _i32, _i32]
+        L.ora_phi_sum.restype = _d
+        L.ora_lambda_T.argtypes = [_P(Params), _d, _d, _i32, _i32]
+        L.ora_lambda_T.restype = _d
+        L.ora_birth_draw.argtypes = [_P(Params), _d, _i32, _i32, _d]
+        L.ora_birth_draw.restype = _i32
+        L.ora_log_likelihood.argtypes = [_P(Params), _vp, _i32, _vp, _i32, _vp]
+        L.ora_log_likelihood.restype = _d
+        L.ora_overlap.argtypes = [_P(Params), _i32, _i32, _i32]
+        L.ora_overlap.restype = _d
+        L.ora_log_alpha.argtypes = [_P(Params), _vp, _i32, _d, _i32, _i32, _d, _vp, _i32, _i32, _i32, _i32, _vp]
+        L.ora_log_alpha.restype = _d
+        L.ora_t0_log_alpha.argtypes = [_P(Params), _d, _i32, _i32, _vp, _i32, _d, _d]
+        L.ora_t0_log_alpha.restype = _d
+        L.ora_run.argtypes = [_P(Params), _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _u64, _i32,
+                              _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32]
+        L.ora_run.restype = ctypes.c_int
+        L.ora_replay.argtypes = [_P(Params), _vp, _i32, _d, _i32, _i32, _i32, _u64, _u64, _i32, _vp, _vp, _vp, _d]
+        L.ora_replay.restype = _i64
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def philox4x32_10(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().ora_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def ser_table(p: Params):
+    cap = 1 << 16
+    out = np.zeros(cap, dtype=np.float64)
+    LV = lib().ora_ser_table(ctypes.byref(p), _ptr(out), cap)
+    return out[: p.sub * LV].copy(), LV
+
+
+def log_likelihood(p: Params, w, z):
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    z = np.ascontiguousarray(z, dtype=np.int32)
+    x = np.zeros(max(len(z), 1), dtype=np.float64)
+    v = lib().ora_log_likelihood(ctypes.byref(p), _ptr(w), len(w), _ptr(z), len(z), _ptr(x))
+    return v, x[: len(z)]
+
+
+def log_alpha(p, w, lam, glo, ghi, t0, z, move, j, gnew):
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    z = np.ascontiguousarray(z, dtype=np.int32)
+    dnu = ctypes.c_double(0.0)
+    zz = z if len(z) else np.zeros(1, np.int32)
+    la = lib().ora_log_alpha(ctypes.byref(p), _ptr(w), len(w), lam, glo, ghi, t0, _ptr(zz), len(z), move, j, gnew,
+                             ctypes.byref(dnu))
+    return la, dnu.value
+
+
+def t0_log_alpha(p, lam, glo, ghi, z, t0, t0p):
+    z = np.ascontiguousarray(z, dtype=np.int32)
+    zz = z if len(z) else np.zeros(1, np.int32)
+    return lib().ora_t0_log_alpha(ctypes.byref(p), lam, glo, ghi, _ptr(zz), len(z), t0, t0p)
+
+
+class RunResult:
+    pass
+
+
+def run(p: Params, wave, offsets, lam, n_chains, n_steps, burn_in, seed, kz, kmax=None, g_range=None, t0_init=None,
+        wave_id=None, log=False, thin=0, n_threads=0):
+    """Run ``n_chains`` chains per waveform; outputs are per chain (index wave*n_chains + chain)."""
+    wave = np.ascontiguousarray(wave, dtype=np.float32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    nw = len(offsets) - 1
+    tot = nw * n_chains
+    kmax = None if kmax is None else np.ascontiguousarray(kmax, dtype=np.int32)
+    g_range = None if g_range is None else np.ascontiguousarray(g_range, dtype=np.int32).reshape(-1)
+    t0_init = None if t0_init is None else np.ascontiguousarray(t0_init, dtype=np.float64)
+    wave_id = None if wave_id is None else np.ascontiguousarray(wave_id, dtype=np.uint64)
+    r = RunResult()
+    r.N = np.zeros(tot, np.int32)
+    r.t0 = np.zeros(tot, np.float64)
+    r.z = np.zeros((tot, kz), np.int32)
+    r.x = np.zeros((tot, kz), np.float64)
+    r.acc = np.zeros((tot, 12), np.float64)
+    r.nhist = np.zeros((tot, kz + 1), np.int32)
+    r.counts = np.zeros((tot, 8), np.int32)
+    r.status = np.zeros(tot, np.uint32)
+    r.log = np.zeros((tot, n_steps), LOGREC_DTYPE) if log else None
+    n_rec = (n_steps - burn_in + thin - 1) // thin if (thin > 0 and n_steps > burn_in) else 0
+    r.trace = np.zeros((tot, n_rec, 3), np.float64) if n_rec else None
+    lib().ora_run(ctypes.byref(p), nw, _ptr(wave), _ptr(offsets), _ptr(lam), _ptr(kmax), _ptr(g_range),
+                  _ptr(t0_init), _ptr(wave_id), n_chains, n_steps, burn_in, seed, kz, _ptr(r.N), _ptr(r.t0),
+                  _ptr(r.z), _ptr(r.x), _ptr(r.acc), _ptr(r.nhist), _ptr(r.counts), _ptr(r.status), _ptr(r.log),
+                  _ptr(r.trace), thin, n_threads)
+    return r
+
+
+def replay(p: Params, w, lam, kmax, glo, ghi, uid, seed, rec, tie_eps=1e-9):
+    """Recompute delta-nu / log-alpha along a recorded log of one chain.
+
+    Returns (dnu_ref, la_ref, n_decision_mismatches)."""
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    rec = np.ascontiguousarray(rec, dtype=LOGREC_DTYPE)
+    n = len(rec)
+    dnu = np.zeros(n, np.float64)
+    la = np.zeros(n, np.float64)
+    bad = lib().ora_replay(ctypes.byref(p), _ptr(w), len(w), lam, kmax, glo, ghi, uid, seed, n, _ptr(rec),
+                           _ptr(dnu), _ptr(la), tie_eps)
+    return dnu, la, int(bad)
+
+
+def summarize(acc, n_steps, burn_in, n_chains):
+    """Posterior mean / variance / MCSE of (N, Q, t0) per waveform from the per-chain accumulators
+    (batch means with floor(sqrt(S)) batches per chain, pooled over chains)."""
+    acc = np.asarray(acc).reshape(-1, n_chains, 12)
+    S = n_steps - burn_in
+    nb = int(np.floor(np.sqrt(S)))
+    lb = S // nb
+    out = {}
+    for a, name in enumerate(("N", "Q", "t0")):
+        s1 = acc[:, :, 2 * a].sum(1)
+        s2 = acc[:, :, 2 * a + 1].sum(1)
+        n = S * n_chains
+        mean = s1 / n
+        var = np.maximum(s2 / n - mean ** 2, 0.0)
+        bsum = acc[:, :, 6 + 2 * a].sum(1)
+        bsq = acc[:, :, 7 + 2 * a].sum(1)
+        B = nb * n_chains
+        bm_mean = bsum / (B * lb)
+        bm_var = np.maximum((bsq / lb ** 2 - B * bm_mean ** 2) / max(B - 1, 1), 0.0)
+        out[name] = (mean, var, np.sqrt(bm_var / B))
+    return out
