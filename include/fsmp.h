@@ -1,0 +1,236 @@
+/*
+ * fsmp.h -- C ABI of libfsmp.so: batched reversible-jump MCMC over the photo-electron
+ * (PE) sequences of PMT waveforms, the Fast Stochastic Matching Pursuit (FSMP) of
+ * Xu et al., "The Fast Stochastic Matching Pursuit for Neutrino and Dark Matter
+ * Experiments", run in HIP kernels on one MI355X (gfx950).
+ *
+ * Problem (Sec. 1 eq. waveform; Sec. 2.1-2.2): a waveform w of L_w samples at
+ * 1 sample per ns is  w(t) = sum_i q_i V(t - t_i) + eps(t),  eps ~ N(0, sigma_eps^2)
+ * white; V is an ex-Gaussian single-electron response (Sec. 3); the charges are
+ * q_i ~ N(mu_q, sigma_q^2) and are integrated out (App. A, eq. mgauss); the PE times
+ * z = {t_i} follow a Poisson point process of intensity lambda0 * phi(t - t0)
+ * (eq. pzmu).  The library samples z and t0 by a Gibbs sweep: t0 by
+ * Metropolis-Hastings, then one birth / death / update jump of z (Sec. 2.4,
+ * eqs. birth, death, update, delta-nu), with J = 1/4 and the empty-sequence rule.
+ *
+ * Conventions shared by every entry point
+ *   - times are in samples (ns at 1 GS/s); PE times live on the grid t = g / grid_sub
+ *     with integer g; the solution space T of a waveform is a range [g_lo, g_hi]
+ *     inside [0, grid_sub * L_w - 1] (default: the whole window).
+ *   - the target is the grid-binned Poisson process on T with normaliser
+ *     exp(-Lambda_T(t0)), Lambda_T(t0) = lambda0 / grid_sub * sum_{g in T} phi(g / grid_sub - t0),
+ *     truncated at K_max PEs (a birth at K_max is rejected and flagged).
+ *   - the t0 prior is uniform on [t0_min, t0_max].
+ *   - every chain draws its random numbers from Philox4x32-10 (Salmon et al., SC'11)
+ *     with key (seed lo, seed hi) and counter (step, block, uid lo, uid hi),
+ *     uid = wave_id * n_chains + chain: a chain's result does not depend on the batch
+ *     it runs in, on the launch shape or on the other chains.
+ *   - pointers marked "device" are HIP device memory of the context's device; pointers
+ *     marked "host" are ordinary host memory read during the call.  The caller owns every
+ *     buffer it passes; the context owns its tables and workspace.
+ *   - work is enqueued on the HIP stream passed as `hip_stream` (NULL = the null stream);
+ *     outputs are valid once that stream has reached the end of the call's work.
+ *   - a function that fails returns a negative fsmp_status and leaves a message for
+ *     fsmp_last_error(); problems of single waveforms do not fail a call: they set bits in
+ *     that chain's status word (FSMP_ST_*).
+ *   - one context serves one host thread at a time.
+ */
+#ifndef FSMP_H
+#define FSMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FSMP_OK = 0,
+  FSMP_EINVAL = -1,   /* invalid argument (message in fsmp_last_error) */
+  FSMP_ENOMEM = -2,   /* device or host allocation failed */
+  FSMP_EDEVICE = -3,  /* HIP runtime error or no usable gfx950 device */
+  FSMP_ENOTSUP = -4,  /* valid request this build does not provide (e.g. K_max above the largest kernel) */
+  FSMP_EBUSY = -5     /* reserved */
+} fsmp_status;
+
+enum { FSMP_PHI_EXP = 0, FSMP_PHI_BIEXP = 1 };
+enum { FSMP_FP64 = 0, FSMP_FP32_REFRESH = 1 };
+
+/* record_flags */
+enum {
+  FSMP_REC_TRACE = 1u, /* per recorded step (N, t0, Q) into fsmp_samples.trace */
+  FSMP_REC_LOG = 2u    /* one fsmp_logrec per step into fsmp_samples.log (for replay checks) */
+};
+
+/* per-chain status bits */
+enum {
+  FSMP_ST_KMAX = 1u,      /* a birth was rejected because N reached K_max */
+  FSMP_ST_NONFINITE = 2u, /* the waveform holds a NaN or an infinity: the chain did not run */
+  FSMP_ST_DRIFT = 4u,     /* FP32 form: refresh found drift above the bound */
+  FSMP_ST_EMPTY_T = 8u,   /* empty solution space: no birth is possible */
+  FSMP_ST_FACTOR = 16u    /* a Schur complement was not positive: proposal rejected */
+};
+
+/* Single-electron response (Sec. 3, ex-Gaussian): V(t) = A f(t) / max f, with f the
+ * ex-Gaussian density of a N(mu, sigma^2) shifted by an Exp(mean tau) (the paper's form
+ * has mu = 4 sigma); V = 0 outside [0, support).  support = 0 picks the smallest multiple
+ * of 16 samples beyond which V / A < 1e-6.  amplitude = 0 switches the data term off
+ * (every delta-nu is exactly 0: the sampler then draws from the prior). */
+typedef struct {
+  double mu, sigma, tau; /* ns, sigma > 0, tau > 0 */
+  double amplitude;      /* peak height; 1 = peak normalised */
+  int32_t support;       /* samples, 0 = automatic, at most 512 */
+} fsmp_ser;
+
+/* Light curve phi (Sec. 3): EXP  phi(t) = e^{-t/tau_decay} / tau_decay;
+ * BIEXP phi(t) = (tau_rise + tau_decay) / tau_decay^2 (1 - e^{-t/tau_rise}) e^{-t/tau_decay};
+ * phi(t) = 0 for t < 0.  t0 has the uniform prior [t0_min, t0_max] (eq. t0prior);
+ * t0_min == t0_max fixes t0. */
+typedef struct {
+  int32_t kind;
+  double tau_rise, tau_decay;
+  double t0_min, t0_max;
+} fsmp_intensity;
+
+/* Sampler settings.  Charge model N(mu_q, sigma_q^2) (Sec. 2.1); noise sigma_eps; grid
+ * step 1 / grid_sub samples; jump probabilities J, J, 1 - 2J (Sec. 2.4); t0 random-walk
+ * step N(0, t0_step_sd^2) and update shift N(0, shift_sd^2) rounded to the grid.
+ * Steps [0, burn_in) are not recorded; accumulators use floor(sqrt(n_steps - burn_in))
+ * batches for the batch-means MCSE.  precision: FSMP_FP64 (all FP64) or
+ * FSMP_FP32_REFRESH (FP32 rank-one updates, FP64 refresh every refresh_M steps). */
+typedef struct {
+  double sigma_eps, mu_q, sigma_q;
+  int32_t grid_sub;      /* 1..16 */
+  double jump_J;         /* 0 < J < 1/2 */
+  double t0_step_sd, shift_sd;
+  int32_t k_max;         /* default PE cap when fsmp_batch.kmax is NULL */
+  int32_t n_steps, n_chains, burn_in, thin;
+  int32_t precision, refresh_M;
+  uint32_t record_flags;
+  uint64_t seed;
+} fsmp_config;
+
+/* One batch of waveforms (ragged).  wave: device, float32, the concatenated samples;
+ * offsets: host, n_wave + 1 int64 sample offsets (offsets[0] = 0, non-decreasing, every
+ * window 1..65536 samples); lambda: host, lambda0 >= 0 per waveform (the intensity's
+ * scale, eq. pzmu); kmax: host or NULL, PE cap per waveform (1..192); g_range: host or
+ * NULL, [g_lo, g_hi] per waveform inside [0, grid_sub * L_w - 1] (g_lo > g_hi = empty T);
+ * t0_init: host or NULL (default (t0_min + t0_max) / 2); wave_id: host or NULL, the
+ * identity that keys the random stream (default: the index in the batch). */
+typedef struct {
+  int64_t n_wave;
+  const float *wave;
+  const int64_t *offsets;
+  const double *lambda;
+  const int32_t *kmax;
+  const int32_t *g_range;
+  const double *t0_init;
+  const uint64_t *wave_id;
+} fsmp_batch;
+
+/* One record per step of one chain (FSMP_REC_LOG). */
+typedef struct {
+  int32_t move;     /* 1 birth, 2 death, 3 update */
+  int32_t flags;    /* bit0 proposal valid (delta-nu computed), bit1 jump accepted, bit2 t0 accepted */
+  int32_t j;        /* index of the removed / moved PE, -1 for a birth */
+  int32_t g;        /* grid index of the new PE, -1 for a death */
+  double t0;        /* t0 after the Metropolis-Hastings half-step */
+  double dnu;       /* delta-nu = log p(w|z') - log p(w|z) of the proposal (0 if not valid) */
+  double log_alpha; /* log of the acceptance (-inf if not valid) */
+} fsmp_logrec;
+
+/* Outputs of fsmp_sample, caller-allocated device buffers; chain c of waveform i is row
+ * i * n_chains + c.  kz >= every waveform's kmax is the row length of z and charge.
+ *   n_pe[chain]           final N
+ *   t0[chain]             final t0
+ *   z[chain][kz]          final PE grid indices (list order), -1 beyond N
+ *   charge[chain][kz]     E[q | z, w] of the final z (Bayesian linear regression), 0 beyond N
+ *   acc[chain][12]        after burn-in: sum N, N^2, Q, Q^2, t0, t0^2, then sum_b S_b and
+ *                         sum_b S_b^2 of the batch sums S_b of N, Q and t0 (Q = sum of E[q|z,w])
+ *   nhist[chain][kz + 1]  after burn-in: steps with N = k
+ *   counts[chain][8]      proposals / accepts of t0, birth, death, update (all steps)
+ *   status[chain]         FSMP_ST_* bits
+ *   log                   NULL, or [chain][n_steps] fsmp_logrec when FSMP_REC_LOG
+ *   trace                 NULL, or [chain][n_rec][3] (N, t0, Q) every `thin` recorded steps
+ *                         when FSMP_REC_TRACE, n_rec = ceil((n_steps - burn_in) / thin) */
+typedef struct {
+  int32_t *n_pe;
+  double *t0;
+  int32_t *z;
+  double *charge;
+  double *acc;
+  int32_t *nhist;
+  int32_t *counts;
+  uint32_t *status;
+  fsmp_logrec *log;
+  double *trace;
+  int32_t kz;
+} fsmp_samples;
+
+/* Posterior summaries per waveform (device buffers, caller-allocated): for (N, Q, t0)
+ * the mean, variance and batch-means MCSE pooled over the waveform's chains; P(N = k)
+ * for k <= kz (NULL to skip); acceptance rates of t0, birth, death, update; the OR of
+ * the chains' status words. */
+typedef struct {
+  double *mean;      /* [n_wave][3] */
+  double *var;       /* [n_wave][3] */
+  double *mcse;      /* [n_wave][3] */
+  double *p_n;       /* [n_wave][kz + 1] or NULL */
+  double *accept;    /* [n_wave][4] */
+  uint32_t *status;  /* [n_wave] */
+} fsmp_posterior_out;
+
+/* Timing of the kernels of the last fsmp_sample call (HIP events on its stream). */
+typedef struct {
+  char name[32];     /* kernel */
+  int32_t kcap;      /* PE capacity of the instance (0 for non-chain kernels) */
+  int32_t lanes;     /* lanes per chain */
+  int64_t chains;    /* chains the launch ran */
+  int64_t blocks;    /* workgroups */
+  double ms;         /* duration between the events around the launch */
+} fsmp_timing;
+
+typedef struct fsmp_ctx fsmp_ctx;
+
+/* Create a context on HIP device `device`: validates the model, builds the SER table
+ * V(m / grid_sub) and the stationary overlap table sum_n V(n - g1/sub) V(n - g2/sub) in
+ * FP64 on the host, and uploads them.  Returns FSMP_EINVAL for a bad model,
+ * FSMP_EDEVICE if the device is missing or not gfx950.  *out is NULL on failure. */
+fsmp_status fsmp_create(fsmp_ctx **out, const fsmp_ser *ser, const fsmp_intensity *phi, const fsmp_config *cfg,
+                        int device);
+
+/* Device workspace (bytes) fsmp_sample needs for a batch of n_wave waveforms whose solution
+ * spaces hold total_grid grid points in all; the context grows its workspace to this on demand. */
+size_t fsmp_workspace_bytes(const fsmp_ctx *ctx, int64_t n_wave, int64_t total_grid);
+
+/* Run cfg.n_chains chains of cfg.n_steps Gibbs sweeps for every waveform of the batch and
+ * write `out`.  Validates every host array first (FSMP_EINVAL, nothing enqueued); returns
+ * FSMP_ENOTSUP if a kmax exceeds 192 or the SER support does not fit a kernel. */
+fsmp_status fsmp_sample(fsmp_ctx *ctx, const fsmp_batch *batch, const fsmp_samples *out, void *hip_stream);
+
+/* Reduce the per-chain accumulators of fsmp_sample's output into per-waveform summaries
+ * (device kernel on `hip_stream`). */
+fsmp_status fsmp_posterior(fsmp_ctx *ctx, int64_t n_wave, const fsmp_samples *in, fsmp_posterior_out *out,
+                           void *hip_stream);
+
+/* Kernel timings of the last fsmp_sample: writes up to `cap` entries, returns how many
+ * kernels ran (timings are taken only when `enable` was set by fsmp_set_timing). */
+int32_t fsmp_last_timings(const fsmp_ctx *ctx, fsmp_timing *out, int32_t cap);
+fsmp_status fsmp_set_timing(fsmp_ctx *ctx, int32_t enable);
+
+/* Message of the last failure on this context (or of the last failed fsmp_create when ctx
+ * is NULL); never NULL. */
+const char *fsmp_last_error(const fsmp_ctx *ctx);
+
+/* Release the context's device memory; NULL is ignored. */
+void fsmp_destroy(fsmp_ctx *ctx);
+
+/* Library version string. */
+const char *fsmp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSMP_H */

@@ -162,7 +162,7 @@ double ora_phi(const ora_params *p, double t) {
   if (t < 0.0) return 0.0;
   if (p->phi_kind == ORA_PHI_EXP) return exp(-t / p->tau_decay) / p->tau_decay;
   double t1 = p->tau_rise, t2 = p->tau_decay;
-  return (t1 + t2) / (t2 * t2) * (1.0 - exp(-t / t1)) * exp(-t / t2);
+  return (t1 + t2) / (t2 * t2) * (-expm1(-t / t1)) * exp(-t / t2);
 }
 
 double ora_log_phi(const ora_params *p, double t) {

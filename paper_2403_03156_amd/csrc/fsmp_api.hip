@@ -1,0 +1,611 @@
+// fsmp_api.hip -- host runtime of libfsmp.so: the C ABI of include/fsmp.h.
+//
+// Builds the SER and overlap tables in FP64 on the host, validates every call,
+// stages per-waveform metadata through pinned memory, groups chains by PE capacity
+// and enqueues the prologue, chain and posterior kernels on the caller's stream.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fsmp_internal.h"
+
+using namespace fsmp;
+
+namespace {
+
+const char *kVersion = "fsmp-mi355x 0.1 (gfx950)";
+std::string g_create_error = "no error";
+
+// ex-Gaussian density (Sec. 3): Gaussian N(mu, sigma^2) convolved with Exp(mean tau)
+double exg(double t, double mu, double sigma, double tau) {
+  const double a = sigma * sigma / tau;
+  return std::exp((2.0 * mu + a - 2.0 * t) / (2.0 * tau)) * std::erfc((mu + a - t) / (std::sqrt(2.0) * sigma)) /
+         (2.0 * tau);
+}
+
+double gauss(double t, double mu, double sigma) {
+  const double u = (t - mu) / sigma;
+  return std::exp(-0.5 * u * u) / (sigma * std::sqrt(2.0 * M_PI));
+}
+
+// Mode of the ex-Gaussian: its derivative is (g - f) / tau with g the Gaussian
+// density, so the mode is the single sign change of g - f; bisection.
+double exg_mode(double mu, double sigma, double tau) {
+  double lo = mu - 10.0 * sigma, hi = mu + 10.0 * sigma + 10.0 * tau;
+  for (int it = 0; it < 300; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (gauss(mid, mu, sigma) - exg(mid, mu, sigma, tau) > 0.0) lo = mid;
+    else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+struct Tables {
+  int LV = 0, M = 0, sub = 0;
+  std::vector<double> vtab, ovl;
+};
+
+bool build_tables(const fsmp_ser &ser, int sub, Tables &t, std::string &err) {
+  const double tm = exg_mode(ser.mu, ser.sigma, ser.tau);
+  const double fm = exg(tm, ser.mu, ser.sigma, ser.tau);
+  if (!(fm > 0.0) || !std::isfinite(fm)) {
+    err = "SER: density not positive at its mode";
+    return false;
+  }
+  int LV = ser.support;
+  if (LV == 0) {
+    LV = 0;
+    for (int L = 16; L <= 8192; L += 16)
+      if ((double)L > tm && exg((double)L, ser.mu, ser.sigma, ser.tau) / fm < 1e-6) {
+        LV = L;
+        break;
+      }
+    if (LV == 0) {
+      err = "SER: automatic support exceeds 8192 samples";
+      return false;
+    }
+  }
+  if (LV < 1 || LV > 512) {
+    err = "SER: support must be 1..512 samples";
+    return false;
+  }
+  t.LV = LV;
+  t.sub = sub;
+  t.M = sub * LV;
+  t.vtab.assign(t.M, 0.0);
+  for (int m = 0; m < t.M; ++m) t.vtab[m] = ser.amplitude * exg((double)m / sub, ser.mu, ser.sigma, ser.tau) / fm;
+  // stationary overlaps: O[p][d] = sum_n V(n - p/sub) V(n - (p + d)/sub), d >= 0
+  t.ovl.assign((size_t)sub * t.M, 0.0);
+  for (int p = 0; p < sub; ++p)
+    for (int d = 0; d < t.M; ++d) {
+      double s = 0.0;
+      const int g2 = p + d;
+      const int n0 = (g2 + sub - 1) / sub;       // first sample of the later column
+      const int n1 = (p + t.M - 1) / sub;        // last sample of the earlier column
+      for (int n = n0; n <= n1; ++n) s += t.vtab[sub * n - p] * t.vtab[sub * n - g2];
+      t.ovl[(size_t)p * t.M + d] = s;
+    }
+  return true;
+}
+
+template <typename T>
+struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  hipError_t ensure(size_t want) {
+    if (want <= n && p) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+    size_t cap = std::max<size_t>(want, 1);
+    hipError_t e = hipMalloc((void **)&p, cap * sizeof(T));
+    if (e == hipSuccess) n = cap;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+struct PinBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t want) {
+    if (want <= bytes && p) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipHostMalloc(&p, std::max<size_t>(want, 64), hipHostMallocDefault);
+    if (e == hipSuccess) bytes = std::max<size_t>(want, 64);
+    return e;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+}  // namespace
+
+struct fsmp_ctx {
+  int device = 0;
+  fsmp_ser ser{};
+  fsmp_intensity phi{};
+  fsmp_config cfg{};
+  Tables tab;
+  ModelDev md{};
+  double *d_vtab = nullptr, *d_ovl = nullptr;
+  // workspace
+  DevBuf<int64_t> woff, mfoff;
+  DevBuf<double> lam, t0init, mf;
+  DevBuf<int32_t> kmax, grange, chains;
+  DevBuf<uint64_t> wid;
+  DevBuf<uint32_t> wflags;
+  PinBuf stage;
+  hipEvent_t stage_done = nullptr;
+  bool stage_pending = false;
+  bool timing = false;
+  std::vector<fsmp_timing> timings;
+  std::vector<hipEvent_t> evpool;
+  std::string err = "no error";
+};
+
+namespace {
+
+fsmp_status fail(fsmp_ctx *c, fsmp_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  else g_create_error = buf;
+  return s;
+}
+
+bool finite(double v) { return std::isfinite(v); }
+
+fsmp_status validate_model(const fsmp_ser *ser, const fsmp_intensity *phi, const fsmp_config *cfg, std::string &m) {
+  char b[256];
+  if (!ser || !phi || !cfg) return m = "null model pointer", FSMP_EINVAL;
+  if (!finite(ser->mu) || !(ser->sigma > 0) || !(ser->tau > 0) || !finite(ser->sigma) || !finite(ser->tau))
+    return m = "SER: need finite mu, sigma > 0, tau > 0", FSMP_EINVAL;
+  if (!finite(ser->amplitude) || ser->amplitude < 0) return m = "SER: amplitude must be finite and >= 0", FSMP_EINVAL;
+  if (ser->support < 0 || ser->support > 512) return m = "SER: support must be 0 (auto) or 1..512", FSMP_EINVAL;
+  if (phi->kind != FSMP_PHI_EXP && phi->kind != FSMP_PHI_BIEXP) return m = "phi: unknown kind", FSMP_EINVAL;
+  if (!(phi->tau_decay > 0) || !finite(phi->tau_decay)) return m = "phi: tau_decay must be > 0", FSMP_EINVAL;
+  if (phi->kind == FSMP_PHI_BIEXP && (!(phi->tau_rise > 0) || !finite(phi->tau_rise)))
+    return m = "phi: BIEXP needs tau_rise > 0", FSMP_EINVAL;
+  if (!finite(phi->t0_min) || !finite(phi->t0_max) || phi->t0_min > phi->t0_max)
+    return m = "phi: need finite t0_min <= t0_max", FSMP_EINVAL;
+  if (!(cfg->sigma_eps > 0) || !finite(cfg->sigma_eps)) return m = "config: sigma_eps must be > 0", FSMP_EINVAL;
+  if (!(cfg->sigma_q > 0) || !finite(cfg->sigma_q) || !finite(cfg->mu_q))
+    return m = "config: need finite mu_q and sigma_q > 0", FSMP_EINVAL;
+  if (cfg->grid_sub < 1 || cfg->grid_sub > 16) return m = "config: grid_sub must be 1..16", FSMP_EINVAL;
+  if (!(cfg->jump_J > 0) || !(cfg->jump_J < 0.5)) return m = "config: jump_J must be in (0, 1/2)", FSMP_EINVAL;
+  if (!(cfg->t0_step_sd > 0) || !(cfg->shift_sd > 0) || !finite(cfg->t0_step_sd) || !finite(cfg->shift_sd))
+    return m = "config: step sizes must be > 0", FSMP_EINVAL;
+  if (cfg->k_max < 1 || cfg->k_max > 192) return m = "config: k_max must be 1..192", FSMP_EINVAL;
+  if (cfg->n_steps < 0 || cfg->n_chains < 1 || cfg->burn_in < 0 || cfg->burn_in > cfg->n_steps) {
+    snprintf(b, sizeof b, "config: need n_steps >= 0, n_chains >= 1, 0 <= burn_in <= n_steps (got %d %d %d)",
+             cfg->n_steps, cfg->n_chains, cfg->burn_in);
+    return m = b, FSMP_EINVAL;
+  }
+  if ((cfg->record_flags & FSMP_REC_TRACE) && cfg->thin < 1) return m = "config: trace needs thin >= 1", FSMP_EINVAL;
+  if (cfg->record_flags & ~(uint32_t)(FSMP_REC_TRACE | FSMP_REC_LOG)) return m = "config: unknown record flag", FSMP_EINVAL;
+  if (cfg->precision != FSMP_FP64 && cfg->precision != FSMP_FP32_REFRESH) return m = "config: unknown precision", FSMP_EINVAL;
+  if (cfg->precision == FSMP_FP32_REFRESH) return m = "config: FP32 refresh form not in this build", FSMP_ENOTSUP;
+  return FSMP_OK;
+}
+
+void fill_model(fsmp_ctx *c) {
+  ModelDev &md = c->md;
+  const fsmp_config &cf = c->cfg;
+  md.s = cf.sigma_eps * cf.sigma_eps;
+  md.inv_s = 1.0 / md.s;
+  md.rho = md.s / (cf.sigma_q * cf.sigma_q);
+  md.log_rho = std::log(md.rho);
+  md.m = cf.mu_q;
+  md.rhom = md.rho * cf.mu_q;
+  md.rhom2 = md.rho * cf.mu_q * cf.mu_q;
+  md.sub = c->tab.sub;
+  md.LV = c->tab.LV;
+  md.M = c->tab.M;
+  md.dt = 1.0 / cf.grid_sub;
+  md.kind = c->phi.kind;
+  const double t2 = c->phi.tau_decay;
+  md.inv_tau2 = 1.0 / t2;
+  md.log_tau2 = std::log(t2);
+  md.den2 = -std::expm1(-md.dt / t2);
+  if (md.kind == FSMP_PHI_BIEXP) {
+    const double t1 = c->phi.tau_rise;
+    const double t12 = 1.0 / (1.0 / t1 + 1.0 / t2);
+    md.inv_tau1 = 1.0 / t1;
+    md.inv_tau12 = 1.0 / t12;
+    md.C = (t1 + t2) / (t2 * t2);
+    md.logC = std::log(md.C);
+    md.den12 = -std::expm1(-md.dt / t12);
+  } else {
+    md.inv_tau1 = 0.0;
+    md.inv_tau12 = 0.0;
+    md.C = 1.0 / t2;
+    md.logC = -md.log_tau2;
+    md.den12 = 1.0;
+  }
+  md.t0_min = c->phi.t0_min;
+  md.t0_max = c->phi.t0_max;
+  md.t0_sd = cf.t0_step_sd;
+  md.shift_sd = cf.shift_sd;
+  md.J = cf.jump_J;
+  md.logJ = std::log(cf.jump_J);
+}
+
+hipEvent_t pool_event(fsmp_ctx *c, size_t i) {
+  while (c->evpool.size() <= i) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->evpool.push_back(e);
+  }
+  return c->evpool[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fsmp_version(void) { return kVersion; }
+
+const char *fsmp_last_error(const fsmp_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+fsmp_status fsmp_create(fsmp_ctx **out, const fsmp_ser *ser, const fsmp_intensity *phi, const fsmp_config *cfg,
+                        int device) {
+  if (!out) return fail(nullptr, FSMP_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string m;
+  fsmp_status s = validate_model(ser, phi, cfg, m);
+  if (s != FSMP_OK) return fail(nullptr, s, "%s", m.c_str());
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return fail(nullptr, FSMP_EDEVICE, "no HIP device");
+  }
+  if (device < 0 || device >= ndev) return fail(nullptr, FSMP_EDEVICE, "device %d out of range (%d devices)", device, ndev);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(nullptr, FSMP_EDEVICE, "hipGetDeviceProperties failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, FSMP_EDEVICE, "device %d is %s, this library is built for gfx950", device, prop.gcnArchName);
+  fsmp_ctx *c = new fsmp_ctx();
+  c->device = device;
+  c->ser = *ser;
+  c->phi = *phi;
+  c->cfg = *cfg;
+  if (!build_tables(c->ser, cfg->grid_sub, c->tab, m)) {
+    delete c;
+    return fail(nullptr, FSMP_EINVAL, "%s", m.c_str());
+  }
+  fill_model(c);
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(device);
+  hipError_t e = hipMalloc((void **)&c->d_vtab, sizeof(double) * c->tab.M);
+  if (e == hipSuccess) e = hipMalloc((void **)&c->d_ovl, sizeof(double) * c->tab.ovl.size());
+  if (e == hipSuccess) e = hipMemcpy(c->d_vtab, c->tab.vtab.data(), sizeof(double) * c->tab.M, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->d_ovl, c->tab.ovl.data(), sizeof(double) * c->tab.ovl.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming);
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) {
+    fsmp_destroy(c);
+    return fail(nullptr, FSMP_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return FSMP_OK;
+}
+
+void fsmp_destroy(fsmp_ctx *c) {
+  if (!c) return;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(c->device);
+  if (c->stage_done) {
+    (void)hipEventSynchronize(c->stage_done);
+    (void)hipEventDestroy(c->stage_done);
+  }
+  for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+  if (c->d_vtab) (void)hipFree(c->d_vtab);
+  if (c->d_ovl) (void)hipFree(c->d_ovl);
+  c->woff.release();
+  c->mfoff.release();
+  c->lam.release();
+  c->t0init.release();
+  c->mf.release();
+  c->kmax.release();
+  c->grange.release();
+  c->chains.release();
+  c->wid.release();
+  c->wflags.release();
+  c->stage.release();
+  (void)hipSetDevice(prev);
+  delete c;
+}
+
+size_t fsmp_workspace_bytes(const fsmp_ctx *c, int64_t n_wave, int64_t total_grid) {
+  if (!c || n_wave < 0 || total_grid < 0) return 0;
+  const size_t n = (size_t)n_wave;
+  return n * (8 + 8 + 8 + 8 + 8 + 4 + 8 + 4 + 4) + 16 + (size_t)total_grid * 8 +
+         n * (size_t)c->cfg.n_chains * 4;
+}
+
+fsmp_status fsmp_set_timing(fsmp_ctx *c, int32_t enable) {
+  if (!c) return FSMP_EINVAL;
+  c->timing = enable != 0;
+  return FSMP_OK;
+}
+
+int32_t fsmp_last_timings(const fsmp_ctx *c, fsmp_timing *out, int32_t cap) {
+  if (!c) return 0;
+  const int32_t n = (int32_t)c->timings.size();
+  for (int32_t i = 0; i < n && i < cap && out; ++i) out[i] = c->timings[i];
+  return n;
+}
+
+fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o, void *hip_stream) {
+  if (!c) return FSMP_EINVAL;
+  if (!b || !o) return fail(c, FSMP_EINVAL, "null batch or output");
+  const fsmp_config &cf = c->cfg;
+  const int64_t n = b->n_wave;
+  if (n < 0) return fail(c, FSMP_EINVAL, "n_wave < 0");
+  if (n > 0 && (!b->wave || !b->offsets || !b->lambda)) return fail(c, FSMP_EINVAL, "wave, offsets and lambda are required");
+  if (n > 0 && (!o->n_pe || !o->t0 || !o->z || !o->charge || !o->acc || !o->nhist || !o->counts || !o->status))
+    return fail(c, FSMP_EINVAL, "an output buffer is NULL");
+  if ((cf.record_flags & FSMP_REC_LOG) && !o->log) return fail(c, FSMP_EINVAL, "FSMP_REC_LOG set but log is NULL");
+  if ((cf.record_flags & FSMP_REC_TRACE) && !o->trace) return fail(c, FSMP_EINVAL, "FSMP_REC_TRACE set but trace is NULL");
+  if (n > 0 && b->offsets[0] != 0) return fail(c, FSMP_EINVAL, "offsets[0] must be 0");
+  const int sub = cf.grid_sub;
+  // ---- per-waveform metadata
+  std::vector<int32_t> kmx(n), gr(2 * n);
+  std::vector<double> t0i(n);
+  std::vector<uint64_t> wid(n);
+  std::vector<int64_t> mfo(n + 1);
+  mfo[0] = 0;
+  int kmax_all = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t L = b->offsets[i + 1] - b->offsets[i];
+    if (L < 1 || L > 65536) return fail(c, FSMP_EINVAL, "waveform %lld: window of %lld samples (need 1..65536)", (long long)i, (long long)L);
+    const double lm = b->lambda[i];
+    if (!std::isfinite(lm) || lm < 0) return fail(c, FSMP_EINVAL, "waveform %lld: lambda must be finite and >= 0", (long long)i);
+    const int km = b->kmax ? b->kmax[i] : cf.k_max;
+    if (km < 1 || km > 192) return fail(c, FSMP_EINVAL, "waveform %lld: kmax %d outside 1..192", (long long)i, km);
+    if (km > o->kz) return fail(c, FSMP_EINVAL, "waveform %lld: kmax %d exceeds the output row length kz %d", (long long)i, km, o->kz);
+    kmx[i] = km;
+    kmax_all = std::max(kmax_all, km);
+    int lo = 0, hi = (int)(sub * L - 1);
+    if (b->g_range) {
+      lo = b->g_range[2 * i];
+      hi = b->g_range[2 * i + 1];
+      if (lo <= hi && (lo < 0 || hi > sub * L - 1))
+        return fail(c, FSMP_EINVAL, "waveform %lld: g_range [%d, %d] outside [0, %lld]", (long long)i, lo, hi, (long long)(sub * L - 1));
+    }
+    gr[2 * i] = lo;
+    gr[2 * i + 1] = hi;
+    const double t0 = b->t0_init ? b->t0_init[i] : 0.5 * (c->phi.t0_min + c->phi.t0_max);
+    if (!(t0 >= c->phi.t0_min && t0 <= c->phi.t0_max)) return fail(c, FSMP_EINVAL, "waveform %lld: t0_init outside the prior", (long long)i);
+    t0i[i] = t0;
+    wid[i] = b->wave_id ? b->wave_id[i] : (uint64_t)i;
+    mfo[i + 1] = mfo[i] + (lo <= hi ? (int64_t)(hi - lo + 1) : 0);
+  }
+  // ---- chains grouped by PE capacity
+  const int caps[3] = {16, 32, 64};
+  std::vector<int32_t> order;
+  order.reserve((size_t)n * cf.n_chains);
+  int64_t bucket_start[4] = {0, 0, 0, 0};
+  for (int bi = 0; bi < 3; ++bi) {
+    bucket_start[bi] = (int64_t)order.size();
+    for (int64_t i = 0; i < n; ++i) {
+      if (chain_kcap_for(kmx[i]) != caps[bi]) continue;
+      for (int ch = 0; ch < cf.n_chains; ++ch) order.push_back((int32_t)(i * cf.n_chains + ch));
+    }
+  }
+  bucket_start[3] = (int64_t)order.size();
+  if ((int64_t)order.size() != n * cf.n_chains)
+    return fail(c, FSMP_ENOTSUP, "kmax above 64 is not provided by this build");
+  if (n * (int64_t)cf.n_chains > INT32_MAX) return fail(c, FSMP_EINVAL, "too many chains");
+  for (int bi = 0; bi < 3; ++bi)
+    if (bucket_start[bi + 1] > bucket_start[bi] && !chain_kcap_supported(caps[bi], c->tab.M, sub))
+      return fail(c, FSMP_ENOTSUP, "SER support %d too long for PE capacity %d", c->tab.LV, caps[bi]);
+  if (n == 0) {
+    c->timings.clear();
+    return FSMP_OK;
+  }
+
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(c->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e = hipSuccess;
+  // ---- workspace
+  if (e == hipSuccess) e = c->woff.ensure(n + 1);
+  if (e == hipSuccess) e = c->mfoff.ensure(n + 1);
+  if (e == hipSuccess) e = c->lam.ensure(n);
+  if (e == hipSuccess) e = c->t0init.ensure(n);
+  if (e == hipSuccess) e = c->kmax.ensure(n);
+  if (e == hipSuccess) e = c->grange.ensure(2 * n);
+  if (e == hipSuccess) e = c->wid.ensure(n);
+  if (e == hipSuccess) e = c->wflags.ensure(n);
+  if (e == hipSuccess) e = c->mf.ensure((size_t)std::max<int64_t>(mfo[n], 1));
+  if (e == hipSuccess) e = c->chains.ensure(order.size());
+  if (e != hipSuccess) {
+    (void)hipSetDevice(prev);
+    return fail(c, FSMP_ENOMEM, "workspace allocation failed: %s", hipGetErrorString(e));
+  }
+  // ---- stage metadata through pinned memory (wait until the previous upload is done)
+  if (c->stage_pending) (void)hipEventSynchronize(c->stage_done);
+  auto pad16 = [](size_t nb) { return (nb + 15) & ~(size_t)15; };
+  const size_t bytes = pad16(sizeof(int64_t) * (n + 1)) * 2 + pad16(sizeof(double) * n) * 2 +
+                       pad16(sizeof(int32_t) * n) + pad16(sizeof(int32_t) * 2 * n) + pad16(sizeof(uint64_t) * n) +
+                       pad16(sizeof(int32_t) * order.size());
+  e = c->stage.ensure(bytes);
+  if (e != hipSuccess) {
+    (void)hipSetDevice(prev);
+    return fail(c, FSMP_ENOMEM, "pinned staging allocation failed: %s", hipGetErrorString(e));
+  }
+  char *sp = (char *)c->stage.p;
+  auto put = [&](void *dst, const void *src, size_t nb) -> hipError_t {
+    std::memcpy(sp, src, nb);
+    hipError_t r = hipMemcpyAsync(dst, sp, nb, hipMemcpyHostToDevice, st);
+    sp += pad16(nb);
+    return r;
+  };
+  if (e == hipSuccess) e = put(c->woff.p, b->offsets, sizeof(int64_t) * (n + 1));
+  if (e == hipSuccess) e = put(c->mfoff.p, mfo.data(), sizeof(int64_t) * (n + 1));
+  if (e == hipSuccess) e = put(c->lam.p, b->lambda, sizeof(double) * n);
+  if (e == hipSuccess) e = put(c->t0init.p, t0i.data(), sizeof(double) * n);
+  if (e == hipSuccess) e = put(c->kmax.p, kmx.data(), sizeof(int32_t) * n);
+  if (e == hipSuccess) e = put(c->grange.p, gr.data(), sizeof(int32_t) * 2 * n);
+  if (e == hipSuccess) e = put(c->wid.p, wid.data(), sizeof(uint64_t) * n);
+  if (e == hipSuccess) e = put(c->chains.p, order.data(), sizeof(int32_t) * order.size());
+  if (e == hipSuccess) e = hipEventRecord(c->stage_done, st);
+  c->stage_pending = (e == hipSuccess);
+  if (e != hipSuccess) {
+    (void)hipSetDevice(prev);
+    return fail(c, FSMP_EDEVICE, "metadata upload failed: %s", hipGetErrorString(e));
+  }
+
+  c->timings.clear();
+  size_t ev = 0;
+  auto timed = [&](const char *name, int kcap, auto &&launch) -> hipError_t {
+    fsmp_timing t{};
+    std::snprintf(t.name, sizeof t.name, "%s", name);
+    t.kcap = kcap;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+      e0 = pool_event(c, ev++);
+      e1 = pool_event(c, ev++);
+      if (e0) (void)hipEventRecord(e0, st);
+    }
+    hipError_t r = launch(t);
+    if (c->timing && e1) {
+      (void)hipEventRecord(e1, st);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      t.ms = ms;
+    }
+    c->timings.push_back(t);
+    return r;
+  };
+
+  // ---- prologue: matched filter over T, non-finite scan
+  PrologueArgs pa{};
+  pa.md = c->md;
+  pa.vtab = c->d_vtab;
+  pa.wave = b->wave;
+  pa.woff = c->woff.p;
+  pa.grange = c->grange.p;
+  pa.mfoff = c->mfoff.p;
+  pa.mf = c->mf.p;
+  pa.wflags = c->wflags.p;
+  pa.n_wave = n;
+  e = timed("prologue", 0, [&](fsmp_timing &t) {
+    t.chains = 0;
+    t.blocks = std::min<int64_t>(n, 65535 * 8);
+    t.lanes = 0;
+    return launch_prologue(pa, st);
+  });
+  // ---- chains
+  ChainArgs ca{};
+  ca.md = c->md;
+  ca.vtab = c->d_vtab;
+  ca.ovl = c->d_ovl;
+  ca.woff = c->woff.p;
+  ca.lam = c->lam.p;
+  ca.kmax = c->kmax.p;
+  ca.grange = c->grange.p;
+  ca.t0init = c->t0init.p;
+  ca.wid = c->wid.p;
+  ca.mf = c->mf.p;
+  ca.mfoff = c->mfoff.p;
+  ca.n_chains = cf.n_chains;
+  ca.n_steps = cf.n_steps;
+  ca.burn_in = cf.burn_in;
+  ca.thin = cf.thin;
+  const int S = cf.n_steps - cf.burn_in;
+  ca.nb = S > 0 ? (int)std::floor(std::sqrt((double)S)) : 0;
+  ca.lb = ca.nb > 0 ? S / ca.nb : 0;
+  ca.n_rec = (cf.thin > 0 && S > 0) ? (S + cf.thin - 1) / cf.thin : 0;
+  ca.key0 = (uint32_t)cf.seed;
+  ca.key1 = (uint32_t)(cf.seed >> 32);
+  ca.n_pe = o->n_pe;
+  ca.t0 = o->t0;
+  ca.z = o->z;
+  ca.charge = o->charge;
+  ca.acc = o->acc;
+  ca.nhist = o->nhist;
+  ca.counts = o->counts;
+  ca.status = o->status;
+  ca.log = (cf.record_flags & FSMP_REC_LOG) ? o->log : nullptr;
+  ca.trace = (cf.record_flags & FSMP_REC_TRACE) ? o->trace : nullptr;
+  ca.kz = o->kz;
+  ca.wflags = c->wflags.p;
+  for (int bi = 0; bi < 3 && e == hipSuccess; ++bi) {
+    const int64_t cnt = bucket_start[bi + 1] - bucket_start[bi];
+    if (cnt == 0) continue;
+    ca.chains = c->chains.p + bucket_start[bi];
+    ca.n_list = cnt;
+    char name[32];
+    std::snprintf(name, sizeof name, "chain_k%d", caps[bi]);
+    e = timed(name, caps[bi], [&](fsmp_timing &t) {
+      t.chains = cnt;
+      return launch_chain(caps[bi], ca, st, &t.lanes, &t.blocks);
+    });
+  }
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) return fail(c, FSMP_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return FSMP_OK;
+}
+
+fsmp_status fsmp_posterior(fsmp_ctx *c, int64_t n_wave, const fsmp_samples *in, fsmp_posterior_out *out,
+                           void *hip_stream) {
+  if (!c) return FSMP_EINVAL;
+  if (!in || !out) return fail(c, FSMP_EINVAL, "null samples or posterior output");
+  if (n_wave < 0) return fail(c, FSMP_EINVAL, "n_wave < 0");
+  if (n_wave == 0) return FSMP_OK;
+  if (!in->acc || !in->nhist || !in->counts || !in->status) return fail(c, FSMP_EINVAL, "sample accumulators are NULL");
+  if (!out->mean || !out->var || !out->mcse || !out->accept || !out->status)
+    return fail(c, FSMP_EINVAL, "a posterior output buffer is NULL");
+  PosteriorArgs a{};
+  a.acc = in->acc;
+  a.nhist = in->nhist;
+  a.counts = in->counts;
+  a.cstatus = in->status;
+  a.n_wave = n_wave;
+  a.n_chains = c->cfg.n_chains;
+  a.kz = in->kz;
+  a.n_steps = c->cfg.n_steps;
+  a.burn_in = c->cfg.burn_in;
+  a.mean = out->mean;
+  a.var = out->var;
+  a.mcse = out->mcse;
+  a.p_n = out->p_n;
+  a.accept = out->accept;
+  a.status = out->status;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(c->device);
+  hipError_t e = launch_posterior(a, (hipStream_t)hip_stream);
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) return fail(c, FSMP_EDEVICE, "posterior launch failed: %s", hipGetErrorString(e));
+  return FSMP_OK;
+}
+
+}  // extern "C"

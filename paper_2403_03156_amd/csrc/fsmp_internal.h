@@ -1,0 +1,92 @@
+// Internal types shared by the host runtime (fsmp_api.hip) and the kernels
+// (fsmp_kernels.hip) of libfsmp.so.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fsmp.h"
+
+namespace fsmp {
+
+// Model constants in the form the kernels use them (all FP64).
+struct ModelDev {
+  // likelihood in PE space: s = sigma_eps^2, rho = s / sigma_q^2, m = mu_q
+  double s, inv_s, rho, log_rho, m, rhom, rhom2;
+  // grid and SER table: dt = 1 / sub samples, M = sub * LV table entries
+  int32_t sub, LV, M, pad0;
+  double dt;
+  // light curve
+  int32_t kind, pad1;
+  double inv_tau2, inv_tau12, inv_tau1, log_tau2, C, logC;
+  double den2, den12;  // -expm1(-dt / tau) for tau2 and tau12
+  // t0 prior and proposals
+  double t0_min, t0_max, t0_sd, shift_sd;
+  double J, logJ;
+};
+
+struct ChainArgs {
+  ModelDev md;
+  const double *vtab;  // [M]  V(m / sub)
+  const double *ovl;   // [sub][M] stationary overlaps, lower grid index's phase, offset >= 0
+  // batch (device copies)
+  const int64_t *woff;
+  const double *lam;
+  const int32_t *kmax;
+  const int32_t *grange;  // [2n]
+  const double *t0init;
+  const uint64_t *wid;
+  const double *mf;       // matched filter sum_n w[n] V(n - g/sub) for g in T, per waveform
+  const int64_t *mfoff;   // [n+1]
+  const int32_t *chains;  // chain indices (wave * n_chains + chain) of this launch
+  int64_t n_list;
+  int32_t n_chains, n_steps, burn_in, thin, nb, lb;
+  int64_t n_rec;
+  uint32_t key0, key1;
+  // outputs
+  int32_t *n_pe;
+  double *t0;
+  int32_t *z;
+  double *charge;
+  double *acc;
+  int32_t *nhist;
+  int32_t *counts;
+  uint32_t *status;
+  fsmp_logrec *log;
+  double *trace;
+  int32_t kz;
+  const uint32_t *wflags;  // per waveform, from the prologue (FSMP_ST_NONFINITE)
+};
+
+struct PrologueArgs {
+  ModelDev md;
+  const double *vtab;
+  const float *wave;
+  const int64_t *woff;
+  const int32_t *grange;
+  const int64_t *mfoff;
+  double *mf;
+  uint32_t *wflags;  // per waveform: bit1 non-finite sample
+  int64_t n_wave;
+};
+
+struct PosteriorArgs {
+  const double *acc;
+  const int32_t *nhist;
+  const int32_t *counts;
+  const uint32_t *cstatus;
+  int64_t n_wave;
+  int32_t n_chains, kz, n_steps, burn_in;
+  double *mean, *var, *mcse, *p_n, *accept;
+  uint32_t *status;
+};
+
+// Launchers (fsmp_kernels.hip).  Each returns hipSuccess or the launch error.
+hipError_t launch_prologue(const PrologueArgs &a, hipStream_t st);
+hipError_t launch_posterior(const PosteriorArgs &a, hipStream_t st);
+// kcap in {16, 32, 64}; fills lanes per chain and blocks
+hipError_t launch_chain(int kcap, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks);
+bool chain_kcap_supported(int kcap, int M, int sub);
+int chain_kcap_for(int kmax);
+
+}  // namespace fsmp

@@ -1,0 +1,672 @@
+// fsmp_kernels.hip -- gfx950 kernels of libfsmp.so.
+//
+//  * prologue_kernel: per waveform, the matched filter c(g) = sum_n w[n] V(n - g/sub)
+//    over the solution space T (FP64 accumulation) and a scan for non-finite samples.
+//  * chain_kernel<KCAP, LPC, WPB>: the Gibbs / RJMCMC chains (Sec. 2.4).  A group of
+//    LPC lanes owns one chain; a 64-lane wavefront runs 64 / LPC chains side by side.
+//    Per chain the LDS holds the inverse PE-space Gram matrix H = G^{-1},
+//    G = A^T A + rho I (full symmetric, KCAP x KCAP), the matched-filter terms b, the
+//    charge means x = H b and the PE grid indices.  With H at hand
+//      birth  : eta = H gamma (one mat-vec), delta^2 = d - gamma^T eta,
+//               u+ = (beta - gamma^T x) / delta,
+//               delta-nu = -1/2 [-log rho + log delta^2 + (rho m^2 - u+^2) / s];
+//      death  : omega = H_jj, delta-nu = 1/2 [-log rho - log omega + (rho m^2 - x_j^2/omega) / s];
+//      update : one mat-vec with gamma' (zero at j) and O(1) corrections;
+//    accepted moves are rank-one (birth, death) or rank-two (update) edits of H.
+//    These are the determinant lemma and Woodbury identity applied in PE space to the
+//    normal law of App. A (eq. mgauss); they give the same delta-nu as the paper's
+//    N_w x N_w rank-2 form (eqs. 11-18) at O(K^2) instead of O(N_w^2) per step.
+//  * posterior_kernel: per waveform, pooled mean / variance / batch-means MCSE.
+//
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = seed,
+// counter = (step, block, uid lo, uid hi).  Words of one step: r0,r1 Box-Muller pair
+// (t0 step, update shift), r2 t0 accept, r3 move, r4 (r5) index or 53-bit birth
+// uniform, r6 jump accept.
+
+#include <math.h>
+
+#include "fsmp_internal.h"
+
+namespace fsmp {
+namespace {
+
+constexpr int kWave = 64;
+
+// Intra-wavefront ordering of LDS traffic between lanes: the LDS executes one
+// wavefront's instructions in order; the fences keep the compiler from moving
+// memory operations across this point.
+#define WAVE_SYNC()                                        \
+  do {                                                     \
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); \
+    __builtin_amdgcn_wave_barrier();                       \
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
+  } while (0)
+
+__device__ inline void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                                     uint32_t *out) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+__device__ inline double u01(uint32_t r) { return ((double)r + 0.5) * 0x1p-32; }
+
+__device__ inline double u53(uint32_t lo, uint32_t hi) {
+  const uint64_t v = ((uint64_t)hi << 32) | lo;
+  return (double)(v >> 11) * 0x1p-53 + 0x1p-54;
+}
+
+// log phi(x); -inf where phi vanishes (x < 0, and x = 0 for BIEXP)
+__device__ inline double log_phi(const ModelDev &md, double x) {
+  if (md.kind == FSMP_PHI_EXP) return x < 0.0 ? -INFINITY : -x * md.inv_tau2 - md.log_tau2;
+  if (!(x > 0.0)) return -INFINITY;
+  return md.logC - x * md.inv_tau2 + log(-expm1(-x * md.inv_tau1));
+}
+
+// sum of phi over the first k grid points of T at or after t0 (geometric series)
+__device__ inline double phi_partial(const ModelDev &md, double xs, int64_t k) {
+  const double kdt = (double)k * md.dt;
+  const double a = exp(-xs * md.inv_tau2) * (-expm1(-kdt * md.inv_tau2)) / md.den2;
+  if (md.kind == FSMP_PHI_EXP) return a * md.inv_tau2;
+  const double b = exp(-xs * md.inv_tau12) * (-expm1(-kdt * md.inv_tau12)) / md.den12;
+  return md.C * (a - b);
+}
+
+struct GridPos {
+  int64_t gs;  // first grid point of T with g dt >= t0
+  int64_t n;   // points of T from gs on (<= 0: none)
+  double xs;   // gs dt - t0
+};
+
+__device__ inline GridPos grid_pos(const ModelDev &md, double t0, int glo, int ghi) {
+  GridPos p;
+  int64_t gs = (int64_t)ceil(t0 / md.dt);
+  if (gs < glo) gs = glo;
+  p.gs = gs;
+  p.n = (int64_t)ghi - gs + 1;
+  p.xs = (double)gs * md.dt - t0;
+  return p;
+}
+
+__device__ inline double phi_total(const ModelDev &md, double t0, int glo, int ghi) {
+  const GridPos p = grid_pos(md, t0, glo, ghi);
+  return p.n > 0 ? phi_partial(md, p.xs, p.n) : 0.0;
+}
+
+template <int W>
+__device__ inline double group_sum(double v) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+  return v;
+}
+
+template <int W>
+__device__ inline int group_or(int v) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, W);
+  return v;
+}
+
+// overlap sum_{n < Lw} V(n - g1/sub) V(n - g2/sub): the stationary table unless both
+// columns run past the window end, then the direct sum over the samples left
+__device__ inline double overlap(const ModelDev &md, const double *vt, const double *ov, int g1, int g2, int Lw) {
+  const int lo = g1 < g2 ? g1 : g2, hi = g1 < g2 ? g2 : g1;
+  const int d = hi - lo;
+  if (d >= md.M) return 0.0;
+  const int nhi = (lo + md.M - 1) / md.sub;  // last sample of the earlier column
+  if (nhi < Lw) return ov[(lo % md.sub) * md.M + d];
+  double s = 0.0;
+  const int n0 = (hi + md.sub - 1) / md.sub;
+  for (int n = n0; n < Lw; ++n) s += vt[md.sub * n - lo] * vt[md.sub * n - hi];
+  return s;
+}
+
+// birth position: smallest g in T with sum_{g' <= g} phi(g' dt - t0) > target
+template <int LPC>
+__device__ inline int birth_draw(const ModelDev &md, double t0, int glo, int ghi, double target, int lane, int grp) {
+  const GridPos p = grid_pos(md, t0, glo, ghi);
+  int64_t k;
+  if (md.kind == FSMP_PHI_EXP) {
+    // closed-form inverse of the truncated geometric law
+    const double c = target * exp(p.xs * md.inv_tau2) * md.den2 / md.inv_tau2;
+    if (c >= 1.0) {
+      k = p.n - 1;
+    } else {
+      const double L = -log1p(-c) / (md.dt * md.inv_tau2);
+      k = (int64_t)floor(L);
+      if (k < 0) k = 0;
+      if (k > p.n - 1) k = p.n - 1;
+      // settle rounding at the boundary against the partial sums
+      if (k > 0 && phi_partial(md, p.xs, k) > target) k -= 1;
+      else if (k < p.n - 1 && !(phi_partial(md, p.xs, k + 1) > target)) k += 1;
+    }
+  } else {
+    // LPC-ary search on the closed-form partial sums
+    int64_t lo = 0, hi = p.n - 1;
+    const uint64_t gmask = (LPC == 64) ? ~0ull : ((1ull << LPC) - 1ull);
+    while (hi > lo) {
+      const int64_t span = hi - lo + 1;
+      const int64_t step = (span + LPC - 1) / LPC;
+      int64_t kl = lo + (int64_t)(lane + 1) * step - 1;
+      if (kl > hi) kl = hi;
+      const bool pred = phi_partial(md, p.xs, kl + 1) > target;
+      const uint64_t bal = (__ballot(pred) >> (grp * LPC)) & gmask;
+      if (bal == 0) {
+        lo = hi;
+        break;
+      }
+      const int l = __ffsll((unsigned long long)bal) - 1;
+      int64_t khi = lo + (int64_t)(l + 1) * step - 1;
+      if (khi > hi) khi = hi;
+      const int64_t klo = (l == 0) ? lo : lo + (int64_t)l * step;
+      lo = klo;
+      hi = khi;
+    }
+    k = lo;
+  }
+  return (int)(p.gs + k);
+}
+
+// ------------------------------------------------------------------ prologue
+__global__ void __launch_bounds__(256) prologue_kernel(PrologueArgs a) {
+  extern __shared__ double vt[];
+  const ModelDev &md = a.md;
+  for (int i = threadIdx.x; i < md.M; i += blockDim.x) vt[i] = a.vtab[i];
+  __syncthreads();
+  for (int64_t w = blockIdx.x; w < a.n_wave; w += gridDim.x) {
+    const float *x = a.wave + a.woff[w];
+    const int Lw = (int)(a.woff[w + 1] - a.woff[w]);
+    int bad = 0;
+    for (int n = threadIdx.x; n < Lw; n += blockDim.x)
+      if (!isfinite(x[n])) bad = 1;
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0) a.wflags[w] = bad ? FSMP_ST_NONFINITE : 0u;
+    const int glo = a.grange[2 * w], ghi = a.grange[2 * w + 1];
+    double *out = a.mf + a.mfoff[w];
+    for (int g = glo + (int)threadIdx.x; g <= ghi; g += blockDim.x) {
+      const int n0 = (g + md.sub - 1) / md.sub;
+      int n1 = (g + md.M - 1) / md.sub;
+      if (n1 > Lw - 1) n1 = Lw - 1;
+      double s = 0.0;
+      for (int n = n0; n <= n1; ++n) s += (double)x[n] * vt[md.sub * n - g];
+      out[g - glo] = s;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ chains
+template <int KCAP>
+struct ChainLayout {
+  static constexpr int LD = KCAP;
+  // H, b, x, three scratch vectors, then int grid indices and the N histogram
+  static constexpr int kDoubles = KCAP * KCAP + 5 * KCAP + (2 * KCAP + 2) / 2;
+};
+
+template <int KCAP, int LPC, int WPB>
+__global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
+  constexpr int CPW = kWave / LPC;
+  constexpr int LD = ChainLayout<KCAP>::LD;
+  extern __shared__ double smem[];
+  const ModelDev &md = a.md;
+  double *vt = smem;
+  double *ov = smem + md.M;
+  for (int i = threadIdx.x; i < md.M; i += blockDim.x) vt[i] = a.vtab[i];
+  for (int i = threadIdx.x; i < md.sub * md.M; i += blockDim.x) ov[i] = a.ovl[i];
+  __syncthreads();
+
+  const int wv = threadIdx.x / kWave, l64 = threadIdx.x % kWave;
+  const int grp = l64 / LPC, lane = l64 % LPC;
+  const int64_t slot = ((int64_t)blockIdx.x * WPB + wv) * CPW + grp;
+  if (slot >= a.n_list) return;
+
+  double *H = smem + md.M * (1 + md.sub) + (int64_t)(wv * CPW + grp) * ChainLayout<KCAP>::kDoubles;
+  double *bv = H + KCAP * LD;
+  double *xv = bv + KCAP;
+  double *s1 = xv + KCAP;
+  double *s2 = s1 + KCAP;
+  double *s3 = s2 + KCAP;
+  int *zg = (int *)(s3 + KCAP);
+  int *hist = zg + KCAP;
+
+  const int64_t c = a.chains[slot];
+  const int64_t w = c / a.n_chains;
+  const int ch = (int)(c % a.n_chains);
+  const int Lw = (int)(a.woff[w + 1] - a.woff[w]);
+  const double lam = a.lam[w];
+  const int kmax = a.kmax[w];
+  const int glo = a.grange[2 * w], ghi = a.grange[2 * w + 1];
+  const double *mf = a.mf + a.mfoff[w];
+  const uint64_t uid = a.wid[w] * (uint64_t)a.n_chains + (uint64_t)ch;
+  const uint32_t uid0 = (uint32_t)uid, uid1 = (uint32_t)(uid >> 32);
+  uint32_t st = a.wflags[w];
+  if (glo > ghi) st |= FSMP_ST_EMPTY_T;
+  const int n_steps = (st & FSMP_ST_NONFINITE) ? 0 : a.n_steps;
+
+  for (int k = lane; k <= KCAP; k += LPC) hist[k] = 0;
+  WAVE_SYNC();
+
+  double t0 = a.t0init[w];
+  int N = 0;
+  double Phi = (glo <= ghi) ? phi_total(md, t0, glo, ghi) : 0.0;
+  double acc[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) acc[i] = 0.0;
+  double bs0 = 0.0, bs1 = 0.0, bs2 = 0.0;
+  int cnt[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) cnt[i] = 0;
+
+  for (int step = 0; step < n_steps; ++step) {
+    uint32_t r[8];
+    philox4x32_10((uint32_t)step, 0u, uid0, uid1, a.key0, a.key1, r);
+    philox4x32_10((uint32_t)step, 1u, uid0, uid1, a.key0, a.key1, r + 4);
+    const double R = sqrt(-2.0 * log(u01(r[0])));
+    const double th = 2.0 * M_PI * u01(r[1]);
+    const double xi_t0 = R * cos(th), xi_sh = R * sin(th);
+
+    // ---- Gibbs half-step 1: t0 by Metropolis-Hastings
+    const double t0p = t0 + md.t0_sd * xi_t0;
+    bool t0acc = false;
+    cnt[0]++;
+    if (t0p >= md.t0_min && t0p <= md.t0_max) {
+      double part = 0.0;
+      int bad = 0;
+      for (int i = lane; i < N; i += LPC) {
+        const double tk = (double)zg[i] * md.dt;
+        const double ln = log_phi(md, tk - t0p);
+        if (ln == -INFINITY) bad = 1;
+        else part += ln - log_phi(md, tk - t0);
+      }
+      part = group_sum<LPC>(part);
+      bad = group_or<LPC>(bad);
+      if (!bad) {
+        const double Phip = (glo <= ghi) ? phi_total(md, t0p, glo, ghi) : 0.0;
+        const double la0 = part - (lam * md.dt * Phip - lam * md.dt * Phi);
+        if (log(u01(r[2])) < la0) {
+          t0 = t0p;
+          Phi = Phip;
+          t0acc = true;
+          cnt[1]++;
+        }
+      }
+    }
+
+    // ---- Gibbs half-step 2: one RJMCMC jump
+    const double Lam = lam * md.dt * Phi;
+    const double um = u01(r[3]);
+    const int move = (N == 0 || um < md.J) ? 1 : (um < 2.0 * md.J ? 2 : 3);
+    int j = -1, gnew = -1, sh = 0;
+    bool valid = false;
+    double dnu = 0.0, la = -INFINITY;
+    double delta2 = 1.0, up = 0.0, om = 1.0, xj = 0.0, ej = 0.0, beta = 0.0;
+    if (move == 1) {
+      cnt[2]++;
+      if (N >= kmax) {
+        st |= FSMP_ST_KMAX;
+      } else if (Phi > 0.0) {
+        gnew = birth_draw<LPC>(md, t0, glo, ghi, u53(r[4], r[5]) * Phi, lane, grp);
+        if (Lam > 0.0) {
+          for (int i = lane; i < N; i += LPC) s1[i] = overlap(md, vt, ov, gnew, zg[i], Lw);
+          const double d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
+          beta = mf[gnew - glo] + md.rhom;
+          WAVE_SYNC();
+          double q = 0.0, p = 0.0;
+          for (int i = lane; i < N; i += LPC) {
+            double e = 0.0;
+            for (int k = 0; k < N; ++k) e += H[k * LD + i] * s1[k];
+            s2[i] = e;
+            q += s1[i] * e;
+            p += s1[i] * xv[i];
+          }
+          q = group_sum<LPC>(q);
+          p = group_sum<LPC>(p);
+          delta2 = d - q;
+          if (delta2 > 0.0) {
+            up = beta - p;
+            dnu = -0.5 * (-md.log_rho + log(delta2) + (md.rhom2 - up * up / delta2) * md.inv_s);
+            la = dnu + log(Lam) - log((double)(N + 1)) + (N == 0 ? md.logJ : 0.0);
+            valid = true;
+          } else {
+            st |= FSMP_ST_FACTOR;
+          }
+        }
+      }
+    } else {
+      j = (int)(((uint64_t)r[4] * (uint64_t)N) >> 32);
+      if (move == 2) {
+        cnt[4]++;
+        om = H[j * LD + j];
+        xj = xv[j];
+        if (om > 0.0) {
+          dnu = 0.5 * (-md.log_rho - log(om) + (md.rhom2 - xj * xj / om) * md.inv_s);
+          la = dnu - log(Lam) + log((double)N) - (N == 1 ? md.logJ : 0.0);
+          valid = true;
+        } else {
+          st |= FSMP_ST_FACTOR;
+        }
+      } else {
+        cnt[6]++;
+        sh = (int)rint(xi_sh * md.shift_sd / md.dt);
+        gnew = zg[j] + sh;
+        if (gnew >= glo && gnew <= ghi) {
+          const double lpn = log_phi(md, (double)gnew * md.dt - t0);
+          if (lpn > -INFINITY) {
+            const double lpo = log_phi(md, (double)zg[j] * md.dt - t0);
+            if (sh == 0) {
+              valid = true;
+              dnu = 0.0;
+              la = lpn - lpo;
+            } else {
+              for (int i = lane; i < N; i += LPC) s1[i] = (i == j) ? 0.0 : overlap(md, vt, ov, gnew, zg[i], Lw);
+              const double d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
+              beta = mf[gnew - glo] + md.rhom;
+              WAVE_SYNC();
+              double q = 0.0, p = 0.0;
+              for (int i = lane; i < N; i += LPC) {
+                double e = 0.0;
+                for (int k = 0; k < N; ++k) e += H[k * LD + i] * s1[k];
+                s2[i] = e;
+                q += s1[i] * e;
+                p += s1[i] * xv[i];
+              }
+              q = group_sum<LPC>(q);
+              p = group_sum<LPC>(p);
+              WAVE_SYNC();
+              om = H[j * LD + j];
+              xj = xv[j];
+              ej = s2[j];
+              delta2 = d - (q - ej * ej / om);
+              up = beta - (p - ej * xj / om);
+              if (delta2 > 0.0 && om > 0.0) {
+                dnu = 0.5 * (-log(om) - log(delta2) + (up * up / delta2 - xj * xj / om) * md.inv_s);
+                la = dnu + lpn - lpo;
+                valid = true;
+              } else {
+                st |= FSMP_ST_FACTOR;
+              }
+            }
+          }
+        }
+      }
+    }
+
+    bool accepted = false;
+    if (valid && log(u01(r[6])) < la) {
+      accepted = true;
+      cnt[2 * move + 1]++;
+      WAVE_SYNC();
+      if (move == 1) {
+        const double inv_d2 = 1.0 / delta2;
+        const double xn = up * inv_d2;
+        for (int i = lane; i < N; i += LPC) {
+          const double ei = s2[i];
+          xv[i] -= ei * xn;
+          for (int k = 0; k < N; ++k) H[k * LD + i] += ei * s2[k] * inv_d2;
+          H[N * LD + i] = -ei * inv_d2;
+          H[i * LD + N] = -ei * inv_d2;
+        }
+        if (lane == 0) {
+          H[N * LD + N] = inv_d2;
+          zg[N] = gnew;
+          bv[N] = beta;
+          xv[N] = xn;
+        }
+        N++;
+        WAVE_SYNC();
+      } else if (move == 2) {
+        const double inv_om = 1.0 / om;
+        for (int i = lane; i < N; i += LPC) s3[i] = H[j * LD + i];
+        WAVE_SYNC();
+        for (int i = lane; i < N; i += LPC) {
+          const double hi = s3[i];
+          xv[i] -= hi * xj * inv_om;
+          for (int k = 0; k < N; ++k) H[k * LD + i] -= hi * s3[k] * inv_om;
+        }
+        WAVE_SYNC();
+        const int last = N - 1;
+        if (j != last) {
+          for (int i = lane; i < N; i += LPC) s3[i] = H[last * LD + i];
+          WAVE_SYNC();
+          const double vd = s3[last];
+          for (int i = lane; i < N; i += LPC) {
+            if (i == j) {
+              H[j * LD + j] = vd;
+            } else {
+              H[j * LD + i] = s3[i];
+              H[i * LD + j] = s3[i];
+            }
+          }
+          if (lane == 0) {
+            zg[j] = zg[last];
+            bv[j] = bv[last];
+            xv[j] = xv[last];
+          }
+        }
+        N--;
+        WAVE_SYNC();
+      } else if (sh != 0) {
+        const double inv_om = 1.0 / om, inv_d2 = 1.0 / delta2;
+        const double xn = up * inv_d2;
+        for (int i = lane; i < N; i += LPC) s3[i] = H[j * LD + i];
+        WAVE_SYNC();
+        for (int i = lane; i < N; i += LPC) s2[i] = (i == j) ? 0.0 : s2[i] - s3[i] * ej * inv_om;
+        WAVE_SYNC();
+        for (int i = lane; i < N; i += LPC) {
+          const double hi = s3[i], ei = s2[i];
+          xv[i] = (i == j) ? xn : xv[i] - hi * xj * inv_om - ei * xn;
+          for (int k = 0; k < N; ++k) H[k * LD + i] += -hi * s3[k] * inv_om + ei * s2[k] * inv_d2;
+        }
+        WAVE_SYNC();
+        for (int i = lane; i < N; i += LPC) {
+          if (i == j) {
+            H[j * LD + j] = inv_d2;
+          } else {
+            const double v = -s2[i] * inv_d2;
+            H[j * LD + i] = v;
+            H[i * LD + j] = v;
+          }
+        }
+        if (lane == 0) {
+          zg[j] = gnew;
+          bv[j] = beta;
+        }
+        WAVE_SYNC();
+      }
+    }
+
+    if (a.log && lane == 0) {
+      fsmp_logrec *lr = a.log + c * (int64_t)a.n_steps + step;
+      lr->move = move;
+      lr->flags = (valid ? 1 : 0) | (accepted ? 2 : 0) | (t0acc ? 4 : 0);
+      lr->j = j;
+      lr->g = gnew;
+      lr->t0 = t0;
+      lr->dnu = valid ? dnu : 0.0;
+      lr->log_alpha = valid ? la : -INFINITY;
+    }
+
+    // ---- record after burn-in
+    if (step >= a.burn_in) {
+      double Q = 0.0;
+      for (int i = lane; i < N; i += LPC) Q += xv[i];
+      Q = group_sum<LPC>(Q);
+      const double v0 = (double)N, v1 = Q, v2 = t0;
+      acc[0] += v0;
+      acc[1] += v0 * v0;
+      acc[2] += v1;
+      acc[3] += v1 * v1;
+      acc[4] += v2;
+      acc[5] += v2 * v2;
+      const int64_t i = step - a.burn_in;
+      if (a.nb > 0 && i < (int64_t)a.nb * a.lb) {
+        bs0 += v0;
+        bs1 += v1;
+        bs2 += v2;
+        if ((i + 1) % a.lb == 0) {
+          acc[6] += bs0;
+          acc[7] += bs0 * bs0;
+          acc[8] += bs1;
+          acc[9] += bs1 * bs1;
+          acc[10] += bs2;
+          acc[11] += bs2 * bs2;
+          bs0 = bs1 = bs2 = 0.0;
+        }
+      }
+      if (lane == 0) hist[N] += 1;
+      if (a.trace && a.thin > 0 && (i % a.thin) == 0 && lane == 0) {
+        double *tr = a.trace + (c * a.n_rec + i / a.thin) * 3;
+        tr[0] = v0;
+        tr[1] = v2;
+        tr[2] = v1;
+      }
+    }
+  }
+
+  WAVE_SYNC();
+  const int kz = a.kz;
+  for (int k = lane; k < kz; k += LPC) {
+    a.z[c * kz + k] = k < N ? zg[k] : -1;
+    a.charge[c * kz + k] = k < N ? xv[k] : 0.0;
+  }
+  for (int k = lane; k <= kz; k += LPC) a.nhist[c * (kz + 1) + k] = k <= KCAP ? hist[k] : 0;
+  if (lane == 0) {
+    a.n_pe[c] = N;
+    a.t0[c] = t0;
+    for (int i = 0; i < 12; ++i) a.acc[c * 12 + i] = acc[i];
+    for (int i = 0; i < 8; ++i) a.counts[c * 8 + i] = cnt[i];
+    a.status[c] = st;
+  }
+}
+
+// ------------------------------------------------------------------ posterior
+__global__ void __launch_bounds__(256) posterior_kernel(PosteriorArgs a) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= a.n_wave) return;
+  const int S = a.n_steps - a.burn_in;
+  const int nb = S > 0 ? (int)floor(sqrt((double)S)) : 0;
+  const int lb = nb > 0 ? S / nb : 0;
+  const int C = a.n_chains;
+  uint32_t st = 0;
+  for (int v = 0; v < 3; ++v) {
+    double s1 = 0.0, s2 = 0.0, b1 = 0.0, b2 = 0.0;
+    for (int ch = 0; ch < C; ++ch) {
+      const double *ac = a.acc + (w * C + ch) * 12;
+      s1 += ac[2 * v];
+      s2 += ac[2 * v + 1];
+      b1 += ac[6 + 2 * v];
+      b2 += ac[7 + 2 * v];
+    }
+    const double n = (double)S * C;
+    const double mean = S > 0 ? s1 / n : 0.0;
+    const double var = S > 0 ? fmax(s2 / n - mean * mean, 0.0) : 0.0;
+    const double B = (double)nb * C;
+    double mcse = 0.0;
+    if (nb > 0 && B > 1.0) {
+      const double bm = b1 / (B * lb);
+      const double bv = fmax((b2 / ((double)lb * lb) - B * bm * bm) / (B - 1.0), 0.0);
+      mcse = sqrt(bv / B);
+    }
+    a.mean[w * 3 + v] = mean;
+    a.var[w * 3 + v] = var;
+    a.mcse[w * 3 + v] = mcse;
+  }
+  double prop[4] = {0, 0, 0, 0}, accp[4] = {0, 0, 0, 0};
+  for (int ch = 0; ch < C; ++ch) {
+    const int32_t *cn = a.counts + (w * C + ch) * 8;
+    for (int m = 0; m < 4; ++m) {
+      prop[m] += cn[2 * m];
+      accp[m] += cn[2 * m + 1];
+    }
+    st |= a.cstatus[w * C + ch];
+  }
+  for (int m = 0; m < 4; ++m) a.accept[w * 4 + m] = prop[m] > 0 ? accp[m] / prop[m] : 0.0;
+  if (a.p_n) {
+    const int kz = a.kz;
+    double tot = 0.0;
+    for (int ch = 0; ch < C; ++ch)
+      for (int k = 0; k <= kz; ++k) tot += a.nhist[(w * C + ch) * (kz + 1) + k];
+    for (int k = 0; k <= kz; ++k) {
+      double s = 0.0;
+      for (int ch = 0; ch < C; ++ch) s += a.nhist[(w * C + ch) * (kz + 1) + k];
+      a.p_n[w * (kz + 1) + k] = tot > 0 ? s / tot : 0.0;
+    }
+  }
+  a.status[w] = st;
+}
+
+template <int KCAP, int LPC, int WPB>
+hipError_t launch_chain_t(const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
+  constexpr int CPB = WPB * (kWave / LPC);
+  const int64_t nb = (a.n_list + CPB - 1) / CPB;
+  const size_t lds = sizeof(double) * ((size_t)a.md.M * (1 + a.md.sub) + (size_t)CPB * ChainLayout<KCAP>::kDoubles);
+  *lanes = LPC;
+  *blocks = nb;
+  if (nb == 0) return hipSuccess;
+  if (lds > 64 * 1024) {
+    // lift the default dynamic-LDS limit; gfx950 has 160 KB per workgroup
+    (void)hipFuncSetAttribute((const void *)chain_kernel<KCAP, LPC, WPB>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipGetLastError();
+  }
+  hipLaunchKernelGGL((chain_kernel<KCAP, LPC, WPB>), dim3((unsigned)nb), dim3(kWave * WPB), lds, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_prologue(const PrologueArgs &a, hipStream_t st) {
+  if (a.n_wave == 0) return hipSuccess;
+  const int64_t nb = a.n_wave < 65535 * 8 ? a.n_wave : 65535 * 8;
+  hipLaunchKernelGGL(prologue_kernel, dim3((unsigned)nb), dim3(256), sizeof(double) * a.md.M, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_posterior(const PosteriorArgs &a, hipStream_t st) {
+  if (a.n_wave == 0) return hipSuccess;
+  const int64_t nb = (a.n_wave + 255) / 256;
+  hipLaunchKernelGGL(posterior_kernel, dim3((unsigned)nb), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+int chain_kcap_for(int kmax) {
+  if (kmax <= 16) return 16;
+  if (kmax <= 32) return 32;
+  if (kmax <= 64) return 64;
+  return 0;
+}
+
+static size_t chain_lds_bytes(int kcap, int M, int sub) {
+  int lpc = kcap < 64 ? kcap : 64;
+  int cpb = 4 * (64 / lpc);
+  size_t per = (size_t)kcap * kcap + 5 * (size_t)kcap + (2 * (size_t)kcap + 2) / 2;
+  return sizeof(double) * ((size_t)M * (1 + sub) + (size_t)cpb * per);
+}
+
+bool chain_kcap_supported(int kcap, int M, int sub) {
+  if (kcap != 16 && kcap != 32 && kcap != 64) return false;
+  return chain_lds_bytes(kcap, M, sub) <= 160 * 1024;
+}
+
+hipError_t launch_chain(int kcap, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
+  switch (kcap) {
+    case 16: return launch_chain_t<16, 16, 4>(a, st, lanes, blocks);
+    case 32: return launch_chain_t<32, 32, 4>(a, st, lanes, blocks);
+    case 64: return launch_chain_t<64, 64, 4>(a, st, lanes, blocks);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fsmp

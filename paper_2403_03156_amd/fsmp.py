@@ -1,0 +1,248 @@
+"""Thin Python binding of libfsmp.so (include/fsmp.h), same names as the C ABI.
+
+Argument marshalling only: torch tensors supply device memory and the current HIP
+stream; every step of the sampler runs in the library's HIP kernels.  There is no
+fallback: if the library is missing or the device is not a gfx950, calls raise.
+"""
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfsmp.so")
+
+FSMP_OK, FSMP_EINVAL, FSMP_ENOMEM, FSMP_EDEVICE, FSMP_ENOTSUP, FSMP_EBUSY = 0, -1, -2, -3, -4, -5
+FSMP_PHI_EXP, FSMP_PHI_BIEXP = 0, 1
+FSMP_FP64, FSMP_FP32_REFRESH = 0, 1
+FSMP_REC_TRACE, FSMP_REC_LOG = 1, 2
+FSMP_ST_KMAX, FSMP_ST_NONFINITE, FSMP_ST_DRIFT, FSMP_ST_EMPTY_T, FSMP_ST_FACTOR = 1, 2, 4, 8, 16
+
+EXPORTS = ("fsmp_create", "fsmp_workspace_bytes", "fsmp_sample", "fsmp_posterior", "fsmp_last_timings",
+           "fsmp_set_timing", "fsmp_last_error", "fsmp_destroy", "fsmp_version")
+
+
+class fsmp_ser(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("sigma", ctypes.c_double), ("tau", ctypes.c_double),
+                ("amplitude", ctypes.c_double), ("support", ctypes.c_int32)]
+
+
+class fsmp_intensity(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("tau_rise", ctypes.c_double), ("tau_decay", ctypes.c_double),
+                ("t0_min", ctypes.c_double), ("t0_max", ctypes.c_double)]
+
+
+class fsmp_config(ctypes.Structure):
+    _fields_ = [("sigma_eps", ctypes.c_double), ("mu_q", ctypes.c_double), ("sigma_q", ctypes.c_double),
+                ("grid_sub", ctypes.c_int32), ("jump_J", ctypes.c_double), ("t0_step_sd", ctypes.c_double),
+                ("shift_sd", ctypes.c_double), ("k_max", ctypes.c_int32), ("n_steps", ctypes.c_int32),
+                ("n_chains", ctypes.c_int32), ("burn_in", ctypes.c_int32), ("thin", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("refresh_M", ctypes.c_int32), ("record_flags", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64)]
+
+
+class fsmp_batch(ctypes.Structure):
+    _fields_ = [("n_wave", ctypes.c_int64), ("wave", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("lambda_", ctypes.c_void_p), ("kmax", ctypes.c_void_p), ("g_range", ctypes.c_void_p),
+                ("t0_init", ctypes.c_void_p), ("wave_id", ctypes.c_void_p)]
+
+
+class fsmp_samples(ctypes.Structure):
+    _fields_ = [("n_pe", ctypes.c_void_p), ("t0", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("charge", ctypes.c_void_p), ("acc", ctypes.c_void_p), ("nhist", ctypes.c_void_p),
+                ("counts", ctypes.c_void_p), ("status", ctypes.c_void_p), ("log", ctypes.c_void_p),
+                ("trace", ctypes.c_void_p), ("kz", ctypes.c_int32)]
+
+
+class fsmp_posterior_out(ctypes.Structure):
+    _fields_ = [("mean", ctypes.c_void_p), ("var", ctypes.c_void_p), ("mcse", ctypes.c_void_p),
+                ("p_n", ctypes.c_void_p), ("accept", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
+class fsmp_timing(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("kcap", ctypes.c_int32), ("lanes", ctypes.c_int32),
+                ("chains", ctypes.c_int64), ("blocks", ctypes.c_int64), ("ms", ctypes.c_double)]
+
+
+LOGREC_DTYPE = np.dtype([("move", "<i4"), ("flags", "<i4"), ("j", "<i4"), ("g", "<i4"),
+                         ("t0", "<f8"), ("dnu", "<f8"), ("log_alpha", "<f8")], align=True)
+
+_lib = None
+
+
+class FsmpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fsmp status {status}: {msg}")
+        self.status = status
+
+
+def load(path: Optional[str] = None):
+    """Load libfsmp.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise FileNotFoundError(f"{p} is not built; run python -m paper_2403_03156_amd.build")
+    L = ctypes.CDLL(p)
+    P = ctypes.POINTER
+    L.fsmp_create.argtypes = [P(ctypes.c_void_p), P(fsmp_ser), P(fsmp_intensity), P(fsmp_config), ctypes.c_int]
+    L.fsmp_create.restype = ctypes.c_int
+    L.fsmp_workspace_bytes.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64]
+    L.fsmp_workspace_bytes.restype = ctypes.c_size_t
+    L.fsmp_sample.argtypes = [ctypes.c_void_p, P(fsmp_batch), P(fsmp_samples), ctypes.c_void_p]
+    L.fsmp_sample.restype = ctypes.c_int
+    L.fsmp_posterior.argtypes = [ctypes.c_void_p, ctypes.c_int64, P(fsmp_samples), P(fsmp_posterior_out),
+                                 ctypes.c_void_p]
+    L.fsmp_posterior.restype = ctypes.c_int
+    L.fsmp_last_timings.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+    L.fsmp_last_timings.restype = ctypes.c_int32
+    L.fsmp_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.fsmp_set_timing.restype = ctypes.c_int
+    L.fsmp_last_error.argtypes = [ctypes.c_void_p]
+    L.fsmp_last_error.restype = ctypes.c_char_p
+    L.fsmp_destroy.argtypes = [ctypes.c_void_p]
+    L.fsmp_destroy.restype = None
+    L.fsmp_version.argtypes = []
+    L.fsmp_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _hptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def fsmp_create(ser: fsmp_ser, phi: fsmp_intensity, cfg: fsmp_config, device: int = 0):
+    L = load()
+    h = ctypes.c_void_p()
+    s = L.fsmp_create(ctypes.byref(h), ctypes.byref(ser), ctypes.byref(phi), ctypes.byref(cfg), device)
+    if s != FSMP_OK:
+        raise FsmpError(s, L.fsmp_last_error(None).decode())
+    return h
+
+
+class Sampler:
+    """Owns one fsmp_ctx; ``sample`` takes a device waveform tensor and host metadata."""
+
+    def __init__(self, ser=(8.0, 1.5, 6.0), ser_amp=1.0, ser_support=0, phi_kind=FSMP_PHI_EXP, tau_rise=0.0,
+                 tau_decay=20.0, t0_min=50.0, t0_max=100.0, sigma_eps=0.1, mu_q=1.0, sigma_q=0.3, grid_sub=4,
+                 jump_J=0.25, t0_step_sd=1.0, shift_sd=1.0, k_max=32, n_steps=2000, n_chains=1, burn_in=None,
+                 thin=1, precision=FSMP_FP64, refresh_M=64, record_flags=0, seed=0, device=0):
+        self.lib = load()
+        self.ser = fsmp_ser(ser[0], ser[1], ser[2], ser_amp, ser_support)
+        self.phi = fsmp_intensity(phi_kind, tau_rise, tau_decay, t0_min, t0_max)
+        if burn_in is None:
+            burn_in = n_steps // 2
+        self.cfg = fsmp_config(sigma_eps, mu_q, sigma_q, grid_sub, jump_J, t0_step_sd, shift_sd, k_max, n_steps,
+                               n_chains, burn_in, thin, precision, refresh_M, record_flags, seed)
+        self.device = device
+        self.h = fsmp_create(self.ser, self.phi, self.cfg, device)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fsmp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, s):
+        if s != FSMP_OK:
+            raise FsmpError(s, self.lib.fsmp_last_error(self.h).decode())
+
+    def set_timing(self, on: bool):
+        self._check(self.lib.fsmp_set_timing(self.h, 1 if on else 0))
+
+    def last_timings(self):
+        n = self.lib.fsmp_last_timings(self.h, None, 0)
+        arr = (fsmp_timing * max(n, 1))()
+        self.lib.fsmp_last_timings(self.h, arr, n)
+        return [{"name": t.name.decode(), "kcap": t.kcap, "lanes": t.lanes, "chains": t.chains, "blocks": t.blocks,
+                 "ms": t.ms} for t in arr[:n]]
+
+    def alloc_samples(self, n_wave, kz):
+        import torch
+        dev = torch.device("cuda", self.device)
+        C = n_wave * self.cfg.n_chains
+        S = self.cfg.n_steps - self.cfg.burn_in
+        out = {
+            "n_pe": torch.zeros(C, dtype=torch.int32, device=dev),
+            "t0": torch.zeros(C, dtype=torch.float64, device=dev),
+            "z": torch.zeros((C, kz), dtype=torch.int32, device=dev),
+            "charge": torch.zeros((C, kz), dtype=torch.float64, device=dev),
+            "acc": torch.zeros((C, 12), dtype=torch.float64, device=dev),
+            "nhist": torch.zeros((C, kz + 1), dtype=torch.int32, device=dev),
+            "counts": torch.zeros((C, 8), dtype=torch.int32, device=dev),
+            "status": torch.zeros(C, dtype=torch.int32, device=dev),
+            "log": None, "trace": None, "kz": kz,
+        }
+        if self.cfg.record_flags & FSMP_REC_LOG:
+            out["log"] = torch.zeros((C, self.cfg.n_steps * LOGREC_DTYPE.itemsize), dtype=torch.uint8, device=dev)
+        if self.cfg.record_flags & FSMP_REC_TRACE:
+            n_rec = (S + self.cfg.thin - 1) // self.cfg.thin if S > 0 else 0
+            out["trace"] = torch.zeros((C, max(n_rec, 1), 3), dtype=torch.float64, device=dev)
+        return out
+
+    def sample(self, wave, offsets, lam, kmax=None, g_range=None, t0_init=None, wave_id=None, out=None, kz=None,
+               stream=None):
+        """wave: torch float32 device tensor; offsets/lam/kmax/g_range/t0_init/wave_id: host numpy arrays."""
+        import torch
+        if not wave.is_cuda or wave.dtype != torch.float32 or not wave.is_contiguous():
+            raise ValueError("wave must be a contiguous float32 device tensor")
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        n = len(offsets) - 1
+        kmax = None if kmax is None else np.ascontiguousarray(kmax, dtype=np.int32)
+        g_range = None if g_range is None else np.ascontiguousarray(g_range, dtype=np.int32).reshape(-1)
+        t0_init = None if t0_init is None else np.ascontiguousarray(t0_init, dtype=np.float64)
+        wave_id = None if wave_id is None else np.ascontiguousarray(wave_id, dtype=np.uint64)
+        if kz is None:
+            kz = int(kmax.max()) if kmax is not None and n > 0 else self.cfg.k_max
+        if out is None:
+            out = self.alloc_samples(n, kz)
+        b = fsmp_batch(n, ctypes.c_void_p(wave.data_ptr()), _hptr(offsets), _hptr(lam), _hptr(kmax), _hptr(g_range),
+                       _hptr(t0_init), _hptr(wave_id))
+        s = fsmp_samples(_dptr(out["n_pe"]), _dptr(out["t0"]), _dptr(out["z"]), _dptr(out["charge"]),
+                         _dptr(out["acc"]), _dptr(out["nhist"]), _dptr(out["counts"]), _dptr(out["status"]),
+                         _dptr(out["log"]), _dptr(out["trace"]), out["kz"])
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._keep = (offsets, lam, kmax, g_range, t0_init, wave_id)
+        self._check(self.lib.fsmp_sample(self.h, ctypes.byref(b), ctypes.byref(s), ctypes.c_void_p(st.cuda_stream)))
+        return out
+
+    def posterior(self, n_wave, samples, with_pn=True, stream=None):
+        import torch
+        dev = torch.device("cuda", self.device)
+        kz = samples["kz"]
+        res = {
+            "mean": torch.zeros((n_wave, 3), dtype=torch.float64, device=dev),
+            "var": torch.zeros((n_wave, 3), dtype=torch.float64, device=dev),
+            "mcse": torch.zeros((n_wave, 3), dtype=torch.float64, device=dev),
+            "p_n": torch.zeros((n_wave, kz + 1), dtype=torch.float64, device=dev) if with_pn else None,
+            "accept": torch.zeros((n_wave, 4), dtype=torch.float64, device=dev),
+            "status": torch.zeros(n_wave, dtype=torch.int32, device=dev),
+        }
+        s = fsmp_samples(_dptr(samples["n_pe"]), _dptr(samples["t0"]), _dptr(samples["z"]), _dptr(samples["charge"]),
+                         _dptr(samples["acc"]), _dptr(samples["nhist"]), _dptr(samples["counts"]),
+                         _dptr(samples["status"]), _dptr(samples["log"]), _dptr(samples["trace"]), kz)
+        po = fsmp_posterior_out(_dptr(res["mean"]), _dptr(res["var"]), _dptr(res["mcse"]), _dptr(res["p_n"]),
+                                _dptr(res["accept"]), _dptr(res["status"]))
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._check(self.lib.fsmp_posterior(self.h, n_wave, ctypes.byref(s), ctypes.byref(po),
+                                            ctypes.c_void_p(st.cuda_stream)))
+        return res
+
+
+def log_records(t):
+    """View a device log tensor (uint8 [chains][n_steps*40]) as a numpy structured array."""
+    a = t.cpu().numpy()
+    return a.view(LOGREC_DTYPE).reshape(a.shape[0], -1)
