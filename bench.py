@@ -1,0 +1,166 @@
+"""Benchmark of the FSMP hot path on one MI355X.
+
+One step = one pass of the whole path over one batch: fsmp_sample (prologue +
+chain kernels: every chain's Gibbs / RJMCMC sweeps) and fsmp_posterior, over the
+batched workload (100,000 waveforms x 1,024 samples, lambda ~ logU[0.1, 30],
+rise 2 / decay 25 ns light curve, 4 chains x 1,000 sweeps, FP64), with the
+waveforms already resident in device memory when the timed region starts.
+
+Prints one JSON line: waveforms/s (whole job) plus MCMC steps/s, the roofline
+of the dominant kernel (measured with HIP events on its stream inside the timed
+region) and the oracle timed on the host cores over a bounded sample.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload batched]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64 = 78.6e12  # MI355X dense FP64 vector, FLOP/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batched")
+    ap.add_argument("--n-wave", type=int, default=0, help="override the workload's waveform count")
+    ap.add_argument("--chain-steps", type=int, default=0, help="override the sweeps per chain")
+    ap.add_argument("--cpu-wave", type=int, default=2000, help="waveforms in the oracle's timed sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def algorithmic_flops(work):
+    """FP64 flops of the PE-space linear algebra: 2K^2 per K x K mat-vec, 2K^2 per rank-one
+    edit of the symmetric inverse Gram matrix, 4K^2 per rank-two edit."""
+    return 2.0 * work[:, 0].sum() + 2.0 * work[:, 1].sum() + 4.0 * work[:, 2].sum()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              f"(the sampler has no cross-GPU path: waveforms are independent)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import oracle
+    from paper_2403_03156_amd import fsmp, synth
+
+    wl = synth.PRESETS[args.workload]
+    n_wave = args.n_wave or wl.n_wave
+    n_steps = args.chain_steps or wl.n_steps
+    burn = n_steps // 2
+    t_gen = time.time()
+    b = synth.generate(wl, n_wave=n_wave, seed=wl.seed)
+    km = synth.kmax_for(b["lam"])
+    kz = int(km.max())
+    print(f"[bench] generated {n_wave} waveforms in {time.time() - t_gen:.1f}s; kmax buckets "
+          f"{dict(zip(*np.unique(km, return_counts=True)))}", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda", 0)
+    wave = torch.from_numpy(b["wave"]).to(dev)
+    smp = fsmp.Sampler(ser=wl.ser, phi_kind=wl.phi_kind, tau_rise=wl.tau_rise, tau_decay=wl.tau_decay,
+                       t0_min=wl.t0_min, t0_max=wl.t0_max, sigma_eps=wl.sigma_eps, mu_q=wl.mu_q, sigma_q=wl.sigma_q,
+                       n_steps=n_steps, n_chains=wl.n_chains, burn_in=burn, seed=wl.seed, device=0)
+    out = smp.alloc_samples(n_wave, kz, work=True)
+    stream = torch.cuda.current_stream(dev)
+
+    def one_step():
+        smp.sample(wave, b["offsets"], b["lam"], kmax=km, kz=kz, out=out, stream=stream)
+        return smp.posterior(n_wave, out, with_pn=False, stream=stream)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    smp.set_timing(True)
+    kernel_ms = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        post = one_step()
+        for t in smp.last_timings():  # waits for this step's kernels (events on the same stream)
+            kernel_ms.setdefault(t["name"], []).append(t)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    smp.set_timing(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    chain_steps = n_wave * wl.n_chains * n_steps
+    wps = n_wave / (ms_per_step / 1e3)
+    sps = chain_steps / (ms_per_step / 1e3)
+
+    # ---- dominant kernel roofline (algorithmic FP64 flops of its chains / its mean duration)
+    work = out["work"].cpu().numpy()
+    chain_kcap = np.repeat(np.where(km <= 16, 16, np.where(km <= 32, 32, 64)), wl.n_chains)
+    avg = {name: float(np.mean([t["ms"] for t in ts])) for name, ts in kernel_ms.items()}
+    dom = max(avg, key=avg.get)
+    dom_t = kernel_ms[dom][0]
+    if dom_t["kcap"] > 0:
+        flops = algorithmic_flops(work[chain_kcap == dom_t["kcap"]])
+    else:
+        flops = 0.0
+    achieved = flops / (avg[dom] / 1e3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64, "traffic": None, "kernel": dom, "kernel_ms": avg[dom],
+                "flops_per_launch": flops}
+    print(f"[bench] kernels (mean ms): {json.dumps(avg)}", file=sys.stderr, flush=True)
+
+    # ---- oracle on a bounded sample of the same workload (first cpu_wave waveforms, same chains)
+    cpu = None
+    if not args.no_cpu:
+        m = min(args.cpu_wave, n_wave)
+        off = b["offsets"][: m + 1]
+        p = oracle.make_params(ser=wl.ser, sigma_eps=wl.sigma_eps, mu_q=wl.mu_q, sigma_q=wl.sigma_q,
+                               phi_kind=wl.phi_kind, tau_rise=wl.tau_rise, tau_decay=wl.tau_decay,
+                               t0_min=wl.t0_min, t0_max=wl.t0_max)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        tc = time.perf_counter()
+        o = oracle.run(p, b["wave"][: off[-1]], off, b["lam"][:m], wl.n_chains, n_steps, burn, wl.seed, kz,
+                       kmax=km[:m], n_threads=threads)
+        dt = time.perf_counter() - tc
+        # the sampled chains are the same chains the GPU ran: they must agree exactly
+        same = (out["z"][: m * wl.n_chains].cpu().numpy() == o.z).all(1).mean()
+        cpu = {"value": m / dt, "unit": "waveforms/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {m} of the {n_wave} waveforms, {wl.n_chains} chains x {n_steps} sweeps, "
+                         f"{dt:.1f}s; {same * 100:.2f}% of its chains identical to the GPU's",
+               "steps_per_s": m * wl.n_chains * n_steps / dt}
+        print(f"[bench] oracle {m} waveforms in {dt:.1f}s on {threads} threads", file=sys.stderr, flush=True)
+
+    res = {
+        "metric": "waveforms/s and MCMC steps/s at matched posterior accuracy; p99 event latency",
+        "value": wps,
+        "unit": "waveforms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {n_wave} waveforms x {wl.lengths} samples, lambda {wl.lam_dist}"
+                               f"[{wl.lam_lo}, {wl.lam_hi}], {wl.n_chains} chains x {n_steps} sweeps, FP64",
+                   "n_wave": n_wave, "chains": wl.n_chains, "sweeps": n_steps, "parallelism": "single GPU"},
+        "mcmc_steps_per_s": sps,
+        "kernel_ms": avg,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -153,7 +153,11 @@ typedef struct {
  *   status[chain]         FSMP_ST_* bits
  *   log                   NULL, or [chain][n_steps] fsmp_logrec when FSMP_REC_LOG
  *   trace                 NULL, or [chain][n_rec][3] (N, t0, Q) every `thin` recorded steps
- *                         when FSMP_REC_TRACE, n_rec = ceil((n_steps - burn_in) / thin) */
+ *                         when FSMP_REC_TRACE, n_rec = ceil((n_steps - burn_in) / thin)
+ *   work                  NULL, or [chain][4] work counters over all steps: sum of K^2 over
+ *                         proposals evaluated with a K x K mat-vec, sum of K^2 over rank-one
+ *                         edits (accepted births and deaths), sum of K^2 over rank-two edits
+ *                         (accepted updates), sum of K over t0 proposals inside the prior */
 typedef struct {
   int32_t *n_pe;
   double *t0;
@@ -166,6 +170,7 @@ typedef struct {
   fsmp_logrec *log;
   double *trace;
   int32_t kz;
+  double *work;
 } fsmp_samples;
 
 /* Posterior summaries per waveform (device buffers, caller-allocated): for (N, Q, t0)
@@ -214,8 +219,10 @@ fsmp_status fsmp_sample(fsmp_ctx *ctx, const fsmp_batch *batch, const fsmp_sampl
 fsmp_status fsmp_posterior(fsmp_ctx *ctx, int64_t n_wave, const fsmp_samples *in, fsmp_posterior_out *out,
                            void *hip_stream);
 
-/* Kernel timings of the last fsmp_sample: writes up to `cap` entries, returns how many
- * kernels ran (timings are taken only when `enable` was set by fsmp_set_timing). */
+/* Kernel timings of the last fsmp_sample: waits for its kernels, writes up to `cap`
+ * entries and returns how many kernels ran.  Timings are taken (HIP events recorded on
+ * the call's stream around each launch, no synchronisation inside fsmp_sample) only
+ * while fsmp_set_timing(ctx, 1) is in effect. */
 int32_t fsmp_last_timings(const fsmp_ctx *ctx, fsmp_timing *out, int32_t cap);
 fsmp_status fsmp_set_timing(fsmp_ctx *ctx, int32_t enable);
 

@@ -156,6 +156,7 @@ struct fsmp_ctx {
   bool stage_pending = false;
   bool timing = false;
   std::vector<fsmp_timing> timings;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> timing_events;
   std::vector<hipEvent_t> evpool;
   std::string err = "no error";
 };
@@ -352,8 +353,16 @@ fsmp_status fsmp_set_timing(fsmp_ctx *c, int32_t enable) {
   return FSMP_OK;
 }
 
-int32_t fsmp_last_timings(const fsmp_ctx *c, fsmp_timing *out, int32_t cap) {
-  if (!c) return 0;
+int32_t fsmp_last_timings(const fsmp_ctx *cc, fsmp_timing *out, int32_t cap) {
+  if (!cc) return 0;
+  fsmp_ctx *c = const_cast<fsmp_ctx *>(cc);
+  for (size_t i = 0; i < c->timings.size() && i < c->timing_events.size(); ++i) {
+    auto &pr = c->timing_events[i];
+    if (!pr.first || !pr.second) continue;
+    if (hipEventSynchronize(pr.second) != hipSuccess) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) c->timings[i].ms = ms;
+  }
   const int32_t n = (int32_t)c->timings.size();
   for (int32_t i = 0; i < n && i < cap && out; ++i) out[i] = c->timings[i];
   return n;
@@ -425,6 +434,7 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
       return fail(c, FSMP_ENOTSUP, "SER support %d too long for PE capacity %d", c->tab.LV, caps[bi]);
   if (n == 0) {
     c->timings.clear();
+    c->timing_events.clear();
     return FSMP_OK;
   }
 
@@ -482,6 +492,7 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   }
 
   c->timings.clear();
+  c->timing_events.clear();
   size_t ev = 0;
   auto timed = [&](const char *name, int kcap, auto &&launch) -> hipError_t {
     fsmp_timing t{};
@@ -494,14 +505,9 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
       if (e0) (void)hipEventRecord(e0, st);
     }
     hipError_t r = launch(t);
-    if (c->timing && e1) {
-      (void)hipEventRecord(e1, st);
-      (void)hipEventSynchronize(e1);
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      t.ms = ms;
-    }
+    if (c->timing && e1) (void)hipEventRecord(e1, st);
     c->timings.push_back(t);
+    c->timing_events.push_back({c->timing ? e0 : nullptr, c->timing ? e1 : nullptr});
     return r;
   };
 
@@ -557,6 +563,7 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   ca.trace = (cf.record_flags & FSMP_REC_TRACE) ? o->trace : nullptr;
   ca.kz = o->kz;
   ca.wflags = c->wflags.p;
+  ca.work = o->work;
   for (int bi = 0; bi < 3 && e == hipSuccess; ++bi) {
     const int64_t cnt = bucket_start[bi + 1] - bucket_start[bi];
     if (cnt == 0) continue;

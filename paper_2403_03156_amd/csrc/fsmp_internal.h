@@ -56,6 +56,7 @@ struct ChainArgs {
   double *trace;
   int32_t kz;
   const uint32_t *wflags;  // per waveform, from the prologue (FSMP_ST_NONFINITE)
+  double *work;            // optional [chain][4]
 };
 
 struct PrologueArgs {

@@ -268,6 +268,7 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
   int cnt[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) cnt[i] = 0;
+  double wk0 = 0.0, wk1 = 0.0, wk2 = 0.0, wk3 = 0.0;
 
   for (int step = 0; step < n_steps; ++step) {
     uint32_t r[8];
@@ -282,6 +283,7 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
     bool t0acc = false;
     cnt[0]++;
     if (t0p >= md.t0_min && t0p <= md.t0_max) {
+      wk3 += N;
       double part = 0.0;
       int bad = 0;
       for (int i = lane; i < N; i += LPC) {
@@ -323,6 +325,7 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
           const double d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
           beta = mf[gnew - glo] + md.rhom;
           WAVE_SYNC();
+          wk0 += (double)N * N;
           double q = 0.0, p = 0.0;
           for (int i = lane; i < N; i += LPC) {
             double e = 0.0;
@@ -374,6 +377,7 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
               const double d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
               beta = mf[gnew - glo] + md.rhom;
               WAVE_SYNC();
+              wk0 += (double)N * N;
               double q = 0.0, p = 0.0;
               for (int i = lane; i < N; i += LPC) {
                 double e = 0.0;
@@ -408,6 +412,8 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
       accepted = true;
       cnt[2 * move + 1]++;
       WAVE_SYNC();
+      if (move == 1 || move == 2) wk1 += (double)N * N;
+      else if (sh != 0) wk2 += (double)N * N;
       if (move == 1) {
         const double inv_d2 = 1.0 / delta2;
         const double xn = up * inv_d2;
@@ -548,6 +554,12 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
     for (int i = 0; i < 12; ++i) a.acc[c * 12 + i] = acc[i];
     for (int i = 0; i < 8; ++i) a.counts[c * 8 + i] = cnt[i];
     a.status[c] = st;
+    if (a.work) {
+      a.work[c * 4 + 0] = wk0;
+      a.work[c * 4 + 1] = wk1;
+      a.work[c * 4 + 2] = wk2;
+      a.work[c * 4 + 3] = wk3;
+    }
   }
 }
 

@@ -52,7 +52,7 @@ class fsmp_samples(ctypes.Structure):
     _fields_ = [("n_pe", ctypes.c_void_p), ("t0", ctypes.c_void_p), ("z", ctypes.c_void_p),
                 ("charge", ctypes.c_void_p), ("acc", ctypes.c_void_p), ("nhist", ctypes.c_void_p),
                 ("counts", ctypes.c_void_p), ("status", ctypes.c_void_p), ("log", ctypes.c_void_p),
-                ("trace", ctypes.c_void_p), ("kz", ctypes.c_int32)]
+                ("trace", ctypes.c_void_p), ("kz", ctypes.c_int32), ("work", ctypes.c_void_p)]
 
 
 class fsmp_posterior_out(ctypes.Structure):
@@ -169,7 +169,7 @@ class Sampler:
         return [{"name": t.name.decode(), "kcap": t.kcap, "lanes": t.lanes, "chains": t.chains, "blocks": t.blocks,
                  "ms": t.ms} for t in arr[:n]]
 
-    def alloc_samples(self, n_wave, kz):
+    def alloc_samples(self, n_wave, kz, work=False):
         import torch
         dev = torch.device("cuda", self.device)
         C = n_wave * self.cfg.n_chains
@@ -184,6 +184,7 @@ class Sampler:
             "counts": torch.zeros((C, 8), dtype=torch.int32, device=dev),
             "status": torch.zeros(C, dtype=torch.int32, device=dev),
             "log": None, "trace": None, "kz": kz,
+            "work": torch.zeros((C, 4), dtype=torch.float64, device=dev) if work else None,
         }
         if self.cfg.record_flags & FSMP_REC_LOG:
             out["log"] = torch.zeros((C, self.cfg.n_steps * LOGREC_DTYPE.itemsize), dtype=torch.uint8, device=dev)
@@ -193,7 +194,7 @@ class Sampler:
         return out
 
     def sample(self, wave, offsets, lam, kmax=None, g_range=None, t0_init=None, wave_id=None, out=None, kz=None,
-               stream=None):
+               stream=None, work=False):
         """wave: torch float32 device tensor; offsets/lam/kmax/g_range/t0_init/wave_id: host numpy arrays."""
         import torch
         if not wave.is_cuda or wave.dtype != torch.float32 or not wave.is_contiguous():
@@ -208,12 +209,12 @@ class Sampler:
         if kz is None:
             kz = int(kmax.max()) if kmax is not None and n > 0 else self.cfg.k_max
         if out is None:
-            out = self.alloc_samples(n, kz)
+            out = self.alloc_samples(n, kz, work=work)
         b = fsmp_batch(n, ctypes.c_void_p(wave.data_ptr()), _hptr(offsets), _hptr(lam), _hptr(kmax), _hptr(g_range),
                        _hptr(t0_init), _hptr(wave_id))
         s = fsmp_samples(_dptr(out["n_pe"]), _dptr(out["t0"]), _dptr(out["z"]), _dptr(out["charge"]),
                          _dptr(out["acc"]), _dptr(out["nhist"]), _dptr(out["counts"]), _dptr(out["status"]),
-                         _dptr(out["log"]), _dptr(out["trace"]), out["kz"])
+                         _dptr(out["log"]), _dptr(out["trace"]), out["kz"], _dptr(out.get("work")))
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._keep = (offsets, lam, kmax, g_range, t0_init, wave_id)
         self._check(self.lib.fsmp_sample(self.h, ctypes.byref(b), ctypes.byref(s), ctypes.c_void_p(st.cuda_stream)))
@@ -233,7 +234,8 @@ class Sampler:
         }
         s = fsmp_samples(_dptr(samples["n_pe"]), _dptr(samples["t0"]), _dptr(samples["z"]), _dptr(samples["charge"]),
                          _dptr(samples["acc"]), _dptr(samples["nhist"]), _dptr(samples["counts"]),
-                         _dptr(samples["status"]), _dptr(samples["log"]), _dptr(samples["trace"]), kz)
+                         _dptr(samples["status"]), _dptr(samples["log"]), _dptr(samples["trace"]), kz,
+                         _dptr(samples.get("work")))
         po = fsmp_posterior_out(_dptr(res["mean"]), _dptr(res["var"]), _dptr(res["mcse"]), _dptr(res["p_n"]),
                                 _dptr(res["accept"]), _dptr(res["status"]))
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
