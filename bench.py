@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--workload", default="batched")
     ap.add_argument("--n-wave", type=int, default=0, help="override the workload's waveform count")
     ap.add_argument("--chain-steps", type=int, default=0, help="override the sweeps per chain")
-    ap.add_argument("--cpu-wave", type=int, default=2000, help="waveforms in the oracle's timed sample")
+X
     ap.add_argument("--no-cpu", action="store_true")
     return ap.parse_args()
 
@@ -103,7 +103,8 @@ def main():
 
     # ---- dominant kernel roofline (algorithmic FP64 flops of its chains / its mean duration)
     work = out["work"].cpu().numpy()
-    chain_kcap = np.repeat(np.where(km <= 16, 16, np.where(km <= 32, 32, 64)), wl.n_chains)
+    caps = np.asarray(synth.KCAPS)
+    chain_kcap = np.repeat(caps[np.searchsorted(caps, km)], wl.n_chains)
     avg = {name: float(np.mean([t["ms"] for t in ts])) for name, ts in kernel_ms.items()}
     dom = max(avg, key=avg.get)
     dom_t = kernel_ms[dom][0]

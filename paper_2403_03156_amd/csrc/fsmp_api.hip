@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -151,6 +152,11 @@ struct fsmp_ctx {
   DevBuf<int32_t> kmax, grange, chains;
   DevBuf<uint64_t> wid;
   DevBuf<uint32_t> wflags;
+  DevBuf<double> lane_d;
+  DevBuf<int32_t> lane_i;
+  // per PE capacity (kCaps): 1 = one lane per chain (state in device memory),
+  // 0 = one lane group per chain (state in LDS; capacities up to 64)
+  int design[kNumCaps] = {1, 1, 0, 0, 1, 1, 1, 1};
   PinBuf stage;
   hipEvent_t stage_done = nullptr;
   bool stage_pending = false;
@@ -295,6 +301,17 @@ fsmp_status fsmp_create(fsmp_ctx **out, const fsmp_ser *ser, const fsmp_intensit
     return fail(nullptr, FSMP_EINVAL, "%s", m.c_str());
   }
   fill_model(c);
+  if (const char *d = std::getenv("FSMP_CHAIN_DESIGN")) {
+    // tuning override: "lane", "group", or three letters l/g for the 16/32/64 capacities
+    // (one letter l / g per capacity in kCaps order; g only where a lane-group instance exists)
+    const size_t L = std::strlen(d);
+    for (int q = 0; q < kNumCaps; ++q) {
+      const char ch = std::strcmp(d, "lane") == 0 ? 'l' : std::strcmp(d, "group") == 0 ? 'g' : (q < (int)L ? d[q] : 'l');
+      c->design[q] = (ch == 'g' && kCaps[q] <= 64) ? 0 : 1;
+    }
+    c->design[2] = 0;  // capacity 48 has only the lane-group kernel
+
+  }
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(device);
@@ -335,6 +352,8 @@ void fsmp_destroy(fsmp_ctx *c) {
   c->chains.release();
   c->wid.release();
   c->wflags.release();
+  c->lane_d.release();
+  c->lane_i.release();
   c->stage.release();
   (void)hipSetDevice(prev);
   delete c;
@@ -414,23 +433,30 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     mfo[i + 1] = mfo[i] + (lo <= hi ? (int64_t)(hi - lo + 1) : 0);
   }
   // ---- chains grouped by PE capacity
-  const int caps[3] = {16, 32, 64};
+  const int *caps = kCaps;
   std::vector<int32_t> order;
   order.reserve((size_t)n * cf.n_chains);
-  int64_t bucket_start[4] = {0, 0, 0, 0};
-  for (int bi = 0; bi < 3; ++bi) {
+  int64_t bucket_start[kNumCaps + 1] = {0};
+  // within a bucket, waveforms in order of lambda: neighbouring lanes then carry chains of
+  // similar PE counts, which keeps the lane-per-chain loops (bounded by the largest K in a
+  // wavefront) short
+  std::vector<int64_t> wsorted(n);
+  for (int64_t i = 0; i < n; ++i) wsorted[i] = i;
+  std::stable_sort(wsorted.begin(), wsorted.end(), [&](int64_t x, int64_t y) { return b->lambda[x] < b->lambda[y]; });
+  for (int bi = 0; bi < kNumCaps; ++bi) {
     bucket_start[bi] = (int64_t)order.size();
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t ii = 0; ii < n; ++ii) {
+      const int64_t i = wsorted[ii];
       if (chain_kcap_for(kmx[i]) != caps[bi]) continue;
       for (int ch = 0; ch < cf.n_chains; ++ch) order.push_back((int32_t)(i * cf.n_chains + ch));
     }
   }
-  bucket_start[3] = (int64_t)order.size();
+  bucket_start[kNumCaps] = (int64_t)order.size();
   if ((int64_t)order.size() != n * cf.n_chains)
-    return fail(c, FSMP_ENOTSUP, "kmax above 64 is not provided by this build");
+    return fail(c, FSMP_ENOTSUP, "kmax above %d is not provided by this build", kCaps[kNumCaps - 1]);
   if (n * (int64_t)cf.n_chains > INT32_MAX) return fail(c, FSMP_EINVAL, "too many chains");
-  for (int bi = 0; bi < 3; ++bi)
-    if (bucket_start[bi + 1] > bucket_start[bi] && !chain_kcap_supported(caps[bi], c->tab.M, sub))
+  for (int bi = 0; bi < kNumCaps; ++bi)
+    if (bucket_start[bi + 1] > bucket_start[bi] && c->design[bi] == 0 && !chain_kcap_supported(caps[bi], c->tab.M, sub))
       return fail(c, FSMP_ENOTSUP, "SER support %d too long for PE capacity %d", c->tab.LV, caps[bi]);
   if (n == 0) {
     c->timings.clear();
@@ -454,6 +480,16 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   if (e == hipSuccess) e = c->wflags.ensure(n);
   if (e == hipSuccess) e = c->mf.ensure((size_t)std::max<int64_t>(mfo[n], 1));
   if (e == hipSuccess) e = c->chains.ensure(order.size());
+  size_t lane_doff[kNumCaps + 1] = {0}, lane_ioff[kNumCaps + 1] = {0};
+  {
+    for (int bi = 0; bi < kNumCaps; ++bi) {
+      const int64_t cnt = c->design[bi] == 1 ? bucket_start[bi + 1] - bucket_start[bi] : 0;
+      lane_doff[bi + 1] = lane_doff[bi] + lane_ws_doubles(caps[bi], cnt);
+      lane_ioff[bi + 1] = lane_ioff[bi] + lane_ws_ints(caps[bi], cnt);
+    }
+    if (e == hipSuccess && lane_doff[kNumCaps] > 0) e = c->lane_d.ensure(lane_doff[kNumCaps]);
+    if (e == hipSuccess && lane_ioff[kNumCaps] > 0) e = c->lane_i.ensure(lane_ioff[kNumCaps]);
+  }
   if (e != hipSuccess) {
     (void)hipSetDevice(prev);
     return fail(c, FSMP_ENOMEM, "workspace allocation failed: %s", hipGetErrorString(e));
@@ -564,16 +600,22 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   ca.kz = o->kz;
   ca.wflags = c->wflags.p;
   ca.work = o->work;
-  for (int bi = 0; bi < 3 && e == hipSuccess; ++bi) {
+  for (int bi = 0; bi < kNumCaps && e == hipSuccess; ++bi) {
     const int64_t cnt = bucket_start[bi + 1] - bucket_start[bi];
     if (cnt == 0) continue;
     ca.chains = c->chains.p + bucket_start[bi];
     ca.n_list = cnt;
     char name[32];
-    std::snprintf(name, sizeof name, "chain_k%d", caps[bi]);
+    const int lane = c->design[bi];
+    std::snprintf(name, sizeof name, "%s_k%d", lane ? "chain_lane" : "chain_group", caps[bi]);
+    if (lane) {
+      ca.dws = c->lane_d.p + lane_doff[bi];
+      ca.iws = c->lane_i.p + lane_ioff[bi];
+    }
     e = timed(name, caps[bi], [&](fsmp_timing &t) {
       t.chains = cnt;
-      return launch_chain(caps[bi], ca, st, &t.lanes, &t.blocks);
+      return lane ? launch_chain_lane(caps[bi], ca, st, &t.lanes, &t.blocks)
+                  : launch_chain(caps[bi], ca, st, &t.lanes, &t.blocks);
     });
   }
   (void)hipSetDevice(prev);

@@ -57,6 +57,10 @@ struct ChainArgs {
   int32_t kz;
   const uint32_t *wflags;  // per waveform, from the prologue (FSMP_ST_NONFINITE)
   double *work;            // optional [chain][4]
+  // lane-per-chain kernels: chain state in device memory, interleaved in tiles of
+  // 64 chains (element e of the chain in lane l of tile t at (t * E + e) * 64 + l)
+  double *dws;
+  int32_t *iws;
 };
 
 struct PrologueArgs {
@@ -85,9 +89,16 @@ struct PosteriorArgs {
 // Launchers (fsmp_kernels.hip).  Each returns hipSuccess or the launch error.
 hipError_t launch_prologue(const PrologueArgs &a, hipStream_t st);
 hipError_t launch_posterior(const PosteriorArgs &a, hipStream_t st);
-// kcap in {16, 32, 64}; fills lanes per chain and blocks
+// lane-group instances for kcap in {16, 32, 48, 64}; fills lanes per chain and blocks
 hipError_t launch_chain(int kcap, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks);
-bool chain_kcap_supported(int kcap, int M, int sub);
+// lane-per-chain variant; dws / iws must hold lane_ws_doubles / lane_ws_ints(kcap, n_list)
+hipError_t launch_chain_lane(int kcap, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks);
+size_t lane_ws_doubles(int kcap, int64_t n_list);
+size_t lane_ws_ints(int kcap, int64_t n_list);
+// PE capacities of the chain kernels; a waveform runs in the smallest one >= its kmax
+constexpr int kNumCaps = 8;
+constexpr int kCaps[kNumCaps] = {16, 32, 48, 64, 96, 128, 160, 192};
+bool chain_kcap_supported(int kcap, int M, int sub);  // lane-group (LDS) instance exists and fits
 int chain_kcap_for(int kmax);
 
 }  // namespace fsmp

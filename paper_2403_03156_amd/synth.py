@@ -28,7 +28,7 @@ from scipy import optimize, stats
 
 PHI_EXP = 0
 PHI_BIEXP = 1
-KCAPS = (16, 32, 64, 96, 128, 160, 192)
+KCAPS = (16, 32, 48, 64, 96, 128, 160, 192)
 
 
 @dataclass
