@@ -74,7 +74,7 @@ def test_designs_agree_with_oracle(design):
 
 def test_large_capacities_pileup():
     wl = synth.PRESETS["pileup"]
-    lam = np.array([20.0, 35.0, 48.0, 60.0, 75.0, 90.0, 100.0, 100.0])
+    lam = np.array([20.0, 28.0, 48.0, 60.0, 75.0, 90.0, 100.0, 100.0])
     b = synth.generate(wl, n_wave=len(lam), seed=3, lam=lam)
     km = synth.kmax_for(b["lam"])
     assert set(km.tolist()) >= {48, 64, 96, 128, 160}
