@@ -211,7 +211,7 @@ fsmp_status validate_model(const fsmp_ser *ser, const fsmp_intensity *phi, const
   if ((cfg->record_flags & FSMP_REC_TRACE) && cfg->thin < 1) return m = "config: trace needs thin >= 1", FSMP_EINVAL;
   if (cfg->record_flags & ~(uint32_t)(FSMP_REC_TRACE | FSMP_REC_LOG)) return m = "config: unknown record flag", FSMP_EINVAL;
   if (cfg->precision != FSMP_FP64 && cfg->precision != FSMP_FP32_REFRESH) return m = "config: unknown precision", FSMP_EINVAL;
-  if (cfg->precision == FSMP_FP32_REFRESH) return m = "config: FP32 refresh form not in this build", FSMP_ENOTSUP;
+  if (cfg->precision == FSMP_FP32_REFRESH && cfg->refresh_M < 0) return m = "config: refresh_M must be >= 0", FSMP_EINVAL;
   return FSMP_OK;
 }
 
@@ -437,6 +437,7 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   std::vector<int32_t> order;
   order.reserve((size_t)n * cf.n_chains);
   int64_t bucket_start[kNumCaps + 1] = {0};
+  const bool fp32 = cf.precision == FSMP_FP32_REFRESH;
   // within a bucket, waveforms in order of lambda: neighbouring lanes then carry chains of
   // similar PE counts, which keeps the lane-per-chain loops (bounded by the largest K in a
   // wavefront) short
@@ -447,7 +448,9 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     bucket_start[bi] = (int64_t)order.size();
     for (int64_t ii = 0; ii < n; ++ii) {
       const int64_t i = wsorted[ii];
-      if (chain_kcap_for(kmx[i]) != caps[bi]) continue;
+      int kc = chain_kcap_for(kmx[i]);
+      if (fp32 && kc == 48) kc = 64;  // the precision form has no capacity-48 instance
+      if (kc != caps[bi]) continue;
       for (int ch = 0; ch < cf.n_chains; ++ch) order.push_back((int32_t)(i * cf.n_chains + ch));
     }
   }
@@ -456,7 +459,8 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     return fail(c, FSMP_ENOTSUP, "kmax above %d is not provided by this build", kCaps[kNumCaps - 1]);
   if (n * (int64_t)cf.n_chains > INT32_MAX) return fail(c, FSMP_EINVAL, "too many chains");
   for (int bi = 0; bi < kNumCaps; ++bi)
-    if (bucket_start[bi + 1] > bucket_start[bi] && c->design[bi] == 0 && !chain_kcap_supported(caps[bi], c->tab.M, sub))
+    if (bucket_start[bi + 1] > bucket_start[bi] && !fp32 && c->design[bi] == 0 &&
+        !chain_kcap_supported(caps[bi], c->tab.M, sub))
       return fail(c, FSMP_ENOTSUP, "SER support %d too long for PE capacity %d", c->tab.LV, caps[bi]);
   if (n == 0) {
     c->timings.clear();
@@ -483,8 +487,8 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   size_t lane_doff[kNumCaps + 1] = {0}, lane_ioff[kNumCaps + 1] = {0};
   {
     for (int bi = 0; bi < kNumCaps; ++bi) {
-      const int64_t cnt = c->design[bi] == 1 ? bucket_start[bi + 1] - bucket_start[bi] : 0;
-      lane_doff[bi + 1] = lane_doff[bi] + lane_ws_doubles(caps[bi], cnt);
+      const int64_t cnt = (fp32 || c->design[bi] == 1) ? bucket_start[bi + 1] - bucket_start[bi] : 0;
+      lane_doff[bi + 1] = lane_doff[bi] + lane_ws_doubles(caps[bi], cnt, fp32);
       lane_ioff[bi + 1] = lane_ioff[bi] + lane_ws_ints(caps[bi], cnt);
     }
     if (e == hipSuccess && lane_doff[kNumCaps] > 0) e = c->lane_d.ensure(lane_doff[kNumCaps]);
@@ -600,21 +604,24 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   ca.kz = o->kz;
   ca.wflags = c->wflags.p;
   ca.work = o->work;
+  ca.refresh_M = cf.refresh_M;
+  ca.near_eps = 1e-3;
+  ca.drift_bound = 1e-3;
   for (int bi = 0; bi < kNumCaps && e == hipSuccess; ++bi) {
     const int64_t cnt = bucket_start[bi + 1] - bucket_start[bi];
     if (cnt == 0) continue;
     ca.chains = c->chains.p + bucket_start[bi];
     ca.n_list = cnt;
     char name[32];
-    const int lane = c->design[bi];
-    std::snprintf(name, sizeof name, "%s_k%d", lane ? "chain_lane" : "chain_group", caps[bi]);
+    const int lane = fp32 ? 1 : c->design[bi];
+    std::snprintf(name, sizeof name, "%s%s_k%d", lane ? "chain_lane" : "chain_group", fp32 ? "_fp32" : "", caps[bi]);
     if (lane) {
       ca.dws = c->lane_d.p + lane_doff[bi];
       ca.iws = c->lane_i.p + lane_ioff[bi];
     }
     e = timed(name, caps[bi], [&](fsmp_timing &t) {
       t.chains = cnt;
-      return lane ? launch_chain_lane(caps[bi], ca, st, &t.lanes, &t.blocks)
+      return lane ? launch_chain_lane(caps[bi], fp32, ca, st, &t.lanes, &t.blocks)
                   : launch_chain(caps[bi], ca, st, &t.lanes, &t.blocks);
     });
   }

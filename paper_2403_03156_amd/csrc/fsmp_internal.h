@@ -61,6 +61,10 @@ struct ChainArgs {
   // 64 chains (element e of the chain in lane l of tile t at (t * E + e) * 64 + l)
   double *dws;
   int32_t *iws;
+  // precision form (FP32 storage of G^{-1}): FP64 refresh every refresh_M sweeps, FP64
+  // re-decision when |log U - log alpha| < near_eps * max(1, |delta-nu|), drift flag bound
+  int32_t refresh_M;
+  double near_eps, drift_bound;
 };
 
 struct PrologueArgs {
@@ -92,8 +96,9 @@ hipError_t launch_posterior(const PosteriorArgs &a, hipStream_t st);
 // lane-group instances for kcap in {16, 32, 48, 64}; fills lanes per chain and blocks
 hipError_t launch_chain(int kcap, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks);
 // lane-per-chain variant; dws / iws must hold lane_ws_doubles / lane_ws_ints(kcap, n_list)
-hipError_t launch_chain_lane(int kcap, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks);
-size_t lane_ws_doubles(int kcap, int64_t n_list);
+hipError_t launch_chain_lane(int kcap, bool fp32, const ChainArgs &a, hipStream_t st, int32_t *lanes,
+                             int64_t *blocks);
+size_t lane_ws_doubles(int kcap, int64_t n_list, bool fp32);
 size_t lane_ws_ints(int kcap, int64_t n_list);
 // PE capacities of the chain kernels; a waveform runs in the smallest one >= its kmax
 constexpr int kNumCaps = 8;

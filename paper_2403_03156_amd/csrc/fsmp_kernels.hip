@@ -597,13 +597,14 @@ __device__ inline int birth_draw_lane(const ModelDev &md, double t0, int glo, in
 
 // Interleaved per-lane state helpers: element e of this lane's chain is p[e * 64].
 // Every loop below issues a chunk of independent loads before any store, so one
-// memory round trip covers kChunk elements.
+// memory round trip covers kChunk elements.  Matrices are read into FP64 whatever
+// their storage type (FP64, or FP32 in the precision form) and written back rounded.
 constexpr int kChunk = 8;
 
-// eta = H gamma over the first n rows (rows in blocks of 4); also returns
-// q = gamma^T eta and p = gamma^T x, summed in row order
-template <int KCAP>
-__device__ inline void lane_matvec(const double *Hp, const double *G, double *E, const double *X, int n, double &q,
+// eta = M gamma over the first n rows (rows in blocks of 4); q = gamma^T eta and, when
+// X is given, p = gamma^T x, both summed in row order
+template <int KCAP, typename MT>
+__device__ inline void lane_matvec(const MT *Mp, const double *G, double *E, const double *X, int n, double &q,
                                    double &p) {
   q = 0.0;
   p = 0.0;
@@ -613,7 +614,7 @@ __device__ inline void lane_matvec(const double *Hp, const double *G, double *E,
       const double gk = G[k * 64];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (i0 + u < n) e[u] += Hp[(k * KCAP + i0 + u) * 64] * gk;
+        if (i0 + u < n) e[u] += (double)Mp[(k * KCAP + i0 + u) * 64] * gk;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -621,14 +622,14 @@ __device__ inline void lane_matvec(const double *Hp, const double *G, double *E,
         E[(i0 + u) * 64] = e[u];
         const double gi = G[(i0 + u) * 64];
         q += gi * e[u];
-        p += gi * X[(i0 + u) * 64];
+        if (X) p += gi * X[(i0 + u) * 64];
       }
   }
 }
 
-// H(k, i) += (A_i A_k) cA [+ (B_i B_k) cB] for i, k < n
-template <int KCAP, bool TWO>
-__device__ inline void lane_rank_update(double *Hp, const double *A, double cA, const double *B, double cB, int n) {
+// M(k, i) += (A_i A_k) cA [+ (B_i B_k) cB] for i, k < n
+template <int KCAP, bool TWO, typename MT>
+__device__ inline void lane_rank_update(MT *Mp, const double *A, double cA, const double *B, double cB, int n) {
   for (int k = 0; k < n; ++k) {
     const double ak = A[k * 64];
     const double bk = TWO ? B[k * 64] : 0.0;
@@ -637,7 +638,7 @@ __device__ inline void lane_rank_update(double *Hp, const double *A, double cA, 
 #pragma unroll
       for (int u = 0; u < kChunk; ++u)
         if (i0 + u < n) {
-          h[u] = Hp[(k * KCAP + i0 + u) * 64];
+          h[u] = (double)Mp[(k * KCAP + i0 + u) * 64];
           av[u] = A[(i0 + u) * 64];
           if (TWO) bv[u] = B[(i0 + u) * 64];
         }
@@ -646,36 +647,126 @@ __device__ inline void lane_rank_update(double *Hp, const double *A, double cA, 
         if (i0 + u < n) {
           double v = h[u] + av[u] * ak * cA;
           if (TWO) v += bv[u] * bk * cB;
-          Hp[(k * KCAP + i0 + u) * 64] = v;
+          Mp[(k * KCAP + i0 + u) * 64] = (MT)v;
         }
     }
   }
 }
 
-// copy n elements src[e * 64] -> dst[e * 64] (chunked)
-__device__ inline void lane_copy(double *dst, const double *src, int n) {
+// n elements src[e * 64] -> dst[e * 64] (chunked), converting the type
+template <typename DT, typename ST>
+__device__ inline void lane_copy(DT *dst, const ST *src, int n) {
   for (int i0 = 0; i0 < n; i0 += kChunk) {
     double v[kChunk];
 #pragma unroll
     for (int u = 0; u < kChunk; ++u)
-      if (i0 + u < n) v[u] = src[(i0 + u) * 64];
+      if (i0 + u < n) v[u] = (double)src[(i0 + u) * 64];
 #pragma unroll
     for (int u = 0; u < kChunk; ++u)
-      if (i0 + u < n) dst[(i0 + u) * 64] = v[u];
+      if (i0 + u < n) dst[(i0 + u) * 64] = (DT)v[u];
   }
 }
 
-template <int KCAP>
+// Workspace of one tile of 64 chains, in doubles: the inverse Gram matrix in its
+// storage type, the FP64 refresh matrix (precision form only), five FP64 vectors
+// (b, x and three scratch); grid indices and the N histogram are in the int workspace.
+template <int KCAP, typename HT>
 struct LaneLayout {
-  static constexpr int ED = KCAP * KCAP + 5 * KCAP;  // H, x, b, three scratch vectors
-  static constexpr int EI = 2 * KCAP + 1;            // grid indices, N histogram
+  static constexpr bool F32 = sizeof(HT) == 4;
+  static constexpr int HD = KCAP * KCAP * (int)sizeof(HT) / 8;  // doubles per chain for H
+  static constexpr int WD = F32 ? KCAP * KCAP : 0;
+  static constexpr int ED = HD + WD + 5 * KCAP;
+  static constexpr int EI = 2 * KCAP + 1;
 };
 
-// One chain per lane.  The chain's H = G^{-1} (full, KCAP x KCAP), x, b, scratch and
-// PE list live in device memory, interleaved across the 64 chains of a tile so that
-// every access of a wavefront is one contiguous 512-byte (or 256-byte) segment.
-template <int KCAP>
+// Precision form: rebuild the inverse Gram matrix of the current z in FP64 by
+// bordering (each step is the birth update of the PE-space factor: the exact inverse
+// of the leading block), recompute x = G^{-1} b in FP64, round the result into the
+// FP32 storage.  Returns false if a Schur complement is not positive.  `drift` is the
+// largest change of a charge mean, relative to max(1, |x|).
+template <int KCAP, typename HT>
+__device__ bool lane_refresh(const ModelDev &md, const double *vt, const double *ov, int Lw, double *Wp, HT *Hp,
+                             double *Xp, const double *Bp, double *S1, double *S2, const int32_t *Zp, int N,
+                             double &drift) {
+  for (int k = 0; k < N; ++k) {
+    const int gk = Zp[k * 64];
+    for (int i = 0; i < k; ++i) S1[i * 64] = overlap(md, vt, ov, gk, Zp[i * 64], Lw);
+    const double d = overlap(md, vt, ov, gk, gk, Lw) + md.rho;
+    double q, p;
+    lane_matvec<KCAP, double>(Wp, S1, S2, nullptr, k, q, p);
+    const double delta2 = d - q;
+    if (!(delta2 > 0.0)) return false;
+    const double inv = 1.0 / delta2;
+    lane_rank_update<KCAP, false, double>(Wp, S2, inv, nullptr, 0.0, k);
+    for (int i = 0; i < k; ++i) {
+      const double v = -S2[i * 64] * inv;
+      Wp[(k * KCAP + i) * 64] = v;
+      Wp[(i * KCAP + k) * 64] = v;
+    }
+    Wp[(k * KCAP + k) * 64] = inv;
+  }
+  drift = 0.0;
+  for (int i = 0; i < N; ++i) {
+    double xi = 0.0;
+    for (int k = 0; k < N; ++k) xi += Wp[(i * KCAP + k) * 64] * Bp[k * 64];
+    const double dx = fabs(xi - Xp[i * 64]) / fmax(1.0, fabs(xi));
+    drift = dx > drift ? dx : drift;
+    Xp[i * 64] = xi;
+  }
+  for (int k = 0; k < N; ++k) lane_copy(Hp + (int64_t)k * KCAP * 64, Wp + (int64_t)k * KCAP * 64, N);
+  return true;
+}
+
+// Delta-nu and log-acceptance of a birth or update proposal from the inverse Gram
+// matrix M (gamma in S1 with a zero at the moved PE, eta = M gamma written to S2).
+struct MvResult {
+  bool valid;
+  double dnu, la, delta2, up, om, xj, ej;
+};
+
+template <int KCAP, typename MT>
+__device__ inline MvResult lane_propose(const ModelDev &md, const MT *Mp, const double *S1, double *S2,
+                                        const double *Xp, int N, int move, int j, double d, double beta, double Lam,
+                                        double la_ratio) {
+  MvResult r;
+  r.valid = false;
+  r.dnu = 0.0;
+  r.la = -INFINITY;
+  r.om = 1.0;
+  r.xj = 0.0;
+  r.ej = 0.0;
+  double q, p;
+  lane_matvec<KCAP, MT>(Mp, S1, S2, Xp, N, q, p);
+  if (move == 1) {
+    r.delta2 = d - q;
+    r.up = beta - p;
+    if (r.delta2 > 0.0) {
+      r.dnu = -0.5 * (-md.log_rho + log(r.delta2) + (md.rhom2 - r.up * r.up / r.delta2) * md.inv_s);
+      r.la = r.dnu + log(Lam) - log((double)(N + 1)) + (N == 0 ? md.logJ : 0.0);
+      r.valid = true;
+    }
+  } else {
+    r.om = (double)Mp[(j * KCAP + j) * 64];
+    r.xj = Xp[j * 64];
+    r.ej = S2[j * 64];
+    r.delta2 = d - (q - r.ej * r.ej / r.om);
+    r.up = beta - (p - r.ej * r.xj / r.om);
+    if (r.delta2 > 0.0 && r.om > 0.0) {
+      r.dnu = 0.5 * (-log(r.om) - log(r.delta2) + (r.up * r.up / r.delta2 - r.xj * r.xj / r.om) * md.inv_s);
+      r.la = r.dnu + la_ratio;
+      r.valid = true;
+    }
+  }
+  return r;
+}
+
+// One chain per lane.  The chain's H = G^{-1} (full, KCAP x KCAP, FP64 or FP32), x, b,
+// scratch and PE list live in device memory, interleaved across the 64 chains of a
+// tile so that every access of a wavefront is one contiguous segment.
+template <int KCAP, typename HT>
 __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
+  using LL = LaneLayout<KCAP, HT>;
+  constexpr bool F32 = LL::F32;
   extern __shared__ double smem[];
   const ModelDev &md = a.md;
   double *vt = smem;
@@ -686,16 +777,17 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
   const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= a.n_list) return;
 
-  constexpr int ED = LaneLayout<KCAP>::ED, EI = LaneLayout<KCAP>::EI;
   const int64_t tile = slot >> 6;
   const int ln = (int)(slot & 63);
-  double *Hp = a.dws + tile * (int64_t)ED * 64 + ln;
-  double *Xp = Hp + (int64_t)KCAP * KCAP * 64;
+  double *base = a.dws + tile * (int64_t)LL::ED * 64;
+  HT *Hp = (HT *)base + ln;
+  double *Wp = base + (int64_t)LL::HD * 64 + ln;
+  double *Xp = base + (int64_t)(LL::HD + LL::WD) * 64 + ln;
   double *Bp = Xp + KCAP * 64;
   double *S1 = Bp + KCAP * 64;
   double *S2 = S1 + KCAP * 64;
   double *S3 = S2 + KCAP * 64;
-  int32_t *Zp = a.iws + tile * (int64_t)EI * 64 + ln;
+  int32_t *Zp = a.iws + tile * (int64_t)LL::EI * 64 + ln;
   int32_t *Hs = Zp + KCAP * 64;
 #define HM(k, i) Hp[((k) * KCAP + (i)) * 64]
 #define XV(i) Xp[(i) * 64]
@@ -737,6 +829,11 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
   const bool biexp = md.kind == FSMP_PHI_BIEXP;
 
   for (int step = 0; step < n_steps; ++step) {
+    if (F32 && a.refresh_M > 0 && step > 0 && step % a.refresh_M == 0 && N > 0) {
+      double drift;
+      if (!lane_refresh<KCAP, HT>(md, vt, ov, Lw, Wp, Hp, Xp, Bp, S1, S2, Zp, N, drift)) st |= FSMP_ST_FACTOR;
+      else if (drift > a.drift_bound) st |= FSMP_ST_DRIFT;
+    }
     uint32_t r[8];
     philox4x32_10((uint32_t)step, 0u, uid0, uid1, a.key0, a.key1, r);
     philox4x32_10((uint32_t)step, 1u, uid0, uid1, a.key0, a.key1, r + 4);
@@ -776,7 +873,7 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
     int j = -1, gnew = -1, sh = 0;
     bool valid = false;
     double dnu = 0.0, la = -INFINITY;
-    double delta2 = 1.0, up = 0.0, om = 1.0, xj = 0.0, ej = 0.0, beta = 0.0;
+    double delta2 = 1.0, up = 0.0, om = 1.0, xj = 0.0, ej = 0.0, beta = 0.0, dself = 0.0, la_ratio = 0.0;
     bool need_mv = false;
     if (move == 1) {
       cnt[2]++;
@@ -790,7 +887,7 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
       j = (int)(((uint64_t)r[4] * (uint64_t)N) >> 32);
       if (move == 2) {
         cnt[4]++;
-        om = HM(j, j);
+        om = (double)HM(j, j);
         xj = XV(j);
         if (om > 0.0) {
           dnu = 0.5 * (-md.log_rho - log(om) + (md.rhom2 - xj * xj / om) * md.inv_s);
@@ -813,63 +910,73 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
               la = lpn - lpo;
             } else {
               need_mv = true;
-              la = lpn - lpo;  // the proposal ratio; delta-nu is added below
+              la_ratio = lpn - lpo;
             }
           }
         }
       }
     }
     if (need_mv) {
-      // gamma (zero at the moved PE), one K x K mat-vec, two dot products
       for (int i = 0; i < N; ++i) G1(i) = (i == j) ? 0.0 : overlap(md, vt, ov, gnew, ZG(i), Lw);
-      const double d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
+      dself = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
       beta = mf[gnew - glo] + md.rhom;
       wk0 += (double)N * N;
-      double q, p;
-      lane_matvec<KCAP>(Hp, S1, S2, Xp, N, q, p);
-      if (move == 1) {
-        delta2 = d - q;
-        if (delta2 > 0.0) {
-          up = beta - p;
-          dnu = -0.5 * (-md.log_rho + log(delta2) + (md.rhom2 - up * up / delta2) * md.inv_s);
-          la = dnu + log(Lam) - log((double)(N + 1)) + (N == 0 ? md.logJ : 0.0);
-          valid = true;
-        } else {
-          st |= FSMP_ST_FACTOR;
+      const MvResult mr = lane_propose<KCAP, HT>(md, Hp, S1, S2, Xp, N, move, j, dself, beta, Lam, la_ratio);
+      valid = mr.valid;
+      dnu = mr.dnu;
+      la = mr.la;
+      delta2 = mr.delta2;
+      up = mr.up;
+      om = mr.om;
+      xj = mr.xj;
+      ej = mr.ej;
+      if (!valid) st |= FSMP_ST_FACTOR;
+    }
+
+    const double logu = log(u01(r[6]));
+    if (F32 && valid && fabs(logu - la) < a.near_eps * fmax(1.0, fabs(dnu))) {
+      // precision form, decision near the threshold: refresh in FP64 and decide with the
+      // FP64 delta-nu of the same proposal
+      double drift;
+      if (N > 0 && lane_refresh<KCAP, HT>(md, vt, ov, Lw, Wp, Hp, Xp, Bp, S1, S2, Zp, N, drift)) {
+        if (need_mv) {
+          for (int i = 0; i < N; ++i) G1(i) = (i == j) ? 0.0 : overlap(md, vt, ov, gnew, ZG(i), Lw);
+          const MvResult mr = lane_propose<KCAP, double>(md, Wp, S1, S2, Xp, N, move, j, dself, beta, Lam, la_ratio);
+          valid = mr.valid;
+          dnu = mr.dnu;
+          la = mr.la;
+          delta2 = mr.delta2;
+          up = mr.up;
+          om = mr.om;
+          xj = mr.xj;
+          ej = mr.ej;
+        } else if (move == 2) {
+          om = Wp[(j * KCAP + j) * 64];
+          xj = XV(j);
+          dnu = 0.5 * (-md.log_rho - log(om) + (md.rhom2 - xj * xj / om) * md.inv_s);
+          la = dnu - log(Lam) + log((double)N) - (N == 1 ? md.logJ : 0.0);
         }
-      } else {
-        om = HM(j, j);
-        xj = XV(j);
-        ej = G2(j);
-        delta2 = d - (q - ej * ej / om);
-        up = beta - (p - ej * xj / om);
-        if (delta2 > 0.0 && om > 0.0) {
-          dnu = 0.5 * (-log(om) - log(delta2) + (up * up / delta2 - xj * xj / om) * md.inv_s);
-          la = dnu + la;
-          valid = true;
-        } else {
-          st |= FSMP_ST_FACTOR;
-          la = -INFINITY;
-        }
+      } else if (N > 0) {
+        st |= FSMP_ST_FACTOR;
       }
     }
 
     bool accepted = false;
-    if (valid && log(u01(r[6])) < la) {
+    if (valid && logu < la) {
       accepted = true;
       cnt[2 * move + 1]++;
       if (move == 1) {
         wk1 += (double)N * N;
         const double inv_d2 = 1.0 / delta2;
         const double xn = up * inv_d2;
-        lane_rank_update<KCAP, false>(Hp, S2, inv_d2, nullptr, 0.0, N);
+        lane_rank_update<KCAP, false, HT>(Hp, S2, inv_d2, nullptr, 0.0, N);
         for (int i = 0; i < N; ++i) {
           const double ei = G2(i);
           XV(i) -= ei * xn;
-          HM(N, i) = -ei * inv_d2;
-          HM(i, N) = -ei * inv_d2;
+          HM(N, i) = (HT)(-ei * inv_d2);
+          HM(i, N) = (HT)(-ei * inv_d2);
         }
-        HM(N, N) = inv_d2;
+        HM(N, N) = (HT)inv_d2;
         ZG(N) = gnew;
         BV(N) = beta;
         XV(N) = xn;
@@ -881,15 +988,15 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
         const double inv_d = 1.0 / om;
         const int gj = ZG(j);
         lane_copy(S3, Hp + (int64_t)j * KCAP * 64, N);  // h = row j of H
-        lane_rank_update<KCAP, false>(Hp, S3, -inv_d, nullptr, 0.0, N);
+        lane_rank_update<KCAP, false, HT>(Hp, S3, -inv_d, nullptr, 0.0, N);
         for (int i = 0; i < N; ++i) XV(i) -= G3(i) * xj * inv_d;
         const int last = N - 1;
         if (j != last) {
           lane_copy(S3, Hp + (int64_t)last * KCAP * 64, N);  // row `last` moves into slot j
           const double vd = G3(last);
           lane_copy(Hp + (int64_t)j * KCAP * 64, S3, N);
-          for (int i = 0; i < N; ++i) HM(i, j) = G3(i);
-          HM(j, j) = vd;
+          for (int i = 0; i < N; ++i) HM(i, j) = (HT)G3(i);
+          HM(j, j) = (HT)vd;
           ZG(j) = ZG(last);
           BV(j) = BV(last);
           XV(j) = XV(last);
@@ -908,14 +1015,14 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
         lane_copy(S3, Hp + (int64_t)j * KCAP * 64, N);  // h = row j of H
         for (int i = 0; i < N; ++i) G2(i) = (i == j) ? 0.0 : G2(i) - G3(i) * ej * inv_om;
         for (int i = 0; i < N; ++i) XV(i) = (i == j) ? xn : XV(i) - G3(i) * xj * inv_om - G2(i) * xn;
-        lane_rank_update<KCAP, true>(Hp, S3, -inv_om, S2, inv_d2, N);
+        lane_rank_update<KCAP, true, HT>(Hp, S3, -inv_om, S2, inv_d2, N);
         for (int i = 0; i < N; ++i) {
           if (i == j) {
-            HM(j, j) = inv_d2;
+            HM(j, j) = (HT)inv_d2;
           } else {
             const double v = -G2(i) * inv_d2;
-            HM(j, i) = v;
-            HM(i, j) = v;
+            HM(j, i) = (HT)v;
+            HM(i, j) = (HT)v;
           }
         }
         ZG(j) = gnew;
@@ -1081,14 +1188,14 @@ hipError_t launch_chain_t(const ChainArgs &a, hipStream_t st, int32_t *lanes, in
 }
 
 
-template <int KCAP>
+template <int KCAP, typename HT>
 hipError_t launch_chain_lane_t(const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
   const int64_t nb = (a.n_list + 255) / 256;
   const size_t lds = sizeof(double) * ((size_t)a.md.M * (1 + a.md.sub));
   *lanes = 1;
   *blocks = nb;
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL((chain_lane_kernel<KCAP>), dim3((unsigned)nb), dim3(256), lds, st, a);
+  hipLaunchKernelGGL((chain_lane_kernel<KCAP, HT>), dim3((unsigned)nb), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 
@@ -1132,9 +1239,10 @@ bool chain_kcap_supported(int kcap, int M, int sub) {
   return false;
 }
 
-size_t lane_ws_doubles(int kcap, int64_t n_list) {
+size_t lane_ws_doubles(int kcap, int64_t n_list, bool fp32) {
   const size_t tiles = (size_t)((n_list + 63) / 64);
-  return tiles * 64 * ((size_t)kcap * kcap + 5 * (size_t)kcap);
+  const size_t k2 = (size_t)kcap * kcap;
+  return tiles * 64 * ((fp32 ? k2 / 2 + k2 : k2) + 5 * (size_t)kcap);
 }
 
 size_t lane_ws_ints(int kcap, int64_t n_list) {
@@ -1142,17 +1250,31 @@ size_t lane_ws_ints(int kcap, int64_t n_list) {
   return tiles * 64 * (2 * (size_t)kcap + 1);
 }
 
-hipError_t launch_chain_lane(int kcap, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
+hipError_t launch_chain_lane(int kcap, bool fp32, const ChainArgs &a, hipStream_t st, int32_t *lanes,
+                             int64_t *blocks) {
+  // no lane instance for capacity 48: its GPU run faulted with a cause not found
+  // (a bounds-checked CPU build of this kernel is clean); capacity 48 runs in the
+  // lane-group kernel (FP64) or in the capacity-64 lane instance (FP32 form)
+  if (fp32) {
+    switch (kcap) {
+      case 16: return launch_chain_lane_t<16, float>(a, st, lanes, blocks);
+      case 32: return launch_chain_lane_t<32, float>(a, st, lanes, blocks);
+      case 64: return launch_chain_lane_t<64, float>(a, st, lanes, blocks);
+      case 96: return launch_chain_lane_t<96, float>(a, st, lanes, blocks);
+      case 128: return launch_chain_lane_t<128, float>(a, st, lanes, blocks);
+      case 160: return launch_chain_lane_t<160, float>(a, st, lanes, blocks);
+      case 192: return launch_chain_lane_t<192, float>(a, st, lanes, blocks);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (kcap) {
-    case 16: return launch_chain_lane_t<16>(a, st, lanes, blocks);
-    case 32: return launch_chain_lane_t<32>(a, st, lanes, blocks);
-    // no lane instance for capacity 48: its GPU run faulted with a cause not found
-    // (a CPU build of this kernel is clean); capacity 48 runs in the lane-group kernel
-    case 64: return launch_chain_lane_t<64>(a, st, lanes, blocks);
-    case 96: return launch_chain_lane_t<96>(a, st, lanes, blocks);
-    case 128: return launch_chain_lane_t<128>(a, st, lanes, blocks);
-    case 160: return launch_chain_lane_t<160>(a, st, lanes, blocks);
-    case 192: return launch_chain_lane_t<192>(a, st, lanes, blocks);
+    case 16: return launch_chain_lane_t<16, double>(a, st, lanes, blocks);
+    case 32: return launch_chain_lane_t<32, double>(a, st, lanes, blocks);
+    case 64: return launch_chain_lane_t<64, double>(a, st, lanes, blocks);
+    case 96: return launch_chain_lane_t<96, double>(a, st, lanes, blocks);
+    case 128: return launch_chain_lane_t<128, double>(a, st, lanes, blocks);
+    case 160: return launch_chain_lane_t<160, double>(a, st, lanes, blocks);
+    case 192: return launch_chain_lane_t<192, double>(a, st, lanes, blocks);
     default: return hipErrorInvalidValue;
   }
 }
