@@ -236,6 +236,49 @@ void fsmp_destroy(fsmp_ctx *ctx);
 /* Library version string. */
 const char *fsmp_version(void);
 
+/* ------------------------------------------------------------------ serving
+ * A continuous-batching request loop over one device.  Trigger events (each a ragged set
+ * of channel waveforms, host memory) are submitted as they arrive; fsmp_server_progress
+ * admits queued events, in arrival order, into micro-batches while the device-memory
+ * budget allows, launches each micro-batch on one of n_streams HIP streams (its own
+ * context and workspace, so micro-batches overlap on the device), and retires finished
+ * ones.  Every chain of an event runs start to finish on the device.  Random streams are
+ * keyed by the waveform identity (event_id * 65536 + channel), so an event's results are
+ * the same whether it runs alone or mixed with others.  Buffers grow to the largest
+ * micro-batch seen and are then reused: in steady state the server allocates nothing.
+ * Latency of an event = completion seen by fsmp_server_progress - fsmp_server_submit. */
+typedef struct {
+  int32_t n_streams;       /* micro-batches in flight (1..16) */
+  int64_t max_batch_wave;  /* waveforms per micro-batch */
+  size_t memory_budget;    /* device bytes the admitted, unfinished micro-batches may hold */
+} fsmp_server_config;
+
+typedef struct fsmp_server fsmp_server;
+
+fsmp_status fsmp_server_create(fsmp_server **out, const fsmp_ser *ser, const fsmp_intensity *phi,
+                               const fsmp_config *cfg, int device, const fsmp_server_config *scfg);
+/* Queue one event: n_wave channels, samples concatenated in wave (host, copied now),
+ * offsets (host, n_wave + 1), lambda and kmax (host; kmax NULL = cfg.k_max).  event_id
+ * must be unique among unfinished events and below 2^48; n_wave <= 65536. */
+fsmp_status fsmp_server_submit(fsmp_server *srv, uint64_t event_id, int64_t n_wave, const float *wave,
+                               const int64_t *offsets, const double *lambda, const int32_t *kmax);
+/* Admit, launch and retire; with wait != 0 blocks until at least one micro-batch finishes
+ * (if any is in flight).  Returns the number of events completed by this call, or a
+ * negative fsmp_status. */
+int32_t fsmp_server_progress(fsmp_server *srv, int32_t wait);
+/* Results of a completed event (host buffers of n_wave rows): posterior mean and MCSE of
+ * (N, Q, t0) per channel, OR of the chains' status words, latency in seconds.  The event
+ * is forgotten afterwards.  FSMP_EBUSY if it has not completed. */
+fsmp_status fsmp_server_result(fsmp_server *srv, uint64_t event_id, double *mean, double *mcse, uint32_t *status,
+                               double *latency_s);
+/* Events queued, in flight, completed-but-not-collected; device bytes held. */
+fsmp_status fsmp_server_stats(const fsmp_server *srv, int64_t *queued, int64_t *in_flight, int64_t *done,
+                              size_t *bytes_held);
+const char *fsmp_server_last_error(const fsmp_server *srv);
+/* Waits for in-flight work, then releases everything; NULL is ignored. */
+void fsmp_server_destroy(fsmp_server *srv);
+
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfsmp.so")
-SOURCES = ["fsmp_api.hip", "fsmp_kernels.hip"]
+SOURCES = ["fsmp_api.hip", "fsmp_kernels.hip", "fsmp_server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -20,7 +20,9 @@ FSMP_REC_TRACE, FSMP_REC_LOG = 1, 2
 FSMP_ST_KMAX, FSMP_ST_NONFINITE, FSMP_ST_DRIFT, FSMP_ST_EMPTY_T, FSMP_ST_FACTOR = 1, 2, 4, 8, 16
 
 EXPORTS = ("fsmp_create", "fsmp_workspace_bytes", "fsmp_sample", "fsmp_posterior", "fsmp_last_timings",
-           "fsmp_set_timing", "fsmp_last_error", "fsmp_destroy", "fsmp_version")
+           "fsmp_set_timing", "fsmp_last_error", "fsmp_destroy", "fsmp_version", "fsmp_server_create",
+           "fsmp_server_submit", "fsmp_server_progress", "fsmp_server_result", "fsmp_server_stats",
+           "fsmp_server_last_error", "fsmp_server_destroy")
 
 
 class fsmp_ser(ctypes.Structure):
@@ -58,6 +60,10 @@ class fsmp_samples(ctypes.Structure):
 class fsmp_posterior_out(ctypes.Structure):
     _fields_ = [("mean", ctypes.c_void_p), ("var", ctypes.c_void_p), ("mcse", ctypes.c_void_p),
                 ("p_n", ctypes.c_void_p), ("accept", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
+class fsmp_server_config(ctypes.Structure):
+    _fields_ = [("n_streams", ctypes.c_int32), ("max_batch_wave", ctypes.c_int64), ("memory_budget", ctypes.c_size_t)]
 
 
 class fsmp_timing(ctypes.Structure):
@@ -106,6 +112,24 @@ def load(path: Optional[str] = None):
     L.fsmp_destroy.restype = None
     L.fsmp_version.argtypes = []
     L.fsmp_version.restype = ctypes.c_char_p
+    L.fsmp_server_create.argtypes = [P(ctypes.c_void_p), P(fsmp_ser), P(fsmp_intensity), P(fsmp_config), ctypes.c_int,
+                                     P(fsmp_server_config)]
+    L.fsmp_server_create.restype = ctypes.c_int
+    L.fsmp_server_submit.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]
+    L.fsmp_server_submit.restype = ctypes.c_int
+    L.fsmp_server_progress.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.fsmp_server_progress.restype = ctypes.c_int32
+    L.fsmp_server_result.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     P(ctypes.c_double)]
+    L.fsmp_server_result.restype = ctypes.c_int
+    L.fsmp_server_stats.argtypes = [ctypes.c_void_p, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64),
+                                    P(ctypes.c_size_t)]
+    L.fsmp_server_stats.restype = ctypes.c_int
+    L.fsmp_server_last_error.argtypes = [ctypes.c_void_p]
+    L.fsmp_server_last_error.restype = ctypes.c_char_p
+    L.fsmp_server_destroy.argtypes = [ctypes.c_void_p]
+    L.fsmp_server_destroy.restype = None
     _lib = L
     return L
 
@@ -248,3 +272,78 @@ def log_records(t):
     """View a device log tensor (uint8 [chains][n_steps*40]) as a numpy structured array."""
     a = t.cpu().numpy()
     return a.view(LOGREC_DTYPE).reshape(a.shape[0], -1)
+
+
+class Server:
+    """Continuous-batching request loop (fsmp_server_*): submit events from host memory,
+    drive it with progress(), collect per-event posteriors and latencies."""
+
+    def __init__(self, sampler_kwargs, n_streams=4, max_batch_wave=20000, memory_budget=8 << 30, device=0):
+        self.lib = load()
+        kw = dict(sampler_kwargs)
+        ser = kw.get("ser", (8.0, 1.5, 6.0))
+        self.ser = fsmp_ser(ser[0], ser[1], ser[2], kw.get("ser_amp", 1.0), kw.get("ser_support", 0))
+        self.phi = fsmp_intensity(kw.get("phi_kind", FSMP_PHI_EXP), kw.get("tau_rise", 0.0), kw.get("tau_decay", 20.0),
+                                  kw.get("t0_min", 50.0), kw.get("t0_max", 100.0))
+        n_steps = kw.get("n_steps", 1000)
+        burn = kw.get("burn_in", n_steps // 2)
+        self.cfg = fsmp_config(kw.get("sigma_eps", 0.1), kw.get("mu_q", 1.0), kw.get("sigma_q", 0.3),
+                               kw.get("grid_sub", 4), kw.get("jump_J", 0.25), kw.get("t0_step_sd", 1.0),
+                               kw.get("shift_sd", 1.0), kw.get("k_max", 32), n_steps, kw.get("n_chains", 1), burn,
+                               kw.get("thin", 1), kw.get("precision", FSMP_FP64), kw.get("refresh_M", 64), 0,
+                               kw.get("seed", 0))
+        self.scfg = fsmp_server_config(n_streams, max_batch_wave, memory_budget)
+        h = ctypes.c_void_p()
+        st = self.lib.fsmp_server_create(ctypes.byref(h), ctypes.byref(self.ser), ctypes.byref(self.phi),
+                                         ctypes.byref(self.cfg), device, ctypes.byref(self.scfg))
+        if st != FSMP_OK:
+            raise FsmpError(st, self.lib.fsmp_server_last_error(None).decode())
+        self.h = h
+        self.sizes = {}
+
+    def _check(self, st):
+        if st < 0:
+            raise FsmpError(st, self.lib.fsmp_server_last_error(self.h).decode())
+        return st
+
+    def submit(self, event_id, wave, offsets, lam, kmax=None):
+        wave = np.ascontiguousarray(wave, dtype=np.float32)
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        kmax = None if kmax is None else np.ascontiguousarray(kmax, dtype=np.int32)
+        n = len(offsets) - 1
+        self._check(self.lib.fsmp_server_submit(self.h, event_id, n, _hptr(wave), _hptr(offsets), _hptr(lam),
+                                                _hptr(kmax)))
+        self.sizes[event_id] = n
+
+    def progress(self, wait=False):
+        return self._check(self.lib.fsmp_server_progress(self.h, 1 if wait else 0))
+
+    def result(self, event_id):
+        n = self.sizes[event_id]
+        mean = np.zeros((n, 3))
+        mcse = np.zeros((n, 3))
+        status = np.zeros(n, np.uint32)
+        lat = ctypes.c_double(0.0)
+        st = self.lib.fsmp_server_result(self.h, event_id, _hptr(mean), _hptr(mcse), _hptr(status), ctypes.byref(lat))
+        if st == FSMP_EBUSY:
+            return None
+        self._check(st)
+        del self.sizes[event_id]
+        return {"mean": mean, "mcse": mcse, "status": status, "latency": lat.value}
+
+    def stats(self):
+        q, f, d, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+        self._check(self.lib.fsmp_server_stats(self.h, ctypes.byref(q), ctypes.byref(f), ctypes.byref(d), ctypes.byref(b)))
+        return {"queued": q.value, "in_flight": f.value, "done": d.value, "bytes_held": b.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fsmp_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
