@@ -35,9 +35,68 @@ def parse():
     ap.add_argument("--workload", default="batched")
     ap.add_argument("--n-wave", type=int, default=0, help="override the workload's waveform count")
     ap.add_argument("--chain-steps", type=int, default=0, help="override the sweeps per chain")
-X
+    ap.add_argument("--cpu-wave", type=int, default=15000, help="waveforms in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="only the serving study (rates x precisions)")
+    ap.add_argument("--serve-events", type=int, default=40, help="events per serving run")
+    ap.add_argument("--serve-rates", default="2000", help="comma-separated event rates (Hz)")
+    ap.add_argument("--no-serve", action="store_true")
     return ap.parse_args()
+
+
+def serving_run(fsmp, synth, pool, rate, n_events, precision, seed=0, n_streams=4, max_batch_wave=20000):
+    """Poisson arrivals of trigger events (500-2000 channels drawn from a pool of synthetic
+    channels, 1,024 samples each); returns latency percentiles and throughput."""
+    wl = synth.PRESETS["serving"]
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, n_events)
+    arrive = np.cumsum(gaps) - gaps[0]
+    events = []
+    L = 1024
+    for e in range(n_events):
+        n = int(rng.integers(500, 2001))
+        idx = rng.integers(0, pool["n"], n)
+        wave = pool["wave"].reshape(pool["n"], L)[idx].reshape(-1)
+        events.append((e + 1, wave, np.arange(n + 1, dtype=np.int64) * L, pool["lam"][idx], pool["kmax"][idx]))
+    kw = dict(ser=wl.ser, phi_kind=wl.phi_kind, tau_rise=wl.tau_rise, tau_decay=wl.tau_decay, t0_min=wl.t0_min,
+              t0_max=wl.t0_max, sigma_eps=wl.sigma_eps, mu_q=wl.mu_q, sigma_q=wl.sigma_q, n_steps=wl.n_steps,
+              n_chains=1, seed=seed, precision=precision, refresh_M=64)
+    srv = fsmp.Server(kw, n_streams=n_streams, max_batch_wave=max_batch_wave, memory_budget=32 << 30)
+    # warm the server's buffers with one event (allocations happen once)
+    srv.submit(1 << 40, events[0][1], events[0][2], events[0][3], events[0][4])
+    while srv.result(1 << 40) is None:
+        srv.progress(wait=True)
+    lat, done, i = {}, 0, 0
+    t0 = time.perf_counter()
+    while done < n_events:
+        now = time.perf_counter() - t0
+        while i < n_events and arrive[i] <= now:
+            eid, w, off, lam, km = events[i]
+            srv.submit(eid, w, off, lam, km)
+            i += 1
+        srv.progress(wait=(i == n_events))
+        for eid, *_ in events[:i]:
+            if eid not in lat:
+                r = srv.result(eid)
+                if r is not None:
+                    lat[eid] = r["latency"]
+                    done += 1
+        if i < n_events and done < i:
+            time.sleep(0)
+    t_end = time.perf_counter() - t0
+    srv.close()
+    waves = sum(len(e[3]) for e in events)
+    l = np.array(list(lat.values()))
+    return {"rate_hz": rate, "events": n_events, "waveforms": waves, "precision": "fp32+refresh" if precision else "fp64",
+            "p50_ms": float(np.percentile(l, 50) * 1e3), "p99_ms": float(np.percentile(l, 99) * 1e3),
+            "mean_ms": float(l.mean() * 1e3), "waveforms_per_s": waves / t_end,
+            "offered_waveforms_per_s": waves / max(arrive[-1], 1e-9)}
+
+
+def serving_pool(synth, n=20000, seed=5):
+    wl = synth.PRESETS["serving"]
+    b = synth.generate(wl, n_wave=n, seed=seed)
+    return {"n": n, "wave": b["wave"], "lam": b["lam"], "kmax": synth.kmax_for(b["lam"])}
 
 
 def algorithmic_flops(work):
@@ -56,6 +115,14 @@ def main():
 
     import oracle
     from paper_2403_03156_amd import fsmp, synth
+
+    if args.serve:
+        pool = serving_pool(synth)
+        for prec in (fsmp.FSMP_FP64, fsmp.FSMP_FP32_REFRESH):
+            for rate in [float(r) for r in args.serve_rates.split(",")]:
+                r = serving_run(fsmp, synth, pool, rate, args.serve_events, prec)
+                print(json.dumps({"serving": r}), flush=True)
+        return
 
     wl = synth.PRESETS[args.workload]
     n_wave = args.n_wave or wl.n_wave
@@ -139,6 +206,14 @@ def main():
                "steps_per_s": m * wl.n_chains * n_steps / dt}
         print(f"[bench] oracle {m} waveforms in {dt:.1f}s on {threads} threads", file=sys.stderr, flush=True)
 
+    # ---- serving: continuous batching at 2 kHz trigger rate, FP64 and FP32+refresh forms
+    serving = None
+    if not args.no_serve:
+        pool = serving_pool(synth)
+        serving = [serving_run(fsmp, synth, pool, float(r), args.serve_events, prec)
+                   for prec in (fsmp.FSMP_FP64, fsmp.FSMP_FP32_REFRESH) for r in args.serve_rates.split(",")]
+        print(f"[bench] serving {json.dumps(serving)}", file=sys.stderr, flush=True)
+
     res = {
         "metric": "waveforms/s and MCMC steps/s at matched posterior accuracy; p99 event latency",
         "value": wps,
@@ -159,6 +234,7 @@ def main():
         "kernel_ms": avg,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(res))
 

@@ -226,6 +226,39 @@ fsmp_status fsmp_posterior(fsmp_ctx *ctx, int64_t n_wave, const fsmp_samples *in
 int32_t fsmp_last_timings(const fsmp_ctx *ctx, fsmp_timing *out, int32_t cap);
 fsmp_status fsmp_set_timing(fsmp_ctx *ctx, int32_t enable);
 
+/* ------------------------------------------------------------------ kernel designs
+ * Two implementations of the same chains (identical results up to rounding order):
+ * FSMP_DESIGN_GROUP runs one chain per group of lanes with G^{-1} in LDS (PE capacities up
+ * to 64); FSMP_DESIGN_LANE runs one chain per lane with G^{-1} interleaved in device
+ * memory (every capacity but 48).  Capacities are 16, 32, 48, 64, 96, 128, 160, 192; a
+ * waveform runs in the smallest one >= its kmax.  capacity 0 = every capacity that has the
+ * design.  FSMP_ENOTSUP if the requested pair does not exist. */
+enum { FSMP_DESIGN_GROUP = 0, FSMP_DESIGN_LANE = 1 };
+fsmp_status fsmp_set_design(fsmp_ctx *ctx, int32_t capacity, int32_t design);
+int32_t fsmp_get_design(const fsmp_ctx *ctx, int32_t capacity);
+
+/* Autotuner: runs the whole batch for trial_steps sweeps once with every capacity in the
+ * lane-group design and once in the lane design (outputs discarded, HIP-event timings of
+ * each capacity's launch), then keeps the faster design per capacity in the context.
+ * Allocates scratch outputs for the trial and synchronises `hip_stream`.  A no-op for the
+ * FP32-refresh form, which has the lane design only. */
+fsmp_status fsmp_autotune(fsmp_ctx *ctx, const fsmp_batch *batch, int32_t trial_steps, void *hip_stream);
+
+/* HIP graph of one batch: makes a private context with ctx's model, configuration and
+ * designs, uploads the batch's metadata into it (synchronising `hip_stream`), records the
+ * prologue and chain kernels of fsmp_sample(batch, out) into a graph and instantiates it.
+ * Each fsmp_graph_launch replays exactly that work (same results as the eager call): it
+ * reads batch->wave and writes `out`'s buffers, which the caller keeps allocated until
+ * fsmp_graph_destroy; the host arrays of `batch` may be freed after creation.  Calls on
+ * ctx afterwards do not affect the graph.  Replays of one graph must not overlap in time
+ * (they share the private workspace and `out`).  No memset nodes are recorded.  Errors
+ * are reported on ctx. */
+typedef struct fsmp_graph fsmp_graph;
+fsmp_status fsmp_graph_create(fsmp_ctx *ctx, const fsmp_batch *batch, const fsmp_samples *out, void *hip_stream,
+                              fsmp_graph **graph);
+fsmp_status fsmp_graph_launch(fsmp_graph *graph, void *hip_stream);
+void fsmp_graph_destroy(fsmp_graph *graph);
+
 /* Message of the last failure on this context (or of the last failed fsmp_create when ctx
  * is NULL); never NULL. */
 const char *fsmp_last_error(const fsmp_ctx *ctx);

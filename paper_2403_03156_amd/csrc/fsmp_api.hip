@@ -161,6 +161,8 @@ struct fsmp_ctx {
   hipEvent_t stage_done = nullptr;
   bool stage_pending = false;
   bool timing = false;
+  hipStream_t capture = nullptr;  // set while fsmp_graph_create captures the kernels
+  hipGraph_t captured = nullptr;
   std::vector<fsmp_timing> timings;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timing_events;
   std::vector<hipEvent_t> evpool;
@@ -534,20 +536,31 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   c->timings.clear();
   c->timing_events.clear();
   size_t ev = 0;
+  const hipStream_t upload_stream = st;
+  if (c->capture) {
+    // graph capture: the metadata upload above is complete before the kernels are recorded
+    e = hipStreamSynchronize(upload_stream);
+    if (e == hipSuccess) e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      (void)hipSetDevice(prev);
+      return fail(c, FSMP_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    }
+    st = c->capture;
+  }
   auto timed = [&](const char *name, int kcap, auto &&launch) -> hipError_t {
     fsmp_timing t{};
     std::snprintf(t.name, sizeof t.name, "%s", name);
     t.kcap = kcap;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
+    if (c->timing && !c->capture) {
       e0 = pool_event(c, ev++);
       e1 = pool_event(c, ev++);
       if (e0) (void)hipEventRecord(e0, st);
     }
     hipError_t r = launch(t);
-    if (c->timing && e1) (void)hipEventRecord(e1, st);
+    if (e1) (void)hipEventRecord(e1, st);
     c->timings.push_back(t);
-    c->timing_events.push_back({c->timing ? e0 : nullptr, c->timing ? e1 : nullptr});
+    c->timing_events.push_back({e0, e1});
     return r;
   };
 
@@ -625,9 +638,206 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
                   : launch_chain(caps[bi], ca, st, &t.lanes, &t.blocks);
     });
   }
+  if (c->capture) {
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(c->capture, &g);
+    if (e == hipSuccess) e = e2;
+    c->captured = g;
+  }
   (void)hipSetDevice(prev);
   if (e != hipSuccess) return fail(c, FSMP_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   return FSMP_OK;
+}
+
+fsmp_status fsmp_set_design(fsmp_ctx *c, int32_t capacity, int32_t design) {
+  if (!c) return FSMP_EINVAL;
+  if (design != FSMP_DESIGN_GROUP && design != FSMP_DESIGN_LANE) return fail(c, FSMP_EINVAL, "unknown design %d", design);
+  bool any = false;
+  for (int q = 0; q < kNumCaps; ++q) {
+    if (capacity != 0 && capacity != kCaps[q]) continue;
+    any = true;
+    if (design == FSMP_DESIGN_GROUP && !chain_kcap_supported(kCaps[q], c->tab.M, c->cfg.grid_sub)) {
+      if (capacity != 0) return fail(c, FSMP_ENOTSUP, "no lane-group kernel for capacity %d", kCaps[q]);
+      continue;
+    }
+    if (design == FSMP_DESIGN_LANE && kCaps[q] == 48) {
+      if (capacity != 0) return fail(c, FSMP_ENOTSUP, "no lane kernel for capacity 48");
+      continue;
+    }
+    c->design[q] = design;
+  }
+  if (!any) return fail(c, FSMP_EINVAL, "capacity %d is not one of the kernel capacities", capacity);
+  return FSMP_OK;
+}
+
+int32_t fsmp_get_design(const fsmp_ctx *c, int32_t capacity) {
+  if (!c) return FSMP_EINVAL;
+  for (int q = 0; q < kNumCaps; ++q)
+    if (kCaps[q] == capacity) return c->design[q];
+  return FSMP_EINVAL;
+}
+
+fsmp_status fsmp_autotune(fsmp_ctx *c, const fsmp_batch *b, int32_t trial_steps, void *hip_stream) {
+  if (!c) return FSMP_EINVAL;
+  if (!b || b->n_wave < 1) return fail(c, FSMP_EINVAL, "autotune needs a non-empty batch");
+  if (trial_steps < 1) return fail(c, FSMP_EINVAL, "trial_steps must be >= 1");
+  if (c->cfg.precision == FSMP_FP32_REFRESH) return FSMP_OK;  // the precision form has the lane design only
+  const int64_t n = b->n_wave;
+  int kz = 1;
+  for (int64_t i = 0; i < n; ++i) kz = std::max(kz, b->kmax ? b->kmax[i] : c->cfg.k_max);
+  const int64_t C = n * c->cfg.n_chains;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(c->device);
+  // scratch outputs for the trials
+  DevBuf<int32_t> i1, i2, i3, i4, i5;
+  DevBuf<double> d1, d2, d3;
+  hipError_t e = i1.ensure(C);
+  if (e == hipSuccess) e = i2.ensure((size_t)C * kz);
+  if (e == hipSuccess) e = i3.ensure((size_t)C * (kz + 1));
+  if (e == hipSuccess) e = i4.ensure((size_t)C * 8);
+  if (e == hipSuccess) e = i5.ensure(C);
+  if (e == hipSuccess) e = d1.ensure(C);
+  if (e == hipSuccess) e = d2.ensure((size_t)C * kz);
+  if (e == hipSuccess) e = d3.ensure((size_t)C * 12);
+  if (e != hipSuccess) {
+    (void)hipSetDevice(prev);
+    return fail(c, FSMP_ENOMEM, "autotune scratch: %s", hipGetErrorString(e));
+  }
+  fsmp_samples o{};
+  o.n_pe = i1.p;
+  o.z = i2.p;
+  o.nhist = i3.p;
+  o.counts = i4.p;
+  o.status = (uint32_t *)i5.p;
+  o.t0 = d1.p;
+  o.charge = d2.p;
+  o.acc = d3.p;
+  o.kz = kz;
+  const fsmp_config saved = c->cfg;
+  const bool saved_timing = c->timing;
+  int saved_design[kNumCaps];
+  std::memcpy(saved_design, c->design, sizeof saved_design);
+  c->cfg.n_steps = trial_steps;
+  c->cfg.burn_in = 0;
+  c->cfg.record_flags = 0;
+  c->timing = true;
+  double ms[2][kNumCaps];
+  fsmp_status st = FSMP_OK;
+  for (int d = 0; d < 2 && st == FSMP_OK; ++d) {
+    for (int q = 0; q < kNumCaps; ++q) {
+      ms[d][q] = -1.0;
+      c->design[q] = saved_design[q];
+      if (d == 0 && chain_kcap_supported(kCaps[q], c->tab.M, c->cfg.grid_sub)) c->design[q] = FSMP_DESIGN_GROUP;
+      if (d == 1 && kCaps[q] != 48) c->design[q] = FSMP_DESIGN_LANE;
+    }
+    st = fsmp_sample(c, b, &o, hip_stream);
+    if (st != FSMP_OK) break;
+    std::vector<fsmp_timing> tv(c->timings.size() + 1);
+    const int32_t nt = fsmp_last_timings(c, tv.data(), (int32_t)tv.size());
+    for (int32_t k = 0; k < nt; ++k)
+      for (int q = 0; q < kNumCaps; ++q)
+        if (tv[k].kcap == kCaps[q]) ms[d][q] = tv[k].ms;
+  }
+  c->cfg = saved;
+  c->timing = saved_timing;
+  std::memcpy(c->design, saved_design, sizeof saved_design);
+  // a capacity is decided only where both designs exist (16, 32, 64)
+  if (st == FSMP_OK)
+    for (int q = 0; q < kNumCaps; ++q)
+      if (ms[0][q] >= 0.0 && ms[1][q] >= 0.0 && kCaps[q] != 48 &&
+          chain_kcap_supported(kCaps[q], c->tab.M, c->cfg.grid_sub))
+        c->design[q] = ms[1][q] < ms[0][q] ? FSMP_DESIGN_LANE : FSMP_DESIGN_GROUP;
+  (void)hipStreamSynchronize((hipStream_t)hip_stream);
+  i1.release();
+  i2.release();
+  i3.release();
+  i4.release();
+  i5.release();
+  d1.release();
+  d2.release();
+  d3.release();
+  (void)hipSetDevice(prev);
+  return st;
+}
+
+// The graph owns a private context: its kernels read that context's workspace
+// (uploaded batch metadata, chain lists, lane-design state), which later calls on the
+// caller's context may overwrite or reallocate without touching the graph.
+struct fsmp_graph {
+  fsmp_ctx *ctx = nullptr;
+  fsmp_ctx *own = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t stream = nullptr;
+};
+
+fsmp_status fsmp_graph_create(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o, void *hip_stream,
+                              fsmp_graph **out) {
+  if (!c) return FSMP_EINVAL;
+  if (!out) return fail(c, FSMP_EINVAL, "graph output pointer is NULL");
+  *out = nullptr;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(c->device);
+  auto *g = new fsmp_graph();
+  g->ctx = c;
+  fsmp_status st = fsmp_create(&g->own, &c->ser, &c->phi, &c->cfg, c->device);
+  if (st != FSMP_OK) {
+    delete g;
+    (void)hipSetDevice(prev);
+    return fail(c, st, "graph context: %s", fsmp_last_error(nullptr));
+  }
+  std::memcpy(g->own->design, c->design, sizeof c->design);
+  hipError_t e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    fsmp_graph_destroy(g);
+    (void)hipSetDevice(prev);
+    return fail(c, FSMP_EDEVICE, "graph stream: %s", hipGetErrorString(e));
+  }
+  fsmp_ctx *k = g->own;
+  k->capture = g->stream;
+  k->captured = nullptr;
+  st = fsmp_sample(k, b, o, hip_stream);
+  k->capture = nullptr;
+  g->graph = k->captured;
+  k->captured = nullptr;
+  if (st != FSMP_OK) st = fail(c, st, "%s", k->err.c_str());
+  if (st == FSMP_OK && g->graph) {
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) st = fail(c, FSMP_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+  } else if (st == FSMP_OK) {
+    st = fail(c, FSMP_EDEVICE, "graph capture produced no graph");
+  }
+  if (st != FSMP_OK) {
+    fsmp_graph_destroy(g);
+    (void)hipSetDevice(prev);
+    return st;
+  }
+  (void)hipSetDevice(prev);
+  *out = g;
+  return FSMP_OK;
+}
+
+fsmp_status fsmp_graph_launch(fsmp_graph *g, void *hip_stream) {
+  if (!g || !g->exec) return FSMP_EINVAL;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(g->ctx->device);
+  const hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)hip_stream);
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) return fail(g->ctx, FSMP_EDEVICE, "graph launch: %s", hipGetErrorString(e));
+  return FSMP_OK;
+}
+
+void fsmp_graph_destroy(fsmp_graph *g) {
+  if (!g) return;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->stream) (void)hipStreamDestroy(g->stream);
+  if (g->own) fsmp_destroy(g->own);
+  delete g;
 }
 
 fsmp_status fsmp_posterior(fsmp_ctx *c, int64_t n_wave, const fsmp_samples *in, fsmp_posterior_out *out,

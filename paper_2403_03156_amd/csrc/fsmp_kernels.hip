@@ -601,20 +601,31 @@ __device__ inline int birth_draw_lane(const ModelDev &md, double t0, int glo, in
 // their storage type (FP64, or FP32 in the precision form) and written back rounded.
 constexpr int kChunk = 8;
 
-// eta = M gamma over the first n rows (rows in blocks of 4); q = gamma^T eta and, when
-// X is given, p = gamma^T x, both summed in row order
+// eta = M gamma over the first n rows; q = gamma^T eta and, when X is given,
+// p = gamma^T x, both summed in row order.  Rows go in blocks of 4 and columns in
+// chunks of 4: the 20 loads of a chunk are issued unconditionally (indices stay below
+// KCAP, a multiple of 4) and the columns past n are dropped by a select, so a chunk
+// costs one memory round trip; each row still sums its terms in column order.
 template <int KCAP, typename MT>
 __device__ inline void lane_matvec(const MT *Mp, const double *G, double *E, const double *X, int n, double &q,
                                    double &p) {
+  static_assert(KCAP % 8 == 0, "capacity must be a multiple of 8");
   q = 0.0;
   p = 0.0;
   for (int i0 = 0; i0 < n; i0 += 4) {
     double e[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < n; ++k) {
-      const double gk = G[k * 64];
+    for (int k0 = 0; k0 < n; k0 += 4) {
+      double g[4], h[4][4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (i0 + u < n) e[u] += (double)Mp[(k * KCAP + i0 + u) * 64] * gk;
+      for (int kk = 0; kk < 4; ++kk) {
+        g[kk] = G[(k0 + kk) * 64];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) h[kk][u] = (double)Mp[((k0 + kk) * KCAP + i0 + u) * 64];
+      }
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) e[u] = (k0 + kk < n) ? e[u] + h[kk][u] * g[kk] : e[u];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -627,7 +638,8 @@ __device__ inline void lane_matvec(const MT *Mp, const double *G, double *E, con
   }
 }
 
-// M(k, i) += (A_i A_k) cA [+ (B_i B_k) cB] for i, k < n
+// M(k, i) += (A_i A_k) cA [+ (B_i B_k) cB] for i, k < n.  Loads of a chunk of 8 columns
+// are unconditional (below KCAP), stores are guarded.
 template <int KCAP, bool TWO, typename MT>
 __device__ inline void lane_rank_update(MT *Mp, const double *A, double cA, const double *B, double cB, int n) {
   for (int k = 0; k < n; ++k) {
@@ -636,31 +648,29 @@ __device__ inline void lane_rank_update(MT *Mp, const double *A, double cA, cons
     for (int i0 = 0; i0 < n; i0 += kChunk) {
       double h[kChunk], av[kChunk], bv[kChunk];
 #pragma unroll
-      for (int u = 0; u < kChunk; ++u)
-        if (i0 + u < n) {
-          h[u] = (double)Mp[(k * KCAP + i0 + u) * 64];
-          av[u] = A[(i0 + u) * 64];
-          if (TWO) bv[u] = B[(i0 + u) * 64];
-        }
+      for (int u = 0; u < kChunk; ++u) {
+        h[u] = (double)Mp[(k * KCAP + i0 + u) * 64];
+        av[u] = A[(i0 + u) * 64];
+        if (TWO) bv[u] = B[(i0 + u) * 64];
+      }
 #pragma unroll
-      for (int u = 0; u < kChunk; ++u)
-        if (i0 + u < n) {
-          double v = h[u] + av[u] * ak * cA;
-          if (TWO) v += bv[u] * bk * cB;
-          Mp[(k * KCAP + i0 + u) * 64] = (MT)v;
-        }
+      for (int u = 0; u < kChunk; ++u) {
+        double v = h[u] + av[u] * ak * cA;
+        if (TWO) v += bv[u] * bk * cB;
+        if (i0 + u < n) Mp[(k * KCAP + i0 + u) * 64] = (MT)v;
+      }
     }
   }
 }
 
-// n elements src[e * 64] -> dst[e * 64] (chunked), converting the type
+// n elements src[e * 64] -> dst[e * 64] (chunked, loads unconditional below the
+// capacity of both rows), converting the type
 template <typename DT, typename ST>
 __device__ inline void lane_copy(DT *dst, const ST *src, int n) {
   for (int i0 = 0; i0 < n; i0 += kChunk) {
     double v[kChunk];
 #pragma unroll
-    for (int u = 0; u < kChunk; ++u)
-      if (i0 + u < n) v[u] = (double)src[(i0 + u) * 64];
+    for (int u = 0; u < kChunk; ++u) v[u] = (double)src[(i0 + u) * 64];
 #pragma unroll
     for (int u = 0; u < kChunk; ++u)
       if (i0 + u < n) dst[(i0 + u) * 64] = (DT)v[u];

@@ -292,6 +292,9 @@ fsmp_status fsmp_server_create(fsmp_server **out, const fsmp_ser *ser, const fsm
       for (auto &x : s->slots) fsmp_destroy(x->ctx);
       return st;
     }
+    // latency: the lane-group kernels finish a sweep in microseconds; one lane per chain
+    // with its state in device memory needs many memory round trips per sweep
+    (void)fsmp_set_design(sl->ctx, 0, FSMP_DESIGN_GROUP);
     (void)hipSetDevice(device);
     if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl->done, hipEventDisableTiming) != hipSuccess) {

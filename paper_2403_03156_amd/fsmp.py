@@ -22,7 +22,9 @@ FSMP_ST_KMAX, FSMP_ST_NONFINITE, FSMP_ST_DRIFT, FSMP_ST_EMPTY_T, FSMP_ST_FACTOR 
 EXPORTS = ("fsmp_create", "fsmp_workspace_bytes", "fsmp_sample", "fsmp_posterior", "fsmp_last_timings",
            "fsmp_set_timing", "fsmp_last_error", "fsmp_destroy", "fsmp_version", "fsmp_server_create",
            "fsmp_server_submit", "fsmp_server_progress", "fsmp_server_result", "fsmp_server_stats",
-           "fsmp_server_last_error", "fsmp_server_destroy")
+           "fsmp_server_last_error", "fsmp_server_destroy", "fsmp_set_design", "fsmp_get_design", "fsmp_autotune",
+           "fsmp_graph_create", "fsmp_graph_launch", "fsmp_graph_destroy")
+FSMP_DESIGN_GROUP, FSMP_DESIGN_LANE = 0, 1
 
 
 class fsmp_ser(ctypes.Structure):
@@ -130,6 +132,19 @@ def load(path: Optional[str] = None):
     L.fsmp_server_last_error.restype = ctypes.c_char_p
     L.fsmp_server_destroy.argtypes = [ctypes.c_void_p]
     L.fsmp_server_destroy.restype = None
+    L.fsmp_set_design.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
+    L.fsmp_set_design.restype = ctypes.c_int
+    L.fsmp_get_design.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.fsmp_get_design.restype = ctypes.c_int32
+    L.fsmp_autotune.argtypes = [ctypes.c_void_p, P(fsmp_batch), ctypes.c_int32, ctypes.c_void_p]
+    L.fsmp_autotune.restype = ctypes.c_int
+    L.fsmp_graph_create.argtypes = [ctypes.c_void_p, P(fsmp_batch), P(fsmp_samples), ctypes.c_void_p,
+                                    P(ctypes.c_void_p)]
+    L.fsmp_graph_create.restype = ctypes.c_int
+    L.fsmp_graph_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    L.fsmp_graph_launch.restype = ctypes.c_int
+    L.fsmp_graph_destroy.argtypes = [ctypes.c_void_p]
+    L.fsmp_graph_destroy.restype = None
     _lib = L
     return L
 
@@ -216,6 +231,55 @@ class Sampler:
             n_rec = (S + self.cfg.thin - 1) // self.cfg.thin if S > 0 else 0
             out["trace"] = torch.zeros((C, max(n_rec, 1), 3), dtype=torch.float64, device=dev)
         return out
+
+    def _batch(self, wave, offsets, lam, kmax=None, g_range=None, t0_init=None, wave_id=None):
+        import torch
+        if not wave.is_cuda or wave.dtype != torch.float32 or not wave.is_contiguous():
+            raise ValueError("wave must be a contiguous float32 device tensor")
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        kmax = None if kmax is None else np.ascontiguousarray(kmax, dtype=np.int32)
+        g_range = None if g_range is None else np.ascontiguousarray(g_range, dtype=np.int32).reshape(-1)
+        t0_init = None if t0_init is None else np.ascontiguousarray(t0_init, dtype=np.float64)
+        wave_id = None if wave_id is None else np.ascontiguousarray(wave_id, dtype=np.uint64)
+        keep = (offsets, lam, kmax, g_range, t0_init, wave_id)
+        b = fsmp_batch(len(offsets) - 1, ctypes.c_void_p(wave.data_ptr()), _hptr(offsets), _hptr(lam), _hptr(kmax),
+                       _hptr(g_range), _hptr(t0_init), _hptr(wave_id))
+        return b, keep
+
+    @staticmethod
+    def _samples(out):
+        return fsmp_samples(_dptr(out["n_pe"]), _dptr(out["t0"]), _dptr(out["z"]), _dptr(out["charge"]),
+                            _dptr(out["acc"]), _dptr(out["nhist"]), _dptr(out["counts"]), _dptr(out["status"]),
+                            _dptr(out["log"]), _dptr(out["trace"]), out["kz"], _dptr(out.get("work")))
+
+    def set_design(self, capacity, design):
+        self._check(self.lib.fsmp_set_design(self.h, capacity, design))
+
+    def get_design(self, capacity):
+        return self.lib.fsmp_get_design(self.h, capacity)
+
+    def autotune(self, wave, offsets, lam, kmax=None, trial_steps=50, stream=None):
+        import torch
+        b, keep = self._batch(wave, offsets, lam, kmax)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._check(self.lib.fsmp_autotune(self.h, ctypes.byref(b), trial_steps, ctypes.c_void_p(st.cuda_stream)))
+        return {c: self.get_design(c) for c in (16, 32, 48, 64, 96, 128, 160, 192)}
+
+    def graph(self, wave, offsets, lam, kmax=None, out=None, kz=None, stream=None):
+        """Capture the kernels of one sample() call into a HIP graph; returns (Graph, out)."""
+        import torch
+        b, keep = self._batch(wave, offsets, lam, kmax)
+        if kz is None:
+            kz = int(np.max(kmax)) if kmax is not None else self.cfg.k_max
+        if out is None:
+            out = self.alloc_samples(len(offsets) - 1, kz)
+        s = self._samples(out)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        g = ctypes.c_void_p()
+        self._check(self.lib.fsmp_graph_create(self.h, ctypes.byref(b), ctypes.byref(s), ctypes.c_void_p(st.cuda_stream),
+                                               ctypes.byref(g)))
+        return Graph(self, g, keep), out
 
     def sample(self, wave, offsets, lam, kmax=None, g_range=None, t0_init=None, wave_id=None, out=None, kz=None,
                stream=None, work=False):
@@ -340,6 +404,29 @@ class Server:
     def close(self):
         if getattr(self, "h", None):
             self.lib.fsmp_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A captured fsmp_sample launch sequence (fsmp_graph_*)."""
+
+    def __init__(self, sampler, handle, keep):
+        self.sampler, self.h, self._keep = sampler, handle, keep
+
+    def launch(self, stream=None):
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream(self.sampler.device)
+        self.sampler._check(self.sampler.lib.fsmp_graph_launch(self.h, ctypes.c_void_p(st.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.sampler.lib.fsmp_graph_destroy(self.h)
             self.h = None
 
     def __del__(self):

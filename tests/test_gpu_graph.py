@@ -1,0 +1,97 @@
+"""Launch machinery around the chain kernels (needs an MI355X).
+
+* fsmp_graph_*: a captured batch replays to bit-identical outputs, several times, with
+  eager sampling on the same context, output clearing and synchronisations between the
+  replays;
+* fsmp_set_design / fsmp_autotune: the chosen design per PE capacity is one that exists,
+  and a batch run with the tuned designs still agrees with the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_03156_amd import fsmp, synth
+from tests.fsmp_cases import compare_chains, gpu_sampler, oracle_params, to_host
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+KEYS = ("n_pe", "t0", "z", "charge", "acc", "nhist", "counts", "status")
+
+
+def _batch(n, seed, preset="batched"):
+    wl = synth.PRESETS[preset]
+    b = synth.generate(wl, n_wave=n, seed=seed)
+    return wl, b, synth.kmax_for(b["lam"])
+
+
+def test_graph_replays_equal_eager():
+    wl, b, km = _batch(96, 41)
+    _, b2, km2 = _batch(40, 42)
+    kz = int(km.max())
+    print(f"[case] graph replay n=96 kz={kz} caps={sorted(set(km.tolist()))}", flush=True)
+    smp = gpu_sampler(wl, 200, 100, 2, 9)
+    wave = torch.from_numpy(b["wave"]).cuda()
+    ref = to_host(smp.sample(wave, b["offsets"], b["lam"], kmax=km, kz=kz))
+    g, out = smp.graph(wave, b["offsets"], b["lam"], kmax=km, kz=kz)
+    wave2 = torch.from_numpy(b2["wave"]).cuda()
+    for r in range(3):
+        for k in KEYS:
+            out[k].zero_()
+        # eager work on the same context between replays: another batch, other sizes
+        smp.sample(wave2, b2["offsets"], b2["lam"], kmax=km2, kz=int(km2.max()))
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        got = to_host(out)
+        for k in KEYS:
+            np.testing.assert_array_equal(got[k], ref[k], err_msg=f"replay {r}: {k}")
+    g.close()
+
+
+def test_graph_rejects_bad_batch():
+    wl, b, km = _batch(4, 3)
+    smp = gpu_sampler(wl, 10, 5, 1, 1)
+    km_bad = km.copy()
+    km_bad[0] = 1000
+    with pytest.raises(RuntimeError):
+        smp.graph(torch.from_numpy(b["wave"]).cuda(), b["offsets"], b["lam"], kmax=km_bad, kz=1000)
+
+
+def test_set_design_validation():
+    wl, _, _ = _batch(2, 1)
+    smp = gpu_sampler(wl, 10, 5, 1, 1)
+    smp.set_design(16, fsmp.FSMP_DESIGN_GROUP)
+    assert smp.get_design(16) == fsmp.FSMP_DESIGN_GROUP
+    smp.set_design(16, fsmp.FSMP_DESIGN_LANE)
+    assert smp.get_design(16) == fsmp.FSMP_DESIGN_LANE
+    with pytest.raises(RuntimeError):
+        smp.set_design(48, fsmp.FSMP_DESIGN_LANE)
+    with pytest.raises(RuntimeError):
+        smp.set_design(96, fsmp.FSMP_DESIGN_GROUP)
+    with pytest.raises(RuntimeError):
+        smp.set_design(20, fsmp.FSMP_DESIGN_LANE)
+    smp.set_design(0, fsmp.FSMP_DESIGN_GROUP)  # every capacity that has the design
+    assert [smp.get_design(c) for c in synth.KCAPS] == [0, 0, 0, 0, 1, 1, 1, 1]
+
+
+def test_autotune_keeps_results_correct():
+    wl, b, km = _batch(400, 51)
+    kz = int(km.max())
+    smp = gpu_sampler(wl, 120, 60, 1, 13)
+    wave = torch.from_numpy(b["wave"]).cuda()
+    designs = smp.autotune(wave, b["offsets"], b["lam"], kmax=km, trial_steps=40)
+    print(f"[autotune] {designs}", flush=True)
+    assert designs[48] == fsmp.FSMP_DESIGN_GROUP
+    assert all(designs[c] == fsmp.FSMP_DESIGN_LANE for c in (96, 128, 160, 192))
+    # a sub-batch in the tuned designs against the oracle
+    n = 60
+    off = b["offsets"][:n + 1]
+    out = smp.sample(torch.from_numpy(b["wave"][:off[-1]].copy()).cuda(), off, b["lam"][:n], kmax=km[:n],
+                     kz=int(km[:n].max()))
+    torch.cuda.synchronize()
+    g = to_host(out)
+    o = oracle.run(oracle_params(wl), b["wave"][:off[-1]], off, b["lam"][:n], 1, 120, 60, 13, int(km[:n].max()),
+                   kmax=km[:n])
+    parted = compare_chains(g, o)
+    assert len(parted) <= 0.3 * n, parted
