@@ -99,7 +99,11 @@ def lib():
         L.ora_t0_log_alpha.argtypes = [_P(Params), _d, _i32, _i32, _vp, _i32, _d, _d]
         L.ora_t0_log_alpha.restype = _d
         L.ora_run.argtypes = [_P(Params), _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _u64, _i32,
-                              _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32]
+                              _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _i32]
+        L.ora_charge_draw.argtypes = [_P(Params), _vp, _i32, _vp, _i32, _vp, _vp]
+        L.ora_charge_draw.restype = ctypes.c_int
+        L.ora_charge_normals.argtypes = [_u64, _u64, _i32, _i32, _vp]
+        L.ora_charge_normals.restype = None
         L.ora_run.restype = ctypes.c_int
         L.ora_replay.argtypes = [_P(Params), _vp, _i32, _d, _i32, _i32, _i32, _u64, _u64, _i32, _vp, _vp, _vp, _d]
         L.ora_replay.restype = _i64
@@ -155,8 +159,11 @@ class RunResult:
 
 
 def run(p: Params, wave, offsets, lam, n_chains, n_steps, burn_in, seed, kz, kmax=None, g_range=None, t0_init=None,
-        wave_id=None, log=False, thin=0, n_threads=0):
-    """Run ``n_chains`` chains per waveform; outputs are per chain (index wave*n_chains + chain)."""
+        wave_id=None, log=False, thin=0, n_threads=0, charges=False):
+    """Run ``n_chains`` chains per waveform; outputs are per chain (index wave*n_chains + chain).
+
+    ``thin`` > 0 records (N, t0, Q) every thin-th step after burn-in into ``trace``; with
+    ``charges`` it also records the PE list (``zdraw``) and one charge draw (``qdraw``)."""
     wave = np.ascontiguousarray(wave, dtype=np.float32)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     lam = np.ascontiguousarray(lam, dtype=np.float64)
@@ -178,11 +185,30 @@ def run(p: Params, wave, offsets, lam, n_chains, n_steps, burn_in, seed, kz, kma
     r.log = np.zeros((tot, n_steps), LOGREC_DTYPE) if log else None
     n_rec = (n_steps - burn_in + thin - 1) // thin if (thin > 0 and n_steps > burn_in) else 0
     r.trace = np.zeros((tot, n_rec, 3), np.float64) if n_rec else None
+    r.qdraw = np.zeros((tot, n_rec, kz), np.float64) if (n_rec and charges) else None
+    r.zdraw = np.zeros((tot, n_rec, kz), np.int32) if (n_rec and charges) else None
     lib().ora_run(ctypes.byref(p), nw, _ptr(wave), _ptr(offsets), _ptr(lam), _ptr(kmax), _ptr(g_range),
                   _ptr(t0_init), _ptr(wave_id), n_chains, n_steps, burn_in, seed, kz, _ptr(r.N), _ptr(r.t0),
                   _ptr(r.z), _ptr(r.x), _ptr(r.acc), _ptr(r.nhist), _ptr(r.counts), _ptr(r.status), _ptr(r.log),
-                  _ptr(r.trace), thin, n_threads)
+                  _ptr(r.trace), thin, _ptr(r.qdraw), _ptr(r.zdraw), n_threads)
     return r
+
+
+def charge_draw(p: Params, w, z, xi):
+    """q = x + sigma_eps L^-T xi for the PE list z (G = L L^T); None if G is not positive definite."""
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    z = np.ascontiguousarray(z, dtype=np.int32)
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    q = np.zeros(max(len(z), 1), np.float64)
+    rc = lib().ora_charge_draw(ctypes.byref(p), _ptr(w), len(w), _ptr(z), len(z), _ptr(xi), _ptr(q))
+    return None if rc else q[: len(z)]
+
+
+def charge_normals(uid, seed, step, K):
+    """The K standard normals of the charge draw at ``step`` of chain ``uid``."""
+    xi = np.zeros(max(K, 1), np.float64)
+    lib().ora_charge_normals(uid, seed, step, K, _ptr(xi))
+    return xi[:K]
 
 
 def replay(p: Params, w, lam, kmax, glo, ghi, uid, seed, rec, tie_eps=1e-9):

@@ -377,6 +377,104 @@ double ora_log_likelihood(const ora_params *p, const float *w, int32_t Lw, const
   return -0.5 * (Lw * log(2.0 * M_PI * s) + ww / s) + nu;
 }
 
+/* ------------------------------------------------------------------ */
+/* Charge draw given z.  With the Gaussian charge model (Sec. 2.1) the  */
+/* charges' conditional law given z and w is normal (App. A, eq.        */
+/* mgauss, read as Bayesian linear regression): mean x = G^-1 b and     */
+/* covariance sigma_eps^2 G^-1, G = A^T A + rho I, b = A^T w + rho mu_q. */
+/* A draw is q = x + sigma_eps L^-T xi with G = L L^T (lower Cholesky)  */
+/* and standard normals xi, one per PE in list order: L^-T xi has       */
+/* covariance L^-T L^-1 = G^-1.  Returns -1 if G is not positive        */
+/* definite.                                                            */
+/* ------------------------------------------------------------------ */
+static int charge_draw(const ora_ctx *c, const int32_t *z, int K, const double *xi, double *q) {
+  const ora_params *p = c->p;
+  double s = p->sigma_eps * p->sigma_eps;
+  double rho = s / (p->sigma_q * p->sigma_q);
+  if (K == 0) return 0;
+  double *G = (double *)malloc(sizeof(double) * K * K);
+  double *L = (double *)calloc((size_t)K * K, sizeof(double));
+  double *b = (double *)malloc(sizeof(double) * K);
+  double *u = (double *)malloc(sizeof(double) * K);
+  double *x = (double *)malloc(sizeof(double) * K);
+  double *y = (double *)malloc(sizeof(double) * K);
+  for (int i = 0; i < K; ++i) {
+    for (int k = 0; k <= i; ++k) {
+      double o = overlap(c, z[i], z[k]);
+      G[i * K + k] = o;
+      G[k * K + i] = o;
+    }
+    G[i * K + i] += rho;
+    b[i] = matched(c, z[i]) + rho * p->mu_q;
+  }
+  int fail = 0;
+  for (int j = 0; j < K && !fail; ++j) {
+    double d = G[j * K + j];
+    for (int k = 0; k < j; ++k) d -= L[j * K + k] * L[j * K + k];
+    if (!(d > 0.0)) { fail = 1; break; }
+    L[j * K + j] = sqrt(d);
+    for (int i = j + 1; i < K; ++i) {
+      double v = G[i * K + j];
+      for (int k = 0; k < j; ++k) v -= L[i * K + k] * L[j * K + k];
+      L[i * K + j] = v / L[j * K + j];
+    }
+  }
+  if (!fail) {
+    /* x = G^-1 b: forward solve L u = b, back solve L^T x = u */
+    for (int i = 0; i < K; ++i) {
+      double v = b[i];
+      for (int k = 0; k < i; ++k) v -= L[i * K + k] * u[k];
+      u[i] = v / L[i * K + i];
+    }
+    for (int i = K - 1; i >= 0; --i) {
+      double v = u[i];
+      for (int k = i + 1; k < K; ++k) v -= L[k * K + i] * x[k];
+      x[i] = v / L[i * K + i];
+    }
+    /* y = L^-T xi: back solve L^T y = xi */
+    for (int i = K - 1; i >= 0; --i) {
+      double v = xi[i];
+      for (int k = i + 1; k < K; ++k) v -= L[k * K + i] * y[k];
+      y[i] = v / L[i * K + i];
+    }
+    for (int i = 0; i < K; ++i) q[i] = x[i] + p->sigma_eps * y[i];
+  }
+  free(G); free(L); free(b); free(u); free(x); free(y);
+  return fail ? -1 : 0;
+}
+
+/* the standard normals of the charge draw at `step` of chain `uid`: PE k of the
+ * list takes Philox block 2 + k/2; the Box-Muller pair of words 0 and 1 gives
+ * the cosine branch to even k and the sine branch to odd k */
+static void charge_normals(uint64_t uid, uint64_t seed, int32_t step, int K, double *xi) {
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (int k = 0; k < K; k += 2) {
+    uint32_t r[4];
+    uint32_t ctr[4] = {(uint32_t)step, 2u + (uint32_t)(k / 2), (uint32_t)uid, (uint32_t)(uid >> 32)};
+    ora_philox4x32_10(ctr, key, r);
+    double R = sqrt(-2.0 * log(u01_open(r[0])));
+    double th = 2.0 * M_PI * u01_open(r[1]);
+    xi[k] = R * cos(th);
+    if (k + 1 < K) xi[k + 1] = R * sin(th);
+  }
+}
+
+/* one charge draw for given z and normals xi (for the tests that pin it) */
+int ora_charge_draw(const ora_params *p, const float *w, int32_t Lw, const int32_t *z, int32_t K, const double *xi,
+                    double *q) {
+  ora_table t;
+  table_init(&t, p);
+  ora_ctx c;
+  ctx_init(&c, p, &t, w, Lw);
+  int rc = charge_draw(&c, z, K, xi, q);
+  table_free(&t);
+  return rc;
+}
+
+void ora_charge_normals(uint64_t uid, uint64_t seed, int32_t step, int32_t K, double *xi) {
+  charge_normals(uid, seed, step, K, xi);
+}
+
 /* matched filter and overlaps, exposed for the table-level pins */
 double ora_overlap(const ora_params *p, int32_t Lw, int32_t g1, int32_t g2) {
   ora_table t;
@@ -504,7 +602,7 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
                           int32_t ghi, double t0_init, uint64_t uid, uint64_t seed, int32_t n_steps, int32_t burn_in,
                           int32_t kz, int32_t *N_out, double *t0_out, int32_t *z_out, double *x_out, double *acc,
                           int32_t *nhist, int32_t *counts, uint32_t *status, ora_logrec *logrec, double *trace,
-                          int32_t thin) {
+                          int32_t thin, double *qdraw, int32_t *zdraw) {
   ora_ctx c;
   ctx_init(&c, p, tab, w, Lw);
   double dt = 1.0 / p->sub;
@@ -516,6 +614,8 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
   int32_t *zb = (int32_t *)calloc((size_t)kmax + 2, sizeof(int32_t));
   double *x = (double *)calloc((size_t)kmax + 1, sizeof(double));
   double *xb = (double *)calloc((size_t)kmax + 2, sizeof(double));
+  double *xi = (double *)calloc((size_t)kmax + 1, sizeof(double));
+  double *qb = (double *)calloc((size_t)kmax + 1, sizeof(double));
   int N = 0;
   double t0 = t0_init, nu_cur = 0.0;
   memset(acc, 0, sizeof(double) * 12);
@@ -630,6 +730,18 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
         tr[1] = t0;
         tr[2] = Q;
       }
+      /* charge draw of the recorded state (NaN if G is not positive definite) */
+      if (qdraw && thin > 0 && (i % thin) == 0) {
+        double *qr = qdraw + (size_t)kz * (i / thin);
+        int32_t *zr = zdraw + (size_t)kz * (i / thin);
+        charge_normals(uid, seed, step, N, xi);
+        int rc = charge_draw(&c, z, N, xi, qb);
+        if (rc) st |= ORA_ST_FACTOR;
+        for (int k = 0; k < kz; ++k) {
+          zr[k] = k < N ? z[k] : -1;
+          qr[k] = k < N ? (rc ? NAN : qb[k]) : 0.0;
+        }
+      }
     }
   }
   *N_out = N;
@@ -639,7 +751,7 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
     x_out[k] = k < N ? x[k] : 0.0;
   }
   *status = st;
-  free(z); free(zb); free(x); free(xb);
+  free(z); free(zb); free(x); free(xb); free(xi); free(qb);
 }
 
 /* Run n_chains chains for every waveform.  Chain c of waveform i writes
@@ -649,7 +761,8 @@ int ora_run(const ora_params *p, int64_t n_wave, const float *wave, const int64_
             const int32_t *kmax, const int32_t *g_range, const double *t0_init, const uint64_t *wave_id,
             int32_t n_chains, int32_t n_steps, int32_t burn_in, uint64_t seed, int32_t kz, int32_t *N_out,
             double *t0_out, int32_t *z_out, double *x_out, double *acc, int32_t *nhist, int32_t *counts,
-            uint32_t *status, ora_logrec *logrec, double *trace, int32_t thin, int32_t n_threads) {
+            uint32_t *status, ora_logrec *logrec, double *trace, int32_t thin, double *qdraw, int32_t *zdraw,
+            int32_t n_threads) {
   int64_t total = n_wave * n_chains;
   int64_t n_rec = (thin > 0 && n_steps > burn_in) ? (n_steps - burn_in + thin - 1) / thin : 0;
   ora_table tab;
@@ -670,7 +783,8 @@ int ora_run(const ora_params *p, int64_t n_wave, const float *wave, const int64_
     run_one_chain(p, &tab, wave + offsets[i], Lw, lambda[i], kmax ? kmax[i] : kz, glo, ghi, t0i, uid, seed, n_steps,
                   burn_in, kz, &N_out[ic], &t0_out[ic], z_out + ic * kz, x_out + ic * kz, acc + ic * 12,
                   nhist + ic * (kz + 1), counts + ic * 8, &status[ic], logrec ? logrec + ic * n_steps : NULL,
-                  trace ? trace + ic * 3 * n_rec : NULL, thin);
+                  trace ? trace + ic * 3 * n_rec : NULL, thin, qdraw ? qdraw + ic * kz * n_rec : NULL,
+                  zdraw ? zdraw + ic * kz * n_rec : NULL);
   }
   table_free(&tab);
   return 0;
