@@ -59,8 +59,10 @@ enum { FSMP_FP64 = 0, FSMP_FP32_REFRESH = 1 };
 
 /* record_flags */
 enum {
-  FSMP_REC_TRACE = 1u, /* per recorded step (N, t0, Q) into fsmp_samples.trace */
-  FSMP_REC_LOG = 2u    /* one fsmp_logrec per step into fsmp_samples.log (for replay checks) */
+  FSMP_REC_TRACE = 1u,  /* per recorded step (N, t0, Q) into fsmp_samples.trace */
+  FSMP_REC_LOG = 2u,    /* one fsmp_logrec per step into fsmp_samples.log (for replay checks) */
+  FSMP_REC_CHARGE = 4u  /* per recorded step the PE list and one charge draw into
+                           fsmp_samples.zdraw / qdraw (needs thin > 0) */
 };
 
 /* per-chain status bits */
@@ -157,7 +159,19 @@ typedef struct {
  *   work                  NULL, or [chain][4] work counters over all steps: sum of K^2 over
  *                         proposals evaluated with a K x K mat-vec, sum of K^2 over rank-one
  *                         edits (accepted births and deaths), sum of K^2 over rank-two edits
- *                         (accepted updates), sum of K over t0 proposals inside the prior */
+ *                         (accepted updates), sum of K over t0 proposals inside the prior
+ *   qdraw, zdraw          NULL, or [chain][n_rec][kz] when FSMP_REC_CHARGE: at every recorded
+ *                         step (the steps of `trace`) the PE grid indices (-1 beyond N) and one
+ *                         draw of the charges from their conditional law given z (Sec. 2.1
+ *                         charge model, App. A eq. mgauss), q ~ N(x, sigma_eps^2 G^-1), as
+ *                         q = x + sigma_eps R xi with R the upper-triangular factor of
+ *                         G^-1 = R R^T (R = L^-T for G = L L^T) and xi standard normals, PE k
+ *                         of the list from Philox block 2 + k/2 of that step (Box-Muller of
+ *                         words 0 and 1: cosine for even k, sine for odd k); 0 beyond N, NaN
+ *                         (with FSMP_ST_FACTOR) if the factorisation fails.  The draw reads
+ *                         the maintained G^-1 (FP32 in the precision form).  Costs O(K^3)
+ *                         per record; FP64 scratch of kcap^2 words per chain is allocated
+ *                         by fsmp_sample while the flag is set. */
 typedef struct {
   int32_t *n_pe;
   double *t0;
@@ -171,6 +185,8 @@ typedef struct {
   double *trace;
   int32_t kz;
   double *work;
+  double *qdraw;
+  int32_t *zdraw;
 } fsmp_samples;
 
 /* Posterior summaries per waveform (device buffers, caller-allocated): for (N, Q, t0)
@@ -288,6 +304,8 @@ typedef struct {
 
 typedef struct fsmp_server fsmp_server;
 
+/* The server returns posterior summaries per channel (fsmp_server_result): cfg.record_flags
+ * must be 0 (FSMP_EINVAL otherwise). */
 fsmp_status fsmp_server_create(fsmp_server **out, const fsmp_ser *ser, const fsmp_intensity *phi,
                                const fsmp_config *cfg, int device, const fsmp_server_config *scfg);
 /* Queue one event: n_wave channels, samples concatenated in wave (host, copied now),

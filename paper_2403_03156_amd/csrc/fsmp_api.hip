@@ -154,6 +154,7 @@ struct fsmp_ctx {
   DevBuf<uint32_t> wflags;
   DevBuf<double> lane_d;
   DevBuf<int32_t> lane_i;
+  DevBuf<double> draw_scr;  // charge draws: KCAP^2 FP64 words per chain
   // per PE capacity (kCaps): 1 = one lane per chain (state in device memory),
   // 0 = one lane group per chain (state in LDS; capacities up to 64)
   int design[kNumCaps] = {1, 1, 0, 0, 1, 1, 1, 1};
@@ -211,7 +212,9 @@ fsmp_status validate_model(const fsmp_ser *ser, const fsmp_intensity *phi, const
     return m = b, FSMP_EINVAL;
   }
   if ((cfg->record_flags & FSMP_REC_TRACE) && cfg->thin < 1) return m = "config: trace needs thin >= 1", FSMP_EINVAL;
-  if (cfg->record_flags & ~(uint32_t)(FSMP_REC_TRACE | FSMP_REC_LOG)) return m = "config: unknown record flag", FSMP_EINVAL;
+  if ((cfg->record_flags & FSMP_REC_CHARGE) && cfg->thin < 1) return m = "config: charge draws need thin >= 1", FSMP_EINVAL;
+  if (cfg->record_flags & ~(uint32_t)(FSMP_REC_TRACE | FSMP_REC_LOG | FSMP_REC_CHARGE))
+    return m = "config: unknown record flag", FSMP_EINVAL;
   if (cfg->precision != FSMP_FP64 && cfg->precision != FSMP_FP32_REFRESH) return m = "config: unknown precision", FSMP_EINVAL;
   if (cfg->precision == FSMP_FP32_REFRESH && cfg->refresh_M < 0) return m = "config: refresh_M must be >= 0", FSMP_EINVAL;
   return FSMP_OK;
@@ -355,6 +358,7 @@ void fsmp_destroy(fsmp_ctx *c) {
   c->wid.release();
   c->wflags.release();
   c->lane_d.release();
+  c->draw_scr.release();
   c->lane_i.release();
   c->stage.release();
   (void)hipSetDevice(prev);
@@ -400,6 +404,8 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     return fail(c, FSMP_EINVAL, "an output buffer is NULL");
   if ((cf.record_flags & FSMP_REC_LOG) && !o->log) return fail(c, FSMP_EINVAL, "FSMP_REC_LOG set but log is NULL");
   if ((cf.record_flags & FSMP_REC_TRACE) && !o->trace) return fail(c, FSMP_EINVAL, "FSMP_REC_TRACE set but trace is NULL");
+  if ((cf.record_flags & FSMP_REC_CHARGE) && (!o->qdraw || !o->zdraw))
+    return fail(c, FSMP_EINVAL, "FSMP_REC_CHARGE set but qdraw or zdraw is NULL");
   if (n > 0 && b->offsets[0] != 0) return fail(c, FSMP_EINVAL, "offsets[0] must be 0");
   const int sub = cf.grid_sub;
   // ---- per-waveform metadata
@@ -495,6 +501,14 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     }
     if (e == hipSuccess && lane_doff[kNumCaps] > 0) e = c->lane_d.ensure(lane_doff[kNumCaps]);
     if (e == hipSuccess && lane_ioff[kNumCaps] > 0) e = c->lane_i.ensure(lane_ioff[kNumCaps]);
+  }
+  size_t draw_off[kNumCaps + 1] = {0};
+  if (cf.record_flags & FSMP_REC_CHARGE) {
+    for (int bi = 0; bi < kNumCaps; ++bi) {
+      const int64_t cnt = bucket_start[bi + 1] - bucket_start[bi];
+      draw_off[bi + 1] = draw_off[bi] + (size_t)((cnt + 63) / 64 * 64) * caps[bi] * caps[bi];
+    }
+    if (e == hipSuccess && draw_off[kNumCaps] > 0) e = c->draw_scr.ensure(draw_off[kNumCaps]);
   }
   if (e != hipSuccess) {
     (void)hipSetDevice(prev);
@@ -614,6 +628,9 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   ca.status = o->status;
   ca.log = (cf.record_flags & FSMP_REC_LOG) ? o->log : nullptr;
   ca.trace = (cf.record_flags & FSMP_REC_TRACE) ? o->trace : nullptr;
+  ca.qdraw = (cf.record_flags & FSMP_REC_CHARGE) ? o->qdraw : nullptr;
+  ca.zdraw = (cf.record_flags & FSMP_REC_CHARGE) ? o->zdraw : nullptr;
+  ca.sigma_eps = cf.sigma_eps;
   ca.kz = o->kz;
   ca.wflags = c->wflags.p;
   ca.work = o->work;
@@ -632,6 +649,7 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
       ca.dws = c->lane_d.p + lane_doff[bi];
       ca.iws = c->lane_i.p + lane_ioff[bi];
     }
+    ca.dscr = ca.qdraw ? c->draw_scr.p + draw_off[bi] : nullptr;
     e = timed(name, caps[bi], [&](fsmp_timing &t) {
       t.chains = cnt;
       return lane ? launch_chain_lane(caps[bi], fp32, ca, st, &t.lanes, &t.blocks)

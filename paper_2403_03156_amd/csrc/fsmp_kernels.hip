@@ -69,6 +69,16 @@ __device__ inline double u53(uint32_t lo, uint32_t hi) {
   return (double)(v >> 11) * 0x1p-53 + 0x1p-54;
 }
 
+// Standard normal k of the charge draw at `step`: Philox block 2 + k/2, Box-Muller of
+// words 0 and 1, the cosine branch for even k and the sine branch for odd k.
+__device__ inline double charge_normal(int step, int k, uint32_t uid0, uint32_t uid1, uint32_t key0, uint32_t key1) {
+  uint32_t r[4];
+  philox4x32_10((uint32_t)step, 2u + (uint32_t)(k >> 1), uid0, uid1, key0, key1, r);
+  const double R = sqrt(-2.0 * log(u01(r[0])));
+  const double th = 2.0 * M_PI * u01(r[1]);
+  return (k & 1) ? R * sin(th) : R * cos(th);
+}
+
 // log phi(x); -inf where phi vanishes (x < 0, and x = 0 for BIEXP)
 __device__ inline double log_phi(const ModelDev &md, double x) {
   if (md.kind == FSMP_PHI_EXP) return x < 0.0 ? -INFINITY : -x * md.inv_tau2 - md.log_tau2;
@@ -538,6 +548,47 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
         tr[1] = v2;
         tr[2] = v1;
       }
+      if (a.qdraw && a.thin > 0 && (i % a.thin) == 0) {
+        // charge draw q = x + sigma_eps R xi, H = R R^T with R upper triangular: the
+        // factorisation runs from the last PE backwards on a copy of H's lower triangle
+        // in the chain's device-memory scratch; y = R xi accumulates column by column
+        const int64_t rec = c * a.n_rec + i / a.thin;
+        double *Ad = a.dscr + slot * (int64_t)(KCAP * KCAP);
+        WAVE_SYNC();
+        for (int r = lane; r < N; r += LPC) {
+          for (int k = 0; k <= r; ++k) Ad[r * KCAP + k] = H[k * LD + r];
+          s1[r] = charge_normal(step, r, uid0, uid1, a.key0, a.key1);
+          s2[r] = 0.0;
+        }
+        WAVE_SYNC();
+        bool ok = true;
+        for (int jj = N - 1; jj >= 0; --jj) {
+          const double ajj = Ad[jj * KCAP + jj];
+          if (!(ajj > 0.0)) {
+            ok = false;
+            break;
+          }
+          const double d = sqrt(ajj), xij = s1[jj];
+          for (int r = lane; r < jj; r += LPC) {
+            const double v = Ad[jj * KCAP + r] / d;
+            s3[r] = v;
+            s2[r] += v * xij;
+          }
+          if (lane == 0) s2[jj] += d * xij;
+          WAVE_SYNC();
+          for (int r = lane; r < jj; r += LPC) {
+            const double vr = s3[r];
+            for (int k = 0; k <= r; ++k) Ad[r * KCAP + k] -= vr * s3[k];
+          }
+          WAVE_SYNC();
+        }
+        if (!ok) st |= FSMP_ST_FACTOR;
+        for (int r = lane; r < a.kz; r += LPC) {
+          a.zdraw[rec * a.kz + r] = r < N ? zg[r] : -1;
+          a.qdraw[rec * a.kz + r] = r < N ? (ok ? xv[r] + a.sigma_eps * s2[r] : NAN) : 0.0;
+        }
+        WAVE_SYNC();
+      }
     }
   }
 
@@ -675,6 +726,46 @@ __device__ inline void lane_copy(DT *dst, const ST *src, int n) {
     for (int u = 0; u < kChunk; ++u)
       if (i0 + u < n) dst[(i0 + u) * 64] = (DT)v[u];
   }
+}
+
+// Charge draw of one lane's chain (q = x + sigma_eps R xi, H = R R^T, R upper
+// triangular): the same backward factorisation as the lane-group kernels on a copy of
+// H's lower triangle in the interleaved scratch Ap, y = R xi accumulated in S2.  Not
+// inlined: it runs only at recorded steps and stays out of the sweep's registers.
+template <int KCAP, typename HT>
+__device__ __attribute__((noinline)) bool lane_charge_draw(double *Ap, const HT *Hp, const double *Xp, double *S1,
+                                                           double *S2, double *S3, const int32_t *Zp, int N, int step,
+                                                           uint32_t uid0, uint32_t uid1, uint32_t key0, uint32_t key1,
+                                                           double sig, double *q, int32_t *zq, int kz) {
+  for (int r = 0; r < N; ++r) {
+    for (int k = 0; k <= r; ++k) Ap[(r * KCAP + k) * 64] = (double)Hp[(k * KCAP + r) * 64];
+    S1[r * 64] = charge_normal(step, r, uid0, uid1, key0, key1);
+    S2[r * 64] = 0.0;
+  }
+  bool ok = true;
+  for (int jj = N - 1; jj >= 0; --jj) {
+    const double ajj = Ap[(jj * KCAP + jj) * 64];
+    if (!(ajj > 0.0)) {
+      ok = false;
+      break;
+    }
+    const double d = sqrt(ajj), xij = S1[jj * 64];
+    for (int r = 0; r < jj; ++r) {
+      const double v = Ap[(jj * KCAP + r) * 64] / d;
+      S3[r * 64] = v;
+      S2[r * 64] += v * xij;
+    }
+    S2[jj * 64] += d * xij;
+    for (int r = 0; r < jj; ++r) {
+      const double vr = S3[r * 64];
+      for (int k = 0; k <= r; ++k) Ap[(r * KCAP + k) * 64] -= vr * S3[k * 64];
+    }
+  }
+  for (int r = 0; r < kz; ++r) {
+    zq[r] = r < N ? Zp[r * 64] : -1;
+    q[r] = r < N ? (ok ? Xp[r * 64] + sig * S2[r * 64] : NAN) : 0.0;
+  }
+  return ok;
 }
 
 // Workspace of one tile of 64 chains, in doubles: the inverse Gram matrix in its
@@ -1092,6 +1183,13 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
         tr[0] = v0;
         tr[1] = v2;
         tr[2] = v1;
+      }
+      if (a.qdraw && a.thin > 0 && (i % a.thin) == 0) {
+        const int64_t rec = c * a.n_rec + i / a.thin;
+        if (!lane_charge_draw<KCAP, HT>(a.dscr + tile * (int64_t)KCAP * KCAP * 64 + ln, Hp, Xp, S1, S2, S3, Zp, N,
+                                        step, uid0, uid1, a.key0, a.key1, a.sigma_eps, a.qdraw + rec * a.kz,
+                                        a.zdraw + rec * a.kz, a.kz))
+          st |= FSMP_ST_FACTOR;
       }
     }
   }

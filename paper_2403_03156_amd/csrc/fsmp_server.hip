@@ -274,6 +274,10 @@ fsmp_status fsmp_server_create(fsmp_server **out, const fsmp_ser *ser, const fsm
                                const fsmp_config *cfg, int device, const fsmp_server_config *scfg) {
   if (!out) return FSMP_EINVAL;
   *out = nullptr;
+  if (cfg && cfg->record_flags != 0) {
+    g_server_create_error = "the server returns posterior summaries only: record_flags must be 0";
+    return FSMP_EINVAL;
+  }
   if (!scfg || scfg->n_streams < 1 || scfg->n_streams > 16 || scfg->max_batch_wave < 1) {
     g_server_create_error = "server config: need 1..16 streams and max_batch_wave >= 1";
     return FSMP_EINVAL;

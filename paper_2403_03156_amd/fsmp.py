@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libfsmp.so")
 FSMP_OK, FSMP_EINVAL, FSMP_ENOMEM, FSMP_EDEVICE, FSMP_ENOTSUP, FSMP_EBUSY = 0, -1, -2, -3, -4, -5
 FSMP_PHI_EXP, FSMP_PHI_BIEXP = 0, 1
 FSMP_FP64, FSMP_FP32_REFRESH = 0, 1
-FSMP_REC_TRACE, FSMP_REC_LOG = 1, 2
+FSMP_REC_TRACE, FSMP_REC_LOG, FSMP_REC_CHARGE = 1, 2, 4
 FSMP_ST_KMAX, FSMP_ST_NONFINITE, FSMP_ST_DRIFT, FSMP_ST_EMPTY_T, FSMP_ST_FACTOR = 1, 2, 4, 8, 16
 
 EXPORTS = ("fsmp_create", "fsmp_workspace_bytes", "fsmp_sample", "fsmp_posterior", "fsmp_last_timings",
@@ -56,7 +56,8 @@ class fsmp_samples(ctypes.Structure):
     _fields_ = [("n_pe", ctypes.c_void_p), ("t0", ctypes.c_void_p), ("z", ctypes.c_void_p),
                 ("charge", ctypes.c_void_p), ("acc", ctypes.c_void_p), ("nhist", ctypes.c_void_p),
                 ("counts", ctypes.c_void_p), ("status", ctypes.c_void_p), ("log", ctypes.c_void_p),
-                ("trace", ctypes.c_void_p), ("kz", ctypes.c_int32), ("work", ctypes.c_void_p)]
+                ("trace", ctypes.c_void_p), ("kz", ctypes.c_int32), ("work", ctypes.c_void_p),
+                ("qdraw", ctypes.c_void_p), ("zdraw", ctypes.c_void_p)]
 
 
 class fsmp_posterior_out(ctypes.Structure):
@@ -227,9 +228,12 @@ class Sampler:
         }
         if self.cfg.record_flags & FSMP_REC_LOG:
             out["log"] = torch.zeros((C, self.cfg.n_steps * LOGREC_DTYPE.itemsize), dtype=torch.uint8, device=dev)
+        n_rec = (S + self.cfg.thin - 1) // self.cfg.thin if (S > 0 and self.cfg.thin > 0) else 0
         if self.cfg.record_flags & FSMP_REC_TRACE:
-            n_rec = (S + self.cfg.thin - 1) // self.cfg.thin if S > 0 else 0
             out["trace"] = torch.zeros((C, max(n_rec, 1), 3), dtype=torch.float64, device=dev)
+        if self.cfg.record_flags & FSMP_REC_CHARGE:
+            out["qdraw"] = torch.zeros((C, max(n_rec, 1), kz), dtype=torch.float64, device=dev)
+            out["zdraw"] = torch.zeros((C, max(n_rec, 1), kz), dtype=torch.int32, device=dev)
         return out
 
     def _batch(self, wave, offsets, lam, kmax=None, g_range=None, t0_init=None, wave_id=None):
@@ -251,7 +255,8 @@ class Sampler:
     def _samples(out):
         return fsmp_samples(_dptr(out["n_pe"]), _dptr(out["t0"]), _dptr(out["z"]), _dptr(out["charge"]),
                             _dptr(out["acc"]), _dptr(out["nhist"]), _dptr(out["counts"]), _dptr(out["status"]),
-                            _dptr(out["log"]), _dptr(out["trace"]), out["kz"], _dptr(out.get("work")))
+                            _dptr(out["log"]), _dptr(out["trace"]), out["kz"], _dptr(out.get("work")),
+                            _dptr(out.get("qdraw")), _dptr(out.get("zdraw")))
 
     def set_design(self, capacity, design):
         self._check(self.lib.fsmp_set_design(self.h, capacity, design))
@@ -300,9 +305,7 @@ class Sampler:
             out = self.alloc_samples(n, kz, work=work)
         b = fsmp_batch(n, ctypes.c_void_p(wave.data_ptr()), _hptr(offsets), _hptr(lam), _hptr(kmax), _hptr(g_range),
                        _hptr(t0_init), _hptr(wave_id))
-        s = fsmp_samples(_dptr(out["n_pe"]), _dptr(out["t0"]), _dptr(out["z"]), _dptr(out["charge"]),
-                         _dptr(out["acc"]), _dptr(out["nhist"]), _dptr(out["counts"]), _dptr(out["status"]),
-                         _dptr(out["log"]), _dptr(out["trace"]), out["kz"], _dptr(out.get("work")))
+        s = self._samples(out)
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._keep = (offsets, lam, kmax, g_range, t0_init, wave_id)
         self._check(self.lib.fsmp_sample(self.h, ctypes.byref(b), ctypes.byref(s), ctypes.c_void_p(st.cuda_stream)))
@@ -320,10 +323,7 @@ class Sampler:
             "accept": torch.zeros((n_wave, 4), dtype=torch.float64, device=dev),
             "status": torch.zeros(n_wave, dtype=torch.int32, device=dev),
         }
-        s = fsmp_samples(_dptr(samples["n_pe"]), _dptr(samples["t0"]), _dptr(samples["z"]), _dptr(samples["charge"]),
-                         _dptr(samples["acc"]), _dptr(samples["nhist"]), _dptr(samples["counts"]),
-                         _dptr(samples["status"]), _dptr(samples["log"]), _dptr(samples["trace"]), kz,
-                         _dptr(samples.get("work")))
+        s = self._samples(samples)
         po = fsmp_posterior_out(_dptr(res["mean"]), _dptr(res["var"]), _dptr(res["mcse"]), _dptr(res["p_n"]),
                                 _dptr(res["accept"]), _dptr(res["status"]))
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
