@@ -243,19 +243,23 @@ int32_t fsmp_last_timings(const fsmp_ctx *ctx, fsmp_timing *out, int32_t cap);
 fsmp_status fsmp_set_timing(fsmp_ctx *ctx, int32_t enable);
 
 /* ------------------------------------------------------------------ kernel designs
- * Two implementations of the same chains (identical results up to rounding order):
+ * Three implementations of the same chains (identical results up to rounding order):
  * FSMP_DESIGN_GROUP runs one chain per group of lanes with G^{-1} in LDS (PE capacities up
  * to 64); FSMP_DESIGN_LANE runs one chain per lane with G^{-1} interleaved in device
- * memory (every capacity but 48).  Capacities are 16, 32, 48, 64, 96, 128, 160, 192; a
- * waveform runs in the smallest one >= its kmax.  capacity 0 = every capacity that has the
- * design.  FSMP_ENOTSUP if the requested pair does not exist. */
-enum { FSMP_DESIGN_GROUP = 0, FSMP_DESIGN_LANE = 1 };
+ * memory (every capacity but 48); FSMP_DESIGN_GROUP_DEVMEM runs one chain per (narrower)
+ * group of lanes with G^{-1} in device memory, interleaved across the chains of a
+ * wavefront, and only the vectors in LDS (every capacity, while the SER tables leave room
+ * in LDS).  Capacities are 16, 32, 48, 64, 96, 128, 160, 192; a waveform runs in the
+ * smallest one >= its kmax.  capacity 0 = every capacity that has the design.
+ * FSMP_ENOTSUP if the requested pair does not exist.  The FP32-refresh form always runs
+ * the lane design. */
+enum { FSMP_DESIGN_GROUP = 0, FSMP_DESIGN_LANE = 1, FSMP_DESIGN_GROUP_DEVMEM = 2 };
 fsmp_status fsmp_set_design(fsmp_ctx *ctx, int32_t capacity, int32_t design);
 int32_t fsmp_get_design(const fsmp_ctx *ctx, int32_t capacity);
 
-/* Autotuner: runs the whole batch for trial_steps sweeps once with every capacity in the
- * lane-group design and once in the lane design (outputs discarded, HIP-event timings of
- * each capacity's launch), then keeps the faster design per capacity in the context.
+/* Autotuner: runs the whole batch for trial_steps sweeps once per design, each capacity
+ * in that design where it exists (outputs discarded, HIP-event timings of each capacity's
+ * launch), then keeps the fastest design per capacity in the context.
  * Allocates scratch outputs for the trial and synchronises `hip_stream`.  A no-op for the
  * FP32-refresh form, which has the lane design only. */
 fsmp_status fsmp_autotune(fsmp_ctx *ctx, const fsmp_batch *batch, int32_t trial_steps, void *hip_stream);

@@ -155,9 +155,12 @@ struct fsmp_ctx {
   DevBuf<double> lane_d;
   DevBuf<int32_t> lane_i;
   DevBuf<double> draw_scr;  // charge draws: KCAP^2 FP64 words per chain
-  // per PE capacity (kCaps): 1 = one lane per chain (state in device memory),
-  // 0 = one lane group per chain (state in LDS; capacities up to 64)
-  int design[kNumCaps] = {1, 1, 0, 0, 1, 1, 1, 1};
+  // per PE capacity (kCaps), FSMP_DESIGN_*: 0 = lane group per chain, H in LDS
+  // (capacities up to 64); 1 = one lane per chain, state in device memory; 2 = lane group
+  // per chain, H in device memory.  Defaults from the batched 100k-waveform measurement:
+  // one lane per chain wins at capacity 16 (few PEs, the serial work shared by 64 chains),
+  // the device-memory groups everywhere above.
+  int design[kNumCaps] = {1, 2, 2, 2, 2, 2, 2, 2};
   PinBuf stage;
   hipEvent_t stage_done = nullptr;
   bool stage_pending = false;
@@ -184,6 +187,16 @@ fsmp_status fail(fsmp_ctx *c, fsmp_status s, const char *fmt, ...) {
 }
 
 bool finite(double v) { return std::isfinite(v); }
+
+// whether a kernel design exists for a PE capacity under this model (LDS footprint)
+bool design_available(const fsmp_ctx *c, int kcap, int design) {
+  switch (design) {
+    case FSMP_DESIGN_GROUP: return chain_kcap_supported(kcap, c->tab.M, c->cfg.grid_sub);
+    case FSMP_DESIGN_LANE: return kcap != 48;
+    case FSMP_DESIGN_GROUP_DEVMEM: return chain_dm_supported(kcap, c->tab.M, c->cfg.grid_sub);
+    default: return false;
+  }
+}
 
 fsmp_status validate_model(const fsmp_ser *ser, const fsmp_intensity *phi, const fsmp_config *cfg, std::string &m) {
   char b[256];
@@ -306,16 +319,21 @@ fsmp_status fsmp_create(fsmp_ctx **out, const fsmp_ser *ser, const fsmp_intensit
     return fail(nullptr, FSMP_EINVAL, "%s", m.c_str());
   }
   fill_model(c);
+  for (int q = 0; q < kNumCaps; ++q)
+    if (!design_available(c, kCaps[q], c->design[q]))
+      c->design[q] = design_available(c, kCaps[q], FSMP_DESIGN_GROUP_DEVMEM) ? FSMP_DESIGN_GROUP_DEVMEM
+                     : kCaps[q] != 48                                         ? FSMP_DESIGN_LANE
+                                                                              : FSMP_DESIGN_GROUP;
   if (const char *d = std::getenv("FSMP_CHAIN_DESIGN")) {
-    // tuning override: "lane", "group", or three letters l/g for the 16/32/64 capacities
-    // (one letter l / g per capacity in kCaps order; g only where a lane-group instance exists)
+    // tuning override: one letter per capacity in kCaps order, g (lane group, H in LDS),
+    // l (lane), d (lane group, H in device memory); a design that does not exist for a
+    // capacity leaves its default
     const size_t L = std::strlen(d);
-    for (int q = 0; q < kNumCaps; ++q) {
-      const char ch = std::strcmp(d, "lane") == 0 ? 'l' : std::strcmp(d, "group") == 0 ? 'g' : (q < (int)L ? d[q] : 'l');
-      c->design[q] = (ch == 'g' && kCaps[q] <= 64) ? 0 : 1;
+    for (int q = 0; q < kNumCaps && q < (int)L; ++q) {
+      const int want = d[q] == 'g' ? FSMP_DESIGN_GROUP : d[q] == 'l' ? FSMP_DESIGN_LANE
+                       : d[q] == 'd' ? FSMP_DESIGN_GROUP_DEVMEM : -1;
+      if (want >= 0 && design_available(c, kCaps[q], want)) c->design[q] = want;
     }
-    c->design[2] = 0;  // capacity 48 has only the lane-group kernel
-
   }
   int prev = 0;
   (void)hipGetDevice(&prev);
@@ -467,9 +485,8 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     return fail(c, FSMP_ENOTSUP, "kmax above %d is not provided by this build", kCaps[kNumCaps - 1]);
   if (n * (int64_t)cf.n_chains > INT32_MAX) return fail(c, FSMP_EINVAL, "too many chains");
   for (int bi = 0; bi < kNumCaps; ++bi)
-    if (bucket_start[bi + 1] > bucket_start[bi] && !fp32 && c->design[bi] == 0 &&
-        !chain_kcap_supported(caps[bi], c->tab.M, sub))
-      return fail(c, FSMP_ENOTSUP, "SER support %d too long for PE capacity %d", c->tab.LV, caps[bi]);
+    if (bucket_start[bi + 1] > bucket_start[bi] && !fp32 && !design_available(c, caps[bi], c->design[bi]))
+      return fail(c, FSMP_ENOTSUP, "SER support %d too long for the design of PE capacity %d", c->tab.LV, caps[bi]);
   if (n == 0) {
     c->timings.clear();
     c->timing_events.clear();
@@ -495,9 +512,13 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   size_t lane_doff[kNumCaps + 1] = {0}, lane_ioff[kNumCaps + 1] = {0};
   {
     for (int bi = 0; bi < kNumCaps; ++bi) {
-      const int64_t cnt = (fp32 || c->design[bi] == 1) ? bucket_start[bi + 1] - bucket_start[bi] : 0;
-      lane_doff[bi + 1] = lane_doff[bi] + lane_ws_doubles(caps[bi], cnt, fp32);
-      lane_ioff[bi + 1] = lane_ioff[bi] + lane_ws_ints(caps[bi], cnt);
+      const int64_t cnt = bucket_start[bi + 1] - bucket_start[bi];
+      const int dz = fp32 ? FSMP_DESIGN_LANE : c->design[bi];
+      const size_t dd = dz == FSMP_DESIGN_LANE ? lane_ws_doubles(caps[bi], cnt, fp32)
+                        : dz == FSMP_DESIGN_GROUP_DEVMEM ? group_dm_ws_doubles(caps[bi], cnt)
+                                                         : 0;
+      lane_doff[bi + 1] = lane_doff[bi] + dd;
+      lane_ioff[bi + 1] = lane_ioff[bi] + (dz == FSMP_DESIGN_LANE ? lane_ws_ints(caps[bi], cnt) : 0);
     }
     if (e == hipSuccess && lane_doff[kNumCaps] > 0) e = c->lane_d.ensure(lane_doff[kNumCaps]);
     if (e == hipSuccess && lane_ioff[kNumCaps] > 0) e = c->lane_i.ensure(lane_ioff[kNumCaps]);
@@ -643,17 +664,18 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     ca.chains = c->chains.p + bucket_start[bi];
     ca.n_list = cnt;
     char name[32];
-    const int lane = fp32 ? 1 : c->design[bi];
-    std::snprintf(name, sizeof name, "%s%s_k%d", lane ? "chain_lane" : "chain_group", fp32 ? "_fp32" : "", caps[bi]);
-    if (lane) {
-      ca.dws = c->lane_d.p + lane_doff[bi];
-      ca.iws = c->lane_i.p + lane_ioff[bi];
-    }
+    const int dz = fp32 ? FSMP_DESIGN_LANE : c->design[bi];
+    std::snprintf(name, sizeof name, "%s%s_k%d",
+                  dz == FSMP_DESIGN_LANE ? "chain_lane" : dz == FSMP_DESIGN_GROUP ? "chain_group" : "chain_group_dm",
+                  fp32 ? "_fp32" : "", caps[bi]);
+    ca.dws = dz != FSMP_DESIGN_GROUP ? c->lane_d.p + lane_doff[bi] : nullptr;
+    ca.iws = dz == FSMP_DESIGN_LANE ? c->lane_i.p + lane_ioff[bi] : nullptr;
     ca.dscr = ca.qdraw ? c->draw_scr.p + draw_off[bi] : nullptr;
     e = timed(name, caps[bi], [&](fsmp_timing &t) {
       t.chains = cnt;
-      return lane ? launch_chain_lane(caps[bi], fp32, ca, st, &t.lanes, &t.blocks)
-                  : launch_chain(caps[bi], ca, st, &t.lanes, &t.blocks);
+      return dz == FSMP_DESIGN_LANE    ? launch_chain_lane(caps[bi], fp32, ca, st, &t.lanes, &t.blocks)
+             : dz == FSMP_DESIGN_GROUP ? launch_chain(caps[bi], ca, st, &t.lanes, &t.blocks)
+                                       : launch_chain_dm(caps[bi], ca, st, &t.lanes, &t.blocks);
     });
   }
   if (c->capture) {
@@ -669,17 +691,14 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
 
 fsmp_status fsmp_set_design(fsmp_ctx *c, int32_t capacity, int32_t design) {
   if (!c) return FSMP_EINVAL;
-  if (design != FSMP_DESIGN_GROUP && design != FSMP_DESIGN_LANE) return fail(c, FSMP_EINVAL, "unknown design %d", design);
+  if (design != FSMP_DESIGN_GROUP && design != FSMP_DESIGN_LANE && design != FSMP_DESIGN_GROUP_DEVMEM)
+    return fail(c, FSMP_EINVAL, "unknown design %d", design);
   bool any = false;
   for (int q = 0; q < kNumCaps; ++q) {
     if (capacity != 0 && capacity != kCaps[q]) continue;
     any = true;
-    if (design == FSMP_DESIGN_GROUP && !chain_kcap_supported(kCaps[q], c->tab.M, c->cfg.grid_sub)) {
-      if (capacity != 0) return fail(c, FSMP_ENOTSUP, "no lane-group kernel for capacity %d", kCaps[q]);
-      continue;
-    }
-    if (design == FSMP_DESIGN_LANE && kCaps[q] == 48) {
-      if (capacity != 0) return fail(c, FSMP_ENOTSUP, "no lane kernel for capacity 48");
+    if (!design_available(c, kCaps[q], design)) {
+      if (capacity != 0) return fail(c, FSMP_ENOTSUP, "design %d does not exist for capacity %d", design, kCaps[q]);
       continue;
     }
     c->design[q] = design;
@@ -740,14 +759,13 @@ fsmp_status fsmp_autotune(fsmp_ctx *c, const fsmp_batch *b, int32_t trial_steps,
   c->cfg.burn_in = 0;
   c->cfg.record_flags = 0;
   c->timing = true;
-  double ms[2][kNumCaps];
+  constexpr int kDesigns = 3;
+  double ms[kDesigns][kNumCaps];
   fsmp_status st = FSMP_OK;
-  for (int d = 0; d < 2 && st == FSMP_OK; ++d) {
+  for (int d = 0; d < kDesigns && st == FSMP_OK; ++d) {
     for (int q = 0; q < kNumCaps; ++q) {
       ms[d][q] = -1.0;
-      c->design[q] = saved_design[q];
-      if (d == 0 && chain_kcap_supported(kCaps[q], c->tab.M, c->cfg.grid_sub)) c->design[q] = FSMP_DESIGN_GROUP;
-      if (d == 1 && kCaps[q] != 48) c->design[q] = FSMP_DESIGN_LANE;
+      c->design[q] = design_available(c, kCaps[q], d) ? d : saved_design[q];
     }
     st = fsmp_sample(c, b, &o, hip_stream);
     if (st != FSMP_OK) break;
@@ -755,17 +773,19 @@ fsmp_status fsmp_autotune(fsmp_ctx *c, const fsmp_batch *b, int32_t trial_steps,
     const int32_t nt = fsmp_last_timings(c, tv.data(), (int32_t)tv.size());
     for (int32_t k = 0; k < nt; ++k)
       for (int q = 0; q < kNumCaps; ++q)
-        if (tv[k].kcap == kCaps[q]) ms[d][q] = tv[k].ms;
+        if (tv[k].kcap == kCaps[q] && c->design[q] == d) ms[d][q] = tv[k].ms;
   }
   c->cfg = saved;
   c->timing = saved_timing;
   std::memcpy(c->design, saved_design, sizeof saved_design);
-  // a capacity is decided only where both designs exist (16, 32, 64)
+  // per capacity the fastest of the designs that ran it
   if (st == FSMP_OK)
-    for (int q = 0; q < kNumCaps; ++q)
-      if (ms[0][q] >= 0.0 && ms[1][q] >= 0.0 && kCaps[q] != 48 &&
-          chain_kcap_supported(kCaps[q], c->tab.M, c->cfg.grid_sub))
-        c->design[q] = ms[1][q] < ms[0][q] ? FSMP_DESIGN_LANE : FSMP_DESIGN_GROUP;
+    for (int q = 0; q < kNumCaps; ++q) {
+      int best = -1;
+      for (int d = 0; d < kDesigns; ++d)
+        if (ms[d][q] >= 0.0 && (best < 0 || ms[d][q] < ms[best][q])) best = d;
+      if (best >= 0) c->design[q] = best;
+    }
   (void)hipStreamSynchronize((hipStream_t)hip_stream);
   i1.release();
   i2.release();

@@ -111,6 +111,10 @@ size_t lane_ws_ints(int kcap, int64_t n_list);
 constexpr int kNumCaps = 8;
 constexpr int kCaps[kNumCaps] = {16, 32, 48, 64, 96, 128, 160, 192};
 bool chain_kcap_supported(int kcap, int M, int sub);  // lane-group (LDS) instance exists and fits
+// lane groups with H in device memory: dws must hold group_dm_ws_doubles(kcap, n_list)
+hipError_t launch_chain_dm(int kcap, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks);
+size_t group_dm_ws_doubles(int kcap, int64_t n_list);
+bool chain_dm_supported(int kcap, int M, int sub);
 int chain_kcap_for(int kmax);
 
 }  // namespace fsmp

@@ -218,17 +218,67 @@ __global__ void __launch_bounds__(256) prologue_kernel(PrologueArgs a) {
 }
 
 // ------------------------------------------------------------------ chains
-template <int KCAP>
+// LDS block of one chain: H (unless it lives in device memory), b, x, three scratch
+// vectors, the accumulators (kAcc doubles: 12 sums, 3 open batch sums, 4 work counters,
+// then 8 int proposal / accept counts), then int grid indices and the N histogram.  The
+// accumulators live in LDS, updated by the group's first lane, to keep registers free.
+template <int KCAP, bool HG>
 struct ChainLayout {
   static constexpr int LD = KCAP;
-  // H, b, x, three scratch vectors, then int grid indices and the N histogram
-  static constexpr int kDoubles = KCAP * KCAP + 5 * KCAP + (2 * KCAP + 2) / 2;
+  static constexpr int kAcc = 24;
+  static constexpr int kDoubles = (HG ? 0 : KCAP * KCAP) + 5 * KCAP + kAcc + (2 * KCAP + 2) / 2;
 };
 
-template <int KCAP, int LPC, int WPB>
+// Column i of H owned by one lane: element (k, i) at H[(k * LD + i) * HS] (HS = 1 in LDS;
+// the number of chains of a wavefront in device memory, where the wavefront's chains are
+// interleaved element by element).  Loads go in chunks of 8 rows, issued unconditionally
+// (rows below the capacity, a multiple of 8) with the rows past N dropped by a select,
+// so a chunk costs one memory round trip; terms are summed in row order.
+template <int LD, int HS>
+__device__ inline double grp_col_dot(const double *H, const double *g, int i, int N) {
+  double e = 0.0;
+  for (int k0 = 0; k0 < N; k0 += 8) {
+    double h[8], v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      h[u] = H[((k0 + u) * LD + i) * HS];
+      v[u] = g[k0 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) e = (k0 + u < N) ? e + h[u] * v[u] : e;
+  }
+  return e;
+}
+
+// H(k, i) += ai A_k cA [+ bi B_k cB] for k < N (loads of a chunk unconditional, stores guarded)
+template <int LD, int HS, bool TWO>
+__device__ inline void grp_col_update(double *H, int i, int N, double ai, const double *A, double cA, double bi,
+                                      const double *B, double cB) {
+  for (int k0 = 0; k0 < N; k0 += 8) {
+    double h[8], av[8], bw[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      h[u] = H[((k0 + u) * LD + i) * HS];
+      av[u] = A[k0 + u];
+      if (TWO) bw[u] = B[k0 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double v = TWO ? h[u] + (ai * av[u] * cA + bi * bw[u] * cB) : h[u] + ai * av[u] * cA;
+      if (k0 + u < N) H[((k0 + u) * LD + i) * HS] = v;
+    }
+  }
+}
+
+// HG: H in device memory (a.dws, the chains of a wavefront interleaved element by element),
+// which leaves the LDS to the tables and the vectors and so fits many more chains per CU;
+// otherwise H in LDS.
+template <int KCAP, int LPC, int WPB, bool HG>
 __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
   constexpr int CPW = kWave / LPC;
-  constexpr int LD = ChainLayout<KCAP>::LD;
+  using CL = ChainLayout<KCAP, HG>;
+  constexpr int LD = CL::LD;
+  constexpr int HS = HG ? CPW : 1;
   extern __shared__ double smem[];
   const ModelDev &md = a.md;
   double *vt = smem;
@@ -239,16 +289,20 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
 
   const int wv = threadIdx.x / kWave, l64 = threadIdx.x % kWave;
   const int grp = l64 / LPC, lane = l64 % LPC;
-  const int64_t slot = ((int64_t)blockIdx.x * WPB + wv) * CPW + grp;
+  const int64_t tile = (int64_t)blockIdx.x * WPB + wv;
+  const int64_t slot = tile * CPW + grp;
   if (slot >= a.n_list) return;
 
-  double *H = smem + md.M * (1 + md.sub) + (int64_t)(wv * CPW + grp) * ChainLayout<KCAP>::kDoubles;
-  double *bv = H + KCAP * LD;
+  double *cb = smem + md.M * (1 + md.sub) + (int64_t)(wv * CPW + grp) * CL::kDoubles;
+  double *H = HG ? a.dws + tile * (int64_t)(KCAP * LD * CPW) + grp : cb;
+  double *bv = HG ? cb : cb + KCAP * LD;
   double *xv = bv + KCAP;
   double *s1 = xv + KCAP;
   double *s2 = s1 + KCAP;
   double *s3 = s2 + KCAP;
-  int *zg = (int *)(s3 + KCAP);
+  double *acc = s3 + KCAP;  // [0..11] sums, [12..14] open batch sums, [15..18] work counters
+  int *cnt = (int *)(acc + 20);
+  int *zg = (int *)(acc + CL::kAcc);
   int *hist = zg + KCAP;
 
   const int64_t c = a.chains[slot];
@@ -271,14 +325,11 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
   double t0 = a.t0init[w];
   int N = 0;
   double Phi = (glo <= ghi) ? phi_total(md, t0, glo, ghi) : 0.0;
-  double acc[12];
-#pragma unroll
-  for (int i = 0; i < 12; ++i) acc[i] = 0.0;
-  double bs0 = 0.0, bs1 = 0.0, bs2 = 0.0;
-  int cnt[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) cnt[i] = 0;
-  double wk0 = 0.0, wk1 = 0.0, wk2 = 0.0, wk3 = 0.0;
+  if (lane == 0) {
+    for (int i = 0; i < 20; ++i) acc[i] = 0.0;
+    for (int i = 0; i < 8; ++i) cnt[i] = 0;
+  }
+  WAVE_SYNC();
 
   for (int step = 0; step < n_steps; ++step) {
     uint32_t r[8];
@@ -291,9 +342,9 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
     // ---- Gibbs half-step 1: t0 by Metropolis-Hastings
     const double t0p = t0 + md.t0_sd * xi_t0;
     bool t0acc = false;
-    cnt[0]++;
+    if (lane == 0) cnt[0]++;
     if (t0p >= md.t0_min && t0p <= md.t0_max) {
-      wk3 += N;
+      if (lane == 0) acc[18] += N;
       double part = 0.0;
       int bad = 0;
       for (int i = lane; i < N; i += LPC) {
@@ -311,7 +362,7 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
           t0 = t0p;
           Phi = Phip;
           t0acc = true;
-          cnt[1]++;
+          if (lane == 0) cnt[1]++;
         }
       }
     }
@@ -325,7 +376,7 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
     double dnu = 0.0, la = -INFINITY;
     double delta2 = 1.0, up = 0.0, om = 1.0, xj = 0.0, ej = 0.0, beta = 0.0;
     if (move == 1) {
-      cnt[2]++;
+      if (lane == 0) cnt[2]++;
       if (N >= kmax) {
         st |= FSMP_ST_KMAX;
       } else if (Phi > 0.0) {
@@ -335,11 +386,10 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
           const double d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
           beta = mf[gnew - glo] + md.rhom;
           WAVE_SYNC();
-          wk0 += (double)N * N;
+          if (lane == 0) acc[15] += (double)N * N;
           double q = 0.0, p = 0.0;
           for (int i = lane; i < N; i += LPC) {
-            double e = 0.0;
-            for (int k = 0; k < N; ++k) e += H[k * LD + i] * s1[k];
+            const double e = grp_col_dot<LD, HS>(H, s1, i, N);
             s2[i] = e;
             q += s1[i] * e;
             p += s1[i] * xv[i];
@@ -360,8 +410,8 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
     } else {
       j = (int)(((uint64_t)r[4] * (uint64_t)N) >> 32);
       if (move == 2) {
-        cnt[4]++;
-        om = H[j * LD + j];
+        if (lane == 0) cnt[4]++;
+        om = H[(j * LD + j) * HS];
         xj = xv[j];
         if (om > 0.0) {
           dnu = 0.5 * (-md.log_rho - log(om) + (md.rhom2 - xj * xj / om) * md.inv_s);
@@ -371,7 +421,7 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
           st |= FSMP_ST_FACTOR;
         }
       } else {
-        cnt[6]++;
+        if (lane == 0) cnt[6]++;
         sh = (int)rint(xi_sh * md.shift_sd / md.dt);
         gnew = zg[j] + sh;
         if (gnew >= glo && gnew <= ghi) {
@@ -387,11 +437,10 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
               const double d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
               beta = mf[gnew - glo] + md.rhom;
               WAVE_SYNC();
-              wk0 += (double)N * N;
+              if (lane == 0) acc[15] += (double)N * N;
               double q = 0.0, p = 0.0;
               for (int i = lane; i < N; i += LPC) {
-                double e = 0.0;
-                for (int k = 0; k < N; ++k) e += H[k * LD + i] * s1[k];
+                const double e = grp_col_dot<LD, HS>(H, s1, i, N);
                 s2[i] = e;
                 q += s1[i] * e;
                 p += s1[i] * xv[i];
@@ -399,7 +448,7 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
               q = group_sum<LPC>(q);
               p = group_sum<LPC>(p);
               WAVE_SYNC();
-              om = H[j * LD + j];
+              om = H[(j * LD + j) * HS];
               xj = xv[j];
               ej = s2[j];
               delta2 = d - (q - ej * ej / om);
@@ -420,22 +469,24 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
     bool accepted = false;
     if (valid && log(u01(r[6])) < la) {
       accepted = true;
-      cnt[2 * move + 1]++;
+      if (lane == 0) cnt[2 * move + 1]++;
       WAVE_SYNC();
-      if (move == 1 || move == 2) wk1 += (double)N * N;
-      else if (sh != 0) wk2 += (double)N * N;
+      if (lane == 0) {
+        if (move == 1 || move == 2) acc[16] += (double)N * N;
+        else if (sh != 0) acc[17] += (double)N * N;
+      }
       if (move == 1) {
         const double inv_d2 = 1.0 / delta2;
         const double xn = up * inv_d2;
         for (int i = lane; i < N; i += LPC) {
           const double ei = s2[i];
           xv[i] -= ei * xn;
-          for (int k = 0; k < N; ++k) H[k * LD + i] += ei * s2[k] * inv_d2;
-          H[N * LD + i] = -ei * inv_d2;
-          H[i * LD + N] = -ei * inv_d2;
+          grp_col_update<LD, HS, false>(H, i, N, ei, s2, inv_d2, 0.0, nullptr, 0.0);
+          H[(N * LD + i) * HS] = -ei * inv_d2;
+          H[(i * LD + N) * HS] = -ei * inv_d2;
         }
         if (lane == 0) {
-          H[N * LD + N] = inv_d2;
+          H[(N * LD + N) * HS] = inv_d2;
           zg[N] = gnew;
           bv[N] = beta;
           xv[N] = xn;
@@ -444,25 +495,25 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
         WAVE_SYNC();
       } else if (move == 2) {
         const double inv_om = 1.0 / om;
-        for (int i = lane; i < N; i += LPC) s3[i] = H[j * LD + i];
+        for (int i = lane; i < N; i += LPC) s3[i] = H[(j * LD + i) * HS];
         WAVE_SYNC();
         for (int i = lane; i < N; i += LPC) {
           const double hi = s3[i];
           xv[i] -= hi * xj * inv_om;
-          for (int k = 0; k < N; ++k) H[k * LD + i] -= hi * s3[k] * inv_om;
+          grp_col_update<LD, HS, false>(H, i, N, hi, s3, -inv_om, 0.0, nullptr, 0.0);
         }
         WAVE_SYNC();
         const int last = N - 1;
         if (j != last) {
-          for (int i = lane; i < N; i += LPC) s3[i] = H[last * LD + i];
+          for (int i = lane; i < N; i += LPC) s3[i] = H[(last * LD + i) * HS];
           WAVE_SYNC();
           const double vd = s3[last];
           for (int i = lane; i < N; i += LPC) {
             if (i == j) {
-              H[j * LD + j] = vd;
+              H[(j * LD + j) * HS] = vd;
             } else {
-              H[j * LD + i] = s3[i];
-              H[i * LD + j] = s3[i];
+              H[(j * LD + i) * HS] = s3[i];
+              H[(i * LD + j) * HS] = s3[i];
             }
           }
           if (lane == 0) {
@@ -476,23 +527,23 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
       } else if (sh != 0) {
         const double inv_om = 1.0 / om, inv_d2 = 1.0 / delta2;
         const double xn = up * inv_d2;
-        for (int i = lane; i < N; i += LPC) s3[i] = H[j * LD + i];
+        for (int i = lane; i < N; i += LPC) s3[i] = H[(j * LD + i) * HS];
         WAVE_SYNC();
         for (int i = lane; i < N; i += LPC) s2[i] = (i == j) ? 0.0 : s2[i] - s3[i] * ej * inv_om;
         WAVE_SYNC();
         for (int i = lane; i < N; i += LPC) {
           const double hi = s3[i], ei = s2[i];
           xv[i] = (i == j) ? xn : xv[i] - hi * xj * inv_om - ei * xn;
-          for (int k = 0; k < N; ++k) H[k * LD + i] += -hi * s3[k] * inv_om + ei * s2[k] * inv_d2;
+          grp_col_update<LD, HS, true>(H, i, N, -hi, s3, inv_om, ei, s2, inv_d2);
         }
         WAVE_SYNC();
         for (int i = lane; i < N; i += LPC) {
           if (i == j) {
-            H[j * LD + j] = inv_d2;
+            H[(j * LD + j) * HS] = inv_d2;
           } else {
             const double v = -s2[i] * inv_d2;
-            H[j * LD + i] = v;
-            H[i * LD + j] = v;
+            H[(j * LD + i) * HS] = v;
+            H[(i * LD + j) * HS] = v;
           }
         }
         if (lane == 0) {
@@ -520,28 +571,30 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
       for (int i = lane; i < N; i += LPC) Q += xv[i];
       Q = group_sum<LPC>(Q);
       const double v0 = (double)N, v1 = Q, v2 = t0;
-      acc[0] += v0;
-      acc[1] += v0 * v0;
-      acc[2] += v1;
-      acc[3] += v1 * v1;
-      acc[4] += v2;
-      acc[5] += v2 * v2;
       const int64_t i = step - a.burn_in;
-      if (a.nb > 0 && i < (int64_t)a.nb * a.lb) {
-        bs0 += v0;
-        bs1 += v1;
-        bs2 += v2;
-        if ((i + 1) % a.lb == 0) {
-          acc[6] += bs0;
-          acc[7] += bs0 * bs0;
-          acc[8] += bs1;
-          acc[9] += bs1 * bs1;
-          acc[10] += bs2;
-          acc[11] += bs2 * bs2;
-          bs0 = bs1 = bs2 = 0.0;
+      if (lane == 0) {
+        acc[0] += v0;
+        acc[1] += v0 * v0;
+        acc[2] += v1;
+        acc[3] += v1 * v1;
+        acc[4] += v2;
+        acc[5] += v2 * v2;
+        if (a.nb > 0 && i < (int64_t)a.nb * a.lb) {
+          acc[12] += v0;
+          acc[13] += v1;
+          acc[14] += v2;
+          if ((i + 1) % a.lb == 0) {
+            acc[6] += acc[12];
+            acc[7] += acc[12] * acc[12];
+            acc[8] += acc[13];
+            acc[9] += acc[13] * acc[13];
+            acc[10] += acc[14];
+            acc[11] += acc[14] * acc[14];
+            acc[12] = acc[13] = acc[14] = 0.0;
+          }
         }
+        hist[N] += 1;
       }
-      if (lane == 0) hist[N] += 1;
       if (a.trace && a.thin > 0 && (i % a.thin) == 0 && lane == 0) {
         double *tr = a.trace + (c * a.n_rec + i / a.thin) * 3;
         tr[0] = v0;
@@ -556,7 +609,7 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
         double *Ad = a.dscr + slot * (int64_t)(KCAP * KCAP);
         WAVE_SYNC();
         for (int r = lane; r < N; r += LPC) {
-          for (int k = 0; k <= r; ++k) Ad[r * KCAP + k] = H[k * LD + r];
+          for (int k = 0; k <= r; ++k) Ad[r * KCAP + k] = H[(k * LD + r) * HS];
           s1[r] = charge_normal(step, r, uid0, uid1, a.key0, a.key1);
           s2[r] = 0.0;
         }
@@ -606,10 +659,7 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
     for (int i = 0; i < 8; ++i) a.counts[c * 8 + i] = cnt[i];
     a.status[c] = st;
     if (a.work) {
-      a.work[c * 4 + 0] = wk0;
-      a.work[c * 4 + 1] = wk1;
-      a.work[c * 4 + 2] = wk2;
-      a.work[c * 4 + 3] = wk3;
+      for (int i = 0; i < 4; ++i) a.work[c * 4 + i] = acc[15 + i];
     }
   }
 }
@@ -1277,21 +1327,22 @@ __global__ void __launch_bounds__(256) posterior_kernel(PosteriorArgs a) {
   a.status[w] = st;
 }
 
-template <int KCAP, int LPC, int WPB>
+template <int KCAP, int LPC, int WPB, bool HG>
 hipError_t launch_chain_t(const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
   constexpr int CPB = WPB * (kWave / LPC);
   const int64_t nb = (a.n_list + CPB - 1) / CPB;
-  const size_t lds = sizeof(double) * ((size_t)a.md.M * (1 + a.md.sub) + (size_t)CPB * ChainLayout<KCAP>::kDoubles);
+  const size_t lds = sizeof(double) * ((size_t)a.md.M * (1 + a.md.sub) + (size_t)CPB * ChainLayout<KCAP, HG>::kDoubles);
   *lanes = LPC;
   *blocks = nb;
   if (nb == 0) return hipSuccess;
+  if (HG && a.dws == nullptr) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
     // lift the default dynamic-LDS limit; gfx950 has 160 KB per workgroup
-    (void)hipFuncSetAttribute((const void *)chain_kernel<KCAP, LPC, WPB>,
+    (void)hipFuncSetAttribute((const void *)chain_kernel<KCAP, LPC, WPB, HG>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipGetLastError();
   }
-  hipLaunchKernelGGL((chain_kernel<KCAP, LPC, WPB>), dim3((unsigned)nb), dim3(kWave * WPB), lds, st, a);
+  hipLaunchKernelGGL((chain_kernel<KCAP, LPC, WPB, HG>), dim3((unsigned)nb), dim3(kWave * WPB), lds, st, a);
   return hipGetLastError();
 }
 
@@ -1329,22 +1380,42 @@ int chain_kcap_for(int kmax) {
   return 0;
 }
 
-// lane-group instances: PE capacity, lanes per chain, wavefronts per workgroup
+// lane-group instances: PE capacity, lanes per chain, wavefronts per workgroup.  With H
+// in LDS the LDS bounds the chains per CU (one chain per wavefront at capacity 64); with H
+// in device memory each chain keeps only its vectors in LDS, so groups are narrower and a
+// CU holds 8-16x more chains.
 struct GroupCfg {
   int kcap, lpc, wpb;
 };
 static const GroupCfg kGroup[] = {{16, 16, 4}, {32, 32, 4}, {48, 64, 3}, {64, 64, 4}};
+static const GroupCfg kGroupDM[] = {{16, 4, 4},    {32, 8, 4},    {48, 16, 4},   {64, 16, 4},
+                                    {96, 16, 2},   {128, 32, 4},  {160, 32, 4},  {192, 32, 2}};
 
-static size_t chain_lds_bytes(const GroupCfg &g, int M, int sub) {
+static size_t chain_lds_bytes(const GroupCfg &g, int M, int sub, bool hg) {
   const int cpb = g.wpb * (64 / g.lpc);
-  const size_t per = (size_t)g.kcap * g.kcap + 5 * (size_t)g.kcap + (2 * (size_t)g.kcap + 2) / 2;
+  const size_t per = (hg ? 0 : (size_t)g.kcap * g.kcap) + 5 * (size_t)g.kcap + 24 + (2 * (size_t)g.kcap + 2) / 2;
   return sizeof(double) * ((size_t)M * (1 + sub) + (size_t)cpb * per);
 }
 
 bool chain_kcap_supported(int kcap, int M, int sub) {
   for (const GroupCfg &g : kGroup)
-    if (g.kcap == kcap) return chain_lds_bytes(g, M, sub) <= 160 * 1024;
+    if (g.kcap == kcap) return chain_lds_bytes(g, M, sub, false) <= 160 * 1024;
   return false;
+}
+
+bool chain_dm_supported(int kcap, int M, int sub) {
+  for (const GroupCfg &g : kGroupDM)
+    if (g.kcap == kcap) return chain_lds_bytes(g, M, sub, true) <= 160 * 1024;
+  return false;
+}
+
+size_t group_dm_ws_doubles(int kcap, int64_t n_list) {
+  for (const GroupCfg &g : kGroupDM)
+    if (g.kcap == kcap) {
+      const int64_t cpw = 64 / g.lpc;
+      return (size_t)((n_list + cpw - 1) / cpw) * cpw * kcap * kcap;
+    }
+  return 0;
 }
 
 size_t lane_ws_doubles(int kcap, int64_t n_list, bool fp32) {
@@ -1389,10 +1460,25 @@ hipError_t launch_chain_lane(int kcap, bool fp32, const ChainArgs &a, hipStream_
 
 hipError_t launch_chain(int kcap, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
   switch (kcap) {
-    case 16: return launch_chain_t<16, 16, 4>(a, st, lanes, blocks);
-    case 32: return launch_chain_t<32, 32, 4>(a, st, lanes, blocks);
-    case 48: return launch_chain_t<48, 64, 3>(a, st, lanes, blocks);
-    case 64: return launch_chain_t<64, 64, 4>(a, st, lanes, blocks);
+    case 16: return launch_chain_t<16, 16, 4, false>(a, st, lanes, blocks);
+    case 32: return launch_chain_t<32, 32, 4, false>(a, st, lanes, blocks);
+    case 48: return launch_chain_t<48, 64, 3, false>(a, st, lanes, blocks);
+    case 64: return launch_chain_t<64, 64, 4, false>(a, st, lanes, blocks);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// instances must match kGroupDM
+hipError_t launch_chain_dm(int kcap, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
+  switch (kcap) {
+    case 16: return launch_chain_t<16, 4, 4, true>(a, st, lanes, blocks);
+    case 32: return launch_chain_t<32, 8, 4, true>(a, st, lanes, blocks);
+    case 48: return launch_chain_t<48, 16, 4, true>(a, st, lanes, blocks);
+    case 64: return launch_chain_t<64, 16, 4, true>(a, st, lanes, blocks);
+    case 96: return launch_chain_t<96, 16, 2, true>(a, st, lanes, blocks);
+    case 128: return launch_chain_t<128, 32, 4, true>(a, st, lanes, blocks);
+    case 160: return launch_chain_t<160, 32, 4, true>(a, st, lanes, blocks);
+    case 192: return launch_chain_t<192, 32, 2, true>(a, st, lanes, blocks);
     default: return hipErrorInvalidValue;
   }
 }

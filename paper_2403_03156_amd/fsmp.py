@@ -24,7 +24,7 @@ EXPORTS = ("fsmp_create", "fsmp_workspace_bytes", "fsmp_sample", "fsmp_posterior
            "fsmp_server_submit", "fsmp_server_progress", "fsmp_server_result", "fsmp_server_stats",
            "fsmp_server_last_error", "fsmp_server_destroy", "fsmp_set_design", "fsmp_get_design", "fsmp_autotune",
            "fsmp_graph_create", "fsmp_graph_launch", "fsmp_graph_destroy")
-FSMP_DESIGN_GROUP, FSMP_DESIGN_LANE = 0, 1
+FSMP_DESIGN_GROUP, FSMP_DESIGN_LANE, FSMP_DESIGN_GROUP_DEVMEM = 0, 1, 2
 
 
 class fsmp_ser(ctypes.Structure):
@@ -92,6 +92,9 @@ def load(path: Optional[str] = None):
     if _lib is not None:
         return _lib
     p = path or LIB_PATH
+    # torch first: the library then binds to the HIP runtime torch has loaded, so device
+    # pointers and streams from torch tensors are valid in it
+    import torch  # noqa: F401
     if not os.path.exists(p):
         raise FileNotFoundError(f"{p} is not built; run python -m paper_2403_03156_amd.build")
     L = ctypes.CDLL(p)

@@ -57,12 +57,14 @@ def _gpu_and_oracle(wl, b, km, n_steps, burn, n_chains, seed, design=None, g_ran
     return smp, out, g, o
 
 
+# FSMP_CHAIN_DESIGN: one letter per PE capacity (16, 32, 48, 64, 96, 128, 160, 192):
+# g lane group with H in LDS, l one lane per chain, d lane group with H in device memory
 @pytest.mark.parametrize("design", [
-    pytest.param("lane", marks=pytest.mark.skip(
+    pytest.param("llllllll", marks=pytest.mark.skip(
         reason="forcing one lane per chain at every capacity faulted the GPU (capacity 48, cause not found; "
                "a bounds-checked CPU build of the kernel is clean on this case); the capacity-48 lane "
                "instance is removed and this case stays off the GPU")),
-    "group"])
+    "gggggggg", "dddddddd"])
 def test_designs_agree_with_oracle(design):
     wl = synth.PRESETS["batched"]
     b = synth.generate(wl, n_wave=40, seed=11)
@@ -72,13 +74,14 @@ def test_designs_agree_with_oracle(design):
     assert len(parted) == 0, parted
 
 
-def test_large_capacities_pileup():
+@pytest.mark.parametrize("design", [None, "dddddddd"])
+def test_large_capacities_pileup(design):
     wl = synth.PRESETS["pileup"]
     lam = np.array([20.0, 28.0, 48.0, 60.0, 75.0, 90.0, 100.0, 100.0])
     b = synth.generate(wl, n_wave=len(lam), seed=3, lam=lam)
     km = synth.kmax_for(b["lam"])
     assert set(km.tolist()) >= {48, 64, 96, 128, 160}
-    _, _, g, o = _gpu_and_oracle(wl, b, km, 250, 100, 1, 6)
+    _, _, g, o = _gpu_and_oracle(wl, b, km, 250, 100, 1, 6, design=design)
     parted = compare_chains(g, o)
     assert len(parted) == 0, parted
     assert (g["n_pe"] > 10).all()

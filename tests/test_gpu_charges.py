@@ -54,7 +54,7 @@ def _check_identical_chains(g, o, rtol, atol):
     return keep
 
 
-@pytest.mark.parametrize("design", [fsmp.FSMP_DESIGN_GROUP, fsmp.FSMP_DESIGN_LANE])
+@pytest.mark.parametrize("design", [fsmp.FSMP_DESIGN_GROUP, fsmp.FSMP_DESIGN_LANE, fsmp.FSMP_DESIGN_GROUP_DEVMEM])
 def test_charge_draws_match_oracle(design):
     wl = synth.PRESETS["batched"]
     b = synth.generate(wl, n_wave=48, seed=61)
@@ -69,8 +69,9 @@ def test_charge_draws_high_capacity():
                         tau_rise=base.tau_rise, tau_decay=base.tau_decay, sigma_q=0.35, sigma_eps=0.1)
     b = synth.generate(wl, n_wave=6, seed=5)
     km = synth.kmax_for(b["lam"])
-    g, o = _run(wl, b, km, 160, 80, 20, 3)
-    _check_identical_chains(g, o, rtol=1e-7, atol=1e-8)
+    for design in (None, fsmp.FSMP_DESIGN_GROUP_DEVMEM):
+        g, o = _run(wl, b, km, 160, 80, 20, 3, design=design)
+        _check_identical_chains(g, o, rtol=1e-7, atol=1e-8)
 
 
 def test_charge_draws_fp32_refresh():

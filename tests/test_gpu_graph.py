@@ -73,6 +73,10 @@ def test_set_design_validation():
         smp.set_design(20, fsmp.FSMP_DESIGN_LANE)
     smp.set_design(0, fsmp.FSMP_DESIGN_GROUP)  # every capacity that has the design
     assert [smp.get_design(c) for c in synth.KCAPS] == [0, 0, 0, 0, 1, 1, 1, 1]
+    smp.set_design(0, fsmp.FSMP_DESIGN_GROUP_DEVMEM)
+    assert [smp.get_design(c) for c in synth.KCAPS] == [2] * 8
+    with pytest.raises(RuntimeError):
+        smp.set_design(16, 3)
 
 
 def test_autotune_keeps_results_correct():
@@ -80,10 +84,11 @@ def test_autotune_keeps_results_correct():
     kz = int(km.max())
     smp = gpu_sampler(wl, 120, 60, 1, 13)
     wave = torch.from_numpy(b["wave"]).cuda()
+    before = {c: smp.get_design(c) for c in synth.KCAPS}
     designs = smp.autotune(wave, b["offsets"], b["lam"], kmax=km, trial_steps=40)
-    print(f"[autotune] {designs}", flush=True)
-    assert designs[48] == fsmp.FSMP_DESIGN_GROUP
-    assert all(designs[c] == fsmp.FSMP_DESIGN_LANE for c in (96, 128, 160, 192))
+    print(f"[autotune] {before} -> {designs}", flush=True)
+    assert designs[48] in (fsmp.FSMP_DESIGN_GROUP, fsmp.FSMP_DESIGN_GROUP_DEVMEM)   # no lane instance at 48
+    assert all(designs[c] == before[c] for c in (96, 128, 160, 192))                # not in the batch: untouched
     # a sub-batch in the tuned designs against the oracle
     n = 60
     off = b["offsets"][:n + 1]
