@@ -11,7 +11,23 @@ of the dominant kernel (measured with HIP events on its stream inside the timed
 region) and the oracle timed on the host cores over a bounded sample.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload batched]
+
+Roofline of a chain kernel whose state lives in device memory (one lane per chain, or
+lane groups with G^-1 in device memory): algorithmic bytes = the G^-1 elements the
+sweeps must touch, 8 bytes (4 in the FP32 form) per element read by a K x K mat-vec and
+per element read and written by a rank-one or rank-two edit, summed from the device work
+counters of the launch's chains, over the launch's mean duration, against 8 TB/s.  The
+dominant kernel is the chain launch with the most such bytes.  Lane-group kernels with
+G^-1 in LDS are reported against the FP64 vector peak with the same work counted as
+flops.  `traffic` is the HBM bytes per launch that rocprofv3 counters recorded for that
+kernel (FETCH_SIZE + WRITE_SIZE, scaled by the factor a plain copy of known size gives),
+read from profiles/traffic_<workload>.json while the kernel source is unchanged:
+
+    rocprofv3 --pmc FETCH_SIZE -d DIR_F -o pmc -- python bench.py --pmc-run
+    rocprofv3 --pmc WRITE_SIZE -d DIR_W -o pmc -- python bench.py --pmc-run
+    python bench.py --pmc-summary DIR_F DIR_W
 """
+import hashlib
 import argparse
 import json
 import os
@@ -25,6 +41,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12  # MI355X dense FP64 vector, FLOP/s
+PEAK_HBM = 8.0e12    # MI355X HBM3E, bytes/s
+KSRC = os.path.join(ROOT, "paper_2403_03156_amd", "csrc", "fsmp_kernels.hip")
+COPY_PROBE_MIB = 1024
 
 
 def parse():
@@ -41,7 +60,87 @@ def parse():
     ap.add_argument("--serve-events", type=int, default=40, help="events per serving run")
     ap.add_argument("--serve-rates", default="2000", help="comma-separated event rates (Hz)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="one untimed step after a plain device copy of known size (for rocprofv3 --pmc)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs into profiles/")
     return ap.parse_args()
+
+
+def kernel_label(name):
+    """bench name of a chain / prologue kernel from its demangled rocprofv3 name"""
+    import re
+    m = re.search(r"chain_kernel<(\d+), (\d+), (\d+), (true|false)>", name)
+    if m:
+        return ("chain_group_dm_k" if m.group(4) == "true" else "chain_group_k") + m.group(1)
+    m = re.search(r"chain_lane_kernel<(\d+), (double|float)>", name)
+    if m:
+        return ("chain_lane_k" if m.group(2) == "double" else "chain_lane_fp32_k") + m.group(1)
+    for k in ("prologue_kernel", "posterior_kernel"):
+        if k in name:
+            return k.replace("_kernel", "")
+    return None
+
+
+def source_hash():
+    return hashlib.sha256(open(KSRC, "rb").read()).hexdigest()
+
+
+def pmc_summary(fdir, wdir, workload):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of two rocprofv3 --pmc runs -> HBM bytes per
+    launch of each kernel, scaled by what the counters read for the plain copy of known size."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        rows = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r.get("Counter_Name") != counter:
+                    continue
+                key = (r.get("Dispatch_Id"), r.get("Kernel_Name"))
+                rows[key] = rows.get(key, 0.0) + float(r["Counter_Value"])
+        return rows
+
+    fetch, write = read(fdir, "FETCH_SIZE"), read(wdir, "WRITE_SIZE")
+    copy_bytes = COPY_PROBE_MIB * 2 ** 20
+
+    def by_kernel(rows):
+        out = {}
+        for (_, name), kib in rows.items():
+            lab = kernel_label(name)
+            if lab is None and ("copy" in name.lower() or "elementwise" in name.lower()):
+                lab = "copy"
+            if lab:
+                out.setdefault(lab, []).append(kib * 1024.0)
+        return out
+
+    fk, wk = by_kernel(fetch), by_kernel(write)
+    # the copy probe is the largest copy-like dispatch: it reads and writes copy_bytes
+    f_scale = copy_bytes / max(fk.get("copy", [copy_bytes]))
+    w_scale = copy_bytes / max(wk.get("copy", [copy_bytes]))
+    kern = {}
+    for lab in sorted(set(fk) | set(wk)):
+        if lab == "copy":
+            continue
+        f = float(np.mean(fk.get(lab, [0.0]))) * f_scale
+        w = float(np.mean(wk.get(lab, [0.0]))) * w_scale
+        kern[lab] = {"fetch_bytes": f, "write_bytes": w, "hbm_bytes": f + w}
+    res = {"workload": workload, "source_sha256": source_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
+           "copy_probe_bytes": copy_bytes, "kernels": kern}
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    json.dump(res, open(path, "w"), indent=1)
+    print(json.dumps(res, indent=1))
+
+
+def recorded_traffic(workload, kernel):
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("source_sha256") != source_hash() or kernel not in t.get("kernels", {}):
+        return None
+    return t["kernels"][kernel]["hbm_bytes"]
 
 
 def serving_run(fsmp, synth, pool, rate, n_events, precision, seed=0, n_streams=4, max_batch_wave=20000):
@@ -105,6 +204,12 @@ def algorithmic_flops(work):
     return 2.0 * work[:, 0].sum() + 2.0 * work[:, 1].sum() + 4.0 * work[:, 2].sum()
 
 
+def algorithmic_bytes(work, word):
+    """device-memory bytes of G^-1 the sweeps must move: K^2 elements read per mat-vec,
+    K^2 read and K^2 written per rank-one or rank-two edit"""
+    return word * (work[:, 0].sum() + 2.0 * work[:, 1].sum() + 2.0 * work[:, 2].sum())
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -115,6 +220,10 @@ def main():
 
     import oracle
     from paper_2403_03156_amd import fsmp, synth
+
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.workload)
+        return
 
     if args.serve:
         pool = serving_pool(synth)
@@ -147,6 +256,19 @@ def main():
         smp.sample(wave, b["offsets"], b["lam"], kmax=km, kz=kz, out=out, stream=stream)
         return smp.posterior(n_wave, out, with_pn=False, stream=stream)
 
+    if args.pmc_run:
+        # counter run: a plain copy of known size (the scale for FETCH_SIZE / WRITE_SIZE), then
+        # one step; nothing is timed
+        x = torch.empty(COPY_PROBE_MIB * 2 ** 20 // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+        one_step()
+        torch.cuda.synchronize()
+        print("[bench] counter run done", file=sys.stderr, flush=True)
+        return
+
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
@@ -168,21 +290,28 @@ def main():
     wps = n_wave / (ms_per_step / 1e3)
     sps = chain_steps / (ms_per_step / 1e3)
 
-    # ---- dominant kernel roofline (algorithmic FP64 flops of its chains / its mean duration)
+    # ---- dominant kernel roofline: the chain launch with the most algorithmic bytes
     work = out["work"].cpu().numpy()
     caps = np.asarray(synth.KCAPS)
     chain_kcap = np.repeat(caps[np.searchsorted(caps, km)], wl.n_chains)
     avg = {name: float(np.mean([t["ms"] for t in ts])) for name, ts in kernel_ms.items()}
-    dom = max(avg, key=avg.get)
-    dom_t = kernel_ms[dom][0]
-    if dom_t["kcap"] > 0:
-        flops = algorithmic_flops(work[chain_kcap == dom_t["kcap"]])
+    per = {}
+    for name, ts in kernel_ms.items():
+        if ts[0]["kcap"] > 0:
+            wsel = work[chain_kcap == ts[0]["kcap"]]
+            per[name] = (algorithmic_bytes(wsel, 4.0 if "fp32" in name else 8.0), algorithmic_flops(wsel))
+    dom = max(per, key=lambda k: per[k][0])
+    nbytes, flops = per[dom]
+    if dom.startswith("chain_group_k"):  # G^-1 in LDS: no device-memory state traffic
+        achieved = flops / (avg[dom] / 1e3)
+        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                    "frac": achieved / PEAK_FP64, "traffic": recorded_traffic(args.workload, dom), "kernel": dom,
+                    "kernel_ms": avg[dom], "flops_per_launch": flops}
     else:
-        flops = 0.0
-    achieved = flops / (avg[dom] / 1e3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64, "traffic": None, "kernel": dom, "kernel_ms": avg[dom],
-                "flops_per_launch": flops}
+        achieved = nbytes / (avg[dom] / 1e3)
+        roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                    "frac": achieved / PEAK_HBM, "traffic": recorded_traffic(args.workload, dom), "kernel": dom,
+                    "kernel_ms": avg[dom], "bytes_per_launch": nbytes}
     print(f"[bench] kernels (mean ms): {json.dumps(avg)}", file=sys.stderr, flush=True)
 
     # ---- oracle on a bounded sample of the same workload (first cpu_wave waveforms, same chains)

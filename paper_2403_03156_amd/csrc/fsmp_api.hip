@@ -170,6 +170,10 @@ struct fsmp_ctx {
   std::vector<fsmp_timing> timings;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timing_events;
   std::vector<hipEvent_t> evpool;
+  // capacity buckets run concurrently: each on its own stream, forked from and joined
+  // back into the caller's stream with events
+  hipStream_t side[kNumCaps] = {};
+  hipEvent_t fork = nullptr, join[kNumCaps] = {};
   std::string err = "no error";
 };
 
@@ -363,6 +367,14 @@ void fsmp_destroy(fsmp_ctx *c) {
     (void)hipEventDestroy(c->stage_done);
   }
   for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+  for (int q = 0; q < kNumCaps; ++q) {
+    if (c->side[q]) {
+      (void)hipStreamSynchronize(c->side[q]);
+      (void)hipStreamDestroy(c->side[q]);
+    }
+    if (c->join[q]) (void)hipEventDestroy(c->join[q]);
+  }
+  if (c->fork) (void)hipEventDestroy(c->fork);
   if (c->d_vtab) (void)hipFree(c->d_vtab);
   if (c->d_ovl) (void)hipFree(c->d_ovl);
   c->woff.release();
@@ -582,7 +594,7 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     }
     st = c->capture;
   }
-  auto timed = [&](const char *name, int kcap, auto &&launch) -> hipError_t {
+  auto timed = [&](const char *name, int kcap, hipStream_t ks, auto &&launch) -> hipError_t {
     fsmp_timing t{};
     std::snprintf(t.name, sizeof t.name, "%s", name);
     t.kcap = kcap;
@@ -590,10 +602,10 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     if (c->timing && !c->capture) {
       e0 = pool_event(c, ev++);
       e1 = pool_event(c, ev++);
-      if (e0) (void)hipEventRecord(e0, st);
+      if (e0) (void)hipEventRecord(e0, ks);
     }
     hipError_t r = launch(t);
-    if (e1) (void)hipEventRecord(e1, st);
+    if (e1) (void)hipEventRecord(e1, ks);
     c->timings.push_back(t);
     c->timing_events.push_back({e0, e1});
     return r;
@@ -610,7 +622,7 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   pa.mf = c->mf.p;
   pa.wflags = c->wflags.p;
   pa.n_wave = n;
-  e = timed("prologue", 0, [&](fsmp_timing &t) {
+  e = timed("prologue", 0, st, [&](fsmp_timing &t) {
     t.chains = 0;
     t.blocks = std::min<int64_t>(n, 65535 * 8);
     t.lanes = 0;
@@ -658,9 +670,24 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   ca.refresh_M = cf.refresh_M;
   ca.near_eps = 1e-3;
   ca.drift_bound = 1e-3;
+  int n_buckets = 0;
+  for (int bi = 0; bi < kNumCaps; ++bi) n_buckets += bucket_start[bi + 1] > bucket_start[bi];
+  const bool fan = n_buckets > 1;
+  if (fan && e == hipSuccess) {
+    if (!c->fork) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(c->fork, st);
+  }
   for (int bi = 0; bi < kNumCaps && e == hipSuccess; ++bi) {
     const int64_t cnt = bucket_start[bi + 1] - bucket_start[bi];
     if (cnt == 0) continue;
+    hipStream_t ks = st;
+    if (fan) {
+      if (!c->side[bi]) e = hipStreamCreateWithFlags(&c->side[bi], hipStreamNonBlocking);
+      if (e == hipSuccess && !c->join[bi]) e = hipEventCreateWithFlags(&c->join[bi], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipStreamWaitEvent(c->side[bi], c->fork, 0);
+      if (e != hipSuccess) break;
+      ks = c->side[bi];
+    }
     ca.chains = c->chains.p + bucket_start[bi];
     ca.n_list = cnt;
     char name[32];
@@ -671,12 +698,17 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     ca.dws = dz != FSMP_DESIGN_GROUP ? c->lane_d.p + lane_doff[bi] : nullptr;
     ca.iws = dz == FSMP_DESIGN_LANE ? c->lane_i.p + lane_ioff[bi] : nullptr;
     ca.dscr = ca.qdraw ? c->draw_scr.p + draw_off[bi] : nullptr;
-    e = timed(name, caps[bi], [&](fsmp_timing &t) {
+    e = timed(name, caps[bi], ks, [&](fsmp_timing &t) {
       t.chains = cnt;
-      return dz == FSMP_DESIGN_LANE    ? launch_chain_lane(caps[bi], fp32, ca, st, &t.lanes, &t.blocks)
-             : dz == FSMP_DESIGN_GROUP ? launch_chain(caps[bi], ca, st, &t.lanes, &t.blocks)
-                                       : launch_chain_dm(caps[bi], ca, st, &t.lanes, &t.blocks);
+      return dz == FSMP_DESIGN_LANE    ? launch_chain_lane(caps[bi], fp32, ca, ks, &t.lanes, &t.blocks)
+             : dz == FSMP_DESIGN_GROUP ? launch_chain(caps[bi], ca, ks, &t.lanes, &t.blocks)
+                                       : launch_chain_dm(caps[bi], ca, ks, &t.lanes, &t.blocks);
     });
+    if (fan) {
+      const hipError_t e2 = hipEventRecord(c->join[bi], ks);
+      const hipError_t e3 = e2 == hipSuccess ? hipStreamWaitEvent(st, c->join[bi], 0) : e2;
+      if (e == hipSuccess) e = e3;
+    }
   }
   if (c->capture) {
     hipGraph_t g = nullptr;

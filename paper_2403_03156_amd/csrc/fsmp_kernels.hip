@@ -1388,8 +1388,8 @@ struct GroupCfg {
   int kcap, lpc, wpb;
 };
 static const GroupCfg kGroup[] = {{16, 16, 4}, {32, 32, 4}, {48, 64, 3}, {64, 64, 4}};
-static const GroupCfg kGroupDM[] = {{16, 4, 4},    {32, 8, 4},    {48, 16, 4},   {64, 16, 4},
-                                    {96, 16, 2},   {128, 32, 4},  {160, 32, 4},  {192, 32, 2}};
+static const GroupCfg kGroupDM[] = {{16, 4, 4},  {32, 8, 4},   {48, 16, 4},  {64, 32, 4},
+                                    {96, 16, 2}, {128, 32, 4}, {160, 32, 4}, {192, 32, 2}};
 
 static size_t chain_lds_bytes(const GroupCfg &g, int M, int sub, bool hg) {
   const int cpb = g.wpb * (64 / g.lpc);
@@ -1474,7 +1474,7 @@ hipError_t launch_chain_dm(int kcap, const ChainArgs &a, hipStream_t st, int32_t
     case 16: return launch_chain_t<16, 4, 4, true>(a, st, lanes, blocks);
     case 32: return launch_chain_t<32, 8, 4, true>(a, st, lanes, blocks);
     case 48: return launch_chain_t<48, 16, 4, true>(a, st, lanes, blocks);
-    case 64: return launch_chain_t<64, 16, 4, true>(a, st, lanes, blocks);
+    case 64: return launch_chain_t<64, 32, 4, true>(a, st, lanes, blocks);
     case 96: return launch_chain_t<96, 16, 2, true>(a, st, lanes, blocks);
     case 128: return launch_chain_t<128, 32, 4, true>(a, st, lanes, blocks);
     case 160: return launch_chain_t<160, 32, 4, true>(a, st, lanes, blocks);

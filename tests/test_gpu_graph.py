@@ -71,8 +71,9 @@ def test_set_design_validation():
         smp.set_design(96, fsmp.FSMP_DESIGN_GROUP)
     with pytest.raises(RuntimeError):
         smp.set_design(20, fsmp.FSMP_DESIGN_LANE)
-    smp.set_design(0, fsmp.FSMP_DESIGN_GROUP)  # every capacity that has the design
-    assert [smp.get_design(c) for c in synth.KCAPS] == [0, 0, 0, 0, 1, 1, 1, 1]
+    before = [smp.get_design(c) for c in synth.KCAPS]
+    smp.set_design(0, fsmp.FSMP_DESIGN_GROUP)  # every capacity that has the design; the rest keep theirs
+    assert [smp.get_design(c) for c in synth.KCAPS] == [0, 0, 0, 0] + before[4:]
     smp.set_design(0, fsmp.FSMP_DESIGN_GROUP_DEVMEM)
     assert [smp.get_design(c) for c in synth.KCAPS] == [2] * 8
     with pytest.raises(RuntimeError):
