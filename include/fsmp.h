@@ -230,6 +230,20 @@ size_t fsmp_workspace_bytes(const fsmp_ctx *ctx, int64_t n_wave, int64_t total_g
  * FSMP_ENOTSUP if a kmax exceeds 192 or the SER support does not fit a kernel. */
 fsmp_status fsmp_sample(fsmp_ctx *ctx, const fsmp_batch *batch, const fsmp_samples *out, void *hip_stream);
 
+/* Replay (a check of the sampler's delta-nu along a given path; Sec. 2.4 moves, App. A
+ * delta-nu): like fsmp_sample, but every chain follows the recorded proposals of `log`
+ * (device, [chain][cfg.n_steps] fsmp_logrec, the FSMP_REC_LOG layout, from this library
+ * or written elsewhere) instead of its own draws: at each step t0 is set to the record's
+ * t0, the record's move, index and grid point are proposed if the record is flagged
+ * valid (bit 0), and the record's accept bit (bit 1) decides.  dnu and log_alpha (device,
+ * [chain][cfg.n_steps]) receive what the kernel computes for each evaluated proposal; 0
+ * and -inf for steps not evaluated (not flagged valid, malformed, or invalid here, e.g. a
+ * Schur complement that is not positive).  Runs the lane-group kernels with G^-1 in
+ * device memory at every capacity, FP64 form only (FSMP_ENOTSUP otherwise).  `out`
+ * receives the final state and accumulators as in fsmp_sample.  Errors as fsmp_sample. */
+fsmp_status fsmp_replay(fsmp_ctx *ctx, const fsmp_batch *batch, const fsmp_logrec *log, double *dnu,
+                        double *log_alpha, const fsmp_samples *out, void *hip_stream);
+
 /* Reduce the per-chain accumulators of fsmp_sample's output into per-waveform summaries
  * (device kernel on `hip_stream`). */
 fsmp_status fsmp_posterior(fsmp_ctx *ctx, int64_t n_wave, const fsmp_samples *in, fsmp_posterior_out *out,

@@ -423,10 +423,18 @@ int32_t fsmp_last_timings(const fsmp_ctx *cc, fsmp_timing *out, int32_t cap) {
   return n;
 }
 
-fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o, void *hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// fsmp_sample, or with `force` set fsmp_replay: the chains follow the recorded proposals
+// and the lane-group kernels with G^-1 in device memory write delta-nu / log-alpha
+fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o, void *hip_stream,
+                        const fsmp_logrec *force, double *rdnu, double *rla) {
   if (!c) return FSMP_EINVAL;
   if (!b || !o) return fail(c, FSMP_EINVAL, "null batch or output");
   const fsmp_config &cf = c->cfg;
+  if (force && cf.precision != FSMP_FP64) return fail(c, FSMP_ENOTSUP, "replay runs the FP64 form only");
   const int64_t n = b->n_wave;
   if (n < 0) return fail(c, FSMP_EINVAL, "n_wave < 0");
   if (n > 0 && (!b->wave || !b->offsets || !b->lambda)) return fail(c, FSMP_EINVAL, "wave, offsets and lambda are required");
@@ -476,6 +484,9 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   order.reserve((size_t)n * cf.n_chains);
   int64_t bucket_start[kNumCaps + 1] = {0};
   const bool fp32 = cf.precision == FSMP_FP32_REFRESH;
+  auto design_of = [&](int bi) {
+    return fp32 ? FSMP_DESIGN_LANE : force ? FSMP_DESIGN_GROUP_DEVMEM : c->design[bi];
+  };
   // within a bucket, waveforms in order of lambda: neighbouring lanes then carry chains of
   // similar PE counts, which keeps the lane-per-chain loops (bounded by the largest K in a
   // wavefront) short
@@ -497,7 +508,7 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     return fail(c, FSMP_ENOTSUP, "kmax above %d is not provided by this build", kCaps[kNumCaps - 1]);
   if (n * (int64_t)cf.n_chains > INT32_MAX) return fail(c, FSMP_EINVAL, "too many chains");
   for (int bi = 0; bi < kNumCaps; ++bi)
-    if (bucket_start[bi + 1] > bucket_start[bi] && !fp32 && !design_available(c, caps[bi], c->design[bi]))
+    if (bucket_start[bi + 1] > bucket_start[bi] && !fp32 && !design_available(c, caps[bi], design_of(bi)))
       return fail(c, FSMP_ENOTSUP, "SER support %d too long for the design of PE capacity %d", c->tab.LV, caps[bi]);
   if (n == 0) {
     c->timings.clear();
@@ -525,7 +536,7 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   {
     for (int bi = 0; bi < kNumCaps; ++bi) {
       const int64_t cnt = bucket_start[bi + 1] - bucket_start[bi];
-      const int dz = fp32 ? FSMP_DESIGN_LANE : c->design[bi];
+      const int dz = design_of(bi);
       const size_t dd = dz == FSMP_DESIGN_LANE ? lane_ws_doubles(caps[bi], cnt, fp32)
                         : dz == FSMP_DESIGN_GROUP_DEVMEM ? group_dm_ws_doubles(caps[bi], cnt)
                                                          : 0;
@@ -664,6 +675,9 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   ca.qdraw = (cf.record_flags & FSMP_REC_CHARGE) ? o->qdraw : nullptr;
   ca.zdraw = (cf.record_flags & FSMP_REC_CHARGE) ? o->zdraw : nullptr;
   ca.sigma_eps = cf.sigma_eps;
+  ca.force = force;
+  ca.rdnu = rdnu;
+  ca.rla = rla;
   ca.kz = o->kz;
   ca.wflags = c->wflags.p;
   ca.work = o->work;
@@ -691,7 +705,7 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     ca.chains = c->chains.p + bucket_start[bi];
     ca.n_list = cnt;
     char name[32];
-    const int dz = fp32 ? FSMP_DESIGN_LANE : c->design[bi];
+    const int dz = design_of(bi);
     std::snprintf(name, sizeof name, "%s%s_k%d",
                   dz == FSMP_DESIGN_LANE ? "chain_lane" : dz == FSMP_DESIGN_GROUP ? "chain_group" : "chain_group_dm",
                   fp32 ? "_fp32" : "", caps[bi]);
@@ -719,6 +733,21 @@ fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   (void)hipSetDevice(prev);
   if (e != hipSuccess) return fail(c, FSMP_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   return FSMP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o, void *hip_stream) {
+  return sample_impl(c, b, o, hip_stream, nullptr, nullptr, nullptr);
+}
+
+fsmp_status fsmp_replay(fsmp_ctx *c, const fsmp_batch *b, const fsmp_logrec *log, double *dnu, double *log_alpha,
+                        const fsmp_samples *o, void *hip_stream) {
+  if (!c) return FSMP_EINVAL;
+  if (!log || !dnu || !log_alpha) return fail(c, FSMP_EINVAL, "replay needs the log and both outputs");
+  return sample_impl(c, b, o, hip_stream, log, dnu, log_alpha);
 }
 
 fsmp_status fsmp_set_design(fsmp_ctx *c, int32_t capacity, int32_t design) {

@@ -72,6 +72,10 @@ struct ChainArgs {
   int32_t *zdraw;
   double *dscr;
   double sigma_eps;
+  // replay (lane groups with H in device memory only): recorded proposals [chain][n_steps]
+  // to follow, and the delta-nu / log-acceptance computed along them
+  const fsmp_logrec *force;
+  double *rdnu, *rla;
 };
 
 struct PrologueArgs {

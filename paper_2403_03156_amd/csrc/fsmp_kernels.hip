@@ -272,8 +272,10 @@ __device__ inline void grp_col_update(double *H, int i, int N, double ai, const 
 
 // HG: H in device memory (a.dws, the chains of a wavefront interleaved element by element),
 // which leaves the LDS to the tables and the vectors and so fits many more chains per CU;
-// otherwise H in LDS.
-template <int KCAP, int LPC, int WPB, bool HG>
+// otherwise H in LDS.  FORCE (replay): every step follows the recorded proposal of a.force
+// (t0 after the half-step, move, index, grid point, accept bit) instead of the chain's
+// own draws, and writes the delta-nu and log-acceptance it computes to a.rdnu / a.rla.
+template <int KCAP, int LPC, int WPB, bool HG, bool FORCE>
 __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
   constexpr int CPW = kWave / LPC;
   using CL = ChainLayout<KCAP, HG>;
@@ -343,7 +345,15 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
     const double t0p = t0 + md.t0_sd * xi_t0;
     bool t0acc = false;
     if (lane == 0) cnt[0]++;
-    if (t0p >= md.t0_min && t0p <= md.t0_max) {
+    fsmp_logrec rec{};
+    if (FORCE) {
+      rec = a.force[c * (int64_t)a.n_steps + step];
+      t0acc = (rec.flags & 4) != 0;
+      if (rec.t0 != t0) {
+        t0 = rec.t0;
+        Phi = (glo <= ghi) ? phi_total(md, t0, glo, ghi) : 0.0;
+      }
+    } else if (t0p >= md.t0_min && t0p <= md.t0_max) {
       if (lane == 0) acc[18] += N;
       double part = 0.0;
       int bad = 0;
@@ -370,7 +380,11 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
     // ---- Gibbs half-step 2: one RJMCMC jump
     const double Lam = lam * md.dt * Phi;
     const double um = u01(r[3]);
-    const int move = (N == 0 || um < md.J) ? 1 : (um < 2.0 * md.J ? 2 : 3);
+    const int move = FORCE ? rec.move : ((N == 0 || um < md.J) ? 1 : (um < 2.0 * md.J ? 2 : 3));
+    // replay: only the recorded valid proposals are evaluated, and only well-formed ones
+    const bool consider =
+        !FORCE || ((rec.flags & 1) && (move == 1 ? (rec.g >= glo && rec.g <= ghi)
+                                                 : (move == 2 || move == 3) && rec.j >= 0 && rec.j < N));
     int j = -1, gnew = -1, sh = 0;
     bool valid = false;
     double dnu = 0.0, la = -INFINITY;
@@ -379,8 +393,8 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
       if (lane == 0) cnt[2]++;
       if (N >= kmax) {
         st |= FSMP_ST_KMAX;
-      } else if (Phi > 0.0) {
-        gnew = birth_draw<LPC>(md, t0, glo, ghi, u53(r[4], r[5]) * Phi, lane, grp);
+      } else if (Phi > 0.0 && consider) {
+        gnew = FORCE ? rec.g : birth_draw<LPC>(md, t0, glo, ghi, u53(r[4], r[5]) * Phi, lane, grp);
         if (Lam > 0.0) {
           for (int i = lane; i < N; i += LPC) s1[i] = overlap(md, vt, ov, gnew, zg[i], Lw);
           const double d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
@@ -408,8 +422,10 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
         }
       }
     } else {
-      j = (int)(((uint64_t)r[4] * (uint64_t)N) >> 32);
-      if (move == 2) {
+      j = FORCE ? rec.j : (int)(((uint64_t)r[4] * (uint64_t)N) >> 32);
+      if (!consider) {
+        j = -1;  // replay: not a recorded valid proposal
+      } else if (move == 2) {
         if (lane == 0) cnt[4]++;
         om = H[(j * LD + j) * HS];
         xj = xv[j];
@@ -422,7 +438,7 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
         }
       } else {
         if (lane == 0) cnt[6]++;
-        sh = (int)rint(xi_sh * md.shift_sd / md.dt);
+        sh = FORCE ? rec.g - zg[j] : (int)rint(xi_sh * md.shift_sd / md.dt);
         gnew = zg[j] + sh;
         if (gnew >= glo && gnew <= ghi) {
           const double lpn = log_phi(md, (double)gnew * md.dt - t0);
@@ -467,7 +483,7 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
     }
 
     bool accepted = false;
-    if (valid && log(u01(r[6])) < la) {
+    if (valid && (FORCE ? (rec.flags & 2) != 0 : log(u01(r[6])) < la)) {
       accepted = true;
       if (lane == 0) cnt[2 * move + 1]++;
       WAVE_SYNC();
@@ -563,6 +579,10 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
       lr->t0 = t0;
       lr->dnu = valid ? dnu : 0.0;
       lr->log_alpha = valid ? la : -INFINITY;
+    }
+    if (FORCE && lane == 0) {
+      a.rdnu[c * (int64_t)a.n_steps + step] = valid ? dnu : 0.0;
+      a.rla[c * (int64_t)a.n_steps + step] = valid ? la : -INFINITY;
     }
 
     // ---- record after burn-in
@@ -1327,7 +1347,7 @@ __global__ void __launch_bounds__(256) posterior_kernel(PosteriorArgs a) {
   a.status[w] = st;
 }
 
-template <int KCAP, int LPC, int WPB, bool HG>
+template <int KCAP, int LPC, int WPB, bool HG, bool FORCE = false>
 hipError_t launch_chain_t(const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
   constexpr int CPB = WPB * (kWave / LPC);
   const int64_t nb = (a.n_list + CPB - 1) / CPB;
@@ -1338,11 +1358,12 @@ hipError_t launch_chain_t(const ChainArgs &a, hipStream_t st, int32_t *lanes, in
   if (HG && a.dws == nullptr) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
     // lift the default dynamic-LDS limit; gfx950 has 160 KB per workgroup
-    (void)hipFuncSetAttribute((const void *)chain_kernel<KCAP, LPC, WPB, HG>,
+    (void)hipFuncSetAttribute((const void *)chain_kernel<KCAP, LPC, WPB, HG, FORCE>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipGetLastError();
   }
-  hipLaunchKernelGGL((chain_kernel<KCAP, LPC, WPB, HG>), dim3((unsigned)nb), dim3(kWave * WPB), lds, st, a);
+  if (FORCE && (a.force == nullptr || a.rdnu == nullptr || a.rla == nullptr)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((chain_kernel<KCAP, LPC, WPB, HG, FORCE>), dim3((unsigned)nb), dim3(kWave * WPB), lds, st, a);
   return hipGetLastError();
 }
 
@@ -1470,6 +1491,19 @@ hipError_t launch_chain(int kcap, const ChainArgs &a, hipStream_t st, int32_t *l
 
 // instances must match kGroupDM
 hipError_t launch_chain_dm(int kcap, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
+  if (a.force) {
+    switch (kcap) {
+      case 16: return launch_chain_t<16, 4, 4, true, true>(a, st, lanes, blocks);
+      case 32: return launch_chain_t<32, 8, 4, true, true>(a, st, lanes, blocks);
+      case 48: return launch_chain_t<48, 16, 4, true, true>(a, st, lanes, blocks);
+      case 64: return launch_chain_t<64, 32, 4, true, true>(a, st, lanes, blocks);
+      case 96: return launch_chain_t<96, 16, 2, true, true>(a, st, lanes, blocks);
+      case 128: return launch_chain_t<128, 32, 4, true, true>(a, st, lanes, blocks);
+      case 160: return launch_chain_t<160, 32, 4, true, true>(a, st, lanes, blocks);
+      case 192: return launch_chain_t<192, 32, 2, true, true>(a, st, lanes, blocks);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (kcap) {
     case 16: return launch_chain_t<16, 4, 4, true>(a, st, lanes, blocks);
     case 32: return launch_chain_t<32, 8, 4, true>(a, st, lanes, blocks);

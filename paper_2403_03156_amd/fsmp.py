@@ -23,7 +23,7 @@ EXPORTS = ("fsmp_create", "fsmp_workspace_bytes", "fsmp_sample", "fsmp_posterior
            "fsmp_set_timing", "fsmp_last_error", "fsmp_destroy", "fsmp_version", "fsmp_server_create",
            "fsmp_server_submit", "fsmp_server_progress", "fsmp_server_result", "fsmp_server_stats",
            "fsmp_server_last_error", "fsmp_server_destroy", "fsmp_set_design", "fsmp_get_design", "fsmp_autotune",
-           "fsmp_graph_create", "fsmp_graph_launch", "fsmp_graph_destroy")
+           "fsmp_graph_create", "fsmp_graph_launch", "fsmp_graph_destroy", "fsmp_replay")
 FSMP_DESIGN_GROUP, FSMP_DESIGN_LANE, FSMP_DESIGN_GROUP_DEVMEM = 0, 1, 2
 
 
@@ -149,6 +149,9 @@ def load(path: Optional[str] = None):
     L.fsmp_graph_launch.restype = ctypes.c_int
     L.fsmp_graph_destroy.argtypes = [ctypes.c_void_p]
     L.fsmp_graph_destroy.restype = None
+    L.fsmp_replay.argtypes = [ctypes.c_void_p, P(fsmp_batch), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                              P(fsmp_samples), ctypes.c_void_p]
+    L.fsmp_replay.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -288,6 +291,33 @@ class Sampler:
         self._check(self.lib.fsmp_graph_create(self.h, ctypes.byref(b), ctypes.byref(s), ctypes.c_void_p(st.cuda_stream),
                                                ctypes.byref(g)))
         return Graph(self, g, keep), out
+
+    def replay(self, wave, offsets, lam, log, kmax=None, kz=None, stream=None):
+        """Follow recorded proposals (``log``: device uint8 [chains, n_steps * 40] or a structured
+        host array [chains, n_steps] of LOGREC_DTYPE); returns (dnu, log_alpha, out) on the device."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        b, keep = self._batch(wave, offsets, lam, kmax)
+        n = len(offsets) - 1
+        if kz is None:
+            kz = int(np.max(kmax)) if kmax is not None else self.cfg.k_max
+        C = n * self.cfg.n_chains
+        if isinstance(log, np.ndarray):
+            rec = np.ascontiguousarray(log, dtype=LOGREC_DTYPE)
+            if rec.shape != (C, self.cfg.n_steps):
+                raise ValueError(f"log must be [{C}, {self.cfg.n_steps}] records")
+            log = torch.from_numpy(rec.view(np.uint8).reshape(C, -1).copy()).to(dev)
+        if not log.is_cuda or log.numel() != C * self.cfg.n_steps * LOGREC_DTYPE.itemsize:
+            raise ValueError("log must hold one record per chain and step")
+        out = self.alloc_samples(n, kz)
+        dnu = torch.zeros((C, self.cfg.n_steps), dtype=torch.float64, device=dev)
+        la = torch.zeros((C, self.cfg.n_steps), dtype=torch.float64, device=dev)
+        s = self._samples(out)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._check(self.lib.fsmp_replay(self.h, ctypes.byref(b), ctypes.c_void_p(log.data_ptr()),
+                                         ctypes.c_void_p(dnu.data_ptr()), ctypes.c_void_p(la.data_ptr()),
+                                         ctypes.byref(s), ctypes.c_void_p(st.cuda_stream)))
+        return dnu, la, out
 
     def sample(self, wave, offsets, lam, kmax=None, g_range=None, t0_init=None, wave_id=None, out=None, kz=None,
                stream=None, work=False):
