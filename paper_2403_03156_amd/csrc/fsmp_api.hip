@@ -271,6 +271,9 @@ void fill_model(fsmp_ctx *c) {
     md.logC = -md.log_tau2;
     md.den12 = 1.0;
   }
+  md.sub_shift = -1;
+  for (int k = 0; k < 31; ++k)
+    if ((1 << k) == md.sub) md.sub_shift = k;
   md.t0_min = c->phi.t0_min;
   md.t0_max = c->phi.t0_max;
   md.t0_sd = cf.t0_step_sd;

@@ -13,8 +13,9 @@ namespace fsmp {
 struct ModelDev {
   // likelihood in PE space: s = sigma_eps^2, rho = s / sigma_q^2, m = mu_q
   double s, inv_s, rho, log_rho, m, rhom, rhom2;
-  // grid and SER table: dt = 1 / sub samples, M = sub * LV table entries
-  int32_t sub, LV, M, pad0;
+  // grid and SER table: dt = 1 / sub samples, M = sub * LV table entries; sub_shift =
+  // log2(sub) when sub is a power of two (divisions of grid indices become shifts), else -1
+  int32_t sub, LV, M, sub_shift;
   double dt;
   // light curve
   int32_t kind, pad1;

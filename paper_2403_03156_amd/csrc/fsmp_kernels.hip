@@ -130,16 +130,37 @@ __device__ inline int group_or(int v) {
   return v;
 }
 
+template <int W>
+__device__ inline int group_min(int v) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) {
+    const int u = __shfl_xor(v, o, W);
+    v = u < v ? u : v;
+  }
+  return v;
+}
+
+// BIEXP part of log phi that depends on t0: log(1 - e^{-(t - t0) / tau_rise})
+__device__ inline double rise_term(const ModelDev &md, int g, double t0) {
+  return log(-expm1(-((double)g * md.dt - t0) * md.inv_tau1));
+}
+
+// v / sub and v % sub for v >= 0 (grid indices): shifts when sub is a power of two
+__device__ inline int sub_div(const ModelDev &md, int v) { return md.sub_shift >= 0 ? v >> md.sub_shift : v / md.sub; }
+__device__ inline int sub_mod(const ModelDev &md, int v) {
+  return md.sub_shift >= 0 ? v & (md.sub - 1) : v % md.sub;
+}
+
 // overlap sum_{n < Lw} V(n - g1/sub) V(n - g2/sub): the stationary table unless both
 // columns run past the window end, then the direct sum over the samples left
 __device__ inline double overlap(const ModelDev &md, const double *vt, const double *ov, int g1, int g2, int Lw) {
   const int lo = g1 < g2 ? g1 : g2, hi = g1 < g2 ? g2 : g1;
   const int d = hi - lo;
   if (d >= md.M) return 0.0;
-  const int nhi = (lo + md.M - 1) / md.sub;  // last sample of the earlier column
-  if (nhi < Lw) return ov[(lo % md.sub) * md.M + d];
+  const int nhi = sub_div(md, lo + md.M - 1);  // last sample of the earlier column
+  if (nhi < Lw) return ov[sub_mod(md, lo) * md.M + d];
   double s = 0.0;
-  const int n0 = (hi + md.sub - 1) / md.sub;
+  const int n0 = sub_div(md, hi + md.sub - 1);
   for (int n = n0; n < Lw; ++n) s += vt[md.sub * n - lo] * vt[md.sub * n - hi];
   return s;
 }
@@ -207,8 +228,8 @@ __global__ void __launch_bounds__(256) prologue_kernel(PrologueArgs a) {
     const int glo = a.grange[2 * w], ghi = a.grange[2 * w + 1];
     double *out = a.mf + a.mfoff[w];
     for (int g = glo + (int)threadIdx.x; g <= ghi; g += blockDim.x) {
-      const int n0 = (g + md.sub - 1) / md.sub;
-      int n1 = (g + md.M - 1) / md.sub;
+      const int n0 = sub_div(md, g + md.sub - 1);
+      int n1 = sub_div(md, g + md.M - 1);
       if (n1 > Lw - 1) n1 = Lw - 1;
       double s = 0.0;
       for (int n = n0; n <= n1; ++n) s += (double)x[n] * vt[md.sub * n - g];
@@ -218,7 +239,7 @@ __global__ void __launch_bounds__(256) prologue_kernel(PrologueArgs a) {
 }
 
 // ------------------------------------------------------------------ chains
-// LDS block of one chain: H (unless it lives in device memory), b, x, three scratch
+// LDS block of one chain: H (unless it lives in device memory), x, three scratch
 // vectors, the accumulators (kAcc doubles: 12 sums, 3 open batch sums, 4 work counters,
 // then 8 int proposal / accept counts), then int grid indices and the N histogram.  The
 // accumulators live in LDS, updated by the group's first lane, to keep registers free.
@@ -226,7 +247,7 @@ template <int KCAP, bool HG>
 struct ChainLayout {
   static constexpr int LD = KCAP;
   static constexpr int kAcc = 24;
-  static constexpr int kDoubles = (HG ? 0 : KCAP * KCAP) + 5 * KCAP + kAcc + (2 * KCAP + 2) / 2;
+  static constexpr int kDoubles = (HG ? 0 : KCAP * KCAP) + 4 * KCAP + kAcc + (2 * KCAP + 2) / 2;
 };
 
 // Column i of H owned by one lane: element (k, i) at H[(k * LD + i) * HS] (HS = 1 in LDS;
@@ -287,6 +308,8 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
   double *ov = smem + md.M;
   for (int i = threadIdx.x; i < md.M; i += blockDim.x) vt[i] = a.vtab[i];
   for (int i = threadIdx.x; i < md.sub * md.M; i += blockDim.x) ov[i] = a.ovl[i];
+  double *lgn = ov + md.sub * md.M;  // log k, k = 0..KCAP + 1
+  for (int i = threadIdx.x; i < KCAP + 2; i += blockDim.x) lgn[i] = log((double)i);
   __syncthreads();
 
   const int wv = threadIdx.x / kWave, l64 = threadIdx.x % kWave;
@@ -295,10 +318,9 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
   const int64_t slot = tile * CPW + grp;
   if (slot >= a.n_list) return;
 
-  double *cb = smem + md.M * (1 + md.sub) + (int64_t)(wv * CPW + grp) * CL::kDoubles;
+  double *cb = smem + md.M * (1 + md.sub) + (KCAP + 2) + (int64_t)(wv * CPW + grp) * CL::kDoubles;
   double *H = HG ? a.dws + tile * (int64_t)(KCAP * LD * CPW) + grp : cb;
-  double *bv = HG ? cb : cb + KCAP * LD;
-  double *xv = bv + KCAP;
+  double *xv = HG ? cb : cb + KCAP * LD;
   double *s1 = xv + KCAP;
   double *s2 = s1 + KCAP;
   double *s3 = s2 + KCAP;
@@ -327,6 +349,13 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
   double t0 = a.t0init[w];
   int N = 0;
   double Phi = (glo <= ghi) ? phi_total(md, t0, glo, ghi) : 0.0;
+  // Lambda_T and its log change only with t0; S_cur = sum over PEs of the BIEXP rise term
+  // at the current t0 and gmin = the smallest PE grid index (phi must stay positive at
+  // every PE) make the t0 step one term per PE
+  double Lam = lam * md.dt * Phi, logLam = log(Lam);
+  const bool biexp = md.kind == FSMP_PHI_BIEXP;
+  double S_cur = 0.0;
+  int gmin = INT32_MAX;
   if (lane == 0) {
     for (int i = 0; i < 20; ++i) acc[i] = 0.0;
     for (int i = 0; i < 8; ++i) cnt[i] = 0;
@@ -352,25 +381,32 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
       if (rec.t0 != t0) {
         t0 = rec.t0;
         Phi = (glo <= ghi) ? phi_total(md, t0, glo, ghi) : 0.0;
+        Lam = lam * md.dt * Phi;
+        logLam = log(Lam);
+        if (biexp) {
+          double sn = 0.0;
+          for (int i = lane; i < N; i += LPC) sn += rise_term(md, zg[i], t0);
+          S_cur = group_sum<LPC>(sn);
+        }
       }
     } else if (t0p >= md.t0_min && t0p <= md.t0_max) {
       if (lane == 0) acc[18] += N;
-      double part = 0.0;
-      int bad = 0;
-      for (int i = lane; i < N; i += LPC) {
-        const double tk = (double)zg[i] * md.dt;
-        const double ln = log_phi(md, tk - t0p);
-        if (ln == -INFINITY) bad = 1;
-        else part += ln - log_phi(md, tk - t0);
-      }
-      part = group_sum<LPC>(part);
-      bad = group_or<LPC>(bad);
-      if (!bad) {
+      const double xmin = (N > 0) ? (double)gmin * md.dt - t0p : 1.0;
+      if (biexp ? (xmin > 0.0) : (xmin >= 0.0)) {
+        double S_new = 0.0;
+        if (biexp) {
+          for (int i = lane; i < N; i += LPC) S_new += rise_term(md, zg[i], t0p);
+          S_new = group_sum<LPC>(S_new);
+        }
+        const double part = (double)N * (t0p - t0) * md.inv_tau2 + (S_new - S_cur);
         const double Phip = (glo <= ghi) ? phi_total(md, t0p, glo, ghi) : 0.0;
         const double la0 = part - (lam * md.dt * Phip - lam * md.dt * Phi);
         if (log(u01(r[2])) < la0) {
           t0 = t0p;
           Phi = Phip;
+          Lam = lam * md.dt * Phi;
+          logLam = log(Lam);
+          S_cur = S_new;
           t0acc = true;
           if (lane == 0) cnt[1]++;
         }
@@ -378,7 +414,6 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
     }
 
     // ---- Gibbs half-step 2: one RJMCMC jump
-    const double Lam = lam * md.dt * Phi;
     const double um = u01(r[3]);
     const int move = FORCE ? rec.move : ((N == 0 || um < md.J) ? 1 : (um < 2.0 * md.J ? 2 : 3));
     // replay: only the recorded valid proposals are evaluated, and only well-formed ones
@@ -414,7 +449,7 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
           if (delta2 > 0.0) {
             up = beta - p;
             dnu = -0.5 * (-md.log_rho + log(delta2) + (md.rhom2 - up * up / delta2) * md.inv_s);
-            la = dnu + log(Lam) - log((double)(N + 1)) + (N == 0 ? md.logJ : 0.0);
+            la = dnu + logLam - lgn[N + 1] + (N == 0 ? md.logJ : 0.0);
             valid = true;
           } else {
             st |= FSMP_ST_FACTOR;
@@ -431,7 +466,7 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
         xj = xv[j];
         if (om > 0.0) {
           dnu = 0.5 * (-md.log_rho - log(om) + (md.rhom2 - xj * xj / om) * md.inv_s);
-          la = dnu - log(Lam) + log((double)N) - (N == 1 ? md.logJ : 0.0);
+          la = dnu - logLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
           valid = true;
         } else {
           st |= FSMP_ST_FACTOR;
@@ -504,12 +539,14 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
         if (lane == 0) {
           H[(N * LD + N) * HS] = inv_d2;
           zg[N] = gnew;
-          bv[N] = beta;
           xv[N] = xn;
         }
         N++;
+        if (biexp) S_cur += rise_term(md, gnew, t0);
+        gmin = gnew < gmin ? gnew : gmin;
         WAVE_SYNC();
       } else if (move == 2) {
+        const int gj = zg[j];
         const double inv_om = 1.0 / om;
         for (int i = lane; i < N; i += LPC) s3[i] = H[(j * LD + i) * HS];
         WAVE_SYNC();
@@ -534,13 +571,19 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
           }
           if (lane == 0) {
             zg[j] = zg[last];
-            bv[j] = bv[last];
             xv[j] = xv[last];
           }
         }
         N--;
         WAVE_SYNC();
+        if (biexp) S_cur -= rise_term(md, gj, t0);
+        if (gj == gmin) {
+          int m = INT32_MAX;
+          for (int i = lane; i < N; i += LPC) m = zg[i] < m ? zg[i] : m;
+          gmin = group_min<LPC>(m);
+        }
       } else if (sh != 0) {
+        const int gj = zg[j];
         const double inv_om = 1.0 / om, inv_d2 = 1.0 / delta2;
         const double xn = up * inv_d2;
         for (int i = lane; i < N; i += LPC) s3[i] = H[(j * LD + i) * HS];
@@ -564,9 +607,16 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
         }
         if (lane == 0) {
           zg[j] = gnew;
-          bv[j] = beta;
         }
         WAVE_SYNC();
+        if (biexp) S_cur += rise_term(md, gnew, t0) - rise_term(md, gj, t0);
+        if (gnew < gmin) {
+          gmin = gnew;
+        } else if (gj == gmin) {
+          int m = INT32_MAX;
+          for (int i = lane; i < N; i += LPC) m = zg[i] < m ? zg[i] : m;
+          gmin = group_min<LPC>(m);
+        }
       }
     }
 
@@ -704,6 +754,8 @@ __device__ inline int birth_draw_lane(const ModelDev &md, double t0, int glo, in
       else if (k < p.n - 1 && !(phi_partial(md, p.xs, k + 1) > target)) k += 1;
     }
   } else {
+    // bisection: the same number of steps in every lane (a Newton inverse with per-lane
+    // iteration counts measured slower on the GPU)
     int64_t lo = 0, hi = p.n - 1;
     while (lo < hi) {
       const int64_t mid = lo + (hi - lo) / 2;
@@ -1351,7 +1403,8 @@ template <int KCAP, int LPC, int WPB, bool HG, bool FORCE = false>
 hipError_t launch_chain_t(const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
   constexpr int CPB = WPB * (kWave / LPC);
   const int64_t nb = (a.n_list + CPB - 1) / CPB;
-  const size_t lds = sizeof(double) * ((size_t)a.md.M * (1 + a.md.sub) + (size_t)CPB * ChainLayout<KCAP, HG>::kDoubles);
+  const size_t lds =
+      sizeof(double) * ((size_t)a.md.M * (1 + a.md.sub) + (KCAP + 2) + (size_t)CPB * ChainLayout<KCAP, HG>::kDoubles);
   *lanes = LPC;
   *blocks = nb;
   if (nb == 0) return hipSuccess;
@@ -1414,8 +1467,8 @@ static const GroupCfg kGroupDM[] = {{16, 4, 4},  {32, 8, 4},   {48, 16, 4},  {64
 
 static size_t chain_lds_bytes(const GroupCfg &g, int M, int sub, bool hg) {
   const int cpb = g.wpb * (64 / g.lpc);
-  const size_t per = (hg ? 0 : (size_t)g.kcap * g.kcap) + 5 * (size_t)g.kcap + 24 + (2 * (size_t)g.kcap + 2) / 2;
-  return sizeof(double) * ((size_t)M * (1 + sub) + (size_t)cpb * per);
+  const size_t per = (hg ? 0 : (size_t)g.kcap * g.kcap) + 4 * (size_t)g.kcap + 24 + (2 * (size_t)g.kcap + 2) / 2;
+  return sizeof(double) * ((size_t)M * (1 + sub) + (size_t)g.kcap + 2 + (size_t)cpb * per);
 }
 
 bool chain_kcap_supported(int kcap, int M, int sub) {
