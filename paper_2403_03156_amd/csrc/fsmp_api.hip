@@ -155,6 +155,7 @@ struct fsmp_ctx {
   DevBuf<double> lane_d;
   DevBuf<int32_t> lane_i;
   DevBuf<double> draw_scr;  // charge draws: KCAP^2 FP64 words per chain
+  DevBuf<double> ptab;      // light-curve partial-sum factors (ModelDev::ptab)
   // per PE capacity (kCaps), FSMP_DESIGN_*: 0 = lane group per chain, H in LDS
   // (capacities up to 64); 1 = one lane per chain, state in device memory; 2 = lane group
   // per chain, H in device memory.  Defaults from the batched 100k-waveform measurement:
@@ -282,6 +283,33 @@ void fill_model(fsmp_ctx *c) {
   md.logJ = std::log(cf.jump_J);
 }
 
+// Table of 1 - e^{-k dt / tau} (tau2, then tau12; 0 for EXP) for k = 0 .. n - 1, n >= need:
+// the count-dependent factors of the light curve's partial sums.  Grown (never shrunk) when
+// a batch has a longer solution space; earlier launches of this context are waited for
+// before the old table is released.
+hipError_t ensure_ptab(fsmp_ctx *c, int64_t need) {
+  if (c->md.ptab && c->md.ptab_n >= need) return hipSuccess;
+  const int64_t n = std::max<int64_t>(need, 4 * 4096 + 1);
+  std::vector<double> h(2 * (size_t)n);
+  for (int64_t k = 0; k < n; ++k) {
+    const double kdt = (double)k * c->md.dt;
+    h[2 * k] = -std::expm1(-kdt * c->md.inv_tau2);
+    h[2 * k + 1] = c->md.kind == FSMP_PHI_EXP ? 0.0 : -std::expm1(-kdt * c->md.inv_tau12);
+  }
+  (void)hipDeviceSynchronize();
+  c->ptab.release();
+  hipError_t e = c->ptab.ensure(2 * (size_t)n);
+  if (e == hipSuccess) e = hipMemcpy(c->ptab.p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    c->md.ptab = nullptr;
+    c->md.ptab_n = 0;
+    return e;
+  }
+  c->md.ptab = c->ptab.p;
+  c->md.ptab_n = n;
+  return hipSuccess;
+}
+
 hipEvent_t pool_event(fsmp_ctx *c, size_t i) {
   while (c->evpool.size() <= i) {
     hipEvent_t e;
@@ -351,6 +379,7 @@ fsmp_status fsmp_create(fsmp_ctx **out, const fsmp_ser *ser, const fsmp_intensit
   if (e == hipSuccess)
     e = hipMemcpy(c->d_ovl, c->tab.ovl.data(), sizeof(double) * c->tab.ovl.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = ensure_ptab(c, 0);
   (void)hipSetDevice(prev);
   if (e != hipSuccess) {
     fsmp_destroy(c);
@@ -392,6 +421,7 @@ void fsmp_destroy(fsmp_ctx *c) {
   c->wflags.release();
   c->lane_d.release();
   c->draw_scr.release();
+  c->ptab.release();
   c->lane_i.release();
   c->stage.release();
   (void)hipSetDevice(prev);
@@ -556,6 +586,11 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
       draw_off[bi + 1] = draw_off[bi] + (size_t)((cnt + 63) / 64 * 64) * caps[bi] * caps[bi];
     }
     if (e == hipSuccess && draw_off[kNumCaps] > 0) e = c->draw_scr.ensure(draw_off[kNumCaps]);
+  }
+  if (e == hipSuccess) {
+    int64_t tmax = 0;
+    for (int64_t i = 0; i < n; ++i) tmax = std::max<int64_t>(tmax, (int64_t)gr[2 * i + 1] - gr[2 * i] + 1);
+    e = ensure_ptab(c, tmax + 1);
   }
   if (e != hipSuccess) {
     (void)hipSetDevice(prev);

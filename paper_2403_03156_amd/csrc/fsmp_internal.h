@@ -24,6 +24,9 @@ struct ModelDev {
   // t0 prior and proposals
   double t0_min, t0_max, t0_sd, shift_sd;
   double J, logJ;
+  // [k][2]: 1 - e^{-k dt / tau2}, 1 - e^{-k dt / tau12} for k = 0 .. ptab_n - 1 (device)
+  const double *ptab;
+  int64_t ptab_n;
 };
 
 struct ChainArgs {

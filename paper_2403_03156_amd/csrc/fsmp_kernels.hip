@@ -86,12 +86,29 @@ __device__ inline double log_phi(const ModelDev &md, double x) {
   return md.logC - x * md.inv_tau2 + log(-expm1(-x * md.inv_tau1));
 }
 
-// sum of phi over the first k grid points of T at or after t0 (geometric series)
-__device__ inline double phi_partial(const ModelDev &md, double xs, int64_t k) {
-  const double kdt = (double)k * md.dt;
-  const double a = exp(-xs * md.inv_tau2) * (-expm1(-kdt * md.inv_tau2)) / md.den2;
+// The partial sums of phi over the grid points at or after t0 are geometric series:
+// with xs = (first point) dt - t0, the sum over the first k points is
+//   EXP:   e^{-xs/tau2} (1 - e^{-k dt/tau2}) / (1 - e^{-dt/tau2}) / tau2,
+//   BIEXP: C [e^{-xs/tau2} (1 - e^{-k dt/tau2}) / (1 - e^{-dt/tau2})
+//             - e^{-xs/tau12} (1 - e^{-k dt/tau12}) / (1 - e^{-dt/tau12})].
+// The t0-dependent factors are computed once per use (XsExp); the count-dependent ones,
+// 1 - e^{-k dt/tau}, come from the table md.ptab ([k][2], k up to the longest T), which
+// turns each evaluation of a search into two loads.
+struct XsExp {
+  double e2, e12;
+};
+
+__device__ inline XsExp xs_exp(const ModelDev &md, double xs) {
+  XsExp x;
+  x.e2 = exp(-xs * md.inv_tau2);
+  x.e12 = md.kind == FSMP_PHI_EXP ? 0.0 : exp(-xs * md.inv_tau12);
+  return x;
+}
+
+__device__ inline double phi_partial(const ModelDev &md, const XsExp &x, int64_t k) {
+  const double a = x.e2 * md.ptab[2 * k] / md.den2;
   if (md.kind == FSMP_PHI_EXP) return a * md.inv_tau2;
-  const double b = exp(-xs * md.inv_tau12) * (-expm1(-kdt * md.inv_tau12)) / md.den12;
+  const double b = x.e12 * md.ptab[2 * k + 1] / md.den12;
   return md.C * (a - b);
 }
 
@@ -113,7 +130,7 @@ __device__ inline GridPos grid_pos(const ModelDev &md, double t0, int glo, int g
 
 __device__ inline double phi_total(const ModelDev &md, double t0, int glo, int ghi) {
   const GridPos p = grid_pos(md, t0, glo, ghi);
-  return p.n > 0 ? phi_partial(md, p.xs, p.n) : 0.0;
+  return p.n > 0 ? phi_partial(md, xs_exp(md, p.xs), p.n) : 0.0;
 }
 
 template <int W>
@@ -169,6 +186,7 @@ __device__ inline double overlap(const ModelDev &md, const double *vt, const dou
 template <int LPC>
 __device__ inline int birth_draw(const ModelDev &md, double t0, int glo, int ghi, double target, int lane, int grp) {
   const GridPos p = grid_pos(md, t0, glo, ghi);
+  const XsExp xe = xs_exp(md, p.xs);
   int64_t k;
   if (md.kind == FSMP_PHI_EXP) {
     // closed-form inverse of the truncated geometric law
@@ -181,8 +199,8 @@ __device__ inline int birth_draw(const ModelDev &md, double t0, int glo, int ghi
       if (k < 0) k = 0;
       if (k > p.n - 1) k = p.n - 1;
       // settle rounding at the boundary against the partial sums
-      if (k > 0 && phi_partial(md, p.xs, k) > target) k -= 1;
-      else if (k < p.n - 1 && !(phi_partial(md, p.xs, k + 1) > target)) k += 1;
+      if (k > 0 && phi_partial(md, xe, k) > target) k -= 1;
+      else if (k < p.n - 1 && !(phi_partial(md, xe, k + 1) > target)) k += 1;
     }
   } else {
     // LPC-ary search on the closed-form partial sums
@@ -193,7 +211,7 @@ __device__ inline int birth_draw(const ModelDev &md, double t0, int glo, int ghi
       const int64_t step = (span + LPC - 1) / LPC;
       int64_t kl = lo + (int64_t)(lane + 1) * step - 1;
       if (kl > hi) kl = hi;
-      const bool pred = phi_partial(md, p.xs, kl + 1) > target;
+      const bool pred = phi_partial(md, xe, kl + 1) > target;
       const uint64_t bal = (__ballot(pred) >> (grp * LPC)) & gmask;
       if (bal == 0) {
         lo = hi;
@@ -740,6 +758,7 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
 // closed-form partial sums (same rule as birth_draw: smallest g with F(g) > target)
 __device__ inline int birth_draw_lane(const ModelDev &md, double t0, int glo, int ghi, double target) {
   const GridPos p = grid_pos(md, t0, glo, ghi);
+  const XsExp xe = xs_exp(md, p.xs);
   int64_t k;
   if (md.kind == FSMP_PHI_EXP) {
     const double c = target * exp(p.xs * md.inv_tau2) * md.den2 / md.inv_tau2;
@@ -750,8 +769,8 @@ __device__ inline int birth_draw_lane(const ModelDev &md, double t0, int glo, in
       k = (int64_t)floor(L);
       if (k < 0) k = 0;
       if (k > p.n - 1) k = p.n - 1;
-      if (k > 0 && phi_partial(md, p.xs, k) > target) k -= 1;
-      else if (k < p.n - 1 && !(phi_partial(md, p.xs, k + 1) > target)) k += 1;
+      if (k > 0 && phi_partial(md, xe, k) > target) k -= 1;
+      else if (k < p.n - 1 && !(phi_partial(md, xe, k + 1) > target)) k += 1;
     }
   } else {
     // bisection: the same number of steps in every lane (a Newton inverse with per-lane
@@ -759,7 +778,7 @@ __device__ inline int birth_draw_lane(const ModelDev &md, double t0, int glo, in
     int64_t lo = 0, hi = p.n - 1;
     while (lo < hi) {
       const int64_t mid = lo + (hi - lo) / 2;
-      if (phi_partial(md, p.xs, mid + 1) > target) hi = mid;
+      if (phi_partial(md, xe, mid + 1) > target) hi = mid;
       else lo = mid + 1;
     }
     k = lo;
