@@ -968,8 +968,8 @@ struct MvResult {
 
 template <int KCAP, typename MT>
 __device__ inline MvResult lane_propose(const ModelDev &md, const MT *Mp, const double *S1, double *S2,
-                                        const double *Xp, int N, int move, int j, double d, double beta, double Lam,
-                                        double la_ratio) {
+                                        const double *Xp, int N, int move, int j, double d, double beta, double logLam,
+                                        double logN1, double la_ratio) {
   MvResult r;
   r.valid = false;
   r.dnu = 0.0;
@@ -984,7 +984,7 @@ __device__ inline MvResult lane_propose(const ModelDev &md, const MT *Mp, const 
     r.up = beta - p;
     if (r.delta2 > 0.0) {
       r.dnu = -0.5 * (-md.log_rho + log(r.delta2) + (md.rhom2 - r.up * r.up / r.delta2) * md.inv_s);
-      r.la = r.dnu + log(Lam) - log((double)(N + 1)) + (N == 0 ? md.logJ : 0.0);
+      r.la = r.dnu + logLam - logN1 + (N == 0 ? md.logJ : 0.0);
       r.valid = true;
     }
   } else {
@@ -1015,6 +1015,8 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
   double *ov = smem + md.M;
   for (int i = threadIdx.x; i < md.M; i += blockDim.x) vt[i] = a.vtab[i];
   for (int i = threadIdx.x; i < md.sub * md.M; i += blockDim.x) ov[i] = a.ovl[i];
+  double *lgn = ov + md.sub * md.M;  // log k, k = 0..KCAP + 1
+  for (int i = threadIdx.x; i < KCAP + 2; i += blockDim.x) lgn[i] = log((double)i);
   __syncthreads();
   const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= a.n_list) return;
@@ -1060,6 +1062,7 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
   int gmin = INT32_MAX;  // smallest PE grid index (phi must stay positive at every PE)
   double S_cur = 0.0;    // BIEXP: sum_k log(1 - e^{-(t_k - t0)/tau_rise})
   double Phi = (glo <= ghi) ? phi_total(md, t0, glo, ghi) : 0.0;
+  double logLam = log(lam * md.dt * Phi);  // changes only with t0
   double acc[12];
 #pragma unroll
   for (int i = 0; i < 12; ++i) acc[i] = 0.0;
@@ -1101,6 +1104,7 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
         if (log(u01(r[2])) < la0) {
           t0 = t0p;
           Phi = Phip;
+          logLam = log(lam * md.dt * Phi);
           S_cur = S_new;
           t0acc = true;
           cnt[1]++;
@@ -1133,7 +1137,7 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
         xj = XV(j);
         if (om > 0.0) {
           dnu = 0.5 * (-md.log_rho - log(om) + (md.rhom2 - xj * xj / om) * md.inv_s);
-          la = dnu - log(Lam) + log((double)N) - (N == 1 ? md.logJ : 0.0);
+          la = dnu - logLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
           valid = true;
         } else {
           st |= FSMP_ST_FACTOR;
@@ -1163,7 +1167,8 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
       dself = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
       beta = mf[gnew - glo] + md.rhom;
       wk0 += (double)N * N;
-      const MvResult mr = lane_propose<KCAP, HT>(md, Hp, S1, S2, Xp, N, move, j, dself, beta, Lam, la_ratio);
+      const MvResult mr =
+          lane_propose<KCAP, HT>(md, Hp, S1, S2, Xp, N, move, j, dself, beta, logLam, lgn[N + 1], la_ratio);
       valid = mr.valid;
       dnu = mr.dnu;
       la = mr.la;
@@ -1183,7 +1188,8 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
       if (N > 0 && lane_refresh<KCAP, HT>(md, vt, ov, Lw, Wp, Hp, Xp, Bp, S1, S2, Zp, N, drift)) {
         if (need_mv) {
           for (int i = 0; i < N; ++i) G1(i) = (i == j) ? 0.0 : overlap(md, vt, ov, gnew, ZG(i), Lw);
-          const MvResult mr = lane_propose<KCAP, double>(md, Wp, S1, S2, Xp, N, move, j, dself, beta, Lam, la_ratio);
+          const MvResult mr =
+              lane_propose<KCAP, double>(md, Wp, S1, S2, Xp, N, move, j, dself, beta, logLam, lgn[N + 1], la_ratio);
           valid = mr.valid;
           dnu = mr.dnu;
           la = mr.la;
@@ -1196,7 +1202,7 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
           om = Wp[(j * KCAP + j) * 64];
           xj = XV(j);
           dnu = 0.5 * (-md.log_rho - log(om) + (md.rhom2 - xj * xj / om) * md.inv_s);
-          la = dnu - log(Lam) + log((double)N) - (N == 1 ? md.logJ : 0.0);
+          la = dnu - logLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
         }
       } else if (N > 0) {
         st |= FSMP_ST_FACTOR;
@@ -1443,7 +1449,7 @@ hipError_t launch_chain_t(const ChainArgs &a, hipStream_t st, int32_t *lanes, in
 template <int KCAP, typename HT>
 hipError_t launch_chain_lane_t(const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
   const int64_t nb = (a.n_list + 255) / 256;
-  const size_t lds = sizeof(double) * ((size_t)a.md.M * (1 + a.md.sub));
+  const size_t lds = sizeof(double) * ((size_t)a.md.M * (1 + a.md.sub) + KCAP + 2);
   *lanes = 1;
   *blocks = nb;
   if (nb == 0) return hipSuccess;
