@@ -315,7 +315,7 @@ __device__ inline void grp_col_update(double *H, int i, int N, double ai, const 
 // (t0 after the half-step, move, index, grid point, accept bit) instead of the chain's
 // own draws, and writes the delta-nu and log-acceptance it computes to a.rdnu / a.rla.
 template <int KCAP, int LPC, int WPB, bool HG, bool FORCE>
-__global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
+__global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu(2))) chain_kernel(ChainArgs a) {
   constexpr int CPW = kWave / LPC;
   using CL = ChainLayout<KCAP, HG>;
   constexpr int LD = CL::LD;
@@ -438,41 +438,20 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
     const bool consider =
         !FORCE || ((rec.flags & 1) && (move == 1 ? (rec.g >= glo && rec.g <= ghi)
                                                  : (move == 2 || move == 3) && rec.j >= 0 && rec.j < N));
+    // A wavefront carries several chains whose moves differ; the expensive parts are
+    // written once so that it executes them once: the proposal evaluation shared by
+    // births and time shifts, and one rank-two edit for every accepted move.
     int j = -1, gnew = -1, sh = 0;
-    bool valid = false;
-    double dnu = 0.0, la = -INFINITY;
-    double delta2 = 1.0, up = 0.0, om = 1.0, xj = 0.0, ej = 0.0, beta = 0.0;
+    bool valid = false, need_mv = false;
+    double dnu = 0.0, la = -INFINITY, lpn = 0.0, lpo = 0.0;
+    double delta2 = 1.0, up = 0.0, om = 1.0, xj = 0.0, ej = 0.0;
     if (move == 1) {
       if (lane == 0) cnt[2]++;
       if (N >= kmax) {
         st |= FSMP_ST_KMAX;
       } else if (Phi > 0.0 && consider) {
         gnew = FORCE ? rec.g : birth_draw<LPC>(md, t0, glo, ghi, u53(r[4], r[5]) * Phi, lane, grp);
-        if (Lam > 0.0) {
-          for (int i = lane; i < N; i += LPC) s1[i] = overlap(md, vt, ov, gnew, zg[i], Lw);
-          const double d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
-          beta = mf[gnew - glo] + md.rhom;
-          WAVE_SYNC();
-          if (lane == 0) acc[15] += (double)N * N;
-          double q = 0.0, p = 0.0;
-          for (int i = lane; i < N; i += LPC) {
-            const double e = grp_col_dot<LD, HS>(H, s1, i, N);
-            s2[i] = e;
-            q += s1[i] * e;
-            p += s1[i] * xv[i];
-          }
-          q = group_sum<LPC>(q);
-          p = group_sum<LPC>(p);
-          delta2 = d - q;
-          if (delta2 > 0.0) {
-            up = beta - p;
-            dnu = -0.5 * (-md.log_rho + log(delta2) + (md.rhom2 - up * up / delta2) * md.inv_s);
-            la = dnu + logLam - lgn[N + 1] + (N == 0 ? md.logJ : 0.0);
-            valid = true;
-          } else {
-            st |= FSMP_ST_FACTOR;
-          }
-        }
+        need_mv = Lam > 0.0;
       }
     } else {
       j = FORCE ? rec.j : (int)(((uint64_t)r[4] * (uint64_t)N) >> 32);
@@ -494,43 +473,61 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
         sh = FORCE ? rec.g - zg[j] : (int)rint(xi_sh * md.shift_sd / md.dt);
         gnew = zg[j] + sh;
         if (gnew >= glo && gnew <= ghi) {
-          const double lpn = log_phi(md, (double)gnew * md.dt - t0);
+          lpn = log_phi(md, (double)gnew * md.dt - t0);
           if (lpn > -INFINITY) {
-            const double lpo = log_phi(md, (double)zg[j] * md.dt - t0);
+            lpo = log_phi(md, (double)zg[j] * md.dt - t0);
             if (sh == 0) {
               valid = true;
               dnu = 0.0;
               la = lpn - lpo;
             } else {
-              for (int i = lane; i < N; i += LPC) s1[i] = (i == j) ? 0.0 : overlap(md, vt, ov, gnew, zg[i], Lw);
-              const double d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
-              beta = mf[gnew - glo] + md.rhom;
-              WAVE_SYNC();
-              if (lane == 0) acc[15] += (double)N * N;
-              double q = 0.0, p = 0.0;
-              for (int i = lane; i < N; i += LPC) {
-                const double e = grp_col_dot<LD, HS>(H, s1, i, N);
-                s2[i] = e;
-                q += s1[i] * e;
-                p += s1[i] * xv[i];
-              }
-              q = group_sum<LPC>(q);
-              p = group_sum<LPC>(p);
-              WAVE_SYNC();
-              om = H[(j * LD + j) * HS];
-              xj = xv[j];
-              ej = s2[j];
-              delta2 = d - (q - ej * ej / om);
-              up = beta - (p - ej * xj / om);
-              if (delta2 > 0.0 && om > 0.0) {
-                dnu = 0.5 * (-log(om) - log(delta2) + (up * up / delta2 - xj * xj / om) * md.inv_s);
-                la = dnu + lpn - lpo;
-                valid = true;
-              } else {
-                st |= FSMP_ST_FACTOR;
-              }
+              need_mv = true;
             }
           }
+        }
+      }
+    }
+    if (need_mv) {
+      // gamma = overlaps of the new position with the PEs (zero at the shifted one),
+      // eta = H gamma, q = gamma^T eta, p = gamma^T x
+      const int jz = move == 3 ? j : -1;
+      for (int i = lane; i < N; i += LPC) s1[i] = (i == jz) ? 0.0 : overlap(md, vt, ov, gnew, zg[i], Lw);
+      const double d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
+      const double beta = mf[gnew - glo] + md.rhom;
+      WAVE_SYNC();
+      if (lane == 0) acc[15] += (double)N * N;
+      double q = 0.0, p = 0.0;
+      for (int i = lane; i < N; i += LPC) {
+        const double e = grp_col_dot<LD, HS>(H, s1, i, N);
+        s2[i] = e;
+        q += s1[i] * e;
+        p += s1[i] * xv[i];
+      }
+      q = group_sum<LPC>(q);
+      p = group_sum<LPC>(p);
+      if (move == 1) {
+        delta2 = d - q;
+        if (delta2 > 0.0) {
+          up = beta - p;
+          dnu = -0.5 * (-md.log_rho + log(delta2) + (md.rhom2 - up * up / delta2) * md.inv_s);
+          la = dnu + logLam - lgn[N + 1] + (N == 0 ? md.logJ : 0.0);
+          valid = true;
+        } else {
+          st |= FSMP_ST_FACTOR;
+        }
+      } else {
+        WAVE_SYNC();
+        om = H[(j * LD + j) * HS];
+        xj = xv[j];
+        ej = s2[j];
+        delta2 = d - (q - ej * ej / om);
+        up = beta - (p - ej * xj / om);
+        if (delta2 > 0.0 && om > 0.0) {
+          dnu = 0.5 * (-log(om) - log(delta2) + (up * up / delta2 - xj * xj / om) * md.inv_s);
+          la = dnu + lpn - lpo;
+          valid = true;
+        } else {
+          st |= FSMP_ST_FACTOR;
         }
       }
     }
@@ -544,96 +541,90 @@ __global__ void __launch_bounds__(kWave *WPB) chain_kernel(ChainArgs a) {
         if (move == 1 || move == 2) acc[16] += (double)N * N;
         else if (sh != 0) acc[17] += (double)N * N;
       }
-      if (move == 1) {
-        const double inv_d2 = 1.0 / delta2;
+      const bool shift = move == 3 && sh != 0;  // an accepted zero shift changes nothing
+      if (move != 3 || shift) {
+        const double inv_d2 = move == 2 ? 0.0 : 1.0 / delta2;
+        const double inv_om = move == 1 ? 0.0 : 1.0 / om;
         const double xn = up * inv_d2;
-        for (int i = lane; i < N; i += LPC) {
-          const double ei = s2[i];
-          xv[i] -= ei * xn;
-          grp_col_update<LD, HS, false>(H, i, N, ei, s2, inv_d2, 0.0, nullptr, 0.0);
-          H[(N * LD + i) * HS] = -ei * inv_d2;
-          H[(i * LD + N) * HS] = -ei * inv_d2;
-        }
-        if (lane == 0) {
-          H[(N * LD + N) * HS] = inv_d2;
-          zg[N] = gnew;
-          xv[N] = xn;
-        }
-        N++;
-        if (biexp) S_cur += rise_term(md, gnew, t0);
-        gmin = gnew < gmin ? gnew : gmin;
-        WAVE_SYNC();
-      } else if (move == 2) {
-        const int gj = zg[j];
-        const double inv_om = 1.0 / om;
-        for (int i = lane; i < N; i += LPC) s3[i] = H[(j * LD + i) * HS];
-        WAVE_SYNC();
-        for (int i = lane; i < N; i += LPC) {
-          const double hi = s3[i];
-          xv[i] -= hi * xj * inv_om;
-          grp_col_update<LD, HS, false>(H, i, N, hi, s3, -inv_om, 0.0, nullptr, 0.0);
-        }
-        WAVE_SYNC();
-        const int last = N - 1;
-        if (j != last) {
-          for (int i = lane; i < N; i += LPC) s3[i] = H[(last * LD + i) * HS];
+        const int gj = move == 1 ? -1 : zg[j];
+        if (move != 1) {
+          for (int i = lane; i < N; i += LPC) s3[i] = H[(j * LD + i) * HS];  // h = row j of H
           WAVE_SYNC();
-          const double vd = s3[last];
-          for (int i = lane; i < N; i += LPC) {
-            if (i == j) {
-              H[(j * LD + j) * HS] = vd;
-            } else {
-              H[(j * LD + i) * HS] = s3[i];
-              H[(i * LD + j) * HS] = s3[i];
+        }
+        if (shift) {
+          for (int i = lane; i < N; i += LPC) s2[i] = (i == j) ? 0.0 : s2[i] - s3[i] * ej * inv_om;
+          WAVE_SYNC();
+        }
+        // H(k, i) += cu u_i u_k + cv v_i v_k for i, k < N:
+        //   birth: u = eta, cu = 1/delta^2; death: u = h, cu = -1/omega;
+        //   shift: u = h, cu = -1/omega, and v = eta (zero at j), cv = 1/delta^2
+        const double *U = move == 1 ? s2 : s3;
+        const double *V = shift ? s2 : U;
+        const double cu = move == 1 ? inv_d2 : -inv_om, cv = shift ? inv_d2 : 0.0;
+        for (int i = lane; i < N; i += LPC) {
+          const double ui = U[i], vi = V[i];
+          if (move == 1) xv[i] -= ui * xn;
+          else if (move == 2) xv[i] -= ui * xj * inv_om;
+          else xv[i] = (i == j) ? xn : xv[i] - ui * xj * inv_om - vi * xn;
+          grp_col_update<LD, HS, true>(H, i, N, ui, U, cu, vi, V, cv);
+          if (move == 1) {
+            H[(N * LD + i) * HS] = -ui * inv_d2;
+            H[(i * LD + N) * HS] = -ui * inv_d2;
+          }
+        }
+        WAVE_SYNC();
+        if (move == 1) {
+          if (lane == 0) {
+            H[(N * LD + N) * HS] = inv_d2;
+            zg[N] = gnew;
+            xv[N] = xn;
+          }
+          N++;
+          if (biexp) S_cur += rise_term(md, gnew, t0);
+          gmin = gnew < gmin ? gnew : gmin;
+        } else if (move == 2) {
+          const int last = N - 1;
+          if (j != last) {
+            for (int i = lane; i < N; i += LPC) s3[i] = H[(last * LD + i) * HS];
+            WAVE_SYNC();
+            const double vd = s3[last];
+            for (int i = lane; i < N; i += LPC) {
+              if (i == j) {
+                H[(j * LD + j) * HS] = vd;
+              } else {
+                H[(j * LD + i) * HS] = s3[i];
+                H[(i * LD + j) * HS] = s3[i];
+              }
+            }
+            if (lane == 0) {
+              zg[j] = zg[last];
+              xv[j] = xv[last];
             }
           }
-          if (lane == 0) {
-            zg[j] = zg[last];
-            xv[j] = xv[last];
+          N--;
+          if (biexp) S_cur -= rise_term(md, gj, t0);
+        } else {
+          for (int i = lane; i < N; i += LPC) {
+            if (i == j) {
+              H[(j * LD + j) * HS] = inv_d2;
+            } else {
+              const double v = -s2[i] * inv_d2;
+              H[(j * LD + i) * HS] = v;
+              H[(i * LD + j) * HS] = v;
+            }
           }
-        }
-        N--;
-        WAVE_SYNC();
-        if (biexp) S_cur -= rise_term(md, gj, t0);
-        if (gj == gmin) {
-          int m = INT32_MAX;
-          for (int i = lane; i < N; i += LPC) m = zg[i] < m ? zg[i] : m;
-          gmin = group_min<LPC>(m);
-        }
-      } else if (sh != 0) {
-        const int gj = zg[j];
-        const double inv_om = 1.0 / om, inv_d2 = 1.0 / delta2;
-        const double xn = up * inv_d2;
-        for (int i = lane; i < N; i += LPC) s3[i] = H[(j * LD + i) * HS];
-        WAVE_SYNC();
-        for (int i = lane; i < N; i += LPC) s2[i] = (i == j) ? 0.0 : s2[i] - s3[i] * ej * inv_om;
-        WAVE_SYNC();
-        for (int i = lane; i < N; i += LPC) {
-          const double hi = s3[i], ei = s2[i];
-          xv[i] = (i == j) ? xn : xv[i] - hi * xj * inv_om - ei * xn;
-          grp_col_update<LD, HS, true>(H, i, N, -hi, s3, inv_om, ei, s2, inv_d2);
+          if (lane == 0) zg[j] = gnew;
+          if (biexp) S_cur += rise_term(md, gnew, t0) - rise_term(md, gj, t0);
         }
         WAVE_SYNC();
-        for (int i = lane; i < N; i += LPC) {
-          if (i == j) {
-            H[(j * LD + j) * HS] = inv_d2;
-          } else {
-            const double v = -s2[i] * inv_d2;
-            H[(j * LD + i) * HS] = v;
-            H[(i * LD + j) * HS] = v;
+        if (move != 1) {
+          if (move == 3 && gnew < gmin) {
+            gmin = gnew;
+          } else if (gj == gmin) {
+            int m = INT32_MAX;
+            for (int i = lane; i < N; i += LPC) m = zg[i] < m ? zg[i] : m;
+            gmin = group_min<LPC>(m);
           }
-        }
-        if (lane == 0) {
-          zg[j] = gnew;
-        }
-        WAVE_SYNC();
-        if (biexp) S_cur += rise_term(md, gnew, t0) - rise_term(md, gj, t0);
-        if (gnew < gmin) {
-          gmin = gnew;
-        } else if (gj == gmin) {
-          int m = INT32_MAX;
-          for (int i = lane; i < N; i += LPC) m = zg[i] < m ? zg[i] : m;
-          gmin = group_min<LPC>(m);
         }
       }
     }
