@@ -70,8 +70,10 @@ def parse():
 def kernel_label(name):
     """bench name of a chain / prologue kernel from its demangled rocprofv3 name"""
     import re
-    m = re.search(r"chain_kernel<(\d+), (\d+), (\d+), (true|false)>", name)
+    m = re.search(r"chain_kernel<(\d+), (\d+), (\d+), (true|false)(?:, (true|false))?>", name)
     if m:
+        if m.group(5) == "true":
+            return "chain_replay_k" + m.group(1)
         return ("chain_group_dm_k" if m.group(4) == "true" else "chain_group_k") + m.group(1)
     m = re.search(r"chain_lane_kernel<(\d+), (double|float)>", name)
     if m:
