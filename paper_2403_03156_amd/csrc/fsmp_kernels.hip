@@ -1204,76 +1204,82 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
     if (valid && logu < la) {
       accepted = true;
       cnt[2 * move + 1]++;
-      if (move == 1) {
-        wk1 += (double)N * N;
-        const double inv_d2 = 1.0 / delta2;
+      // One edit path for every accepted move (the wavefront's 64 chains run whichever
+      // moves they drew; one path is executed once): with h = row j of H and eta from the
+      // proposal, M(k, i) += cu u_i u_k + cv v_i v_k over i, k < N with
+      //   birth: u = eta, cu = 1/delta^2; death: u = h, cu = -1/omega;
+      //   shift: u = h, cu = -1/omega and v = eta (zero at j), cv = 1/delta^2.
+      const bool shift = move == 3 && sh != 0;  // an accepted zero shift changes nothing
+      if (move != 3 || shift) {
+        if (shift) wk2 += (double)N * N;
+        else wk1 += (double)N * N;
+        const double inv_d2 = move == 2 ? 0.0 : 1.0 / delta2;
+        const double inv_om = move == 1 ? 0.0 : 1.0 / om;
         const double xn = up * inv_d2;
-        lane_rank_update<KCAP, false, HT>(Hp, S2, inv_d2, nullptr, 0.0, N);
+        const int gj = move == 1 ? -1 : ZG(j);
+        if (move != 1) lane_copy(S3, Hp + (int64_t)j * KCAP * 64, N);  // h = row j of H
+        if (shift)
+          for (int i = 0; i < N; ++i) G2(i) = (i == j) ? 0.0 : G2(i) - G3(i) * ej * inv_om;
+        const double *U = move == 1 ? S2 : S3;
+        const double *V = shift ? S2 : U;
+        const double cu = move == 1 ? inv_d2 : -inv_om, cv = shift ? inv_d2 : 0.0;
         for (int i = 0; i < N; ++i) {
-          const double ei = G2(i);
-          XV(i) -= ei * xn;
-          HM(N, i) = (HT)(-ei * inv_d2);
-          HM(i, N) = (HT)(-ei * inv_d2);
+          const double ui = U[i * 64], vi = V[i * 64];
+          XV(i) = move == 1 ? XV(i) - ui * xn
+                  : move == 2 ? XV(i) - ui * xj * inv_om
+                              : ((i == j) ? xn : XV(i) - ui * xj * inv_om - vi * xn);
         }
-        HM(N, N) = (HT)inv_d2;
-        ZG(N) = gnew;
-        BV(N) = beta;
-        XV(N) = xn;
-        if (biexp) S_cur += log(-expm1(-((double)gnew * md.dt - t0) * md.inv_tau1));
-        gmin = gnew < gmin ? gnew : gmin;
-        N++;
-      } else if (move == 2) {
-        wk1 += (double)N * N;
-        const double inv_d = 1.0 / om;
-        const int gj = ZG(j);
-        lane_copy(S3, Hp + (int64_t)j * KCAP * 64, N);  // h = row j of H
-        lane_rank_update<KCAP, false, HT>(Hp, S3, -inv_d, nullptr, 0.0, N);
-        for (int i = 0; i < N; ++i) XV(i) -= G3(i) * xj * inv_d;
-        const int last = N - 1;
-        if (j != last) {
-          lane_copy(S3, Hp + (int64_t)last * KCAP * 64, N);  // row `last` moves into slot j
-          const double vd = G3(last);
-          lane_copy(Hp + (int64_t)j * KCAP * 64, S3, N);
-          for (int i = 0; i < N; ++i) HM(i, j) = (HT)G3(i);
-          HM(j, j) = (HT)vd;
-          ZG(j) = ZG(last);
-          BV(j) = BV(last);
-          XV(j) = XV(last);
-        }
-        N--;
-        if (biexp) S_cur -= log(-expm1(-((double)gj * md.dt - t0) * md.inv_tau1));
-        if (gj == gmin) {
-          gmin = INT32_MAX;
-          for (int i = 0; i < N; ++i) gmin = ZG(i) < gmin ? ZG(i) : gmin;
-        }
-      } else if (sh != 0) {
-        wk2 += (double)N * N;
-        const double inv_om = 1.0 / om, inv_d2 = 1.0 / delta2;
-        const double xn = up * inv_d2;
-        const int gj = ZG(j);
-        lane_copy(S3, Hp + (int64_t)j * KCAP * 64, N);  // h = row j of H
-        for (int i = 0; i < N; ++i) G2(i) = (i == j) ? 0.0 : G2(i) - G3(i) * ej * inv_om;
-        for (int i = 0; i < N; ++i) XV(i) = (i == j) ? xn : XV(i) - G3(i) * xj * inv_om - G2(i) * xn;
-        lane_rank_update<KCAP, true, HT>(Hp, S3, -inv_om, S2, inv_d2, N);
-        for (int i = 0; i < N; ++i) {
-          if (i == j) {
-            HM(j, j) = (HT)inv_d2;
-          } else {
+        lane_rank_update<KCAP, true, HT>(Hp, U, cu, V, cv, N);
+        if (move == 1) {
+          for (int i = 0; i < N; ++i) {
             const double v = -G2(i) * inv_d2;
-            HM(j, i) = (HT)v;
-            HM(i, j) = (HT)v;
+            HM(N, i) = (HT)v;
+            HM(i, N) = (HT)v;
           }
+          HM(N, N) = (HT)inv_d2;
+          ZG(N) = gnew;
+          BV(N) = beta;
+          XV(N) = xn;
+          if (biexp) S_cur += log(-expm1(-((double)gnew * md.dt - t0) * md.inv_tau1));
+          gmin = gnew < gmin ? gnew : gmin;
+          N++;
+        } else if (move == 2) {
+          const int last = N - 1;
+          if (j != last) {
+            lane_copy(S3, Hp + (int64_t)last * KCAP * 64, N);  // row `last` moves into slot j
+            const double vd = G3(last);
+            lane_copy(Hp + (int64_t)j * KCAP * 64, S3, N);
+            for (int i = 0; i < N; ++i) HM(i, j) = (HT)G3(i);
+            HM(j, j) = (HT)vd;
+            ZG(j) = ZG(last);
+            BV(j) = BV(last);
+            XV(j) = XV(last);
+          }
+          N--;
+          if (biexp) S_cur -= log(-expm1(-((double)gj * md.dt - t0) * md.inv_tau1));
+        } else {
+          for (int i = 0; i < N; ++i) {
+            if (i == j) {
+              HM(j, j) = (HT)inv_d2;
+            } else {
+              const double v = -G2(i) * inv_d2;
+              HM(j, i) = (HT)v;
+              HM(i, j) = (HT)v;
+            }
+          }
+          ZG(j) = gnew;
+          BV(j) = beta;
+          if (biexp)
+            S_cur += log(-expm1(-((double)gnew * md.dt - t0) * md.inv_tau1)) -
+                     log(-expm1(-((double)gj * md.dt - t0) * md.inv_tau1));
         }
-        ZG(j) = gnew;
-        BV(j) = beta;
-        if (biexp)
-          S_cur += log(-expm1(-((double)gnew * md.dt - t0) * md.inv_tau1)) -
-                   log(-expm1(-((double)gj * md.dt - t0) * md.inv_tau1));
-        if (gnew < gmin) {
-          gmin = gnew;
-        } else if (gj == gmin) {
-          gmin = INT32_MAX;
-          for (int i = 0; i < N; ++i) gmin = ZG(i) < gmin ? ZG(i) : gmin;
+        if (move != 1) {
+          if (move == 3 && gnew < gmin) {
+            gmin = gnew;
+          } else if (gj == gmin) {
+            gmin = INT32_MAX;
+            for (int i = 0; i < N; ++i) gmin = ZG(i) < gmin ? ZG(i) : gmin;
+          }
         }
       }
     }
