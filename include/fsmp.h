@@ -170,7 +170,7 @@ typedef struct {
  *                         words 0 and 1: cosine for even k, sine for odd k); 0 beyond N, NaN
  *                         (with FSMP_ST_FACTOR) if the factorisation fails.  The draw reads
  *                         the maintained G^-1 (FP32 in the precision form).  Costs O(K^3)
- *                         per record; FP64 scratch of kcap^2 words per chain is allocated
+ *                         per record; FP64 scratch of kcap (kcap + 1) words per chain is allocated
  *                         by fsmp_sample while the flag is set. */
 typedef struct {
   int32_t *n_pe;

@@ -154,7 +154,7 @@ struct fsmp_ctx {
   DevBuf<uint32_t> wflags;
   DevBuf<double> lane_d;
   DevBuf<int32_t> lane_i;
-  DevBuf<double> draw_scr;  // charge draws: KCAP^2 FP64 words per chain
+  DevBuf<double> draw_scr;  // charge draws: KCAP (KCAP + 1) FP64 words per chain
   DevBuf<double> ptab;      // light-curve partial-sum factors (ModelDev::ptab)
   // per PE capacity (kCaps), FSMP_DESIGN_*: 0 = lane group per chain, H in LDS
   // (capacities up to 64); 1 = one lane per chain, state in device memory; 2 = lane group
@@ -583,7 +583,7 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   if (cf.record_flags & FSMP_REC_CHARGE) {
     for (int bi = 0; bi < kNumCaps; ++bi) {
       const int64_t cnt = bucket_start[bi + 1] - bucket_start[bi];
-      draw_off[bi + 1] = draw_off[bi] + (size_t)((cnt + 63) / 64 * 64) * caps[bi] * caps[bi];
+      draw_off[bi + 1] = draw_off[bi] + (size_t)((cnt + 63) / 64 * 64) * caps[bi] * (caps[bi] + 1);
     }
     if (e == hipSuccess && draw_off[kNumCaps] > 0) e = c->draw_scr.ensure(draw_off[kNumCaps]);
   }

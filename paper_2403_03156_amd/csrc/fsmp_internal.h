@@ -70,7 +70,7 @@ struct ChainArgs {
   int32_t refresh_M;
   double near_eps, drift_bound;
   // charge draws at recorded steps (optional): outputs [chain][n_rec][kz] and FP64
-  // scratch of KCAP^2 words per chain (per-chain rows for the lane-group kernels,
+  // scratch of KCAP (KCAP + 1) words per chain (per-chain rows for the lane-group kernels,
   // interleaved in tiles of 64 for the lane kernels)
   double *qdraw;
   int32_t *zdraw;

@@ -257,15 +257,17 @@ __global__ void __launch_bounds__(256) prologue_kernel(PrologueArgs a) {
 }
 
 // ------------------------------------------------------------------ chains
-// LDS block of one chain: H (unless it lives in device memory), x, three scratch
-// vectors, the accumulators (kAcc doubles: 12 sums, 3 open batch sums, 4 work counters,
-// then 8 int proposal / accept counts), then int grid indices and the N histogram.  The
-// accumulators live in LDS, updated by the group's first lane, to keep registers free.
+// LDS block of one chain: H (unless it lives in device memory), x, two scratch vectors,
+// the accumulators (kAcc doubles: 12 sums, 3 open batch sums, 4 work counters, one spare,
+// then 8 int proposal / accept counts and the current run of N: value, first step), then
+// the int grid indices.  The accumulators live in LDS,
+// updated by the group's first lane, to keep registers free; the N histogram is kept in
+// the output row by run lengths.
 template <int KCAP, bool HG>
 struct ChainLayout {
   static constexpr int LD = KCAP;
-  static constexpr int kAcc = 24;
-  static constexpr int kDoubles = (HG ? 0 : KCAP * KCAP) + 4 * KCAP + kAcc + (2 * KCAP + 2) / 2;
+  static constexpr int kAcc = 25;
+  static constexpr int kDoubles = (HG ? 0 : KCAP * KCAP) + 3 * KCAP + kAcc + (KCAP + 1) / 2;
 };
 
 // Column i of H owned by one lane: element (k, i) at H[(k * LD + i) * HS] (HS = 1 in LDS;
@@ -341,11 +343,10 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
   double *xv = HG ? cb : cb + KCAP * LD;
   double *s1 = xv + KCAP;
   double *s2 = s1 + KCAP;
-  double *s3 = s2 + KCAP;
-  double *acc = s3 + KCAP;  // [0..11] sums, [12..14] open batch sums, [15..18] work counters
+  double *acc = s2 + KCAP;  // [0..11] sums, [12..14] open batch sums, [15..18] work counters
   int *cnt = (int *)(acc + 20);
+  int *run = cnt + 8;  // N of the current run among the recorded steps (-1: none yet), its first step
   int *zg = (int *)(acc + CL::kAcc);
-  int *hist = zg + KCAP;
 
   const int64_t c = a.chains[slot];
   const int64_t w = c / a.n_chains;
@@ -361,7 +362,13 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
   if (glo > ghi) st |= FSMP_ST_EMPTY_T;
   const int n_steps = (st & FSMP_ST_NONFINITE) ? 0 : a.n_steps;
 
-  for (int k = lane; k <= KCAP; k += LPC) hist[k] = 0;
+  // N histogram: the output row, zeroed here, receives the length of every run of equal
+  // N among the recorded steps (atomic adds that nothing waits for)
+  for (int k = lane; k <= a.kz; k += LPC) a.nhist[c * (a.kz + 1) + k] = 0;
+  if (lane == 0) {
+    run[0] = -1;
+    run[1] = 0;
+  }
   WAVE_SYNC();
 
   double t0 = a.t0init[w];
@@ -548,17 +555,17 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         const double xn = up * inv_d2;
         const int gj = move == 1 ? -1 : zg[j];
         if (move != 1) {
-          for (int i = lane; i < N; i += LPC) s3[i] = H[(j * LD + i) * HS];  // h = row j of H
+          for (int i = lane; i < N; i += LPC) s1[i] = H[(j * LD + i) * HS];  // h = row j of H
           WAVE_SYNC();
         }
         if (shift) {
-          for (int i = lane; i < N; i += LPC) s2[i] = (i == j) ? 0.0 : s2[i] - s3[i] * ej * inv_om;
+          for (int i = lane; i < N; i += LPC) s2[i] = (i == j) ? 0.0 : s2[i] - s1[i] * ej * inv_om;
           WAVE_SYNC();
         }
         // H(k, i) += cu u_i u_k + cv v_i v_k for i, k < N:
         //   birth: u = eta, cu = 1/delta^2; death: u = h, cu = -1/omega;
         //   shift: u = h, cu = -1/omega, and v = eta (zero at j), cv = 1/delta^2
-        const double *U = move == 1 ? s2 : s3;
+        const double *U = move == 1 ? s2 : s1;
         const double *V = shift ? s2 : U;
         const double cu = move == 1 ? inv_d2 : -inv_om, cv = shift ? inv_d2 : 0.0;
         for (int i = lane; i < N; i += LPC) {
@@ -585,15 +592,15 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         } else if (move == 2) {
           const int last = N - 1;
           if (j != last) {
-            for (int i = lane; i < N; i += LPC) s3[i] = H[(last * LD + i) * HS];
+            for (int i = lane; i < N; i += LPC) s1[i] = H[(last * LD + i) * HS];
             WAVE_SYNC();
-            const double vd = s3[last];
+            const double vd = s1[last];
             for (int i = lane; i < N; i += LPC) {
               if (i == j) {
                 H[(j * LD + j) * HS] = vd;
               } else {
-                H[(j * LD + i) * HS] = s3[i];
-                H[(i * LD + j) * HS] = s3[i];
+                H[(j * LD + i) * HS] = s1[i];
+                H[(i * LD + j) * HS] = s1[i];
               }
             }
             if (lane == 0) {
@@ -672,7 +679,11 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
             acc[12] = acc[13] = acc[14] = 0.0;
           }
         }
-        hist[N] += 1;
+        if (N != run[0]) {
+          if (run[0] >= 0) atomicAdd(a.nhist + c * (a.kz + 1) + run[0], step - run[1]);
+          run[0] = N;
+          run[1] = step;
+        }
       }
       if (a.trace && a.thin > 0 && (i % a.thin) == 0 && lane == 0) {
         double *tr = a.trace + (c * a.n_rec + i / a.thin) * 3;
@@ -685,7 +696,8 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         // factorisation runs from the last PE backwards on a copy of H's lower triangle
         // in the chain's device-memory scratch; y = R xi accumulates column by column
         const int64_t rec = c * a.n_rec + i / a.thin;
-        double *Ad = a.dscr + slot * (int64_t)(KCAP * KCAP);
+        double *Ad = a.dscr + slot * (int64_t)(KCAP * KCAP + KCAP);
+        double *Av = Ad + KCAP * KCAP;  // the column being eliminated
         WAVE_SYNC();
         for (int r = lane; r < N; r += LPC) {
           for (int k = 0; k <= r; ++k) Ad[r * KCAP + k] = H[(k * LD + r) * HS];
@@ -703,14 +715,14 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
           const double d = sqrt(ajj), xij = s1[jj];
           for (int r = lane; r < jj; r += LPC) {
             const double v = Ad[jj * KCAP + r] / d;
-            s3[r] = v;
+            Av[r] = v;
             s2[r] += v * xij;
           }
           if (lane == 0) s2[jj] += d * xij;
           WAVE_SYNC();
           for (int r = lane; r < jj; r += LPC) {
-            const double vr = s3[r];
-            for (int k = 0; k <= r; ++k) Ad[r * KCAP + k] -= vr * s3[k];
+            const double vr = Av[r];
+            for (int k = 0; k <= r; ++k) Ad[r * KCAP + k] -= vr * Av[k];
           }
           WAVE_SYNC();
         }
@@ -730,7 +742,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
     a.z[c * kz + k] = k < N ? zg[k] : -1;
     a.charge[c * kz + k] = k < N ? xv[k] : 0.0;
   }
-  for (int k = lane; k <= kz; k += LPC) a.nhist[c * (kz + 1) + k] = k <= KCAP ? hist[k] : 0;
+  if (lane == 0 && run[0] >= 0) atomicAdd(a.nhist + c * (a.kz + 1) + run[0], n_steps - run[1]);
   if (lane == 0) {
     a.n_pe[c] = N;
     a.t0[c] = t0;
@@ -1484,12 +1496,12 @@ struct GroupCfg {
   int kcap, lpc, wpb;
 };
 static const GroupCfg kGroup[] = {{16, 16, 4}, {32, 32, 4}, {48, 64, 3}, {64, 64, 4}};
-static const GroupCfg kGroupDM[] = {{16, 4, 4},  {32, 8, 4},   {48, 16, 4},  {64, 32, 4},
+static const GroupCfg kGroupDM[] = {{16, 4, 4},  {32, 4, 8},   {48, 16, 4},  {64, 32, 4},
                                     {96, 16, 2}, {128, 32, 4}, {160, 32, 4}, {192, 32, 2}};
 
 static size_t chain_lds_bytes(const GroupCfg &g, int M, int sub, bool hg) {
   const int cpb = g.wpb * (64 / g.lpc);
-  const size_t per = (hg ? 0 : (size_t)g.kcap * g.kcap) + 4 * (size_t)g.kcap + 24 + (2 * (size_t)g.kcap + 2) / 2;
+  const size_t per = (hg ? 0 : (size_t)g.kcap * g.kcap) + 3 * (size_t)g.kcap + 25 + ((size_t)g.kcap + 1) / 2;
   return sizeof(double) * ((size_t)M * (1 + sub) + (size_t)g.kcap + 2 + (size_t)cpb * per);
 }
 
@@ -1569,7 +1581,7 @@ hipError_t launch_chain_dm(int kcap, const ChainArgs &a, hipStream_t st, int32_t
   if (a.force) {
     switch (kcap) {
       case 16: return launch_chain_t<16, 4, 4, true, true>(a, st, lanes, blocks);
-      case 32: return launch_chain_t<32, 8, 4, true, true>(a, st, lanes, blocks);
+      case 32: return launch_chain_t<32, 4, 8, true, true>(a, st, lanes, blocks);
       case 48: return launch_chain_t<48, 16, 4, true, true>(a, st, lanes, blocks);
       case 64: return launch_chain_t<64, 32, 4, true, true>(a, st, lanes, blocks);
       case 96: return launch_chain_t<96, 16, 2, true, true>(a, st, lanes, blocks);
@@ -1581,7 +1593,7 @@ hipError_t launch_chain_dm(int kcap, const ChainArgs &a, hipStream_t st, int32_t
   }
   switch (kcap) {
     case 16: return launch_chain_t<16, 4, 4, true>(a, st, lanes, blocks);
-    case 32: return launch_chain_t<32, 8, 4, true>(a, st, lanes, blocks);
+    case 32: return launch_chain_t<32, 4, 8, true>(a, st, lanes, blocks);
     case 48: return launch_chain_t<48, 16, 4, true>(a, st, lanes, blocks);
     case 64: return launch_chain_t<64, 32, 4, true>(a, st, lanes, blocks);
     case 96: return launch_chain_t<96, 16, 2, true>(a, st, lanes, blocks);
