@@ -119,7 +119,10 @@ typedef struct {
  * scale, eq. pzmu); kmax: host or NULL, PE cap per waveform (1..192); g_range: host or
  * NULL, [g_lo, g_hi] per waveform inside [0, grid_sub * L_w - 1] (g_lo > g_hi = empty T);
  * t0_init: host or NULL (default (t0_min + t0_max) / 2); wave_id: host or NULL, the
- * identity that keys the random stream (default: the index in the batch). */
+ * identity that keys the random stream (default: the index in the batch); n_steps: host
+ * or NULL, sweeps per waveform (1..cfg.n_steps; NULL = cfg.n_steps for all), each with
+ * burn-in floor(n_steps * cfg.burn_in / cfg.n_steps) -- it needs fsmp_samples.rec_steps
+ * so that fsmp_posterior divides by each chain's own number of recorded sweeps. */
 typedef struct {
   int64_t n_wave;
   const float *wave;
@@ -129,6 +132,7 @@ typedef struct {
   const int32_t *g_range;
   const double *t0_init;
   const uint64_t *wave_id;
+  const int32_t *n_steps;
 } fsmp_batch;
 
 /* One record per step of one chain (FSMP_REC_LOG). */
@@ -160,6 +164,9 @@ typedef struct {
  *                         proposals evaluated with a K x K mat-vec, sum of K^2 over rank-one
  *                         edits (accepted births and deaths), sum of K^2 over rank-two edits
  *                         (accepted updates), sum of K over t0 proposals inside the prior
+ *   rec_steps             NULL, or [chain] the number of recorded sweeps (after burn-in) of
+ *                         the chain; required with per-waveform sweep counts, read by
+ *                         fsmp_posterior when present
  *   qdraw, zdraw          NULL, or [chain][n_rec][kz] when FSMP_REC_CHARGE: at every recorded
  *                         step (the steps of `trace`) the PE grid indices (-1 beyond N) and one
  *                         draw of the charges from their conditional law given z (Sec. 2.1
@@ -187,6 +194,7 @@ typedef struct {
   double *work;
   double *qdraw;
   int32_t *zdraw;
+  int32_t *rec_steps;
 } fsmp_samples;
 
 /* Posterior summaries per waveform (device buffers, caller-allocated): for (N, Q, t0)
@@ -277,6 +285,17 @@ int32_t fsmp_get_design(const fsmp_ctx *ctx, int32_t capacity);
  * Allocates scratch outputs for the trial and synchronises `hip_stream`.  A no-op for the
  * FP32-refresh form, which has the lane design only. */
 fsmp_status fsmp_autotune(fsmp_ctx *ctx, const fsmp_batch *batch, int32_t trial_steps, void *hip_stream);
+
+/* Chain-length autotuner: runs the batch once for pilot_steps sweeps (the configured
+ * burn-in fraction, outputs discarded), takes each waveform's batch-means MCSE of N from
+ * the pilot and writes to steps_out (host, n_wave) the sweeps that bring it to
+ * target_rel_mcse * max(1, mean N) under MCSE ~ 1 / sqrt(recorded sweeps), clamped to
+ * [min_steps, min(max_steps, cfg.n_steps)] (a waveform whose pilot shows no variation gets
+ * min_steps).  Pass the result as fsmp_batch.n_steps.  Allocates scratch and
+ * synchronises `hip_stream`.  The MCSE of a short pilot is itself noisy: the result is a
+ * budget, not a guarantee. */
+fsmp_status fsmp_autotune_steps(fsmp_ctx *ctx, const fsmp_batch *batch, int32_t pilot_steps, double target_rel_mcse,
+                                int32_t min_steps, int32_t max_steps, int32_t *steps_out, void *hip_stream);
 
 /* HIP graph of one batch: makes a private context with ctx's model, configuration and
  * designs, uploads the batch's metadata into it (synchronising `hip_stream`), records the

@@ -100,6 +100,10 @@ template <typename T>
 struct DevBuf {
   T *p = nullptr;
   size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
   hipError_t ensure(size_t want) {
     if (want <= n && p) return hipSuccess;
     if (p) (void)hipFree(p);
@@ -151,6 +155,7 @@ struct fsmp_ctx {
   DevBuf<double> lam, t0init, mf;
   DevBuf<int32_t> kmax, grange, chains;
   DevBuf<uint64_t> wid;
+  DevBuf<int32_t> wsteps;  // per-waveform sweeps (fsmp_batch.n_steps)
   DevBuf<uint32_t> wflags;
   DevBuf<double> lane_d;
   DevBuf<int32_t> lane_i;
@@ -475,6 +480,8 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     return fail(c, FSMP_EINVAL, "an output buffer is NULL");
   if ((cf.record_flags & FSMP_REC_LOG) && !o->log) return fail(c, FSMP_EINVAL, "FSMP_REC_LOG set but log is NULL");
   if ((cf.record_flags & FSMP_REC_TRACE) && !o->trace) return fail(c, FSMP_EINVAL, "FSMP_REC_TRACE set but trace is NULL");
+  if (n > 0 && b->n_steps && !o->rec_steps)
+    return fail(c, FSMP_EINVAL, "per-waveform n_steps needs fsmp_samples.rec_steps");
   if ((cf.record_flags & FSMP_REC_CHARGE) && (!o->qdraw || !o->zdraw))
     return fail(c, FSMP_EINVAL, "FSMP_REC_CHARGE set but qdraw or zdraw is NULL");
   if (n > 0 && b->offsets[0] != 0) return fail(c, FSMP_EINVAL, "offsets[0] must be 0");
@@ -496,6 +503,8 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     if (km > o->kz) return fail(c, FSMP_EINVAL, "waveform %lld: kmax %d exceeds the output row length kz %d", (long long)i, km, o->kz);
     kmx[i] = km;
     kmax_all = std::max(kmax_all, km);
+    if (b->n_steps && (b->n_steps[i] < 1 || b->n_steps[i] > cf.n_steps))
+      return fail(c, FSMP_EINVAL, "waveform %lld: n_steps %d outside 1..%d", (long long)i, b->n_steps[i], cf.n_steps);
     int lo = 0, hi = (int)(sub * L - 1);
     if (b->g_range) {
       lo = b->g_range[2 * i];
@@ -562,6 +571,7 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   if (e == hipSuccess) e = c->kmax.ensure(n);
   if (e == hipSuccess) e = c->grange.ensure(2 * n);
   if (e == hipSuccess) e = c->wid.ensure(n);
+  if (e == hipSuccess && b->n_steps) e = c->wsteps.ensure(n);
   if (e == hipSuccess) e = c->wflags.ensure(n);
   if (e == hipSuccess) e = c->mf.ensure((size_t)std::max<int64_t>(mfo[n], 1));
   if (e == hipSuccess) e = c->chains.ensure(order.size());
@@ -601,7 +611,7 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   auto pad16 = [](size_t nb) { return (nb + 15) & ~(size_t)15; };
   const size_t bytes = pad16(sizeof(int64_t) * (n + 1)) * 2 + pad16(sizeof(double) * n) * 2 +
                        pad16(sizeof(int32_t) * n) + pad16(sizeof(int32_t) * 2 * n) + pad16(sizeof(uint64_t) * n) +
-                       pad16(sizeof(int32_t) * order.size());
+                       pad16(sizeof(int32_t) * order.size()) + pad16(sizeof(int32_t) * n);
   e = c->stage.ensure(bytes);
   if (e != hipSuccess) {
     (void)hipSetDevice(prev);
@@ -622,6 +632,7 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   if (e == hipSuccess) e = put(c->grange.p, gr.data(), sizeof(int32_t) * 2 * n);
   if (e == hipSuccess) e = put(c->wid.p, wid.data(), sizeof(uint64_t) * n);
   if (e == hipSuccess) e = put(c->chains.p, order.data(), sizeof(int32_t) * order.size());
+  if (e == hipSuccess && b->n_steps) e = put(c->wsteps.p, b->n_steps, sizeof(int32_t) * n);
   if (e == hipSuccess) e = hipEventRecord(c->stage_done, st);
   c->stage_pending = (e == hipSuccess);
   if (e != hipSuccess) {
@@ -695,8 +706,8 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   ca.burn_in = cf.burn_in;
   ca.thin = cf.thin;
   const int S = cf.n_steps - cf.burn_in;
-  ca.nb = S > 0 ? (int)std::floor(std::sqrt((double)S)) : 0;
-  ca.lb = ca.nb > 0 ? S / ca.nb : 0;
+  ca.wsteps = b->n_steps ? c->wsteps.p : nullptr;
+  ca.rec_steps = o->rec_steps;
   ca.n_rec = (cf.thin > 0 && S > 0) ? (S + cf.thin - 1) / cf.thin : 0;
   ca.key0 = (uint32_t)cf.seed;
   ca.key1 = (uint32_t)(cf.seed >> 32);
@@ -901,6 +912,101 @@ fsmp_status fsmp_autotune(fsmp_ctx *c, const fsmp_batch *b, int32_t trial_steps,
 // The graph owns a private context: its kernels read that context's workspace
 // (uploaded batch metadata, chain lists, lane-design state), which later calls on the
 // caller's context may overwrite or reallocate without touching the graph.
+fsmp_status fsmp_autotune_steps(fsmp_ctx *c, const fsmp_batch *b, int32_t pilot_steps, double target_rel_mcse,
+                                int32_t min_steps, int32_t max_steps, int32_t *steps_out, void *hip_stream) {
+  if (!c) return FSMP_EINVAL;
+  if (!b || b->n_wave < 1 || !steps_out) return fail(c, FSMP_EINVAL, "steps autotuner needs a batch and steps_out");
+  if (pilot_steps < 4) return fail(c, FSMP_EINVAL, "pilot_steps must be >= 4");
+  if (!(target_rel_mcse > 0.0)) return fail(c, FSMP_EINVAL, "target_rel_mcse must be > 0");
+  if (min_steps < 1 || max_steps < min_steps) return fail(c, FSMP_EINVAL, "need 1 <= min_steps <= max_steps");
+  const int64_t n = b->n_wave;
+  int kz = 1;
+  for (int64_t i = 0; i < n; ++i) kz = std::max(kz, b->kmax ? b->kmax[i] : c->cfg.k_max);
+  const int64_t C = n * c->cfg.n_chains;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(c->device);
+  DevBuf<int32_t> i1, i2, i3, i4, i5, i6;
+  DevBuf<double> d1, d2, d3, pm, pv, pe, pa;
+  DevBuf<uint32_t> ps;
+  hipError_t e = i1.ensure(C);
+  if (e == hipSuccess) e = i2.ensure((size_t)C * kz);
+  if (e == hipSuccess) e = i3.ensure((size_t)C * (kz + 1));
+  if (e == hipSuccess) e = i4.ensure((size_t)C * 8);
+  if (e == hipSuccess) e = i5.ensure(C);
+  if (e == hipSuccess) e = i6.ensure(C);
+  if (e == hipSuccess) e = d1.ensure(C);
+  if (e == hipSuccess) e = d2.ensure((size_t)C * kz);
+  if (e == hipSuccess) e = d3.ensure((size_t)C * 12);
+  if (e == hipSuccess) e = pm.ensure(3 * n);
+  if (e == hipSuccess) e = pv.ensure(3 * n);
+  if (e == hipSuccess) e = pe.ensure(3 * n);
+  if (e == hipSuccess) e = pa.ensure(4 * n);
+  if (e == hipSuccess) e = ps.ensure(n);
+  if (e != hipSuccess) {
+    (void)hipSetDevice(prev);
+    return fail(c, FSMP_ENOMEM, "steps autotuner scratch: %s", hipGetErrorString(e));
+  }
+  fsmp_samples o{};
+  o.n_pe = i1.p;
+  o.z = i2.p;
+  o.nhist = i3.p;
+  o.counts = i4.p;
+  o.status = (uint32_t *)i5.p;
+  o.rec_steps = i6.p;
+  o.t0 = d1.p;
+  o.charge = d2.p;
+  o.acc = d3.p;
+  o.kz = kz;
+  fsmp_posterior_out po{};
+  po.mean = pm.p;
+  po.var = pv.p;
+  po.mcse = pe.p;
+  po.accept = pa.p;
+  po.status = ps.p;
+  // the pilot: pilot_steps sweeps with the configured burn-in fraction, no records
+  const fsmp_config saved = c->cfg;
+  const bool saved_timing = c->timing;
+  const int burn_pilot = (int)((int64_t)pilot_steps * saved.burn_in / saved.n_steps);
+  c->cfg.n_steps = pilot_steps;
+  c->cfg.burn_in = burn_pilot;
+  c->cfg.record_flags = 0;
+  c->timing = false;
+  fsmp_batch bp = *b;
+  bp.n_steps = nullptr;
+  fsmp_status st = fsmp_sample(c, &bp, &o, hip_stream);
+  if (st == FSMP_OK) st = fsmp_posterior(c, n, &o, &po, hip_stream);
+  c->cfg = saved;
+  c->timing = saved_timing;
+  std::vector<double> mean(3 * n), mcse(3 * n);
+  if (st == FSMP_OK) {
+    e = hipMemcpyAsync(mean.data(), pm.p, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, (hipStream_t)hip_stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(mcse.data(), pe.p, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, (hipStream_t)hip_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)hip_stream);
+    if (e != hipSuccess) st = fail(c, FSMP_EDEVICE, "steps autotuner read-back: %s", hipGetErrorString(e));
+  }
+  if (st == FSMP_OK) {
+    // MCSE ~ 1 / sqrt(recorded sweeps): the recorded sweeps that reach the target, then the
+    // sweeps that leave that many after the configured burn-in fraction
+    const double kept_pilot = (double)(pilot_steps - burn_pilot);
+    const double keep_frac = (double)(saved.n_steps - saved.burn_in) / saved.n_steps;
+    const int32_t hi = std::min(max_steps, saved.n_steps);
+    for (int64_t i = 0; i < n; ++i) {
+      const double target = target_rel_mcse * std::max(1.0, mean[3 * i]);
+      const double m = mcse[3 * i];
+      double want = (m > 0.0 && kept_pilot > 0.0) ? kept_pilot * (m / target) * (m / target) / keep_frac : 0.0;
+      if (!std::isfinite(want)) want = (double)hi;
+      int64_t w = (int64_t)std::ceil(want);
+      w = std::max<int64_t>(w, min_steps);
+      w = std::min<int64_t>(w, hi);
+      steps_out[i] = (int32_t)std::max<int64_t>(w, 1);
+    }
+  }
+  (void)hipSetDevice(prev);
+  return st;
+}
+
 struct fsmp_graph {
   fsmp_ctx *ctx = nullptr;
   fsmp_ctx *own = nullptr;
@@ -996,6 +1102,7 @@ fsmp_status fsmp_posterior(fsmp_ctx *c, int64_t n_wave, const fsmp_samples *in, 
   a.kz = in->kz;
   a.n_steps = c->cfg.n_steps;
   a.burn_in = c->cfg.burn_in;
+  a.rec_steps = in->rec_steps;
   a.mean = out->mean;
   a.var = out->var;
   a.mcse = out->mcse;

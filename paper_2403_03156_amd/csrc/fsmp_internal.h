@@ -44,7 +44,7 @@ struct ChainArgs {
   const int64_t *mfoff;   // [n+1]
   const int32_t *chains;  // chain indices (wave * n_chains + chain) of this launch
   int64_t n_list;
-  int32_t n_chains, n_steps, burn_in, thin, nb, lb;
+  int32_t n_chains, n_steps, burn_in, thin;
   int64_t n_rec;
   uint32_t key0, key1;
   // outputs
@@ -80,6 +80,10 @@ struct ChainArgs {
   // to follow, and the delta-nu / log-acceptance computed along them
   const fsmp_logrec *force;
   double *rdnu, *rla;
+  // per-waveform sweep counts (device, or NULL: n_steps for all) and the per-chain count
+  // of recorded sweeps (output, or NULL)
+  const int32_t *wsteps;
+  int32_t *rec_steps;
 };
 
 struct PrologueArgs {
@@ -101,6 +105,7 @@ struct PosteriorArgs {
   const uint32_t *cstatus;
   int64_t n_wave;
   int32_t n_chains, kz, n_steps, burn_in;
+  const int32_t *rec_steps;  // per chain recorded sweeps, or NULL (n_steps - burn_in)
   double *mean, *var, *mcse, *p_n, *accept;
   uint32_t *status;
 };

@@ -360,7 +360,13 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
   const uint32_t uid0 = (uint32_t)uid, uid1 = (uint32_t)(uid >> 32);
   uint32_t st = a.wflags[w];
   if (glo > ghi) st |= FSMP_ST_EMPTY_T;
-  const int n_steps = (st & FSMP_ST_NONFINITE) ? 0 : a.n_steps;
+  // this waveform's sweeps and burn-in (the configured burn-in fraction), batch means
+  const int steps_w = a.wsteps ? a.wsteps[w] : a.n_steps;
+  const int burn = a.wsteps ? (int)((int64_t)steps_w * a.burn_in / a.n_steps) : a.burn_in;
+  const int n_steps = (st & FSMP_ST_NONFINITE) ? 0 : steps_w;
+  const int S_rec = n_steps > burn ? n_steps - burn : 0;
+  const int nb = S_rec > 0 ? (int)floor(sqrt((double)S_rec)) : 0;
+  const int lb = nb > 0 ? S_rec / nb : 0;
 
   // N histogram: the output row, zeroed here, receives the length of every run of equal
   // N among the recorded steps (atomic adds that nothing waits for)
@@ -652,12 +658,12 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
     }
 
     // ---- record after burn-in
-    if (step >= a.burn_in) {
+    if (step >= burn) {
       double Q = 0.0;
       for (int i = lane; i < N; i += LPC) Q += xv[i];
       Q = group_sum<LPC>(Q);
       const double v0 = (double)N, v1 = Q, v2 = t0;
-      const int64_t i = step - a.burn_in;
+      const int64_t i = step - burn;
       if (lane == 0) {
         acc[0] += v0;
         acc[1] += v0 * v0;
@@ -665,11 +671,11 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         acc[3] += v1 * v1;
         acc[4] += v2;
         acc[5] += v2 * v2;
-        if (a.nb > 0 && i < (int64_t)a.nb * a.lb) {
+        if (nb > 0 && i < (int64_t)nb * lb) {
           acc[12] += v0;
           acc[13] += v1;
           acc[14] += v2;
-          if ((i + 1) % a.lb == 0) {
+          if ((i + 1) % lb == 0) {
             acc[6] += acc[12];
             acc[7] += acc[12] * acc[12];
             acc[8] += acc[13];
@@ -746,6 +752,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
   if (lane == 0) {
     a.n_pe[c] = N;
     a.t0[c] = t0;
+    if (a.rec_steps) a.rec_steps[c] = S_rec;
     for (int i = 0; i < 12; ++i) a.acc[c * 12 + i] = acc[i];
     for (int i = 0; i < 8; ++i) a.counts[c * 8 + i] = cnt[i];
     a.status[c] = st;
@@ -1057,7 +1064,13 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
   const uint32_t uid0 = (uint32_t)uid, uid1 = (uint32_t)(uid >> 32);
   uint32_t st = a.wflags[w];
   if (glo > ghi) st |= FSMP_ST_EMPTY_T;
-  const int n_steps = (st & FSMP_ST_NONFINITE) ? 0 : a.n_steps;
+  // this waveform's sweeps and burn-in (the configured burn-in fraction), batch means
+  const int steps_w = a.wsteps ? a.wsteps[w] : a.n_steps;
+  const int burn = a.wsteps ? (int)((int64_t)steps_w * a.burn_in / a.n_steps) : a.burn_in;
+  const int n_steps = (st & FSMP_ST_NONFINITE) ? 0 : steps_w;
+  const int S_rec = n_steps > burn ? n_steps - burn : 0;
+  const int nb = S_rec > 0 ? (int)floor(sqrt((double)S_rec)) : 0;
+  const int lb = nb > 0 ? S_rec / nb : 0;
   for (int k = 0; k <= KCAP; ++k) HIST(k) = 0;
 
   double t0 = a.t0init[w];
@@ -1308,7 +1321,7 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
     }
 
     // ---- record after burn-in
-    if (step >= a.burn_in) {
+    if (step >= burn) {
       double Q = 0.0;
       for (int i = 0; i < N; ++i) Q += XV(i);
       const double v0 = (double)N, v1 = Q, v2 = t0;
@@ -1318,12 +1331,12 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
       acc[3] += v1 * v1;
       acc[4] += v2;
       acc[5] += v2 * v2;
-      const int64_t i = step - a.burn_in;
-      if (a.nb > 0 && i < (int64_t)a.nb * a.lb) {
+      const int64_t i = step - burn;
+      if (nb > 0 && i < (int64_t)nb * lb) {
         bs0 += v0;
         bs1 += v1;
         bs2 += v2;
-        if ((i + 1) % a.lb == 0) {
+        if ((i + 1) % lb == 0) {
           acc[6] += bs0;
           acc[7] += bs0 * bs0;
           acc[8] += bs1;
@@ -1358,6 +1371,7 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
   for (int k = 0; k <= kz; ++k) a.nhist[c * (kz + 1) + k] = k <= KCAP ? HIST(k) : 0;
   a.n_pe[c] = N;
   a.t0[c] = t0;
+  if (a.rec_steps) a.rec_steps[c] = S_rec;
   for (int i = 0; i < 12; ++i) a.acc[c * 12 + i] = acc[i];
   for (int i = 0; i < 8; ++i) a.counts[c * 8 + i] = cnt[i];
   a.status[c] = st;
@@ -1381,7 +1395,8 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
 __global__ void __launch_bounds__(256) posterior_kernel(PosteriorArgs a) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= a.n_wave) return;
-  const int S = a.n_steps - a.burn_in;
+  // the chains of one waveform ran the same number of sweeps
+  const int S = a.rec_steps ? a.rec_steps[w * a.n_chains] : a.n_steps - a.burn_in;
   const int nb = S > 0 ? (int)floor(sqrt((double)S)) : 0;
   const int lb = nb > 0 ? S / nb : 0;
   const int C = a.n_chains;

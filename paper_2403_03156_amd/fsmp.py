@@ -23,7 +23,8 @@ EXPORTS = ("fsmp_create", "fsmp_workspace_bytes", "fsmp_sample", "fsmp_posterior
            "fsmp_set_timing", "fsmp_last_error", "fsmp_destroy", "fsmp_version", "fsmp_server_create",
            "fsmp_server_submit", "fsmp_server_progress", "fsmp_server_result", "fsmp_server_stats",
            "fsmp_server_last_error", "fsmp_server_destroy", "fsmp_set_design", "fsmp_get_design", "fsmp_autotune",
-           "fsmp_graph_create", "fsmp_graph_launch", "fsmp_graph_destroy", "fsmp_replay")
+           "fsmp_graph_create", "fsmp_graph_launch", "fsmp_graph_destroy", "fsmp_replay",
+           "fsmp_autotune_steps")
 FSMP_DESIGN_GROUP, FSMP_DESIGN_LANE, FSMP_DESIGN_GROUP_DEVMEM = 0, 1, 2
 
 
@@ -49,7 +50,7 @@ class fsmp_config(ctypes.Structure):
 class fsmp_batch(ctypes.Structure):
     _fields_ = [("n_wave", ctypes.c_int64), ("wave", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
                 ("lambda_", ctypes.c_void_p), ("kmax", ctypes.c_void_p), ("g_range", ctypes.c_void_p),
-                ("t0_init", ctypes.c_void_p), ("wave_id", ctypes.c_void_p)]
+                ("t0_init", ctypes.c_void_p), ("wave_id", ctypes.c_void_p), ("n_steps", ctypes.c_void_p)]
 
 
 class fsmp_samples(ctypes.Structure):
@@ -57,7 +58,7 @@ class fsmp_samples(ctypes.Structure):
                 ("charge", ctypes.c_void_p), ("acc", ctypes.c_void_p), ("nhist", ctypes.c_void_p),
                 ("counts", ctypes.c_void_p), ("status", ctypes.c_void_p), ("log", ctypes.c_void_p),
                 ("trace", ctypes.c_void_p), ("kz", ctypes.c_int32), ("work", ctypes.c_void_p),
-                ("qdraw", ctypes.c_void_p), ("zdraw", ctypes.c_void_p)]
+                ("qdraw", ctypes.c_void_p), ("zdraw", ctypes.c_void_p), ("rec_steps", ctypes.c_void_p)]
 
 
 class fsmp_posterior_out(ctypes.Structure):
@@ -152,6 +153,9 @@ def load(path: Optional[str] = None):
     L.fsmp_replay.argtypes = [ctypes.c_void_p, P(fsmp_batch), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                               P(fsmp_samples), ctypes.c_void_p]
     L.fsmp_replay.restype = ctypes.c_int
+    L.fsmp_autotune_steps.argtypes = [ctypes.c_void_p, P(fsmp_batch), ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    L.fsmp_autotune_steps.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -229,6 +233,7 @@ class Sampler:
             "nhist": torch.zeros((C, kz + 1), dtype=torch.int32, device=dev),
             "counts": torch.zeros((C, 8), dtype=torch.int32, device=dev),
             "status": torch.zeros(C, dtype=torch.int32, device=dev),
+            "rec_steps": torch.zeros(C, dtype=torch.int32, device=dev),
             "log": None, "trace": None, "kz": kz,
             "work": torch.zeros((C, 4), dtype=torch.float64, device=dev) if work else None,
         }
@@ -242,7 +247,7 @@ class Sampler:
             out["zdraw"] = torch.zeros((C, max(n_rec, 1), kz), dtype=torch.int32, device=dev)
         return out
 
-    def _batch(self, wave, offsets, lam, kmax=None, g_range=None, t0_init=None, wave_id=None):
+    def _batch(self, wave, offsets, lam, kmax=None, g_range=None, t0_init=None, wave_id=None, n_steps=None):
         import torch
         if not wave.is_cuda or wave.dtype != torch.float32 or not wave.is_contiguous():
             raise ValueError("wave must be a contiguous float32 device tensor")
@@ -252,17 +257,29 @@ class Sampler:
         g_range = None if g_range is None else np.ascontiguousarray(g_range, dtype=np.int32).reshape(-1)
         t0_init = None if t0_init is None else np.ascontiguousarray(t0_init, dtype=np.float64)
         wave_id = None if wave_id is None else np.ascontiguousarray(wave_id, dtype=np.uint64)
-        keep = (offsets, lam, kmax, g_range, t0_init, wave_id)
+        n_steps = None if n_steps is None else np.ascontiguousarray(n_steps, dtype=np.int32)
+        keep = (offsets, lam, kmax, g_range, t0_init, wave_id, n_steps)
         b = fsmp_batch(len(offsets) - 1, ctypes.c_void_p(wave.data_ptr()), _hptr(offsets), _hptr(lam), _hptr(kmax),
-                       _hptr(g_range), _hptr(t0_init), _hptr(wave_id))
+                       _hptr(g_range), _hptr(t0_init), _hptr(wave_id), _hptr(n_steps))
         return b, keep
+
+    def autotune_steps(self, wave, offsets, lam, kmax=None, pilot_steps=200, target_rel_mcse=0.02, min_steps=500,
+                       max_steps=4000, stream=None):
+        """Per-waveform sweep counts from a pilot run's batch-means MCSE of N (fsmp_autotune_steps)."""
+        import torch
+        b, keep = self._batch(wave, offsets, lam, kmax)
+        steps = np.zeros(len(offsets) - 1, dtype=np.int32)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._check(self.lib.fsmp_autotune_steps(self.h, ctypes.byref(b), pilot_steps, target_rel_mcse, min_steps,
+                                                 max_steps, _hptr(steps), ctypes.c_void_p(st.cuda_stream)))
+        return steps
 
     @staticmethod
     def _samples(out):
         return fsmp_samples(_dptr(out["n_pe"]), _dptr(out["t0"]), _dptr(out["z"]), _dptr(out["charge"]),
                             _dptr(out["acc"]), _dptr(out["nhist"]), _dptr(out["counts"]), _dptr(out["status"]),
                             _dptr(out["log"]), _dptr(out["trace"]), out["kz"], _dptr(out.get("work")),
-                            _dptr(out.get("qdraw")), _dptr(out.get("zdraw")))
+                            _dptr(out.get("qdraw")), _dptr(out.get("zdraw")), _dptr(out.get("rec_steps")))
 
     def set_design(self, capacity, design):
         self._check(self.lib.fsmp_set_design(self.h, capacity, design))
@@ -320,27 +337,20 @@ class Sampler:
         return dnu, la, out
 
     def sample(self, wave, offsets, lam, kmax=None, g_range=None, t0_init=None, wave_id=None, out=None, kz=None,
-               stream=None, work=False):
-        """wave: torch float32 device tensor; offsets/lam/kmax/g_range/t0_init/wave_id: host numpy arrays."""
+               stream=None, work=False, n_steps=None):
+        """wave: torch float32 device tensor; offsets/lam/kmax/g_range/t0_init/wave_id/n_steps: host numpy
+        arrays (n_steps: sweeps per waveform, at most the configured n_steps)."""
         import torch
-        if not wave.is_cuda or wave.dtype != torch.float32 or not wave.is_contiguous():
-            raise ValueError("wave must be a contiguous float32 device tensor")
-        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
-        lam = np.ascontiguousarray(lam, dtype=np.float64)
-        n = len(offsets) - 1
-        kmax = None if kmax is None else np.ascontiguousarray(kmax, dtype=np.int32)
-        g_range = None if g_range is None else np.ascontiguousarray(g_range, dtype=np.int32).reshape(-1)
-        t0_init = None if t0_init is None else np.ascontiguousarray(t0_init, dtype=np.float64)
-        wave_id = None if wave_id is None else np.ascontiguousarray(wave_id, dtype=np.uint64)
+        b, keep = self._batch(wave, offsets, lam, kmax, g_range, t0_init, wave_id, n_steps)
+        n = int(b.n_wave)
+        kmax = keep[2]
         if kz is None:
             kz = int(kmax.max()) if kmax is not None and n > 0 else self.cfg.k_max
         if out is None:
             out = self.alloc_samples(n, kz, work=work)
-        b = fsmp_batch(n, ctypes.c_void_p(wave.data_ptr()), _hptr(offsets), _hptr(lam), _hptr(kmax), _hptr(g_range),
-                       _hptr(t0_init), _hptr(wave_id))
         s = self._samples(out)
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self._keep = (offsets, lam, kmax, g_range, t0_init, wave_id)
+        self._keep = keep
         self._check(self.lib.fsmp_sample(self.h, ctypes.byref(b), ctypes.byref(s), ctypes.c_void_p(st.cuda_stream)))
         return out
 
