@@ -229,9 +229,13 @@ typedef struct fsmp_ctx fsmp_ctx;
 fsmp_status fsmp_create(fsmp_ctx **out, const fsmp_ser *ser, const fsmp_intensity *phi, const fsmp_config *cfg,
                         int device);
 
-/* Device workspace (bytes) fsmp_sample needs for a batch of n_wave waveforms whose solution
- * spaces hold total_grid grid points in all; the context grows its workspace to this on demand. */
-size_t fsmp_workspace_bytes(const fsmp_ctx *ctx, int64_t n_wave, int64_t total_grid);
+/* Device workspace (bytes) fsmp_sample would hold for this batch with the context's current
+ * designs and configuration: batch metadata, the matched filter over every solution space,
+ * the chain state of each PE-capacity bucket (K_cap^2 words of G^-1 per chain in the
+ * device-memory designs, nothing for G^-1 in LDS), charge-draw scratch when recorded, and
+ * the light-curve table.  The context grows its workspace to this on demand and keeps it.
+ * Host arrays of `batch` are read (wave is not); 0 for an invalid batch. */
+size_t fsmp_workspace_bytes(const fsmp_ctx *ctx, const fsmp_batch *batch);
 
 /* Run cfg.n_chains chains of cfg.n_steps Gibbs sweeps for every waveform of the batch and
  * write `out`.  Validates every host array first (FSMP_EINVAL, nothing enqueued); returns

@@ -433,11 +433,40 @@ void fsmp_destroy(fsmp_ctx *c) {
   delete c;
 }
 
-size_t fsmp_workspace_bytes(const fsmp_ctx *c, int64_t n_wave, int64_t total_grid) {
-  if (!c || n_wave < 0 || total_grid < 0) return 0;
-  const size_t n = (size_t)n_wave;
-  return n * (8 + 8 + 8 + 8 + 8 + 4 + 8 + 4 + 4) + 16 + (size_t)total_grid * 8 +
-         n * (size_t)c->cfg.n_chains * 4;
+size_t fsmp_workspace_bytes(const fsmp_ctx *c, const fsmp_batch *b) {
+  if (!c || !b || b->n_wave < 0 || (b->n_wave > 0 && !b->offsets)) return 0;
+  const int64_t n = b->n_wave;
+  const fsmp_config &cf = c->cfg;
+  const bool fp32 = cf.precision == FSMP_FP32_REFRESH;
+  const int sub = cf.grid_sub;
+  int64_t cnt[kNumCaps] = {0};
+  size_t grid = 0;
+  int64_t tmax = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t L = b->offsets[i + 1] - b->offsets[i];
+    const int64_t lo = b->g_range ? b->g_range[2 * i] : 0, hi = b->g_range ? b->g_range[2 * i + 1] : sub * L - 1;
+    const int64_t T = hi >= lo ? hi - lo + 1 : 0;
+    grid += (size_t)T;
+    tmax = std::max(tmax, T);
+    int kc = chain_kcap_for(b->kmax ? b->kmax[i] : cf.k_max);
+    if (fp32 && kc == 48) kc = 64;
+    for (int q = 0; q < kNumCaps; ++q)
+      if (kCaps[q] == kc) cnt[q] += cf.n_chains;
+  }
+  // batch metadata, chain lists, matched filter over T
+  size_t bytes = (size_t)(n + 1) * 16 + (size_t)n * (8 + 8 + 4 + 8 + 8 + 4 + 4) + (size_t)n * cf.n_chains * 4 + grid * 8;
+  // chain state of each bucket in its design; charge-draw scratch; partial-sum table
+  for (int q = 0; q < kNumCaps; ++q) {
+    if (!cnt[q]) continue;
+    const int dz = fp32 ? FSMP_DESIGN_LANE : c->design[q];
+    if (dz == FSMP_DESIGN_LANE)
+      bytes += lane_ws_doubles(kCaps[q], cnt[q], fp32) * 8 + lane_ws_ints(kCaps[q], cnt[q]) * 4;
+    else if (dz == FSMP_DESIGN_GROUP_DEVMEM)
+      bytes += group_dm_ws_doubles(kCaps[q], cnt[q]) * 8;
+    if (cf.record_flags & FSMP_REC_CHARGE) bytes += (size_t)((cnt[q] + 63) / 64 * 64) * kCaps[q] * (kCaps[q] + 1) * 8;
+  }
+  bytes += (size_t)std::max<int64_t>(tmax + 1, 4 * 4096 + 1) * 16;
+  return bytes;
 }
 
 fsmp_status fsmp_set_timing(fsmp_ctx *c, int32_t enable) {

@@ -102,7 +102,7 @@ def load(path: Optional[str] = None):
     P = ctypes.POINTER
     L.fsmp_create.argtypes = [P(ctypes.c_void_p), P(fsmp_ser), P(fsmp_intensity), P(fsmp_config), ctypes.c_int]
     L.fsmp_create.restype = ctypes.c_int
-    L.fsmp_workspace_bytes.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64]
+    L.fsmp_workspace_bytes.argtypes = [ctypes.c_void_p, P(fsmp_batch)]
     L.fsmp_workspace_bytes.restype = ctypes.c_size_t
     L.fsmp_sample.argtypes = [ctypes.c_void_p, P(fsmp_batch), P(fsmp_samples), ctypes.c_void_p]
     L.fsmp_sample.restype = ctypes.c_int
@@ -262,6 +262,16 @@ class Sampler:
         b = fsmp_batch(len(offsets) - 1, ctypes.c_void_p(wave.data_ptr()), _hptr(offsets), _hptr(lam), _hptr(kmax),
                        _hptr(g_range), _hptr(t0_init), _hptr(wave_id), _hptr(n_steps))
         return b, keep
+
+    def workspace_bytes(self, offsets, lam, kmax=None, g_range=None):
+        """Device workspace fsmp_sample would hold for this batch (fsmp_workspace_bytes)."""
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        kmax = None if kmax is None else np.ascontiguousarray(kmax, dtype=np.int32)
+        g_range = None if g_range is None else np.ascontiguousarray(g_range, dtype=np.int32).reshape(-1)
+        b = fsmp_batch(len(offsets) - 1, None, _hptr(offsets), _hptr(lam), _hptr(kmax), _hptr(g_range), None, None,
+                       None)
+        return int(self.lib.fsmp_workspace_bytes(self.h, ctypes.byref(b)))
 
     def autotune_steps(self, wave, offsets, lam, kmax=None, pilot_steps=200, target_rel_mcse=0.02, min_steps=500,
                        max_steps=4000, stream=None):

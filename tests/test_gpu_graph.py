@@ -101,3 +101,19 @@ def test_autotune_keeps_results_correct():
                    kmax=km[:n])
     parted = compare_chains(g, o)
     assert len(parted) <= 0.3 * n, parted
+
+
+def test_workspace_bytes_matches_device_allocation():
+    wl, b, km = _batch(20000, 61)
+    kz = int(km.max())
+    smp = gpu_sampler(wl, 50, 25, 2, 3)
+    wave = torch.from_numpy(b["wave"]).cuda()
+    out = smp.alloc_samples(20000, kz)
+    predicted = smp.workspace_bytes(b["offsets"], b["lam"], kmax=km)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    smp.sample(wave, b["offsets"], b["lam"], kmax=km, kz=kz, out=out)
+    torch.cuda.synchronize()
+    used = free0 - torch.cuda.mem_get_info()[0]
+    print(f"[workspace] predicted {predicted / 2**20:.1f} MiB, device memory taken {used / 2**20:.1f} MiB", flush=True)
+    assert 0.9 * predicted <= used <= 1.1 * predicted + (64 << 20)
