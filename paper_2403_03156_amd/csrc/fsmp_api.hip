@@ -198,14 +198,21 @@ fsmp_status fail(fsmp_ctx *c, fsmp_status s, const char *fmt, ...) {
 
 bool finite(double v) { return std::isfinite(v); }
 
-// whether a kernel design exists for a PE capacity under this model (LDS footprint)
+// whether a kernel design exists for a PE capacity under this model (LDS footprint) and
+// precision (the FP32 form has no lane groups with G^-1 in LDS and no capacity 48)
 bool design_available(const fsmp_ctx *c, int kcap, int design) {
+  const bool fp32 = c->cfg.precision == FSMP_FP32_REFRESH;
   switch (design) {
-    case FSMP_DESIGN_GROUP: return chain_kcap_supported(kcap, c->tab.M, c->cfg.grid_sub);
+    case FSMP_DESIGN_GROUP: return !fp32 && chain_kcap_supported(kcap, c->tab.M, c->cfg.grid_sub);
     case FSMP_DESIGN_LANE: return kcap != 48;
-    case FSMP_DESIGN_GROUP_DEVMEM: return chain_dm_supported(kcap, c->tab.M, c->cfg.grid_sub);
+    case FSMP_DESIGN_GROUP_DEVMEM: return chain_dm_supported(kcap, c->tab.M, c->cfg.grid_sub, fp32);
     default: return false;
   }
+}
+
+// the design a bucket runs in: the context's choice where it exists, else one lane per chain
+int effective_design(const fsmp_ctx *c, int kcap, int design) {
+  return design_available(c, kcap, design) ? design : FSMP_DESIGN_LANE;
 }
 
 fsmp_status validate_model(const fsmp_ser *ser, const fsmp_intensity *phi, const fsmp_config *cfg, std::string &m) {
@@ -458,11 +465,11 @@ size_t fsmp_workspace_bytes(const fsmp_ctx *c, const fsmp_batch *b) {
   // chain state of each bucket in its design; charge-draw scratch; partial-sum table
   for (int q = 0; q < kNumCaps; ++q) {
     if (!cnt[q]) continue;
-    const int dz = fp32 ? FSMP_DESIGN_LANE : c->design[q];
+    const int dz = effective_design(c, kCaps[q], c->design[q]);
     if (dz == FSMP_DESIGN_LANE)
       bytes += lane_ws_doubles(kCaps[q], cnt[q], fp32) * 8 + lane_ws_ints(kCaps[q], cnt[q]) * 4;
     else if (dz == FSMP_DESIGN_GROUP_DEVMEM)
-      bytes += group_dm_ws_doubles(kCaps[q], cnt[q]) * 8;
+      bytes += group_dm_ws_doubles(kCaps[q], cnt[q], fp32) * 8;
     if (cf.record_flags & FSMP_REC_CHARGE) bytes += (size_t)((cnt[q] + 63) / 64 * 64) * kCaps[q] * (kCaps[q] + 1) * 8;
   }
   bytes += (size_t)std::max<int64_t>(tmax + 1, 4 * 4096 + 1) * 16;
@@ -556,7 +563,7 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   int64_t bucket_start[kNumCaps + 1] = {0};
   const bool fp32 = cf.precision == FSMP_FP32_REFRESH;
   auto design_of = [&](int bi) {
-    return fp32 ? FSMP_DESIGN_LANE : force ? FSMP_DESIGN_GROUP_DEVMEM : c->design[bi];
+    return force ? FSMP_DESIGN_GROUP_DEVMEM : effective_design(c, caps[bi], c->design[bi]);
   };
   // within a bucket, waveforms in order of lambda: neighbouring lanes then carry chains of
   // similar PE counts, which keeps the lane-per-chain loops (bounded by the largest K in a
@@ -610,7 +617,7 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
       const int64_t cnt = bucket_start[bi + 1] - bucket_start[bi];
       const int dz = design_of(bi);
       const size_t dd = dz == FSMP_DESIGN_LANE ? lane_ws_doubles(caps[bi], cnt, fp32)
-                        : dz == FSMP_DESIGN_GROUP_DEVMEM ? group_dm_ws_doubles(caps[bi], cnt)
+                        : dz == FSMP_DESIGN_GROUP_DEVMEM ? group_dm_ws_doubles(caps[bi], cnt, fp32)
                                                          : 0;
       lane_doff[bi + 1] = lane_doff[bi] + dd;
       lane_ioff[bi + 1] = lane_ioff[bi] + (dz == FSMP_DESIGN_LANE ? lane_ws_ints(caps[bi], cnt) : 0);
@@ -794,7 +801,7 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
       t.chains = cnt;
       return dz == FSMP_DESIGN_LANE    ? launch_chain_lane(caps[bi], fp32, ca, ks, &t.lanes, &t.blocks)
              : dz == FSMP_DESIGN_GROUP ? launch_chain(caps[bi], ca, ks, &t.lanes, &t.blocks)
-                                       : launch_chain_dm(caps[bi], ca, ks, &t.lanes, &t.blocks);
+                                       : launch_chain_dm(caps[bi], fp32, ca, ks, &t.lanes, &t.blocks);
     });
     if (fan) {
       const hipError_t e2 = hipEventRecord(c->join[bi], ks);
@@ -857,7 +864,6 @@ fsmp_status fsmp_autotune(fsmp_ctx *c, const fsmp_batch *b, int32_t trial_steps,
   if (!c) return FSMP_EINVAL;
   if (!b || b->n_wave < 1) return fail(c, FSMP_EINVAL, "autotune needs a non-empty batch");
   if (trial_steps < 1) return fail(c, FSMP_EINVAL, "trial_steps must be >= 1");
-  if (c->cfg.precision == FSMP_FP32_REFRESH) return FSMP_OK;  // the precision form has the lane design only
   const int64_t n = b->n_wave;
   int kz = 1;
   for (int64_t i = 0; i < n; ++i) kz = std::max(kz, b->kmax ? b->kmax[i] : c->cfg.k_max);

@@ -25,6 +25,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "fsmp_internal.h"
 
 namespace fsmp {
@@ -263,11 +265,12 @@ __global__ void __launch_bounds__(256) prologue_kernel(PrologueArgs a) {
 // the int grid indices.  The accumulators live in LDS,
 // updated by the group's first lane, to keep registers free; the N histogram is kept in
 // the output row by run lengths.
-template <int KCAP, bool HG>
+template <int KCAP, bool HG, bool F32 = false>
 struct ChainLayout {
   static constexpr int LD = KCAP;
   static constexpr int kAcc = 25;
-  static constexpr int kDoubles = (HG ? 0 : KCAP * KCAP) + 3 * KCAP + kAcc + (KCAP + 1) / 2;
+  // the FP32 form also keeps b (matched filter + rho mu_q per PE) for its FP64 refresh
+  static constexpr int kDoubles = (HG ? 0 : KCAP * KCAP) + (F32 ? 4 : 3) * KCAP + kAcc + (KCAP + 1) / 2;
 };
 
 // Column i of H owned by one lane: element (k, i) at H[(k * LD + i) * HS] (HS = 1 in LDS;
@@ -275,14 +278,14 @@ struct ChainLayout {
 // interleaved element by element).  Loads go in chunks of 8 rows, issued unconditionally
 // (rows below the capacity, a multiple of 8) with the rows past N dropped by a select,
 // so a chunk costs one memory round trip; terms are summed in row order.
-template <int LD, int HS>
-__device__ inline double grp_col_dot(const double *H, const double *g, int i, int N) {
+template <int LD, int HS, typename MT>
+__device__ inline double grp_col_dot(const MT *H, const double *g, int i, int N) {
   double e = 0.0;
   for (int k0 = 0; k0 < N; k0 += 8) {
     double h[8], v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      h[u] = H[((k0 + u) * LD + i) * HS];
+      h[u] = (double)H[((k0 + u) * LD + i) * HS];
       v[u] = g[k0 + u];
     }
 #pragma unroll
@@ -291,24 +294,79 @@ __device__ inline double grp_col_dot(const double *H, const double *g, int i, in
   return e;
 }
 
-// H(k, i) += ai A_k cA [+ bi B_k cB] for k < N (loads of a chunk unconditional, stores guarded)
-template <int LD, int HS, bool TWO>
-__device__ inline void grp_col_update(double *H, int i, int N, double ai, const double *A, double cA, double bi,
+// H(k, i) += ai A_k cA [+ bi B_k cB] for k < N (loads of a chunk unconditional, stores guarded;
+// an FP32 H is read into FP64 and written back rounded)
+template <int LD, int HS, bool TWO, typename MT>
+__device__ inline void grp_col_update(MT *H, int i, int N, double ai, const double *A, double cA, double bi,
                                       const double *B, double cB) {
   for (int k0 = 0; k0 < N; k0 += 8) {
     double h[8], av[8], bw[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      h[u] = H[((k0 + u) * LD + i) * HS];
+      h[u] = (double)H[((k0 + u) * LD + i) * HS];
       av[u] = A[k0 + u];
       if (TWO) bw[u] = B[k0 + u];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const double v = TWO ? h[u] + (ai * av[u] * cA + bi * bw[u] * cB) : h[u] + ai * av[u] * cA;
-      if (k0 + u < N) H[((k0 + u) * LD + i) * HS] = v;
+      if (k0 + u < N) H[((k0 + u) * LD + i) * HS] = (MT)v;
     }
   }
+}
+
+template <int W>
+__device__ inline double group_max(double v) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, W));
+  return v;
+}
+
+// Precision form, lane groups: rebuild G^{-1} of the current PE list in FP64 into W by
+// bordering (each step is the birth update of the inverse of the leading block, its
+// columns owned by the group's lanes), recompute x = G^{-1} b in FP64 and round W into
+// the FP32 H.  False if a Schur complement is not positive.  `drift` = the largest change
+// of a charge mean, relative to max(1, |x|).  s1, s2 are scratch.
+template <int LPC, int LD, int HS, typename HT>
+__device__ bool grp_refresh(const ModelDev &md, const double *vt, const double *ov, int Lw, double *W, HT *H,
+                            double *xv, const double *bv, double *s1, double *s2, const int *zg, int N, int lane,
+                            double &drift) {
+  for (int k = 0; k < N; ++k) {
+    const int gk = zg[k];
+    for (int i = lane; i < k; i += LPC) s1[i] = overlap(md, vt, ov, gk, zg[i], Lw);
+    const double d = overlap(md, vt, ov, gk, gk, Lw) + md.rho;
+    WAVE_SYNC();
+    double q = 0.0;
+    for (int i = lane; i < k; i += LPC) {
+      const double e = grp_col_dot<LD, HS>(W, s1, i, k);
+      s2[i] = e;
+      q += s1[i] * e;
+    }
+    q = group_sum<LPC>(q);
+    const double delta2 = d - q;
+    if (!(delta2 > 0.0)) return false;
+    const double inv = 1.0 / delta2;
+    WAVE_SYNC();
+    for (int i = lane; i < k; i += LPC) {
+      const double ei = s2[i];
+      grp_col_update<LD, HS, false>(W, i, k, ei, s2, inv, 0.0, s2, 0.0);
+      W[(k * LD + i) * HS] = -ei * inv;
+      W[(i * LD + k) * HS] = -ei * inv;
+    }
+    if (lane == 0) W[(k * LD + k) * HS] = inv;
+    WAVE_SYNC();
+  }
+  double dr = 0.0;
+  for (int i = lane; i < N; i += LPC) {
+    const double xi = grp_col_dot<LD, HS>(W, bv, i, N);
+    dr = fmax(dr, fabs(xi - xv[i]) / fmax(1.0, fabs(xi)));
+    xv[i] = xi;
+  }
+  drift = group_max<LPC>(dr);
+  for (int i = lane; i < N; i += LPC)
+    for (int k = 0; k < N; ++k) H[(k * LD + i) * HS] = (HT)W[(k * LD + i) * HS];
+  WAVE_SYNC();
+  return true;
 }
 
 // HG: H in device memory (a.dws, the chains of a wavefront interleaved element by element),
@@ -316,10 +374,12 @@ __device__ inline void grp_col_update(double *H, int i, int N, double ai, const 
 // otherwise H in LDS.  FORCE (replay): every step follows the recorded proposal of a.force
 // (t0 after the half-step, move, index, grid point, accept bit) instead of the chain's
 // own draws, and writes the delta-nu and log-acceptance it computes to a.rdnu / a.rla.
-template <int KCAP, int LPC, int WPB, bool HG, bool FORCE>
+template <int KCAP, int LPC, int WPB, bool HG, bool FORCE, bool F32>
 __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu(2))) chain_kernel(ChainArgs a) {
+  static_assert(!F32 || (HG && !FORCE), "the FP32 form keeps H in device memory and does not replay");
+  using HT = typename std::conditional<F32, float, double>::type;
   constexpr int CPW = kWave / LPC;
-  using CL = ChainLayout<KCAP, HG>;
+  using CL = ChainLayout<KCAP, HG, F32>;
   constexpr int LD = CL::LD;
   constexpr int HS = HG ? CPW : 1;
   extern __shared__ double smem[];
@@ -339,11 +399,17 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
   if (slot >= a.n_list) return;
 
   double *cb = smem + md.M * (1 + md.sub) + (KCAP + 2) + (int64_t)(wv * CPW + grp) * CL::kDoubles;
-  double *H = HG ? a.dws + tile * (int64_t)(KCAP * LD * CPW) + grp : cb;
+  // device memory of a tile (the wavefront's chains interleaved element by element): H in
+  // its storage type, then in the FP32 form the FP64 refresh matrix W
+  constexpr int64_t kHD = (int64_t)KCAP * LD * CPW * (int64_t)sizeof(HT) / 8;
+  constexpr int64_t kTile = kHD + (F32 ? (int64_t)KCAP * LD * CPW : 0);
+  HT *H = HG ? (HT *)(a.dws + tile * kTile) + grp : (HT *)cb;
+  double *W = F32 ? a.dws + tile * kTile + kHD + grp : nullptr;
   double *xv = HG ? cb : cb + KCAP * LD;
   double *s1 = xv + KCAP;
   double *s2 = s1 + KCAP;
-  double *acc = s2 + KCAP;  // [0..11] sums, [12..14] open batch sums, [15..18] work counters
+  double *bv = F32 ? s2 + KCAP : nullptr;  // b of each PE (FP32 form)
+  double *acc = s2 + KCAP + (F32 ? KCAP : 0);  // [0..11] sums, [12..14] open batch sums, [15..18] work counters
   int *cnt = (int *)(acc + 20);
   int *run = cnt + 8;  // N of the current run among the recorded steps (-1: none yet), its first step
   int *zg = (int *)(acc + CL::kAcc);
@@ -394,6 +460,14 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
   WAVE_SYNC();
 
   for (int step = 0; step < n_steps; ++step) {
+    if constexpr (F32) {
+      if (a.refresh_M > 0 && step > 0 && step % a.refresh_M == 0 && N > 0) {
+        // precision form: FP64 rebuild of G^{-1} every refresh_M sweeps
+        double drift;
+        if (!grp_refresh<LPC, LD, HS>(md, vt, ov, Lw, W, H, xv, bv, s1, s2, zg, N, lane, drift)) st |= FSMP_ST_FACTOR;
+        else if (drift > a.drift_bound) st |= FSMP_ST_DRIFT;
+      }
+    }
     uint32_t r[8];
     philox4x32_10((uint32_t)step, 0u, uid0, uid1, a.key0, a.key1, r);
     philox4x32_10((uint32_t)step, 1u, uid0, uid1, a.key0, a.key1, r + 4);
@@ -457,7 +531,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
     int j = -1, gnew = -1, sh = 0;
     bool valid = false, need_mv = false;
     double dnu = 0.0, la = -INFINITY, lpn = 0.0, lpo = 0.0;
-    double delta2 = 1.0, up = 0.0, om = 1.0, xj = 0.0, ej = 0.0;
+    double delta2 = 1.0, up = 0.0, om = 1.0, xj = 0.0, ej = 0.0, beta = 0.0;
     if (move == 1) {
       if (lane == 0) cnt[2]++;
       if (N >= kmax) {
@@ -500,18 +574,19 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         }
       }
     }
-    if (need_mv) {
-      // gamma = overlaps of the new position with the PEs (zero at the shifted one),
-      // eta = H gamma, q = gamma^T eta, p = gamma^T x
+    // birth or time shift: gamma = overlaps of the new position with the PEs (zero at the
+    // shifted one), eta = M gamma, q = gamma^T eta, p = gamma^T x, for M = H or (precision
+    // form, near the threshold) its FP64 rebuild W
+    auto eval_mv = [&](auto *M) {
+      valid = false;
       const int jz = move == 3 ? j : -1;
       for (int i = lane; i < N; i += LPC) s1[i] = (i == jz) ? 0.0 : overlap(md, vt, ov, gnew, zg[i], Lw);
       const double d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
-      const double beta = mf[gnew - glo] + md.rhom;
+      beta = mf[gnew - glo] + md.rhom;
       WAVE_SYNC();
-      if (lane == 0) acc[15] += (double)N * N;
       double q = 0.0, p = 0.0;
       for (int i = lane; i < N; i += LPC) {
-        const double e = grp_col_dot<LD, HS>(H, s1, i, N);
+        const double e = grp_col_dot<LD, HS>(M, s1, i, N);
         s2[i] = e;
         q += s1[i] * e;
         p += s1[i] * xv[i];
@@ -530,7 +605,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         }
       } else {
         WAVE_SYNC();
-        om = H[(j * LD + j) * HS];
+        om = (double)M[(j * LD + j) * HS];
         xj = xv[j];
         ej = s2[j];
         delta2 = d - (q - ej * ej / om);
@@ -543,10 +618,35 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
           st |= FSMP_ST_FACTOR;
         }
       }
+    };
+    if (need_mv) {
+      if (lane == 0) acc[15] += (double)N * N;
+      eval_mv(H);
+    }
+
+    // precision form, a decision near the threshold: refresh in FP64 and decide with the
+    // FP64 delta-nu of the same proposal
+    const double logu = (F32 && valid) ? log(u01(r[6])) : 0.0;
+    if constexpr (F32) {
+      if (valid && fabs(logu - la) < a.near_eps * fmax(1.0, fabs(dnu))) {
+        double drift;
+        if (N > 0 && grp_refresh<LPC, LD, HS>(md, vt, ov, Lw, W, H, xv, bv, s1, s2, zg, N, lane, drift)) {
+          if (need_mv) {
+            eval_mv(W);
+          } else if (move == 2) {
+            om = W[(j * LD + j) * HS];
+            xj = xv[j];
+            dnu = 0.5 * (-md.log_rho - log(om) + (md.rhom2 - xj * xj / om) * md.inv_s);
+            la = dnu - logLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
+          }
+        } else if (N > 0) {
+          st |= FSMP_ST_FACTOR;
+        }
+      }
     }
 
     bool accepted = false;
-    if (valid && (FORCE ? (rec.flags & 2) != 0 : log(u01(r[6])) < la)) {
+    if (valid && (FORCE ? (rec.flags & 2) != 0 : F32 ? logu < la : log(u01(r[6])) < la)) {
       accepted = true;
       if (lane == 0) cnt[2 * move + 1]++;
       WAVE_SYNC();
@@ -591,6 +691,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
             H[(N * LD + N) * HS] = inv_d2;
             zg[N] = gnew;
             xv[N] = xn;
+            if (F32) bv[N] = beta;
           }
           N++;
           if (biexp) S_cur += rise_term(md, gnew, t0);
@@ -612,6 +713,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
             if (lane == 0) {
               zg[j] = zg[last];
               xv[j] = xv[last];
+              if (F32) bv[j] = bv[last];
             }
           }
           N--;
@@ -626,7 +728,10 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
               H[(i * LD + j) * HS] = v;
             }
           }
-          if (lane == 0) zg[j] = gnew;
+          if (lane == 0) {
+            zg[j] = gnew;
+            if (F32) bv[j] = beta;
+          }
           if (biexp) S_cur += rise_term(md, gnew, t0) - rise_term(md, gj, t0);
         }
         WAVE_SYNC();
@@ -1448,24 +1553,25 @@ __global__ void __launch_bounds__(256) posterior_kernel(PosteriorArgs a) {
   a.status[w] = st;
 }
 
-template <int KCAP, int LPC, int WPB, bool HG, bool FORCE = false>
+template <int KCAP, int LPC, int WPB, bool HG, bool FORCE = false, bool F32 = false>
 hipError_t launch_chain_t(const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
   constexpr int CPB = WPB * (kWave / LPC);
   const int64_t nb = (a.n_list + CPB - 1) / CPB;
-  const size_t lds =
-      sizeof(double) * ((size_t)a.md.M * (1 + a.md.sub) + (KCAP + 2) + (size_t)CPB * ChainLayout<KCAP, HG>::kDoubles);
+  const size_t lds = sizeof(double) * ((size_t)a.md.M * (1 + a.md.sub) + (KCAP + 2) +
+                                       (size_t)CPB * ChainLayout<KCAP, HG, F32>::kDoubles);
   *lanes = LPC;
   *blocks = nb;
   if (nb == 0) return hipSuccess;
   if (HG && a.dws == nullptr) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
     // lift the default dynamic-LDS limit; gfx950 has 160 KB per workgroup
-    (void)hipFuncSetAttribute((const void *)chain_kernel<KCAP, LPC, WPB, HG, FORCE>,
+    (void)hipFuncSetAttribute((const void *)chain_kernel<KCAP, LPC, WPB, HG, FORCE, F32>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipGetLastError();
   }
   if (FORCE && (a.force == nullptr || a.rdnu == nullptr || a.rla == nullptr)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((chain_kernel<KCAP, LPC, WPB, HG, FORCE>), dim3((unsigned)nb), dim3(kWave * WPB), lds, st, a);
+  hipLaunchKernelGGL((chain_kernel<KCAP, LPC, WPB, HG, FORCE, F32>), dim3((unsigned)nb), dim3(kWave * WPB), lds, st,
+                     a);
   return hipGetLastError();
 }
 
@@ -1514,9 +1620,9 @@ static const GroupCfg kGroup[] = {{16, 16, 4}, {32, 32, 4}, {48, 64, 3}, {64, 64
 static const GroupCfg kGroupDM[] = {{16, 4, 4},  {32, 4, 8},   {48, 16, 4},  {64, 32, 4},
                                     {96, 16, 2}, {128, 32, 4}, {160, 32, 4}, {192, 32, 2}};
 
-static size_t chain_lds_bytes(const GroupCfg &g, int M, int sub, bool hg) {
+static size_t chain_lds_bytes(const GroupCfg &g, int M, int sub, bool hg, bool f32 = false) {
   const int cpb = g.wpb * (64 / g.lpc);
-  const size_t per = (hg ? 0 : (size_t)g.kcap * g.kcap) + 3 * (size_t)g.kcap + 25 + ((size_t)g.kcap + 1) / 2;
+  const size_t per = (hg ? 0 : (size_t)g.kcap * g.kcap) + (f32 ? 4 : 3) * (size_t)g.kcap + 25 + ((size_t)g.kcap + 1) / 2;
   return sizeof(double) * ((size_t)M * (1 + sub) + (size_t)g.kcap + 2 + (size_t)cpb * per);
 }
 
@@ -1526,17 +1632,20 @@ bool chain_kcap_supported(int kcap, int M, int sub) {
   return false;
 }
 
-bool chain_dm_supported(int kcap, int M, int sub) {
+bool chain_dm_supported(int kcap, int M, int sub, bool f32) {
+  if (f32 && kcap == 48) return false;  // the precision form runs capacity 48 at 64
   for (const GroupCfg &g : kGroupDM)
-    if (g.kcap == kcap) return chain_lds_bytes(g, M, sub, true) <= 160 * 1024;
+    if (g.kcap == kcap) return chain_lds_bytes(g, M, sub, true, f32) <= 160 * 1024;
   return false;
 }
 
-size_t group_dm_ws_doubles(int kcap, int64_t n_list) {
+// H (FP64, or FP32 plus the FP64 refresh matrix) of every chain, in tiles of a wavefront
+size_t group_dm_ws_doubles(int kcap, int64_t n_list, bool f32) {
   for (const GroupCfg &g : kGroupDM)
     if (g.kcap == kcap) {
       const int64_t cpw = 64 / g.lpc;
-      return (size_t)((n_list + cpw - 1) / cpw) * cpw * kcap * kcap;
+      const size_t k2 = (size_t)kcap * kcap;
+      return (size_t)((n_list + cpw - 1) / cpw) * cpw * (f32 ? k2 / 2 + k2 : k2);
     }
   return 0;
 }
@@ -1592,7 +1701,7 @@ hipError_t launch_chain(int kcap, const ChainArgs &a, hipStream_t st, int32_t *l
 }
 
 // instances must match kGroupDM
-hipError_t launch_chain_dm(int kcap, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
+hipError_t launch_chain_dm(int kcap, bool fp32, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
   if (a.force) {
     switch (kcap) {
       case 16: return launch_chain_t<16, 4, 4, true, true>(a, st, lanes, blocks);
@@ -1603,6 +1712,18 @@ hipError_t launch_chain_dm(int kcap, const ChainArgs &a, hipStream_t st, int32_t
       case 128: return launch_chain_t<128, 32, 4, true, true>(a, st, lanes, blocks);
       case 160: return launch_chain_t<160, 32, 4, true, true>(a, st, lanes, blocks);
       case 192: return launch_chain_t<192, 32, 2, true, true>(a, st, lanes, blocks);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (fp32) {
+    switch (kcap) {
+      case 16: return launch_chain_t<16, 4, 4, true, false, true>(a, st, lanes, blocks);
+      case 32: return launch_chain_t<32, 4, 8, true, false, true>(a, st, lanes, blocks);
+      case 64: return launch_chain_t<64, 32, 4, true, false, true>(a, st, lanes, blocks);
+      case 96: return launch_chain_t<96, 16, 2, true, false, true>(a, st, lanes, blocks);
+      case 128: return launch_chain_t<128, 32, 4, true, false, true>(a, st, lanes, blocks);
+      case 160: return launch_chain_t<160, 32, 4, true, false, true>(a, st, lanes, blocks);
+      case 192: return launch_chain_t<192, 32, 2, true, false, true>(a, st, lanes, blocks);
       default: return hipErrorInvalidValue;
     }
   }

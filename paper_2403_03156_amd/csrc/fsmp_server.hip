@@ -297,8 +297,9 @@ fsmp_status fsmp_server_create(fsmp_server **out, const fsmp_ser *ser, const fsm
       return st;
     }
     // latency: the lane-group kernels finish a sweep in microseconds; one lane per chain
-    // with its state in device memory needs many memory round trips per sweep
-    (void)fsmp_set_design(sl->ctx, 0, FSMP_DESIGN_GROUP);
+    // with its state in device memory needs many memory round trips per sweep.  The FP32
+    // form has lane groups with G^-1 in device memory only.
+    (void)fsmp_set_design(sl->ctx, 0, cfg->precision == FSMP_FP32_REFRESH ? FSMP_DESIGN_GROUP_DEVMEM : FSMP_DESIGN_GROUP);
     (void)hipSetDevice(device);
     if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl->done, hipEventDisableTiming) != hipSuccess) {

@@ -33,16 +33,18 @@ def _sampler(wl, n_steps, burn, n_chains, seed, precision, refresh_M=64, flags=0
                         precision=precision, refresh_M=refresh_M, record_flags=flags)
 
 
+@pytest.mark.parametrize("design", [fsmp.FSMP_DESIGN_LANE, fsmp.FSMP_DESIGN_GROUP_DEVMEM])
 @pytest.mark.parametrize("sigma_eps", [0.05, 0.1, 0.2])
-def test_fp32_refresh_delta_nu_replay(sigma_eps):
+def test_fp32_refresh_delta_nu_replay(sigma_eps, design):
     base = synth.PRESETS["pileup"]
     wl = synth.Workload("pileup", 12, base.lengths, "uniform", 20.0, 100.0, phi_kind=base.phi_kind,
                         tau_rise=base.tau_rise, tau_decay=base.tau_decay, sigma_q=0.35, sigma_eps=sigma_eps)
     b = synth.generate(wl, n_wave=12, seed=17)
     km = synth.kmax_for(b["lam"])
     n_steps = 300
-    print(f"[case] fp32 pileup sigma_eps={sigma_eps} kmax={sorted(set(km.tolist()))}", flush=True)
+    print(f"[case] fp32 pileup sigma_eps={sigma_eps} design={design} kmax={sorted(set(km.tolist()))}", flush=True)
     smp = _sampler(wl, n_steps, 150, 1, 5, fsmp.FSMP_FP32_REFRESH, refresh_M=64, flags=fsmp.FSMP_REC_LOG)
+    smp.set_design(0, design)
     out = smp.sample(torch.from_numpy(b["wave"]).cuda(), b["offsets"], b["lam"], kmax=km, kz=int(km.max()))
     torch.cuda.synchronize()
     logs = fsmp.log_records(out["log"])
@@ -58,14 +60,15 @@ def test_fp32_refresh_delta_nu_replay(sigma_eps):
         errs.append(e)
         flips += bad
     e = np.concatenate(errs)
-    print(f"[precision] sigma_eps={sigma_eps}: {e.size} proposals, delta-nu rel err max {e.max():.2e}, "
+    print(f"[precision] design {design} sigma_eps={sigma_eps}: {e.size} proposals, delta-nu rel err max {e.max():.2e}, "
           f"p99 {np.quantile(e, 0.99):.2e}, median {np.median(e):.2e}; decision flips {flips}", flush=True)
     assert np.isfinite(e).all()
     assert np.median(e) < MEDIAN_ENVELOPE[sigma_eps]
     assert flips <= FLIP_FRAC * e.size
 
 
-def test_fp32_refresh_posterior_matches_fp64():
+@pytest.mark.parametrize("design", [fsmp.FSMP_DESIGN_LANE, fsmp.FSMP_DESIGN_GROUP_DEVMEM])
+def test_fp32_refresh_posterior_matches_fp64(design):
     wl = synth.PRESETS["batched"]
     b = synth.generate(wl, n_wave=200, seed=23)
     km = synth.kmax_for(b["lam"])
@@ -74,6 +77,8 @@ def test_fp32_refresh_posterior_matches_fp64():
     res = {}
     for prec in (fsmp.FSMP_FP64, fsmp.FSMP_FP32_REFRESH):
         smp = _sampler(wl, n_steps, burn, C, 31, prec, refresh_M=64)
+        if prec == fsmp.FSMP_FP32_REFRESH:
+            smp.set_design(0, design)
         out = smp.sample(torch.from_numpy(b["wave"]).cuda(), b["offsets"], b["lam"], kmax=km, kz=kz)
         post = smp.posterior(200, out)
         torch.cuda.synchronize()
