@@ -178,7 +178,15 @@ typedef struct {
  *                         (with FSMP_ST_FACTOR) if the factorisation fails.  The draw reads
  *                         the maintained G^-1 (FP32 in the precision form).  Costs O(K^3)
  *                         per record; FP64 scratch of kcap (kcap + 1) words per chain is allocated
- *                         by fsmp_sample while the flag is set. */
+ *                         by fsmp_sample while the flag is set.
+ *   occ                   NULL, or the grid occupancy (Sec. 2.2: the PE sequence as a point
+ *                         pattern on the grid of T): per waveform one int32 per grid point of its
+ *                         window, the row of waveform i at occ + grid_sub * offsets[i] with
+ *                         grid_sub * L_i entries (grid_sub * offsets[n_wave] in all), counting
+ *                         over the waveform's chains and recorded sweeps the PEs at each grid
+ *                         point (with multiplicity; a row sums to the sum of N over the recorded
+ *                         steps).  fsmp_sample zeroes the rows; FSMP_EINVAL if n_chains x
+ *                         (n_steps - burn_in) x kmax could overflow a count. */
 typedef struct {
   int32_t *n_pe;
   double *t0;
@@ -195,12 +203,16 @@ typedef struct {
   double *qdraw;
   int32_t *zdraw;
   int32_t *rec_steps;
+  int32_t *occ;
 } fsmp_samples;
 
 /* Posterior summaries per waveform (device buffers, caller-allocated): for (N, Q, t0)
  * the mean, variance and batch-means MCSE pooled over the waveform's chains; P(N = k)
  * for k <= kz (NULL to skip); acceptance rates of t0, birth, death, update; the OR of
- * the chains' status words. */
+ * the chains' status words; optionally the posterior occupancy of the grid, the expected
+ * number of PEs at every grid point (fsmp_samples.occ over the waveform's recorded
+ * (chain, sweep) pairs, in the same layout), which needs fsmp_samples.occ and the batch's
+ * host offsets. */
 typedef struct {
   double *mean;      /* [n_wave][3] */
   double *var;       /* [n_wave][3] */
@@ -208,6 +220,8 @@ typedef struct {
   double *p_n;       /* [n_wave][kz + 1] or NULL */
   double *accept;    /* [n_wave][4] */
   uint32_t *status;  /* [n_wave] */
+  double *occupancy; /* NULL, or grid_sub * offsets[n_wave] doubles, rows as fsmp_samples.occ */
+  const int64_t *offsets; /* host, n_wave + 1: the batch's sample offsets (with occupancy) */
 } fsmp_posterior_out;
 
 /* Timing of the kernels of the last fsmp_sample call (HIP events on its stream). */

@@ -602,7 +602,7 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
                           int32_t ghi, double t0_init, uint64_t uid, uint64_t seed, int32_t n_steps, int32_t burn_in,
                           int32_t kz, int32_t *N_out, double *t0_out, int32_t *z_out, double *x_out, double *acc,
                           int32_t *nhist, int32_t *counts, uint32_t *status, ora_logrec *logrec, double *trace,
-                          int32_t thin, double *qdraw, int32_t *zdraw) {
+                          int32_t thin, double *qdraw, int32_t *zdraw, int32_t *occ) {
   ora_ctx c;
   ctx_init(&c, p, tab, w, Lw);
   double dt = 1.0 / p->sub;
@@ -724,6 +724,9 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
         }
       }
       if (N <= kz) nhist[N]++;
+      /* grid occupancy: every PE of the recorded state counts once at its grid point */
+      if (occ)
+        for (int k = 0; k < N; ++k) occ[z[k]]++;
       if (trace && thin > 0 && (i % thin) == 0) {
         double *tr = trace + 3 * (i / thin);
         tr[0] = (double)N;
@@ -756,13 +759,17 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
 
 /* Run n_chains chains for every waveform.  Chain c of waveform i writes
  * index i * n_chains + c of every output.  kz is the row length of z_out /
- * x_out (>= every kmax) and nhist rows have kz + 1 entries. */
+ * x_out (>= every kmax) and nhist rows have kz + 1 entries.  occ (NULL to
+ * skip; zeroed by the caller) holds one row of sub * L_i grid points per chain,
+ * chain c of waveform i at n_chains * sub * offsets[i] + c * sub * L_i: the
+ * number of recorded sweeps with a PE at each grid point, PEs counted with
+ * their multiplicity. */
 int ora_run(const ora_params *p, int64_t n_wave, const float *wave, const int64_t *offsets, const double *lambda,
             const int32_t *kmax, const int32_t *g_range, const double *t0_init, const uint64_t *wave_id,
             int32_t n_chains, int32_t n_steps, int32_t burn_in, uint64_t seed, int32_t kz, int32_t *N_out,
             double *t0_out, int32_t *z_out, double *x_out, double *acc, int32_t *nhist, int32_t *counts,
             uint32_t *status, ora_logrec *logrec, double *trace, int32_t thin, double *qdraw, int32_t *zdraw,
-            int32_t n_threads) {
+            int32_t *occ, int32_t n_threads) {
   int64_t total = n_wave * n_chains;
   int64_t n_rec = (thin > 0 && n_steps > burn_in) ? (n_steps - burn_in + thin - 1) / thin : 0;
   ora_table tab;
@@ -784,7 +791,8 @@ int ora_run(const ora_params *p, int64_t n_wave, const float *wave, const int64_
                   burn_in, kz, &N_out[ic], &t0_out[ic], z_out + ic * kz, x_out + ic * kz, acc + ic * 12,
                   nhist + ic * (kz + 1), counts + ic * 8, &status[ic], logrec ? logrec + ic * n_steps : NULL,
                   trace ? trace + ic * 3 * n_rec : NULL, thin, qdraw ? qdraw + ic * kz * n_rec : NULL,
-                  zdraw ? zdraw + ic * kz * n_rec : NULL);
+                  zdraw ? zdraw + ic * kz * n_rec : NULL,
+                  occ ? occ + n_chains * p->sub * offsets[i] + (int64_t)ch * p->sub * Lw : NULL);
   }
   table_free(&tab);
   return 0;

@@ -156,6 +156,7 @@ struct fsmp_ctx {
   DevBuf<int32_t> kmax, grange, chains;
   DevBuf<uint64_t> wid;
   DevBuf<int32_t> wsteps;  // per-waveform sweeps (fsmp_batch.n_steps)
+  DevBuf<int64_t> poff;    // fsmp_posterior: the batch offsets of the occupancy rows
   DevBuf<uint32_t> wflags;
   DevBuf<double> lane_d;
   DevBuf<int32_t> lane_i;
@@ -422,6 +423,7 @@ void fsmp_destroy(fsmp_ctx *c) {
   if (c->d_vtab) (void)hipFree(c->d_vtab);
   if (c->d_ovl) (void)hipFree(c->d_ovl);
   c->woff.release();
+  c->poff.release();
   c->mfoff.release();
   c->lam.release();
   c->t0init.release();
@@ -556,6 +558,9 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     wid[i] = b->wave_id ? b->wave_id[i] : (uint64_t)i;
     mfo[i + 1] = mfo[i] + (lo <= hi ? (int64_t)(hi - lo + 1) : 0);
   }
+  // the occupancy counts of one grid point stay below n_chains * recorded sweeps * kmax
+  if (o->occ && (int64_t)cf.n_chains * (cf.n_steps - cf.burn_in) * kmax_all > INT32_MAX)
+    return fail(c, FSMP_EINVAL, "occupancy counts could exceed int32 (n_chains x recorded sweeps x kmax >= 2^31)");
   // ---- chains grouped by PE capacity
   const int *caps = kCaps;
   std::vector<int32_t> order;
@@ -717,6 +722,7 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   pa.mfoff = c->mfoff.p;
   pa.mf = c->mf.p;
   pa.wflags = c->wflags.p;
+  pa.occ = o->occ;
   pa.n_wave = n;
   e = timed("prologue", 0, st, [&](fsmp_timing &t) {
     t.chains = 0;
@@ -766,6 +772,7 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   ca.kz = o->kz;
   ca.wflags = c->wflags.p;
   ca.work = o->work;
+  ca.occ = o->occ;
   ca.refresh_M = cf.refresh_M;
   ca.near_eps = 1e-3;
   ca.drift_bound = 1e-3;
@@ -1144,10 +1151,37 @@ fsmp_status fsmp_posterior(fsmp_ctx *c, int64_t n_wave, const fsmp_samples *in, 
   a.p_n = out->p_n;
   a.accept = out->accept;
   a.status = out->status;
+  if (out->occupancy) {
+    if (!in->occ || !out->offsets) return fail(c, FSMP_EINVAL, "occupancy needs fsmp_samples.occ and the batch offsets");
+    if (out->offsets[0] != 0) return fail(c, FSMP_EINVAL, "offsets[0] must be 0");
+    for (int64_t i = 0; i < n_wave; ++i)
+      if (out->offsets[i + 1] < out->offsets[i]) return fail(c, FSMP_EINVAL, "offsets must be non-decreasing");
+  }
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(c->device);
-  hipError_t e = launch_posterior(a, (hipStream_t)hip_stream);
+  hipError_t e = hipSuccess;
+  if (out->occupancy) {
+    // the row offsets go up through the pinned stage, after the previous upload is done
+    const hipStream_t st = (hipStream_t)hip_stream;
+    const size_t nb = sizeof(int64_t) * (n_wave + 1);
+    if (c->stage_pending) (void)hipEventSynchronize(c->stage_done);
+    e = c->poff.ensure(n_wave + 1);
+    if (e == hipSuccess) e = c->stage.ensure(nb);
+    if (e != hipSuccess) {
+      (void)hipSetDevice(prev);
+      return fail(c, FSMP_ENOMEM, "posterior workspace allocation failed: %s", hipGetErrorString(e));
+    }
+    std::memcpy(c->stage.p, out->offsets, nb);
+    e = hipMemcpyAsync(c->poff.p, c->stage.p, nb, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(c->stage_done, st);
+    c->stage_pending = (e == hipSuccess);
+    a.occ = in->occ;
+    a.occupancy = out->occupancy;
+    a.woff = c->poff.p;
+    a.sub = c->cfg.grid_sub;
+  }
+  if (e == hipSuccess) e = launch_posterior(a, (hipStream_t)hip_stream);
   (void)hipSetDevice(prev);
   if (e != hipSuccess) return fail(c, FSMP_EDEVICE, "posterior launch failed: %s", hipGetErrorString(e));
   return FSMP_OK;

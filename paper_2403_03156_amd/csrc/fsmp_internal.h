@@ -84,6 +84,9 @@ struct ChainArgs {
   // of recorded sweeps (output, or NULL)
   const int32_t *wsteps;
   int32_t *rec_steps;
+  // grid occupancy rows (zeroed by the prologue), or null: row of waveform w at
+  // md.sub * woff[w], one count per grid point
+  int32_t *occ;
 };
 
 struct PrologueArgs {
@@ -95,6 +98,7 @@ struct PrologueArgs {
   const int64_t *mfoff;
   double *mf;
   uint32_t *wflags;  // per waveform: bit1 non-finite sample
+  int32_t *occ;      // grid occupancy rows to zero, or null
   int64_t n_wave;
 };
 
@@ -108,6 +112,12 @@ struct PosteriorArgs {
   const int32_t *rec_steps;  // per chain recorded sweeps, or NULL (n_steps - burn_in)
   double *mean, *var, *mcse, *p_n, *accept;
   uint32_t *status;
+  // optional grid occupancy: counts in, expected PEs per grid point out (rows of sub * L_w
+  // points at sub * woff[w], woff on the device)
+  const int32_t *occ;
+  double *occupancy;
+  const int64_t *woff;
+  int32_t sub;
 };
 
 // Launchers (fsmp_kernels.hip).  Each returns hipSuccess or the launch error.

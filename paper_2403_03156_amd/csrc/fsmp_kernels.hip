@@ -231,6 +231,23 @@ __device__ inline int birth_draw(const ModelDev &md, double t0, int glo, int ghi
   return (int)(p.gs + k);
 }
 
+// ------------------------------------------------------------------ grid occupancy
+// The occupancy row of waveform w (grid_sub * L_w points from grid_sub * offsets[w]) counts,
+// over its chains' recorded sweeps, the PEs at every grid point.  It is accumulated by
+// residence instead of per sweep: a PE that arrives in sweep s is present at the end of
+// the sweeps s .. n_steps - 1, so it adds the recorded ones among them, n_steps - max(s,
+// burn); one that leaves in sweep s removes the same amount.  The sum over a PE's arrival
+// and departure is its number of recorded sweeps at that point, PEs still present at the
+// end keep their arrival's count, and a chain starts empty.  Edits that cancel (both before
+// burn-in) cost two atomics; nothing waits for the adds.
+__device__ inline void occ_edit(int32_t *occ, int64_t row, int move, int gj, int gnew, int step, int burn,
+                                int n_steps) {
+  const int rem = n_steps - (step > burn ? step : burn);
+  if (!occ || rem <= 0) return;
+  if (move != 1) atomicAdd(occ + row + gj, -rem);
+  if (move != 2) atomicAdd(occ + row + gnew, rem);
+}
+
 // ------------------------------------------------------------------ prologue
 __global__ void __launch_bounds__(256) prologue_kernel(PrologueArgs a) {
   extern __shared__ double vt[];
@@ -245,6 +262,8 @@ __global__ void __launch_bounds__(256) prologue_kernel(PrologueArgs a) {
       if (!isfinite(x[n])) bad = 1;
     bad = __syncthreads_or(bad);
     if (threadIdx.x == 0) a.wflags[w] = bad ? FSMP_ST_NONFINITE : 0u;
+    if (a.occ)
+      for (int64_t g = threadIdx.x; g < (int64_t)md.sub * Lw; g += blockDim.x) a.occ[md.sub * a.woff[w] + g] = 0;
     const int glo = a.grange[2 * w], ghi = a.grange[2 * w + 1];
     double *out = a.mf + a.mfoff[w];
     for (int g = glo + (int)threadIdx.x; g <= ghi; g += blockDim.x) {
@@ -660,6 +679,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         const double inv_om = move == 1 ? 0.0 : 1.0 / om;
         const double xn = up * inv_d2;
         const int gj = move == 1 ? -1 : zg[j];
+        if (lane == 0) occ_edit(a.occ, md.sub * a.woff[w], move, gj, gnew, step, burn, n_steps);
         if (move != 1) {
           for (int i = lane; i < N; i += LPC) s1[i] = H[(j * LD + i) * HS];  // h = row j of H
           WAVE_SYNC();
@@ -1347,6 +1367,7 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
         const double inv_om = move == 1 ? 0.0 : 1.0 / om;
         const double xn = up * inv_d2;
         const int gj = move == 1 ? -1 : ZG(j);
+        occ_edit(a.occ, md.sub * a.woff[w], move, gj, gnew, step, burn, n_steps);
         if (move != 1) lane_copy(S3, Hp + (int64_t)j * KCAP * 64, N);  // h = row j of H
         if (shift)
           for (int i = 0; i < N; ++i) G2(i) = (i == j) ? 0.0 : G2(i) - G3(i) * ej * inv_om;
@@ -1497,6 +1518,17 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
 }
 
 // ------------------------------------------------------------------ posterior
+// Expected number of PEs at every grid point: the occupancy counts of a waveform's chains
+// over its recorded (chain, sweep) pairs; one workgroup per waveform, coalesced over its row.
+__global__ void __launch_bounds__(256) occupancy_kernel(PosteriorArgs a) {
+  for (int64_t w = blockIdx.x; w < a.n_wave; w += gridDim.x) {
+    const int S = a.rec_steps ? a.rec_steps[w * a.n_chains] : a.n_steps - a.burn_in;
+    const double inv = S > 0 ? 1.0 / ((double)S * a.n_chains) : 0.0;
+    const int64_t b = (int64_t)a.sub * a.woff[w], e = (int64_t)a.sub * a.woff[w + 1];
+    for (int64_t g = b + threadIdx.x; g < e; g += blockDim.x) a.occupancy[g] = (double)a.occ[g] * inv;
+  }
+}
+
 __global__ void __launch_bounds__(256) posterior_kernel(PosteriorArgs a) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= a.n_wave) return;
@@ -1600,7 +1632,13 @@ hipError_t launch_posterior(const PosteriorArgs &a, hipStream_t st) {
   if (a.n_wave == 0) return hipSuccess;
   const int64_t nb = (a.n_wave + 255) / 256;
   hipLaunchKernelGGL(posterior_kernel, dim3((unsigned)nb), dim3(256), 0, st, a);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && a.occupancy) {
+    const int64_t nw = a.n_wave < 65535 * 8 ? a.n_wave : 65535 * 8;
+    hipLaunchKernelGGL(occupancy_kernel, dim3((unsigned)nw), dim3(256), 0, st, a);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 int chain_kcap_for(int kmax) {

@@ -58,12 +58,14 @@ class fsmp_samples(ctypes.Structure):
                 ("charge", ctypes.c_void_p), ("acc", ctypes.c_void_p), ("nhist", ctypes.c_void_p),
                 ("counts", ctypes.c_void_p), ("status", ctypes.c_void_p), ("log", ctypes.c_void_p),
                 ("trace", ctypes.c_void_p), ("kz", ctypes.c_int32), ("work", ctypes.c_void_p),
-                ("qdraw", ctypes.c_void_p), ("zdraw", ctypes.c_void_p), ("rec_steps", ctypes.c_void_p)]
+                ("qdraw", ctypes.c_void_p), ("zdraw", ctypes.c_void_p), ("rec_steps", ctypes.c_void_p),
+                ("occ", ctypes.c_void_p)]
 
 
 class fsmp_posterior_out(ctypes.Structure):
     _fields_ = [("mean", ctypes.c_void_p), ("var", ctypes.c_void_p), ("mcse", ctypes.c_void_p),
-                ("p_n", ctypes.c_void_p), ("accept", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+                ("p_n", ctypes.c_void_p), ("accept", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("occupancy", ctypes.c_void_p), ("offsets", ctypes.c_void_p)]
 
 
 class fsmp_server_config(ctypes.Structure):
@@ -219,7 +221,8 @@ class Sampler:
         return [{"name": t.name.decode(), "kcap": t.kcap, "lanes": t.lanes, "chains": t.chains, "blocks": t.blocks,
                  "ms": t.ms} for t in arr[:n]]
 
-    def alloc_samples(self, n_wave, kz, work=False):
+    def alloc_samples(self, n_wave, kz, work=False, occ_len=0):
+        """Device output buffers; occ_len > 0 adds the grid occupancy (grid_sub * offsets[-1])."""
         import torch
         dev = torch.device("cuda", self.device)
         C = n_wave * self.cfg.n_chains
@@ -236,6 +239,7 @@ class Sampler:
             "rec_steps": torch.zeros(C, dtype=torch.int32, device=dev),
             "log": None, "trace": None, "kz": kz,
             "work": torch.zeros((C, 4), dtype=torch.float64, device=dev) if work else None,
+            "occ": torch.zeros(occ_len, dtype=torch.int32, device=dev) if occ_len > 0 else None,
         }
         if self.cfg.record_flags & FSMP_REC_LOG:
             out["log"] = torch.zeros((C, self.cfg.n_steps * LOGREC_DTYPE.itemsize), dtype=torch.uint8, device=dev)
@@ -289,7 +293,8 @@ class Sampler:
         return fsmp_samples(_dptr(out["n_pe"]), _dptr(out["t0"]), _dptr(out["z"]), _dptr(out["charge"]),
                             _dptr(out["acc"]), _dptr(out["nhist"]), _dptr(out["counts"]), _dptr(out["status"]),
                             _dptr(out["log"]), _dptr(out["trace"]), out["kz"], _dptr(out.get("work")),
-                            _dptr(out.get("qdraw")), _dptr(out.get("zdraw")), _dptr(out.get("rec_steps")))
+                            _dptr(out.get("qdraw")), _dptr(out.get("zdraw")), _dptr(out.get("rec_steps")),
+                            _dptr(out.get("occ")))
 
     def set_design(self, capacity, design):
         self._check(self.lib.fsmp_set_design(self.h, capacity, design))
@@ -319,7 +324,7 @@ class Sampler:
                                                ctypes.byref(g)))
         return Graph(self, g, keep), out
 
-    def replay(self, wave, offsets, lam, log, kmax=None, kz=None, stream=None):
+    def replay(self, wave, offsets, lam, log, kmax=None, kz=None, stream=None, occupancy=False):
         """Follow recorded proposals (``log``: device uint8 [chains, n_steps * 40] or a structured
         host array [chains, n_steps] of LOGREC_DTYPE); returns (dnu, log_alpha, out) on the device."""
         import torch
@@ -336,7 +341,7 @@ class Sampler:
             log = torch.from_numpy(rec.view(np.uint8).reshape(C, -1).copy()).to(dev)
         if not log.is_cuda or log.numel() != C * self.cfg.n_steps * LOGREC_DTYPE.itemsize:
             raise ValueError("log must hold one record per chain and step")
-        out = self.alloc_samples(n, kz)
+        out = self.alloc_samples(n, kz, occ_len=self.cfg.grid_sub * int(keep[0][-1]) if occupancy else 0)
         dnu = torch.zeros((C, self.cfg.n_steps), dtype=torch.float64, device=dev)
         la = torch.zeros((C, self.cfg.n_steps), dtype=torch.float64, device=dev)
         s = self._samples(out)
@@ -347,9 +352,10 @@ class Sampler:
         return dnu, la, out
 
     def sample(self, wave, offsets, lam, kmax=None, g_range=None, t0_init=None, wave_id=None, out=None, kz=None,
-               stream=None, work=False, n_steps=None):
+               stream=None, work=False, n_steps=None, occupancy=False):
         """wave: torch float32 device tensor; offsets/lam/kmax/g_range/t0_init/wave_id/n_steps: host numpy
-        arrays (n_steps: sweeps per waveform, at most the configured n_steps)."""
+        arrays (n_steps: sweeps per waveform, at most the configured n_steps).  occupancy: also count
+        the PEs per grid point over the recorded sweeps (out["occ"])."""
         import torch
         b, keep = self._batch(wave, offsets, lam, kmax, g_range, t0_init, wave_id, n_steps)
         n = int(b.n_wave)
@@ -357,14 +363,17 @@ class Sampler:
         if kz is None:
             kz = int(kmax.max()) if kmax is not None and n > 0 else self.cfg.k_max
         if out is None:
-            out = self.alloc_samples(n, kz, work=work)
+            out = self.alloc_samples(n, kz, work=work,
+                                     occ_len=self.cfg.grid_sub * int(keep[0][-1]) if occupancy and n > 0 else 0)
         s = self._samples(out)
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._keep = keep
         self._check(self.lib.fsmp_sample(self.h, ctypes.byref(b), ctypes.byref(s), ctypes.c_void_p(st.cuda_stream)))
         return out
 
-    def posterior(self, n_wave, samples, with_pn=True, stream=None):
+    def posterior(self, n_wave, samples, with_pn=True, stream=None, offsets=None):
+        """Per-waveform summaries (fsmp_posterior); with the batch's offsets and sampled occupancy
+        counts also the expected number of PEs per grid point ("occupancy")."""
         import torch
         dev = torch.device("cuda", self.device)
         kz = samples["kz"]
@@ -375,10 +384,15 @@ class Sampler:
             "p_n": torch.zeros((n_wave, kz + 1), dtype=torch.float64, device=dev) if with_pn else None,
             "accept": torch.zeros((n_wave, 4), dtype=torch.float64, device=dev),
             "status": torch.zeros(n_wave, dtype=torch.int32, device=dev),
+            "occupancy": None,
         }
+        hoff = None
+        if offsets is not None and samples.get("occ") is not None:
+            hoff = np.ascontiguousarray(offsets, dtype=np.int64)
+            res["occupancy"] = torch.zeros(self.cfg.grid_sub * int(hoff[-1]), dtype=torch.float64, device=dev)
         s = self._samples(samples)
         po = fsmp_posterior_out(_dptr(res["mean"]), _dptr(res["var"]), _dptr(res["mcse"]), _dptr(res["p_n"]),
-                                _dptr(res["accept"]), _dptr(res["status"]))
+                                _dptr(res["accept"]), _dptr(res["status"]), _dptr(res["occupancy"]), _hptr(hoff))
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._check(self.lib.fsmp_posterior(self.h, n_wave, ctypes.byref(s), ctypes.byref(po),
                                             ctypes.c_void_p(st.cuda_stream)))
