@@ -212,7 +212,25 @@ typedef struct {
  * the chains' status words; optionally the posterior occupancy of the grid, the expected
  * number of PEs at every grid point (fsmp_samples.occ over the waveform's recorded
  * (chain, sweep) pairs, in the same layout), which needs fsmp_samples.occ and the batch's
- * host offsets. */
+ * host offsets.
+ *
+ * Convergence (Sec. 6.2): rhat is the potential scale reduction of Gelman and Rubin over the
+ * waveform's C chains of S recorded sweeps, without the degrees-of-freedom factor or chain
+ * splitting: with chain means m_i and unbiased chain variances s_i^2, W = mean s_i^2,
+ * B = S / (C - 1) sum_i (m_i - m)^2, R = sqrt(((S - 1) / S W + B / S) / W); 1 when every chain
+ * is constant at one value, inf when they are constant at different values, NaN for C < 2
+ * or S < 2.  The batch-means mcse reads only within-chain correlation and underestimates
+ * the error of short, slowly mixing chains; mcse_chains does not, given enough chains.
+ *
+ * lambda_hat (Sec. 2.2, eq. reduce-mu0): the maximiser over lambda >= 0 of
+ * f(lambda) = -(lambda - lambda0) + log sum_k h_k (lambda / lambda0)^k, h the waveform's
+ * N histogram over all chains (the whole-line normaliser e^-lambda of eq. pzmu).  Its
+ * maxima solve lambda = m(lambda), the mean of k under the weights h_k (lambda / lambda0)^k,
+ * with d = m - lambda going from + to -; all lie between the smallest and largest sampled
+ * N (k_lo, k_hi).  A single sampled N is returned as is; otherwise d is evaluated on 64
+ * evenly spaced points of [k_lo, k_hi], every interval where d goes from > 0 to <= 0 is
+ * bisected to the root, lambda = 0 is a candidate when k_lo = 0 and d <= 0 at the second
+ * point, and the candidate with the largest f wins (the smallest of equals). */
 typedef struct {
   double *mean;      /* [n_wave][3] */
   double *var;       /* [n_wave][3] */
@@ -222,6 +240,12 @@ typedef struct {
   uint32_t *status;  /* [n_wave] */
   double *occupancy; /* NULL, or grid_sub * offsets[n_wave] doubles, rows as fsmp_samples.occ */
   const int64_t *offsets; /* host, n_wave + 1: the batch's sample offsets (with occupancy) */
+  double *rhat;        /* NULL, or [n_wave][3]: Gelman-Rubin R of N, Q, t0 (see below) */
+  double *mcse_chains; /* NULL, or [n_wave][3]: MCSE of the pooled means from the spread of the
+                          chain means, sqrt(sum_i (m_i - m)^2 / (C (C - 1))); NaN for C < 2 */
+  double *lambda_hat;  /* NULL, or [n_wave][2]: lambda-hat_FSMP (eq. reduce-mu0) and
+                          lambda-hat_Q = E[Q] / mu_q */
+  const double *lambda; /* host, n_wave: the batch's lambda0 (with lambda_hat) */
 } fsmp_posterior_out;
 
 /* Timing of the kernels of the last fsmp_sample call (HIP events on its stream). */

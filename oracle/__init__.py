@@ -259,3 +259,92 @@ def summarize(acc, n_steps, burn_in, n_chains):
         bm_var = np.maximum((bsq / lb ** 2 - B * bm_mean ** 2) / max(B - 1, 1), 0.0)
         out[name] = (mean, var, np.sqrt(bm_var / B))
     return out
+
+
+def chain_diagnostics(acc, S, n_chains):
+    """Per waveform and for each of (N, Q, t0), from the per-chain sums of v and v^2 over
+    S recorded sweeps:
+
+    * the Gelman-Rubin potential scale reduction (Sec. 6.2 convergence check; the form of
+      Gelman and Rubin 1992 without the degrees-of-freedom factor or chain splitting):
+      chain means m_i and unbiased chain variances s_i^2, W = mean of s_i^2,
+      B = S / (C - 1) sum_i (m_i - m)^2, V = (S - 1) / S W + B / S, R = sqrt(V / W);
+      R = 1 when V = W = 0 (every chain constant at one value), inf when only W = 0,
+      NaN with fewer than 2 chains or 2 sweeps;
+    * the Monte Carlo error of the pooled mean from the spread of the chain means,
+      sqrt(sum_i (m_i - m)^2 / (C (C - 1))) (NaN with fewer than 2 chains).
+    Returns (rhat [n_wave, 3], mcse_chains [n_wave, 3])."""
+    acc = np.asarray(acc, np.float64).reshape(-1, n_chains, 12)
+    nw = acc.shape[0]
+    rhat = np.full((nw, 3), np.nan)
+    mcb = np.full((nw, 3), np.nan)
+    if n_chains < 2:
+        return rhat, mcb
+    for a in range(3):
+        m = acc[:, :, 2 * a] / S
+        dev2 = ((m - m.mean(1, keepdims=True)) ** 2).sum(1)
+        mcb[:, a] = np.sqrt(dev2 / (n_chains * (n_chains - 1)))
+        if S < 2:
+            continue
+        s2 = np.maximum((acc[:, :, 2 * a + 1] - S * m * m) / (S - 1), 0.0)
+        W = s2.mean(1)
+        B = S * dev2 / (n_chains - 1)
+        V = (S - 1) / S * W + B / S
+        with np.errstate(divide="ignore", invalid="ignore"):
+            r = np.sqrt(V / W)
+        r[(W == 0) & (V == 0)] = 1.0
+        r[(W == 0) & (V > 0)] = np.inf
+        rhat[:, a] = r
+    return rhat, mcb
+
+
+def lambda_mle(hist, lam0, n_grid=64):
+    """lambda-hat of eq. reduce-mu0: the maximiser over lambda >= 0 of
+        f(lambda) = -(lambda - lambda0) + log sum_k h_k (lambda / lambda0)^k,
+    the importance-sampling estimate of log p(w | lambda, t0) from the sampled PE counts
+    (h_k: the sweeps with N = k, any normalisation; the whole-line normaliser e^-lambda of
+    eq. pzmu).  Stationary points solve d(lambda) = m(lambda) - lambda = 0, m the mean of k
+    under the weights h_k (lambda / lambda0)^k; the maxima are where d goes from + to -, and
+    all lie between the smallest and largest k with h_k > 0 (k_lo, k_hi).
+    Steps: a single support point k gives k; otherwise d on n_grid evenly spaced points of
+    [k_lo, k_hi]; every grid interval with d > 0 at its left end and d <= 0 at its right
+    end holds a maximum, found by scipy's brentq to 1e-14; lambda = 0 is a candidate too
+    when k_lo = 0 and d <= 0 at the second grid point; the candidate with the largest f
+    wins (the smallest lambda of equals)."""
+    from scipy.optimize import brentq
+    h = np.asarray(hist, np.float64)
+    ks = np.nonzero(h > 0)[0]
+    if len(ks) == 0:
+        return np.nan
+    k_lo, k_hi = float(ks[0]), float(ks[-1])
+    if k_lo == k_hi:
+        return k_lo
+    k = np.arange(len(h), dtype=np.float64)
+    lh = np.full(len(h), -np.inf)
+    lh[h > 0] = np.log(h[h > 0])
+
+    def tilt(lam):
+        # log-weights of the tilted law; lambda = 0 keeps k = 0 only
+        a = np.where(k == 0, lh, -np.inf) if lam == 0.0 else lh + k * np.log(lam / lam0)
+        mx = a.max()
+        return mx, np.exp(a - mx)
+
+    def f(lam):
+        mx, e = tilt(lam)
+        return -(lam - lam0) + mx + np.log(e.sum())
+
+    def d(lam):
+        _, e = tilt(lam)
+        return (k * e).sum() / e.sum() - lam
+
+    grid = k_lo + (k_hi - k_lo) * np.arange(n_grid) / (n_grid - 1)
+    dv = np.array([d(x) for x in grid])
+    cand = []
+    if k_lo == 0.0 and dv[1] <= 0:
+        cand.append(0.0)
+    for i in range(n_grid - 1):
+        if dv[i] > 0 and dv[i + 1] <= 0:
+            cand.append(grid[i + 1] if dv[i + 1] == 0 else brentq(d, grid[i], grid[i + 1], xtol=1e-14, rtol=1e-14,
+                                                                   maxiter=500))
+    fv = [f(x) for x in cand]
+    return cand[int(np.argmax(fv))]

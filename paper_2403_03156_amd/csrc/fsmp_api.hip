@@ -157,6 +157,7 @@ struct fsmp_ctx {
   DevBuf<uint64_t> wid;
   DevBuf<int32_t> wsteps;  // per-waveform sweeps (fsmp_batch.n_steps)
   DevBuf<int64_t> poff;    // fsmp_posterior: the batch offsets of the occupancy rows
+  DevBuf<double> plam;     // fsmp_posterior: lambda0 per waveform for lambda-hat
   DevBuf<uint32_t> wflags;
   DevBuf<double> lane_d;
   DevBuf<int32_t> lane_i;
@@ -424,6 +425,7 @@ void fsmp_destroy(fsmp_ctx *c) {
   if (c->d_ovl) (void)hipFree(c->d_ovl);
   c->woff.release();
   c->poff.release();
+  c->plam.release();
   c->mfoff.release();
   c->lam.release();
   c->t0init.release();
@@ -1157,29 +1159,49 @@ fsmp_status fsmp_posterior(fsmp_ctx *c, int64_t n_wave, const fsmp_samples *in, 
     for (int64_t i = 0; i < n_wave; ++i)
       if (out->offsets[i + 1] < out->offsets[i]) return fail(c, FSMP_EINVAL, "offsets must be non-decreasing");
   }
+  if (out->lambda_hat) {
+    if (!out->lambda) return fail(c, FSMP_EINVAL, "lambda_hat needs the batch's lambda0");
+    for (int64_t i = 0; i < n_wave; ++i)
+      if (!(out->lambda[i] >= 0.0) || !std::isfinite(out->lambda[i]))
+        return fail(c, FSMP_EINVAL, "waveform %lld: lambda0 must be finite and >= 0", (long long)i);
+  }
+  a.rhat = out->rhat;
+  a.mcse_chains = out->mcse_chains;
+  a.lambda_hat = out->lambda_hat;
+  a.mu_q = c->cfg.mu_q;
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(c->device);
   hipError_t e = hipSuccess;
-  if (out->occupancy) {
-    // the row offsets go up through the pinned stage, after the previous upload is done
+  if (out->occupancy || out->lambda_hat) {
+    // the row offsets and lambda0 go up through the pinned stage, after the previous upload
     const hipStream_t st = (hipStream_t)hip_stream;
-    const size_t nb = sizeof(int64_t) * (n_wave + 1);
+    const size_t nbo = out->occupancy ? sizeof(int64_t) * (n_wave + 1) : 0;
+    const size_t nbl = out->lambda_hat ? sizeof(double) * n_wave : 0;
     if (c->stage_pending) (void)hipEventSynchronize(c->stage_done);
-    e = c->poff.ensure(n_wave + 1);
-    if (e == hipSuccess) e = c->stage.ensure(nb);
+    if (nbo) e = c->poff.ensure(n_wave + 1);
+    if (e == hipSuccess && nbl) e = c->plam.ensure(n_wave);
+    if (e == hipSuccess) e = c->stage.ensure(nbo + nbl);
     if (e != hipSuccess) {
       (void)hipSetDevice(prev);
       return fail(c, FSMP_ENOMEM, "posterior workspace allocation failed: %s", hipGetErrorString(e));
     }
-    std::memcpy(c->stage.p, out->offsets, nb);
-    e = hipMemcpyAsync(c->poff.p, c->stage.p, nb, hipMemcpyHostToDevice, st);
+    char *sp = (char *)c->stage.p;
+    if (nbo) {
+      std::memcpy(sp, out->offsets, nbo);
+      e = hipMemcpyAsync(c->poff.p, sp, nbo, hipMemcpyHostToDevice, st);
+      a.occ = in->occ;
+      a.occupancy = out->occupancy;
+      a.woff = c->poff.p;
+      a.sub = c->cfg.grid_sub;
+    }
+    if (e == hipSuccess && nbl) {
+      std::memcpy(sp + nbo, out->lambda, nbl);
+      e = hipMemcpyAsync(c->plam.p, sp + nbo, nbl, hipMemcpyHostToDevice, st);
+      a.lam0 = c->plam.p;
+    }
     if (e == hipSuccess) e = hipEventRecord(c->stage_done, st);
     c->stage_pending = (e == hipSuccess);
-    a.occ = in->occ;
-    a.occupancy = out->occupancy;
-    a.woff = c->poff.p;
-    a.sub = c->cfg.grid_sub;
   }
   if (e == hipSuccess) e = launch_posterior(a, (hipStream_t)hip_stream);
   (void)hipSetDevice(prev);

@@ -118,6 +118,11 @@ struct PosteriorArgs {
   double *occupancy;
   const int64_t *woff;
   int32_t sub;
+  // optional chain diagnostics [n_wave][3] and lambda estimates [n_wave][2] (lambda0 per
+  // waveform on the device, mu_q of the charge model)
+  double *rhat, *mcse_chains, *lambda_hat;
+  const double *lam0;
+  double mu_q;
 };
 
 // Launchers (fsmp_kernels.hip).  Each returns hipSuccess or the launch error.

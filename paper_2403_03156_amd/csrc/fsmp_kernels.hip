@@ -1585,6 +1585,125 @@ __global__ void __launch_bounds__(256) posterior_kernel(PosteriorArgs a) {
   a.status[w] = st;
 }
 
+// ---- posterior extras: chain diagnostics and the lambda estimates, one thread per waveform
+
+// d(lambda) = m(lambda) - lambda, m the mean of k under the weights h_k (lambda / lambda0)^k
+// (computed from the largest log-weight down); with `f` also the log-likelihood estimate
+// f(lambda) = -(lambda - lambda0) + log sum_k h_k (lambda / lambda0)^k.  lambda = 0 keeps k = 0.
+__device__ inline double lam_tilt(const int32_t *nh, int C, int kz1, int k_lo, int k_hi, double lam, double lam0,
+                                  double *f) {
+  const double lr = lam > 0.0 ? log(lam / lam0) : 0.0;
+  const int top = lam > 0.0 ? k_hi : 0;
+  double mx = -INFINITY;
+  for (int k = k_lo; k <= top; ++k) {
+    double h = 0.0;
+    for (int ch = 0; ch < C; ++ch) h += nh[ch * kz1 + k];
+    if (h > 0.0) mx = fmax(mx, log(h) + k * lr);
+  }
+  double se = 0.0, sk = 0.0;
+  for (int k = k_lo; k <= top; ++k) {
+    double h = 0.0;
+    for (int ch = 0; ch < C; ++ch) h += nh[ch * kz1 + k];
+    if (h > 0.0) {
+      const double e = exp(log(h) + k * lr - mx);
+      se += e;
+      sk += k * e;
+    }
+  }
+  if (f) *f = -(lam - lam0) + mx + log(se);
+  return sk / se - lam;
+}
+
+__global__ void __launch_bounds__(256) posterior_extra_kernel(PosteriorArgs a) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= a.n_wave) return;
+  const int C = a.n_chains;
+  const int S = a.rec_steps ? a.rec_steps[w * C] : a.n_steps - a.burn_in;
+  // Gelman-Rubin R and the Monte Carlo error from the spread of the chain means
+  for (int v = 0; v < 3; ++v) {
+    double msum = 0.0;
+    for (int ch = 0; ch < C; ++ch) msum += a.acc[(w * C + ch) * 12 + 2 * v] / S;
+    const double mbar = msum / C;
+    double dev2 = 0.0, wsum = 0.0;
+    for (int ch = 0; ch < C; ++ch) {
+      const double *ac = a.acc + (w * C + ch) * 12;
+      const double m = ac[2 * v] / S;
+      dev2 += (m - mbar) * (m - mbar);
+      wsum += fmax((ac[2 * v + 1] - S * m * m) / (S - 1), 0.0);
+    }
+    double r = NAN, mc = NAN;
+    if (C >= 2 && S >= 1) mc = sqrt(dev2 / ((double)C * (C - 1)));
+    if (C >= 2 && S >= 2) {
+      const double W = wsum / C;
+      const double B = S * dev2 / (C - 1);
+      const double V = (double)(S - 1) / S * W + B / S;
+      r = W > 0.0 ? sqrt(V / W) : (V > 0.0 ? INFINITY : 1.0);
+    }
+    if (a.rhat) a.rhat[w * 3 + v] = r;
+    if (a.mcse_chains) a.mcse_chains[w * 3 + v] = mc;
+  }
+  if (!a.lambda_hat) return;
+  // lambda-hat: the + to - crossings of d on 64 grid points of [k_lo, k_hi], each refined by
+  // bisection, and lambda = 0 when k_lo = 0 and d <= 0 at the second point; the largest f wins
+  const int kz1 = a.kz + 1;
+  const int32_t *nh = a.nhist + w * C * kz1;
+  int k_lo = -1, k_hi = -1;
+  for (int k = 0; k < kz1; ++k) {
+    int32_t h = 0;
+    for (int ch = 0; ch < C; ++ch) h += nh[ch * kz1 + k];
+    if (h > 0) {
+      if (k_lo < 0) k_lo = k;
+      k_hi = k;
+    }
+  }
+  double est = NAN;
+  const double lam0 = a.lam0[w];
+  if (k_lo >= 0 && k_lo == k_hi) {
+    est = k_lo;
+  } else if (k_lo >= 0) {
+    constexpr int kGrid = 64;
+    const double span = (double)(k_hi - k_lo);
+    double best_f = -INFINITY;
+    double dprev = 0.0;
+    for (int i = 0; i < kGrid; ++i) {
+      const double x = k_lo + span * i / (kGrid - 1);
+      const double dx = lam_tilt(nh, C, kz1, k_lo, k_hi, x, lam0, nullptr);
+      double cand = NAN;
+      if (i == 1 && k_lo == 0 && dx <= 0.0) {
+        double f0;
+        (void)lam_tilt(nh, C, kz1, k_lo, k_hi, 0.0, lam0, &f0);
+        if (f0 > best_f) {
+          best_f = f0;
+          est = 0.0;
+        }
+      }
+      if (i > 0 && dprev > 0.0 && dx <= 0.0) {
+        if (dx == 0.0) {
+          cand = x;
+        } else {
+          double lo = k_lo + span * (i - 1) / (kGrid - 1), hi = x;
+          for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (!(mid > lo && mid < hi)) break;
+            if (lam_tilt(nh, C, kz1, k_lo, k_hi, mid, lam0, nullptr) > 0.0) lo = mid;
+            else hi = mid;
+          }
+          cand = 0.5 * (lo + hi);
+        }
+        double fc;
+        (void)lam_tilt(nh, C, kz1, k_lo, k_hi, cand, lam0, &fc);
+        if (fc > best_f) {
+          best_f = fc;
+          est = cand;
+        }
+      }
+      dprev = dx;
+    }
+  }
+  a.lambda_hat[w * 2] = est;
+  a.lambda_hat[w * 2 + 1] = a.mean[w * 3 + 1] / a.mu_q;  // lambda-hat_Q = E[Q] / mu_q
+}
+
 template <int KCAP, int LPC, int WPB, bool HG, bool FORCE = false, bool F32 = false>
 hipError_t launch_chain_t(const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
   constexpr int CPB = WPB * (kWave / LPC);
@@ -1633,6 +1752,10 @@ hipError_t launch_posterior(const PosteriorArgs &a, hipStream_t st) {
   const int64_t nb = (a.n_wave + 255) / 256;
   hipLaunchKernelGGL(posterior_kernel, dim3((unsigned)nb), dim3(256), 0, st, a);
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess && (a.rhat || a.mcse_chains || a.lambda_hat)) {
+    hipLaunchKernelGGL(posterior_extra_kernel, dim3((unsigned)nb), dim3(256), 0, st, a);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess && a.occupancy) {
     const int64_t nw = a.n_wave < 65535 * 8 ? a.n_wave : 65535 * 8;
     hipLaunchKernelGGL(occupancy_kernel, dim3((unsigned)nw), dim3(256), 0, st, a);

@@ -65,7 +65,8 @@ class fsmp_samples(ctypes.Structure):
 class fsmp_posterior_out(ctypes.Structure):
     _fields_ = [("mean", ctypes.c_void_p), ("var", ctypes.c_void_p), ("mcse", ctypes.c_void_p),
                 ("p_n", ctypes.c_void_p), ("accept", ctypes.c_void_p), ("status", ctypes.c_void_p),
-                ("occupancy", ctypes.c_void_p), ("offsets", ctypes.c_void_p)]
+                ("occupancy", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("rhat", ctypes.c_void_p),
+                ("mcse_chains", ctypes.c_void_p), ("lambda_hat", ctypes.c_void_p), ("lambda_", ctypes.c_void_p)]
 
 
 class fsmp_server_config(ctypes.Structure):
@@ -371,9 +372,11 @@ class Sampler:
         self._check(self.lib.fsmp_sample(self.h, ctypes.byref(b), ctypes.byref(s), ctypes.c_void_p(st.cuda_stream)))
         return out
 
-    def posterior(self, n_wave, samples, with_pn=True, stream=None, offsets=None):
+    def posterior(self, n_wave, samples, with_pn=True, stream=None, offsets=None, diagnostics=False, lam=None):
         """Per-waveform summaries (fsmp_posterior); with the batch's offsets and sampled occupancy
-        counts also the expected number of PEs per grid point ("occupancy")."""
+        counts also the expected number of PEs per grid point ("occupancy"); with diagnostics the
+        Gelman-Rubin R and the between-chain MCSE ("rhat", "mcse_chains"); with the batch's lambda0
+        the estimates lambda-hat_FSMP and lambda-hat_Q ("lambda_hat")."""
         import torch
         dev = torch.device("cuda", self.device)
         kz = samples["kz"]
@@ -385,14 +388,19 @@ class Sampler:
             "accept": torch.zeros((n_wave, 4), dtype=torch.float64, device=dev),
             "status": torch.zeros(n_wave, dtype=torch.int32, device=dev),
             "occupancy": None,
+            "rhat": torch.zeros((n_wave, 3), dtype=torch.float64, device=dev) if diagnostics else None,
+            "mcse_chains": torch.zeros((n_wave, 3), dtype=torch.float64, device=dev) if diagnostics else None,
+            "lambda_hat": torch.zeros((n_wave, 2), dtype=torch.float64, device=dev) if lam is not None else None,
         }
+        hlam = None if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
         hoff = None
         if offsets is not None and samples.get("occ") is not None:
             hoff = np.ascontiguousarray(offsets, dtype=np.int64)
             res["occupancy"] = torch.zeros(self.cfg.grid_sub * int(hoff[-1]), dtype=torch.float64, device=dev)
         s = self._samples(samples)
         po = fsmp_posterior_out(_dptr(res["mean"]), _dptr(res["var"]), _dptr(res["mcse"]), _dptr(res["p_n"]),
-                                _dptr(res["accept"]), _dptr(res["status"]), _dptr(res["occupancy"]), _hptr(hoff))
+                                _dptr(res["accept"]), _dptr(res["status"]), _dptr(res["occupancy"]), _hptr(hoff),
+                                _dptr(res["rhat"]), _dptr(res["mcse_chains"]), _dptr(res["lambda_hat"]), _hptr(hlam))
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._check(self.lib.fsmp_posterior(self.h, n_wave, ctypes.byref(s), ctypes.byref(po),
                                             ctypes.c_void_p(st.cuda_stream)))
