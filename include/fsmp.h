@@ -122,7 +122,15 @@ typedef struct {
  * identity that keys the random stream (default: the index in the batch); n_steps: host
  * or NULL, sweeps per waveform (1..cfg.n_steps; NULL = cfg.n_steps for all), each with
  * burn-in floor(n_steps * cfg.burn_in / cfg.n_steps) -- it needs fsmp_samples.rec_steps
- * so that fsmp_posterior divides by each chain's own number of recorded sweeps. */
+ * so that fsmp_posterior divides by each chain's own number of recorded sweeps.
+ * z_init, z_init_offsets: host or NULL (every chain starts from the empty list), the initial
+ * PE sequence of every chain (Sec. 2.3: an initial guess of z, e.g. from a deconvolution;
+ * Sec. 6.2: chains started from different sequences): chain c = i * n_chains + k starts
+ * from the grid indices z_init[z_init_offsets[c] .. z_init_offsets[c + 1]), n_wave *
+ * n_chains + 1 offsets from 0.  Each list holds at most the waveform's kmax PEs, each inside
+ * the waveform's T where phi(g / grid_sub - t0_init) > 0, and needs lambda > 0; G^-1 and
+ * the charges of the list are built before the first sweep, which draws no random numbers
+ * for it (a chain's stream is the same as from the empty list). */
 typedef struct {
   int64_t n_wave;
   const float *wave;
@@ -133,6 +141,8 @@ typedef struct {
   const double *t0_init;
   const uint64_t *wave_id;
   const int32_t *n_steps;
+  const int32_t *z_init;
+  const int64_t *z_init_offsets;
 } fsmp_batch;
 
 /* One record per step of one chain (FSMP_REC_LOG). */

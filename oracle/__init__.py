@@ -99,7 +99,7 @@ def lib():
         L.ora_t0_log_alpha.argtypes = [_P(Params), _d, _i32, _i32, _vp, _i32, _d, _d]
         L.ora_t0_log_alpha.restype = _d
         L.ora_run.argtypes = [_P(Params), _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _u64, _i32,
-                              _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _i32]
+                              _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32]
         L.ora_charge_draw.argtypes = [_P(Params), _vp, _i32, _vp, _i32, _vp, _vp]
         L.ora_charge_draw.restype = ctypes.c_int
         L.ora_charge_normals.argtypes = [_u64, _u64, _i32, _i32, _vp]
@@ -159,14 +159,15 @@ class RunResult:
 
 
 def run(p: Params, wave, offsets, lam, n_chains, n_steps, burn_in, seed, kz, kmax=None, g_range=None, t0_init=None,
-        wave_id=None, log=False, thin=0, n_threads=0, charges=False, occupancy=False):
+        wave_id=None, log=False, thin=0, n_threads=0, charges=False, occupancy=False, z_init=None):
     """Run ``n_chains`` chains per waveform; outputs are per chain (index wave*n_chains + chain).
 
     ``thin`` > 0 records (N, t0, Q) every thin-th step after burn-in into ``trace``; with
     ``charges`` it also records the PE list (``zdraw``) and one charge draw (``qdraw``).
     ``occupancy`` gives ``occ``: per waveform the sub * L_i grid points (the waveform's row
     starts at sub * offsets[i]), the number of (chain, recorded sweep) pairs with a PE there,
-    PEs counted with multiplicity (``occ_chain`` keeps the per-chain rows)."""
+    PEs counted with multiplicity (``occ_chain`` keeps the per-chain rows).  ``z_init``: None
+    (empty start) or one initial PE list (grid indices) per chain."""
     wave = np.ascontiguousarray(wave, dtype=np.float32)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     lam = np.ascontiguousarray(lam, dtype=np.float64)
@@ -191,10 +192,11 @@ def run(p: Params, wave, offsets, lam, n_chains, n_steps, burn_in, seed, kz, kma
     r.qdraw = np.zeros((tot, n_rec, kz), np.float64) if (n_rec and charges) else None
     r.zdraw = np.zeros((tot, n_rec, kz), np.int32) if (n_rec and charges) else None
     r.occ_chain = np.zeros(n_chains * p.sub * int(offsets[-1]), np.int32) if occupancy else None
+    zi, zo = flatten_lists(z_init, tot)
     lib().ora_run(ctypes.byref(p), nw, _ptr(wave), _ptr(offsets), _ptr(lam), _ptr(kmax), _ptr(g_range),
                   _ptr(t0_init), _ptr(wave_id), n_chains, n_steps, burn_in, seed, kz, _ptr(r.N), _ptr(r.t0),
                   _ptr(r.z), _ptr(r.x), _ptr(r.acc), _ptr(r.nhist), _ptr(r.counts), _ptr(r.status), _ptr(r.log),
-                  _ptr(r.trace), thin, _ptr(r.qdraw), _ptr(r.zdraw), _ptr(r.occ_chain), n_threads)
+                  _ptr(r.trace), thin, _ptr(r.qdraw), _ptr(r.zdraw), _ptr(r.occ_chain), _ptr(zi), _ptr(zo), n_threads)
     r.occ = None
     if occupancy:
         # sum the chains' rows of every waveform
@@ -205,6 +207,19 @@ def run(p: Params, wave, offsets, lam, n_chains, n_steps, burn_in, seed, kz, kma
             r.occ[p.sub * offsets[i]:p.sub * offsets[i + 1]] = \
                 r.occ_chain[base:base + n_chains * n_g].reshape(n_chains, n_g).sum(0)
     return r
+
+
+def flatten_lists(lists, n):
+    """None, or n integer lists -> (concatenated int32 values, int64 offsets n + 1)."""
+    if lists is None:
+        return None, None
+    if len(lists) != n:
+        raise ValueError(f"need {n} lists, got {len(lists)}")
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum([len(z) for z in lists])
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(z, np.int32).reshape(-1) for z in lists] +
+                                               [np.zeros(1, np.int32)]))
+    return flat, off
 
 
 def charge_draw(p: Params, w, z, xi):

@@ -602,7 +602,7 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
                           int32_t ghi, double t0_init, uint64_t uid, uint64_t seed, int32_t n_steps, int32_t burn_in,
                           int32_t kz, int32_t *N_out, double *t0_out, int32_t *z_out, double *x_out, double *acc,
                           int32_t *nhist, int32_t *counts, uint32_t *status, ora_logrec *logrec, double *trace,
-                          int32_t thin, double *qdraw, int32_t *zdraw, int32_t *occ) {
+                          int32_t thin, double *qdraw, int32_t *zdraw, int32_t *occ, const int32_t *z0, int32_t n0) {
   ora_ctx c;
   ctx_init(&c, p, tab, w, Lw);
   double dt = 1.0 / p->sub;
@@ -627,6 +627,12 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
   double bs[3] = {0.0, 0.0, 0.0};
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   if (st & ORA_ST_NONFINITE) n_steps = 0;
+  /* a given initial PE sequence (Sec. 2.3 initial guess): its nu and charges from scratch */
+  if (n_steps > 0 && n0 > 0) {
+    memcpy(z, z0, sizeof(int32_t) * n0);
+    N = n0;
+    if (nu_of(&c, z, N, &nu_cur, x)) st |= ORA_ST_FACTOR;
+  }
   for (int32_t step = 0; step < n_steps; ++step) {
     uint32_t r[8];
     uint32_t ctr0[4] = {(uint32_t)step, 0u, (uint32_t)uid, (uint32_t)(uid >> 32)};
@@ -763,13 +769,15 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
  * skip; zeroed by the caller) holds one row of sub * L_i grid points per chain,
  * chain c of waveform i at n_chains * sub * offsets[i] + c * sub * L_i: the
  * number of recorded sweeps with a PE at each grid point, PEs counted with
- * their multiplicity. */
+ * their multiplicity.  z_init / z_init_off (NULL: empty start) give chain c the
+ * initial PE list z_init[z_init_off[c] .. z_init_off[c + 1]), which the caller has
+ * checked (at most kmax PEs, inside T, phi > 0 at t0_init). */
 int ora_run(const ora_params *p, int64_t n_wave, const float *wave, const int64_t *offsets, const double *lambda,
             const int32_t *kmax, const int32_t *g_range, const double *t0_init, const uint64_t *wave_id,
             int32_t n_chains, int32_t n_steps, int32_t burn_in, uint64_t seed, int32_t kz, int32_t *N_out,
             double *t0_out, int32_t *z_out, double *x_out, double *acc, int32_t *nhist, int32_t *counts,
             uint32_t *status, ora_logrec *logrec, double *trace, int32_t thin, double *qdraw, int32_t *zdraw,
-            int32_t *occ, int32_t n_threads) {
+            int32_t *occ, const int32_t *z_init, const int64_t *z_init_off, int32_t n_threads) {
   int64_t total = n_wave * n_chains;
   int64_t n_rec = (thin > 0 && n_steps > burn_in) ? (n_steps - burn_in + thin - 1) / thin : 0;
   ora_table tab;
@@ -792,7 +800,9 @@ int ora_run(const ora_params *p, int64_t n_wave, const float *wave, const int64_
                   nhist + ic * (kz + 1), counts + ic * 8, &status[ic], logrec ? logrec + ic * n_steps : NULL,
                   trace ? trace + ic * 3 * n_rec : NULL, thin, qdraw ? qdraw + ic * kz * n_rec : NULL,
                   zdraw ? zdraw + ic * kz * n_rec : NULL,
-                  occ ? occ + n_chains * p->sub * offsets[i] + (int64_t)ch * p->sub * Lw : NULL);
+                  occ ? occ + n_chains * p->sub * offsets[i] + (int64_t)ch * p->sub * Lw : NULL,
+                  z_init_off ? z_init + z_init_off[ic] : NULL,
+                  z_init_off ? (int32_t)(z_init_off[ic + 1] - z_init_off[ic]) : 0);
   }
   table_free(&tab);
   return 0;

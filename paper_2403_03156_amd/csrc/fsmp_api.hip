@@ -156,6 +156,8 @@ struct fsmp_ctx {
   DevBuf<int32_t> kmax, grange, chains;
   DevBuf<uint64_t> wid;
   DevBuf<int32_t> wsteps;  // per-waveform sweeps (fsmp_batch.n_steps)
+  DevBuf<int32_t> zinit;   // initial PE lists (fsmp_batch.z_init) and their chain offsets
+  DevBuf<int64_t> zinit_off;
   DevBuf<int64_t> poff;    // fsmp_posterior: the batch offsets of the occupancy rows
   DevBuf<double> plam;     // fsmp_posterior: lambda0 per waveform for lambda-hat
   DevBuf<uint32_t> wflags;
@@ -425,6 +427,8 @@ void fsmp_destroy(fsmp_ctx *c) {
   if (c->d_ovl) (void)hipFree(c->d_ovl);
   c->woff.release();
   c->poff.release();
+  c->zinit.release();
+  c->zinit_off.release();
   c->plam.release();
   c->mfoff.release();
   c->lam.release();
@@ -477,6 +481,8 @@ size_t fsmp_workspace_bytes(const fsmp_ctx *c, const fsmp_batch *b) {
     if (cf.record_flags & FSMP_REC_CHARGE) bytes += (size_t)((cnt[q] + 63) / 64 * 64) * kCaps[q] * (kCaps[q] + 1) * 8;
   }
   bytes += (size_t)std::max<int64_t>(tmax + 1, 4 * 4096 + 1) * 16;
+  if (b->z_init_offsets && n > 0)
+    bytes += (size_t)(n * cf.n_chains + 1) * 8 + (size_t)b->z_init_offsets[n * cf.n_chains] * 4;
   return bytes;
 }
 
@@ -560,6 +566,29 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     wid[i] = b->wave_id ? b->wave_id[i] : (uint64_t)i;
     mfo[i + 1] = mfo[i] + (lo <= hi ? (int64_t)(hi - lo + 1) : 0);
   }
+  // initial PE lists: per chain at most kmax PEs, each inside T where phi(t - t0_init) > 0
+  int64_t n_init = 0;
+  if (b->z_init_offsets && n > 0) {
+    const int64_t nc = n * cf.n_chains;
+    if (b->z_init_offsets[0] != 0) return fail(c, FSMP_EINVAL, "z_init_offsets[0] must be 0");
+    if (b->z_init_offsets[nc] > 0 && !b->z_init) return fail(c, FSMP_EINVAL, "z_init is NULL");
+    for (int64_t ci = 0; ci < nc; ++ci) {
+      const int64_t i = ci / cf.n_chains, o0 = b->z_init_offsets[ci], o1 = b->z_init_offsets[ci + 1];
+      if (o1 < o0 || o1 - o0 > kmx[i])
+        return fail(c, FSMP_EINVAL, "chain %lld: initial list of %lld PEs (need 0..kmax %d)", (long long)ci,
+                    (long long)(o1 - o0), kmx[i]);
+      if (o1 > o0 && !(b->lambda[i] > 0.0))
+        return fail(c, FSMP_EINVAL, "chain %lld: an initial PE list needs lambda > 0", (long long)ci);
+      for (int64_t k = o0; k < o1; ++k) {
+        const int32_t g = b->z_init[k];
+        const double x = g * (1.0 / sub) - t0i[i];
+        const bool pos = c->phi.kind == FSMP_PHI_BIEXP ? x > 0.0 : x >= 0.0;
+        if (g < gr[2 * i] || g > gr[2 * i + 1] || !pos)
+          return fail(c, FSMP_EINVAL, "chain %lld: initial PE at grid point %d outside T or before t0", (long long)ci, g);
+      }
+    }
+    n_init = b->z_init_offsets[nc];
+  }
   // the occupancy counts of one grid point stay below n_chains * recorded sweeps * kmax
   if (o->occ && (int64_t)cf.n_chains * (cf.n_steps - cf.burn_in) * kmax_all > INT32_MAX)
     return fail(c, FSMP_EINVAL, "occupancy counts could exceed int32 (n_chains x recorded sweeps x kmax >= 2^31)");
@@ -615,6 +644,8 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   if (e == hipSuccess) e = c->grange.ensure(2 * n);
   if (e == hipSuccess) e = c->wid.ensure(n);
   if (e == hipSuccess && b->n_steps) e = c->wsteps.ensure(n);
+  if (e == hipSuccess && b->z_init_offsets) e = c->zinit_off.ensure(n * cf.n_chains + 1);
+  if (e == hipSuccess && n_init > 0) e = c->zinit.ensure(n_init);
   if (e == hipSuccess) e = c->wflags.ensure(n);
   if (e == hipSuccess) e = c->mf.ensure((size_t)std::max<int64_t>(mfo[n], 1));
   if (e == hipSuccess) e = c->chains.ensure(order.size());
@@ -654,7 +685,9 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   auto pad16 = [](size_t nb) { return (nb + 15) & ~(size_t)15; };
   const size_t bytes = pad16(sizeof(int64_t) * (n + 1)) * 2 + pad16(sizeof(double) * n) * 2 +
                        pad16(sizeof(int32_t) * n) + pad16(sizeof(int32_t) * 2 * n) + pad16(sizeof(uint64_t) * n) +
-                       pad16(sizeof(int32_t) * order.size()) + pad16(sizeof(int32_t) * n);
+                       pad16(sizeof(int32_t) * order.size()) + pad16(sizeof(int32_t) * n) +
+                       (b->z_init_offsets ? pad16(sizeof(int64_t) * (n * cf.n_chains + 1)) + pad16(sizeof(int32_t) * n_init)
+                                          : 0);
   e = c->stage.ensure(bytes);
   if (e != hipSuccess) {
     (void)hipSetDevice(prev);
@@ -676,6 +709,10 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   if (e == hipSuccess) e = put(c->wid.p, wid.data(), sizeof(uint64_t) * n);
   if (e == hipSuccess) e = put(c->chains.p, order.data(), sizeof(int32_t) * order.size());
   if (e == hipSuccess && b->n_steps) e = put(c->wsteps.p, b->n_steps, sizeof(int32_t) * n);
+  if (e == hipSuccess && b->z_init_offsets && n > 0) {
+    e = put(c->zinit_off.p, b->z_init_offsets, sizeof(int64_t) * (n * cf.n_chains + 1));
+    if (e == hipSuccess && n_init > 0) e = put(c->zinit.p, b->z_init, sizeof(int32_t) * n_init);
+  }
   if (e == hipSuccess) e = hipEventRecord(c->stage_done, st);
   c->stage_pending = (e == hipSuccess);
   if (e != hipSuccess) {
@@ -775,6 +812,8 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   ca.wflags = c->wflags.p;
   ca.work = o->work;
   ca.occ = o->occ;
+  ca.zinit = (b->z_init_offsets && n > 0) ? c->zinit.p : nullptr;
+  ca.zinit_off = (b->z_init_offsets && n > 0) ? c->zinit_off.p : nullptr;
   ca.refresh_M = cf.refresh_M;
   ca.near_eps = 1e-3;
   ca.drift_bound = 1e-3;

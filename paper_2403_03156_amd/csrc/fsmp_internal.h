@@ -87,6 +87,10 @@ struct ChainArgs {
   // grid occupancy rows (zeroed by the prologue), or null: row of waveform w at
   // md.sub * woff[w], one count per grid point
   int32_t *occ;
+  // optional initial PE lists (device): chain c starts from zinit[zinit_off[c] ..
+  // zinit_off[c + 1]) instead of the empty list
+  const int32_t *zinit;
+  const int64_t *zinit_off;
 };
 
 struct PrologueArgs {

@@ -240,12 +240,14 @@ __device__ inline int birth_draw(const ModelDev &md, double t0, int glo, int ghi
 // and departure is its number of recorded sweeps at that point, PEs still present at the
 // end keep their arrival's count, and a chain starts empty.  Edits that cancel (both before
 // burn-in) cost two atomics; nothing waits for the adds.
-__device__ inline void occ_edit(int32_t *occ, int64_t row, int move, int gj, int gnew, int step, int burn,
+__device__ inline void occ_edit(const ChainArgs &a, int64_t c, int move, int gj, int gnew, int step, int burn,
                                 int n_steps) {
   const int rem = n_steps - (step > burn ? step : burn);
-  if (!occ || rem <= 0) return;
-  if (move != 1) atomicAdd(occ + row + gj, -rem);
-  if (move != 2) atomicAdd(occ + row + gnew, rem);
+  if (!a.occ || rem <= 0) return;
+  // the row is looked up here rather than kept live across the sweep loop
+  int32_t *row = a.occ + a.md.sub * a.woff[c / a.n_chains];
+  if (move != 1) atomicAdd(row + gj, -rem);
+  if (move != 2) atomicAdd(row + gnew, rem);
 }
 
 // ------------------------------------------------------------------ prologue
@@ -346,10 +348,11 @@ __device__ inline double group_max(double v) {
 // columns owned by the group's lanes), recompute x = G^{-1} b in FP64 and round W into
 // the FP32 H.  False if a Schur complement is not positive.  `drift` = the largest change
 // of a charge mean, relative to max(1, |x|).  s1, s2 are scratch.
-template <int LPC, int LD, int HS, typename HT>
-__device__ bool grp_refresh(const ModelDev &md, const double *vt, const double *ov, int Lw, double *W, HT *H,
-                            double *xv, const double *bv, double *s1, double *s2, const int *zg, int N, int lane,
-                            double &drift) {
+// G^-1 of the PE list zg[0..N) by bordering, in FP64 into M (device-memory layout of the
+// lane-group kernels): false if a Schur complement is not positive.  s1, s2: scratch.
+template <int LPC, int LD, int HS>
+__device__ bool grp_build(const ModelDev &md, const double *vt, const double *ov, int Lw, double *M, double *s1,
+                          double *s2, const int *zg, int N, int lane) {
   for (int k = 0; k < N; ++k) {
     const int gk = zg[k];
     for (int i = lane; i < k; i += LPC) s1[i] = overlap(md, vt, ov, gk, zg[i], Lw);
@@ -357,7 +360,7 @@ __device__ bool grp_refresh(const ModelDev &md, const double *vt, const double *
     WAVE_SYNC();
     double q = 0.0;
     for (int i = lane; i < k; i += LPC) {
-      const double e = grp_col_dot<LD, HS>(W, s1, i, k);
+      const double e = grp_col_dot<LD, HS>(M, s1, i, k);
       s2[i] = e;
       q += s1[i] * e;
     }
@@ -368,13 +371,21 @@ __device__ bool grp_refresh(const ModelDev &md, const double *vt, const double *
     WAVE_SYNC();
     for (int i = lane; i < k; i += LPC) {
       const double ei = s2[i];
-      grp_col_update<LD, HS, false>(W, i, k, ei, s2, inv, 0.0, s2, 0.0);
-      W[(k * LD + i) * HS] = -ei * inv;
-      W[(i * LD + k) * HS] = -ei * inv;
+      grp_col_update<LD, HS, false>(M, i, k, ei, s2, inv, 0.0, s2, 0.0);
+      M[(k * LD + i) * HS] = -ei * inv;
+      M[(i * LD + k) * HS] = -ei * inv;
     }
-    if (lane == 0) W[(k * LD + k) * HS] = inv;
+    if (lane == 0) M[(k * LD + k) * HS] = inv;
     WAVE_SYNC();
   }
+  return true;
+}
+
+template <int LPC, int LD, int HS, typename HT>
+__device__ bool grp_refresh(const ModelDev &md, const double *vt, const double *ov, int Lw, double *W, HT *H,
+                            double *xv, const double *bv, double *s1, double *s2, const int *zg, int N, int lane,
+                            double &drift) {
+  if (!grp_build<LPC, LD, HS>(md, vt, ov, Lw, W, s1, s2, zg, N, lane)) return false;
   double dr = 0.0;
   for (int i = lane; i < N; i += LPC) {
     const double xi = grp_col_dot<LD, HS>(W, bv, i, N);
@@ -478,6 +489,41 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
   }
   WAVE_SYNC();
 
+  // a caller-supplied initial PE list: G^-1 (FP64, by bordering) and x = G^-1 b of the
+  // list before the first sweep; no random numbers are drawn for it
+  if (a.zinit && n_steps > 0) {
+    const int n0 = (int)(a.zinit_off[c + 1] - a.zinit_off[c]);
+    if (n0 > 0) {
+      const int32_t *z0 = a.zinit + a.zinit_off[c];
+      for (int k = lane; k < n0; k += LPC) zg[k] = z0[k];
+      WAVE_SYNC();
+      double *M = F32 ? W : (double *)H;
+      if (grp_build<LPC, LD, HS>(md, vt, ov, Lw, M, s1, s2, zg, n0, lane)) {
+        for (int k = lane; k < n0; k += LPC) s1[k] = mf[zg[k] - glo] + md.rhom;  // b
+        WAVE_SYNC();
+        for (int i = lane; i < n0; i += LPC) {
+          xv[i] = grp_col_dot<LD, HS>(M, s1, i, n0);
+          if constexpr (F32) {
+            bv[i] = s1[i];
+            for (int k = 0; k < n0; ++k) H[(k * LD + i) * HS] = (HT)W[(k * LD + i) * HS];
+          }
+        }
+        N = n0;
+        double sn = 0.0;
+        int m = INT32_MAX;
+        for (int i = lane; i < N; i += LPC) {
+          if (biexp) sn += rise_term(md, zg[i], t0);
+          m = zg[i] < m ? zg[i] : m;
+          occ_edit(a, c, 1, -1, zg[i], 0, burn, n_steps);
+        }
+        S_cur = group_sum<LPC>(sn);
+        gmin = group_min<LPC>(m);
+      } else {
+        st |= FSMP_ST_FACTOR;
+      }
+      WAVE_SYNC();
+    }
+  }
   for (int step = 0; step < n_steps; ++step) {
     if constexpr (F32) {
       if (a.refresh_M > 0 && step > 0 && step % a.refresh_M == 0 && N > 0) {
@@ -679,7 +725,6 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         const double inv_om = move == 1 ? 0.0 : 1.0 / om;
         const double xn = up * inv_d2;
         const int gj = move == 1 ? -1 : zg[j];
-        if (lane == 0) occ_edit(a.occ, md.sub * a.woff[w], move, gj, gnew, step, burn, n_steps);
         if (move != 1) {
           for (int i = lane; i < N; i += LPC) s1[i] = H[(j * LD + i) * HS];  // h = row j of H
           WAVE_SYNC();
@@ -764,6 +809,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
             gmin = group_min<LPC>(m);
           }
         }
+        if (lane == 0) occ_edit(a, c, move, gj, gnew, step, burn, n_steps);
       }
     }
 
@@ -1056,15 +1102,12 @@ struct LaneLayout {
   static constexpr int EI = 2 * KCAP + 1;
 };
 
-// Precision form: rebuild the inverse Gram matrix of the current z in FP64 by
-// bordering (each step is the birth update of the PE-space factor: the exact inverse
-// of the leading block), recompute x = G^{-1} b in FP64, round the result into the
-// FP32 storage.  Returns false if a Schur complement is not positive.  `drift` is the
-// largest change of a charge mean, relative to max(1, |x|).
-template <int KCAP, typename HT>
-__device__ bool lane_refresh(const ModelDev &md, const double *vt, const double *ov, int Lw, double *Wp, HT *Hp,
-                             double *Xp, const double *Bp, double *S1, double *S2, const int32_t *Zp, int N,
-                             double &drift) {
+// The inverse Gram matrix of the PE list Zp[0..N) in FP64 by bordering (each step is the
+// birth update of the PE-space factor: the exact inverse of the leading block), into Wp.
+// Returns false if a Schur complement is not positive.
+template <int KCAP>
+__device__ bool lane_build(const ModelDev &md, const double *vt, const double *ov, int Lw, double *Wp, double *S1,
+                           double *S2, const int32_t *Zp, int N) {
   for (int k = 0; k < N; ++k) {
     const int gk = Zp[k * 64];
     for (int i = 0; i < k; ++i) S1[i * 64] = overlap(md, vt, ov, gk, Zp[i * 64], Lw);
@@ -1082,6 +1125,17 @@ __device__ bool lane_refresh(const ModelDev &md, const double *vt, const double 
     }
     Wp[(k * KCAP + k) * 64] = inv;
   }
+  return true;
+}
+
+// Precision form: rebuild the inverse Gram matrix of the current z in FP64, recompute
+// x = G^{-1} b in FP64, round the result into the FP32 storage.  `drift` is the largest
+// change of a charge mean, relative to max(1, |x|).
+template <int KCAP, typename HT>
+__device__ bool lane_refresh(const ModelDev &md, const double *vt, const double *ov, int Lw, double *Wp, HT *Hp,
+                             double *Xp, const double *Bp, double *S1, double *S2, const int32_t *Zp, int N,
+                             double &drift) {
+  if (!lane_build<KCAP>(md, vt, ov, Lw, Wp, S1, S2, Zp, N)) return false;
   drift = 0.0;
   for (int i = 0; i < N; ++i) {
     double xi = 0.0;
@@ -1214,6 +1268,34 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
   double wk0 = 0.0, wk1 = 0.0, wk2 = 0.0, wk3 = 0.0;
   const bool biexp = md.kind == FSMP_PHI_BIEXP;
 
+  // a caller-supplied initial PE list: G^-1 (FP64, by bordering) and x = G^-1 b of the
+  // list before the first sweep; no random numbers are drawn for it
+  if (a.zinit && n_steps > 0) {
+    const int n0 = (int)(a.zinit_off[c + 1] - a.zinit_off[c]);
+    if (n0 > 0) {
+      const int32_t *z0 = a.zinit + a.zinit_off[c];
+      for (int k = 0; k < n0; ++k) ZG(k) = z0[k];
+      double *M = F32 ? Wp : (double *)Hp;
+      if (lane_build<KCAP>(md, vt, ov, Lw, M, S1, S2, Zp, n0)) {
+        for (int k = 0; k < n0; ++k) BV(k) = mf[ZG(k) - glo] + md.rhom;
+        for (int i = 0; i < n0; ++i) {
+          double xi = 0.0;
+          for (int k = 0; k < n0; ++k) xi += M[(i * KCAP + k) * 64] * BV(k);
+          XV(i) = xi;
+        }
+        if (F32)
+          for (int k = 0; k < n0; ++k) lane_copy(Hp + (int64_t)k * KCAP * 64, Wp + (int64_t)k * KCAP * 64, n0);
+        N = n0;
+        for (int i = 0; i < N; ++i) {
+          if (biexp) S_cur += log(-expm1(-((double)ZG(i) * md.dt - t0) * md.inv_tau1));
+          gmin = ZG(i) < gmin ? ZG(i) : gmin;
+          occ_edit(a, c, 1, -1, ZG(i), 0, burn, n_steps);
+        }
+      } else {
+        st |= FSMP_ST_FACTOR;
+      }
+    }
+  }
   for (int step = 0; step < n_steps; ++step) {
     if (F32 && a.refresh_M > 0 && step > 0 && step % a.refresh_M == 0 && N > 0) {
       double drift;
@@ -1367,7 +1449,7 @@ __global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
         const double inv_om = move == 1 ? 0.0 : 1.0 / om;
         const double xn = up * inv_d2;
         const int gj = move == 1 ? -1 : ZG(j);
-        occ_edit(a.occ, md.sub * a.woff[w], move, gj, gnew, step, burn, n_steps);
+        occ_edit(a, c, move, gj, gnew, step, burn, n_steps);
         if (move != 1) lane_copy(S3, Hp + (int64_t)j * KCAP * 64, N);  // h = row j of H
         if (shift)
           for (int i = 0; i < N; ++i) G2(i) = (i == j) ? 0.0 : G2(i) - G3(i) * ej * inv_om;

@@ -50,7 +50,8 @@ class fsmp_config(ctypes.Structure):
 class fsmp_batch(ctypes.Structure):
     _fields_ = [("n_wave", ctypes.c_int64), ("wave", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
                 ("lambda_", ctypes.c_void_p), ("kmax", ctypes.c_void_p), ("g_range", ctypes.c_void_p),
-                ("t0_init", ctypes.c_void_p), ("wave_id", ctypes.c_void_p), ("n_steps", ctypes.c_void_p)]
+                ("t0_init", ctypes.c_void_p), ("wave_id", ctypes.c_void_p), ("n_steps", ctypes.c_void_p),
+                ("z_init", ctypes.c_void_p), ("z_init_offsets", ctypes.c_void_p)]
 
 
 class fsmp_samples(ctypes.Structure):
@@ -252,7 +253,8 @@ class Sampler:
             out["zdraw"] = torch.zeros((C, max(n_rec, 1), kz), dtype=torch.int32, device=dev)
         return out
 
-    def _batch(self, wave, offsets, lam, kmax=None, g_range=None, t0_init=None, wave_id=None, n_steps=None):
+    def _batch(self, wave, offsets, lam, kmax=None, g_range=None, t0_init=None, wave_id=None, n_steps=None,
+               z_init=None):
         import torch
         if not wave.is_cuda or wave.dtype != torch.float32 or not wave.is_contiguous():
             raise ValueError("wave must be a contiguous float32 device tensor")
@@ -263,9 +265,18 @@ class Sampler:
         t0_init = None if t0_init is None else np.ascontiguousarray(t0_init, dtype=np.float64)
         wave_id = None if wave_id is None else np.ascontiguousarray(wave_id, dtype=np.uint64)
         n_steps = None if n_steps is None else np.ascontiguousarray(n_steps, dtype=np.int32)
-        keep = (offsets, lam, kmax, g_range, t0_init, wave_id, n_steps)
+        zi, zo = (None, None)
+        if z_init is not None:
+            n_ch = (len(offsets) - 1) * self.cfg.n_chains
+            if len(z_init) != n_ch:
+                raise ValueError(f"z_init needs one list per chain ({n_ch})")
+            zo = np.zeros(n_ch + 1, np.int64)
+            zo[1:] = np.cumsum([len(z) for z in z_init])
+            zi = np.ascontiguousarray(np.concatenate([np.asarray(z, np.int32).reshape(-1) for z in z_init] +
+                                                     [np.zeros(1, np.int32)]))
+        keep = (offsets, lam, kmax, g_range, t0_init, wave_id, n_steps, zi, zo)
         b = fsmp_batch(len(offsets) - 1, ctypes.c_void_p(wave.data_ptr()), _hptr(offsets), _hptr(lam), _hptr(kmax),
-                       _hptr(g_range), _hptr(t0_init), _hptr(wave_id), _hptr(n_steps))
+                       _hptr(g_range), _hptr(t0_init), _hptr(wave_id), _hptr(n_steps), _hptr(zi), _hptr(zo))
         return b, keep
 
     def workspace_bytes(self, offsets, lam, kmax=None, g_range=None):
@@ -325,12 +336,12 @@ class Sampler:
                                                ctypes.byref(g)))
         return Graph(self, g, keep), out
 
-    def replay(self, wave, offsets, lam, log, kmax=None, kz=None, stream=None, occupancy=False):
+    def replay(self, wave, offsets, lam, log, kmax=None, kz=None, stream=None, occupancy=False, z_init=None):
         """Follow recorded proposals (``log``: device uint8 [chains, n_steps * 40] or a structured
         host array [chains, n_steps] of LOGREC_DTYPE); returns (dnu, log_alpha, out) on the device."""
         import torch
         dev = torch.device("cuda", self.device)
-        b, keep = self._batch(wave, offsets, lam, kmax)
+        b, keep = self._batch(wave, offsets, lam, kmax, z_init=z_init)
         n = len(offsets) - 1
         if kz is None:
             kz = int(np.max(kmax)) if kmax is not None else self.cfg.k_max
@@ -353,12 +364,13 @@ class Sampler:
         return dnu, la, out
 
     def sample(self, wave, offsets, lam, kmax=None, g_range=None, t0_init=None, wave_id=None, out=None, kz=None,
-               stream=None, work=False, n_steps=None, occupancy=False):
+               stream=None, work=False, n_steps=None, occupancy=False, z_init=None):
         """wave: torch float32 device tensor; offsets/lam/kmax/g_range/t0_init/wave_id/n_steps: host numpy
         arrays (n_steps: sweeps per waveform, at most the configured n_steps).  occupancy: also count
-        the PEs per grid point over the recorded sweeps (out["occ"])."""
+        the PEs per grid point over the recorded sweeps (out["occ"]).  z_init: one initial PE list
+        (grid indices) per chain, or None for the empty start."""
         import torch
-        b, keep = self._batch(wave, offsets, lam, kmax, g_range, t0_init, wave_id, n_steps)
+        b, keep = self._batch(wave, offsets, lam, kmax, g_range, t0_init, wave_id, n_steps, z_init)
         n = int(b.n_wave)
         kmax = keep[2]
         if kz is None:
