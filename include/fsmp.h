@@ -309,6 +309,42 @@ fsmp_status fsmp_replay(fsmp_ctx *ctx, const fsmp_batch *batch, const fsmp_logre
 fsmp_status fsmp_posterior(fsmp_ctx *ctx, int64_t n_wave, const fsmp_samples *in, fsmp_posterior_out *out,
                            void *hip_stream);
 
+/* Initial state by deconvolution (Sec. 2.3), for fsmp_batch's z_init, g_range, t0_init and
+ * lambda: n_iter iterations of Lucy's multiplicative update of qhat over tau = -L_V + 1 ..
+ * L_w - 1 (whole samples), with the SER sampled at whole samples and normalised to unit
+ * sum (so that qhat is in units of one PE's charge), the data clipped at 0 and a uniform
+ * start with the data's total; then
+ *   z         {tau >= 0 : qhat(tau) > threshold} (the paper takes 0.1), the kmax largest
+ *             when more pass (ties: earlier tau), in time order, as grid indices
+ *             grid_sub * tau, without PEs at or before t0;
+ *   t0        the first PE time minus half a grid step, held inside [t0_min, t0_max];
+ *   g_range   T = [t_min - margin, t_max + margin] (the paper takes 4 ns) on the grid,
+ *             clipped to the window; g_lo > g_hi (an empty T: the waveform is taken as
+ *             no PE) when no point passes;
+ *   cut       the sample range [t_min - margin, t_max + margin + L_V] of the waveform
+ *             that the paper keeps (clipped; the whole window when no point passes);
+ *   lambda    the total of qhat, the initial intensity scale.
+ * Outputs are device buffers; qhat (NULL to skip) holds row i at offsets[i] + i (L_V - 1),
+ * L_i + L_V - 1 entries.  FP64 throughout.  Windows are held in LDS: FSMP_ENOTSUP when the
+ * longest does not fit (about 6,000 samples at L_V = 96).  kz >= every kmax. */
+typedef struct {
+  int32_t *z;       /* [n_wave][kz], -1 beyond n_pe */
+  int32_t *n_pe;    /* [n_wave] */
+  int32_t *g_range; /* [n_wave][2] */
+  double *t0;       /* [n_wave] */
+  double *lambda;   /* [n_wave] */
+  int32_t *cut;     /* [n_wave][2] */
+  double *qhat;     /* NULL or see above */
+  int32_t kz;
+} fsmp_lucy_out;
+
+fsmp_status fsmp_lucy(fsmp_ctx *ctx, const fsmp_batch *batch, int32_t n_iter, double threshold, int32_t margin,
+                      fsmp_lucy_out *out, void *hip_stream);
+
+/* L_V, the SER support in samples of the context (the row length of the response the
+ * deconvolution uses); -1 for a NULL context. */
+int32_t fsmp_ser_support(const fsmp_ctx *ctx);
+
 /* Kernel timings of the last fsmp_sample: waits for its kernels, writes up to `cap`
  * entries and returns how many kernels ran.  Timings are taken (HIP events recorded on
  * the call's stream around each launch, no synchronisation inside fsmp_sample) only

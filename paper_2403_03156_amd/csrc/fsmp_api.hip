@@ -158,6 +158,9 @@ struct fsmp_ctx {
   DevBuf<int32_t> wsteps;  // per-waveform sweeps (fsmp_batch.n_steps)
   DevBuf<int32_t> zinit;   // initial PE lists (fsmp_batch.z_init) and their chain offsets
   DevBuf<int64_t> zinit_off;
+  DevBuf<int64_t> lwoff;    // fsmp_lucy: offsets, kmax, the unit-sum SER kernel
+  DevBuf<int32_t> lkmax;
+  DevBuf<double> lkern;
   DevBuf<int64_t> poff;    // fsmp_posterior: the batch offsets of the occupancy rows
   DevBuf<double> plam;     // fsmp_posterior: lambda0 per waveform for lambda-hat
   DevBuf<uint32_t> wflags;
@@ -429,6 +432,9 @@ void fsmp_destroy(fsmp_ctx *c) {
   c->poff.release();
   c->zinit.release();
   c->zinit_off.release();
+  c->lwoff.release();
+  c->lkmax.release();
+  c->lkern.release();
   c->plam.release();
   c->mfoff.release();
   c->lam.release();
@@ -1164,6 +1170,94 @@ void fsmp_graph_destroy(fsmp_graph *g) {
   if (g->stream) (void)hipStreamDestroy(g->stream);
   if (g->own) fsmp_destroy(g->own);
   delete g;
+}
+
+int32_t fsmp_ser_support(const fsmp_ctx *c) { return c ? c->tab.LV : -1; }
+
+fsmp_status fsmp_lucy(fsmp_ctx *c, const fsmp_batch *b, int32_t n_iter, double threshold, int32_t margin,
+                      fsmp_lucy_out *out, void *hip_stream) {
+  if (!c) return FSMP_EINVAL;
+  if (!b || !out) return fail(c, FSMP_EINVAL, "null batch or output");
+  const int64_t n = b->n_wave;
+  if (n < 0) return fail(c, FSMP_EINVAL, "n_wave < 0");
+  if (n == 0) return FSMP_OK;
+  if (!b->wave || !b->offsets) return fail(c, FSMP_EINVAL, "wave and offsets are required");
+  if (!out->z || !out->n_pe || !out->g_range || !out->t0 || !out->lambda || !out->cut)
+    return fail(c, FSMP_EINVAL, "an output buffer is NULL");
+  if (n_iter < 0 || !(threshold >= 0.0) || !std::isfinite(threshold) || margin < 0)
+    return fail(c, FSMP_EINVAL, "need n_iter >= 0, a finite threshold >= 0 and margin >= 0");
+  if (b->offsets[0] != 0) return fail(c, FSMP_EINVAL, "offsets[0] must be 0");
+  const int LV = c->tab.LV, sub = c->cfg.grid_sub;
+  const int LVp = (LV + 7) / 8 * 8;
+  std::vector<int32_t> kmx(n);
+  int64_t max_len = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t L = b->offsets[i + 1] - b->offsets[i];
+    if (L < 1 || L > 65536) return fail(c, FSMP_EINVAL, "waveform %lld: window of %lld samples (need 1..65536)", (long long)i, (long long)L);
+    kmx[i] = b->kmax ? b->kmax[i] : c->cfg.k_max;
+    if (kmx[i] < 1 || kmx[i] > 192 || kmx[i] > out->kz)
+      return fail(c, FSMP_EINVAL, "waveform %lld: kmax %d outside 1..192 or above kz %d", (long long)i, kmx[i], out->kz);
+    max_len = std::max(max_len, L);
+  }
+  if (lucy_lds_bytes(max_len, LVp) + 1024 > 160 * 1024)
+    return fail(c, FSMP_ENOTSUP, "a window of %lld samples does not fit the deconvolution's LDS", (long long)max_len);
+  // the SER at whole samples, normalised to unit sum
+  std::vector<double> kern(LVp, 0.0);
+  double area = 0.0;
+  for (int s0 = 0; s0 < LV; ++s0) area += c->tab.vtab[(size_t)s0 * sub];
+  if (!(area > 0.0)) return fail(c, FSMP_EINVAL, "the SER has no area at whole samples");
+  for (int s0 = 0; s0 < LV; ++s0) kern[s0] = c->tab.vtab[(size_t)s0 * sub] / area;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(c->device);
+  const hipStream_t st = (hipStream_t)hip_stream;
+  if (c->stage_pending) (void)hipEventSynchronize(c->stage_done);
+  auto pad16 = [](size_t nb) { return (nb + 15) & ~(size_t)15; };
+  const size_t nbo = sizeof(int64_t) * (n + 1), nbk = sizeof(int32_t) * n, nbv = sizeof(double) * LVp;
+  hipError_t e = c->lwoff.ensure(n + 1);
+  if (e == hipSuccess) e = c->lkmax.ensure(n);
+  if (e == hipSuccess) e = c->lkern.ensure(LVp);
+  if (e == hipSuccess) e = c->stage.ensure(pad16(nbo) + pad16(nbk) + pad16(nbv));
+  if (e != hipSuccess) {
+    (void)hipSetDevice(prev);
+    return fail(c, FSMP_ENOMEM, "deconvolution workspace allocation failed: %s", hipGetErrorString(e));
+  }
+  char *sp = (char *)c->stage.p;
+  std::memcpy(sp, b->offsets, nbo);
+  std::memcpy(sp + pad16(nbo), kmx.data(), nbk);
+  std::memcpy(sp + pad16(nbo) + pad16(nbk), kern.data(), nbv);
+  e = hipMemcpyAsync(c->lwoff.p, sp, nbo, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->lkmax.p, sp + pad16(nbo), nbk, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->lkern.p, sp + pad16(nbo) + pad16(nbk), nbv, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventRecord(c->stage_done, st);
+  c->stage_pending = (e == hipSuccess);
+  LucyArgs a{};
+  a.wave = b->wave;
+  a.woff = c->lwoff.p;
+  a.kmax = c->lkmax.p;
+  a.kern = c->lkern.p;
+  a.LV = LV;
+  a.LVp = LVp;
+  a.sub = sub;
+  a.n_iter = n_iter;
+  a.kz = out->kz;
+  a.n_wave = n;
+  a.inv_area = 1.0 / area;
+  a.threshold = threshold;
+  a.margin = margin;
+  a.t0_min = c->phi.t0_min;
+  a.t0_max = c->phi.t0_max;
+  a.z = out->z;
+  a.n_pe = out->n_pe;
+  a.g_range = out->g_range;
+  a.t0 = out->t0;
+  a.lam = out->lambda;
+  a.cut = out->cut;
+  a.qhat = out->qhat;
+  if (e == hipSuccess) e = launch_lucy(a, max_len, st);
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) return fail(c, FSMP_EDEVICE, "deconvolution failed: %s", hipGetErrorString(e));
+  return FSMP_OK;
 }
 
 fsmp_status fsmp_posterior(fsmp_ctx *c, int64_t n_wave, const fsmp_samples *in, fsmp_posterior_out *out,

@@ -129,6 +129,31 @@ struct PosteriorArgs {
   double mu_q;
 };
 
+// Lucy-Richardson initialisation (one workgroup per waveform, everything in LDS)
+struct LucyArgs {
+  const float *wave;
+  const int64_t *woff;     // [n+1]
+  const int32_t *kmax;     // [n]
+  const double *kern;      // [LVp] V(s) / sum V, zero-padded to LVp (a multiple of 8)
+  int32_t LV, LVp, sub, n_iter, kz;
+  int64_t n_wave;
+  double inv_area;         // 1 / sum_s V(s): deconvolved flux -> PE charge
+  double threshold;
+  int32_t margin;          // ns
+  double t0_min, t0_max;
+  // outputs
+  int32_t *z;              // [n][kz]
+  int32_t *n_pe;           // [n]
+  int32_t *g_range;        // [n][2]
+  double *t0;              // [n]
+  double *lam;             // [n]
+  int32_t *cut;            // [n][2]
+  double *qhat;            // optional: row w at woff[w] + w (LV - 1), L_w + LV - 1 entries
+};
+constexpr int kLucyR = 8;  // outputs per thread of a convolution pass
+size_t lucy_lds_bytes(int64_t Lw, int LVp);
+hipError_t launch_lucy(const LucyArgs &a, int64_t max_len, hipStream_t st);
+
 // Launchers (fsmp_kernels.hip).  Each returns hipSuccess or the launch error.
 hipError_t launch_prologue(const PrologueArgs &a, hipStream_t st);
 hipError_t launch_posterior(const PosteriorArgs &a, hipStream_t st);

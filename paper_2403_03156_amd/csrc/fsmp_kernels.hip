@@ -1820,12 +1820,209 @@ hipError_t launch_chain_lane_t(const ChainArgs &a, hipStream_t st, int32_t *lane
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ Lucy-Richardson
+// Initial PE sequence by deconvolution (Sec. 2.3): one workgroup per waveform, all arrays
+// in LDS, FP64.  Both sums of an iteration are correlations of an LDS array with the
+// kernel, out[i] = sum_s X[i + s] k[s]:
+//   w^r(t)  = sum_s u[t + s] K[LV - 1 - s]          (u indexed by tau + LV - 1)
+//   c(tau)  = sum_s rp[tau + LV - 1 + s] K[s]        (rp: the ratio d / w^r, zero-padded)
+// each thread computes kLucyR consecutive outputs from a sliding window of X in
+// registers, one LDS read of X and one broadcast read of k per kLucyR FMAs.
+template <int R>
+__device__ inline void lucy_corr(const double *X, const double *k, int LVp, int i0, double *acc) {
+  double xw[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    xw[j] = X[i0 + j];
+    acc[j] = 0.0;
+  }
+  for (int s = 0; s < LVp; s += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double ks = k[s + u];
+#pragma unroll
+      for (int j = 0; j < R; ++j) acc[j] = fma(xw[j], ks, acc[j]);
+#pragma unroll
+      for (int j = 0; j < R - 1; ++j) xw[j] = xw[j + 1];
+      xw[R - 1] = X[i0 + R + s + u];
+    }
+  }
+}
+
+
+__global__ void __launch_bounds__(256) lucy_kernel(LucyArgs a) {
+  extern __shared__ double lds[];
+  const int LV = a.LV, LVp = a.LVp;
+  double *K = lds;              // [LVp]
+  double *Kr = K + LVp;         // [LVp] reversed, K[LV - 1 - s], zero beyond LV
+  for (int s = threadIdx.x; s < LVp; s += blockDim.x) {
+    K[s] = a.kern[s];
+    Kr[s] = s < LV ? a.kern[LV - 1 - s] : 0.0;
+  }
+  for (int64_t w = blockIdx.x; w < a.n_wave; w += gridDim.x) {
+    const int Lw = (int)(a.woff[w + 1] - a.woff[w]);
+    const int ntau = Lw + LV - 1;
+    const int nch = (ntau + kLucyR - 1) / kLucyR * kLucyR;
+    double *d = Kr + LVp;                  // [Lw]
+    double *u = d + Lw;                    // [nch + LVp + R]: tau + LV - 1, zero beyond ntau
+    double *rp = u + nch + LVp + kLucyR;   // [LV - 1 zeros | ratio(Lw) | zeros]
+    const int nrp = nch + LVp + kLucyR + LVp;
+    const float *x = a.wave + a.woff[w];
+    __syncthreads();
+    double sd = 0.0;
+    for (int t = threadIdx.x; t < Lw; t += blockDim.x) {
+      const double v = fmax((double)x[t], 0.0);
+      d[t] = v;
+      sd += v;
+    }
+    // block sum of the clipped data
+    __shared__ double red[8];
+    for (int o = 32; o > 0; o >>= 1) sd += __shfl_xor(sd, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sd;
+    __syncthreads();
+    double tot = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) tot += red[i];
+    const double u0 = tot / ntau;
+    for (int i = threadIdx.x; i < nch + LVp + kLucyR; i += blockDim.x) u[i] = i < ntau ? u0 : 0.0;
+    for (int i = threadIdx.x; i < nrp; i += blockDim.x) rp[i] = 0.0;
+    __syncthreads();
+    for (int it = 0; it < a.n_iter; ++it) {
+      // w^r and the ratio d / w^r (0 where w^r is not positive)
+      for (int c0 = threadIdx.x * kLucyR; c0 < Lw; c0 += blockDim.x * kLucyR) {
+        double acc[kLucyR];
+        lucy_corr<kLucyR>(u, Kr, LVp, c0, acc);
+#pragma unroll
+        for (int j = 0; j < kLucyR; ++j) {
+          const int t = c0 + j;
+          if (t < Lw) rp[LV - 1 + t] = acc[j] > 0.0 ? d[t] / acc[j] : 0.0;
+        }
+      }
+      __syncthreads();
+      // u(tau) *= sum_t ratio(t) K(t - tau)
+      for (int c0 = threadIdx.x * kLucyR; c0 < ntau; c0 += blockDim.x * kLucyR) {
+        double acc[kLucyR];
+        lucy_corr<kLucyR>(rp, K, LVp, c0, acc);
+#pragma unroll
+        for (int j = 0; j < kLucyR; ++j)
+          if (c0 + j < ntau) u[c0 + j] *= acc[j];
+      }
+      __syncthreads();
+    }
+    // qhat in PE-charge units; candidates tau >= 0 above the threshold (flags in d)
+    double lam = 0.0;
+    int cnt = 0;
+    for (int i = threadIdx.x; i < ntau; i += blockDim.x) {
+      const double q = u[i] * a.inv_area;
+      u[i] = q;
+      lam += q;
+      if (a.qhat) a.qhat[a.woff[w] + w * (int64_t)(LV - 1) + i] = q;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < Lw; i += blockDim.x) {
+      const bool c = u[i + LV - 1] > a.threshold;   // tau = i >= 0
+      d[i] = c ? 1.0 : 0.0;
+      cnt += c;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      lam += __shfl_xor(lam, o);
+      cnt += __shfl_xor(cnt, o);
+    }
+    __syncthreads();
+    __shared__ double redl[8];
+    __shared__ int redc[8];
+    if ((threadIdx.x & 63) == 0) {
+      redl[threadIdx.x >> 6] = lam;
+      redc[threadIdx.x >> 6] = cnt;
+    }
+    __syncthreads();
+    lam = 0.0;
+    cnt = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+      lam += redl[i];
+      cnt += redc[i];
+    }
+    const int kmax = a.kmax[w];
+    if (cnt > kmax) {
+      // keep the kmax largest qhat (ties: earlier tau): rank every candidate
+      for (int i = threadIdx.x; i < Lw; i += blockDim.x) {
+        if (d[i] == 0.0) {
+          rp[i] = 0.0;
+          continue;
+        }
+        const double qi = u[i + LV - 1];
+        int rank = 0;
+        for (int j = 0; j < Lw; ++j) {
+          const double qj = u[j + LV - 1];
+          rank += (qj > a.threshold) && (qj > qi || (qj == qi && j < i));
+        }
+        rp[i] = rank < kmax ? 1.0 : 0.0;
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < Lw; i += blockDim.x) d[i] = rp[i];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      int t_min = -1, t_max = -1;
+      for (int i = 0; i < Lw; ++i)
+        if (d[i] != 0.0) {
+          if (t_min < 0) t_min = i;
+          t_max = i;
+        }
+      int n = 0;
+      double t0 = 0.5 * (a.t0_min + a.t0_max);
+      const int sub = a.sub;
+      if (t_min < 0) {
+        a.g_range[2 * w] = 1;
+        a.g_range[2 * w + 1] = 0;
+        a.cut[2 * w] = 0;
+        a.cut[2 * w + 1] = Lw - 1;
+      } else {
+        t0 = fmin(fmax(t_min - 0.5 / sub, a.t0_min), a.t0_max);
+        for (int i = t_min; i <= t_max; ++i)
+          if (d[i] != 0.0 && i - t0 > 0.0 && n < a.kz) a.z[w * (int64_t)a.kz + n++] = sub * i;
+        a.g_range[2 * w] = max(0, sub * (t_min - a.margin));
+        a.g_range[2 * w + 1] = min(sub * Lw - 1, sub * (t_max + a.margin));
+        a.cut[2 * w] = max(0, t_min - a.margin);
+        a.cut[2 * w + 1] = min(Lw - 1, t_max + a.margin + LV);
+      }
+      for (int k = n; k < a.kz; ++k) a.z[w * (int64_t)a.kz + k] = -1;
+      a.n_pe[w] = n;
+      a.t0[w] = t0;
+      a.lam[w] = lam;
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 hipError_t launch_prologue(const PrologueArgs &a, hipStream_t st) {
   if (a.n_wave == 0) return hipSuccess;
   const int64_t nb = a.n_wave < 65535 * 8 ? a.n_wave : 65535 * 8;
   hipLaunchKernelGGL(prologue_kernel, dim3((unsigned)nb), dim3(256), sizeof(double) * a.md.M, st, a);
+  return hipGetLastError();
+}
+
+size_t lucy_lds_bytes(int64_t Lw, int LVp) {
+  const int64_t ntau = Lw + LVp - 1;
+  const int64_t nch = (ntau + kLucyR - 1) / kLucyR * kLucyR;
+  // K, reversed K, d, u (padded for the window reads), rp (padded both sides)
+  return sizeof(double) * (size_t)(2 * LVp + Lw + (nch + LVp + kLucyR) + (nch + LVp + kLucyR + LVp));
+}
+
+hipError_t launch_lucy(const LucyArgs &a, int64_t max_len, hipStream_t st) {
+  if (a.n_wave == 0) return hipSuccess;
+  const size_t lds = lucy_lds_bytes(max_len, a.LVp);
+  // enough threads for the longer pass of the longest window, in whole wavefronts
+  const int64_t chunks = (max_len + a.LV - 1 + kLucyR - 1) / kLucyR;
+  int threads = (int)((chunks + 63) / 64 * 64);
+  threads = threads < 64 ? 64 : (threads > 256 ? 256 : threads);
+  if (lds > 64 * 1024) {
+    (void)hipFuncSetAttribute((const void *)lucy_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipGetLastError();
+  }
+  const int64_t nb = a.n_wave < 65535 * 8 ? a.n_wave : 65535 * 8;
+  hipLaunchKernelGGL(lucy_kernel, dim3((unsigned)nb), dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 

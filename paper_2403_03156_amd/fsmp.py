@@ -70,6 +70,12 @@ class fsmp_posterior_out(ctypes.Structure):
                 ("mcse_chains", ctypes.c_void_p), ("lambda_hat", ctypes.c_void_p), ("lambda_", ctypes.c_void_p)]
 
 
+class fsmp_lucy_out(ctypes.Structure):
+    _fields_ = [("z", ctypes.c_void_p), ("n_pe", ctypes.c_void_p), ("g_range", ctypes.c_void_p),
+                ("t0", ctypes.c_void_p), ("lambda_", ctypes.c_void_p), ("cut", ctypes.c_void_p),
+                ("qhat", ctypes.c_void_p), ("kz", ctypes.c_int32)]
+
+
 class fsmp_server_config(ctypes.Structure):
     _fields_ = [("n_streams", ctypes.c_int32), ("max_batch_wave", ctypes.c_int64), ("memory_budget", ctypes.c_size_t)]
 
@@ -160,6 +166,11 @@ def load(path: Optional[str] = None):
     L.fsmp_autotune_steps.argtypes = [ctypes.c_void_p, P(fsmp_batch), ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
     L.fsmp_autotune_steps.restype = ctypes.c_int
+    L.fsmp_lucy.argtypes = [ctypes.c_void_p, P(fsmp_batch), ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                            P(fsmp_lucy_out), ctypes.c_void_p]
+    L.fsmp_lucy.restype = ctypes.c_int
+    L.fsmp_ser_support.argtypes = [ctypes.c_void_p]
+    L.fsmp_ser_support.restype = ctypes.c_int32
     _lib = L
     return L
 
@@ -307,6 +318,52 @@ class Sampler:
                             _dptr(out["log"]), _dptr(out["trace"]), out["kz"], _dptr(out.get("work")),
                             _dptr(out.get("qdraw")), _dptr(out.get("zdraw")), _dptr(out.get("rec_steps")),
                             _dptr(out.get("occ")))
+
+    def lucy(self, wave, offsets, kmax=None, kz=None, n_iter=2000, threshold=0.1, margin=4, qhat=False,
+             stream=None):
+        """Initial state by deconvolution (fsmp_lucy): device tensors z [n, kz], n_pe, g_range [n, 2],
+        t0, lambda, cut [n, 2] and optionally qhat (row i at offsets[i] + i (L_V - 1))."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        b, keep = self._batch(wave, offsets, np.zeros(len(offsets) - 1), kmax)
+        n = int(b.n_wave)
+        km = keep[2]
+        if kz is None:
+            kz = int(km.max()) if km is not None and n > 0 else self.cfg.k_max
+        lv = self.support_samples()
+        res = {
+            "z": torch.empty((n, kz), dtype=torch.int32, device=dev),
+            "n_pe": torch.empty(n, dtype=torch.int32, device=dev),
+            "g_range": torch.empty((n, 2), dtype=torch.int32, device=dev),
+            "t0": torch.empty(n, dtype=torch.float64, device=dev),
+            "lambda": torch.empty(n, dtype=torch.float64, device=dev),
+            "cut": torch.empty((n, 2), dtype=torch.int32, device=dev),
+            "qhat": (torch.empty(int(keep[0][-1]) + n * (lv - 1), dtype=torch.float64, device=dev)
+                     if qhat else None),
+            "kz": kz,
+        }
+        o = fsmp_lucy_out(_dptr(res["z"]), _dptr(res["n_pe"]), _dptr(res["g_range"]), _dptr(res["t0"]),
+                          _dptr(res["lambda"]), _dptr(res["cut"]), _dptr(res["qhat"]), kz)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._check(self.lib.fsmp_lucy(self.h, ctypes.byref(b), n_iter, ctypes.c_double(threshold), margin,
+                                       ctypes.byref(o), ctypes.c_void_p(st.cuda_stream)))
+        return res
+
+    def support_samples(self):
+        """L_V, the SER support in samples."""
+        return int(self.lib.fsmp_ser_support(self.h))
+
+    @staticmethod
+    def start_from(lucy_res, n_chains):
+        """Host inputs of sample() from a fsmp_lucy result: z_init (one list per chain, the
+        waveform's list for each of its chains), g_range, t0_init."""
+        z = lucy_res["z"].cpu().numpy()
+        n = lucy_res["n_pe"].cpu().numpy()
+        lists = []
+        for i in range(len(n)):
+            zi = z[i, :n[i]].tolist()
+            lists.extend([zi] * n_chains)
+        return lists, lucy_res["g_range"].cpu().numpy(), lucy_res["t0"].cpu().numpy()
 
     def set_design(self, capacity, design):
         self._check(self.lib.fsmp_set_design(self.h, capacity, design))

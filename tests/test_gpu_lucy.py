@@ -1,0 +1,142 @@
+"""Lucy-Richardson initialisation (fsmp_lucy, Sec. 2.3) against the oracle (needs an MI355X).
+
+Both sides iterate in FP64; 2,000 iterations in two summation orders differ by about
+3e-14 relative (measured on the batched workload), so qhat must agree to 1e-9 relative
+(1e-12 absolute), and every decision taken from it -- the initial PE list, T, the cut, t0
+-- must be identical except on a waveform where the oracle's qhat lies within 1e-9 of the
+threshold (none in these cases; the test says so if one appears).  Covered: the batched
+workload at r = 2,000, ragged windows of 128-2,048 samples, the kmax ranking when more
+points pass than kmax allows, a waveform with no positive sample, r = 0, the LDS limit,
+and sampling started from the deconvolution's state against the oracle started from its
+own.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import lucy
+from paper_2403_03156_amd import synth
+from tests.fsmp_cases import compare_chains, gpu_sampler, oracle_params, to_host
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SUB = 4
+
+
+def _oracle(wl, b, km, n_iter, LV, threshold=0.1, margin=4):
+    p = oracle_params(wl)
+    V = lucy.ser_samples(p, LV)
+    out = []
+    for i in range(len(km)):
+        w = b["wave"][b["offsets"][i]:b["offsets"][i + 1]].astype(np.float64)
+        q = lucy.lucy(w, V, n_iter)
+        st = lucy.initial_state(q, LV, SUB, threshold, margin, int(km[i]), wl.t0_min, wl.t0_max, len(w))
+        st["qhat"] = q
+        out.append(st)
+    return out
+
+
+def _compare(res, ref, b, LV, threshold=0.1):
+    n = len(ref)
+    qh = res["qhat"].cpu().numpy()
+    z = res["z"].cpu().numpy()
+    n_pe = res["n_pe"].cpu().numpy()
+    gr = res["g_range"].cpu().numpy()
+    cut = res["cut"].cpu().numpy()
+    t0 = res["t0"].cpu().numpy()
+    lam = res["lambda"].cpu().numpy()
+    worst = 0.0
+    for i in range(n):
+        lo = b["offsets"][i] + i * (LV - 1)
+        q = qh[lo:lo + len(ref[i]["qhat"])]
+        np.testing.assert_allclose(q, ref[i]["qhat"], rtol=1e-9, atol=1e-12, err_msg=f"waveform {i}")
+        worst = max(worst, float(np.max(np.abs(q - ref[i]["qhat"]) / np.maximum(np.abs(ref[i]["qhat"]), 1e-3))))
+        assert np.abs(ref[i]["qhat"] - threshold).min() > 1e-9, f"waveform {i}: qhat at the threshold"
+        assert z[i, :n_pe[i]].tolist() == ref[i]["z"], i
+        assert (z[i, n_pe[i]:] == -1).all()
+        assert tuple(gr[i]) == tuple(ref[i]["g_range"]), i
+        assert tuple(cut[i]) == tuple(ref[i]["cut"]), i
+        assert t0[i] == ref[i]["t0"], i
+        assert lam[i] == pytest.approx(ref[i]["lam"], rel=1e-9)
+    return worst
+
+
+def test_lucy_batched_matches_oracle():
+    wl = synth.PRESETS["batched"]
+    b = synth.generate(wl, n_wave=32, seed=151)
+    km = synth.kmax_for(b["lam"])
+    smp = gpu_sampler(wl, 10, 5, 1, 1)
+    LV = smp.support_samples()
+    print(f"[case] lucy batched n=32 r=2000 LV={LV}", flush=True)
+    res = smp.lucy(torch.from_numpy(b["wave"]).cuda(), b["offsets"], kmax=km, n_iter=2000, qhat=True)
+    torch.cuda.synchronize()
+    worst = _compare(res, _oracle(wl, b, km, 2000, LV), b, LV)
+    print(f"[lucy] 32 waveforms: qhat max rel diff {worst:.2e}, PEs listed "
+          f"{int(res['n_pe'].sum())}", flush=True)
+
+
+def test_lucy_ragged_windows_and_kmax_ranking():
+    wl = synth.PRESETS["uneven"]
+    b = synth.generate(wl, n_wave=24, seed=152)
+    km = np.minimum(synth.kmax_for(b["lam"]), 8).astype(np.int32)   # forces the ranking on busy waveforms
+    smp = gpu_sampler(wl, 10, 5, 1, 1)
+    LV = smp.support_samples()
+    print(f"[case] lucy ragged lengths={sorted(set(np.diff(b['offsets']).tolist()))} kmax=8", flush=True)
+    res = smp.lucy(torch.from_numpy(b["wave"]).cuda(), b["offsets"], kmax=km, kz=8, n_iter=300, qhat=True)
+    torch.cuda.synchronize()
+    ref = _oracle(wl, b, km, 300, LV)
+    _compare(res, ref, b, LV)
+    passed = [int((r["qhat"][LV - 1:] > 0.1).sum()) for r in ref]
+    assert max(passed) > 8   # some waveform had more candidates than kmax
+
+
+def test_lucy_degenerate_and_limits():
+    wl = synth.PRESETS["batched"]
+    b = synth.generate(wl, n_wave=3, seed=153)
+    wave = b["wave"].copy()
+    wave[b["offsets"][1]:b["offsets"][2]] = -np.abs(wave[b["offsets"][1]:b["offsets"][2]]) - 0.01
+    km = np.full(3, 16, np.int32)
+    smp = gpu_sampler(wl, 10, 5, 1, 1)
+    LV = smp.support_samples()
+    res = smp.lucy(torch.from_numpy(wave).cuda(), b["offsets"], kmax=km, n_iter=50, qhat=True)
+    torch.cuda.synchronize()
+    assert int(res["n_pe"][1]) == 0
+    gr = res["g_range"].cpu().numpy()
+    assert gr[1, 0] > gr[1, 1]
+    # r = 0: the uniform start with the clipped data's total, in PE-charge units
+    res0 = smp.lucy(torch.from_numpy(wave).cuda(), b["offsets"], kmax=km, n_iter=0, qhat=True)
+    torch.cuda.synchronize()
+    V = lucy.ser_samples(oracle_params(wl), LV)
+    w0 = wave[:b["offsets"][1]].astype(np.float64)
+    q0 = res0["qhat"].cpu().numpy()[:len(w0) + LV - 1]
+    np.testing.assert_allclose(q0, np.maximum(w0, 0).sum() / (len(w0) + LV - 1) / V.sum(), rtol=1e-12)
+    # windows beyond the LDS are refused
+    long_off = np.array([0, 20000], np.int64)
+    with pytest.raises(RuntimeError):
+        smp.lucy(torch.zeros(20000, dtype=torch.float32).cuda(), long_off, kmax=np.array([16], np.int32))
+
+
+def test_sampling_from_the_deconvolution():
+    wl = synth.PRESETS["batched"]
+    n, C, n_steps, burn = 40, 2, 300, 150
+    b = synth.generate(wl, n_wave=n, seed=154)
+    km = synth.kmax_for(b["lam"])
+    kz = int(km.max())
+    smp = gpu_sampler(wl, n_steps, burn, C, 29)
+    LV = smp.support_samples()
+    wave = torch.from_numpy(b["wave"]).cuda()
+    res = smp.lucy(wave, b["offsets"], kmax=km, n_iter=2000)
+    z_init, g_range, t0_init = smp.start_from(res, C)
+    print(f"[case] sampling from the deconvolution n={n}: {int(res['n_pe'].sum())} initial PEs", flush=True)
+    g = to_host(smp.sample(wave, b["offsets"], b["lam"], kmax=km, kz=kz, g_range=g_range, t0_init=t0_init,
+                           z_init=z_init))
+    ref = _oracle(wl, b, km, 2000, LV)
+    zo = [r["z"] for r in ref for _ in range(C)]
+    assert zo == z_init
+    o = oracle.run(oracle_params(wl), b["wave"], b["offsets"], b["lam"], C, n_steps, burn, 29, kz, kmax=km,
+                   g_range=np.array([r["g_range"] for r in ref], np.int32), t0_init=np.array([r["t0"] for r in ref]),
+                   z_init=zo)
+    parted = compare_chains(g, o)
+    print(f"[lucy] sampling from the deconvolution: {len(parted)} of {n * C} chains parted", flush=True)
+    assert len(parted) <= 0.1 * n * C
