@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--serve-events", type=int, default=40, help="events per serving run")
     ap.add_argument("--serve-rates", default="2000", help="comma-separated event rates (Hz)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--lucy-iter", type=int, default=2000, help="Lucy-Richardson iterations of the init stage (0: skip)")
     ap.add_argument("--pmc-run", action="store_true",
                     help="one untimed step after a plain device copy of known size (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -316,6 +317,29 @@ def main():
                     "kernel_ms": avg[dom], "bytes_per_launch": nbytes}
     print(f"[bench] kernels (mean ms): {json.dumps(avg)}", file=sys.stderr, flush=True)
 
+    # ---- the initialisation stage: Lucy-Richardson deconvolution of every waveform (fsmp_lucy),
+    # timed with events on the stream it runs on; algorithmic flops = the two sums of each
+    # iteration, 2 (L_w L_V + (L_w + L_V - 1) L_V) per waveform
+    lucy = None
+    if args.lucy_iter > 0:
+        LV = smp.support_samples()
+        smp.lucy(wave, b["offsets"], kmax=km, kz=kz, n_iter=args.lucy_iter, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lres = smp.lucy(wave, b["offsets"], kmax=km, kz=kz, n_iter=args.lucy_iter, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        lms = e0.elapsed_time(e1)
+        L = np.diff(b["offsets"]).astype(np.float64)
+        lflops = 2.0 * args.lucy_iter * float((L * LV + (L + LV - 1) * LV).sum())
+        lach = lflops / (lms / 1e3)
+        lucy = {"iterations": args.lucy_iter, "ms": lms, "waveforms_per_s": n_wave / (lms / 1e3),
+                "initial_pes": int(lres["n_pe"].sum()),
+                "roofline": {"bound": "alu", "achieved": lach / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                             "frac": lach / PEAK_FP64, "traffic": None, "kernel": "lucy_kernel",
+                             "flops_per_launch": lflops}}
+        print(f"[bench] lucy {args.lucy_iter} iterations: {lms:.1f} ms", file=sys.stderr, flush=True)
+
     # ---- oracle on a bounded sample of the same workload (first cpu_wave waveforms, same chains)
     cpu = None
     if not args.no_cpu:
@@ -366,6 +390,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serving": serving,
+        "init_stage": lucy,
     }
     print(json.dumps(res))
 

@@ -125,7 +125,7 @@ typedef struct {
  * so that fsmp_posterior divides by each chain's own number of recorded sweeps.
  * z_init, z_init_offsets: host or NULL (every chain starts from the empty list), the initial
  * PE sequence of every chain (Sec. 2.3: an initial guess of z, e.g. from a deconvolution;
- * Sec. 6.2: chains started from different sequences): chain c = i * n_chains + k starts
+ * Sec. 3.2: chains started from different sequences): chain c = i * n_chains + k starts
  * from the grid indices z_init[z_init_offsets[c] .. z_init_offsets[c + 1]), n_wave *
  * n_chains + 1 offsets from 0.  Each list holds at most the waveform's kmax PEs, each inside
  * the waveform's T where phi(g / grid_sub - t0_init) > 0, and needs lambda > 0; G^-1 and
@@ -224,7 +224,7 @@ typedef struct {
  * (chain, sweep) pairs, in the same layout), which needs fsmp_samples.occ and the batch's
  * host offsets.
  *
- * Convergence (Sec. 6.2): rhat is the potential scale reduction of Gelman and Rubin over the
+ * Convergence (Sec. 3.2): rhat is the potential scale reduction of Gelman and Rubin over the
  * waveform's C chains of S recorded sweeps, without the degrees-of-freedom factor or chain
  * splitting: with chain means m_i and unbiased chain variances s_i^2, W = mean s_i^2,
  * B = S / (C - 1) sum_i (m_i - m)^2, R = sqrt(((S - 1) / S W + B / S) / W); 1 when every chain

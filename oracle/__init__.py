@@ -280,7 +280,7 @@ def chain_diagnostics(acc, S, n_chains):
     """Per waveform and for each of (N, Q, t0), from the per-chain sums of v and v^2 over
     S recorded sweeps:
 
-    * the Gelman-Rubin potential scale reduction (Sec. 6.2 convergence check; the form of
+    * the Gelman-Rubin potential scale reduction (Sec. 3.2 convergence check; the form of
       Gelman and Rubin 1992 without the degrees-of-freedom factor or chain splitting):
       chain means m_i and unbiased chain variances s_i^2, W = mean of s_i^2,
       B = S / (C - 1) sum_i (m_i - m)^2, V = (S - 1) / S W + B / S, R = sqrt(V / W);

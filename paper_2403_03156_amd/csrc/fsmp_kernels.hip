@@ -1826,29 +1826,34 @@ hipError_t launch_chain_lane_t(const ChainArgs &a, hipStream_t st, int32_t *lane
 // kernel, out[i] = sum_s X[i + s] k[s]:
 //   w^r(t)  = sum_s u[t + s] K[LV - 1 - s]          (u indexed by tau + LV - 1)
 //   c(tau)  = sum_s rp[tau + LV - 1 + s] K[s]        (rp: the ratio d / w^r, zero-padded)
-// each thread computes kLucyR consecutive outputs from a sliding window of X in
-// registers, one LDS read of X and one broadcast read of k per kLucyR FMAs.
-template <int R>
+// each thread computes kLucyR = 8 consecutive outputs from a sliding window of X in
+// registers: one LDS read of X and one broadcast read of k per 8 FMAs.  The lanes of a
+// wavefront read X 8 elements apart, so X is stored skewed, element e at e + e / 8: the
+// lanes' reads then fall in different banks.
+__device__ inline int lsk(int e) { return e + (e >> 3); }
+
 __device__ inline void lucy_corr(const double *X, const double *k, int LVp, int i0, double *acc) {
-  double xw[R];
+  // i0 and LVp are multiples of 8, so every 8-element block of X starts at 9 * block
+  double xw[kLucyR];
+  const double *xb = X + 9 * (i0 >> 3);
 #pragma unroll
-  for (int j = 0; j < R; ++j) {
-    xw[j] = X[i0 + j];
+  for (int j = 0; j < kLucyR; ++j) {
+    xw[j] = xb[j];
     acc[j] = 0.0;
   }
   for (int s = 0; s < LVp; s += 8) {
+    const double *nb = X + 9 * ((i0 + kLucyR + s) >> 3);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const double ks = k[s + u];
 #pragma unroll
-      for (int j = 0; j < R; ++j) acc[j] = fma(xw[j], ks, acc[j]);
+      for (int j = 0; j < kLucyR; ++j) acc[j] = fma(xw[j], ks, acc[j]);
 #pragma unroll
-      for (int j = 0; j < R - 1; ++j) xw[j] = xw[j + 1];
-      xw[R - 1] = X[i0 + R + s + u];
+      for (int j = 0; j < kLucyR - 1; ++j) xw[j] = xw[j + 1];
+      xw[kLucyR - 1] = nb[u];
     }
   }
 }
-
 
 __global__ void __launch_bounds__(256) lucy_kernel(LucyArgs a) {
   extern __shared__ double lds[];
@@ -1859,14 +1864,17 @@ __global__ void __launch_bounds__(256) lucy_kernel(LucyArgs a) {
     K[s] = a.kern[s];
     Kr[s] = s < LV ? a.kern[LV - 1 - s] : 0.0;
   }
+  __shared__ double redl[8];
+  __shared__ int redc[8];
   for (int64_t w = blockIdx.x; w < a.n_wave; w += gridDim.x) {
     const int Lw = (int)(a.woff[w + 1] - a.woff[w]);
     const int ntau = Lw + LV - 1;
     const int nch = (ntau + kLucyR - 1) / kLucyR * kLucyR;
-    double *d = Kr + LVp;                  // [Lw]
-    double *u = d + Lw;                    // [nch + LVp + R]: tau + LV - 1, zero beyond ntau
-    double *rp = u + nch + LVp + kLucyR;   // [LV - 1 zeros | ratio(Lw) | zeros]
-    const int nrp = nch + LVp + kLucyR + LVp;
+    const int nu = nch + LVp + kLucyR;          // elements of u (zero beyond ntau)
+    const int nrp = nch + LVp + kLucyR + LVp;   // elements of rp: LV - 1 zeros | ratio | zeros
+    double *d = Kr + LVp;                       // [Lw], plain layout
+    double *u = d + Lw;                         // skewed, lsk(nu) + 1 doubles
+    double *rp = u + lsk(nu) + 1;               // skewed, lsk(nrp) + 1 doubles
     const float *x = a.wave + a.woff[w];
     __syncthreads();
     double sd = 0.0;
@@ -1875,51 +1883,53 @@ __global__ void __launch_bounds__(256) lucy_kernel(LucyArgs a) {
       d[t] = v;
       sd += v;
     }
-    // block sum of the clipped data
-    __shared__ double red[8];
     for (int o = 32; o > 0; o >>= 1) sd += __shfl_xor(sd, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sd;
+    if ((threadIdx.x & 63) == 0) redl[threadIdx.x >> 6] = sd;
     __syncthreads();
     double tot = 0.0;
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) tot += red[i];
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) tot += redl[i];
     const double u0 = tot / ntau;
-    for (int i = threadIdx.x; i < nch + LVp + kLucyR; i += blockDim.x) u[i] = i < ntau ? u0 : 0.0;
-    for (int i = threadIdx.x; i < nrp; i += blockDim.x) rp[i] = 0.0;
+    for (int i = threadIdx.x; i < nu; i += blockDim.x) u[lsk(i)] = i < ntau ? u0 : 0.0;
+    for (int i = threadIdx.x; i < nrp; i += blockDim.x) rp[lsk(i)] = 0.0;
     __syncthreads();
     for (int it = 0; it < a.n_iter; ++it) {
       // w^r and the ratio d / w^r (0 where w^r is not positive)
       for (int c0 = threadIdx.x * kLucyR; c0 < Lw; c0 += blockDim.x * kLucyR) {
         double acc[kLucyR];
-        lucy_corr<kLucyR>(u, Kr, LVp, c0, acc);
+        lucy_corr(u, Kr, LVp, c0, acc);
 #pragma unroll
         for (int j = 0; j < kLucyR; ++j) {
           const int t = c0 + j;
-          if (t < Lw) rp[LV - 1 + t] = acc[j] > 0.0 ? d[t] / acc[j] : 0.0;
+          if (t < Lw) rp[lsk(LV - 1 + t)] = acc[j] > 0.0 ? d[t] / acc[j] : 0.0;
         }
       }
       __syncthreads();
       // u(tau) *= sum_t ratio(t) K(t - tau)
       for (int c0 = threadIdx.x * kLucyR; c0 < ntau; c0 += blockDim.x * kLucyR) {
         double acc[kLucyR];
-        lucy_corr<kLucyR>(rp, K, LVp, c0, acc);
+        lucy_corr(rp, K, LVp, c0, acc);
+        double *ub = u + 9 * (c0 >> 3);
 #pragma unroll
         for (int j = 0; j < kLucyR; ++j)
-          if (c0 + j < ntau) u[c0 + j] *= acc[j];
+          if (c0 + j < ntau) ub[j] *= acc[j];
       }
       __syncthreads();
     }
-    // qhat in PE-charge units; candidates tau >= 0 above the threshold (flags in d)
+    // qhat in PE-charge units (back into a plain layout in rp); candidates tau >= 0 above the
+    // threshold (flags in d)
     double lam = 0.0;
     int cnt = 0;
     for (int i = threadIdx.x; i < ntau; i += blockDim.x) {
-      const double q = u[i] * a.inv_area;
-      u[i] = q;
+      const double q = u[lsk(i)] * a.inv_area;
+      rp[i] = q;
       lam += q;
       if (a.qhat) a.qhat[a.woff[w] + w * (int64_t)(LV - 1) + i] = q;
     }
     __syncthreads();
+    const double *qh = rp;
+    double *flag = u;  // plain layout from here on
     for (int i = threadIdx.x; i < Lw; i += blockDim.x) {
-      const bool c = u[i + LV - 1] > a.threshold;   // tau = i >= 0
+      const bool c = qh[i + LV - 1] > a.threshold;   // tau = i >= 0
       d[i] = c ? 1.0 : 0.0;
       cnt += c;
     }
@@ -1928,8 +1938,6 @@ __global__ void __launch_bounds__(256) lucy_kernel(LucyArgs a) {
       cnt += __shfl_xor(cnt, o);
     }
     __syncthreads();
-    __shared__ double redl[8];
-    __shared__ int redc[8];
     if ((threadIdx.x & 63) == 0) {
       redl[threadIdx.x >> 6] = lam;
       redc[threadIdx.x >> 6] = cnt;
@@ -1946,19 +1954,19 @@ __global__ void __launch_bounds__(256) lucy_kernel(LucyArgs a) {
       // keep the kmax largest qhat (ties: earlier tau): rank every candidate
       for (int i = threadIdx.x; i < Lw; i += blockDim.x) {
         if (d[i] == 0.0) {
-          rp[i] = 0.0;
+          flag[i] = 0.0;
           continue;
         }
-        const double qi = u[i + LV - 1];
+        const double qi = qh[i + LV - 1];
         int rank = 0;
         for (int j = 0; j < Lw; ++j) {
-          const double qj = u[j + LV - 1];
+          const double qj = qh[j + LV - 1];
           rank += (qj > a.threshold) && (qj > qi || (qj == qi && j < i));
         }
-        rp[i] = rank < kmax ? 1.0 : 0.0;
+        flag[i] = rank < kmax ? 1.0 : 0.0;
       }
       __syncthreads();
-      for (int i = threadIdx.x; i < Lw; i += blockDim.x) d[i] = rp[i];
+      for (int i = threadIdx.x; i < Lw; i += blockDim.x) d[i] = flag[i];
       __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -2006,8 +2014,9 @@ hipError_t launch_prologue(const PrologueArgs &a, hipStream_t st) {
 size_t lucy_lds_bytes(int64_t Lw, int LVp) {
   const int64_t ntau = Lw + LVp - 1;
   const int64_t nch = (ntau + kLucyR - 1) / kLucyR * kLucyR;
-  // K, reversed K, d, u (padded for the window reads), rp (padded both sides)
-  return sizeof(double) * (size_t)(2 * LVp + Lw + (nch + LVp + kLucyR) + (nch + LVp + kLucyR + LVp));
+  const int64_t nu = nch + LVp + kLucyR, nrp = nu + LVp;
+  // K, reversed K, d, then u and rp skewed by one double in nine
+  return sizeof(double) * (size_t)(2 * LVp + Lw + (nu + nu / 8 + 1) + (nrp + nrp / 8 + 1));
 }
 
 hipError_t launch_lucy(const LucyArgs &a, int64_t max_len, hipStream_t st) {

@@ -1,5 +1,5 @@
 """Posterior extras of fsmp_posterior against the oracle (needs an MI355X): the Gelman-Rubin
-R and the between-chain MCSE of N, Q and t0 (Sec. 6.2 convergence check), lambda-hat_FSMP
+R and the between-chain MCSE of N, Q and t0 (Sec. 3.2 convergence check), lambda-hat_FSMP
 (eq. reduce-mu0) and lambda-hat_Q = E[Q] / mu_q.
 
 On every waveform whose chains all match the oracle's, the kernel's values must equal the

@@ -1,7 +1,7 @@
 """The oracle's convergence diagnostics and lambda estimate against hand-derived values,
 closed forms and brute force.
 
-* Gelman-Rubin R (Sec. 6.2 convergence check) on two chains worked by hand:
+* Gelman-Rubin R (Sec. 3.2 convergence check) on two chains worked by hand:
   (1, -1, 1, -1) and (3, 1, 3, 1) give W = 4/3, B = 8, V = 3, R = 1.5, and a
   between-chain MCSE of 1; constant chains give 1 (equal) or inf (different);
 * R near 1 for long independent chains of one law, well above 1.1 for chains of two

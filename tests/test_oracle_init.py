@@ -1,5 +1,5 @@
 """The oracle started from given PE sequences (Sec. 2.3: an initial guess of z speeds up
-convergence but does not change the target; Sec. 6.2: chains from different starts).
+convergence but does not change the target; Sec. 3.2: chains from different starts).
 
 * tiny grids: chains started from random multisets (different per chain) reach the
   enumerated posterior P(N = k), E[N];
