@@ -1188,7 +1188,7 @@ fsmp_status fsmp_lucy(fsmp_ctx *c, const fsmp_batch *b, int32_t n_iter, double t
     return fail(c, FSMP_EINVAL, "need n_iter >= 0, a finite threshold >= 0 and margin >= 0");
   if (b->offsets[0] != 0) return fail(c, FSMP_EINVAL, "offsets[0] must be 0");
   const int LV = c->tab.LV, sub = c->cfg.grid_sub;
-  const int LVp = (LV + 7) / 8 * 8;
+  const int LVp = (LV + 23) / 24 * 24;  // a multiple of both window widths of the kernel
   std::vector<int32_t> kmx(n);
   int64_t max_len = 0;
   for (int64_t i = 0; i < n; ++i) {
@@ -1202,21 +1202,22 @@ fsmp_status fsmp_lucy(fsmp_ctx *c, const fsmp_batch *b, int32_t n_iter, double t
   if (lucy_lds_bytes(max_len, LVp) + 1024 > 160 * 1024)
     return fail(c, FSMP_ENOTSUP, "a window of %lld samples does not fit the deconvolution's LDS", (long long)max_len);
   // the SER at whole samples, normalised to unit sum
-  std::vector<double> kern(LVp, 0.0);
+  std::vector<double> kern(2 * (size_t)LVp, 0.0);  // K, then K reversed
   double area = 0.0;
   for (int s0 = 0; s0 < LV; ++s0) area += c->tab.vtab[(size_t)s0 * sub];
   if (!(area > 0.0)) return fail(c, FSMP_EINVAL, "the SER has no area at whole samples");
   for (int s0 = 0; s0 < LV; ++s0) kern[s0] = c->tab.vtab[(size_t)s0 * sub] / area;
+  for (int s0 = 0; s0 < LV; ++s0) kern[LVp + s0] = kern[LV - 1 - s0];
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(c->device);
   const hipStream_t st = (hipStream_t)hip_stream;
   if (c->stage_pending) (void)hipEventSynchronize(c->stage_done);
   auto pad16 = [](size_t nb) { return (nb + 15) & ~(size_t)15; };
-  const size_t nbo = sizeof(int64_t) * (n + 1), nbk = sizeof(int32_t) * n, nbv = sizeof(double) * LVp;
+  const size_t nbo = sizeof(int64_t) * (n + 1), nbk = sizeof(int32_t) * n, nbv = sizeof(double) * 2 * LVp;
   hipError_t e = c->lwoff.ensure(n + 1);
   if (e == hipSuccess) e = c->lkmax.ensure(n);
-  if (e == hipSuccess) e = c->lkern.ensure(LVp);
+  if (e == hipSuccess) e = c->lkern.ensure(2 * (size_t)LVp);
   if (e == hipSuccess) e = c->stage.ensure(pad16(nbo) + pad16(nbk) + pad16(nbv));
   if (e != hipSuccess) {
     (void)hipSetDevice(prev);
@@ -1236,6 +1237,7 @@ fsmp_status fsmp_lucy(fsmp_ctx *c, const fsmp_batch *b, int32_t n_iter, double t
   a.woff = c->lwoff.p;
   a.kmax = c->lkmax.p;
   a.kern = c->lkern.p;
+  a.kern_rev = c->lkern.p + LVp;
   a.LV = LV;
   a.LVp = LVp;
   a.sub = sub;

@@ -134,7 +134,8 @@ struct LucyArgs {
   const float *wave;
   const int64_t *woff;     // [n+1]
   const int32_t *kmax;     // [n]
-  const double *kern;      // [LVp] V(s) / sum V, zero-padded to LVp (a multiple of 8)
+  const double *kern;      // [LVp] V(s) / sum V, zero-padded to LVp (a multiple of 24)
+  const double *kern_rev;  // [LVp] kern[LV - 1 - s], zero beyond LV
   int32_t LV, LVp, sub, n_iter, kz;
   int64_t n_wave;
   double inv_area;         // 1 / sum_s V(s): deconvolved flux -> PE charge
@@ -150,7 +151,6 @@ struct LucyArgs {
   int32_t *cut;            // [n][2]
   double *qhat;            // optional: row w at woff[w] + w (LV - 1), L_w + LV - 1 entries
 };
-constexpr int kLucyR = 8;  // outputs per thread of a convolution pass
 size_t lucy_lds_bytes(int64_t Lw, int LVp);
 hipError_t launch_lucy(const LucyArgs &a, int64_t max_len, hipStream_t st);
 

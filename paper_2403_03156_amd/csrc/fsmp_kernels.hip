@@ -25,6 +25,7 @@
 
 #include <math.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "fsmp_internal.h"
@@ -1826,31 +1827,45 @@ hipError_t launch_chain_lane_t(const ChainArgs &a, hipStream_t st, int32_t *lane
 // kernel, out[i] = sum_s X[i + s] k[s]:
 //   w^r(t)  = sum_s u[t + s] K[LV - 1 - s]          (u indexed by tau + LV - 1)
 //   c(tau)  = sum_s rp[tau + LV - 1 + s] K[s]        (rp: the ratio d / w^r, zero-padded)
-// each thread computes kLucyR = 8 consecutive outputs from a sliding window of X in
-// registers: one LDS read of X and one broadcast read of k per 8 FMAs.  The lanes of a
-// wavefront read X 8 elements apart, so X is stored skewed, element e at e + e / 8: the
-// lanes' reads then fall in different banks.
-__device__ inline int lsk(int e) { return e + (e >> 3); }
+// each thread computes R consecutive outputs from a sliding window of X in registers:
+// one LDS read of X per R FMAs.  The kernel k is the same for every lane: it is read from
+// a read-only device array by scalar loads (eight values per load, through the scalar
+// cache), which costs no LDS bandwidth and no vector issue slot.  The lanes of a wavefront
+// read X R elements apart, so X is stored skewed by one pad element per R (element e at
+// e + e / R): the lanes' reads then fall in different banks.  The first sum uses R = 8;
+// the second, which has L_V - 1 more outputs, R = 6, which fills whole wavefronts at the
+// usual window lengths (1,024 samples: 128 and 187 chunks, three wavefronts).
+constexpr int kLucyR1 = 8, kLucyR2 = 6;
 
-__device__ inline void lucy_corr(const double *X, const double *k, int LVp, int i0, double *acc) {
-  // i0 and LVp are multiples of 8, so every 8-element block of X starts at 9 * block
-  double xw[kLucyR];
-  const double *xb = X + 9 * (i0 >> 3);
+template <int R>
+__device__ inline int lsk(int e) {
+  return e + e / R;
+}
+
+// the read-only kernel array, seen through the constant address space so that its
+// wavefront-uniform reads compile to scalar loads
+typedef const __attribute__((address_space(4))) double *ConstD;
+
+template <int R>
+__device__ inline void lucy_corr(const double *X, ConstD k, int LVp, int i0, double *acc) {
+  // i0 and LVp are multiples of R, so every R-element block of X starts at (R + 1) * block
+  double xw[R];
+  const double *xb = X + (R + 1) * (i0 / R);
 #pragma unroll
-  for (int j = 0; j < kLucyR; ++j) {
+  for (int j = 0; j < R; ++j) {
     xw[j] = xb[j];
     acc[j] = 0.0;
   }
-  for (int s = 0; s < LVp; s += 8) {
-    const double *nb = X + 9 * ((i0 + kLucyR + s) >> 3);
+  const double *nb = xb + (R + 1);  // the next block; one block further per R taps
+  for (int s = 0; s < LVp; s += R, nb += R + 1) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < R; ++u) {
       const double ks = k[s + u];
 #pragma unroll
-      for (int j = 0; j < kLucyR; ++j) acc[j] = fma(xw[j], ks, acc[j]);
+      for (int j = 0; j < R; ++j) acc[j] = fma(xw[j], ks, acc[j]);
 #pragma unroll
-      for (int j = 0; j < kLucyR - 1; ++j) xw[j] = xw[j + 1];
-      xw[kLucyR - 1] = nb[u];
+      for (int j = 0; j < R - 1; ++j) xw[j] = xw[j + 1];
+      xw[R - 1] = nb[u];
     }
   }
 }
@@ -1858,28 +1873,26 @@ __device__ inline void lucy_corr(const double *X, const double *k, int LVp, int 
 __global__ void __launch_bounds__(256) lucy_kernel(LucyArgs a) {
   extern __shared__ double lds[];
   const int LV = a.LV, LVp = a.LVp;
-  double *K = lds;              // [LVp]
-  double *Kr = K + LVp;         // [LVp] reversed, K[LV - 1 - s], zero beyond LV
-  for (int s = threadIdx.x; s < LVp; s += blockDim.x) {
-    K[s] = a.kern[s];
-    Kr[s] = s < LV ? a.kern[LV - 1 - s] : 0.0;
-  }
+  const ConstD K = (ConstD)a.kern;       // [LVp] K[s], zero beyond LV
+  const ConstD Kr = (ConstD)a.kern_rev;  // [LVp] K[LV - 1 - s], zero beyond LV
   __shared__ double redl[8];
   __shared__ int redc[8];
+  constexpr int R1 = kLucyR1, R2 = kLucyR2;
   for (int64_t w = blockIdx.x; w < a.n_wave; w += gridDim.x) {
     const int Lw = (int)(a.woff[w + 1] - a.woff[w]);
     const int ntau = Lw + LV - 1;
-    const int nch = (ntau + kLucyR - 1) / kLucyR * kLucyR;
-    const int nu = nch + LVp + kLucyR;          // elements of u (zero beyond ntau)
-    const int nrp = nch + LVp + kLucyR + LVp;   // elements of rp: LV - 1 zeros | ratio | zeros
-    double *d = Kr + LVp;                       // [Lw], plain layout
-    double *u = d + Lw;                         // skewed, lsk(nu) + 1 doubles
-    double *rp = u + lsk(nu) + 1;               // skewed, lsk(nrp) + 1 doubles
+    const int nd = (Lw + R1 - 1) / R1 * R1;       // d zero-padded to whole first-sum chunks
+    const int n2 = (ntau + R2 - 1) / R2 * R2;     // outputs of the second sum, whole chunks
+    const int nu = n2 + LVp + R1;                 // elements of u (zero beyond ntau)
+    const int nrp = n2 + LVp + R2;                // elements of rp: LV - 1 zeros | ratio | zeros
+    double *d = lds;                              // [nd], plain layout
+    double *u = d + nd;                           // skewed by R1
+    double *rp = u + lsk<R1>(nu) + 1;             // skewed by R2
     const float *x = a.wave + a.woff[w];
     __syncthreads();
     double sd = 0.0;
-    for (int t = threadIdx.x; t < Lw; t += blockDim.x) {
-      const double v = fmax((double)x[t], 0.0);
+    for (int t = threadIdx.x; t < nd; t += blockDim.x) {
+      const double v = t < Lw ? fmax((double)x[t], 0.0) : 0.0;
       d[t] = v;
       sd += v;
     }
@@ -1889,29 +1902,33 @@ __global__ void __launch_bounds__(256) lucy_kernel(LucyArgs a) {
     double tot = 0.0;
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) tot += redl[i];
     const double u0 = tot / ntau;
-    for (int i = threadIdx.x; i < nu; i += blockDim.x) u[lsk(i)] = i < ntau ? u0 : 0.0;
-    for (int i = threadIdx.x; i < nrp; i += blockDim.x) rp[lsk(i)] = 0.0;
+    for (int i = threadIdx.x; i < nu; i += blockDim.x) u[lsk<R1>(i)] = i < ntau ? u0 : 0.0;
+    for (int i = threadIdx.x; i < nrp; i += blockDim.x) rp[lsk<R2>(i)] = 0.0;
     __syncthreads();
     for (int it = 0; it < a.n_iter; ++it) {
-      // w^r and the ratio d / w^r (0 where w^r is not positive)
-      for (int c0 = threadIdx.x * kLucyR; c0 < Lw; c0 += blockDim.x * kLucyR) {
-        double acc[kLucyR];
-        lucy_corr(u, Kr, LVp, c0, acc);
+      // w^r and the ratio d / w^r (0 where w^r is not positive).  The writes need no
+      // bounds: d is zero past L_w, so the ratios written past the window stay 0
+      for (int c0 = threadIdx.x * R1; c0 < Lw; c0 += blockDim.x * R1) {
+        double acc[R1];
+        lucy_corr<R1>(u, Kr, LVp, c0, acc);
 #pragma unroll
-        for (int j = 0; j < kLucyR; ++j) {
-          const int t = c0 + j;
-          if (t < Lw) rp[lsk(LV - 1 + t)] = acc[j] > 0.0 ? d[t] / acc[j] : 0.0;
+        for (int j = 0; j < R1; ++j) {
+          // exact division: w^r decays to denormals where d is 0 (0 / w^r must stay 0)
+          const double v = acc[j];
+          const double q = d[c0 + j] / v;
+          rp[lsk<R2>(LV - 1 + c0 + j)] = v > 0.0 ? q : 0.0;
         }
       }
       __syncthreads();
-      // u(tau) *= sum_t ratio(t) K(t - tau)
-      for (int c0 = threadIdx.x * kLucyR; c0 < ntau; c0 += blockDim.x * kLucyR) {
-        double acc[kLucyR];
-        lucy_corr(rp, K, LVp, c0, acc);
-        double *ub = u + 9 * (c0 >> 3);
+      // u(tau) *= sum_t ratio(t) K(t - tau); u stays 0 past tau = L_w - 1 (a select, no branch)
+      for (int c0 = threadIdx.x * R2; c0 < ntau; c0 += blockDim.x * R2) {
+        double acc[R2];
+        lucy_corr<R2>(rp, K, LVp, c0, acc);
 #pragma unroll
-        for (int j = 0; j < kLucyR; ++j)
-          if (c0 + j < ntau) ub[j] *= acc[j];
+        for (int j = 0; j < R2; ++j) {
+          double *ue = u + lsk<R1>(c0 + j);
+          *ue = c0 + j < ntau ? *ue * acc[j] : 0.0;
+        }
       }
       __syncthreads();
     }
@@ -1920,7 +1937,7 @@ __global__ void __launch_bounds__(256) lucy_kernel(LucyArgs a) {
     double lam = 0.0;
     int cnt = 0;
     for (int i = threadIdx.x; i < ntau; i += blockDim.x) {
-      const double q = u[lsk(i)] * a.inv_area;
+      const double q = u[lsk<R1>(i)] * a.inv_area;
       rp[i] = q;
       lam += q;
       if (a.qhat) a.qhat[a.woff[w] + w * (int64_t)(LV - 1) + i] = q;
@@ -2012,18 +2029,19 @@ hipError_t launch_prologue(const PrologueArgs &a, hipStream_t st) {
 }
 
 size_t lucy_lds_bytes(int64_t Lw, int LVp) {
+  const int64_t R1 = kLucyR1, R2 = kLucyR2;
   const int64_t ntau = Lw + LVp - 1;
-  const int64_t nch = (ntau + kLucyR - 1) / kLucyR * kLucyR;
-  const int64_t nu = nch + LVp + kLucyR, nrp = nu + LVp;
-  // K, reversed K, d, then u and rp skewed by one double in nine
-  return sizeof(double) * (size_t)(2 * LVp + Lw + (nu + nu / 8 + 1) + (nrp + nrp / 8 + 1));
+  const int64_t nd = (Lw + R1 - 1) / R1 * R1, n2 = (ntau + R2 - 1) / R2 * R2;
+  const int64_t nu = n2 + LVp + R1, nrp = n2 + LVp + R2;
+  // d, then u and rp, each skewed by one pad element per window width
+  return sizeof(double) * (size_t)(nd + (nu + nu / R1 + 1) + (nrp + nrp / R2 + 1));
 }
 
 hipError_t launch_lucy(const LucyArgs &a, int64_t max_len, hipStream_t st) {
   if (a.n_wave == 0) return hipSuccess;
   const size_t lds = lucy_lds_bytes(max_len, a.LVp);
   // enough threads for the longer pass of the longest window, in whole wavefronts
-  const int64_t chunks = (max_len + a.LV - 1 + kLucyR - 1) / kLucyR;
+  const int64_t chunks = std::max((max_len + kLucyR1 - 1) / kLucyR1, (max_len + a.LV - 1 + kLucyR2 - 1) / kLucyR2);
   int threads = (int)((chunks + 63) / 64 * 64);
   threads = threads < 64 ? 64 : (threads > 256 ? 256 : threads);
   if (lds > 64 * 1024) {

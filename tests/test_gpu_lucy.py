@@ -91,6 +91,23 @@ def test_lucy_ragged_windows_and_kmax_ranking():
     assert max(passed) > 8   # some waveform had more candidates than kmax
 
 
+def test_lucy_noise_dominated_windows():
+    # mostly noise: the clipped data are 0 over long stretches, where qhat and w^r decay
+    # geometrically into denormals over 2,000 iterations; 0 / w^r must stay 0 there
+    wl = synth.PRESETS["batched"]
+    lam = np.array([0.0, 0.0, 0.05, 0.1, 0.5, 1.0, 0.0, 2.0])
+    b = synth.generate(wl, n_wave=len(lam), seed=155, lam=lam)
+    km = np.full(len(lam), 16, np.int32)
+    smp = gpu_sampler(wl, 10, 5, 1, 1)
+    LV = smp.support_samples()
+    res = smp.lucy(torch.from_numpy(b["wave"]).cuda(), b["offsets"], kmax=km, n_iter=2000, qhat=True)
+    torch.cuda.synchronize()
+    assert np.isfinite(res["qhat"].cpu().numpy()).all()
+    ref = _oracle(wl, b, km, 2000, LV)
+    assert min(r["qhat"][r["qhat"] > 0].min() for r in ref) < 1e-300   # denormals reached
+    _compare(res, ref, b, LV)
+
+
 def test_lucy_degenerate_and_limits():
     wl = synth.PRESETS["batched"]
     b = synth.generate(wl, n_wave=3, seed=153)
