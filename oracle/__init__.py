@@ -41,6 +41,10 @@ class Params(ctypes.Structure):
         ("J", ctypes.c_double),
         ("t0_sd", ctypes.c_double),
         ("shift_sd", ctypes.c_double),
+        ("n_mix", ctypes.c_int32),
+        ("mix_w", ctypes.c_double * 8),
+        ("mix_mu", ctypes.c_double * 8),
+        ("mix_sigma", ctypes.c_double * 8),
     ]
 
 
@@ -52,9 +56,17 @@ assert LOGREC_DTYPE.itemsize == 40
 
 def make_params(ser=(8.0, 1.5, 6.0), ser_amp=1.0, ser_support=0, sub=4, sigma_eps=0.1, mu_q=1.0, sigma_q=0.3,
                 phi_kind=PHI_EXP, tau_rise=0.0, tau_decay=20.0, t0_min=50.0, t0_max=100.0, J=0.25,
-                t0_sd=1.0, shift_sd=1.0) -> Params:
-    return Params(ser[0], ser[1], ser[2], ser_amp, ser_support, sub, sigma_eps, mu_q, sigma_q, phi_kind,
-                  tau_rise, tau_decay, t0_min, t0_max, J, t0_sd, shift_sd)
+                t0_sd=1.0, shift_sd=1.0, mix=None) -> Params:
+    """mix: None (one normal charge law N(mu_q, sigma_q^2)) or (G, mu, sigma) of the MCP-PMT
+    Gaussian mixture (Sec. 2.1, eq. mcp-multi-norm), up to 8 components."""
+    p = Params(ser[0], ser[1], ser[2], ser_amp, ser_support, sub, sigma_eps, mu_q, sigma_q, phi_kind,
+               tau_rise, tau_decay, t0_min, t0_max, J, t0_sd, shift_sd)
+    if mix is not None:
+        g, mu, sg = (list(map(float, v)) for v in mix)
+        p.n_mix = len(g)
+        for i in range(len(g)):
+            p.mix_w[i], p.mix_mu[i], p.mix_sigma[i] = g[i], mu[i], sg[i]
+    return p
 
 
 _lib = None
@@ -90,7 +102,7 @@ def lib():
         L.ora_lambda_T.restype = _d
         L.ora_birth_draw.argtypes = [_P(Params), _d, _i32, _i32, _d]
         L.ora_birth_draw.restype = _i32
-        L.ora_log_likelihood.argtypes = [_P(Params), _vp, _i32, _vp, _i32, _vp]
+        L.ora_log_likelihood.argtypes = [_P(Params), _vp, _i32, _vp, _vp, _i32, _vp]
         L.ora_log_likelihood.restype = _d
         L.ora_overlap.argtypes = [_P(Params), _i32, _i32, _i32]
         L.ora_overlap.restype = _d
@@ -99,7 +111,7 @@ def lib():
         L.ora_t0_log_alpha.argtypes = [_P(Params), _d, _i32, _i32, _vp, _i32, _d, _d]
         L.ora_t0_log_alpha.restype = _d
         L.ora_run.argtypes = [_P(Params), _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _u64, _i32,
-                              _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32]
+                              _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32]
         L.ora_charge_draw.argtypes = [_P(Params), _vp, _i32, _vp, _i32, _vp, _vp]
         L.ora_charge_draw.restype = ctypes.c_int
         L.ora_charge_normals.argtypes = [_u64, _u64, _i32, _i32, _vp]
@@ -130,11 +142,13 @@ def ser_table(p: Params):
     return out[: p.sub * LV].copy(), LV
 
 
-def log_likelihood(p: Params, w, z):
+def log_likelihood(p: Params, w, z, e=None):
+    """log p(w | z) and the charges' conditional mean; e: the PEs' mixture components (MCP form)."""
     w = np.ascontiguousarray(w, dtype=np.float32)
     z = np.ascontiguousarray(z, dtype=np.int32)
+    e = None if e is None else np.ascontiguousarray(e, dtype=np.int32)
     x = np.zeros(max(len(z), 1), dtype=np.float64)
-    v = lib().ora_log_likelihood(ctypes.byref(p), _ptr(w), len(w), _ptr(z), len(z), _ptr(x))
+    v = lib().ora_log_likelihood(ctypes.byref(p), _ptr(w), len(w), _ptr(z), _ptr(e), len(z), _ptr(x))
     return v, x[: len(z)]
 
 
@@ -193,10 +207,11 @@ def run(p: Params, wave, offsets, lam, n_chains, n_steps, burn_in, seed, kz, kma
     r.zdraw = np.zeros((tot, n_rec, kz), np.int32) if (n_rec and charges) else None
     r.occ_chain = np.zeros(n_chains * p.sub * int(offsets[-1]), np.int32) if occupancy else None
     zi, zo = flatten_lists(z_init, tot)
+    r.e = np.zeros((tot, kz), np.int32) if p.n_mix > 0 else None
     lib().ora_run(ctypes.byref(p), nw, _ptr(wave), _ptr(offsets), _ptr(lam), _ptr(kmax), _ptr(g_range),
                   _ptr(t0_init), _ptr(wave_id), n_chains, n_steps, burn_in, seed, kz, _ptr(r.N), _ptr(r.t0),
                   _ptr(r.z), _ptr(r.x), _ptr(r.acc), _ptr(r.nhist), _ptr(r.counts), _ptr(r.status), _ptr(r.log),
-                  _ptr(r.trace), thin, _ptr(r.qdraw), _ptr(r.zdraw), _ptr(r.occ_chain), _ptr(zi), _ptr(zo), n_threads)
+                  _ptr(r.trace), thin, _ptr(r.qdraw), _ptr(r.zdraw), _ptr(r.occ_chain), _ptr(zi), _ptr(zo), _ptr(r.e), n_threads)
     r.occ = None
     if occupancy:
         # sum the chains' rows of every waveform

@@ -188,3 +188,74 @@ def shift_pmf(m: Model, s):
     """P(rint(xi / dt) = s) for xi ~ N(0, shift_sd^2): normal mass of the cell around s dt."""
     dt = 1.0 / m.sub
     return stats.norm.cdf((s + 0.5) * dt / m.shift_sd) - stats.norm.cdf((s - 0.5) * dt / m.shift_sd)
+
+
+# ---------------------------------------------------------------- MCP-PMT mixture charge law
+# Sec. 2.1 (eq. mcp-multi-norm), Sec. 2.4 (eq. mcp), App. A for MCP-PMTs: every PE carries a
+# component e with charge law N(mu_e, sigma_e^2) and prior weight G(e).
+
+def dense_logp_mix(m: Model, w, z, e, mix):
+    """log N(w; A mu_e, A diag(sigma_e^2) A^T + sigma_eps^2 I), the definition."""
+    G, mu, sg = (np.asarray(v, np.float64) for v in mix)
+    w = np.asarray(w, dtype=np.float64)
+    Lw = len(w)
+    A = m.A(z, Lw)
+    e = np.asarray(e, dtype=np.int64)
+    U = A @ mu[e] if len(z) else np.zeros(Lw)
+    Sig = (A * sg[e] ** 2) @ A.T + m.sigma_eps ** 2 * np.eye(Lw)
+    return stats.multivariate_normal(mean=U, cov=Sig).logpdf(w)
+
+
+def charge_mean_mix(m: Model, w, z, e, mix):
+    """E[q | z, e, w] by lstsq on [A/sigma_eps; diag(1/sigma_e)] q = [w/sigma_eps; mu_e/sigma_e]."""
+    G, mu, sg = (np.asarray(v, np.float64) for v in mix)
+    w = np.asarray(w, dtype=np.float64)
+    K = len(z)
+    if K == 0:
+        return np.zeros(0)
+    e = np.asarray(e, dtype=np.int64)
+    A = m.A(z, len(w))
+    M = np.vstack([A / m.sigma_eps, np.diag(1.0 / sg[e])])
+    r = np.concatenate([w / m.sigma_eps, mu[e] / sg[e]])
+    return np.linalg.lstsq(M, r, rcond=None)[0]
+
+
+def posterior_exact_mix(m: Model, w, lam, glo, ghi, kmax, t0, mix):
+    """Enumeration of the posterior of z = {(t_k, e_k)} at fixed t0: every multiset of
+    (grid point, component) pairs with N <= kmax, weight p(w|z) times the Poisson process
+    on T x E binned into cells (g, e) of mean lam dt phi(g dt - t0) G(e) (eq. mcp-pzmu),
+    so the prior carries 1 / prod over cells of n!.  Returns P(N = k), E[N], E[Q] and the
+    expected number of PEs in each component."""
+    G = np.asarray(mix[0], np.float64)
+    E = len(G)
+    dt = 1.0 / m.sub
+    cells = [(g, e) for g in range(glo, ghi + 1) for e in range(E)]
+    LamT = m.Lambda_T(lam, t0, glo, ghi)
+    states, lw, Qs = [], [], []
+    for k in range(kmax + 1):
+        for c in itertools.combinations_with_replacement(cells, k):
+            z = [g for g, _ in c]
+            e = [x for _, x in c]
+            lp = -LamT
+            ok = True
+            for g, x in c:
+                f = float(m.phi(g * dt - t0))
+                if f <= 0:
+                    ok = False
+                    break
+                lp += math.log(lam * dt * f * G[x])
+            if not ok:
+                continue
+            _, counts = np.unique(np.asarray(c).reshape(-1, 2), axis=0, return_counts=True) if k else (None, [])
+            lp -= sum(gammaln(n + 1) for n in counts)
+            states.append(c)
+            lw.append(dense_logp_mix(m, w, z, e, mix) + lp)
+            Qs.append(charge_mean_mix(m, w, z, e, mix).sum())
+    lw = np.array(lw)
+    wt = np.exp(lw - lw.max())
+    wt /= wt.sum()
+    Ns = np.array([len(c) for c in states])
+    pN = np.array([wt[Ns == k].sum() for k in range(kmax + 1)])
+    ne = np.array([[sum(1 for _, x in c if x == q) for q in range(E)] for c in states], np.float64)
+    return {"pN": pN, "EN": float((Ns * wt).sum()), "EQ": float((np.array(Qs) * wt).sum()),
+            "En_e": (ne * wt[:, None]).sum(0)}

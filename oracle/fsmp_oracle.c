@@ -64,7 +64,36 @@ typedef struct {
   int32_t phi_kind;
   double tau_rise, tau_decay, t0_min, t0_max;
   double J, t0_sd, shift_sd;
+  /* MCP-PMT charge model (Sec. 2.1, eq. mcp-multi-norm): n_mix > 0 components with
+   * probabilities mix_w, means mix_mu and standard deviations mix_sigma; every PE carries
+   * its component index e.  n_mix = 0: the single normal N(mu_q, sigma_q^2). */
+  int32_t n_mix;
+  double mix_w[8], mix_mu[8], mix_sigma[8];
 } ora_params;
+
+/* charge law of a PE: ridge rho = sigma_eps^2 / sigma^2 and mean mu of its component */
+static void pe_law(const ora_params *p, const int32_t *ez, int k, double *rho, double *mu) {
+  double s = p->sigma_eps * p->sigma_eps;
+  if (p->n_mix > 0 && ez) {
+    double sg = p->mix_sigma[ez[k]];
+    *rho = s / (sg * sg);
+    *mu = p->mix_mu[ez[k]];
+  } else {
+    *rho = s / (p->sigma_q * p->sigma_q);
+    *mu = p->mu_q;
+  }
+}
+
+/* component of a new PE: the inverse CDF of the mixture probabilities at u (Sec. 2.4: the
+ * proposal of e is G(e) itself) */
+static int32_t mix_draw(const ora_params *p, double u) {
+  double c = 0.0;
+  for (int32_t e = 0; e < p->n_mix - 1; ++e) {
+    c += p->mix_w[e];
+    if (u < c) return e;
+  }
+  return p->n_mix - 1;
+}
 
 /* one record per step of one chain; same layout as the library's log */
 typedef struct {
@@ -308,12 +337,13 @@ static double matched(const ora_ctx *c, int32_t g) {
 
 /* nu(z) from scratch; x (if not NULL) receives G^-1 b, the charges' posterior
  * mean given z.  Returns 0 on success, -1 if G is not positive definite. */
-static int nu_of(const ora_ctx *c, const int32_t *z, int K, double *nu, double *x) {
+static int nu_of(const ora_ctx *c, const int32_t *z, const int32_t *ez, int K, double *nu, double *x) {
   const ora_params *p = c->p;
   double s = p->sigma_eps * p->sigma_eps;
-  double rho = s / (p->sigma_q * p->sigma_q);
-  double m = p->mu_q;
   if (K == 0) { *nu = 0.0; return 0; }
+  /* per PE: sum log rho_k and sum rho_k mu_k^2 (App. A; for MCP-PMTs every PE has its
+   * component's mean and variance, App. A for MCP-PMTs) */
+  double slr = 0.0, srm = 0.0;
   double *G = (double *)malloc(sizeof(double) * K * K);
   double *L = (double *)calloc((size_t)K * K, sizeof(double));
   double *b = (double *)malloc(sizeof(double) * K);
@@ -324,8 +354,12 @@ static int nu_of(const ora_ctx *c, const int32_t *z, int K, double *nu, double *
       G[i * K + k] = o;
       G[k * K + i] = o;
     }
+    double rho, m;
+    pe_law(p, ez, i, &rho, &m);
     G[i * K + i] += rho;
     b[i] = matched(c, z[i]) + rho * m;
+    slr += log(rho);
+    srm += rho * m * m;
   }
   /* Cholesky G = L L^T */
   int fail = 0;
@@ -349,7 +383,7 @@ static int nu_of(const ora_ctx *c, const int32_t *z, int K, double *nu, double *
       uu += u[i] * u[i];
       logdet += 2.0 * log(L[i * K + i]);
     }
-    *nu = -0.5 * (-(double)K * log(rho) + logdet + (rho * m * m * K - uu) / s);
+    *nu = -0.5 * (-slr + logdet + (srm - uu) / s);
     if (x) {
       for (int i = K - 1; i >= 0; --i) {
         double v = u[i];
@@ -362,14 +396,16 @@ static int nu_of(const ora_ctx *c, const int32_t *z, int K, double *nu, double *
   return fail ? -1 : 0;
 }
 
-/* full log p(w|z), for the tests that pin nu against the dense normal law */
-double ora_log_likelihood(const ora_params *p, const float *w, int32_t Lw, const int32_t *z, int32_t K, double *x_out) {
+/* full log p(w|z), for the tests that pin nu against the dense normal law; ez (NULL
+ * without a mixture) holds the PEs' components */
+double ora_log_likelihood(const ora_params *p, const float *w, int32_t Lw, const int32_t *z, const int32_t *ez,
+                          int32_t K, double *x_out) {
   ora_table t;
   table_init(&t, p);
   ora_ctx c;
   ctx_init(&c, p, &t, w, Lw);
   double nu = 0.0;
-  int rc = nu_of(&c, z, K, &nu, x_out);
+  int rc = nu_of(&c, z, ez, K, &nu, x_out);
   double s = p->sigma_eps * p->sigma_eps, ww = 0.0;
   for (int32_t n = 0; n < Lw; ++n) ww += (double)w[n] * w[n];
   table_free(&t);
@@ -387,10 +423,8 @@ double ora_log_likelihood(const ora_params *p, const float *w, int32_t Lw, const
 /* covariance L^-T L^-1 = G^-1.  Returns -1 if G is not positive        */
 /* definite.                                                            */
 /* ------------------------------------------------------------------ */
-static int charge_draw(const ora_ctx *c, const int32_t *z, int K, const double *xi, double *q) {
+static int charge_draw(const ora_ctx *c, const int32_t *z, const int32_t *ez, int K, const double *xi, double *q) {
   const ora_params *p = c->p;
-  double s = p->sigma_eps * p->sigma_eps;
-  double rho = s / (p->sigma_q * p->sigma_q);
   if (K == 0) return 0;
   double *G = (double *)malloc(sizeof(double) * K * K);
   double *L = (double *)calloc((size_t)K * K, sizeof(double));
@@ -404,8 +438,10 @@ static int charge_draw(const ora_ctx *c, const int32_t *z, int K, const double *
       G[i * K + k] = o;
       G[k * K + i] = o;
     }
+    double rho, m;
+    pe_law(p, ez, i, &rho, &m);
     G[i * K + i] += rho;
-    b[i] = matched(c, z[i]) + rho * p->mu_q;
+    b[i] = matched(c, z[i]) + rho * m;
   }
   int fail = 0;
   for (int j = 0; j < K && !fail; ++j) {
@@ -466,7 +502,7 @@ int ora_charge_draw(const ora_params *p, const float *w, int32_t Lw, const int32
   table_init(&t, p);
   ora_ctx c;
   ctx_init(&c, p, &t, w, Lw);
-  int rc = charge_draw(&c, z, K, xi, q);
+  int rc = charge_draw(&c, z, NULL, K, xi, q);
   table_free(&t);
   return rc;
 }
@@ -503,9 +539,13 @@ typedef struct {
   double nu_new;
 } proposal_eval;
 
+/* The MCP form (Sec. 2.4, eq. mcp): a born PE's component e is proposed from G(e) and the
+ * update moves both time and component (e_new); G(e) enters both the target (eq.
+ * mcp-pzmu) and the proposal, and cancels from every acceptance, which keeps the form above
+ * with delta-nu of the per-PE charge law.  ez / ebuf / e_new are unused without a mixture. */
 static proposal_eval eval_proposal(const ora_ctx *c, double lambda0, int32_t glo, int32_t ghi, double t0,
-                                   const int32_t *z, int N, double nu_cur, int move, int j, int32_t gnew,
-                                   int32_t *zbuf, double *xbuf) {
+                                   const int32_t *z, const int32_t *ez, int N, double nu_cur, int move, int j,
+                                   int32_t gnew, int32_t e_new, int32_t *zbuf, int32_t *ebuf, double *xbuf) {
   const ora_params *p = c->p;
   double dt = 1.0 / p->sub;
   proposal_eval e;
@@ -518,8 +558,12 @@ static proposal_eval eval_proposal(const ora_ctx *c, double lambda0, int32_t glo
     if (!(LamT > 0.0) || gnew < glo || gnew > ghi) return e;
     memcpy(zbuf, z, sizeof(int32_t) * N);
     zbuf[N] = gnew;
+    if (ez) {
+      memcpy(ebuf, ez, sizeof(int32_t) * N);
+      ebuf[N] = e_new;
+    }
     double nu;
-    if (nu_of(c, zbuf, N + 1, &nu, xbuf)) return e;
+    if (nu_of(c, zbuf, ez ? ebuf : NULL, N + 1, &nu, xbuf)) return e;
     e.valid = 1;
     e.nu_new = nu;
     e.dnu = nu - nu_cur;
@@ -527,8 +571,12 @@ static proposal_eval eval_proposal(const ora_ctx *c, double lambda0, int32_t glo
   } else if (move == MOVE_DEATH) {
     memcpy(zbuf, z, sizeof(int32_t) * N);
     zbuf[j] = zbuf[N - 1];
+    if (ez) {
+      memcpy(ebuf, ez, sizeof(int32_t) * N);
+      ebuf[j] = ebuf[N - 1];
+    }
     double nu;
-    if (nu_of(c, zbuf, N - 1, &nu, xbuf)) return e;
+    if (nu_of(c, zbuf, ez ? ebuf : NULL, N - 1, &nu, xbuf)) return e;
     e.valid = 1;
     e.nu_new = nu;
     e.dnu = nu - nu_cur;
@@ -540,8 +588,12 @@ static proposal_eval eval_proposal(const ora_ctx *c, double lambda0, int32_t glo
     if (lpn == -INFINITY) return e;
     memcpy(zbuf, z, sizeof(int32_t) * N);
     zbuf[j] = gnew;
+    if (ez) {
+      memcpy(ebuf, ez, sizeof(int32_t) * N);
+      ebuf[j] = e_new;
+    }
     double nu;
-    if (nu_of(c, zbuf, N, &nu, xbuf)) return e;
+    if (nu_of(c, zbuf, ez ? ebuf : NULL, N, &nu, xbuf)) return e;
     e.valid = 1;
     e.nu_new = nu;
     e.dnu = nu - nu_cur;
@@ -559,10 +611,10 @@ double ora_log_alpha(const ora_params *p, const float *w, int32_t Lw, double lam
   ora_ctx c;
   ctx_init(&c, p, &t, w, Lw);
   double nu_cur = 0.0;
-  nu_of(&c, z, N, &nu_cur, NULL);
+  nu_of(&c, z, NULL, N, &nu_cur, NULL);
   int32_t *zb = (int32_t *)malloc(sizeof(int32_t) * (N + 1));
   double *xb = (double *)malloc(sizeof(double) * (N + 1));
-  proposal_eval e = eval_proposal(&c, lambda0, glo, ghi, t0, z, N, nu_cur, move, j, gnew, zb, xb);
+  proposal_eval e = eval_proposal(&c, lambda0, glo, ghi, t0, z, NULL, N, nu_cur, move, j, gnew, 0, zb, NULL, xb);
   free(zb); free(xb);
   table_free(&t);
   if (dnu_out) *dnu_out = e.dnu;
@@ -602,7 +654,8 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
                           int32_t ghi, double t0_init, uint64_t uid, uint64_t seed, int32_t n_steps, int32_t burn_in,
                           int32_t kz, int32_t *N_out, double *t0_out, int32_t *z_out, double *x_out, double *acc,
                           int32_t *nhist, int32_t *counts, uint32_t *status, ora_logrec *logrec, double *trace,
-                          int32_t thin, double *qdraw, int32_t *zdraw, int32_t *occ, const int32_t *z0, int32_t n0) {
+                          int32_t thin, double *qdraw, int32_t *zdraw, int32_t *occ, const int32_t *z0, int32_t n0,
+                          int32_t *e_out) {
   ora_ctx c;
   ctx_init(&c, p, tab, w, Lw);
   double dt = 1.0 / p->sub;
@@ -616,6 +669,10 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
   double *xb = (double *)calloc((size_t)kmax + 2, sizeof(double));
   double *xi = (double *)calloc((size_t)kmax + 1, sizeof(double));
   double *qb = (double *)calloc((size_t)kmax + 1, sizeof(double));
+  /* MCP form: the component of every PE, in list order */
+  const int mcp = p->n_mix > 0;
+  int32_t *ez = mcp ? (int32_t *)calloc((size_t)kmax + 1, sizeof(int32_t)) : NULL;
+  int32_t *eb = mcp ? (int32_t *)calloc((size_t)kmax + 2, sizeof(int32_t)) : NULL;
   int N = 0;
   double t0 = t0_init, nu_cur = 0.0;
   memset(acc, 0, sizeof(double) * 12);
@@ -631,7 +688,7 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
   if (n_steps > 0 && n0 > 0) {
     memcpy(z, z0, sizeof(int32_t) * n0);
     N = n0;
-    if (nu_of(&c, z, N, &nu_cur, x)) st |= ORA_ST_FACTOR;
+    if (nu_of(&c, z, ez, N, &nu_cur, x)) st |= ORA_ST_FACTOR;
   }
   for (int32_t step = 0; step < n_steps; ++step) {
     uint32_t r[8];
@@ -658,6 +715,8 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
     int move = (N == 0 || um < p->J) ? MOVE_BIRTH : (um < 2.0 * p->J ? MOVE_DEATH : MOVE_UPDATE);
     int j = -1;
     int32_t gnew = -1;
+    /* MCP form: the component of a born or updated PE, from word r7 */
+    const int32_t enew = mcp ? mix_draw(p, u01_open(r[7])) : 0;
     proposal_eval e;
     e.valid = 0;
     e.dnu = 0.0;
@@ -669,18 +728,18 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
         st |= ORA_ST_KMAX;
       } else if (ora_phi_sum(p, t0, glo, ghi) > 0.0) {
         gnew = ora_birth_draw(p, t0, glo, ghi, u53_open(r[4], r[5]));
-        e = eval_proposal(&c, lambda0, glo, ghi, t0, z, N, nu_cur, move, -1, gnew, zb, xb);
+        e = eval_proposal(&c, lambda0, glo, ghi, t0, z, ez, N, nu_cur, move, -1, gnew, enew, zb, eb, xb);
       }
     } else {
       j = (int)(((uint64_t)r[4] * (uint64_t)N) >> 32);
       if (move == MOVE_DEATH) {
         counts[4]++;
-        e = eval_proposal(&c, lambda0, glo, ghi, t0, z, N, nu_cur, move, j, -1, zb, xb);
+        e = eval_proposal(&c, lambda0, glo, ghi, t0, z, ez, N, nu_cur, move, j, -1, 0, zb, eb, xb);
       } else {
         counts[6]++;
         int32_t shift = (int32_t)rint(xi_sh * p->shift_sd / dt);
         gnew = z[j] + shift;
-        e = eval_proposal(&c, lambda0, glo, ghi, t0, z, N, nu_cur, move, j, gnew, zb, xb);
+        e = eval_proposal(&c, lambda0, glo, ghi, t0, z, ez, N, nu_cur, move, j, gnew, enew, zb, eb, xb);
       }
     }
     int accepted = 0;
@@ -689,12 +748,15 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
       counts[2 * move + 1]++;
       if (move == MOVE_BIRTH) {
         z[N] = gnew;
+        if (mcp) ez[N] = enew;
         N++;
       } else if (move == MOVE_DEATH) {
         z[j] = z[N - 1];
+        if (mcp) ez[j] = ez[N - 1];
         N--;
       } else {
         z[j] = gnew;
+        if (mcp) ez[j] = enew;
       }
       nu_cur = e.nu_new;
       memcpy(x, xb, sizeof(double) * N);
@@ -744,7 +806,7 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
         double *qr = qdraw + (size_t)kz * (i / thin);
         int32_t *zr = zdraw + (size_t)kz * (i / thin);
         charge_normals(uid, seed, step, N, xi);
-        int rc = charge_draw(&c, z, N, xi, qb);
+        int rc = charge_draw(&c, z, ez, N, xi, qb);
         if (rc) st |= ORA_ST_FACTOR;
         for (int k = 0; k < kz; ++k) {
           zr[k] = k < N ? z[k] : -1;
@@ -760,7 +822,9 @@ static void run_one_chain(const ora_params *p, const ora_table *tab, const float
     x_out[k] = k < N ? x[k] : 0.0;
   }
   *status = st;
-  free(z); free(zb); free(x); free(xb); free(xi); free(qb);
+  if (e_out)
+    for (int k = 0; k < kz; ++k) e_out[k] = (mcp && k < N) ? ez[k] : -1;
+  free(z); free(zb); free(x); free(xb); free(xi); free(qb); free(ez); free(eb);
 }
 
 /* Run n_chains chains for every waveform.  Chain c of waveform i writes
@@ -777,7 +841,7 @@ int ora_run(const ora_params *p, int64_t n_wave, const float *wave, const int64_
             int32_t n_chains, int32_t n_steps, int32_t burn_in, uint64_t seed, int32_t kz, int32_t *N_out,
             double *t0_out, int32_t *z_out, double *x_out, double *acc, int32_t *nhist, int32_t *counts,
             uint32_t *status, ora_logrec *logrec, double *trace, int32_t thin, double *qdraw, int32_t *zdraw,
-            int32_t *occ, const int32_t *z_init, const int64_t *z_init_off, int32_t n_threads) {
+            int32_t *occ, const int32_t *z_init, const int64_t *z_init_off, int32_t *e_out, int32_t n_threads) {
   int64_t total = n_wave * n_chains;
   int64_t n_rec = (thin > 0 && n_steps > burn_in) ? (n_steps - burn_in + thin - 1) / thin : 0;
   ora_table tab;
@@ -802,7 +866,7 @@ int ora_run(const ora_params *p, int64_t n_wave, const float *wave, const int64_
                   zdraw ? zdraw + ic * kz * n_rec : NULL,
                   occ ? occ + n_chains * p->sub * offsets[i] + (int64_t)ch * p->sub * Lw : NULL,
                   z_init_off ? z_init + z_init_off[ic] : NULL,
-                  z_init_off ? (int32_t)(z_init_off[ic + 1] - z_init_off[ic]) : 0);
+                  z_init_off ? (int32_t)(z_init_off[ic + 1] - z_init_off[ic]) : 0, e_out ? e_out + ic * kz : NULL);
   }
   table_free(&tab);
   return 0;
@@ -836,7 +900,7 @@ int64_t ora_replay(const ora_params *p, const float *w, int32_t Lw, double lambd
     if (!(lr->flags & 1)) continue;
     if (lr->move == MOVE_BIRTH && N >= kmax) { bad++; continue; }
     if ((lr->move == MOVE_DEATH || lr->move == MOVE_UPDATE) && (lr->j < 0 || lr->j >= N)) { bad++; continue; }
-    proposal_eval e = eval_proposal(&c, lambda0, glo, ghi, t0, z, N, nu_cur, lr->move, lr->j, lr->g, zb, xb);
+    proposal_eval e = eval_proposal(&c, lambda0, glo, ghi, t0, z, NULL, N, nu_cur, lr->move, lr->j, lr->g, 0, zb, NULL, xb);
     if (!e.valid) { bad++; continue; }
     dnu_ref[step] = e.dnu;
     la_ref[step] = e.log_alpha;
