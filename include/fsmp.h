@@ -111,6 +111,19 @@ typedef struct {
   int32_t precision, refresh_M;
   uint32_t record_flags;
   uint64_t seed;
+  /* MCP-PMT charge model (Sec. 2.1, eq. mcp-multi-norm; Sec. 2.4, eq. mcp; App. A for
+   * MCP-PMTs): n_mix = 0 uses N(mu_q, sigma_q^2); 1..8 a Gaussian mixture in which every PE
+   * carries a component e with probability mix_weight[e] (positive, summing to 1 within
+   * 1e-9), charge mean mix_mu[e] and standard deviation mix_sigma[e] > 0.  A born PE's
+   * component, and an updated PE's new one, are drawn from the mixture weights (Philox
+   * word 7 of the step, inverse CDF with the weights accumulated in index order); the
+   * weights cancel from every acceptance, which keeps the dynode form with delta-nu of the
+   * per-PE charge law (G = A^T A + diag(rho_e), b = A^T w + rho_e mu_e, rho_e =
+   * sigma_eps^2 / sigma_e^2).  The mixture form runs the FP64 lane-group kernels with G^-1 in
+   * device memory at every capacity; FP32 storage, replay and start lists are not offered
+   * with it (FSMP_ENOTSUP). */
+  int32_t n_mix;
+  double mix_weight[8], mix_mu[8], mix_sigma[8];
 } fsmp_config;
 
 /* One batch of waveforms (ragged).  wave: device, float32, the concatenated samples;
@@ -214,6 +227,7 @@ typedef struct {
   int32_t *zdraw;
   int32_t *rec_steps;
   int32_t *occ;
+  int32_t *comp;   /* NULL, or [chain][kz] with a mixture: the final PEs' components, -1 beyond N */
 } fsmp_samples;
 
 /* Posterior summaries per waveform (device buffers, caller-allocated): for (N, Q, t0)

@@ -207,19 +207,23 @@ bool finite(double v) { return std::isfinite(v); }
 
 // whether a kernel design exists for a PE capacity under this model (LDS footprint) and
 // precision (the FP32 form has no lane groups with G^-1 in LDS and no capacity 48)
+// (the mixture charge law runs only in the lane groups with G^-1 in device memory)
 bool design_available(const fsmp_ctx *c, int kcap, int design) {
   const bool fp32 = c->cfg.precision == FSMP_FP32_REFRESH;
+  const bool mcp = c->cfg.n_mix > 0;
   switch (design) {
-    case FSMP_DESIGN_GROUP: return !fp32 && chain_kcap_supported(kcap, c->tab.M, c->cfg.grid_sub);
-    case FSMP_DESIGN_LANE: return kcap != 48;
-    case FSMP_DESIGN_GROUP_DEVMEM: return chain_dm_supported(kcap, c->tab.M, c->cfg.grid_sub, fp32);
+    case FSMP_DESIGN_GROUP: return !fp32 && !mcp && chain_kcap_supported(kcap, c->tab.M, c->cfg.grid_sub);
+    case FSMP_DESIGN_LANE: return kcap != 48 && !mcp;
+    case FSMP_DESIGN_GROUP_DEVMEM: return chain_dm_supported(kcap, c->tab.M, c->cfg.grid_sub, fp32, mcp);
     default: return false;
   }
 }
 
 // the design a bucket runs in: the context's choice where it exists, else one lane per chain
+// (lane groups with G^-1 in device memory under the mixture law)
 int effective_design(const fsmp_ctx *c, int kcap, int design) {
-  return design_available(c, kcap, design) ? design : FSMP_DESIGN_LANE;
+  if (design_available(c, kcap, design)) return design;
+  return c->cfg.n_mix > 0 ? FSMP_DESIGN_GROUP_DEVMEM : FSMP_DESIGN_LANE;
 }
 
 fsmp_status validate_model(const fsmp_ser *ser, const fsmp_intensity *phi, const fsmp_config *cfg, std::string &m) {
@@ -254,6 +258,18 @@ fsmp_status validate_model(const fsmp_ser *ser, const fsmp_intensity *phi, const
     return m = "config: unknown record flag", FSMP_EINVAL;
   if (cfg->precision != FSMP_FP64 && cfg->precision != FSMP_FP32_REFRESH) return m = "config: unknown precision", FSMP_EINVAL;
   if (cfg->precision == FSMP_FP32_REFRESH && cfg->refresh_M < 0) return m = "config: refresh_M must be >= 0", FSMP_EINVAL;
+  if (cfg->n_mix < 0 || cfg->n_mix > 8) return m = "config: n_mix must be 0..8", FSMP_EINVAL;
+  if (cfg->n_mix > 0) {
+    double wsum = 0.0;
+    for (int e = 0; e < cfg->n_mix; ++e) {
+      if (!(cfg->mix_weight[e] > 0) || !finite(cfg->mix_weight[e]) || !finite(cfg->mix_mu[e]) ||
+          !(cfg->mix_sigma[e] > 0) || !finite(cfg->mix_sigma[e]))
+        return m = "config: mixture components need weight > 0, finite mu and sigma > 0", FSMP_EINVAL;
+      wsum += cfg->mix_weight[e];
+    }
+    if (std::fabs(wsum - 1.0) > 1e-9) return m = "config: mixture weights must sum to 1", FSMP_EINVAL;
+    if (cfg->precision != FSMP_FP64) return m = "config: the mixture charge law runs in FP64 only", FSMP_ENOTSUP;
+  }
   return FSMP_OK;
 }
 
@@ -267,6 +283,23 @@ void fill_model(fsmp_ctx *c) {
   md.m = cf.mu_q;
   md.rhom = md.rho * cf.mu_q;
   md.rhom2 = md.rho * cf.mu_q * cf.mu_q;
+  // mixture: weights accumulated in index order (the component draw compares a uniform with
+  // these partial sums), and the per-component ridge terms
+  md.n_mix = cf.n_mix;
+  double cdf = 0.0;
+  for (int e = 0; e < 8; ++e) {
+    if (e < cf.n_mix) {
+      cdf += cf.mix_weight[e];
+      const double rho = md.s / (cf.mix_sigma[e] * cf.mix_sigma[e]);
+      md.mix_cdf[e] = cdf;
+      md.mix_rho[e] = rho;
+      md.mix_lrho[e] = std::log(rho);
+      md.mix_rhom[e] = rho * cf.mix_mu[e];
+      md.mix_rhom2[e] = rho * cf.mix_mu[e] * cf.mix_mu[e];
+    } else {
+      md.mix_cdf[e] = md.mix_rho[e] = md.mix_lrho[e] = md.mix_rhom[e] = md.mix_rhom2[e] = 0.0;
+    }
+  }
   md.sub = c->tab.sub;
   md.LV = c->tab.LV;
   md.M = c->tab.M;
@@ -525,6 +558,9 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   if (!b || !o) return fail(c, FSMP_EINVAL, "null batch or output");
   const fsmp_config &cf = c->cfg;
   if (force && cf.precision != FSMP_FP64) return fail(c, FSMP_ENOTSUP, "replay runs the FP64 form only");
+  if (force && cf.n_mix > 0) return fail(c, FSMP_ENOTSUP, "replay runs the single-normal charge law only");
+  if (b && b->z_init_offsets && cf.n_mix > 0)
+    return fail(c, FSMP_ENOTSUP, "start lists are not offered with the mixture charge law");
   const int64_t n = b->n_wave;
   if (n < 0) return fail(c, FSMP_EINVAL, "n_wave < 0");
   if (n > 0 && (!b->wave || !b->offsets || !b->lambda)) return fail(c, FSMP_EINVAL, "wave, offsets and lambda are required");
@@ -818,6 +854,7 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   ca.wflags = c->wflags.p;
   ca.work = o->work;
   ca.occ = o->occ;
+  ca.comp = o->comp;
   ca.zinit = (b->z_init_offsets && n > 0) ? c->zinit.p : nullptr;
   ca.zinit_off = (b->z_init_offsets && n > 0) ? c->zinit_off.p : nullptr;
   ca.refresh_M = cf.refresh_M;

@@ -27,6 +27,10 @@ struct ModelDev {
   // [k][2]: 1 - e^{-k dt / tau2}, 1 - e^{-k dt / tau12} for k = 0 .. ptab_n - 1 (device)
   const double *ptab;
   int64_t ptab_n;
+  // MCP-PMT mixture (n_mix > 0): cumulative weights (accumulated in index order) and, per
+  // component, rho_e = s / sigma_e^2, log rho_e, rho_e mu_e, rho_e mu_e^2
+  int32_t n_mix, pad2;
+  double mix_cdf[8], mix_rho[8], mix_lrho[8], mix_rhom[8], mix_rhom2[8];
 };
 
 struct ChainArgs {
@@ -91,6 +95,7 @@ struct ChainArgs {
   // zinit_off[c + 1]) instead of the empty list
   const int32_t *zinit;
   const int64_t *zinit_off;
+  int32_t *comp;  // mixture form: final components [chain][kz], or null
 };
 
 struct PrologueArgs {
@@ -172,7 +177,7 @@ bool chain_kcap_supported(int kcap, int M, int sub);  // lane-group (LDS) instan
 // group_dm_ws_doubles(kcap, n_list, fp32)
 hipError_t launch_chain_dm(int kcap, bool fp32, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks);
 size_t group_dm_ws_doubles(int kcap, int64_t n_list, bool fp32);
-bool chain_dm_supported(int kcap, int M, int sub, bool fp32);
+bool chain_dm_supported(int kcap, int M, int sub, bool fp32, bool mcp = false);
 int chain_kcap_for(int kmax);
 
 }  // namespace fsmp

@@ -287,12 +287,14 @@ __global__ void __launch_bounds__(256) prologue_kernel(PrologueArgs a) {
 // the int grid indices.  The accumulators live in LDS,
 // updated by the group's first lane, to keep registers free; the N histogram is kept in
 // the output row by run lengths.
-template <int KCAP, bool HG, bool F32 = false>
+template <int KCAP, bool HG, bool F32 = false, bool MCP = false>
 struct ChainLayout {
   static constexpr int LD = KCAP;
   static constexpr int kAcc = 25;
-  // the FP32 form also keeps b (matched filter + rho mu_q per PE) for its FP64 refresh
-  static constexpr int kDoubles = (HG ? 0 : KCAP * KCAP) + (F32 ? 4 : 3) * KCAP + kAcc + (KCAP + 1) / 2;
+  // the FP32 form also keeps b (matched filter + rho mu_q per PE) for its FP64 refresh; the
+  // mixture form the PEs' components after their grid indices
+  static constexpr int kDoubles =
+      (HG ? 0 : KCAP * KCAP) + (F32 ? 4 : 3) * KCAP + kAcc + (KCAP + 1) / 2 + (MCP ? (KCAP + 1) / 2 : 0);
 };
 
 // Column i of H owned by one lane: element (k, i) at H[(k * LD + i) * HS] (HS = 1 in LDS;
@@ -405,12 +407,14 @@ __device__ bool grp_refresh(const ModelDev &md, const double *vt, const double *
 // otherwise H in LDS.  FORCE (replay): every step follows the recorded proposal of a.force
 // (t0 after the half-step, move, index, grid point, accept bit) instead of the chain's
 // own draws, and writes the delta-nu and log-acceptance it computes to a.rdnu / a.rla.
-template <int KCAP, int LPC, int WPB, bool HG, bool FORCE, bool F32>
+// MCP: the Gaussian-mixture charge law, every PE with its component.
+template <int KCAP, int LPC, int WPB, bool HG, bool FORCE, bool F32, bool MCP>
 __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu(2))) chain_kernel(ChainArgs a) {
   static_assert(!F32 || (HG && !FORCE), "the FP32 form keeps H in device memory and does not replay");
+  static_assert(!MCP || (HG && !FORCE && !F32), "the mixture form runs FP64 with H in device memory");
   using HT = typename std::conditional<F32, float, double>::type;
   constexpr int CPW = kWave / LPC;
-  using CL = ChainLayout<KCAP, HG, F32>;
+  using CL = ChainLayout<KCAP, HG, F32, MCP>;
   constexpr int LD = CL::LD;
   constexpr int HS = HG ? CPW : 1;
   extern __shared__ double smem[];
@@ -444,6 +448,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
   int *cnt = (int *)(acc + 20);
   int *run = cnt + 8;  // N of the current run among the recorded steps (-1: none yet), its first step
   int *zg = (int *)(acc + CL::kAcc);
+  int *ek = zg + 2 * ((KCAP + 1) / 2);  // mixture form: the PEs' components
 
   const int64_t c = a.chains[slot];
   const int64_t w = c / a.n_chains;
@@ -598,6 +603,21 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
     bool valid = false, need_mv = false;
     double dnu = 0.0, la = -INFINITY, lpn = 0.0, lpo = 0.0;
     double delta2 = 1.0, up = 0.0, om = 1.0, xj = 0.0, ej = 0.0, beta = 0.0;
+    // mixture form: the component of a born or updated PE from word r7 (inverse CDF of the
+    // weights); rho, its log, rho mu, rho mu^2 of the new and of the removed / moved PE
+    int enew = 0;
+    double rn = md.rho, lrn = md.log_rho, rmn = md.rhom, rm2n = md.rhom2;
+    double lro = md.log_rho, rm2o = md.rhom2;
+    if constexpr (MCP) {
+      const double ue = u01(r[7]);
+      enew = md.n_mix - 1;
+      for (int q = md.n_mix - 2; q >= 0; --q)
+        if (ue < md.mix_cdf[q]) enew = q;
+      rn = md.mix_rho[enew];
+      lrn = md.mix_lrho[enew];
+      rmn = md.mix_rhom[enew];
+      rm2n = md.mix_rhom2[enew];
+    }
     if (move == 1) {
       if (lane == 0) cnt[2]++;
       if (N >= kmax) {
@@ -614,8 +634,12 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         if (lane == 0) cnt[4]++;
         om = H[(j * LD + j) * HS];
         xj = xv[j];
+        if constexpr (MCP) {
+          lro = md.mix_lrho[ek[j]];
+          rm2o = md.mix_rhom2[ek[j]];
+        }
         if (om > 0.0) {
-          dnu = 0.5 * (-md.log_rho - log(om) + (md.rhom2 - xj * xj / om) * md.inv_s);
+          dnu = 0.5 * (-lro - log(om) + (rm2o - xj * xj / om) * md.inv_s);
           la = dnu - logLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
           valid = true;
         } else {
@@ -629,7 +653,11 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
           lpn = log_phi(md, (double)gnew * md.dt - t0);
           if (lpn > -INFINITY) {
             lpo = log_phi(md, (double)zg[j] * md.dt - t0);
-            if (sh == 0) {
+            if constexpr (MCP) {
+              lro = md.mix_lrho[ek[j]];
+              rm2o = md.mix_rhom2[ek[j]];
+            }
+            if (sh == 0 && (!MCP || enew == ek[j])) {
               valid = true;
               dnu = 0.0;
               la = lpn - lpo;
@@ -647,8 +675,8 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
       valid = false;
       const int jz = move == 3 ? j : -1;
       for (int i = lane; i < N; i += LPC) s1[i] = (i == jz) ? 0.0 : overlap(md, vt, ov, gnew, zg[i], Lw);
-      const double d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
-      beta = mf[gnew - glo] + md.rhom;
+      const double d = overlap(md, vt, ov, gnew, gnew, Lw) + rn;
+      beta = mf[gnew - glo] + rmn;
       WAVE_SYNC();
       double q = 0.0, p = 0.0;
       for (int i = lane; i < N; i += LPC) {
@@ -663,7 +691,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         delta2 = d - q;
         if (delta2 > 0.0) {
           up = beta - p;
-          dnu = -0.5 * (-md.log_rho + log(delta2) + (md.rhom2 - up * up / delta2) * md.inv_s);
+          dnu = -0.5 * (-lrn + log(delta2) + (rm2n - up * up / delta2) * md.inv_s);
           la = dnu + logLam - lgn[N + 1] + (N == 0 ? md.logJ : 0.0);
           valid = true;
         } else {
@@ -678,6 +706,8 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         up = beta - (p - ej * xj / om);
         if (delta2 > 0.0 && om > 0.0) {
           dnu = 0.5 * (-log(om) - log(delta2) + (up * up / delta2 - xj * xj / om) * md.inv_s);
+          // mixture form: the removed and the added PE carry their own rho and rho mu^2
+          if constexpr (MCP) dnu += 0.5 * (lrn - lro + (rm2o - rm2n) * md.inv_s);
           la = dnu + lpn - lpo;
           valid = true;
         } else {
@@ -720,7 +750,8 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         if (move == 1 || move == 2) acc[16] += (double)N * N;
         else if (sh != 0) acc[17] += (double)N * N;
       }
-      const bool shift = move == 3 && sh != 0;  // an accepted zero shift changes nothing
+      // an accepted zero shift changes nothing (unless it changes the PE's component)
+      const bool shift = move == 3 && (sh != 0 || (MCP && enew != ek[j]));
       if (move != 3 || shift) {
         const double inv_d2 = move == 2 ? 0.0 : 1.0 / delta2;
         const double inv_om = move == 1 ? 0.0 : 1.0 / om;
@@ -756,6 +787,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
           if (lane == 0) {
             H[(N * LD + N) * HS] = inv_d2;
             zg[N] = gnew;
+            if constexpr (MCP) ek[N] = enew;
             xv[N] = xn;
             if (F32) bv[N] = beta;
           }
@@ -778,6 +810,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
             }
             if (lane == 0) {
               zg[j] = zg[last];
+              if constexpr (MCP) ek[j] = ek[last];
               xv[j] = xv[last];
               if (F32) bv[j] = bv[last];
             }
@@ -796,6 +829,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
           }
           if (lane == 0) {
             zg[j] = gnew;
+            if constexpr (MCP) ek[j] = enew;
             if (F32) bv[j] = beta;
           }
           if (biexp) S_cur += rise_term(md, gnew, t0) - rise_term(md, gj, t0);
@@ -919,6 +953,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
   for (int k = lane; k < kz; k += LPC) {
     a.z[c * kz + k] = k < N ? zg[k] : -1;
     a.charge[c * kz + k] = k < N ? xv[k] : 0.0;
+    if (MCP && a.comp) a.comp[c * kz + k] = k < N ? ek[k] : -1;
   }
   if (lane == 0 && run[0] >= 0) atomicAdd(a.nhist + c * (a.kz + 1) + run[0], n_steps - run[1]);
   if (lane == 0) {
@@ -1787,25 +1822,25 @@ __global__ void __launch_bounds__(256) posterior_extra_kernel(PosteriorArgs a) {
   a.lambda_hat[w * 2 + 1] = a.mean[w * 3 + 1] / a.mu_q;  // lambda-hat_Q = E[Q] / mu_q
 }
 
-template <int KCAP, int LPC, int WPB, bool HG, bool FORCE = false, bool F32 = false>
+template <int KCAP, int LPC, int WPB, bool HG, bool FORCE = false, bool F32 = false, bool MCP = false>
 hipError_t launch_chain_t(const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
   constexpr int CPB = WPB * (kWave / LPC);
   const int64_t nb = (a.n_list + CPB - 1) / CPB;
   const size_t lds = sizeof(double) * ((size_t)a.md.M * (1 + a.md.sub) + (KCAP + 2) +
-                                       (size_t)CPB * ChainLayout<KCAP, HG, F32>::kDoubles);
+                                       (size_t)CPB * ChainLayout<KCAP, HG, F32, MCP>::kDoubles);
   *lanes = LPC;
   *blocks = nb;
   if (nb == 0) return hipSuccess;
   if (HG && a.dws == nullptr) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
     // lift the default dynamic-LDS limit; gfx950 has 160 KB per workgroup
-    (void)hipFuncSetAttribute((const void *)chain_kernel<KCAP, LPC, WPB, HG, FORCE, F32>,
+    (void)hipFuncSetAttribute((const void *)chain_kernel<KCAP, LPC, WPB, HG, FORCE, F32, MCP>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipGetLastError();
   }
   if (FORCE && (a.force == nullptr || a.rdnu == nullptr || a.rla == nullptr)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((chain_kernel<KCAP, LPC, WPB, HG, FORCE, F32>), dim3((unsigned)nb), dim3(kWave * WPB), lds, st,
-                     a);
+  hipLaunchKernelGGL((chain_kernel<KCAP, LPC, WPB, HG, FORCE, F32, MCP>), dim3((unsigned)nb), dim3(kWave * WPB), lds,
+                     st, a);
   return hipGetLastError();
 }
 
@@ -2087,9 +2122,10 @@ static const GroupCfg kGroup[] = {{16, 16, 4}, {32, 32, 4}, {48, 64, 3}, {64, 64
 static const GroupCfg kGroupDM[] = {{16, 4, 4},  {32, 4, 8},   {48, 16, 4},  {64, 32, 4},
                                     {96, 16, 2}, {128, 32, 4}, {160, 32, 4}, {192, 32, 2}};
 
-static size_t chain_lds_bytes(const GroupCfg &g, int M, int sub, bool hg, bool f32 = false) {
+static size_t chain_lds_bytes(const GroupCfg &g, int M, int sub, bool hg, bool f32 = false, bool mcp = false) {
   const int cpb = g.wpb * (64 / g.lpc);
-  const size_t per = (hg ? 0 : (size_t)g.kcap * g.kcap) + (f32 ? 4 : 3) * (size_t)g.kcap + 25 + ((size_t)g.kcap + 1) / 2;
+  const size_t per = (hg ? 0 : (size_t)g.kcap * g.kcap) + (f32 ? 4 : 3) * (size_t)g.kcap + 25 +
+                     ((size_t)g.kcap + 1) / 2 * (mcp ? 2 : 1);
   return sizeof(double) * ((size_t)M * (1 + sub) + (size_t)g.kcap + 2 + (size_t)cpb * per);
 }
 
@@ -2099,10 +2135,14 @@ bool chain_kcap_supported(int kcap, int M, int sub) {
   return false;
 }
 
-bool chain_dm_supported(int kcap, int M, int sub, bool f32) {
+bool chain_dm_supported(int kcap, int M, int sub, bool f32, bool mcp) {
   if (f32 && kcap == 48) return false;  // the precision form runs capacity 48 at 64
-  for (const GroupCfg &g : kGroupDM)
-    if (g.kcap == kcap) return chain_lds_bytes(g, M, sub, true, f32) <= 160 * 1024;
+  if (f32 && mcp) return false;
+  for (GroupCfg g : kGroupDM)
+    if (g.kcap == kcap) {
+      if (mcp && kcap == 32) g.wpb = 4;  // the components' LDS: 64 chains per workgroup
+      return chain_lds_bytes(g, M, sub, true, f32, mcp) <= 160 * 1024;
+    }
   return false;
 }
 
@@ -2169,6 +2209,20 @@ hipError_t launch_chain(int kcap, const ChainArgs &a, hipStream_t st, int32_t *l
 
 // instances must match kGroupDM
 hipError_t launch_chain_dm(int kcap, bool fp32, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
+  if (a.md.n_mix > 0) {
+    if (a.force || fp32) return hipErrorInvalidValue;
+    switch (kcap) {
+      case 16: return launch_chain_t<16, 4, 4, true, false, false, true>(a, st, lanes, blocks);
+      case 32: return launch_chain_t<32, 4, 4, true, false, false, true>(a, st, lanes, blocks);
+      case 48: return launch_chain_t<48, 16, 4, true, false, false, true>(a, st, lanes, blocks);
+      case 64: return launch_chain_t<64, 32, 4, true, false, false, true>(a, st, lanes, blocks);
+      case 96: return launch_chain_t<96, 16, 2, true, false, false, true>(a, st, lanes, blocks);
+      case 128: return launch_chain_t<128, 32, 4, true, false, false, true>(a, st, lanes, blocks);
+      case 160: return launch_chain_t<160, 32, 4, true, false, false, true>(a, st, lanes, blocks);
+      case 192: return launch_chain_t<192, 32, 2, true, false, false, true>(a, st, lanes, blocks);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (a.force) {
     switch (kcap) {
       case 16: return launch_chain_t<16, 4, 4, true, true>(a, st, lanes, blocks);

@@ -44,7 +44,8 @@ class fsmp_config(ctypes.Structure):
                 ("shift_sd", ctypes.c_double), ("k_max", ctypes.c_int32), ("n_steps", ctypes.c_int32),
                 ("n_chains", ctypes.c_int32), ("burn_in", ctypes.c_int32), ("thin", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("refresh_M", ctypes.c_int32), ("record_flags", ctypes.c_uint32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("n_mix", ctypes.c_int32), ("mix_weight", ctypes.c_double * 8),
+                ("mix_mu", ctypes.c_double * 8), ("mix_sigma", ctypes.c_double * 8)]
 
 
 class fsmp_batch(ctypes.Structure):
@@ -60,7 +61,7 @@ class fsmp_samples(ctypes.Structure):
                 ("counts", ctypes.c_void_p), ("status", ctypes.c_void_p), ("log", ctypes.c_void_p),
                 ("trace", ctypes.c_void_p), ("kz", ctypes.c_int32), ("work", ctypes.c_void_p),
                 ("qdraw", ctypes.c_void_p), ("zdraw", ctypes.c_void_p), ("rec_steps", ctypes.c_void_p),
-                ("occ", ctypes.c_void_p)]
+                ("occ", ctypes.c_void_p), ("comp", ctypes.c_void_p)]
 
 
 class fsmp_posterior_out(ctypes.Structure):
@@ -198,7 +199,9 @@ class Sampler:
     def __init__(self, ser=(8.0, 1.5, 6.0), ser_amp=1.0, ser_support=0, phi_kind=FSMP_PHI_EXP, tau_rise=0.0,
                  tau_decay=20.0, t0_min=50.0, t0_max=100.0, sigma_eps=0.1, mu_q=1.0, sigma_q=0.3, grid_sub=4,
                  jump_J=0.25, t0_step_sd=1.0, shift_sd=1.0, k_max=32, n_steps=2000, n_chains=1, burn_in=None,
-                 thin=1, precision=FSMP_FP64, refresh_M=64, record_flags=0, seed=0, device=0):
+                 thin=1, precision=FSMP_FP64, refresh_M=64, record_flags=0, seed=0, device=0, mix=None):
+        """mix: None (charge law N(mu_q, sigma_q^2)) or (weights, means, sigmas) of the MCP-PMT
+        Gaussian mixture, up to 8 components."""
         self.lib = load()
         self.ser = fsmp_ser(ser[0], ser[1], ser[2], ser_amp, ser_support)
         self.phi = fsmp_intensity(phi_kind, tau_rise, tau_decay, t0_min, t0_max)
@@ -206,6 +209,13 @@ class Sampler:
             burn_in = n_steps // 2
         self.cfg = fsmp_config(sigma_eps, mu_q, sigma_q, grid_sub, jump_J, t0_step_sd, shift_sd, k_max, n_steps,
                                n_chains, burn_in, thin, precision, refresh_M, record_flags, seed)
+        if mix is not None:
+            g, mu, sg = (list(map(float, v)) for v in mix)
+            if not (len(g) == len(mu) == len(sg)) or len(g) > 8:
+                raise ValueError("mix needs equal-length weights, means and sigmas (at most 8)")
+            self.cfg.n_mix = len(g)
+            for i in range(len(g)):
+                self.cfg.mix_weight[i], self.cfg.mix_mu[i], self.cfg.mix_sigma[i] = g[i], mu[i], sg[i]
         self.device = device
         self.h = fsmp_create(self.ser, self.phi, self.cfg, device)
 
@@ -253,6 +263,7 @@ class Sampler:
             "log": None, "trace": None, "kz": kz,
             "work": torch.zeros((C, 4), dtype=torch.float64, device=dev) if work else None,
             "occ": torch.zeros(occ_len, dtype=torch.int32, device=dev) if occ_len > 0 else None,
+            "comp": torch.zeros((C, kz), dtype=torch.int32, device=dev) if self.cfg.n_mix > 0 else None,
         }
         if self.cfg.record_flags & FSMP_REC_LOG:
             out["log"] = torch.zeros((C, self.cfg.n_steps * LOGREC_DTYPE.itemsize), dtype=torch.uint8, device=dev)
@@ -317,7 +328,7 @@ class Sampler:
                             _dptr(out["acc"]), _dptr(out["nhist"]), _dptr(out["counts"]), _dptr(out["status"]),
                             _dptr(out["log"]), _dptr(out["trace"]), out["kz"], _dptr(out.get("work")),
                             _dptr(out.get("qdraw")), _dptr(out.get("zdraw")), _dptr(out.get("rec_steps")),
-                            _dptr(out.get("occ")))
+                            _dptr(out.get("occ")), _dptr(out.get("comp")))
 
     def lucy(self, wave, offsets, kmax=None, kz=None, n_iter=2000, threshold=0.1, margin=4, qhat=False,
              stream=None):
