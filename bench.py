@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--serve-rates", default="2000", help="comma-separated event rates (Hz)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--lucy-iter", type=int, default=2000, help="Lucy-Richardson iterations of the init stage (0: skip)")
+    ap.add_argument("--no-mcp", action="store_true", help="skip the MCP-PMT mixture-law leg")
     ap.add_argument("--pmc-run", action="store_true",
                     help="one untimed step after a plain device copy of known size (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -343,6 +344,30 @@ def main():
                              "flops_per_launch": lflops}}
         print(f"[bench] lucy {args.lucy_iter} iterations: {lms:.1f} ms", file=sys.stderr, flush=True)
 
+    # ---- the MCP-PMT charge law (the paper's five-Gaussian table) on the same batch: one
+    # timed step of sample + posterior after a warm-up, HIP events around the step on the stream
+    mcp = None
+    if not args.no_mcp:
+        mix = ([0.041, 0.516, 0.187, 0.195, 0.061], [0.92, 1.98, 3.01, 4.70, 6.79], [0.22, 0.48, 0.80, 1.30, 2.04])
+        msmp = fsmp.Sampler(ser=wl.ser, phi_kind=wl.phi_kind, tau_rise=wl.tau_rise, tau_decay=wl.tau_decay,
+                            t0_min=wl.t0_min, t0_max=wl.t0_max, sigma_eps=wl.sigma_eps, mu_q=wl.mu_q,
+                            sigma_q=wl.sigma_q, n_steps=n_steps, n_chains=wl.n_chains, burn_in=burn, seed=wl.seed,
+                            device=0, mix=mix)
+        mout = msmp.alloc_samples(n_wave, kz)
+        msmp.sample(wave, b["offsets"], b["lam"], kmax=km, kz=kz, out=mout, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        msmp.sample(wave, b["offsets"], b["lam"], kmax=km, kz=kz, out=mout, stream=stream)
+        msmp.posterior(n_wave, mout, with_pn=False, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        mms = e0.elapsed_time(e1)
+        mcp = {"components": len(mix[0]), "ms_per_step": mms, "waveforms_per_s": n_wave / (mms / 1e3),
+               "mcmc_steps_per_s": chain_steps / (mms / 1e3)}
+        msmp.close()
+        print(f"[bench] mcp mixture law: {mms:.1f} ms per step", file=sys.stderr, flush=True)
+
     # ---- oracle on a bounded sample of the same workload (first cpu_wave waveforms, same chains)
     cpu = None
     if not args.no_cpu:
@@ -394,6 +419,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "init_stage": lucy,
+        "mcp_charge_law": mcp,
     }
     print(json.dumps(res))
 

@@ -18,6 +18,8 @@
  *   - Gibbs sweep: t0 by Metropolis-Hastings, then one RJMCMC jump
  *     (birth / death / update) with J = 1/4 and the empty-sequence rule
  *     (Sec. 2.4, eqs. birth, death, update, delta-nu)
+ *   - MCP-PMT form: each PE's charge from a Gaussian mixture component e
+ *     (Sec. 2.1, eq. mcp-multi-norm; Sec. 2.4, eq. mcp; App. A for MCP-PMTs)
  *
  * Readings where the paper leaves a choice (each is listed in the design notes):
  *   - PE times live on a grid t = g * dt with dt = 1/sub samples; the prior is
@@ -39,7 +41,8 @@
  * (seed lo, seed hi), counter = (step, block, uid lo, uid hi) with
  * uid = wave_id * n_chains + chain; block 0 gives r0..r3, block 1 r4..r7:
  *   r0,r1 -> Box-Muller pair (t0 step, update shift); r2 -> t0 accept;
- *   r3 -> move choice; r4 (and r5) -> index / birth position; r6 -> jump accept.
+ *   r3 -> move choice; r4 (and r5) -> index / birth position; r6 -> jump accept;
+ *   r7 -> the mixture component of a born or updated PE (MCP-PMT form only).
  */
 #include <math.h>
 #include <stdint.h>

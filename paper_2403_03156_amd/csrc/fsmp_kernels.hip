@@ -21,7 +21,7 @@
 // Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = seed,
 // counter = (step, block, uid lo, uid hi).  Words of one step: r0,r1 Box-Muller pair
 // (t0 step, update shift), r2 t0 accept, r3 move, r4 (r5) index or 53-bit birth
-// uniform, r6 jump accept.
+// uniform, r6 jump accept, r7 the mixture component of a born or updated PE (MCP-PMT law).
 
 #include <math.h>
 
