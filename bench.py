@@ -73,13 +73,15 @@ def kernel_label(name):
     """bench name of a chain / prologue kernel from its demangled rocprofv3 name"""
     import re
     # chain_kernel<KCAP, lanes per chain, wavefronts per workgroup, G^-1 in device memory,
-    # replay, FP32 storage>
-    m = re.search(r"chain_kernel<(\d+), (\d+), (\d+), (true|false)(?:, (true|false))?(?:, (true|false))?>", name)
+    # replay, FP32 storage, mixture charge law>
+    m = re.search(r"chain_kernel<(\d+), (\d+), (\d+), (true|false)(?:, (true|false))?(?:, (true|false))?"
+                  r"(?:, (true|false))?>", name)
     if m:
         if m.group(5) == "true":
             return "chain_replay_k" + m.group(1)
         base = "chain_group_dm" if m.group(4) == "true" else "chain_group"
-        return base + ("_fp32" if m.group(6) == "true" else "") + "_k" + m.group(1)
+        return (base + ("_fp32" if m.group(6) == "true" else "") + ("_mcp" if m.group(7) == "true" else "")
+                + "_k" + m.group(1))
     m = re.search(r"chain_lane_kernel<(\d+), (double|float)>", name)
     if m:
         return ("chain_lane_k" if m.group(2) == "double" else "chain_lane_fp32_k") + m.group(1)

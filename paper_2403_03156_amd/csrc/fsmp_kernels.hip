@@ -1229,9 +1229,11 @@ __device__ inline MvResult lane_propose(const ModelDev &md, const MT *Mp, const 
 
 // One chain per lane.  The chain's H = G^{-1} (full, KCAP x KCAP, FP64 or FP32), x, b,
 // scratch and PE list live in device memory, interleaved across the 64 chains of a
-// tile so that every access of a wavefront is one contiguous segment.
+// tile so that every access of a wavefront is one contiguous segment.  Two wavefronts per
+// SIMD at the least (the register budget halves): with one, nothing hides the device-
+// memory round trips of the state (measured 21% slower at capacity 16).
 template <int KCAP, typename HT>
-__global__ void __launch_bounds__(256) chain_lane_kernel(ChainArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) chain_lane_kernel(ChainArgs a) {
   using LL = LaneLayout<KCAP, HT>;
   constexpr bool F32 = LL::F32;
   extern __shared__ double smem[];
@@ -2119,7 +2121,7 @@ struct GroupCfg {
   int kcap, lpc, wpb;
 };
 static const GroupCfg kGroup[] = {{16, 16, 4}, {32, 32, 4}, {48, 64, 3}, {64, 64, 4}};
-static const GroupCfg kGroupDM[] = {{16, 4, 4},  {32, 4, 8},   {48, 16, 4},  {64, 32, 4},
+static const GroupCfg kGroupDM[] = {{16, 4, 4},  {32, 4, 4},   {48, 16, 4},  {64, 32, 4},
                                     {96, 16, 2}, {128, 32, 4}, {160, 32, 4}, {192, 32, 2}};
 
 static size_t chain_lds_bytes(const GroupCfg &g, int M, int sub, bool hg, bool f32 = false, bool mcp = false) {
@@ -2138,11 +2140,8 @@ bool chain_kcap_supported(int kcap, int M, int sub) {
 bool chain_dm_supported(int kcap, int M, int sub, bool f32, bool mcp) {
   if (f32 && kcap == 48) return false;  // the precision form runs capacity 48 at 64
   if (f32 && mcp) return false;
-  for (GroupCfg g : kGroupDM)
-    if (g.kcap == kcap) {
-      if (mcp && kcap == 32) g.wpb = 4;  // the components' LDS: 64 chains per workgroup
-      return chain_lds_bytes(g, M, sub, true, f32, mcp) <= 160 * 1024;
-    }
+  for (const GroupCfg &g : kGroupDM)
+    if (g.kcap == kcap) return chain_lds_bytes(g, M, sub, true, f32, mcp) <= 160 * 1024;
   return false;
 }
 
@@ -2226,7 +2225,7 @@ hipError_t launch_chain_dm(int kcap, bool fp32, const ChainArgs &a, hipStream_t 
   if (a.force) {
     switch (kcap) {
       case 16: return launch_chain_t<16, 4, 4, true, true>(a, st, lanes, blocks);
-      case 32: return launch_chain_t<32, 4, 8, true, true>(a, st, lanes, blocks);
+      case 32: return launch_chain_t<32, 4, 4, true, true>(a, st, lanes, blocks);
       case 48: return launch_chain_t<48, 16, 4, true, true>(a, st, lanes, blocks);
       case 64: return launch_chain_t<64, 32, 4, true, true>(a, st, lanes, blocks);
       case 96: return launch_chain_t<96, 16, 2, true, true>(a, st, lanes, blocks);
@@ -2239,7 +2238,7 @@ hipError_t launch_chain_dm(int kcap, bool fp32, const ChainArgs &a, hipStream_t 
   if (fp32) {
     switch (kcap) {
       case 16: return launch_chain_t<16, 4, 4, true, false, true>(a, st, lanes, blocks);
-      case 32: return launch_chain_t<32, 4, 8, true, false, true>(a, st, lanes, blocks);
+      case 32: return launch_chain_t<32, 4, 4, true, false, true>(a, st, lanes, blocks);
       case 64: return launch_chain_t<64, 32, 4, true, false, true>(a, st, lanes, blocks);
       case 96: return launch_chain_t<96, 16, 2, true, false, true>(a, st, lanes, blocks);
       case 128: return launch_chain_t<128, 32, 4, true, false, true>(a, st, lanes, blocks);
@@ -2250,7 +2249,7 @@ hipError_t launch_chain_dm(int kcap, bool fp32, const ChainArgs &a, hipStream_t 
   }
   switch (kcap) {
     case 16: return launch_chain_t<16, 4, 4, true>(a, st, lanes, blocks);
-    case 32: return launch_chain_t<32, 4, 8, true>(a, st, lanes, blocks);
+    case 32: return launch_chain_t<32, 4, 4, true>(a, st, lanes, blocks);
     case 48: return launch_chain_t<48, 16, 4, true>(a, st, lanes, blocks);
     case 64: return launch_chain_t<64, 32, 4, true>(a, st, lanes, blocks);
     case 96: return launch_chain_t<96, 16, 2, true>(a, st, lanes, blocks);
