@@ -2121,7 +2121,7 @@ struct GroupCfg {
   int kcap, lpc, wpb;
 };
 static const GroupCfg kGroup[] = {{16, 16, 4}, {32, 32, 4}, {48, 64, 3}, {64, 64, 4}};
-static const GroupCfg kGroupDM[] = {{16, 4, 4},  {32, 4, 4},   {48, 16, 4},  {64, 32, 4},
+static const GroupCfg kGroupDM[] = {{16, 4, 4},  {32, 4, 4},   {48, 16, 2},  {64, 32, 4},
                                     {96, 16, 2}, {128, 32, 4}, {160, 32, 4}, {192, 32, 2}};
 
 static size_t chain_lds_bytes(const GroupCfg &g, int M, int sub, bool hg, bool f32 = false, bool mcp = false) {
@@ -2213,7 +2213,7 @@ hipError_t launch_chain_dm(int kcap, bool fp32, const ChainArgs &a, hipStream_t 
     switch (kcap) {
       case 16: return launch_chain_t<16, 4, 4, true, false, false, true>(a, st, lanes, blocks);
       case 32: return launch_chain_t<32, 4, 4, true, false, false, true>(a, st, lanes, blocks);
-      case 48: return launch_chain_t<48, 16, 4, true, false, false, true>(a, st, lanes, blocks);
+      case 48: return launch_chain_t<48, 16, 2, true, false, false, true>(a, st, lanes, blocks);
       case 64: return launch_chain_t<64, 32, 4, true, false, false, true>(a, st, lanes, blocks);
       case 96: return launch_chain_t<96, 16, 2, true, false, false, true>(a, st, lanes, blocks);
       case 128: return launch_chain_t<128, 32, 4, true, false, false, true>(a, st, lanes, blocks);
@@ -2226,7 +2226,7 @@ hipError_t launch_chain_dm(int kcap, bool fp32, const ChainArgs &a, hipStream_t 
     switch (kcap) {
       case 16: return launch_chain_t<16, 4, 4, true, true>(a, st, lanes, blocks);
       case 32: return launch_chain_t<32, 4, 4, true, true>(a, st, lanes, blocks);
-      case 48: return launch_chain_t<48, 16, 4, true, true>(a, st, lanes, blocks);
+      case 48: return launch_chain_t<48, 16, 2, true, true>(a, st, lanes, blocks);
       case 64: return launch_chain_t<64, 32, 4, true, true>(a, st, lanes, blocks);
       case 96: return launch_chain_t<96, 16, 2, true, true>(a, st, lanes, blocks);
       case 128: return launch_chain_t<128, 32, 4, true, true>(a, st, lanes, blocks);
@@ -2250,7 +2250,7 @@ hipError_t launch_chain_dm(int kcap, bool fp32, const ChainArgs &a, hipStream_t 
   switch (kcap) {
     case 16: return launch_chain_t<16, 4, 4, true>(a, st, lanes, blocks);
     case 32: return launch_chain_t<32, 4, 4, true>(a, st, lanes, blocks);
-    case 48: return launch_chain_t<48, 16, 4, true>(a, st, lanes, blocks);
+    case 48: return launch_chain_t<48, 16, 2, true>(a, st, lanes, blocks);
     case 64: return launch_chain_t<64, 32, 4, true>(a, st, lanes, blocks);
     case 96: return launch_chain_t<96, 16, 2, true>(a, st, lanes, blocks);
     case 128: return launch_chain_t<128, 32, 4, true>(a, st, lanes, blocks);
