@@ -26,6 +26,17 @@ read from profiles/traffic_<workload>.json while the kernel source is unchanged:
     rocprofv3 --pmc FETCH_SIZE -d DIR_F -o pmc -- python bench.py --pmc-run
     rocprofv3 --pmc WRITE_SIZE -d DIR_W -o pmc -- python bench.py --pmc-run
     python bench.py --pmc-summary DIR_F DIR_W
+
+The chain kernels are limited by instruction issue, not by bytes: two more counter runs give
+each kernel's VALU busy fraction (4 x SQ_ACTIVE_INST_VALU SIMD cycles over 1,024 SIMDs x
+2.4 GHz x its duration; a wave64 VALU instruction occupies its SIMD 4 cycles, so the issue
+ceiling is 614.4e9 wave-instructions/s, the FP64 vector peak over 128 flops):
+
+    rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVE_CYCLES SQ_BUSY_CYCLES
+              SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU -d DIR_A -o pmc -- python bench.py --pmc-run
+    rocprofv3 --pmc SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_SMEM SQ_INSTS_FLAT SQ_WAIT_ANY
+              SQ_INSTS_BRANCH GRBM_GUI_ACTIVE -d DIR_B -o pmc -- python bench.py --pmc-run
+    python bench.py --issue-summary DIR_A DIR_B
 """
 import hashlib
 import argparse
@@ -42,6 +53,7 @@ if ROOT not in sys.path:
 
 PEAK_FP64 = 78.6e12  # MI355X dense FP64 vector, FLOP/s
 PEAK_HBM = 8.0e12    # MI355X HBM3E, bytes/s
+N_SIMD, CLOCK_HZ = 1024, 2.4e9  # MI355X: 256 CUs x 4 SIMDs, peak engine clock
 KSRC = os.path.join(ROOT, "paper_2403_03156_amd", "csrc", "fsmp_kernels.hip")
 COPY_PROBE_MIB = 1024
 
@@ -66,6 +78,9 @@ def parse():
                     help="one untimed step after a plain device copy of known size (for rocprofv3 --pmc)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs into profiles/")
+    ap.add_argument("--issue-summary", nargs=2, metavar=("SQ_DIR_A", "SQ_DIR_B"),
+                    help="summarise two rocprofv3 --pmc runs of SQ counters into profiles/")
+    ap.add_argument("--step-ms", type=float, default=0.0, help="concurrent step time for --issue-summary")
     return ap.parse_args()
 
 
@@ -140,6 +155,65 @@ def pmc_summary(fdir, wdir, workload):
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     json.dump(res, open(path, "w"), indent=1)
     print(json.dumps(res, indent=1))
+
+
+def issue_summary(adir, bdir, workload, step_ms):
+    """Per-kernel instruction mix and VALU busy fraction from two rocprofv3 --pmc runs of SQ
+    counters (--pmc-run: the kernels run one at a time, so each duration is the kernel alone)."""
+    import csv
+    import glob
+
+    def read(d):
+        agg, dur = {}, {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                lab = kernel_label(r["Kernel_Name"])
+                if lab is None:
+                    continue
+                agg.setdefault(lab, {})
+                agg[lab][r["Counter_Name"]] = agg[lab].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+                dur[(lab, r["Dispatch_Id"])] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+        t = {}
+        for (lab, _), v in dur.items():
+            t[lab] = t.get(lab, 0.0) + v
+        return agg, t
+
+    a, ta = read(adir)
+    b, _ = read(bdir)
+    lines = [f"# Instruction issue of the {workload} step, per kernel", "",
+             "Commands (each counter pass a run of its own, the kernels of one step run one at a time):", "",
+             "    rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
+             "SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU --output-format csv -d " + adir + " -o pmc -- python bench.py "
+             "--pmc-run",
+             "    rocprofv3 --pmc SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_SMEM SQ_INSTS_FLAT SQ_WAIT_ANY "
+             "SQ_INSTS_BRANCH GRBM_GUI_ACTIVE --output-format csv -d " + bdir + " -o pmc -- python bench.py --pmc-run",
+             f"    python bench.py --issue-summary {adir} {bdir}", "",
+             f"Source sha256 of the kernels: `{source_hash()}`.", "",
+             "VALU busy = 4 x SQ_ACTIVE_INST_VALU (quad-cycles; it reads 1.00-1.05 x SQ_INSTS_VALU here) over "
+             f"{N_SIMD} SIMDs x {CLOCK_HZ / 1e9:.1f} GHz x the kernel's duration.  The issue ceiling, one wave64 VALU "
+             f"instruction per SIMD every 4 cycles, is {N_SIMD * CLOCK_HZ / 4 / 1e9:.1f}e9 wave-instructions/s "
+             "(the 78.6 TFLOP/s FP64 vector peak over 64 lanes x 2 flops).", "",
+             "| kernel | ms alone | waves | VALU instr | VALU instr/s | VALU busy | SALU/VALU | LDS/VALU | "
+             "branch/VALU | VMEM rd+wr/VALU |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    busy_total = 0.0
+    for lab in sorted(a, key=lambda k: -a[k].get("SQ_INSTS_VALU", 0.0)):
+        v, w, t = a[lab], b.get(lab, {}), ta[lab]
+        valu = v.get("SQ_INSTS_VALU", 0.0)
+        busy = 4.0 * v.get("SQ_ACTIVE_INST_VALU", 0.0)
+        busy_total += busy
+        if valu <= 0:
+            continue
+        vm = w.get("SQ_INSTS_VMEM_RD", 0.0) + w.get("SQ_INSTS_VMEM_WR", 0.0)
+        lines.append(f"| {lab} | {t * 1e3:.1f} | {v.get('SQ_WAVES', 0):.0f} | {valu:.3g} | {valu / t / 1e9:.0f}e9 | "
+                     f"{busy / (N_SIMD * CLOCK_HZ * t):.1%} | {v.get('SQ_INSTS_SALU', 0) / valu:.2f} | "
+                     f"{v.get('SQ_INSTS_LDS', 0) / valu:.3f} | {w.get('SQ_INSTS_BRANCH', 0) / valu:.3f} | "
+                     f"{vm / valu:.3f} |")
+    lines += ["", f"Whole step: {busy_total / 4:.3g} VALU quad-cycles; over the concurrent step of {step_ms:.1f} ms "
+              f"that is {busy_total / (N_SIMD * CLOCK_HZ * step_ms * 1e-3):.1%} VALU busy on every SIMD.", ""]
+    path = os.path.join(ROOT, "profiles", f"chain_kernels_{workload}_valu_issue.md")
+    open(path, "w").write("\n".join(lines))
+    print("\n".join(lines))
 
 
 def recorded_traffic(workload, kernel):
@@ -232,6 +306,9 @@ def main():
 
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.workload)
+        return
+    if args.issue_summary:
+        issue_summary(args.issue_summary[0], args.issue_summary[1], args.workload, args.step_ms)
         return
 
     if args.serve:
