@@ -136,6 +136,19 @@ __device__ inline double phi_total(const ModelDev &md, double t0, int glo, int g
   return p.n > 0 ? phi_partial(md, xs_exp(md, p.xs), p.n) : 0.0;
 }
 
+// phi_total for a chain's lane group (t0, glo, ghi the same in all its lanes, every lane
+// active): the two exponentials are one evaluation (the group's first lane e2, its second
+// e12)
+__device__ inline double phi_total_group(const ModelDev &md, double t0, int glo, int ghi, int lane, int base) {
+  const GridPos p = grid_pos(md, t0, glo, ghi);
+  const double v = exp(-p.xs * (lane == 0 ? md.inv_tau2 : md.inv_tau12));
+  XsExp x;
+  x.e2 = __shfl(v, base, kWave);
+  const double v12 = __shfl(v, base + 1, kWave);
+  x.e12 = md.kind == FSMP_PHI_EXP ? 0.0 : v12;
+  return p.n > 0 ? phi_partial(md, x, p.n) : 0.0;
+}
+
 template <int W>
 __device__ inline double group_sum(double v) {
 #pragma unroll
@@ -158,6 +171,15 @@ __device__ inline int group_min(int v) {
     v = u < v ? u : v;
   }
   return v;
+}
+
+// The logs of two values that are the same in every lane of a chain's group, in one
+// evaluation: the group's first lane takes x0, its second x1, and both results go to the
+// whole group (base = the group's first lane; every lane of the group must be active)
+__device__ inline void group_log2(double x0, double x1, int lane, int base, double &l0, double &l1) {
+  const double v = log(lane == 0 ? x0 : x1);
+  l0 = __shfl(v, base, kWave);
+  l1 = __shfl(v, base + 1, kWave);
 }
 
 // BIEXP part of log phi that depends on t0: log(1 - e^{-(t - t0) / tau_rise})
@@ -189,7 +211,14 @@ __device__ inline double overlap(const ModelDev &md, const double *vt, const dou
 template <int LPC>
 __device__ inline int birth_draw(const ModelDev &md, double t0, int glo, int ghi, double target, int lane, int grp) {
   const GridPos p = grid_pos(md, t0, glo, ghi);
-  const XsExp xe = xs_exp(md, p.xs);
+  XsExp xe;
+  {
+    // the two exponentials in one evaluation (the group's first lane e2, its second e12)
+    const double v = exp(-p.xs * (lane == 0 ? md.inv_tau2 : md.inv_tau12));
+    xe.e2 = __shfl(v, grp * LPC, kWave);
+    const double v12 = __shfl(v, grp * LPC + 1, kWave);
+    xe.e12 = md.kind == FSMP_PHI_EXP ? 0.0 : v12;
+  }
   int64_t k;
   if (md.kind == FSMP_PHI_EXP) {
     // closed-form inverse of the truncated geometric law
@@ -429,6 +458,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
 
   const int wv = threadIdx.x / kWave, l64 = threadIdx.x % kWave;
   const int grp = l64 / LPC, lane = l64 % LPC;
+  const int gbase = grp * LPC;  // the group's first lane in the wavefront
   const int64_t tile = (int64_t)blockIdx.x * WPB + wv;
   const int64_t slot = tile * CPW + grp;
   if (slot >= a.n_list) return;
@@ -481,11 +511,11 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
 
   double t0 = a.t0init[w];
   int N = 0;
-  double Phi = (glo <= ghi) ? phi_total(md, t0, glo, ghi) : 0.0;
-  // Lambda_T and its log change only with t0; S_cur = sum over PEs of the BIEXP rise term
+  double Phi = (glo <= ghi) ? phi_total_group(md, t0, glo, ghi, lane, gbase) : 0.0;
+  // Lambda_T changes only with t0 (its log is taken with the jump's own log); S_cur = sum over PEs of the BIEXP rise term
   // at the current t0 and gmin = the smallest PE grid index (phi must stay positive at
   // every PE) make the t0 step one term per PE
-  double Lam = lam * md.dt * Phi, logLam = log(Lam);
+  double Lam = lam * md.dt * Phi;
   const bool biexp = md.kind == FSMP_PHI_BIEXP;
   double S_cur = 0.0;
   int gmin = INT32_MAX;
@@ -539,10 +569,29 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         else if (drift > a.drift_bound) st |= FSMP_ST_DRIFT;
       }
     }
+    // The step's random words and the logs of its three uniforms (Box-Muller radius, t0
+    // acceptance, jump acceptance) do not depend on the chain's state: the group's first
+    // lane makes Philox block 0 and its second lane block 1, its first three lanes one log
+    // each, and the values go to the whole group by lane permutes (the same values as
+    // computing all of it in every lane, with a third of the VALU work)
+    static_assert(LPC >= 4, "a chain's group needs at least three lanes");
     uint32_t r[8];
-    philox4x32_10((uint32_t)step, 0u, uid0, uid1, a.key0, a.key1, r);
-    philox4x32_10((uint32_t)step, 1u, uid0, uid1, a.key0, a.key1, r + 4);
-    const double R = sqrt(-2.0 * log(u01(r[0])));
+    double lg0, lg2, lg6;  // log u01(r0), log u01(r2), log u01(r6)
+    {
+      const int base = gbase;
+      uint32_t q[4];
+      philox4x32_10((uint32_t)step, (uint32_t)(lane & 1), uid0, uid1, a.key0, a.key1, q);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        r[u] = (uint32_t)__shfl((int)q[u], base, kWave);
+        r[4 + u] = (uint32_t)__shfl((int)q[u], base + 1, kWave);
+      }
+      const double lv = log(u01(lane == 0 ? r[0] : lane == 1 ? r[2] : r[6]));
+      lg0 = __shfl(lv, base, kWave);
+      lg2 = __shfl(lv, base + 1, kWave);
+      lg6 = __shfl(lv, base + 2, kWave);
+    }
+    const double R = sqrt(-2.0 * lg0);
     const double th = 2.0 * M_PI * u01(r[1]);
     const double xi_t0 = R * cos(th), xi_sh = R * sin(th);
 
@@ -556,9 +605,8 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
       t0acc = (rec.flags & 4) != 0;
       if (rec.t0 != t0) {
         t0 = rec.t0;
-        Phi = (glo <= ghi) ? phi_total(md, t0, glo, ghi) : 0.0;
+        Phi = (glo <= ghi) ? phi_total_group(md, t0, glo, ghi, lane, gbase) : 0.0;
         Lam = lam * md.dt * Phi;
-        logLam = log(Lam);
         if (biexp) {
           double sn = 0.0;
           for (int i = lane; i < N; i += LPC) sn += rise_term(md, zg[i], t0);
@@ -575,13 +623,12 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
           S_new = group_sum<LPC>(S_new);
         }
         const double part = (double)N * (t0p - t0) * md.inv_tau2 + (S_new - S_cur);
-        const double Phip = (glo <= ghi) ? phi_total(md, t0p, glo, ghi) : 0.0;
+        const double Phip = (glo <= ghi) ? phi_total_group(md, t0p, glo, ghi, lane, gbase) : 0.0;
         const double la0 = part - (lam * md.dt * Phip - lam * md.dt * Phi);
-        if (log(u01(r[2])) < la0) {
+        if (lg2 < la0) {
           t0 = t0p;
           Phi = Phip;
           Lam = lam * md.dt * Phi;
-          logLam = log(Lam);
           S_cur = S_new;
           t0acc = true;
           if (lane == 0) cnt[1]++;
@@ -639,8 +686,10 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
           rm2o = md.mix_rhom2[ek[j]];
         }
         if (om > 0.0) {
-          dnu = 0.5 * (-lro - log(om) + (rm2o - xj * xj / om) * md.inv_s);
-          la = dnu - logLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
+          double lom, lLam;
+          group_log2(om, Lam, lane, gbase, lom, lLam);
+          dnu = 0.5 * (-lro - lom + (rm2o - xj * xj / om) * md.inv_s);
+          la = dnu - lLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
           valid = true;
         } else {
           st |= FSMP_ST_FACTOR;
@@ -650,9 +699,12 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         sh = FORCE ? rec.g - zg[j] : (int)rint(xi_sh * md.shift_sd / md.dt);
         gnew = zg[j] + sh;
         if (gnew >= glo && gnew <= ghi) {
-          lpn = log_phi(md, (double)gnew * md.dt - t0);
+          // log phi at the new and at the old position, one evaluation for both
+          const double lv = log_phi(md, (double)(lane == 0 ? gnew : zg[j]) * md.dt - t0);
+          lpn = __shfl(lv, gbase, kWave);
+          const double lpo_v = __shfl(lv, gbase + 1, kWave);
           if (lpn > -INFINITY) {
-            lpo = log_phi(md, (double)zg[j] * md.dt - t0);
+            lpo = lpo_v;
             if constexpr (MCP) {
               lro = md.mix_lrho[ek[j]];
               rm2o = md.mix_rhom2[ek[j]];
@@ -691,8 +743,10 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         delta2 = d - q;
         if (delta2 > 0.0) {
           up = beta - p;
-          dnu = -0.5 * (-lrn + log(delta2) + (rm2n - up * up / delta2) * md.inv_s);
-          la = dnu + logLam - lgn[N + 1] + (N == 0 ? md.logJ : 0.0);
+          double ld2, lLam;
+          group_log2(delta2, Lam, lane, gbase, ld2, lLam);
+          dnu = -0.5 * (-lrn + ld2 + (rm2n - up * up / delta2) * md.inv_s);
+          la = dnu + lLam - lgn[N + 1] + (N == 0 ? md.logJ : 0.0);
           valid = true;
         } else {
           st |= FSMP_ST_FACTOR;
@@ -705,7 +759,9 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         delta2 = d - (q - ej * ej / om);
         up = beta - (p - ej * xj / om);
         if (delta2 > 0.0 && om > 0.0) {
-          dnu = 0.5 * (-log(om) - log(delta2) + (up * up / delta2 - xj * xj / om) * md.inv_s);
+          double lom, ld2;
+          group_log2(om, delta2, lane, gbase, lom, ld2);
+          dnu = 0.5 * (-lom - ld2 + (up * up / delta2 - xj * xj / om) * md.inv_s);
           // mixture form: the removed and the added PE carry their own rho and rho mu^2
           if constexpr (MCP) dnu += 0.5 * (lrn - lro + (rm2o - rm2n) * md.inv_s);
           la = dnu + lpn - lpo;
@@ -722,7 +778,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
 
     // precision form, a decision near the threshold: refresh in FP64 and decide with the
     // FP64 delta-nu of the same proposal
-    const double logu = (F32 && valid) ? log(u01(r[6])) : 0.0;
+    const double logu = lg6;
     if constexpr (F32) {
       if (valid && fabs(logu - la) < a.near_eps * fmax(1.0, fabs(dnu))) {
         double drift;
@@ -732,8 +788,10 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
           } else if (move == 2) {
             om = W[(j * LD + j) * HS];
             xj = xv[j];
-            dnu = 0.5 * (-md.log_rho - log(om) + (md.rhom2 - xj * xj / om) * md.inv_s);
-            la = dnu - logLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
+            double lom, lLam;
+            group_log2(om, Lam, lane, gbase, lom, lLam);
+            dnu = 0.5 * (-md.log_rho - lom + (md.rhom2 - xj * xj / om) * md.inv_s);
+            la = dnu - lLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
           }
         } else if (N > 0) {
           st |= FSMP_ST_FACTOR;
@@ -742,7 +800,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
     }
 
     bool accepted = false;
-    if (valid && (FORCE ? (rec.flags & 2) != 0 : F32 ? logu < la : log(u01(r[6])) < la)) {
+    if (valid && (FORCE ? (rec.flags & 2) != 0 : logu < la)) {
       accepted = true;
       if (lane == 0) cnt[2 * move + 1]++;
       WAVE_SYNC();
