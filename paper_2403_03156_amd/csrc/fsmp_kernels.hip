@@ -298,13 +298,43 @@ __global__ void __launch_bounds__(256) prologue_kernel(PrologueArgs a) {
       for (int64_t g = threadIdx.x; g < (int64_t)md.sub * Lw; g += blockDim.x) a.occ[md.sub * a.woff[w] + g] = 0;
     const int glo = a.grange[2 * w], ghi = a.grange[2 * w + 1];
     double *out = a.mf + a.mfoff[w];
-    for (int g = glo + (int)threadIdx.x; g <= ghi; g += blockDim.x) {
-      const int n0 = sub_div(md, g + md.sub - 1);
-      int n1 = sub_div(md, g + md.M - 1);
-      if (n1 > Lw - 1) n1 = Lw - 1;
-      double s = 0.0;
-      for (int n = n0; n <= n1; ++n) s += (double)x[n] * vt[md.sub * n - g];
-      out[g - glo] = s;
+    // four consecutive grid points per thread share each sample load; every point sums its
+    // own samples n0(g) .. n1(g) in increasing n (both bounds nondecreasing in g)
+    for (int g0 = glo + 4 * (int)threadIdx.x; g0 <= ghi; g0 += 4 * (int)blockDim.x) {
+      int n0[4], n1[4];
+      double s[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int g = g0 + u;
+        n0[u] = g <= ghi ? sub_div(md, g + md.sub - 1) : INT32_MAX;
+        n1[u] = g <= ghi ? sub_div(md, g + md.M - 1) : -1;
+        if (n1[u] > Lw - 1) n1[u] = Lw - 1;
+        s[u] = 0.0;
+      }
+      const int gl = ghi - g0 < 3 ? ghi - g0 : 3;
+      // samples that all four points take (four points in T) need no range checks
+      const int blo = gl == 3 ? n0[3] : INT32_MAX, bhi = n1[0];
+      int n = n0[0];
+      for (; n <= n1[gl] && n < blo; ++n) {
+        const double xv = (double)x[n];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (n >= n0[u] && n <= n1[u]) s[u] += xv * vt[md.sub * n - (g0 + u)];
+      }
+      for (; n <= bhi; ++n) {
+        const double xv = (double)x[n];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s[u] += xv * vt[md.sub * n - (g0 + u)];
+      }
+      for (; n <= n1[gl]; ++n) {
+        const double xv = (double)x[n];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (n >= n0[u] && n <= n1[u]) s[u] += xv * vt[md.sub * n - (g0 + u)];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (g0 + u <= ghi) out[g0 + u - glo] = s[u];
     }
   }
 }
