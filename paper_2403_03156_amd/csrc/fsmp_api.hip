@@ -345,8 +345,8 @@ hipError_t ensure_ptab(fsmp_ctx *c, int64_t need) {
   std::vector<double> h(2 * (size_t)n);
   for (int64_t k = 0; k < n; ++k) {
     const double kdt = (double)k * c->md.dt;
-    h[2 * k] = -std::expm1(-kdt * c->md.inv_tau2);
-    h[2 * k + 1] = c->md.kind == FSMP_PHI_EXP ? 0.0 : -std::expm1(-kdt * c->md.inv_tau12);
+    h[2 * k] = -std::expm1(-kdt * c->md.inv_tau2) / c->md.den2;
+    h[2 * k + 1] = c->md.kind == FSMP_PHI_EXP ? 0.0 : -std::expm1(-kdt * c->md.inv_tau12) / c->md.den12;
   }
   (void)hipDeviceSynchronize();
   c->ptab.release();

@@ -24,7 +24,8 @@ struct ModelDev {
   // t0 prior and proposals
   double t0_min, t0_max, t0_sd, shift_sd;
   double J, logJ;
-  // [k][2]: 1 - e^{-k dt / tau2}, 1 - e^{-k dt / tau12} for k = 0 .. ptab_n - 1 (device)
+  // [k][2]: (1 - e^{-k dt / tau2}) / den2, (1 - e^{-k dt / tau12}) / den12 for k = 0 .. ptab_n - 1
+  // (device; the geometric series' denominators divided out on the host)
   const double *ptab;
   int64_t ptab_n;
   // MCP-PMT mixture (n_mix > 0): cumulative weights (accumulated in index order) and, per

@@ -95,8 +95,9 @@ __device__ inline double log_phi(const ModelDev &md, double x) {
 //   BIEXP: C [e^{-xs/tau2} (1 - e^{-k dt/tau2}) / (1 - e^{-dt/tau2})
 //             - e^{-xs/tau12} (1 - e^{-k dt/tau12}) / (1 - e^{-dt/tau12})].
 // The t0-dependent factors are computed once per use (XsExp); the count-dependent ones,
-// 1 - e^{-k dt/tau}, come from the table md.ptab ([k][2], k up to the longest T), which
-// turns each evaluation of a search into two loads.
+// (1 - e^{-k dt/tau}) / (1 - e^{-dt/tau}), come from the table md.ptab ([k][2], k up to the
+// longest T, divided on the host), which turns each evaluation of a search into two loads
+// and two multiplies.
 struct XsExp {
   double e2, e12;
 };
@@ -109,9 +110,9 @@ __device__ inline XsExp xs_exp(const ModelDev &md, double xs) {
 }
 
 __device__ inline double phi_partial(const ModelDev &md, const XsExp &x, int64_t k) {
-  const double a = x.e2 * md.ptab[2 * k] / md.den2;
+  const double a = x.e2 * md.ptab[2 * k];
   if (md.kind == FSMP_PHI_EXP) return a * md.inv_tau2;
-  const double b = x.e12 * md.ptab[2 * k + 1] / md.den12;
+  const double b = x.e12 * md.ptab[2 * k + 1];
   return md.C * (a - b);
 }
 
