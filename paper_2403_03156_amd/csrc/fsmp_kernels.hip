@@ -543,9 +543,9 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
   double t0 = a.t0init[w];
   int N = 0;
   double Phi = (glo <= ghi) ? phi_total_group(md, t0, glo, ghi, lane, gbase) : 0.0;
-  // Lambda_T changes only with t0 (its log is taken with the jump's own log); S_cur = sum over PEs of the BIEXP rise term
-  // at the current t0 and gmin = the smallest PE grid index (phi must stay positive at
-  // every PE) make the t0 step one term per PE
+  // Lambda_T changes only with t0 (its log is taken with the jump's own log); S_cur = sum
+  // over PEs of the BIEXP rise term at the current t0 and gmin = the smallest PE grid index
+  // (phi must stay positive at every PE) make the t0 step one term per PE
   double Lam = lam * md.dt * Phi;
   const bool biexp = md.kind == FSMP_PHI_BIEXP;
   double S_cur = 0.0;
