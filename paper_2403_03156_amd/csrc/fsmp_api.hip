@@ -863,6 +863,41 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   int n_buckets = 0;
   for (int bi = 0; bi < kNumCaps; ++bi) n_buckets += bucket_start[bi + 1] > bucket_start[bi];
   const bool fan = n_buckets > 1;
+  // Side streams: no more than the process has hardware queues (GPU_MAX_HW_QUEUES, HIP's
+  // default 4), since streams beyond that share a queue and run one after the other. The
+  // buckets go to them largest estimated cost first, each to the least loaded stream (cost
+  // = chains x a per-capacity weight, the measured time of one sweep of one chain relative
+  // to capacity 16); a stream runs its buckets in capacity order.
+  int side_of[kNumCaps] = {};
+  if (fan) {
+    int n_side = 4;
+    if (const char *q = std::getenv("GPU_MAX_HW_QUEUES")) {
+      const int v = std::atoi(q);
+      if (v > 0) n_side = v;
+    }
+    if (n_side > n_buckets) n_side = n_buckets;
+    if (n_side > kNumCaps) n_side = kNumCaps;
+    static const double kWeight[kNumCaps] = {1.0, 3.8, 5.4, 8.8, 16.0, 25.0, 35.0, 45.0};
+    double load[kNumCaps] = {};
+    bool done[kNumCaps] = {};
+    for (int r = 0; r < n_buckets; ++r) {
+      int best = -1;
+      double bc = -1.0;
+      for (int bi = 0; bi < kNumCaps; ++bi) {
+        const double cost = (double)(bucket_start[bi + 1] - bucket_start[bi]) * kWeight[bi];
+        if (!done[bi] && bucket_start[bi + 1] > bucket_start[bi] && cost > bc) {
+          bc = cost;
+          best = bi;
+        }
+      }
+      int sq = 0;
+      for (int k = 1; k < n_side; ++k)
+        if (load[k] < load[sq]) sq = k;
+      side_of[best] = sq;
+      load[sq] += bc;
+      done[best] = true;
+    }
+  }
   if (fan && e == hipSuccess) {
     if (!c->fork) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(c->fork, st);
@@ -872,11 +907,12 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     if (cnt == 0) continue;
     hipStream_t ks = st;
     if (fan) {
-      if (!c->side[bi]) e = hipStreamCreateWithFlags(&c->side[bi], hipStreamNonBlocking);
+      const int sq = side_of[bi];
+      if (!c->side[sq]) e = hipStreamCreateWithFlags(&c->side[sq], hipStreamNonBlocking);
       if (e == hipSuccess && !c->join[bi]) e = hipEventCreateWithFlags(&c->join[bi], hipEventDisableTiming);
-      if (e == hipSuccess) e = hipStreamWaitEvent(c->side[bi], c->fork, 0);
+      if (e == hipSuccess) e = hipStreamWaitEvent(c->side[sq], c->fork, 0);
       if (e != hipSuccess) break;
-      ks = c->side[bi];
+      ks = c->side[sq];
     }
     ca.chains = c->chains.p + bucket_start[bi];
     ca.n_list = cnt;
