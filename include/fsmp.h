@@ -301,7 +301,12 @@ size_t fsmp_workspace_bytes(const fsmp_ctx *ctx, const fsmp_batch *batch);
 
 /* Run cfg.n_chains chains of cfg.n_steps Gibbs sweeps for every waveform of the batch and
  * write `out`.  Validates every host array first (FSMP_EINVAL, nothing enqueued); returns
- * FSMP_ENOTSUP if a kmax exceeds 192 or the SER support does not fit a kernel. */
+ * FSMP_ENOTSUP if a kmax exceeds 192 or the SER support does not fit a kernel.  The work is
+ * enqueued on `hip_stream` (a hipStream_t; NULL = the null stream) and is complete when that
+ * stream is: the PE-capacity buckets of the batch run concurrently on the context's own
+ * side streams (at most GPU_MAX_HW_QUEUES of them, default 4), forked from and joined back
+ * into `hip_stream` with events.  The calls of one context share its workspace: give them
+ * one stream, or order their streams, so that two calls never run on the device at once. */
 fsmp_status fsmp_sample(fsmp_ctx *ctx, const fsmp_batch *batch, const fsmp_samples *out, void *hip_stream);
 
 /* Replay (a check of the sampler's delta-nu along a given path; Sec. 2.4 moves, App. A
