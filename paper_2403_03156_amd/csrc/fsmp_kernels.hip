@@ -188,6 +188,12 @@ __device__ inline double rise_term(const ModelDev &md, int g, double t0) {
   return log(-expm1(-((double)g * md.dt - t0) * md.inv_tau1));
 }
 
+// its factor 1 - e^{-(t - t0) / tau_rise}, in (0, 1) for t > t0; t - t0 is at least an ulp
+// of t0, so a product of eight factors stays far above the FP64 underflow threshold
+__device__ inline double rise_factor(const ModelDev &md, int g, double t0) {
+  return -expm1(-((double)g * md.dt - t0) * md.inv_tau1);
+}
+
 // v / sub and v % sub for v >= 0 (grid indices): shifts when sub is a power of two
 __device__ inline int sub_div(const ModelDev &md, int v) { return md.sub_shift >= 0 ? v >> md.sub_shift : v / md.sub; }
 __device__ inline int sub_mod(const ModelDev &md, int v) {
@@ -650,7 +656,18 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
       if (biexp ? (xmin > 0.0) : (xmin >= 0.0)) {
         double S_new = 0.0;
         if (biexp) {
-          for (int i = lane; i < N; i += LPC) S_new += rise_term(md, zg[i], t0p);
+          // the rise factors of a lane's PEs multiplied in runs of up to eight, one log per run
+          double pr = 1.0;
+          int m = 0;
+          for (int i = lane; i < N; i += LPC) {
+            pr *= rise_factor(md, zg[i], t0p);
+            if (++m == 8) {
+              S_new += log(pr);
+              pr = 1.0;
+              m = 0;
+            }
+          }
+          S_new += log(pr);
           S_new = group_sum<LPC>(S_new);
         }
         const double part = (double)N * (t0p - t0) * md.inv_tau2 + (S_new - S_cur);
@@ -1447,7 +1464,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
       if (ok) {
         double S_new = 0.0;
         if (biexp)
-          for (int i = 0; i < N; ++i) S_new += log(-expm1(-((double)ZG(i) * md.dt - t0p) * md.inv_tau1));
+        {
+          // the rise factors multiplied in runs of up to eight, one log per run
+          double pr = 1.0;
+          int m = 0;
+          for (int i = 0; i < N; ++i) {
+            pr *= rise_factor(md, ZG(i), t0p);
+            if (++m == 8) {
+              S_new += log(pr);
+              pr = 1.0;
+              m = 0;
+            }
+          }
+          S_new += log(pr);
+        }
         const double part = (double)N * (t0p - t0) * md.inv_tau2 + (S_new - S_cur);
         const double Phip = (glo <= ghi) ? phi_total(md, t0p, glo, ghi) : 0.0;
         const double la0 = part - (lam * md.dt * Phip - lam * md.dt * Phi);
