@@ -150,10 +150,33 @@ __device__ inline double phi_total_group(const ModelDev &md, double t0, int glo,
   return p.n > 0 ? phi_partial(md, x, p.n) : 0.0;
 }
 
+// v from the lane the DPP control CTRL selects, for a double (its two halves moved alike)
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over a group of W lanes (W a power of two, groups aligned to W): a butterfly over lane
+// offsets W/2, ..., 2, 1, each lane adding the value of lane (its index xor the offset), so
+// every lane ends with the same sum.  Offsets of 16 and more go through lane permutes; the
+// rest are DPP moves inside a row of 16: xor 8 is a rotation of the row by 8, xor 4 after it
+// a rotation by 4 (the values then depend only on the lane index mod 8, where a rotation by
+// 4 and xor 4 agree), xor 2 and xor 1 quad permutations.  The pairs, and so the sums, are
+// the same as with lane permutes for every offset.
 template <int W>
 __device__ inline double group_sum(double v) {
 #pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+  for (int o = W / 2; o >= 16; o >>= 1) v += __shfl_xor(v, o, W);
+  if constexpr (W >= 16) {
+    v += dpp_move<0x128>(v);  // row_ror:8
+    v += dpp_move<0x124>(v);  // row_ror:4
+  } else if constexpr (W == 8) {
+    v += __shfl_xor(v, 4, W);
+  }
+  if constexpr (W >= 4) v += dpp_move<0x4E>(v);  // quad_perm [2, 3, 0, 1]: xor 2
+  if constexpr (W >= 2) v += dpp_move<0xB1>(v);  // quad_perm [1, 0, 3, 2]: xor 1
   return v;
 }
 
