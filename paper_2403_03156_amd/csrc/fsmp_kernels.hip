@@ -89,6 +89,30 @@ __device__ inline double log_phi(const ModelDev &md, double x) {
   return md.logC - x * md.inv_tau2 + log(-expm1(-x * md.inv_tau1));
 }
 
+// v from the lane the DPP control CTRL selects, for a double (its two halves moved alike)
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// The value of lane K of the caller's group of W lanes (groups aligned to W, every lane of
+// the group active): a DPP broadcast inside a quad (W = 4: quad_perm [K, K, K, K]) or a row
+// (W = 16: row_newbcast:K), else a lane permute from lane base + K
+template <int W, int K>
+__device__ inline double group_bcast(double v, int base) {
+  if constexpr (W == 4) return dpp_move<K * 0x55>(v);
+  else if constexpr (W == 16) return dpp_move<0x150 + K>(v);
+  else return __shfl(v, base + K, kWave);
+}
+template <int W, int K>
+__device__ inline uint32_t group_bcast(uint32_t v, int base) {
+  if constexpr (W == 4) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, K * 0x55, 0xF, 0xF, false);
+  else if constexpr (W == 16) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + K, 0xF, 0xF, false);
+  else return (uint32_t)__shfl((int)v, base + K, kWave);
+}
+
 // The partial sums of phi over the grid points at or after t0 are geometric series:
 // with xs = (first point) dt - t0, the sum over the first k points is
 //   EXP:   e^{-xs/tau2} (1 - e^{-k dt/tau2}) / (1 - e^{-dt/tau2}) / tau2,
@@ -140,22 +164,15 @@ __device__ inline double phi_total(const ModelDev &md, double t0, int glo, int g
 // phi_total for a chain's lane group (t0, glo, ghi the same in all its lanes, every lane
 // active): the two exponentials are one evaluation (the group's first lane e2, its second
 // e12)
+template <int W>
 __device__ inline double phi_total_group(const ModelDev &md, double t0, int glo, int ghi, int lane, int base) {
   const GridPos p = grid_pos(md, t0, glo, ghi);
   const double v = exp(-p.xs * (lane == 0 ? md.inv_tau2 : md.inv_tau12));
   XsExp x;
-  x.e2 = __shfl(v, base, kWave);
-  const double v12 = __shfl(v, base + 1, kWave);
+  x.e2 = group_bcast<W, 0>(v, base);
+  const double v12 = group_bcast<W, 1>(v, base);
   x.e12 = md.kind == FSMP_PHI_EXP ? 0.0 : v12;
   return p.n > 0 ? phi_partial(md, x, p.n) : 0.0;
-}
-
-// v from the lane the DPP control CTRL selects, for a double (its two halves moved alike)
-template <int CTRL>
-__device__ inline double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
 }
 
 // Sum over a group of W lanes (W a power of two, groups aligned to W): a butterfly over lane
@@ -200,10 +217,11 @@ __device__ inline int group_min(int v) {
 // The logs of two values that are the same in every lane of a chain's group, in one
 // evaluation: the group's first lane takes x0, its second x1, and both results go to the
 // whole group (base = the group's first lane; every lane of the group must be active)
+template <int W>
 __device__ inline void group_log2(double x0, double x1, int lane, int base, double &l0, double &l1) {
   const double v = log(lane == 0 ? x0 : x1);
-  l0 = __shfl(v, base, kWave);
-  l1 = __shfl(v, base + 1, kWave);
+  l0 = group_bcast<W, 0>(v, base);
+  l1 = group_bcast<W, 1>(v, base);
 }
 
 // BIEXP part of log phi that depends on t0: log(1 - e^{-(t - t0) / tau_rise})
@@ -245,8 +263,8 @@ __device__ inline int birth_draw(const ModelDev &md, double t0, int glo, int ghi
   {
     // the two exponentials in one evaluation (the group's first lane e2, its second e12)
     const double v = exp(-p.xs * (lane == 0 ? md.inv_tau2 : md.inv_tau12));
-    xe.e2 = __shfl(v, grp * LPC, kWave);
-    const double v12 = __shfl(v, grp * LPC + 1, kWave);
+    xe.e2 = group_bcast<LPC, 0>(v, grp * LPC);
+    const double v12 = group_bcast<LPC, 1>(v, grp * LPC);
     xe.e12 = md.kind == FSMP_PHI_EXP ? 0.0 : v12;
   }
   int64_t k;
@@ -571,7 +589,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
 
   double t0 = a.t0init[w];
   int N = 0;
-  double Phi = (glo <= ghi) ? phi_total_group(md, t0, glo, ghi, lane, gbase) : 0.0;
+  double Phi = (glo <= ghi) ? phi_total_group<LPC>(md, t0, glo, ghi, lane, gbase) : 0.0;
   // Lambda_T changes only with t0 (its log is taken with the jump's own log); S_cur = sum
   // over PEs of the BIEXP rise term at the current t0 and gmin = the smallest PE grid index
   // (phi must stay positive at every PE) make the t0 step one term per PE
@@ -643,13 +661,13 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
       philox4x32_10((uint32_t)step, (uint32_t)(lane & 1), uid0, uid1, a.key0, a.key1, q);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        r[u] = (uint32_t)__shfl((int)q[u], base, kWave);
-        r[4 + u] = (uint32_t)__shfl((int)q[u], base + 1, kWave);
+        r[u] = group_bcast<LPC, 0>(q[u], base);
+        r[4 + u] = group_bcast<LPC, 1>(q[u], base);
       }
       const double lv = log(u01(lane == 0 ? r[0] : lane == 1 ? r[2] : r[6]));
-      lg0 = __shfl(lv, base, kWave);
-      lg2 = __shfl(lv, base + 1, kWave);
-      lg6 = __shfl(lv, base + 2, kWave);
+      lg0 = group_bcast<LPC, 0>(lv, base);
+      lg2 = group_bcast<LPC, 1>(lv, base);
+      lg6 = group_bcast<LPC, 2>(lv, base);
     }
     const double R = sqrt(-2.0 * lg0);
     const double th = 2.0 * M_PI * u01(r[1]);
@@ -665,7 +683,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
       t0acc = (rec.flags & 4) != 0;
       if (rec.t0 != t0) {
         t0 = rec.t0;
-        Phi = (glo <= ghi) ? phi_total_group(md, t0, glo, ghi, lane, gbase) : 0.0;
+        Phi = (glo <= ghi) ? phi_total_group<LPC>(md, t0, glo, ghi, lane, gbase) : 0.0;
         Lam = lam * md.dt * Phi;
         if (biexp) {
           double sn = 0.0;
@@ -694,7 +712,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
           S_new = group_sum<LPC>(S_new);
         }
         const double part = (double)N * (t0p - t0) * md.inv_tau2 + (S_new - S_cur);
-        const double Phip = (glo <= ghi) ? phi_total_group(md, t0p, glo, ghi, lane, gbase) : 0.0;
+        const double Phip = (glo <= ghi) ? phi_total_group<LPC>(md, t0p, glo, ghi, lane, gbase) : 0.0;
         const double la0 = part - (lam * md.dt * Phip - lam * md.dt * Phi);
         if (lg2 < la0) {
           t0 = t0p;
@@ -758,7 +776,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         }
         if (om > 0.0) {
           double lom, lLam;
-          group_log2(om, Lam, lane, gbase, lom, lLam);
+          group_log2<LPC>(om, Lam, lane, gbase, lom, lLam);
           dnu = 0.5 * (-lro - lom + (rm2o - xj * xj / om) * md.inv_s);
           la = dnu - lLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
           valid = true;
@@ -772,8 +790,8 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         if (gnew >= glo && gnew <= ghi) {
           // log phi at the new and at the old position, one evaluation for both
           const double lv = log_phi(md, (double)(lane == 0 ? gnew : zg[j]) * md.dt - t0);
-          lpn = __shfl(lv, gbase, kWave);
-          const double lpo_v = __shfl(lv, gbase + 1, kWave);
+          lpn = group_bcast<LPC, 0>(lv, gbase);
+          const double lpo_v = group_bcast<LPC, 1>(lv, gbase);
           if (lpn > -INFINITY) {
             lpo = lpo_v;
             if constexpr (MCP) {
@@ -815,7 +833,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         if (delta2 > 0.0) {
           up = beta - p;
           double ld2, lLam;
-          group_log2(delta2, Lam, lane, gbase, ld2, lLam);
+          group_log2<LPC>(delta2, Lam, lane, gbase, ld2, lLam);
           dnu = -0.5 * (-lrn + ld2 + (rm2n - up * up / delta2) * md.inv_s);
           la = dnu + lLam - lgn[N + 1] + (N == 0 ? md.logJ : 0.0);
           valid = true;
@@ -831,7 +849,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         up = beta - (p - ej * xj / om);
         if (delta2 > 0.0 && om > 0.0) {
           double lom, ld2;
-          group_log2(om, delta2, lane, gbase, lom, ld2);
+          group_log2<LPC>(om, delta2, lane, gbase, lom, ld2);
           dnu = 0.5 * (-lom - ld2 + (up * up / delta2 - xj * xj / om) * md.inv_s);
           // mixture form: the removed and the added PE carry their own rho and rho mu^2
           if constexpr (MCP) dnu += 0.5 * (lrn - lro + (rm2o - rm2n) * md.inv_s);
@@ -860,7 +878,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
             om = W[(j * LD + j) * HS];
             xj = xv[j];
             double lom, lLam;
-            group_log2(om, Lam, lane, gbase, lom, lLam);
+            group_log2<LPC>(om, Lam, lane, gbase, lom, lLam);
             dnu = 0.5 * (-md.log_rho - lom + (md.rhom2 - xj * xj / om) * md.inv_s);
             la = dnu - lLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
           }
