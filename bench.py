@@ -1,27 +1,33 @@
 """Benchmark of the FSMP hot path on one MI355X.
 
-One step = one pass of the whole path over one batch: fsmp_sample (prologue +
-chain kernels: every chain's Gibbs / RJMCMC sweeps) and fsmp_posterior, over the
-batched workload (100,000 waveforms x 1,024 samples, lambda ~ logU[0.1, 30],
-rise 2 / decay 25 ns light curve, 4 chains x 1,000 sweeps, FP64), with the
-waveforms already resident in device memory when the timed region starts.
+One step = one pass of the whole path over one batch: fsmp_sample (prologue + chain
+kernels: every chain's Gibbs / RJMCMC sweeps) and fsmp_posterior (with P(N = k)), with the
+waveforms already resident in device memory when the timed region starts.  The default
+workload is the largest single-GPU one, the uneven batch: 250,000 windows of 128 / 256 /
+512 / 1,024 / 2,048 samples, lambda ~ logU[0.05, 100] (PE capacities 16-160), rise 2 /
+decay 25 ns light curve, one chain per waveform, FP64, with the kernel design per PE
+capacity (fsmp_autotune) and the sweeps per waveform (fsmp_autotune_steps: 500-4,000 from
+a 200-sweep pilot's batch-means MCSE of N) tuned before the timed region.
 
-Prints one JSON line: waveforms/s (whole job) plus MCMC steps/s, the roofline
-of the dominant kernel (measured with HIP events on its stream inside the timed
-region) and the oracle timed on the host cores over a bounded sample.
+Prints one JSON line: waveforms/s (whole job) and MCMC steps/s; the roofline of the chain
+launch with the longest time in the step (HIP events on its own stream inside the timed
+region); the oracle timed on the host cores over a bounded sample; and as extra keys the
+FP32+refresh form at refresh_M = 16, 64, 256, the batched workload (100,000 x 1,024
+samples, 4 chains x 1,000 sweeps), the serving loop over trigger rates, the Lucy-Richardson
+initialisation stage and the MCP-PMT mixture law.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload batched]
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload uneven|batched|plain|pileup]
 
-Roofline of a chain kernel whose state lives in device memory (one lane per chain, or
-lane groups with G^-1 in device memory): algorithmic bytes = the G^-1 elements the
-sweeps must touch, 8 bytes (4 in the FP32 form) per element read by a K x K mat-vec and
-per element read and written by a rank-one or rank-two edit, summed from the device work
-counters of the launch's chains, over the launch's mean duration, against 8 TB/s.  The
-dominant kernel is the chain launch with the most such bytes.  Lane-group kernels with
-G^-1 in LDS are reported against the FP64 vector peak with the same work counted as
-flops.  `traffic` is the HBM bytes per launch that rocprofv3 counters recorded for that
-kernel (FETCH_SIZE + WRITE_SIZE, scaled by the factor a plain copy of known size gives),
-read from profiles/traffic_<workload>.json while the kernel source is unchanged:
+Roofline: algorithmic bytes = the words of a packed Cholesky factor that the proposals must
+read and the accepted moves must edit (birth K(K+1)/2 + 2K + 3 and K + 3; death
+(K-j)(K-j+1)/2 + 1 and (K-1-j)(K-j) + K(K+1)/2; update both, with the birth on K - 1 PEs;
+K the PE count, j the removed PE's index), 8 bytes a word, counted on the device for every
+chain (fsmp_samples.work), summed over the chains of the launch, over the launch's mean
+duration; against the 8 TB/s HBM peak, and against the LDS stream bandwidth that
+liblds_probe.so measures on the device (the LDS fraction).  `traffic` is the HBM bytes per
+launch that rocprofv3 counters recorded for that kernel (FETCH_SIZE + WRITE_SIZE, scaled by
+the factor a plain copy of known size gives), read from profiles/traffic_<workload>.json
+while the kernel source is unchanged:
 
     rocprofv3 --pmc FETCH_SIZE -d DIR_F -o pmc -- python bench.py --pmc-run
     rocprofv3 --pmc WRITE_SIZE -d DIR_W -o pmc -- python bench.py --pmc-run
@@ -63,15 +69,19 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batched")
+    ap.add_argument("--workload", default="uneven")
     ap.add_argument("--n-wave", type=int, default=0, help="override the workload's waveform count")
-    ap.add_argument("--chain-steps", type=int, default=0, help="override the sweeps per chain")
-    ap.add_argument("--cpu-wave", type=int, default=15000, help="waveforms in the oracle's timed sample")
+    ap.add_argument("--chain-steps", type=int, default=0, help="fixed sweeps per chain (no step autotuning)")
+    ap.add_argument("--target-mcse", type=float, default=0.02,
+                    help="relative batch-means MCSE of N the step autotuner aims at")
+    ap.add_argument("--cpu-wave", type=int, default=1000, help="waveforms in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve", action="store_true", help="only the serving study (rates x precisions)")
-    ap.add_argument("--serve-events", type=int, default=40, help="events per serving run")
-    ap.add_argument("--serve-rates", default="2000", help="comma-separated event rates (Hz)")
+    ap.add_argument("--serve-events", type=int, default=48, help="events per serving run")
+    ap.add_argument("--serve-rates", default="50,100,150,200,300,2000,5000,10000,20000",
+                    help="comma-separated event rates (Hz)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP32, batched, Lucy and MCP legs")
     ap.add_argument("--lucy-iter", type=int, default=2000, help="Lucy-Richardson iterations of the init stage (0: skip)")
     ap.add_argument("--no-mcp", action="store_true", help="skip the MCP-PMT mixture-law leg")
     ap.add_argument("--pmc-run", action="store_true",
@@ -81,6 +91,8 @@ def parse():
     ap.add_argument("--issue-summary", nargs=2, metavar=("SQ_DIR_A", "SQ_DIR_B"),
                     help="summarise two rocprofv3 --pmc runs of SQ counters into profiles/")
     ap.add_argument("--step-ms", type=float, default=0.0, help="concurrent step time for --issue-summary")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "LAST"),
+                    help="per-kernel durations of the last LAST dispatches of a rocprofv3 --kernel-trace run")
     return ap.parse_args()
 
 
@@ -97,9 +109,9 @@ def kernel_label(name):
         base = "chain_group_dm" if m.group(4) == "true" else "chain_group"
         return (base + ("_fp32" if m.group(6) == "true" else "") + ("_mcp" if m.group(7) == "true" else "")
                 + "_k" + m.group(1))
-    m = re.search(r"chain_lane_kernel<(\d+), (double|float)>", name)
+    m = re.search(r"chain_lane_kernel<(\d+)>", name)
     if m:
-        return ("chain_lane_k" if m.group(2) == "double" else "chain_lane_fp32_k") + m.group(1)
+        return "chain_lane_k" + m.group(1)
     for k in ("prologue_kernel", "posterior_kernel"):
         if k in name:
             return k.replace("_kernel", "")
@@ -130,19 +142,25 @@ def pmc_summary(fdir, wdir, workload):
     copy_bytes = COPY_PROBE_MIB * 2 ** 20
 
     def by_kernel(rows):
-        out = {}
-        for (_, name), kib in rows.items():
+        # the last dispatch of each kernel: the counter run's step comes after the set-up
+        # (autotuner trials and pilot) and after the copy probe
+        last = {}
+        for (did, name), kib in rows.items():
             lab = kernel_label(name)
             if lab is None and ("copy" in name.lower() or "elementwise" in name.lower()):
                 lab = "copy"
-            if lab:
-                out.setdefault(lab, []).append(kib * 1024.0)
-        return out
+            if lab and (lab not in last or int(did) > last[lab][0]):
+                last[lab] = (int(did), kib * 1024.0)
+        return {lab: [v] for lab, (_, v) in last.items()}
+
+    def copies(rows):
+        return [kib * 1024.0 for (_, name), kib in rows.items()
+                if kernel_label(name) is None and ("copy" in name.lower() or "elementwise" in name.lower())]
 
     fk, wk = by_kernel(fetch), by_kernel(write)
     # the copy probe is the largest copy-like dispatch: it reads and writes copy_bytes
-    f_scale = copy_bytes / max(fk.get("copy", [copy_bytes]))
-    w_scale = copy_bytes / max(wk.get("copy", [copy_bytes]))
+    f_scale = copy_bytes / max(copies(fetch) or [copy_bytes])
+    w_scale = copy_bytes / max(copies(write) or [copy_bytes])
     kern = {}
     for lab in sorted(set(fk) | set(wk)):
         if lab == "copy":
@@ -164,18 +182,22 @@ def issue_summary(adir, bdir, workload, step_ms):
     import glob
 
     def read(d):
-        agg, dur = {}, {}
+        # the last dispatch of each kernel (the counter run's step, after the set-up)
+        rows = []
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
-            for r in csv.DictReader(open(f)):
-                lab = kernel_label(r["Kernel_Name"])
-                if lab is None:
-                    continue
-                agg.setdefault(lab, {})
-                agg[lab][r["Counter_Name"]] = agg[lab].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
-                dur[(lab, r["Dispatch_Id"])] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
-        t = {}
-        for (lab, _), v in dur.items():
-            t[lab] = t.get(lab, 0.0) + v
+            rows += [r for r in csv.DictReader(open(f)) if kernel_label(r["Kernel_Name"]) is not None]
+        last = {}
+        for r in rows:
+            lab = kernel_label(r["Kernel_Name"])
+            last[lab] = max(last.get(lab, -1), int(r["Dispatch_Id"]))
+        agg, t = {}, {}
+        for r in rows:
+            lab = kernel_label(r["Kernel_Name"])
+            if int(r["Dispatch_Id"]) != last[lab]:
+                continue
+            agg.setdefault(lab, {})
+            agg[lab][r["Counter_Name"]] = agg[lab].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+            t[lab] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
         return agg, t
 
     a, ta = read(adir)
@@ -216,6 +238,30 @@ def issue_summary(adir, bdir, workload, step_ms):
     print("\n".join(lines))
 
 
+def trace_summary(tdir, last, workload):
+    """mean / min / max duration of the last `last` dispatches of every chain, prologue and
+    posterior kernel in a rocprofv3 --kernel-trace run (csv), as markdown"""
+    import csv
+    import glob
+    rows = {}
+    for f in glob.glob(os.path.join(tdir, "**", "*kernel_trace.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            lab = kernel_label(r["Kernel_Name"])
+            if lab is None:
+                continue
+            ms = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
+            rows.setdefault(lab, []).append((int(r["Dispatch_Id"]), ms, r["Kernel_Name"]))
+    lines = [f"| kernel | label | dispatches averaged | average ms | min ms | max ms |", "|---|---|---|---|---|---|"]
+    res = {}
+    for lab in sorted(rows, key=lambda k: -np.mean([m for _, m, _ in sorted(rows[k])[-last:]])):
+        sel = sorted(rows[lab])[-last:]
+        ms = [m for _, m, _ in sel]
+        res[lab] = float(np.mean(ms))
+        lines.append(f"| `{sel[-1][2][:110]}` | {lab} | {len(ms)} | {np.mean(ms):.2f} | {min(ms):.2f} | {max(ms):.2f} |")
+    print("\n".join(lines))
+    return res
+
+
 def recorded_traffic(workload, kernel):
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
@@ -228,7 +274,10 @@ def recorded_traffic(workload, kernel):
 
 def serving_run(fsmp, synth, pool, rate, n_events, precision, seed=0, n_streams=4, max_batch_wave=20000):
     """Poisson arrivals of trigger events (500-2000 channels drawn from a pool of synthetic
-    channels, 1,024 samples each); returns latency percentiles and throughput."""
+    channels, 1,024 samples each) submitted to the serving loop as they arrive; latency
+    percentiles, throughput, and whether the rate is sustained (served at the offered rate
+    without a growing queue: the last third of the events waits at most 1.5x as long as
+    the first third)."""
     wl = synth.PRESETS["serving"]
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, n_events)
@@ -268,11 +317,15 @@ def serving_run(fsmp, synth, pool, rate, n_events, precision, seed=0, n_streams=
     t_end = time.perf_counter() - t0
     srv.close()
     waves = sum(len(e[3]) for e in events)
-    l = np.array(list(lat.values()))
+    l = np.array([lat[e[0]] for e in events])
+    third = max(1, n_events // 3)
+    served = waves / t_end
+    offered = waves / max(arrive[-1], 1e-9)
+    sustained = bool(served >= 0.95 * offered and l[-third:].mean() <= 1.5 * l[:third].mean())
     return {"rate_hz": rate, "events": n_events, "waveforms": waves, "precision": "fp32+refresh" if precision else "fp64",
             "p50_ms": float(np.percentile(l, 50) * 1e3), "p99_ms": float(np.percentile(l, 99) * 1e3),
-            "mean_ms": float(l.mean() * 1e3), "waveforms_per_s": waves / t_end,
-            "offered_waveforms_per_s": waves / max(arrive[-1], 1e-9)}
+            "mean_ms_first_third": float(l[:third].mean() * 1e3), "mean_ms_last_third": float(l[-third:].mean() * 1e3),
+            "waveforms_per_s": served, "offered_waveforms_per_s": offered, "sustained": sustained}
 
 
 def serving_pool(synth, n=20000, seed=5):
@@ -281,16 +334,71 @@ def serving_pool(synth, n=20000, seed=5):
     return {"n": n, "wave": b["wave"], "lam": b["lam"], "kmax": synth.kmax_for(b["lam"])}
 
 
-def algorithmic_flops(work):
-    """FP64 flops of the PE-space linear algebra: 2K^2 per K x K mat-vec, 2K^2 per rank-one
-    edit of the symmetric inverse Gram matrix, 4K^2 per rank-two edit."""
-    return 2.0 * work[:, 0].sum() + 2.0 * work[:, 1].sum() + 4.0 * work[:, 2].sum()
+def serving_study(fsmp, synth, rates, n_events):
+    """both precision forms over the rates; per form the largest sustained rate and the p50 /
+    p99 latency there"""
+    pool = serving_pool(synth)
+    runs, best = [], {}
+    for prec in (fsmp.FSMP_FP64, fsmp.FSMP_FP32_REFRESH):
+        for rate in rates:
+            r = serving_run(fsmp, synth, pool, rate, n_events, prec)
+            print(f"[bench] serving {json.dumps(r)}", file=sys.stderr, flush=True)
+            runs.append(r)
+            if r["sustained"] and r["rate_hz"] > best.get(r["precision"], {}).get("rate_hz", -1):
+                best[r["precision"]] = {k: r[k] for k in ("rate_hz", "p50_ms", "p99_ms", "waveforms_per_s")}
+    return {"runs": runs, "largest_sustained": best}
 
 
-def algorithmic_bytes(work, word):
-    """device-memory bytes of G^-1 the sweeps must move: K^2 elements read per mat-vec,
-    K^2 read and K^2 written per rank-one or rank-two edit"""
-    return word * (work[:, 0].sum() + 2.0 * work[:, 1].sum() + 2.0 * work[:, 2].sum())
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def lds_peak():
+    """LDS stream bandwidth of device 0 in bytes/s (reads, writes) from liblds_probe.so"""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2403_03156_amd", "liblds_probe.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built (python -m paper_2403_03156_amd.build)")
+    L = ctypes.CDLL(path)
+    L.lds_probe.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.lds_probe.restype = ctypes.c_int
+    r, w = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = L.lds_probe(0, 400, ctypes.byref(r), ctypes.byref(w))
+    if rc != 0:
+        raise RuntimeError(f"lds_probe failed (HIP error {rc})")
+    return r.value, w.value
+
+
+def algorithmic_bytes(work):
+    """bytes of a packed FP64 Cholesky factor the proposals must read and the accepted moves
+    must edit (work counters 0 and 1, 8-byte words)"""
+    return 8.0 * (work[:, 0].sum() + work[:, 1].sum())
+
+
+def timed_steps(smp, one_step, n, warm):
+    """warm untimed steps, then n timed ones (synchronised around); ms per step and the mean
+    HIP-event time of every kernel launch"""
+    import torch
+    for _ in range(warm):
+        one_step()
+    torch.cuda.synchronize()
+    smp.set_timing(True)
+    kernel_ms = {}
+    t0 = time.perf_counter()
+    for _ in range(n):
+        one_step()
+        for t in smp.last_timings():  # waits for this step's kernels (events on their streams)
+            kernel_ms.setdefault(t["name"], []).append(t)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    smp.set_timing(False)
+    return (t1 - t0) * 1e3 / n, kernel_ms
 
 
 def main():
@@ -310,18 +418,18 @@ def main():
     if args.issue_summary:
         issue_summary(args.issue_summary[0], args.issue_summary[1], args.workload, args.step_ms)
         return
-
+    if args.trace_summary:
+        trace_summary(args.trace_summary[0], int(args.trace_summary[1]), args.workload)
+        return
     if args.serve:
-        pool = serving_pool(synth)
-        for prec in (fsmp.FSMP_FP64, fsmp.FSMP_FP32_REFRESH):
-            for rate in [float(r) for r in args.serve_rates.split(",")]:
-                r = serving_run(fsmp, synth, pool, rate, args.serve_events, prec)
-                print(json.dumps({"serving": r}), flush=True)
+        res = serving_study(fsmp, synth, [float(r) for r in args.serve_rates.split(",")], args.serve_events)
+        print(json.dumps({"serving": res}), flush=True)
         return
 
     wl = synth.PRESETS[args.workload]
     n_wave = args.n_wave or wl.n_wave
-    n_steps = args.chain_steps or wl.n_steps
+    tuned = wl.name == "uneven" and not args.chain_steps
+    n_steps = 4000 if tuned else (args.chain_steps or wl.n_steps)
     burn = n_steps // 2
     t_gen = time.time()
     b = synth.generate(wl, n_wave=n_wave, seed=wl.seed)
@@ -332,15 +440,32 @@ def main():
 
     dev = torch.device("cuda", 0)
     wave = torch.from_numpy(b["wave"]).to(dev)
-    smp = fsmp.Sampler(ser=wl.ser, phi_kind=wl.phi_kind, tau_rise=wl.tau_rise, tau_decay=wl.tau_decay,
-                       t0_min=wl.t0_min, t0_max=wl.t0_max, sigma_eps=wl.sigma_eps, mu_q=wl.mu_q, sigma_q=wl.sigma_q,
-                       n_steps=n_steps, n_chains=wl.n_chains, burn_in=burn, seed=wl.seed, device=0)
-    out = smp.alloc_samples(n_wave, kz, work=True)
     stream = torch.cuda.current_stream(dev)
 
-    def one_step():
-        smp.sample(wave, b["offsets"], b["lam"], kmax=km, kz=kz, out=out, stream=stream)
-        return smp.posterior(n_wave, out, with_pn=False, stream=stream)
+    def sampler(precision=fsmp.FSMP_FP64, refresh_M=64, chains=wl.n_chains):
+        return fsmp.Sampler(ser=wl.ser, phi_kind=wl.phi_kind, tau_rise=wl.tau_rise, tau_decay=wl.tau_decay,
+                            t0_min=wl.t0_min, t0_max=wl.t0_max, sigma_eps=wl.sigma_eps, mu_q=wl.mu_q,
+                            sigma_q=wl.sigma_q, n_steps=n_steps, n_chains=chains, burn_in=burn, seed=wl.seed,
+                            device=0, precision=precision, refresh_M=refresh_M)
+
+    smp = sampler()
+    steps, designs = None, None
+    if tuned:
+        # set-up, outside the timed region: the kernel design per PE capacity, then the sweeps
+        # per waveform from a pilot run
+        t_tune = time.time()
+        designs = smp.autotune(wave, b["offsets"], b["lam"], kmax=km, trial_steps=30)
+        steps = smp.autotune_steps(wave, b["offsets"], b["lam"], kmax=km, pilot_steps=200,
+                                   target_rel_mcse=args.target_mcse, min_steps=500, max_steps=4000)
+        torch.cuda.synchronize()
+        print(f"[bench] autotuned in {time.time() - t_tune:.1f}s: designs {designs}; sweeps min {steps.min()} "
+              f"median {int(np.median(steps))} mean {steps.mean():.0f} max {steps.max()}", file=sys.stderr, flush=True)
+    chain_sweeps = float(steps.sum()) * wl.n_chains if tuned else float(n_wave) * wl.n_chains * n_steps
+    out = smp.alloc_samples(n_wave, kz, work=True)
+
+    def one_step(s=smp, o=out):
+        s.sample(wave, b["offsets"], b["lam"], kmax=km, kz=kz, out=o, stream=stream, n_steps=steps)
+        return s.posterior(n_wave, o, with_pn=True, stream=stream)
 
     if args.pmc_run:
         # counter run: a plain copy of known size (the scale for FETCH_SIZE / WRITE_SIZE), then
@@ -355,127 +480,30 @@ def main():
         print("[bench] counter run done", file=sys.stderr, flush=True)
         return
 
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    print("[bench] warmup done", file=sys.stderr, flush=True)
-
-    smp.set_timing(True)
-    kernel_ms = {}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        post = one_step()
-        for t in smp.last_timings():  # waits for this step's kernels (events on the same stream)
-            kernel_ms.setdefault(t["name"], []).append(t)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    smp.set_timing(False)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    chain_steps = n_wave * wl.n_chains * n_steps
+    ms_per_step, kernel_ms = timed_steps(smp, one_step, args.steps, args.warmup)
+    print("[bench] timed steps done", file=sys.stderr, flush=True)
     wps = n_wave / (ms_per_step / 1e3)
-    sps = chain_steps / (ms_per_step / 1e3)
+    sps = chain_sweeps / (ms_per_step / 1e3)
 
-    # ---- dominant kernel roofline: the chain launch with the most algorithmic bytes
+    # ---- roofline of the chain launch with the longest time in the step
     work = out["work"].cpu().numpy()
     caps = np.asarray(synth.KCAPS)
     chain_kcap = np.repeat(caps[np.searchsorted(caps, km)], wl.n_chains)
     avg = {name: float(np.mean([t["ms"] for t in ts])) for name, ts in kernel_ms.items()}
-    per = {}
-    for name, ts in kernel_ms.items():
-        if ts[0]["kcap"] > 0:
-            wsel = work[chain_kcap == ts[0]["kcap"]]
-            per[name] = (algorithmic_bytes(wsel, 4.0 if "fp32" in name else 8.0), algorithmic_flops(wsel))
-    dom = max(per, key=lambda k: per[k][0])
-    nbytes, flops = per[dom]
-    if dom.startswith("chain_group_k"):  # G^-1 in LDS: no device-memory state traffic
-        achieved = flops / (avg[dom] / 1e3)
-        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-                    "frac": achieved / PEAK_FP64, "traffic": recorded_traffic(args.workload, dom), "kernel": dom,
-                    "kernel_ms": avg[dom], "flops_per_launch": flops}
-    else:
-        achieved = nbytes / (avg[dom] / 1e3)
-        roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                    "frac": achieved / PEAK_HBM, "traffic": recorded_traffic(args.workload, dom), "kernel": dom,
-                    "kernel_ms": avg[dom], "bytes_per_launch": nbytes}
+    chains_of = {name: ts[0]["kcap"] for name, ts in kernel_ms.items() if ts[0]["kcap"] > 0}
+    dom = max(chains_of, key=lambda k: avg[k])
+    wsel = work[chain_kcap == chains_of[dom]]
+    nbytes = algorithmic_bytes(wsel)
+    achieved = nbytes / (avg[dom] / 1e3)
+    lds_r, lds_w = lds_peak()
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM, "traffic": recorded_traffic(args.workload, dom), "kernel": dom,
+                "kernel_ms": avg[dom], "bytes_per_launch": nbytes,
+                "lds": {"peak_read_measured_GBps": lds_r / 1e9, "peak_write_measured_GBps": lds_w / 1e9,
+                        "frac_of_read_peak": achieved / lds_r,
+                        "peak_nominal_GBps": 256 * 128 * CLOCK_HZ / 1e9},
+                "impl_bytes_per_launch": 8.0 * (wsel[:, 2].sum() + wsel[:, 3].sum())}
     print(f"[bench] kernels (mean ms): {json.dumps(avg)}", file=sys.stderr, flush=True)
-
-    # ---- the initialisation stage: Lucy-Richardson deconvolution of every waveform (fsmp_lucy),
-    # timed with events on the stream it runs on; algorithmic flops = the two sums of each
-    # iteration, 2 (L_w L_V + (L_w + L_V - 1) L_V) per waveform
-    lucy = None
-    if args.lucy_iter > 0:
-        LV = smp.support_samples()
-        smp.lucy(wave, b["offsets"], kmax=km, kz=kz, n_iter=args.lucy_iter, stream=stream)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        lres = smp.lucy(wave, b["offsets"], kmax=km, kz=kz, n_iter=args.lucy_iter, stream=stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        lms = e0.elapsed_time(e1)
-        L = np.diff(b["offsets"]).astype(np.float64)
-        lflops = 2.0 * args.lucy_iter * float((L * LV + (L + LV - 1) * LV).sum())
-        lach = lflops / (lms / 1e3)
-        lucy = {"iterations": args.lucy_iter, "ms": lms, "waveforms_per_s": n_wave / (lms / 1e3),
-                "initial_pes": int(lres["n_pe"].sum()),
-                "roofline": {"bound": "alu", "achieved": lach / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-                             "frac": lach / PEAK_FP64, "traffic": None, "kernel": "lucy_kernel",
-                             "flops_per_launch": lflops}}
-        print(f"[bench] lucy {args.lucy_iter} iterations: {lms:.1f} ms", file=sys.stderr, flush=True)
-
-    # ---- the MCP-PMT charge law (the paper's five-Gaussian table) on the same batch: one
-    # timed step of sample + posterior after a warm-up, HIP events around the step on the stream
-    mcp = None
-    if not args.no_mcp:
-        mix = ([0.041, 0.516, 0.187, 0.195, 0.061], [0.92, 1.98, 3.01, 4.70, 6.79], [0.22, 0.48, 0.80, 1.30, 2.04])
-        msmp = fsmp.Sampler(ser=wl.ser, phi_kind=wl.phi_kind, tau_rise=wl.tau_rise, tau_decay=wl.tau_decay,
-                            t0_min=wl.t0_min, t0_max=wl.t0_max, sigma_eps=wl.sigma_eps, mu_q=wl.mu_q,
-                            sigma_q=wl.sigma_q, n_steps=n_steps, n_chains=wl.n_chains, burn_in=burn, seed=wl.seed,
-                            device=0, mix=mix)
-        mout = msmp.alloc_samples(n_wave, kz)
-        msmp.sample(wave, b["offsets"], b["lam"], kmax=km, kz=kz, out=mout, stream=stream)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        msmp.sample(wave, b["offsets"], b["lam"], kmax=km, kz=kz, out=mout, stream=stream)
-        msmp.posterior(n_wave, mout, with_pn=False, stream=stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        mms = e0.elapsed_time(e1)
-        mcp = {"components": len(mix[0]), "ms_per_step": mms, "waveforms_per_s": n_wave / (mms / 1e3),
-               "mcmc_steps_per_s": chain_steps / (mms / 1e3)}
-        msmp.close()
-        print(f"[bench] mcp mixture law: {mms:.1f} ms per step", file=sys.stderr, flush=True)
-
-    # ---- oracle on a bounded sample of the same workload (first cpu_wave waveforms, same chains)
-    cpu = None
-    if not args.no_cpu:
-        m = min(args.cpu_wave, n_wave)
-        off = b["offsets"][: m + 1]
-        p = oracle.make_params(ser=wl.ser, sigma_eps=wl.sigma_eps, mu_q=wl.mu_q, sigma_q=wl.sigma_q,
-                               phi_kind=wl.phi_kind, tau_rise=wl.tau_rise, tau_decay=wl.tau_decay,
-                               t0_min=wl.t0_min, t0_max=wl.t0_max)
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-        tc = time.perf_counter()
-        o = oracle.run(p, b["wave"][: off[-1]], off, b["lam"][:m], wl.n_chains, n_steps, burn, wl.seed, kz,
-                       kmax=km[:m], n_threads=threads)
-        dt = time.perf_counter() - tc
-        # the sampled chains are the same chains the GPU ran: they must agree exactly
-        same = (out["z"][: m * wl.n_chains].cpu().numpy() == o.z).all(1).mean()
-        cpu = {"value": m / dt, "unit": "waveforms/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {m} of the {n_wave} waveforms, {wl.n_chains} chains x {n_steps} sweeps, "
-                         f"{dt:.1f}s; {same * 100:.2f}% of its chains identical to the GPU's",
-               "steps_per_s": m * wl.n_chains * n_steps / dt}
-        print(f"[bench] oracle {m} waveforms in {dt:.1f}s on {threads} threads", file=sys.stderr, flush=True)
-
-    # ---- serving: continuous batching at 2 kHz trigger rate, FP64 and FP32+refresh forms
-    serving = None
-    if not args.no_serve:
-        pool = serving_pool(synth)
-        serving = [serving_run(fsmp, synth, pool, float(r), args.serve_events, prec)
-                   for prec in (fsmp.FSMP_FP64, fsmp.FSMP_FP32_REFRESH) for r in args.serve_rates.split(",")]
-        print(f"[bench] serving {json.dumps(serving)}", file=sys.stderr, flush=True)
-
     res = {
         "metric": "waveforms/s and MCMC steps/s at matched posterior accuracy; p99 event latency",
         "value": wps,
@@ -489,17 +517,121 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {n_wave} waveforms x {wl.lengths} samples, lambda {wl.lam_dist}"
-                               f"[{wl.lam_lo}, {wl.lam_hi}], {wl.n_chains} chains x {n_steps} sweeps, FP64",
-                   "n_wave": n_wave, "chains": wl.n_chains, "sweeps": n_steps, "parallelism": "single GPU"},
+        "config": {"workload": (f"{wl.name}: {n_wave} waveforms x {wl.lengths} samples, lambda {wl.lam_dist}"
+                                f"[{wl.lam_lo}, {wl.lam_hi}], {wl.n_chains} chain(s) x "
+                                + (f"autotuned {int(steps.min())}-{int(steps.max())} sweeps (mean {steps.mean():.0f})"
+                                   if tuned else f"{n_steps} sweeps") + ", FP64"),
+                   "n_wave": n_wave, "chains": wl.n_chains,
+                   "sweeps_mean": chain_sweeps / (n_wave * wl.n_chains), "parallelism": "single GPU"},
         "mcmc_steps_per_s": sps,
         "kernel_ms": avg,
         "roofline": roofline,
-        "cpu_baseline": cpu,
-        "serving": serving,
-        "init_stage": lucy,
-        "mcp_charge_law": mcp,
     }
+
+    # ---- the FP32+refresh form on the same batch and sweeps: one timed step per refresh_M
+    if not args.no_extra:
+        fp32 = []
+        for M in (16, 64, 256):
+            s32 = sampler(fsmp.FSMP_FP32_REFRESH, M)
+            o32 = s32.alloc_samples(n_wave, kz, work=True)
+            ms32, _ = timed_steps(s32, lambda: one_step(s32, o32), 1, 1)
+            w32 = o32["work"].cpu().numpy()
+            fp32.append({"refresh_M": M, "ms_per_step": ms32, "waveforms_per_s": n_wave / (ms32 / 1e3),
+                         "fp64_reevaluations_per_sweep": float(w32[:, 4].sum() / chain_sweeps)})
+            s32.close()
+            print(f"[bench] fp32 refresh_M={M}: {ms32:.1f} ms", file=sys.stderr, flush=True)
+        res["fp32_refresh"] = fp32
+
+    # ---- the batched workload (100,000 x 1,024 samples, 4 chains x 1,000 sweeps): one timed step
+    if not args.no_extra and wl.name != "batched":
+        bw = synth.PRESETS["batched"]
+        bb = synth.generate(bw, seed=bw.seed)
+        bkm = synth.kmax_for(bb["lam"])
+        bwave = torch.from_numpy(bb["wave"]).to(dev)
+        bs = fsmp.Sampler(ser=bw.ser, phi_kind=bw.phi_kind, tau_rise=bw.tau_rise, tau_decay=bw.tau_decay,
+                          t0_min=bw.t0_min, t0_max=bw.t0_max, sigma_eps=bw.sigma_eps, mu_q=bw.mu_q,
+                          sigma_q=bw.sigma_q, n_steps=bw.n_steps, n_chains=bw.n_chains, burn_in=bw.n_steps // 2,
+                          seed=bw.seed, device=0)
+        bo = bs.alloc_samples(bw.n_wave, int(bkm.max()))
+
+        def bstep():
+            bs.sample(bwave, bb["offsets"], bb["lam"], kmax=bkm, kz=int(bkm.max()), out=bo, stream=stream)
+            return bs.posterior(bw.n_wave, bo, with_pn=True, stream=stream)
+        bms, _ = timed_steps(bs, bstep, 2, 1)
+        res["batched"] = {"workload": "batched: 100000 waveforms x 1024 samples, lambda loguniform[0.1, 30], "
+                                      "4 chains x 1000 sweeps, FP64",
+                          "ms_per_step": bms, "waveforms_per_s": bw.n_wave / (bms / 1e3),
+                          "mcmc_steps_per_s": bw.n_wave * bw.n_chains * bw.n_steps / (bms / 1e3)}
+        bs.close()
+        del bwave
+        print(f"[bench] batched: {bms:.1f} ms per step", file=sys.stderr, flush=True)
+
+    # ---- the initialisation stage: Lucy-Richardson deconvolution of every waveform (fsmp_lucy),
+    # timed with events on the stream it runs on; algorithmic flops = the two sums of each
+    # iteration, 2 (L_w L_V + (L_w + L_V - 1) L_V) per waveform
+    if not args.no_extra and args.lucy_iter > 0:
+        LV = smp.support_samples()
+        smp.lucy(wave, b["offsets"], kmax=km, kz=kz, n_iter=args.lucy_iter, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lres = smp.lucy(wave, b["offsets"], kmax=km, kz=kz, n_iter=args.lucy_iter, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        lms = e0.elapsed_time(e1)
+        L = np.diff(b["offsets"]).astype(np.float64)
+        lflops = 2.0 * args.lucy_iter * float((L * LV + (L + LV - 1) * LV).sum())
+        lach = lflops / (lms / 1e3)
+        res["init_stage"] = {"iterations": args.lucy_iter, "ms": lms, "waveforms_per_s": n_wave / (lms / 1e3),
+                             "initial_pes": int(lres["n_pe"].sum()),
+                             "roofline": {"bound": "alu", "achieved": lach / 1e12, "peak": PEAK_FP64 / 1e12,
+                                          "unit": "TFLOP/s", "frac": lach / PEAK_FP64, "traffic": None,
+                                          "kernel": "lucy_kernel", "flops_per_launch": lflops}}
+        print(f"[bench] lucy {args.lucy_iter} iterations: {lms:.1f} ms", file=sys.stderr, flush=True)
+
+    # ---- the MCP-PMT charge law (the paper's five-Gaussian table) on the same batch and sweeps
+    if not args.no_extra and not args.no_mcp:
+        mix = ([0.041, 0.516, 0.187, 0.195, 0.061], [0.92, 1.98, 3.01, 4.70, 6.79], [0.22, 0.48, 0.80, 1.30, 2.04])
+        msmp = fsmp.Sampler(ser=wl.ser, phi_kind=wl.phi_kind, tau_rise=wl.tau_rise, tau_decay=wl.tau_decay,
+                            t0_min=wl.t0_min, t0_max=wl.t0_max, sigma_eps=wl.sigma_eps, mu_q=wl.mu_q,
+                            sigma_q=wl.sigma_q, n_steps=n_steps, n_chains=wl.n_chains, burn_in=burn, seed=wl.seed,
+                            device=0, mix=mix)
+        mout = msmp.alloc_samples(n_wave, kz)
+        mms, _ = timed_steps(msmp, lambda: one_step(msmp, mout), 1, 1)
+        res["mcp_charge_law"] = {"components": len(mix[0]), "ms_per_step": mms, "waveforms_per_s": n_wave / (mms / 1e3),
+                                 "mcmc_steps_per_s": chain_sweeps / (mms / 1e3)}
+        msmp.close()
+        print(f"[bench] mcp mixture law: {mms:.1f} ms per step", file=sys.stderr, flush=True)
+
+    # ---- oracle on a bounded sample of the same workload (first cpu_wave waveforms, same chains
+    # and sweeps)
+    if not args.no_cpu:
+        m = min(args.cpu_wave, n_wave)
+        off = b["offsets"][: m + 1]
+        p = oracle.make_params(ser=wl.ser, sigma_eps=wl.sigma_eps, mu_q=wl.mu_q, sigma_q=wl.sigma_q,
+                               phi_kind=wl.phi_kind, tau_rise=wl.tau_rise, tau_decay=wl.tau_decay,
+                               t0_min=wl.t0_min, t0_max=wl.t0_max)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        tc = time.perf_counter()
+        o = oracle.run(p, b["wave"][: off[-1]], off, b["lam"][:m], wl.n_chains, n_steps, burn, wl.seed, kz,
+                       kmax=km[:m], n_threads=threads, wsteps=None if steps is None else steps[:m])
+        dt = time.perf_counter() - tc
+        # the sampled chains are the chains the GPU ran: they must agree exactly
+        same = (out["z"][: m * wl.n_chains].cpu().numpy() == o.z).all(1).mean()
+        sweeps = float(steps[:m].sum()) * wl.n_chains if tuned else float(m) * wl.n_chains * n_steps
+        res["cpu_baseline"] = {"value": m / dt, "unit": "waveforms/s", "cores": threads, "kind": "oracle",
+                               "cpu": cpu_model(),
+                               "sample": f"first {m} of the {n_wave} waveforms, {wl.n_chains} chain(s), the same "
+                                         f"sweeps ({sweeps / (m * wl.n_chains):.0f} mean), {dt:.1f}s; "
+                                         f"{same * 100:.2f}% of its chains identical to the GPU's",
+                               "steps_per_s": sweeps / dt}
+        print(f"[bench] oracle {m} waveforms in {dt:.1f}s on {threads} threads", file=sys.stderr, flush=True)
+    else:
+        res["cpu_baseline"] = None
+
+    # ---- serving: continuous batching over trigger rates, FP64 and FP32+refresh forms
+    if not args.no_serve:
+        res["serving"] = serving_study(fsmp, synth, [float(r) for r in args.serve_rates.split(",")],
+                                       args.serve_events)
     print(json.dumps(res))
 
 

@@ -99,8 +99,14 @@ typedef struct {
  * step 1 / grid_sub samples; jump probabilities J, J, 1 - 2J (Sec. 2.4); t0 random-walk
  * step N(0, t0_step_sd^2) and update shift N(0, shift_sd^2) rounded to the grid.
  * Steps [0, burn_in) are not recorded; accumulators use floor(sqrt(n_steps - burn_in))
- * batches for the batch-means MCSE.  precision: FSMP_FP64 (all FP64) or
- * FSMP_FP32_REFRESH (FP32 rank-one updates, FP64 refresh every refresh_M steps). */
+ * batches for the batch-means MCSE.  precision: FSMP_FP64 (all FP64) or FSMP_FP32_REFRESH:
+ * G^-1 stored in FP32 and updated by its rank-one / rank-two edits (computed in FP64,
+ * stored rounded); each proposal's delta-nu is evaluated from it with a two-term residual
+ * correction against the exact FP64 G (App. A, eqs. 11-18: the quantities delta^2, u+, omega
+ * and x_j of the PE-space form), whose last term bounds the error left; the proposal is
+ * re-evaluated from an FP64 rebuild of G^-1 when that bound exceeds 1e-5 max(1, |delta-nu|) or
+ * could turn the accept decision, and G^-1 and the charges are rebuilt in FP64 every
+ * refresh_M sweeps (0: only at those re-evaluations) and at every recorded charge draw. */
 typedef struct {
   double sigma_eps, mu_q, sigma_q;
   int32_t grid_sub;      /* 1..16 */
@@ -183,10 +189,16 @@ typedef struct {
  *   log                   NULL, or [chain][n_steps] fsmp_logrec when FSMP_REC_LOG
  *   trace                 NULL, or [chain][n_rec][3] (N, t0, Q) every `thin` recorded steps
  *                         when FSMP_REC_TRACE, n_rec = ceil((n_steps - burn_in) / thin)
- *   work                  NULL, or [chain][4] work counters over all steps: sum of K^2 over
- *                         proposals evaluated with a K x K mat-vec, sum of K^2 over rank-one
- *                         edits (accepted births and deaths), sum of K^2 over rank-two edits
- *                         (accepted updates), sum of K over t0 proposals inside the prior
+ *   work                  NULL, or [chain][5] work counters over all steps, K the PE count
+ *                         before the move, j the removed or moved PE's index (from 0):
+ *                         [0] the words of a packed Cholesky factor a proposal must read
+ *                             (birth K(K+1)/2 + 2K + 3, death (K-j)(K-j+1)/2 + 1, update both
+ *                             with the birth on K - 1 PEs), [1] the words an accepted move
+ *                             must edit (birth K + 3, death (K-1-j)(K-j) + K(K+1)/2, update
+ *                             both), [2] the G^-1 elements this library's proposals read
+ *                             (K^2 per K x K mat-vec), [3] the G^-1 elements its accepted edits
+ *                             read and write (2 K^2 per edit), [4] FP64 re-evaluations of the
+ *                             FP32 form
  *   rec_steps             NULL, or [chain] the number of recorded sweeps (after burn-in) of
  *                         the chain; required with per-waveform sweep counts, read by
  *                         fsmp_posterior when present
@@ -199,7 +211,7 @@ typedef struct {
  *                         of the list from Philox block 2 + k/2 of that step (Box-Muller of
  *                         words 0 and 1: cosine for even k, sine for odd k); 0 beyond N, NaN
  *                         (with FSMP_ST_FACTOR) if the factorisation fails.  The draw reads
- *                         the maintained G^-1 (FP32 in the precision form).  Costs O(K^3)
+ *                         the maintained G^-1 (its FP64 rebuild in the precision form).  Costs O(K^3)
  *                         per record; FP64 scratch of kcap (kcap + 1) words per chain is allocated
  *                         by fsmp_sample while the flag is set.
  *   occ                   NULL, or the grid occupancy (Sec. 2.2: the PE sequence as a point
@@ -375,13 +387,13 @@ fsmp_status fsmp_set_timing(fsmp_ctx *ctx, int32_t enable);
  * Three implementations of the same chains (identical results up to rounding order):
  * FSMP_DESIGN_GROUP runs one chain per group of lanes with G^{-1} in LDS (PE capacities up
  * to 64); FSMP_DESIGN_LANE runs one chain per lane with G^{-1} interleaved in device
- * memory (every capacity but 48); FSMP_DESIGN_GROUP_DEVMEM runs one chain per (narrower)
+ * memory (capacities 16 and 32); FSMP_DESIGN_GROUP_DEVMEM runs one chain per (narrower)
  * group of lanes with G^{-1} in device memory, interleaved across the chains of a
  * wavefront, and only the vectors in LDS (every capacity, while the SER tables leave room
  * in LDS).  Capacities are 16, 32, 48, 64, 96, 128, 160, 192; a waveform runs in the
  * smallest one >= its kmax.  capacity 0 = every capacity that has the design.
- * FSMP_ENOTSUP if the requested pair does not exist.  The FP32-refresh form always runs
- * the lane design. */
+ * FSMP_ENOTSUP if the requested pair does not exist.  The FP32-refresh form and the mixture
+ * charge law run FSMP_DESIGN_GROUP_DEVMEM only (the FP32 form runs capacity 48 at 64). */
 enum { FSMP_DESIGN_GROUP = 0, FSMP_DESIGN_LANE = 1, FSMP_DESIGN_GROUP_DEVMEM = 2 };
 fsmp_status fsmp_set_design(fsmp_ctx *ctx, int32_t capacity, int32_t design);
 int32_t fsmp_get_design(const fsmp_ctx *ctx, int32_t capacity);
@@ -389,8 +401,8 @@ int32_t fsmp_get_design(const fsmp_ctx *ctx, int32_t capacity);
 /* Autotuner: runs the whole batch for trial_steps sweeps once per design, each capacity
  * in that design where it exists (outputs discarded, HIP-event timings of each capacity's
  * launch), then keeps the fastest design per capacity in the context.
- * Allocates scratch outputs for the trial and synchronises `hip_stream`.  A no-op for the
- * FP32-refresh form, which has the lane design only. */
+ * Allocates scratch outputs for the trial and synchronises `hip_stream`.  The FP32-refresh
+ * form and the mixture law have one design, which it keeps. */
 fsmp_status fsmp_autotune(fsmp_ctx *ctx, const fsmp_batch *batch, int32_t trial_steps, void *hip_stream);
 
 /* Chain-length autotuner: runs the batch once for pilot_steps sweeps (the configured

@@ -111,13 +111,14 @@ def lib():
         L.ora_t0_log_alpha.argtypes = [_P(Params), _d, _i32, _i32, _vp, _i32, _d, _d]
         L.ora_t0_log_alpha.restype = _d
         L.ora_run.argtypes = [_P(Params), _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _u64, _i32,
-                              _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32]
+                              _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32,
+                              _vp]
         L.ora_charge_draw.argtypes = [_P(Params), _vp, _i32, _vp, _i32, _vp, _vp]
         L.ora_charge_draw.restype = ctypes.c_int
         L.ora_charge_normals.argtypes = [_u64, _u64, _i32, _i32, _vp]
         L.ora_charge_normals.restype = None
         L.ora_run.restype = ctypes.c_int
-        L.ora_replay.argtypes = [_P(Params), _vp, _i32, _d, _i32, _i32, _i32, _u64, _u64, _i32, _vp, _vp, _vp, _d]
+        L.ora_replay.argtypes = [_P(Params), _vp, _i32, _d, _i32, _i32, _i32, _u64, _u64, _i32, _vp, _vp, _vp, _d, _i32]
         L.ora_replay.restype = _i64
         _lib = L
     return _lib
@@ -162,6 +163,11 @@ def log_alpha(p, w, lam, glo, ghi, t0, z, move, j, gnew):
     return la, dnu.value
 
 
+def phi_sum(p, t0, glo, ghi):
+    """sum of phi(g dt - t0) over the grid points glo..ghi (closed-form geometric series)"""
+    return lib().ora_phi_sum(ctypes.byref(p), t0, glo, ghi)
+
+
 def t0_log_alpha(p, lam, glo, ghi, z, t0, t0p):
     z = np.ascontiguousarray(z, dtype=np.int32)
     zz = z if len(z) else np.zeros(1, np.int32)
@@ -173,7 +179,7 @@ class RunResult:
 
 
 def run(p: Params, wave, offsets, lam, n_chains, n_steps, burn_in, seed, kz, kmax=None, g_range=None, t0_init=None,
-        wave_id=None, log=False, thin=0, n_threads=0, charges=False, occupancy=False, z_init=None):
+        wave_id=None, log=False, thin=0, n_threads=0, charges=False, occupancy=False, z_init=None, wsteps=None):
     """Run ``n_chains`` chains per waveform; outputs are per chain (index wave*n_chains + chain).
 
     ``thin`` > 0 records (N, t0, Q) every thin-th step after burn-in into ``trace``; with
@@ -181,7 +187,8 @@ def run(p: Params, wave, offsets, lam, n_chains, n_steps, burn_in, seed, kz, kma
     ``occupancy`` gives ``occ``: per waveform the sub * L_i grid points (the waveform's row
     starts at sub * offsets[i]), the number of (chain, recorded sweep) pairs with a PE there,
     PEs counted with multiplicity (``occ_chain`` keeps the per-chain rows).  ``z_init``: None
-    (empty start) or one initial PE list (grid indices) per chain."""
+    (empty start) or one initial PE list (grid indices) per chain.  ``wsteps``: None, or the
+    sweeps of every waveform (at most n_steps), each with burn-in wsteps * burn_in // n_steps."""
     wave = np.ascontiguousarray(wave, dtype=np.float32)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     lam = np.ascontiguousarray(lam, dtype=np.float64)
@@ -191,6 +198,9 @@ def run(p: Params, wave, offsets, lam, n_chains, n_steps, burn_in, seed, kz, kma
     g_range = None if g_range is None else np.ascontiguousarray(g_range, dtype=np.int32).reshape(-1)
     t0_init = None if t0_init is None else np.ascontiguousarray(t0_init, dtype=np.float64)
     wave_id = None if wave_id is None else np.ascontiguousarray(wave_id, dtype=np.uint64)
+    wsteps = None if wsteps is None else np.ascontiguousarray(wsteps, dtype=np.int32)
+    if wsteps is not None and (len(wsteps) != nw or wsteps.min() < 1 or wsteps.max() > n_steps):
+        raise ValueError("wsteps: one count in 1..n_steps per waveform")
     r = RunResult()
     r.N = np.zeros(tot, np.int32)
     r.t0 = np.zeros(tot, np.float64)
@@ -211,7 +221,8 @@ def run(p: Params, wave, offsets, lam, n_chains, n_steps, burn_in, seed, kz, kma
     lib().ora_run(ctypes.byref(p), nw, _ptr(wave), _ptr(offsets), _ptr(lam), _ptr(kmax), _ptr(g_range),
                   _ptr(t0_init), _ptr(wave_id), n_chains, n_steps, burn_in, seed, kz, _ptr(r.N), _ptr(r.t0),
                   _ptr(r.z), _ptr(r.x), _ptr(r.acc), _ptr(r.nhist), _ptr(r.counts), _ptr(r.status), _ptr(r.log),
-                  _ptr(r.trace), thin, _ptr(r.qdraw), _ptr(r.zdraw), _ptr(r.occ_chain), _ptr(zi), _ptr(zo), _ptr(r.e), n_threads)
+                  _ptr(r.trace), thin, _ptr(r.qdraw), _ptr(r.zdraw), _ptr(r.occ_chain), _ptr(zi), _ptr(zo), _ptr(r.e), n_threads,
+                  _ptr(wsteps))
     r.occ = None
     if occupancy:
         # sum the chains' rows of every waveform
@@ -254,8 +265,9 @@ def charge_normals(uid, seed, step, K):
     return xi[:K]
 
 
-def replay(p: Params, w, lam, kmax, glo, ghi, uid, seed, rec, tie_eps=1e-9):
-    """Recompute delta-nu / log-alpha along a recorded log of one chain.
+def replay(p: Params, w, lam, kmax, glo, ghi, uid, seed, rec, tie_eps=1e-9, ext=False):
+    """Recompute delta-nu / log-alpha along a recorded log of one chain.  ext: delta-nu as the
+    difference of two from-scratch nu's in extended precision (long double), else in FP64.
 
     Returns (dnu_ref, la_ref, n_decision_mismatches)."""
     w = np.ascontiguousarray(w, dtype=np.float32)
@@ -264,7 +276,7 @@ def replay(p: Params, w, lam, kmax, glo, ghi, uid, seed, rec, tie_eps=1e-9):
     dnu = np.zeros(n, np.float64)
     la = np.zeros(n, np.float64)
     bad = lib().ora_replay(ctypes.byref(p), _ptr(w), len(w), lam, kmax, glo, ghi, uid, seed, n, _ptr(rec),
-                           _ptr(dnu), _ptr(la), tie_eps)
+                           _ptr(dnu), _ptr(la), tie_eps, 1 if ext else 0)
     return dnu, la, int(bad)
 
 

@@ -536,6 +536,75 @@ double ora_overlap(const ora_params *p, int32_t Lw, int32_t g1, int32_t g2) {
  * with the empty-sequence rule: a birth from N = 0 is multiplied by J and  */
 /* a death to N = 0 divided by J.                                          */
 /* ------------------------------------------------------------------ */
+/* nu(z) from scratch in extended precision (long double: a 64-bit significand on x86-64):
+ * the same overlaps, matched filter and Cholesky as nu_of with every sum and product carried
+ * in long double from the double SER table and the float samples; the reference of the
+ * replay check where nu(z) reaches ~1e6 (pile-up waveforms) and a difference of two FP64 nu's
+ * would carry their rounding.  Single charge law only.  Returns 0, or -1 if G is not positive
+ * definite. */
+static long double overlap_ext(const ora_ctx *c, int32_t g1, int32_t g2) {
+  int32_t a0, a1, b0, b1;
+  col_span(c, g1, &a0, &a1);
+  col_span(c, g2, &b0, &b1);
+  int32_t lo = a0 > b0 ? a0 : b0, hi = a1 < b1 ? a1 : b1;
+  long double s = 0.0L;
+  for (int32_t n = lo; n <= hi; ++n) s += (long double)col(c, g1, n) * (long double)col(c, g2, n);
+  return s;
+}
+
+static long double matched_ext(const ora_ctx *c, int32_t g) {
+  int32_t a0, a1;
+  col_span(c, g, &a0, &a1);
+  long double s = 0.0L;
+  for (int32_t n = a0; n <= a1; ++n) s += (long double)col(c, g, n) * (long double)c->w[n];
+  return s;
+}
+
+static int nu_of_ext(const ora_ctx *c, const int32_t *z, int K, long double *nu) {
+  const ora_params *p = c->p;
+  const long double s = (long double)p->sigma_eps * (long double)p->sigma_eps;
+  const long double rho = s / ((long double)p->sigma_q * (long double)p->sigma_q), m = p->mu_q;
+  if (K == 0) { *nu = 0.0L; return 0; }
+  long double *G = (long double *)malloc(sizeof(long double) * K * K);
+  long double *L = (long double *)calloc((size_t)K * K, sizeof(long double));
+  long double *b = (long double *)malloc(sizeof(long double) * K);
+  long double *u = (long double *)malloc(sizeof(long double) * K);
+  for (int i = 0; i < K; ++i) {
+    for (int k = 0; k <= i; ++k) {
+      long double o = overlap_ext(c, z[i], z[k]);
+      G[i * K + k] = o;
+      G[k * K + i] = o;
+    }
+    G[i * K + i] += rho;
+    b[i] = matched_ext(c, z[i]) + rho * m;
+  }
+  int fail = 0;
+  for (int j = 0; j < K && !fail; ++j) {
+    long double d = G[j * K + j];
+    for (int k = 0; k < j; ++k) d -= L[j * K + k] * L[j * K + k];
+    if (!(d > 0.0L)) { fail = 1; break; }
+    L[j * K + j] = sqrtl(d);
+    for (int i = j + 1; i < K; ++i) {
+      long double v = G[i * K + j];
+      for (int k = 0; k < j; ++k) v -= L[i * K + k] * L[j * K + k];
+      L[i * K + j] = v / L[j * K + j];
+    }
+  }
+  if (!fail) {
+    long double logdet = 0.0L, uu = 0.0L;
+    for (int i = 0; i < K; ++i) {
+      long double v = b[i];
+      for (int k = 0; k < i; ++k) v -= L[i * K + k] * u[k];
+      u[i] = v / L[i * K + i];
+      uu += u[i] * u[i];
+      logdet += 2.0L * logl(L[i * K + i]);
+    }
+    *nu = -0.5L * (-(long double)K * logl(rho) + logdet + ((long double)K * rho * m * m - uu) / s);
+  }
+  free(G); free(L); free(b); free(u);
+  return fail ? -1 : 0;
+}
+
 typedef struct {
   int valid;
   double dnu, log_alpha;
@@ -844,7 +913,8 @@ int ora_run(const ora_params *p, int64_t n_wave, const float *wave, const int64_
             int32_t n_chains, int32_t n_steps, int32_t burn_in, uint64_t seed, int32_t kz, int32_t *N_out,
             double *t0_out, int32_t *z_out, double *x_out, double *acc, int32_t *nhist, int32_t *counts,
             uint32_t *status, ora_logrec *logrec, double *trace, int32_t thin, double *qdraw, int32_t *zdraw,
-            int32_t *occ, const int32_t *z_init, const int64_t *z_init_off, int32_t *e_out, int32_t n_threads) {
+            int32_t *occ, const int32_t *z_init, const int64_t *z_init_off, int32_t *e_out, int32_t n_threads,
+            const int32_t *wsteps) {
   int64_t total = n_wave * n_chains;
   int64_t n_rec = (thin > 0 && n_steps > burn_in) ? (n_steps - burn_in + thin - 1) / thin : 0;
   ora_table tab;
@@ -862,8 +932,11 @@ int ora_run(const ora_params *p, int64_t n_wave, const float *wave, const int64_
     double t0i = t0_init ? t0_init[i] : 0.5 * (p->t0_min + p->t0_max);
     uint64_t wid = wave_id ? wave_id[i] : (uint64_t)i;
     uint64_t uid = wid * (uint64_t)n_chains + (uint64_t)ch;
-    run_one_chain(p, &tab, wave + offsets[i], Lw, lambda[i], kmax ? kmax[i] : kz, glo, ghi, t0i, uid, seed, n_steps,
-                  burn_in, kz, &N_out[ic], &t0_out[ic], z_out + ic * kz, x_out + ic * kz, acc + ic * 12,
+    /* a waveform's own sweep count keeps the configured burn-in fraction, rounded down */
+    int32_t ns = wsteps ? wsteps[i] : n_steps;
+    int32_t bw = wsteps ? (int32_t)((int64_t)ns * burn_in / n_steps) : burn_in;
+    run_one_chain(p, &tab, wave + offsets[i], Lw, lambda[i], kmax ? kmax[i] : kz, glo, ghi, t0i, uid, seed, ns,
+                  bw, kz, &N_out[ic], &t0_out[ic], z_out + ic * kz, x_out + ic * kz, acc + ic * 12,
                   nhist + ic * (kz + 1), counts + ic * 8, &status[ic], logrec ? logrec + ic * n_steps : NULL,
                   trace ? trace + ic * 3 * n_rec : NULL, thin, qdraw ? qdraw + ic * kz * n_rec : NULL,
                   zdraw ? zdraw + ic * kz * n_rec : NULL,
@@ -883,7 +956,7 @@ int ora_run(const ora_params *p, int64_t n_wave, const float *wave, const int64_
  * although |log U - log alpha| > tie_eps. */
 int64_t ora_replay(const ora_params *p, const float *w, int32_t Lw, double lambda0, int32_t kmax, int32_t glo,
                    int32_t ghi, uint64_t uid, uint64_t seed, int32_t n_steps, const ora_logrec *rec, double *dnu_ref,
-                   double *la_ref, double tie_eps) {
+                   double *la_ref, double tie_eps, int32_t ext) {
   ora_table t;
   table_init(&t, p);
   ora_ctx c;
@@ -893,6 +966,7 @@ int64_t ora_replay(const ora_params *p, const float *w, int32_t Lw, double lambd
   double *xb = (double *)calloc((size_t)kmax + 2, sizeof(double));
   int N = 0;
   double nu_cur = 0.0;
+  long double nu_cur_ext = 0.0L, nu_new_ext = 0.0L;
   int64_t bad = 0;
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   for (int32_t step = 0; step < n_steps; ++step) {
@@ -905,6 +979,14 @@ int64_t ora_replay(const ora_params *p, const float *w, int32_t Lw, double lambd
     if ((lr->move == MOVE_DEATH || lr->move == MOVE_UPDATE) && (lr->j < 0 || lr->j >= N)) { bad++; continue; }
     proposal_eval e = eval_proposal(&c, lambda0, glo, ghi, t0, z, NULL, N, nu_cur, lr->move, lr->j, lr->g, 0, zb, NULL, xb);
     if (!e.valid) { bad++; continue; }
+    if (ext) {
+      /* the proposed list as eval_proposal formed it, nu in extended precision */
+      const int Kn = lr->move == MOVE_BIRTH ? N + 1 : lr->move == MOVE_DEATH ? N - 1 : N;
+      if (nu_of_ext(&c, zb, Kn, &nu_new_ext)) { bad++; continue; }
+      const double d = (double)(nu_new_ext - nu_cur_ext);
+      e.log_alpha += d - e.dnu;
+      e.dnu = d;
+    }
     dnu_ref[step] = e.dnu;
     la_ref[step] = e.log_alpha;
     uint32_t r[4];
@@ -925,6 +1007,7 @@ int64_t ora_replay(const ora_params *p, const float *w, int32_t Lw, double lambd
         z[lr->j] = lr->g;
       }
       nu_cur = e.nu_new;
+      nu_cur_ext = nu_new_ext;
     }
   }
   free(z); free(zb); free(xb);

@@ -205,25 +205,26 @@ fsmp_status fail(fsmp_ctx *c, fsmp_status s, const char *fmt, ...) {
 
 bool finite(double v) { return std::isfinite(v); }
 
-// whether a kernel design exists for a PE capacity under this model (LDS footprint) and
-// precision (the FP32 form has no lane groups with G^-1 in LDS and no capacity 48)
-// (the mixture charge law runs only in the lane groups with G^-1 in device memory)
+// whether a kernel design exists for a PE capacity under this model (LDS footprint),
+// precision and charge law: the FP32 form and the mixture law run only in the lane groups
+// with G^-1 in device memory (the FP32 form without capacity 48, which it runs at 64); one
+// lane per chain exists at capacities 16 and 32 (FP64)
 bool design_available(const fsmp_ctx *c, int kcap, int design) {
   const bool fp32 = c->cfg.precision == FSMP_FP32_REFRESH;
   const bool mcp = c->cfg.n_mix > 0;
   switch (design) {
     case FSMP_DESIGN_GROUP: return !fp32 && !mcp && chain_kcap_supported(kcap, c->tab.M, c->cfg.grid_sub);
-    case FSMP_DESIGN_LANE: return kcap != 48 && !mcp;
+    case FSMP_DESIGN_LANE: return !fp32 && !mcp && (kcap == 16 || kcap == 32);
     case FSMP_DESIGN_GROUP_DEVMEM: return chain_dm_supported(kcap, c->tab.M, c->cfg.grid_sub, fp32, mcp);
     default: return false;
   }
 }
 
-// the design a bucket runs in: the context's choice where it exists, else one lane per chain
-// (lane groups with G^-1 in device memory under the mixture law)
+// the design a bucket runs in: the context's choice where it exists, else the lane groups
+// with G^-1 in device memory
 int effective_design(const fsmp_ctx *c, int kcap, int design) {
   if (design_available(c, kcap, design)) return design;
-  return c->cfg.n_mix > 0 ? FSMP_DESIGN_GROUP_DEVMEM : FSMP_DESIGN_LANE;
+  return FSMP_DESIGN_GROUP_DEVMEM;
 }
 
 fsmp_status validate_model(const fsmp_ser *ser, const fsmp_intensity *phi, const fsmp_config *cfg, std::string &m) {
@@ -407,10 +408,7 @@ fsmp_status fsmp_create(fsmp_ctx **out, const fsmp_ser *ser, const fsmp_intensit
   }
   fill_model(c);
   for (int q = 0; q < kNumCaps; ++q)
-    if (!design_available(c, kCaps[q], c->design[q]))
-      c->design[q] = design_available(c, kCaps[q], FSMP_DESIGN_GROUP_DEVMEM) ? FSMP_DESIGN_GROUP_DEVMEM
-                     : kCaps[q] != 48                                         ? FSMP_DESIGN_LANE
-                                                                              : FSMP_DESIGN_GROUP;
+    if (!design_available(c, kCaps[q], c->design[q])) c->design[q] = FSMP_DESIGN_GROUP_DEVMEM;
   if (const char *d = std::getenv("FSMP_CHAIN_DESIGN")) {
     // tuning override: one letter per capacity in kCaps order, g (lane group, H in LDS),
     // l (lane), d (lane group, H in device memory); a design that does not exist for a
@@ -514,7 +512,7 @@ size_t fsmp_workspace_bytes(const fsmp_ctx *c, const fsmp_batch *b) {
     if (!cnt[q]) continue;
     const int dz = effective_design(c, kCaps[q], c->design[q]);
     if (dz == FSMP_DESIGN_LANE)
-      bytes += lane_ws_doubles(kCaps[q], cnt[q], fp32) * 8 + lane_ws_ints(kCaps[q], cnt[q]) * 4;
+      bytes += lane_ws_doubles(kCaps[q], cnt[q]) * 8 + lane_ws_ints(kCaps[q], cnt[q]) * 4;
     else if (dz == FSMP_DESIGN_GROUP_DEVMEM)
       bytes += group_dm_ws_doubles(kCaps[q], cnt[q], fp32) * 8;
     if (cf.record_flags & FSMP_REC_CHARGE) bytes += (size_t)((cnt[q] + 63) / 64 * 64) * kCaps[q] * (kCaps[q] + 1) * 8;
@@ -664,7 +662,7 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     return fail(c, FSMP_ENOTSUP, "kmax above %d is not provided by this build", kCaps[kNumCaps - 1]);
   if (n * (int64_t)cf.n_chains > INT32_MAX) return fail(c, FSMP_EINVAL, "too many chains");
   for (int bi = 0; bi < kNumCaps; ++bi)
-    if (bucket_start[bi + 1] > bucket_start[bi] && !fp32 && !design_available(c, caps[bi], design_of(bi)))
+    if (bucket_start[bi + 1] > bucket_start[bi] && !design_available(c, caps[bi], design_of(bi)))
       return fail(c, FSMP_ENOTSUP, "SER support %d too long for the design of PE capacity %d", c->tab.LV, caps[bi]);
   if (n == 0) {
     c->timings.clear();
@@ -696,7 +694,7 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     for (int bi = 0; bi < kNumCaps; ++bi) {
       const int64_t cnt = bucket_start[bi + 1] - bucket_start[bi];
       const int dz = design_of(bi);
-      const size_t dd = dz == FSMP_DESIGN_LANE ? lane_ws_doubles(caps[bi], cnt, fp32)
+      const size_t dd = dz == FSMP_DESIGN_LANE ? lane_ws_doubles(caps[bi], cnt)
                         : dz == FSMP_DESIGN_GROUP_DEVMEM ? group_dm_ws_doubles(caps[bi], cnt, fp32)
                                                          : 0;
       lane_doff[bi + 1] = lane_doff[bi] + dd;
@@ -858,7 +856,6 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   ca.zinit = (b->z_init_offsets && n > 0) ? c->zinit.p : nullptr;
   ca.zinit_off = (b->z_init_offsets && n > 0) ? c->zinit_off.p : nullptr;
   ca.refresh_M = cf.refresh_M;
-  ca.near_eps = 1e-3;
   ca.drift_bound = 1e-3;
   int n_buckets = 0;
   for (int bi = 0; bi < kNumCaps; ++bi) n_buckets += bucket_start[bi + 1] > bucket_start[bi];
@@ -926,7 +923,7 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     ca.dscr = ca.qdraw ? c->draw_scr.p + draw_off[bi] : nullptr;
     e = timed(name, caps[bi], ks, [&](fsmp_timing &t) {
       t.chains = cnt;
-      return dz == FSMP_DESIGN_LANE    ? launch_chain_lane(caps[bi], fp32, ca, ks, &t.lanes, &t.blocks)
+      return dz == FSMP_DESIGN_LANE    ? launch_chain_lane(caps[bi], ca, ks, &t.lanes, &t.blocks)
              : dz == FSMP_DESIGN_GROUP ? launch_chain(caps[bi], ca, ks, &t.lanes, &t.blocks)
                                        : launch_chain_dm(caps[bi], fp32, ca, ks, &t.lanes, &t.blocks);
     });

@@ -65,15 +65,15 @@ struct ChainArgs {
   double *trace;
   int32_t kz;
   const uint32_t *wflags;  // per waveform, from the prologue (FSMP_ST_NONFINITE)
-  double *work;            // optional [chain][4]
+  double *work;            // optional [chain][5]
   // lane-per-chain kernels: chain state in device memory, interleaved in tiles of
   // 64 chains (element e of the chain in lane l of tile t at (t * E + e) * 64 + l)
   double *dws;
   int32_t *iws;
-  // precision form (FP32 storage of G^{-1}): FP64 refresh every refresh_M sweeps, FP64
-  // re-decision when |log U - log alpha| < near_eps * max(1, |delta-nu|), drift flag bound
+  // precision form (FP32 storage of G^{-1}): FP64 refresh every refresh_M sweeps, drift
+  // flag bound
   int32_t refresh_M;
-  double near_eps, drift_bound;
+  double drift_bound;
   // charge draws at recorded steps (optional): outputs [chain][n_rec][kz] and FP64
   // scratch of KCAP (KCAP + 1) words per chain (per-chain rows for the lane-group kernels,
   // interleaved in tiles of 64 for the lane kernels)
@@ -165,10 +165,10 @@ hipError_t launch_prologue(const PrologueArgs &a, hipStream_t st);
 hipError_t launch_posterior(const PosteriorArgs &a, hipStream_t st);
 // lane-group instances for kcap in {16, 32, 48, 64}; fills lanes per chain and blocks
 hipError_t launch_chain(int kcap, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks);
-// lane-per-chain variant; dws / iws must hold lane_ws_doubles / lane_ws_ints(kcap, n_list)
-hipError_t launch_chain_lane(int kcap, bool fp32, const ChainArgs &a, hipStream_t st, int32_t *lanes,
-                             int64_t *blocks);
-size_t lane_ws_doubles(int kcap, int64_t n_list, bool fp32);
+// lane-per-chain variant (FP64, capacities 16 and 32); dws / iws must hold lane_ws_doubles /
+// lane_ws_ints(kcap, n_list)
+hipError_t launch_chain_lane(int kcap, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks);
+size_t lane_ws_doubles(int kcap, int64_t n_list);
 size_t lane_ws_ints(int kcap, int64_t n_list);
 // PE capacities of the chain kernels; a waveform runs in the smallest one >= its kmax
 constexpr int kNumCaps = 8;

@@ -34,6 +34,9 @@ namespace fsmp {
 namespace {
 
 constexpr int kWave = 64;
+// FP32 form: the largest error bound, relative to max(1, |delta-nu|), with which a
+// proposal is decided from the corrected FP32 evaluation (above it: the FP64 rebuild)
+constexpr double kF32Tol = 1e-5;
 
 // Intra-wavefront ordering of LDS traffic between lanes: the LDS executes one
 // wavefront's instructions in order; the fences keep the compiler from moving
@@ -388,20 +391,22 @@ __global__ void __launch_bounds__(256) prologue_kernel(PrologueArgs a) {
 }
 
 // ------------------------------------------------------------------ chains
-// LDS block of one chain: H (unless it lives in device memory), x, two scratch vectors,
-// the accumulators (kAcc doubles: 12 sums, 3 open batch sums, 4 work counters, one spare,
-// then 8 int proposal / accept counts and the current run of N: value, first step), then
-// the int grid indices.  The accumulators live in LDS,
-// updated by the group's first lane, to keep registers free; the N histogram is kept in
-// the output row by run lengths.
+// LDS block of one chain: H (unless it lives in device memory), x, two scratch vectors (six
+// and b in the FP32 form), the accumulators (kAcc doubles: 12 sums, 3 open batch sums, 5 work
+// counters, then 8 int proposal / accept counts and the current run of N: value, first
+// step), then the int grid indices.  The accumulators live in LDS, updated by the group's
+// first lane, to keep registers free; the N histogram is kept in the output row by run
+// lengths.
 template <int KCAP, bool HG, bool F32 = false, bool MCP = false>
 struct ChainLayout {
   static constexpr int LD = KCAP;
   static constexpr int kAcc = 25;
-  // the FP32 form also keeps b (matched filter + rho mu_q per PE) for its FP64 refresh; the
-  // mixture form the PEs' components after their grid indices
+  // the FP32 form keeps b (matched filter + rho mu_q per PE) for its residuals and refresh,
+  // and the vectors of its corrected proposals; the mixture form the PEs' components after
+  // their grid indices
+  static constexpr int kVec = F32 ? 8 : 3;
   static constexpr int kDoubles =
-      (HG ? 0 : KCAP * KCAP) + (F32 ? 4 : 3) * KCAP + kAcc + (KCAP + 1) / 2 + (MCP ? (KCAP + 1) / 2 : 0);
+      (HG ? 0 : KCAP * KCAP) + kVec * KCAP + kAcc + (KCAP + 1) / 2 + (MCP ? (KCAP + 1) / 2 : 0);
 };
 
 // Column i of H owned by one lane: element (k, i) at H[(k * LD + i) * HS] (HS = 1 in LDS;
@@ -443,6 +448,33 @@ __device__ inline void grp_col_update(MT *H, int i, int N, double ai, const doub
       const double v = TWO ? h[u] + (ai * av[u] * cA + bi * bw[u] * cB) : h[u] + ai * av[u] * cA;
       if (k0 + u < N) H[((k0 + u) * LD + i) * HS] = (MT)v;
     }
+  }
+}
+
+// Residuals against the exact Gram matrix G = A^T A + rho I of the PE list zg[0..N), its
+// entries taken from the SER overlap tables, for the rows i owned by this lane of the group:
+//   o1 = t1 - G v1 (t1 the unit vector at u1 when null),  o2 = t2 - G v2.
+// Row `skip` (-1: none) is left out: its outputs are 0, and v1, v2 must be 0 there, so that
+// the products are those of G without row and column `skip`.  Terms in column order.
+template <int LPC>
+__device__ inline void gram_resid2(const ModelDev &md, const double *vt, const double *ov, int Lw, const int *zg, int N,
+                                   int skip, int lane, const double *t1, int u1, const double *v1, const double *t2,
+                                   const double *v2, double *o1, double *o2) {
+  for (int i = lane; i < N; i += LPC) {
+    if (i == skip) {
+      o1[i] = 0.0;
+      o2[i] = 0.0;
+      continue;
+    }
+    const int gi = zg[i];
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < N; ++k) {
+      const double g = overlap(md, vt, ov, gi, zg[k], Lw) + (k == i ? md.rho : 0.0);
+      a += g * v1[k];
+      b += g * v2[k];
+    }
+    o1[i] = (t1 ? t1[i] : (i == u1 ? 1.0 : 0.0)) - a;
+    o2[i] = t2[i] - b;
   }
 }
 
@@ -551,8 +583,13 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
   double *xv = HG ? cb : cb + KCAP * LD;
   double *s1 = xv + KCAP;
   double *s2 = s1 + KCAP;
-  double *bv = F32 ? s2 + KCAP : nullptr;  // b of each PE (FP32 form)
-  double *acc = s2 + KCAP + (F32 ? KCAP : 0);  // [0..11] sums, [12..14] open batch sums, [15..18] work counters
+  // FP32 form: four more scratch vectors and b of each PE
+  double *s3 = F32 ? s2 + KCAP : nullptr;
+  double *s4 = F32 ? s3 + KCAP : nullptr;
+  double *s5 = F32 ? s4 + KCAP : nullptr;
+  double *s6 = F32 ? s5 + KCAP : nullptr;
+  double *bv = F32 ? s6 + KCAP : nullptr;
+  double *acc = xv + CL::kVec * KCAP;  // [0..11] sums, [12..14] open batch sums, [15..19] work counters
   int *cnt = (int *)(acc + 20);
   int *run = cnt + 8;  // N of the current run among the recorded steps (-1: none yet), its first step
   int *zg = (int *)(acc + CL::kAcc);
@@ -692,7 +729,6 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         }
       }
     } else if (t0p >= md.t0_min && t0p <= md.t0_max) {
-      if (lane == 0) acc[18] += N;
       const double xmin = (N > 0) ? (double)gmin * md.dt - t0p : 1.0;
       if (biexp ? (xmin > 0.0) : (xmin >= 0.0)) {
         double S_new = 0.0;
@@ -736,7 +772,9 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
     // written once so that it executes them once: the proposal evaluation shared by
     // births and time shifts, and one rank-two edit for every accepted move.
     int j = -1, gnew = -1, sh = 0;
-    bool valid = false, need_mv = false;
+    // need_mv: a birth part (births, shifts); need_dp: in the FP32 form, a death part
+    // (deaths, shifts) evaluated with the residual correction
+    bool valid = false, need_mv = false, need_dp = false;
     double dnu = 0.0, la = -INFINITY, lpn = 0.0, lpo = 0.0;
     double delta2 = 1.0, up = 0.0, om = 1.0, xj = 0.0, ej = 0.0, beta = 0.0;
     // mixture form: the component of a born or updated PE from word r7 (inverse CDF of the
@@ -768,20 +806,24 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         j = -1;  // replay: not a recorded valid proposal
       } else if (move == 2) {
         if (lane == 0) cnt[4]++;
-        om = H[(j * LD + j) * HS];
-        xj = xv[j];
-        if constexpr (MCP) {
-          lro = md.mix_lrho[ek[j]];
-          rm2o = md.mix_rhom2[ek[j]];
-        }
-        if (om > 0.0) {
-          double lom, lLam;
-          group_log2<LPC>(om, Lam, lane, gbase, lom, lLam);
-          dnu = 0.5 * (-lro - lom + (rm2o - xj * xj / om) * md.inv_s);
-          la = dnu - lLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
-          valid = true;
+        if constexpr (F32) {
+          need_dp = true;
         } else {
-          st |= FSMP_ST_FACTOR;
+          om = H[(j * LD + j) * HS];
+          xj = xv[j];
+          if constexpr (MCP) {
+            lro = md.mix_lrho[ek[j]];
+            rm2o = md.mix_rhom2[ek[j]];
+          }
+          if (om > 0.0) {
+            double lom, lLam;
+            group_log2<LPC>(om, Lam, lane, gbase, lom, lLam);
+            dnu = 0.5 * (-lro - lom + (rm2o - xj * xj / om) * md.inv_s);
+            la = dnu - lLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
+            valid = true;
+          } else {
+            st |= FSMP_ST_FACTOR;
+          }
         }
       } else {
         if (lane == 0) cnt[6]++;
@@ -804,6 +846,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
               la = lpn - lpo;
             } else {
               need_mv = true;
+              need_dp = F32;
             }
           }
         }
@@ -860,32 +903,220 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         }
       }
     };
-    if (need_mv) {
-      if (lane == 0) acc[15] += (double)N * N;
-      eval_mv(H);
-    }
-
-    // precision form, a decision near the threshold: refresh in FP64 and decide with the
-    // FP64 delta-nu of the same proposal
-    const double logu = lg6;
-    if constexpr (F32) {
-      if (valid && fabs(logu - la) < a.near_eps * fmax(1.0, fabs(dnu))) {
-        double drift;
-        if (N > 0 && grp_refresh<LPC, LD, HS>(md, vt, ov, Lw, W, H, xv, bv, s1, s2, zg, N, lane, drift)) {
-          if (need_mv) {
-            eval_mv(W);
-          } else if (move == 2) {
-            om = W[(j * LD + j) * HS];
-            xj = xv[j];
-            double lom, lLam;
-            group_log2<LPC>(om, Lam, lane, gbase, lom, lLam);
-            dnu = 0.5 * (-md.log_rho - lom + (md.rhom2 - xj * xj / om) * md.inv_s);
-            la = dnu - lLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
-          }
-        } else if (N > 0) {
-          st |= FSMP_ST_FACTOR;
+    // The FP32 form evaluates a proposal from its FP32 H with a two-term correction against
+    // the exact G, whose entries come from the overlap tables:
+    //   death part (deaths, shifts): h = row j of H, r = e_j - G h, s = b - G x, then
+    //     omega = h_j + h^T r + r^T H r,  x_j = x_j + h^T s + (H r)^T s,  u = h + H r
+    //     (u: G^-1 e_j to second order);
+    //   birth part (births; shifts on the PEs without j, through the inverse of G without row
+    //     and column j, Hj = H - u u^T / omega): gamma, eta = Hj gamma, x~ = x (birth) or
+    //     x - u x_j / omega (shift), r = gamma - G eta, s = b - G x~, then
+    //     q = gamma^T eta + eta^T r + r^T Hj r,  p = gamma^T x~ + eta^T s + (Hj r)^T s,
+    //     v = eta + Hj r;
+    // delta^2 = d - q, u+ = beta - p.  The first correction term cancels the first-order error
+    // of the FP32 inverse exactly; the size of the second bounds what is left (the error
+    // contracts by the factor |I - H G| per term).  bnd is that bound carried into delta-nu
+    // to first order, times four.  Vectors: u in s1, v (or eta) in s3.
+    double bnd = 0.0;
+    bool inexact = false;
+    auto f32_dnu = [&](double Bom, double Bxj, double Bq, double Bp) {
+      const double s = md.s;
+      if (move == 1) {
+        double ld2, lLam;
+        group_log2<LPC>(delta2, Lam, lane, gbase, ld2, lLam);
+        dnu = -0.5 * (-md.log_rho + ld2 + (md.rhom2 - up * up / delta2) * md.inv_s);
+        la = dnu + lLam - lgn[N + 1] + (N == 0 ? md.logJ : 0.0);
+      } else if (move == 2) {
+        double lom, lLam;
+        group_log2<LPC>(om, Lam, lane, gbase, lom, lLam);
+        dnu = 0.5 * (-md.log_rho - lom + (md.rhom2 - xj * xj / om) * md.inv_s);
+        la = dnu - lLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
+      } else {
+        double lom, ld2;
+        group_log2<LPC>(om, delta2, lane, gbase, lom, ld2);
+        dnu = 0.5 * (-lom - ld2 + (up * up / delta2 - xj * xj / om) * md.inv_s);
+        la = dnu + lpn - lpo;
+      }
+      double b = 0.0;
+      if (move != 2) b += 0.5 * fabs(1.0 / delta2 + up * up / (delta2 * delta2 * s)) * Bq + fabs(up) / (delta2 * s) * Bp;
+      if (move != 1) b += 0.5 * fabs(1.0 / om - xj * xj / (om * om * s)) * Bom + fabs(xj) / (om * s) * Bxj;
+      bnd = 4.0 * b;
+      valid = true;
+    };
+    auto f32_eval = [&]() {
+      valid = false;
+      double Bom = 0.0, Bxj = 0.0, Bq = 0.0, Bp = 0.0;
+      if (need_dp) {
+        for (int i = lane; i < N; i += LPC) s1[i] = (double)H[(j * LD + i) * HS];
+        WAVE_SYNC();
+        gram_resid2<LPC>(md, vt, ov, Lw, zg, N, -1, lane, nullptr, j, s1, bv, xv, s3, s4);
+        WAVE_SYNC();
+        double a1 = 0.0, a2 = 0.0, c1 = 0.0, c2 = 0.0;
+        for (int i = lane; i < N; i += LPC) {
+          const double hr = grp_col_dot<LD, HS>(H, s3, i, N);
+          a1 += s1[i] * s3[i];
+          a2 += s1[i] * s4[i];
+          c1 += s3[i] * hr;
+          c2 += hr * s4[i];
+          s5[i] = hr;
+        }
+        a1 = group_sum<LPC>(a1);
+        a2 = group_sum<LPC>(a2);
+        c1 = group_sum<LPC>(c1);
+        c2 = group_sum<LPC>(c2);
+        WAVE_SYNC();
+        om = s1[j] + a1 + c1;
+        xj = xv[j] + a2 + c2;
+        Bom = fabs(c1);
+        Bxj = fabs(c2);
+        WAVE_SYNC();
+        for (int i = lane; i < N; i += LPC) s1[i] += s5[i];
+        WAVE_SYNC();
+        if (!(om > 0.0) || !(Bom < 0.1 * om)) {
+          inexact = true;
+          return;
         }
       }
+      if (need_mv) {
+        const int jz = move == 3 ? j : -1;
+        for (int i = lane; i < N; i += LPC) s2[i] = (i == jz) ? 0.0 : overlap(md, vt, ov, gnew, zg[i], Lw);
+        const double d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
+        beta = mf[gnew - glo] + md.rhom;
+        WAVE_SYNC();
+        double gg = 0.0;
+        for (int i = lane; i < N; i += LPC) {
+          s3[i] = grp_col_dot<LD, HS>(H, s2, i, N);
+          gg += s1[i] * s2[i];
+        }
+        const double *xt = xv;
+        if (move == 3) {
+          gg = group_sum<LPC>(gg);
+          const double cg = gg / om, cx = xj / om;
+          for (int i = lane; i < N; i += LPC) {
+            s3[i] = (i == j) ? 0.0 : s3[i] - s1[i] * cg;
+            s4[i] = (i == j) ? 0.0 : xv[i] - s1[i] * cx;
+          }
+          xt = s4;
+        }
+        WAVE_SYNC();
+        gram_resid2<LPC>(md, vt, ov, Lw, zg, N, jz, lane, s2, -1, s3, bv, xt, s5, s6);
+        WAVE_SYNC();
+        double qa = 0.0, pa = 0.0, qb = 0.0, pb = 0.0, gr = 0.0;
+        for (int i = lane; i < N; i += LPC) {
+          qa += s2[i] * s3[i];
+          pa += s2[i] * xt[i];
+          qb += s3[i] * s5[i];
+          pb += s3[i] * s6[i];
+          gr += s1[i] * s5[i];
+        }
+        qa = group_sum<LPC>(qa);
+        pa = group_sum<LPC>(pa);
+        qb = group_sum<LPC>(qb);
+        pb = group_sum<LPC>(pb);
+        if (move == 3) gr = group_sum<LPC>(gr);
+        WAVE_SYNC();
+        const double cr = move == 3 ? gr / om : 0.0;
+        double qc = 0.0, pc = 0.0;
+        for (int i = lane; i < N; i += LPC) {
+          double t = grp_col_dot<LD, HS>(H, s5, i, N);
+          if (move == 3) t = (i == j) ? 0.0 : t - s1[i] * cr;
+          qc += s5[i] * t;
+          pc += t * s6[i];
+          s2[i] = t;
+        }
+        qc = group_sum<LPC>(qc);
+        pc = group_sum<LPC>(pc);
+        for (int i = lane; i < N; i += LPC) s3[i] += s2[i];
+        WAVE_SYNC();
+        Bq = fabs(qc);
+        Bp = fabs(pc);
+        delta2 = d - (qa + qb + qc);
+        up = beta - (pa + pb + pc);
+        if (!(delta2 > 0.0) || !(Bq < 0.1 * delta2)) {
+          inexact = true;
+          return;
+        }
+      }
+      f32_dnu(Bom, Bxj, Bq, Bp);
+    };
+    // the same proposal from the FP64 rebuild W (exact to FP64 rounding), vectors as above
+    auto f64_eval_W = [&]() {
+      valid = false;
+      if (need_dp) {
+        for (int i = lane; i < N; i += LPC) s1[i] = W[(j * LD + i) * HS];
+        WAVE_SYNC();
+        om = s1[j];
+        xj = xv[j];
+      }
+      if (need_mv) {
+        const int jz = move == 3 ? j : -1;
+        for (int i = lane; i < N; i += LPC) s2[i] = (i == jz) ? 0.0 : overlap(md, vt, ov, gnew, zg[i], Lw);
+        const double d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
+        beta = mf[gnew - glo] + md.rhom;
+        WAVE_SYNC();
+        double q = 0.0, p = 0.0;
+        for (int i = lane; i < N; i += LPC) {
+          const double e = grp_col_dot<LD, HS>(W, s2, i, N);
+          s3[i] = e;
+          q += s2[i] * e;
+          p += s2[i] * xv[i];
+        }
+        q = group_sum<LPC>(q);
+        p = group_sum<LPC>(p);
+        if (move == 3) {
+          WAVE_SYNC();
+          const double e = s3[j];
+          q -= e * e / om;
+          p -= e * xj / om;
+          WAVE_SYNC();
+          for (int i = lane; i < N; i += LPC) s3[i] = (i == j) ? 0.0 : s3[i] - s1[i] * e / om;
+          WAVE_SYNC();
+        }
+        delta2 = d - q;
+        up = beta - p;
+      }
+      if ((move != 1 && !(om > 0.0)) || (move != 2 && !(delta2 > 0.0))) {
+        st |= FSMP_ST_FACTOR;
+        return;
+      }
+      f32_dnu(0.0, 0.0, 0.0, 0.0);
+      bnd = 0.0;
+    };
+
+    const double logu = lg6;
+    if constexpr (F32) {
+      if (need_mv || need_dp) {
+        f32_eval();
+        // an estimate above the tolerance, or a decision the error could turn: decide with
+        // the FP64 rebuild
+        if (inexact || (valid && (bnd > kF32Tol * fmax(1.0, fabs(dnu)) || fabs(logu - la) <= bnd))) {
+          double drift;
+          if (N == 0 || grp_refresh<LPC, LD, HS>(md, vt, ov, Lw, W, H, xv, bv, s1, s2, zg, N, lane, drift)) {
+            f64_eval_W();
+          } else {
+            valid = false;
+            st |= FSMP_ST_FACTOR;
+          }
+          if (lane == 0) acc[19] += 1.0;
+        } else if (!valid) {
+          st |= FSMP_ST_FACTOR;
+        }
+        if (lane == 0) acc[17] += (double)N * N * (need_dp ? 1.0 : 0.0) + (double)N * N * (need_mv ? 2.0 : 0.0) +
+                                  (need_dp ? (double)N : 0.0);
+      }
+    } else if (need_mv) {
+      if (lane == 0) acc[17] += (double)N * N;
+      eval_mv(H);
+    } else if (move == 2 && valid && lane == 0) {
+      acc[17] += 1.0;
+    }
+    // the survey's word count of the proposal (a packed Cholesky factor): birth K(K+1)/2 +
+    // 2K + 3, death (K - j)(K - j + 1)/2 + 1, update both (the birth on K - 1 PEs)
+    if (lane == 0 && (valid || need_mv || need_dp)) {
+      const double K = N, r = N - j;
+      const double wb = move == 1 ? K * (K + 1) / 2 + 2 * K + 3 : (K - 1) * K / 2 + 2 * (K - 1) + 3;
+      const double wd = r * (r + 1) / 2 + 1;
+      acc[15] += move == 1 ? wb : move == 2 ? wd : (need_mv ? wd + wb : 0.0);
     }
 
     bool accepted = false;
@@ -893,30 +1124,40 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
       accepted = true;
       if (lane == 0) cnt[2 * move + 1]++;
       WAVE_SYNC();
-      if (lane == 0) {
-        if (move == 1 || move == 2) acc[16] += (double)N * N;
-        else if (sh != 0) acc[17] += (double)N * N;
-      }
       // an accepted zero shift changes nothing (unless it changes the PE's component)
       const bool shift = move == 3 && (sh != 0 || (MCP && enew != ek[j]));
+      if (lane == 0) {
+        // the survey's word count of the edit (packed factor): birth K + 3, death
+        // (K - 1 - j)(K - j) + K(K + 1)/2, update both; and the G^-1 elements this kernel reads
+        // and writes in its rank-one or rank-two edit
+        const double K = N, r = N - j;
+        const double eb = move == 1 ? K + 3 : (K - 1) + 3, ed = (r - 1) * r + K * (K + 1) / 2;
+        acc[16] += move == 1 ? eb : move == 2 ? ed : (shift ? ed + eb : 0.0);
+        if (move != 3 || shift) acc[18] += 2.0 * K * K;
+      }
       if (move != 3 || shift) {
         const double inv_d2 = move == 2 ? 0.0 : 1.0 / delta2;
         const double inv_om = move == 1 ? 0.0 : 1.0 / om;
         const double xn = up * inv_d2;
         const int gj = move == 1 ? -1 : zg[j];
-        if (move != 1) {
-          for (int i = lane; i < N; i += LPC) s1[i] = H[(j * LD + i) * HS];  // h = row j of H
-          WAVE_SYNC();
+        // the FP32 form has its corrected vectors at hand: u (column j of G^-1) in s1, eta or v
+        // in s3
+        if constexpr (!F32) {
+          if (move != 1) {
+            for (int i = lane; i < N; i += LPC) s1[i] = H[(j * LD + i) * HS];  // h = row j of H
+            WAVE_SYNC();
+          }
+          if (shift) {
+            for (int i = lane; i < N; i += LPC) s2[i] = (i == j) ? 0.0 : s2[i] - s1[i] * ej * inv_om;
+            WAVE_SYNC();
+          }
         }
-        if (shift) {
-          for (int i = lane; i < N; i += LPC) s2[i] = (i == j) ? 0.0 : s2[i] - s1[i] * ej * inv_om;
-          WAVE_SYNC();
-        }
+        double *EV = F32 ? s3 : s2;  // eta (birth) or v (shift)
         // H(k, i) += cu u_i u_k + cv v_i v_k for i, k < N:
         //   birth: u = eta, cu = 1/delta^2; death: u = h, cu = -1/omega;
         //   shift: u = h, cu = -1/omega, and v = eta (zero at j), cv = 1/delta^2
-        const double *U = move == 1 ? s2 : s1;
-        const double *V = shift ? s2 : U;
+        const double *U = move == 1 ? EV : s1;
+        const double *V = shift ? EV : U;
         const double cu = move == 1 ? inv_d2 : -inv_om, cv = shift ? inv_d2 : 0.0;
         for (int i = lane; i < N; i += LPC) {
           const double ui = U[i], vi = V[i];
@@ -969,7 +1210,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
             if (i == j) {
               H[(j * LD + j) * HS] = inv_d2;
             } else {
-              const double v = -s2[i] * inv_d2;
+              const double v = -EV[i] * inv_d2;
               H[(j * LD + i) * HS] = v;
               H[(i * LD + j) * HS] = v;
             }
@@ -1053,19 +1294,27 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
       if (a.qdraw && a.thin > 0 && (i % a.thin) == 0) {
         // charge draw q = x + sigma_eps R xi, H = R R^T with R upper triangular: the
         // factorisation runs from the last PE backwards on a copy of H's lower triangle
-        // in the chain's device-memory scratch; y = R xi accumulates column by column
+        // in the chain's device-memory scratch; y = R xi accumulates column by column.  The
+        // FP32 form draws from its FP64 rebuild W (and the x it recomputes).
         const int64_t rec = c * a.n_rec + i / a.thin;
         double *Ad = a.dscr + slot * (int64_t)(KCAP * KCAP + KCAP);
         double *Av = Ad + KCAP * KCAP;  // the column being eliminated
         WAVE_SYNC();
+        bool ok = true;
+        if constexpr (F32) {
+          double drift;
+          if (N > 0 && !grp_refresh<LPC, LD, HS>(md, vt, ov, Lw, W, H, xv, bv, s1, s2, zg, N, lane, drift)) ok = false;
+        }
         for (int r = lane; r < N; r += LPC) {
-          for (int k = 0; k <= r; ++k) Ad[r * KCAP + k] = H[(k * LD + r) * HS];
+          for (int k = 0; k <= r; ++k) {
+            if constexpr (F32) Ad[r * KCAP + k] = W[(k * LD + r) * HS];
+            else Ad[r * KCAP + k] = H[(k * LD + r) * HS];
+          }
           s1[r] = charge_normal(step, r, uid0, uid1, a.key0, a.key1);
           s2[r] = 0.0;
         }
         WAVE_SYNC();
-        bool ok = true;
-        for (int jj = N - 1; jj >= 0; --jj) {
+        for (int jj = N - 1; jj >= 0 && ok; --jj) {
           const double ajj = Ad[jj * KCAP + jj];
           if (!(ajj > 0.0)) {
             ok = false;
@@ -1111,7 +1360,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
     for (int i = 0; i < 8; ++i) a.counts[c * 8 + i] = cnt[i];
     a.status[c] = st;
     if (a.work) {
-      for (int i = 0; i < 4; ++i) a.work[c * 4 + i] = acc[15 + i];
+      for (int i = 0; i < 5; ++i) a.work[c * 5 + i] = acc[15 + i];
     }
   }
 }
@@ -1273,15 +1522,12 @@ __device__ __attribute__((noinline)) bool lane_charge_draw(double *Ap, const HT 
   return ok;
 }
 
-// Workspace of one tile of 64 chains, in doubles: the inverse Gram matrix in its
-// storage type, the FP64 refresh matrix (precision form only), five FP64 vectors
+// Workspace of one tile of 64 chains, in doubles: the inverse Gram matrix, five vectors
 // (b, x and three scratch); grid indices and the N histogram are in the int workspace.
-template <int KCAP, typename HT>
+template <int KCAP>
 struct LaneLayout {
-  static constexpr bool F32 = sizeof(HT) == 4;
-  static constexpr int HD = KCAP * KCAP * (int)sizeof(HT) / 8;  // doubles per chain for H
-  static constexpr int WD = F32 ? KCAP * KCAP : 0;
-  static constexpr int ED = HD + WD + 5 * KCAP;
+  static constexpr int HD = KCAP * KCAP;  // doubles per chain for H
+  static constexpr int ED = HD + 5 * KCAP;
   static constexpr int EI = 2 * KCAP + 1;
 };
 
@@ -1308,26 +1554,6 @@ __device__ bool lane_build(const ModelDev &md, const double *vt, const double *o
     }
     Wp[(k * KCAP + k) * 64] = inv;
   }
-  return true;
-}
-
-// Precision form: rebuild the inverse Gram matrix of the current z in FP64, recompute
-// x = G^{-1} b in FP64, round the result into the FP32 storage.  `drift` is the largest
-// change of a charge mean, relative to max(1, |x|).
-template <int KCAP, typename HT>
-__device__ bool lane_refresh(const ModelDev &md, const double *vt, const double *ov, int Lw, double *Wp, HT *Hp,
-                             double *Xp, const double *Bp, double *S1, double *S2, const int32_t *Zp, int N,
-                             double &drift) {
-  if (!lane_build<KCAP>(md, vt, ov, Lw, Wp, S1, S2, Zp, N)) return false;
-  drift = 0.0;
-  for (int i = 0; i < N; ++i) {
-    double xi = 0.0;
-    for (int k = 0; k < N; ++k) xi += Wp[(i * KCAP + k) * 64] * Bp[k * 64];
-    const double dx = fabs(xi - Xp[i * 64]) / fmax(1.0, fabs(xi));
-    drift = dx > drift ? dx : drift;
-    Xp[i * 64] = xi;
-  }
-  for (int k = 0; k < N; ++k) lane_copy(Hp + (int64_t)k * KCAP * 64, Wp + (int64_t)k * KCAP * 64, N);
   return true;
 }
 
@@ -1374,15 +1600,14 @@ __device__ inline MvResult lane_propose(const ModelDev &md, const MT *Mp, const 
   return r;
 }
 
-// One chain per lane.  The chain's H = G^{-1} (full, KCAP x KCAP, FP64 or FP32), x, b,
-// scratch and PE list live in device memory, interleaved across the 64 chains of a
-// tile so that every access of a wavefront is one contiguous segment.  Two wavefronts per
-// SIMD at the least (the register budget halves): with one, nothing hides the device-
-// memory round trips of the state (measured 21% slower at capacity 16).
-template <int KCAP, typename HT>
+// One chain per lane.  The chain's H = G^{-1} (full, KCAP x KCAP, FP64), x, b, scratch and
+// PE list live in device memory, interleaved across the 64 chains of a tile so that every
+// access of a wavefront is one contiguous segment.  Two wavefronts per SIMD at the least
+// (the register budget halves): with one, nothing hides the device-memory round trips of
+// the state (measured 21% slower at capacity 16).
+template <int KCAP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) chain_lane_kernel(ChainArgs a) {
-  using LL = LaneLayout<KCAP, HT>;
-  constexpr bool F32 = LL::F32;
+  using LL = LaneLayout<KCAP>;
   extern __shared__ double smem[];
   const ModelDev &md = a.md;
   double *vt = smem;
@@ -1398,9 +1623,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
   const int64_t tile = slot >> 6;
   const int ln = (int)(slot & 63);
   double *base = a.dws + tile * (int64_t)LL::ED * 64;
-  HT *Hp = (HT *)base + ln;
-  double *Wp = base + (int64_t)LL::HD * 64 + ln;
-  double *Xp = base + (int64_t)(LL::HD + LL::WD) * 64 + ln;
+  double *Hp = base + ln;
+  double *Xp = base + (int64_t)LL::HD * 64 + ln;
   double *Bp = Xp + KCAP * 64;
   double *S1 = Bp + KCAP * 64;
   double *S2 = S1 + KCAP * 64;
@@ -1460,16 +1684,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
     if (n0 > 0) {
       const int32_t *z0 = a.zinit + a.zinit_off[c];
       for (int k = 0; k < n0; ++k) ZG(k) = z0[k];
-      double *M = F32 ? Wp : (double *)Hp;
-      if (lane_build<KCAP>(md, vt, ov, Lw, M, S1, S2, Zp, n0)) {
+      if (lane_build<KCAP>(md, vt, ov, Lw, Hp, S1, S2, Zp, n0)) {
         for (int k = 0; k < n0; ++k) BV(k) = mf[ZG(k) - glo] + md.rhom;
         for (int i = 0; i < n0; ++i) {
           double xi = 0.0;
-          for (int k = 0; k < n0; ++k) xi += M[(i * KCAP + k) * 64] * BV(k);
+          for (int k = 0; k < n0; ++k) xi += Hp[(i * KCAP + k) * 64] * BV(k);
           XV(i) = xi;
         }
-        if (F32)
-          for (int k = 0; k < n0; ++k) lane_copy(Hp + (int64_t)k * KCAP * 64, Wp + (int64_t)k * KCAP * 64, n0);
         N = n0;
         for (int i = 0; i < N; ++i) {
           if (biexp) S_cur += log(-expm1(-((double)ZG(i) * md.dt - t0) * md.inv_tau1));
@@ -1482,11 +1703,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
     }
   }
   for (int step = 0; step < n_steps; ++step) {
-    if (F32 && a.refresh_M > 0 && step > 0 && step % a.refresh_M == 0 && N > 0) {
-      double drift;
-      if (!lane_refresh<KCAP, HT>(md, vt, ov, Lw, Wp, Hp, Xp, Bp, S1, S2, Zp, N, drift)) st |= FSMP_ST_FACTOR;
-      else if (drift > a.drift_bound) st |= FSMP_ST_DRIFT;
-    }
     uint32_t r[8];
     philox4x32_10((uint32_t)step, 0u, uid0, uid1, a.key0, a.key1, r);
     philox4x32_10((uint32_t)step, 1u, uid0, uid1, a.key0, a.key1, r + 4);
@@ -1499,7 +1715,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
     bool t0acc = false;
     cnt[0]++;
     if (t0p >= md.t0_min && t0p <= md.t0_max) {
-      wk3 += N;
       const double xmin = (N > 0) ? (double)gmin * md.dt - t0p : 1.0;
       const bool ok = biexp ? (xmin > 0.0) : (xmin >= 0.0);
       if (ok) {
@@ -1554,12 +1769,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
       j = (int)(((uint64_t)r[4] * (uint64_t)N) >> 32);
       if (move == 2) {
         cnt[4]++;
-        om = (double)HM(j, j);
+        om = HM(j, j);
         xj = XV(j);
         if (om > 0.0) {
           dnu = 0.5 * (-md.log_rho - log(om) + (md.rhom2 - xj * xj / om) * md.inv_s);
           la = dnu - logLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
           valid = true;
+          const double r = N - j;
+          wk0 += r * (r + 1) / 2 + 1;
+          wk2 += 1.0;
         } else {
           st |= FSMP_ST_FACTOR;
         }
@@ -1587,9 +1805,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
       for (int i = 0; i < N; ++i) G1(i) = (i == j) ? 0.0 : overlap(md, vt, ov, gnew, ZG(i), Lw);
       dself = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
       beta = mf[gnew - glo] + md.rhom;
-      wk0 += (double)N * N;
+      // the survey's word count of the proposal (packed factor), and the G^-1 elements read
+      {
+        const double K = N, r = N - j;
+        wk0 += move == 1 ? K * (K + 1) / 2 + 2 * K + 3 : r * (r + 1) / 2 + 1 + (K - 1) * K / 2 + 2 * (K - 1) + 3;
+        wk2 += K * K;
+      }
       const MvResult mr =
-          lane_propose<KCAP, HT>(md, Hp, S1, S2, Xp, N, move, j, dself, beta, logLam, lgn[N + 1], la_ratio);
+          lane_propose<KCAP, double>(md, Hp, S1, S2, Xp, N, move, j, dself, beta, logLam, lgn[N + 1], la_ratio);
       valid = mr.valid;
       dnu = mr.dnu;
       la = mr.la;
@@ -1602,34 +1825,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
     }
 
     const double logu = log(u01(r[6]));
-    if (F32 && valid && fabs(logu - la) < a.near_eps * fmax(1.0, fabs(dnu))) {
-      // precision form, decision near the threshold: refresh in FP64 and decide with the
-      // FP64 delta-nu of the same proposal
-      double drift;
-      if (N > 0 && lane_refresh<KCAP, HT>(md, vt, ov, Lw, Wp, Hp, Xp, Bp, S1, S2, Zp, N, drift)) {
-        if (need_mv) {
-          for (int i = 0; i < N; ++i) G1(i) = (i == j) ? 0.0 : overlap(md, vt, ov, gnew, ZG(i), Lw);
-          const MvResult mr =
-              lane_propose<KCAP, double>(md, Wp, S1, S2, Xp, N, move, j, dself, beta, logLam, lgn[N + 1], la_ratio);
-          valid = mr.valid;
-          dnu = mr.dnu;
-          la = mr.la;
-          delta2 = mr.delta2;
-          up = mr.up;
-          om = mr.om;
-          xj = mr.xj;
-          ej = mr.ej;
-        } else if (move == 2) {
-          om = Wp[(j * KCAP + j) * 64];
-          xj = XV(j);
-          dnu = 0.5 * (-md.log_rho - log(om) + (md.rhom2 - xj * xj / om) * md.inv_s);
-          la = dnu - logLam + lgn[N] - (N == 1 ? md.logJ : 0.0);
-        }
-      } else if (N > 0) {
-        st |= FSMP_ST_FACTOR;
-      }
-    }
-
     bool accepted = false;
     if (valid && logu < la) {
       accepted = true;
@@ -1640,9 +1835,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
       //   birth: u = eta, cu = 1/delta^2; death: u = h, cu = -1/omega;
       //   shift: u = h, cu = -1/omega and v = eta (zero at j), cv = 1/delta^2.
       const bool shift = move == 3 && sh != 0;  // an accepted zero shift changes nothing
+      {
+        const double K = N, r = N - j;
+        const double eb = move == 1 ? K + 3 : (K - 1) + 3, ed = (r - 1) * r + K * (K + 1) / 2;
+        wk1 += move == 1 ? eb : move == 2 ? ed : (shift ? ed + eb : 0.0);
+      }
       if (move != 3 || shift) {
-        if (shift) wk2 += (double)N * N;
-        else wk1 += (double)N * N;
+        wk3 += 2.0 * (double)N * N;
         const double inv_d2 = move == 2 ? 0.0 : 1.0 / delta2;
         const double inv_om = move == 1 ? 0.0 : 1.0 / om;
         const double xn = up * inv_d2;
@@ -1660,14 +1859,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
                   : move == 2 ? XV(i) - ui * xj * inv_om
                               : ((i == j) ? xn : XV(i) - ui * xj * inv_om - vi * xn);
         }
-        lane_rank_update<KCAP, true, HT>(Hp, U, cu, V, cv, N);
+        lane_rank_update<KCAP, true, double>(Hp, U, cu, V, cv, N);
         if (move == 1) {
           for (int i = 0; i < N; ++i) {
             const double v = -G2(i) * inv_d2;
-            HM(N, i) = (HT)v;
-            HM(i, N) = (HT)v;
+            HM(N, i) = v;
+            HM(i, N) = v;
           }
-          HM(N, N) = (HT)inv_d2;
+          HM(N, N) = inv_d2;
           ZG(N) = gnew;
           BV(N) = beta;
           XV(N) = xn;
@@ -1680,8 +1879,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
             lane_copy(S3, Hp + (int64_t)last * KCAP * 64, N);  // row `last` moves into slot j
             const double vd = G3(last);
             lane_copy(Hp + (int64_t)j * KCAP * 64, S3, N);
-            for (int i = 0; i < N; ++i) HM(i, j) = (HT)G3(i);
-            HM(j, j) = (HT)vd;
+            for (int i = 0; i < N; ++i) HM(i, j) = G3(i);
+            HM(j, j) = vd;
             ZG(j) = ZG(last);
             BV(j) = BV(last);
             XV(j) = XV(last);
@@ -1691,11 +1890,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
         } else {
           for (int i = 0; i < N; ++i) {
             if (i == j) {
-              HM(j, j) = (HT)inv_d2;
+              HM(j, j) = inv_d2;
             } else {
               const double v = -G2(i) * inv_d2;
-              HM(j, i) = (HT)v;
-              HM(i, j) = (HT)v;
+              HM(j, i) = v;
+              HM(i, j) = v;
             }
           }
           ZG(j) = gnew;
@@ -1761,7 +1960,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
       }
       if (a.qdraw && a.thin > 0 && (i % a.thin) == 0) {
         const int64_t rec = c * a.n_rec + i / a.thin;
-        if (!lane_charge_draw<KCAP, HT>(a.dscr + tile * (int64_t)KCAP * KCAP * 64 + ln, Hp, Xp, S1, S2, S3, Zp, N,
+        if (!lane_charge_draw<KCAP, double>(a.dscr + tile * (int64_t)KCAP * KCAP * 64 + ln, Hp, Xp, S1, S2, S3, Zp, N,
                                         step, uid0, uid1, a.key0, a.key1, a.sigma_eps, a.qdraw + rec * a.kz,
                                         a.zdraw + rec * a.kz, a.kz))
           st |= FSMP_ST_FACTOR;
@@ -1782,10 +1981,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
   for (int i = 0; i < 8; ++i) a.counts[c * 8 + i] = cnt[i];
   a.status[c] = st;
   if (a.work) {
-    a.work[c * 4 + 0] = wk0;
-    a.work[c * 4 + 1] = wk1;
-    a.work[c * 4 + 2] = wk2;
-    a.work[c * 4 + 3] = wk3;
+    a.work[c * 5 + 0] = wk0;
+    a.work[c * 5 + 1] = wk1;
+    a.work[c * 5 + 2] = wk2;
+    a.work[c * 5 + 3] = wk3;
+    a.work[c * 5 + 4] = 0.0;
   }
 #undef HM
 #undef XV
@@ -1994,6 +2194,7 @@ hipError_t launch_chain_t(const ChainArgs &a, hipStream_t st, int32_t *lanes, in
   *blocks = nb;
   if (nb == 0) return hipSuccess;
   if (HG && a.dws == nullptr) return hipErrorInvalidValue;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;  // the host checks the configurations against this
   if (lds > 64 * 1024) {
     // lift the default dynamic-LDS limit; gfx950 has 160 KB per workgroup
     (void)hipFuncSetAttribute((const void *)chain_kernel<KCAP, LPC, WPB, HG, FORCE, F32, MCP>,
@@ -2007,14 +2208,14 @@ hipError_t launch_chain_t(const ChainArgs &a, hipStream_t st, int32_t *lanes, in
 }
 
 
-template <int KCAP, typename HT>
+template <int KCAP>
 hipError_t launch_chain_lane_t(const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
   const int64_t nb = (a.n_list + 255) / 256;
   const size_t lds = sizeof(double) * ((size_t)a.md.M * (1 + a.md.sub) + KCAP + 2);
   *lanes = 1;
   *blocks = nb;
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL((chain_lane_kernel<KCAP, HT>), dim3((unsigned)nb), dim3(256), lds, st, a);
+  hipLaunchKernelGGL((chain_lane_kernel<KCAP>), dim3((unsigned)nb), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 
@@ -2283,10 +2484,15 @@ struct GroupCfg {
 static const GroupCfg kGroup[] = {{16, 16, 4}, {32, 32, 4}, {48, 64, 3}, {64, 64, 4}};
 static const GroupCfg kGroupDM[] = {{16, 4, 4},  {32, 4, 4},   {48, 16, 2},  {64, 32, 4},
                                     {96, 16, 2}, {128, 32, 4}, {160, 32, 4}, {192, 32, 2}};
+// the FP32 form keeps eight vectors per chain in LDS: two wavefronts per workgroup at the
+// capacities of 4-lane groups (at four, capacity 32 would need 168 KB)
+static const GroupCfg kGroupDMF32[] = {{16, 4, 2},  {32, 4, 2},   {64, 32, 4},  {96, 16, 2},
+                                       {128, 32, 4}, {160, 32, 4}, {192, 32, 2}};
 
 static size_t chain_lds_bytes(const GroupCfg &g, int M, int sub, bool hg, bool f32 = false, bool mcp = false) {
   const int cpb = g.wpb * (64 / g.lpc);
-  const size_t per = (hg ? 0 : (size_t)g.kcap * g.kcap) + (f32 ? 4 : 3) * (size_t)g.kcap + 25 +
+  const size_t per = (hg ? 0 : (size_t)g.kcap * g.kcap) + (size_t)ChainLayout<16, true, false, false>::kAcc +
+                     (f32 ? ChainLayout<16, true, true>::kVec : ChainLayout<16, true>::kVec) * (size_t)g.kcap +
                      ((size_t)g.kcap + 1) / 2 * (mcp ? 2 : 1);
   return sizeof(double) * ((size_t)M * (1 + sub) + (size_t)g.kcap + 2 + (size_t)cpb * per);
 }
@@ -2298,10 +2504,15 @@ bool chain_kcap_supported(int kcap, int M, int sub) {
 }
 
 bool chain_dm_supported(int kcap, int M, int sub, bool f32, bool mcp) {
-  if (f32 && kcap == 48) return false;  // the precision form runs capacity 48 at 64
   if (f32 && mcp) return false;
+  if (f32) {
+    // no capacity 48: the precision form runs it at 64
+    for (const GroupCfg &g : kGroupDMF32)
+      if (g.kcap == kcap) return chain_lds_bytes(g, M, sub, true, true, false) <= 160 * 1024;
+    return false;
+  }
   for (const GroupCfg &g : kGroupDM)
-    if (g.kcap == kcap) return chain_lds_bytes(g, M, sub, true, f32, mcp) <= 160 * 1024;
+    if (g.kcap == kcap) return chain_lds_bytes(g, M, sub, true, false, mcp) <= 160 * 1024;
   return false;
 }
 
@@ -2316,10 +2527,9 @@ size_t group_dm_ws_doubles(int kcap, int64_t n_list, bool f32) {
   return 0;
 }
 
-size_t lane_ws_doubles(int kcap, int64_t n_list, bool fp32) {
+size_t lane_ws_doubles(int kcap, int64_t n_list) {
   const size_t tiles = (size_t)((n_list + 63) / 64);
-  const size_t k2 = (size_t)kcap * kcap;
-  return tiles * 64 * ((fp32 ? k2 / 2 + k2 : k2) + 5 * (size_t)kcap);
+  return tiles * 64 * ((size_t)kcap * kcap + 5 * (size_t)kcap);
 }
 
 size_t lane_ws_ints(int kcap, int64_t n_list) {
@@ -2327,31 +2537,11 @@ size_t lane_ws_ints(int kcap, int64_t n_list) {
   return tiles * 64 * (2 * (size_t)kcap + 1);
 }
 
-hipError_t launch_chain_lane(int kcap, bool fp32, const ChainArgs &a, hipStream_t st, int32_t *lanes,
-                             int64_t *blocks) {
-  // no lane instance for capacity 48: its GPU run faulted with a cause not found
-  // (a bounds-checked CPU build of this kernel is clean); capacity 48 runs in the
-  // lane-group kernel (FP64) or in the capacity-64 lane instance (FP32 form)
-  if (fp32) {
-    switch (kcap) {
-      case 16: return launch_chain_lane_t<16, float>(a, st, lanes, blocks);
-      case 32: return launch_chain_lane_t<32, float>(a, st, lanes, blocks);
-      case 64: return launch_chain_lane_t<64, float>(a, st, lanes, blocks);
-      case 96: return launch_chain_lane_t<96, float>(a, st, lanes, blocks);
-      case 128: return launch_chain_lane_t<128, float>(a, st, lanes, blocks);
-      case 160: return launch_chain_lane_t<160, float>(a, st, lanes, blocks);
-      case 192: return launch_chain_lane_t<192, float>(a, st, lanes, blocks);
-      default: return hipErrorInvalidValue;
-    }
-  }
+hipError_t launch_chain_lane(int kcap, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
+  // one lane per chain pays off only for small PE counts: instances at capacities 16 and 32
   switch (kcap) {
-    case 16: return launch_chain_lane_t<16, double>(a, st, lanes, blocks);
-    case 32: return launch_chain_lane_t<32, double>(a, st, lanes, blocks);
-    case 64: return launch_chain_lane_t<64, double>(a, st, lanes, blocks);
-    case 96: return launch_chain_lane_t<96, double>(a, st, lanes, blocks);
-    case 128: return launch_chain_lane_t<128, double>(a, st, lanes, blocks);
-    case 160: return launch_chain_lane_t<160, double>(a, st, lanes, blocks);
-    case 192: return launch_chain_lane_t<192, double>(a, st, lanes, blocks);
+    case 16: return launch_chain_lane_t<16>(a, st, lanes, blocks);
+    case 32: return launch_chain_lane_t<32>(a, st, lanes, blocks);
     default: return hipErrorInvalidValue;
   }
 }
@@ -2396,9 +2586,10 @@ hipError_t launch_chain_dm(int kcap, bool fp32, const ChainArgs &a, hipStream_t 
     }
   }
   if (fp32) {
+    // instances must match kGroupDMF32
     switch (kcap) {
-      case 16: return launch_chain_t<16, 4, 4, true, false, true>(a, st, lanes, blocks);
-      case 32: return launch_chain_t<32, 4, 4, true, false, true>(a, st, lanes, blocks);
+      case 16: return launch_chain_t<16, 4, 2, true, false, true>(a, st, lanes, blocks);
+      case 32: return launch_chain_t<32, 4, 2, true, false, true>(a, st, lanes, blocks);
       case 64: return launch_chain_t<64, 32, 4, true, false, true>(a, st, lanes, blocks);
       case 96: return launch_chain_t<96, 16, 2, true, false, true>(a, st, lanes, blocks);
       case 128: return launch_chain_t<128, 32, 4, true, false, true>(a, st, lanes, blocks);

@@ -261,7 +261,7 @@ class Sampler:
             "status": torch.zeros(C, dtype=torch.int32, device=dev),
             "rec_steps": torch.zeros(C, dtype=torch.int32, device=dev),
             "log": None, "trace": None, "kz": kz,
-            "work": torch.zeros((C, 4), dtype=torch.float64, device=dev) if work else None,
+            "work": torch.zeros((C, 5), dtype=torch.float64, device=dev) if work else None,
             "occ": torch.zeros(occ_len, dtype=torch.int32, device=dev) if occ_len > 0 else None,
             "comp": torch.zeros((C, kz), dtype=torch.int32, device=dev) if self.cfg.n_mix > 0 else None,
         }

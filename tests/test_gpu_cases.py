@@ -74,6 +74,18 @@ def test_designs_agree_with_oracle(design):
     assert len(parted) == 0, parted
 
 
+def test_lane_design_at_its_capacities():
+    # one lane per chain at capacities 16 and 32 (the capacities it has), lane groups with
+    # G^-1 in device memory above
+    wl = synth.PRESETS["batched"]
+    b = synth.generate(wl, n_wave=60, seed=12)
+    km = synth.kmax_for(b["lam"])
+    assert {16, 32} <= set(km.tolist())
+    _, _, g, o = _gpu_and_oracle(wl, b, km, 300, 150, 2, 6, design="lldddddd")
+    parted = compare_chains(g, o)
+    assert len(parted) == 0, parted
+
+
 @pytest.mark.parametrize("design", [None, "dddddddd"])
 def test_large_capacities_pileup(design):
     wl = synth.PRESETS["pileup"]

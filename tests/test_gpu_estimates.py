@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from paper_2403_03156_amd import synth
-from tests.fsmp_cases import compare_chains, gpu_sampler, oracle_params, to_host
+from tests.fsmp_cases import check_partings, compare_chains, gpu_sampler, oracle_params, to_host
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -34,9 +34,10 @@ def test_diagnostics_and_lambda_hat_match_oracle():
     g = to_host(out)
     o = oracle.run(oracle_params(wl), b["wave"], b["offsets"], b["lam"], C, n_steps, burn, 17, kz, kmax=km)
     parted = compare_chains(g, o)
+    check_partings(parted, oracle_params(wl), b, b["lam"], km, C, n_steps, burn, 17, kz,
+                   lambda flags: gpu_sampler(wl, n_steps, burn, C, 17, record_flags=flags))
     bad = set(int(c) // C for c in parted)
     keep = np.array([i for i in range(n) if i not in bad])
-    assert len(keep) >= 0.8 * n
     rh, mc = oracle.chain_diagnostics(o.acc, n_steps - burn, C)
     grh = post["rhat"].cpu().numpy()
     gmc = post["mcse_chains"].cpu().numpy()

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from paper_2403_03156_amd import fsmp, synth
-from tests.fsmp_cases import compare_chains, gpu_sampler, oracle_params, to_host
+from tests.fsmp_cases import check_partings, compare_chains, gpu_sampler, oracle_params, to_host
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -65,8 +65,10 @@ def test_set_design_validation():
     assert smp.get_design(16) == fsmp.FSMP_DESIGN_GROUP
     smp.set_design(16, fsmp.FSMP_DESIGN_LANE)
     assert smp.get_design(16) == fsmp.FSMP_DESIGN_LANE
-    with pytest.raises(RuntimeError):
-        smp.set_design(48, fsmp.FSMP_DESIGN_LANE)
+    smp.set_design(32, fsmp.FSMP_DESIGN_LANE)
+    for cap in (48, 64, 96, 128, 160, 192):   # one lane per chain exists at capacities 16 and 32 only
+        with pytest.raises(RuntimeError):
+            smp.set_design(cap, fsmp.FSMP_DESIGN_LANE)
     with pytest.raises(RuntimeError):
         smp.set_design(96, fsmp.FSMP_DESIGN_GROUP)
     with pytest.raises(RuntimeError):
@@ -88,7 +90,8 @@ def test_autotune_keeps_results_correct():
     before = {c: smp.get_design(c) for c in synth.KCAPS}
     designs = smp.autotune(wave, b["offsets"], b["lam"], kmax=km, trial_steps=40)
     print(f"[autotune] {before} -> {designs}", flush=True)
-    assert designs[48] in (fsmp.FSMP_DESIGN_GROUP, fsmp.FSMP_DESIGN_GROUP_DEVMEM)   # no lane instance at 48
+    assert all(designs[c] in (fsmp.FSMP_DESIGN_GROUP, fsmp.FSMP_DESIGN_GROUP_DEVMEM) for c in (48, 64))  # no lane
+
     assert all(designs[c] == before[c] for c in (96, 128, 160, 192))                # not in the batch: untouched
     # a sub-batch in the tuned designs against the oracle
     n = 60
@@ -100,7 +103,14 @@ def test_autotune_keeps_results_correct():
     o = oracle.run(oracle_params(wl), b["wave"][:off[-1]], off, b["lam"][:n], 1, 120, 60, 13, int(km[:n].max()),
                    kmax=km[:n])
     parted = compare_chains(g, o)
-    assert len(parted) <= 0.3 * n, parted
+
+    def tuned(flags):
+        s = gpu_sampler(wl, 120, 60, 1, 13, record_flags=flags)
+        for cap, d in designs.items():
+            s.set_design(cap, d)
+        return s
+    check_partings(parted, oracle_params(wl), {"wave": b["wave"][:off[-1]], "offsets": off}, b["lam"][:n], km[:n], 1,
+                   120, 60, 13, int(km[:n].max()), tuned)
 
 
 def test_workspace_bytes_matches_device_allocation():

@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 from paper_2403_03156_amd import fsmp, synth
-from tests.fsmp_cases import compare_chains, oracle_params, to_host
+from tests.fsmp_cases import check_partings, compare_chains, oracle_params, to_host
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -44,6 +44,8 @@ def _run(wl, b, km, n_steps, burn, C, seed):
     g = to_host(smp.sample(torch.from_numpy(b["wave"]).cuda(), b["offsets"], b["lam"], kmax=km, kz=kz))
     o = oracle.run(_oracle_params(wl), b["wave"], b["offsets"], b["lam"], C, n_steps, burn, seed, kz, kmax=km)
     parted = compare_chains(g, o)
+    check_partings(parted, _oracle_params(wl), b, b["lam"], km, C, n_steps, burn, seed, kz,
+                   lambda flags: _sampler(wl, n_steps, burn, C, seed, record_flags=flags))
     keep = np.setdiff1d(np.arange(len(g["n_pe"])), parted)
     np.testing.assert_array_equal(g["comp"][keep], o.e[keep])
     return g, o, parted
@@ -58,7 +60,6 @@ def test_mcp_chains_match_oracle():
     g, o, parted = _run(wl, b, km, 300, 150, C, 41)
     used = np.bincount(g["comp"][g["comp"] >= 0], minlength=5)
     print(f"[mcp] {len(parted)} of {n * C} chains parted; final PEs per component {used.tolist()}", flush=True)
-    assert len(parted) <= 0.1 * n * C, parted
     assert (used > 0).sum() >= 4
 
 
@@ -71,7 +72,6 @@ def test_mcp_high_capacity():
     print(f"[case] mcp pileup caps={km.tolist()}", flush=True)
     g, o, parted = _run(wl, b, km, 150, 75, 1, 42)
     print(f"[mcp] high capacity: {len(parted)} of {len(km)} chains parted", flush=True)
-    assert len(parted) <= 1
 
 
 def test_one_component_equals_single_normal():

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from paper_2403_03156_amd import synth
-from tests.fsmp_cases import compare_chains, gpu_sampler, oracle_params, to_host
+from tests.fsmp_cases import check_partings, compare_chains, gpu_sampler, oracle_params, to_host
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -30,7 +30,8 @@ def test_uneven_sample_every_chain():
     o = oracle.run(oracle_params(wl), b["wave"], b["offsets"], b["lam"], 1, 300, 150, 7, kz, kmax=km)
     parted = compare_chains(g, o)
     print(f"[uneven] {len(parted)} of 90 chains parted", flush=True)
-    assert len(parted) <= 2, parted
+    check_partings(parted, oracle_params(wl), b, b["lam"], km, 1, 300, 150, 7, kz,
+                   lambda flags: gpu_sampler(wl, 300, 150, 1, 7, record_flags=flags))
 
 
 def test_uneven_full_size_sampled_chains():
@@ -67,4 +68,6 @@ def test_uneven_full_size_sampled_chains():
     sub = {k: (v[pick] if isinstance(v, np.ndarray) else v) for k, v in g.items()}
     parted = compare_chains(sub, o)
     print(f"[uneven] full size: {len(pick)} sampled chains, {len(parted)} parted", flush=True)
-    assert len(parted) <= 1, parted
+    check_partings(parted, oracle_params(wl), {"wave": wave, "offsets": off}, b["lam"][pick], km[pick], 1, n_steps,
+                   n_steps // 2, 3, kz, lambda flags: gpu_sampler(wl, n_steps, n_steps // 2, 1, 3, record_flags=flags),
+                   wave_id=pick)

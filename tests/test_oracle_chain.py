@@ -166,3 +166,22 @@ def test_replay_of_own_log():
         valid = (r.log[i]["flags"] & 1) != 0
         np.testing.assert_array_equal(dnu[valid], r.log[i]["dnu"][valid])
         assert valid.sum() > 100
+
+
+def test_per_waveform_sweeps_equal_separate_runs():
+    """wsteps: every waveform runs its own sweep count with burn-in wsteps * burn_in // n_steps,
+    the same chains as separate runs of each count"""
+    p = oracle.make_params()
+    rng = np.random.default_rng(8)
+    L, n = 96, 5
+    wave = (0.1 * rng.standard_normal(n * L)).astype(np.float32)
+    off = np.arange(n + 1, dtype=np.int64) * L
+    lam = np.full(n, 2.0)
+    steps = np.array([40, 100, 73, 100, 1], np.int32)
+    r = oracle.run(p, wave, off, lam, 2, 100, 50, 9, 8, wsteps=steps)
+    for i, s in enumerate(steps):
+        one = oracle.run(p, wave[off[i]:off[i + 1]], np.array([0, L], np.int64), lam[i:i + 1], 2, int(s),
+                         int(s) * 50 // 100, 9, 8, wave_id=np.array([i], np.uint64))
+        np.testing.assert_array_equal(r.z[2 * i:2 * i + 2], one.z)
+        np.testing.assert_array_equal(r.nhist[2 * i:2 * i + 2], one.nhist)
+        np.testing.assert_array_equal(r.acc[2 * i:2 * i + 2], one.acc)

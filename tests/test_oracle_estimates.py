@@ -113,3 +113,76 @@ def test_lambda_hat_against_dense_maximisation():
         f = -(xs - lam0) + mx + np.log(np.exp(a - mx[:, None]).sum(1))
         best = xs[np.argmax(f)]
         assert abs(est - best) <= 2 * (hi - lo) / 200000 + 1e-9, (trial, est, best)
+
+
+def _batch_means_mcse(x):
+    """[C][S] recorded values -> batch-means MCSE of the pooled mean, written out from the
+    definition: floor(sqrt(S)) batches of S // floor(sqrt(S)) consecutive values per chain (the
+    values past the last whole batch are left out), the unbiased variance of all C x nb batch
+    means, divided by their number"""
+    C, S = x.shape
+    nb = int(math.isqrt(S))
+    lb = S // nb
+    bm = x[:, :nb * lb].reshape(C, nb, lb).mean(2).reshape(-1)
+    return math.sqrt(bm.var(ddof=1) / bm.size)
+
+
+def test_summarize_matches_batch_means_of_recorded_traces():
+    """the pooled mean, variance and batch-means MCSE that summarize() forms from the chain
+    driver's accumulators (sums and batch sums) against numpy on the thin = 1 trace of the same
+    chains (S = 440 and 899 recorded sweeps: 20 batches of 22, and 29 batches of 31, so that a
+    batch count swapped with a batch length fails)"""
+    p = oracle.make_params(t0_min=0.0, t0_max=10.0)
+    rng = np.random.default_rng(4)
+    L = 64
+    n = np.arange(L)
+    waves = []
+    for k in range(3):
+        w = (0.1 * rng.standard_normal(L)).astype(np.float32)
+        for t in rng.uniform(5, 40, k + 1):
+            w += np.exp(-0.5 * ((n - t - 4) / 1.5) ** 2).astype(np.float32)
+        waves.append(w)
+    wave = np.concatenate(waves)
+    off = np.arange(4, dtype=np.int64) * L
+    C = 3
+    for n_steps, burn in ((640, 200), (1099, 200)):
+        r = oracle.run(p, wave, off, np.array([2.0, 4.0, 6.0]), C, n_steps, burn, 7, 16, thin=1)
+        s = oracle.summarize(r.acc, n_steps, burn, C)
+        tr = r.trace.reshape(3, C, n_steps - burn, 3)
+        for name, col in (("N", 0), ("t0", 1), ("Q", 2)):
+            mean, var, mcse = s[name]
+            for i in range(3):
+                x = tr[i, :, :, col]
+                assert mean[i] == pytest.approx(x.mean(), rel=1e-12, abs=1e-12)
+                assert var[i] == pytest.approx(x.var(), rel=1e-9, abs=1e-12)
+                assert mcse[i] == pytest.approx(_batch_means_mcse(x), rel=1e-8, abs=1e-12)
+
+
+def test_summarize_mcse_of_ar1_chains_matches_closed_form():
+    """chains of a stationary AR(1) process v_t = phi v_{t-1} + e_t, e_t ~ N(0, 1): the mean of
+    S values has variance (1 / (1 - phi^2)) (1 + phi) / (1 - phi) / S for large S, so the batch-
+    means MCSE of C chains of S values must approach sqrt(1 / ((1 - phi)^2 C S)); with
+    floor(sqrt(S)) = 447 batches of 447 values per chain (far longer than the correlation
+    time) and 4 chains, the estimate's own relative error is about 1/sqrt(2 x 1788) = 1.7%"""
+    rng = np.random.default_rng(6)
+    phi, C, S = 0.8, 4, 200000
+    acc = np.zeros((C, 12))
+    nb = int(math.isqrt(S))
+    lb = S // nb
+    for c in range(C):
+        e = rng.standard_normal(S)
+        v = np.empty(S)
+        v[0] = e[0] / math.sqrt(1.0 - phi * phi)
+        for t in range(1, S):
+            v[t] = phi * v[t - 1] + e[t]
+        bs = v[:nb * lb].reshape(nb, lb).sum(1)
+        for a in range(3):
+            acc[c, 2 * a] = v.sum()
+            acc[c, 2 * a + 1] = (v * v).sum()
+            acc[c, 6 + 2 * a] = bs.sum()
+            acc[c, 7 + 2 * a] = (bs * bs).sum()
+    s = oracle.summarize(acc[None].reshape(C, 12), S, 0, C)
+    want = math.sqrt(1.0 / ((1.0 - phi) ** 2 * C * S))
+    mean, var, mcse = s["N"]
+    assert mcse[0] == pytest.approx(want, rel=0.07)
+    assert var[0] == pytest.approx(1.0 / (1.0 - phi * phi), rel=0.05)
