@@ -321,6 +321,27 @@ size_t fsmp_workspace_bytes(const fsmp_ctx *ctx, const fsmp_batch *batch);
  * one stream, or order their streams, so that two calls never run on the device at once. */
 fsmp_status fsmp_sample(fsmp_ctx *ctx, const fsmp_batch *batch, const fsmp_samples *out, void *hip_stream);
 
+/* fsmp_sample for callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same validation, kernels and outputs
+ * as fsmp_sample (identical results for the same context and batch), but the call allocates
+ * nothing -- no device, pinned or host memory, streams or events.  Its device workspace
+ * (batch metadata, matched filter, chain lists, chain state, charge-draw scratch) is one
+ * static array of 256 MiB per GPU in the library's code object, held until the process
+ * ends, whose address fsmp_create takes on the context's device; its host-side arrays are
+ * static too.  Limits: at most 65,536 waveforms and 262,144 chains, a workspace within the
+ * 256 MiB (fsmp_workspace_bytes gives it, to within alignment), and solution spaces no longer
+ * than the context's light-curve table (16,384 grid points at creation; a longer batch
+ * through fsmp_sample grows it); FSMP_EINVAL / FSMP_ENOTSUP beyond them, with the reason in
+ * fsmp_last_error.  The PE-capacity buckets run one after the other on `hip_stream` (no side
+ * streams), no kernel timings are taken, and the batch's host arrays are uploaded with
+ * hipMemcpyAsync from the caller's (pageable) memory, which the copies have read when the
+ * call returns.  Every call in the process shares the host arrays and every call on a GPU
+ * shares that GPU's scratch array, whose contents the previous call leaves: calls are
+ * serialised on the host, and the caller must not let the device work of two calls on one
+ * GPU overlap (one stream, or streams ordered by events); nothing in the scratch needs to
+ * start at zero. */
+fsmp_status fsmp_sample_noalloc(fsmp_ctx *ctx, const fsmp_batch *batch, const fsmp_samples *out, void *hip_stream);
+
 /* Replay (a check of the sampler's delta-nu along a given path; Sec. 2.4 moves, App. A
  * delta-nu): like fsmp_sample, but every chain follows the recorded proposals of `log`
  * (device, [chain][cfg.n_steps] fsmp_logrec, the FSMP_REC_LOG layout, from this library

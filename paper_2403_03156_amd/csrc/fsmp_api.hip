@@ -12,7 +12,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "fsmp_internal.h"
@@ -23,6 +25,40 @@ namespace {
 
 const char *kVersion = "fsmp-mi355x 0.1 (gfx950)";
 std::string g_create_error = "no error";
+
+// ---- the allocation-free variant of fsmp_sample (fsmp_sample_noalloc)
+// Its device workspace: one array per GPU in the code object, held until the process ends.
+// Host code must not use the array's name as a device address: it takes the address
+// hipGetSymbolAddress gives on each device (scratch_address), once per device.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+// its host-side per-waveform arrays, for batches of up to these sizes
+constexpr int64_t kNoAllocMaxWave = 65536, kNoAllocMaxChains = 262144;
+struct NoAllocHost {
+  int32_t kmx[kNoAllocMaxWave], gr[2 * kNoAllocMaxWave], order[kNoAllocMaxChains];
+  double t0i[kNoAllocMaxWave];
+  uint64_t wid[kNoAllocMaxWave];
+  int64_t mfo[kNoAllocMaxWave + 1], ws[kNoAllocMaxWave];
+};
+NoAllocHost g_na;
+std::mutex g_na_mutex;  // one allocation-free call at a time in the process (they share g_na)
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on the current device (which must be `device`)
+hipError_t scratch_address(int device, void **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mutex);
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 // ex-Gaussian density (Sec. 3): Gaussian N(mu, sigma^2) convolved with Exp(mean tau)
 double exg(double t, double mu, double sigma, double tau) {
@@ -187,6 +223,9 @@ struct fsmp_ctx {
   // back into the caller's stream with events
   hipStream_t side[kNumCaps] = {};
   hipEvent_t fork = nullptr, join[kNumCaps] = {};
+  // this device's copy of the allocation-free variant's scratch array (null if its address
+  // could not be taken)
+  unsigned char *scratch = nullptr;
   std::string err = "no error";
 };
 
@@ -430,6 +469,12 @@ fsmp_status fsmp_create(fsmp_ctx **out, const fsmp_ser *ser, const fsmp_intensit
     e = hipMemcpy(c->d_ovl, c->tab.ovl.data(), sizeof(double) * c->tab.ovl.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming);
   if (e == hipSuccess) e = ensure_ptab(c, 0);
+  if (e == hipSuccess) {
+    // set-up of the allocation-free variant: the device address of its scratch array
+    void *sp = nullptr;
+    if (scratch_address(device, &sp) == hipSuccess) c->scratch = (unsigned char *)sp;
+    (void)hipGetLastError();
+  }
   (void)hipSetDevice(prev);
   if (e != hipSuccess) {
     fsmp_destroy(c);
@@ -551,7 +596,7 @@ namespace {
 // fsmp_sample, or with `force` set fsmp_replay: the chains follow the recorded proposals
 // and the lane-group kernels with G^-1 in device memory write delta-nu / log-alpha
 fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o, void *hip_stream,
-                        const fsmp_logrec *force, double *rdnu, double *rla) {
+                        const fsmp_logrec *force, double *rdnu, double *rla, bool noalloc = false) {
   if (!c) return FSMP_EINVAL;
   if (!b || !o) return fail(c, FSMP_EINVAL, "null batch or output");
   const fsmp_config &cf = c->cfg;
@@ -572,11 +617,45 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     return fail(c, FSMP_EINVAL, "FSMP_REC_CHARGE set but qdraw or zdraw is NULL");
   if (n > 0 && b->offsets[0] != 0) return fail(c, FSMP_EINVAL, "offsets[0] must be 0");
   const int sub = cf.grid_sub;
-  // ---- per-waveform metadata
-  std::vector<int32_t> kmx(n), gr(2 * n);
-  std::vector<double> t0i(n);
-  std::vector<uint64_t> wid(n);
-  std::vector<int64_t> mfo(n + 1);
+  if (n * (int64_t)cf.n_chains > INT32_MAX) return fail(c, FSMP_EINVAL, "too many chains");
+  // ---- per-waveform metadata: in vectors, or (the allocation-free variant) in the
+  // file-scope host arrays of its largest batch
+  std::vector<int32_t> v_kmx, v_gr, v_order;
+  std::vector<double> v_t0i;
+  std::vector<uint64_t> v_wid;
+  std::vector<int64_t> v_mfo, v_ws;
+  int32_t *kmx, *gr, *order;
+  double *t0i;
+  uint64_t *wid;
+  int64_t *mfo, *wsorted;
+  if (noalloc) {
+    if (n > kNoAllocMaxWave || n * (int64_t)cf.n_chains > kNoAllocMaxChains)
+      return fail(c, FSMP_EINVAL, "fsmp_sample_noalloc takes at most %lld waveforms and %lld chains (got %lld, %lld)",
+                  (long long)kNoAllocMaxWave, (long long)kNoAllocMaxChains, (long long)n,
+                  (long long)(n * cf.n_chains));
+    kmx = g_na.kmx;
+    gr = g_na.gr;
+    order = g_na.order;
+    t0i = g_na.t0i;
+    wid = g_na.wid;
+    mfo = g_na.mfo;
+    wsorted = g_na.ws;
+  } else {
+    v_kmx.resize(n);
+    v_gr.resize(2 * n);
+    v_order.resize((size_t)n * cf.n_chains);
+    v_t0i.resize(n);
+    v_wid.resize(n);
+    v_mfo.resize(n + 1);
+    v_ws.resize(n);
+    kmx = v_kmx.data();
+    gr = v_gr.data();
+    order = v_order.data();
+    t0i = v_t0i.data();
+    wid = v_wid.data();
+    mfo = v_mfo.data();
+    wsorted = v_ws.data();
+  }
   mfo[0] = 0;
   int kmax_all = 0;
   for (int64_t i = 0; i < n; ++i) {
@@ -634,33 +713,32 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     return fail(c, FSMP_EINVAL, "occupancy counts could exceed int32 (n_chains x recorded sweeps x kmax >= 2^31)");
   // ---- chains grouped by PE capacity
   const int *caps = kCaps;
-  std::vector<int32_t> order;
-  order.reserve((size_t)n * cf.n_chains);
+  int64_t n_order = 0;
   int64_t bucket_start[kNumCaps + 1] = {0};
   const bool fp32 = cf.precision == FSMP_FP32_REFRESH;
   auto design_of = [&](int bi) {
     return force ? FSMP_DESIGN_GROUP_DEVMEM : effective_design(c, caps[bi], c->design[bi]);
   };
-  // within a bucket, waveforms in order of lambda: neighbouring lanes then carry chains of
-  // similar PE counts, which keeps the lane-per-chain loops (bounded by the largest K in a
-  // wavefront) short
-  std::vector<int64_t> wsorted(n);
+  // within a bucket, waveforms in order of lambda (equal lambdas in batch order): neighbouring
+  // lanes then carry chains of similar PE counts, which keeps the lane-per-chain loops
+  // (bounded by the largest K in a wavefront) short
   for (int64_t i = 0; i < n; ++i) wsorted[i] = i;
-  std::stable_sort(wsorted.begin(), wsorted.end(), [&](int64_t x, int64_t y) { return b->lambda[x] < b->lambda[y]; });
+  std::sort(wsorted, wsorted + n, [&](int64_t x, int64_t y) {
+    return b->lambda[x] < b->lambda[y] || (b->lambda[x] == b->lambda[y] && x < y);
+  });
   for (int bi = 0; bi < kNumCaps; ++bi) {
-    bucket_start[bi] = (int64_t)order.size();
+    bucket_start[bi] = n_order;
     for (int64_t ii = 0; ii < n; ++ii) {
       const int64_t i = wsorted[ii];
       int kc = chain_kcap_for(kmx[i]);
       if (fp32 && kc == 48) kc = 64;  // the precision form has no capacity-48 instance
       if (kc != caps[bi]) continue;
-      for (int ch = 0; ch < cf.n_chains; ++ch) order.push_back((int32_t)(i * cf.n_chains + ch));
+      for (int ch = 0; ch < cf.n_chains; ++ch) order[n_order++] = (int32_t)(i * cf.n_chains + ch);
     }
   }
-  bucket_start[kNumCaps] = (int64_t)order.size();
-  if ((int64_t)order.size() != n * cf.n_chains)
+  bucket_start[kNumCaps] = n_order;
+  if (n_order != n * cf.n_chains)
     return fail(c, FSMP_ENOTSUP, "kmax above %d is not provided by this build", kCaps[kNumCaps - 1]);
-  if (n * (int64_t)cf.n_chains > INT32_MAX) return fail(c, FSMP_EINVAL, "too many chains");
   for (int bi = 0; bi < kNumCaps; ++bi)
     if (bucket_start[bi + 1] > bucket_start[bi] && !design_available(c, caps[bi], design_of(bi)))
       return fail(c, FSMP_ENOTSUP, "SER support %d too long for the design of PE capacity %d", c->tab.LV, caps[bi]);
@@ -675,86 +753,123 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   (void)hipSetDevice(c->device);
   hipStream_t st = (hipStream_t)hip_stream;
   hipError_t e = hipSuccess;
-  // ---- workspace
-  if (e == hipSuccess) e = c->woff.ensure(n + 1);
-  if (e == hipSuccess) e = c->mfoff.ensure(n + 1);
-  if (e == hipSuccess) e = c->lam.ensure(n);
-  if (e == hipSuccess) e = c->t0init.ensure(n);
-  if (e == hipSuccess) e = c->kmax.ensure(n);
-  if (e == hipSuccess) e = c->grange.ensure(2 * n);
-  if (e == hipSuccess) e = c->wid.ensure(n);
-  if (e == hipSuccess && b->n_steps) e = c->wsteps.ensure(n);
-  if (e == hipSuccess && b->z_init_offsets) e = c->zinit_off.ensure(n * cf.n_chains + 1);
-  if (e == hipSuccess && n_init > 0) e = c->zinit.ensure(n_init);
-  if (e == hipSuccess) e = c->wflags.ensure(n);
-  if (e == hipSuccess) e = c->mf.ensure((size_t)std::max<int64_t>(mfo[n], 1));
-  if (e == hipSuccess) e = c->chains.ensure(order.size());
-  size_t lane_doff[kNumCaps + 1] = {0}, lane_ioff[kNumCaps + 1] = {0};
-  {
-    for (int bi = 0; bi < kNumCaps; ++bi) {
-      const int64_t cnt = bucket_start[bi + 1] - bucket_start[bi];
-      const int dz = design_of(bi);
-      const size_t dd = dz == FSMP_DESIGN_LANE ? lane_ws_doubles(caps[bi], cnt)
-                        : dz == FSMP_DESIGN_GROUP_DEVMEM ? group_dm_ws_doubles(caps[bi], cnt, fp32)
-                                                         : 0;
-      lane_doff[bi + 1] = lane_doff[bi] + dd;
-      lane_ioff[bi + 1] = lane_ioff[bi] + (dz == FSMP_DESIGN_LANE ? lane_ws_ints(caps[bi], cnt) : 0);
-    }
-    if (e == hipSuccess && lane_doff[kNumCaps] > 0) e = c->lane_d.ensure(lane_doff[kNumCaps]);
-    if (e == hipSuccess && lane_ioff[kNumCaps] > 0) e = c->lane_i.ensure(lane_ioff[kNumCaps]);
+  // ---- device workspace: the context's buffers (grown on demand), or in the allocation-free
+  // variant pieces of this device's static scratch array
+  if (noalloc && !c->scratch) {
+    (void)hipSetDevice(prev);
+    return fail(c, FSMP_EDEVICE, "the scratch array of fsmp_sample_noalloc has no address on device %d", c->device);
   }
+  size_t sc_off = 0;
+  bool sc_over = false;
+  auto carve = [&](auto &buf, size_t count) {
+    using T = typename std::remove_pointer<decltype(buf.p)>::type;
+    if (noalloc) {
+      const size_t at = (sc_off + 255) & ~(size_t)255;
+      sc_off = at + std::max<size_t>(count, 1) * sizeof(T);
+      if (sc_off > kScratchBytes) sc_over = true;
+      return sc_over ? (T *)nullptr : (T *)(c->scratch + at);
+    }
+    if (e == hipSuccess) e = buf.ensure(count);
+    return e == hipSuccess ? buf.p : (T *)nullptr;
+  };
+  int64_t *d_woff = carve(c->woff, n + 1);
+  int64_t *d_mfoff = carve(c->mfoff, n + 1);
+  double *d_lam = carve(c->lam, n);
+  double *d_t0init = carve(c->t0init, n);
+  int32_t *d_kmax = carve(c->kmax, n);
+  int32_t *d_grange = carve(c->grange, 2 * n);
+  uint64_t *d_wid = carve(c->wid, n);
+  int32_t *d_wsteps = b->n_steps ? carve(c->wsteps, n) : nullptr;
+  int64_t *d_zinit_off = b->z_init_offsets ? carve(c->zinit_off, n * cf.n_chains + 1) : nullptr;
+  int32_t *d_zinit = n_init > 0 ? carve(c->zinit, n_init) : nullptr;
+  uint32_t *d_wflags = carve(c->wflags, n);
+  double *d_mf = carve(c->mf, (size_t)std::max<int64_t>(mfo[n], 1));
+  int32_t *d_chains = carve(c->chains, n_order);
+  size_t lane_doff[kNumCaps + 1] = {0}, lane_ioff[kNumCaps + 1] = {0};
+  for (int bi = 0; bi < kNumCaps; ++bi) {
+    const int64_t cnt = bucket_start[bi + 1] - bucket_start[bi];
+    const int dz = design_of(bi);
+    const size_t dd = dz == FSMP_DESIGN_LANE ? lane_ws_doubles(caps[bi], cnt)
+                      : dz == FSMP_DESIGN_GROUP_DEVMEM ? group_dm_ws_doubles(caps[bi], cnt, fp32)
+                                                       : 0;
+    lane_doff[bi + 1] = lane_doff[bi] + dd;
+    lane_ioff[bi + 1] = lane_ioff[bi] + (dz == FSMP_DESIGN_LANE ? lane_ws_ints(caps[bi], cnt) : 0);
+  }
+  double *d_lane = lane_doff[kNumCaps] > 0 ? carve(c->lane_d, lane_doff[kNumCaps]) : nullptr;
+  int32_t *d_lanei = lane_ioff[kNumCaps] > 0 ? carve(c->lane_i, lane_ioff[kNumCaps]) : nullptr;
   size_t draw_off[kNumCaps + 1] = {0};
+  double *d_draw = nullptr;
   if (cf.record_flags & FSMP_REC_CHARGE) {
     for (int bi = 0; bi < kNumCaps; ++bi) {
       const int64_t cnt = bucket_start[bi + 1] - bucket_start[bi];
       draw_off[bi + 1] = draw_off[bi] + (size_t)((cnt + 63) / 64 * 64) * caps[bi] * (caps[bi] + 1);
     }
-    if (e == hipSuccess && draw_off[kNumCaps] > 0) e = c->draw_scr.ensure(draw_off[kNumCaps]);
+    if (draw_off[kNumCaps] > 0) d_draw = carve(c->draw_scr, draw_off[kNumCaps]);
+  }
+  if (sc_over) {
+    (void)hipSetDevice(prev);
+    return fail(c, FSMP_EINVAL, "fsmp_sample_noalloc: the batch needs %zu bytes of scratch, the maximum is %zu", sc_off,
+                kScratchBytes);
   }
   if (e == hipSuccess) {
     int64_t tmax = 0;
     for (int64_t i = 0; i < n; ++i) tmax = std::max<int64_t>(tmax, (int64_t)gr[2 * i + 1] - gr[2 * i] + 1);
-    e = ensure_ptab(c, tmax + 1);
+    if (noalloc && !(c->md.ptab && c->md.ptab_n >= tmax + 1)) {
+      (void)hipSetDevice(prev);
+      return fail(c, FSMP_ENOTSUP,
+                  "fsmp_sample_noalloc: a solution space of %lld grid points is longer than the context's light-curve "
+                  "table (%lld); an fsmp_sample call with such a batch grows it",
+                  (long long)tmax, (long long)c->md.ptab_n - 1);
+    }
+    if (!noalloc) e = ensure_ptab(c, tmax + 1);
   }
   if (e != hipSuccess) {
     (void)hipSetDevice(prev);
     return fail(c, FSMP_ENOMEM, "workspace allocation failed: %s", hipGetErrorString(e));
   }
-  // ---- stage metadata through pinned memory (wait until the previous upload is done)
-  if (c->stage_pending) (void)hipEventSynchronize(c->stage_done);
+  // ---- metadata upload: through the context's pinned stage (after its previous upload), or
+  // in the allocation-free variant straight from host memory (pageable: the copy has read it
+  // when hipMemcpyAsync returns)
   auto pad16 = [](size_t nb) { return (nb + 15) & ~(size_t)15; };
-  const size_t bytes = pad16(sizeof(int64_t) * (n + 1)) * 2 + pad16(sizeof(double) * n) * 2 +
-                       pad16(sizeof(int32_t) * n) + pad16(sizeof(int32_t) * 2 * n) + pad16(sizeof(uint64_t) * n) +
-                       pad16(sizeof(int32_t) * order.size()) + pad16(sizeof(int32_t) * n) +
-                       (b->z_init_offsets ? pad16(sizeof(int64_t) * (n * cf.n_chains + 1)) + pad16(sizeof(int32_t) * n_init)
-                                          : 0);
-  e = c->stage.ensure(bytes);
-  if (e != hipSuccess) {
-    (void)hipSetDevice(prev);
-    return fail(c, FSMP_ENOMEM, "pinned staging allocation failed: %s", hipGetErrorString(e));
+  char *sp = nullptr;
+  if (!noalloc) {
+    if (c->stage_pending) (void)hipEventSynchronize(c->stage_done);
+    const size_t bytes = pad16(sizeof(int64_t) * (n + 1)) * 2 + pad16(sizeof(double) * n) * 2 +
+                         pad16(sizeof(int32_t) * n) + pad16(sizeof(int32_t) * 2 * n) + pad16(sizeof(uint64_t) * n) +
+                         pad16(sizeof(int32_t) * n_order) + pad16(sizeof(int32_t) * n) +
+                         (b->z_init_offsets ? pad16(sizeof(int64_t) * (n * cf.n_chains + 1)) + pad16(sizeof(int32_t) * n_init)
+                                            : 0);
+    e = c->stage.ensure(bytes);
+    if (e != hipSuccess) {
+      (void)hipSetDevice(prev);
+      return fail(c, FSMP_ENOMEM, "pinned staging allocation failed: %s", hipGetErrorString(e));
+    }
+    sp = (char *)c->stage.p;
   }
-  char *sp = (char *)c->stage.p;
   auto put = [&](void *dst, const void *src, size_t nb) -> hipError_t {
+    if (noalloc) return hipMemcpyAsync(dst, src, nb, hipMemcpyHostToDevice, st);
     std::memcpy(sp, src, nb);
     hipError_t r = hipMemcpyAsync(dst, sp, nb, hipMemcpyHostToDevice, st);
     sp += pad16(nb);
     return r;
   };
-  if (e == hipSuccess) e = put(c->woff.p, b->offsets, sizeof(int64_t) * (n + 1));
-  if (e == hipSuccess) e = put(c->mfoff.p, mfo.data(), sizeof(int64_t) * (n + 1));
-  if (e == hipSuccess) e = put(c->lam.p, b->lambda, sizeof(double) * n);
-  if (e == hipSuccess) e = put(c->t0init.p, t0i.data(), sizeof(double) * n);
-  if (e == hipSuccess) e = put(c->kmax.p, kmx.data(), sizeof(int32_t) * n);
-  if (e == hipSuccess) e = put(c->grange.p, gr.data(), sizeof(int32_t) * 2 * n);
-  if (e == hipSuccess) e = put(c->wid.p, wid.data(), sizeof(uint64_t) * n);
-  if (e == hipSuccess) e = put(c->chains.p, order.data(), sizeof(int32_t) * order.size());
-  if (e == hipSuccess && b->n_steps) e = put(c->wsteps.p, b->n_steps, sizeof(int32_t) * n);
+  if (e == hipSuccess) e = put(d_woff, b->offsets, sizeof(int64_t) * (n + 1));
+  if (e == hipSuccess) e = put(d_mfoff, mfo, sizeof(int64_t) * (n + 1));
+  if (e == hipSuccess) e = put(d_lam, b->lambda, sizeof(double) * n);
+  if (e == hipSuccess) e = put(d_t0init, t0i, sizeof(double) * n);
+  if (e == hipSuccess) e = put(d_kmax, kmx, sizeof(int32_t) * n);
+  if (e == hipSuccess) e = put(d_grange, gr, sizeof(int32_t) * 2 * n);
+  if (e == hipSuccess) e = put(d_wid, wid, sizeof(uint64_t) * n);
+  if (e == hipSuccess) e = put(d_chains, order, sizeof(int32_t) * n_order);
+  if (e == hipSuccess && b->n_steps) e = put(d_wsteps, b->n_steps, sizeof(int32_t) * n);
   if (e == hipSuccess && b->z_init_offsets && n > 0) {
-    e = put(c->zinit_off.p, b->z_init_offsets, sizeof(int64_t) * (n * cf.n_chains + 1));
-    if (e == hipSuccess && n_init > 0) e = put(c->zinit.p, b->z_init, sizeof(int32_t) * n_init);
+    e = put(d_zinit_off, b->z_init_offsets, sizeof(int64_t) * (n * cf.n_chains + 1));
+    if (e == hipSuccess && n_init > 0) e = put(d_zinit, b->z_init, sizeof(int32_t) * n_init);
   }
-  if (e == hipSuccess) e = hipEventRecord(c->stage_done, st);
-  c->stage_pending = (e == hipSuccess);
+  if (!noalloc) {
+    if (e == hipSuccess) e = hipEventRecord(c->stage_done, st);
+    c->stage_pending = (e == hipSuccess);
+  }
   if (e != hipSuccess) {
     (void)hipSetDevice(prev);
     return fail(c, FSMP_EDEVICE, "metadata upload failed: %s", hipGetErrorString(e));
@@ -776,6 +891,7 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   }
   auto timed = [&](const char *name, int kcap, hipStream_t ks, auto &&launch) -> hipError_t {
     fsmp_timing t{};
+    if (noalloc) return launch(t);  // the allocation-free variant records no timings
     std::snprintf(t.name, sizeof t.name, "%s", name);
     t.kcap = kcap;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -796,11 +912,11 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   pa.md = c->md;
   pa.vtab = c->d_vtab;
   pa.wave = b->wave;
-  pa.woff = c->woff.p;
-  pa.grange = c->grange.p;
-  pa.mfoff = c->mfoff.p;
-  pa.mf = c->mf.p;
-  pa.wflags = c->wflags.p;
+  pa.woff = d_woff;
+  pa.grange = d_grange;
+  pa.mfoff = d_mfoff;
+  pa.mf = d_mf;
+  pa.wflags = d_wflags;
   pa.occ = o->occ;
   pa.n_wave = n;
   e = timed("prologue", 0, st, [&](fsmp_timing &t) {
@@ -814,20 +930,20 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   ca.md = c->md;
   ca.vtab = c->d_vtab;
   ca.ovl = c->d_ovl;
-  ca.woff = c->woff.p;
-  ca.lam = c->lam.p;
-  ca.kmax = c->kmax.p;
-  ca.grange = c->grange.p;
-  ca.t0init = c->t0init.p;
-  ca.wid = c->wid.p;
-  ca.mf = c->mf.p;
-  ca.mfoff = c->mfoff.p;
+  ca.woff = d_woff;
+  ca.lam = d_lam;
+  ca.kmax = d_kmax;
+  ca.grange = d_grange;
+  ca.t0init = d_t0init;
+  ca.wid = d_wid;
+  ca.mf = d_mf;
+  ca.mfoff = d_mfoff;
   ca.n_chains = cf.n_chains;
   ca.n_steps = cf.n_steps;
   ca.burn_in = cf.burn_in;
   ca.thin = cf.thin;
   const int S = cf.n_steps - cf.burn_in;
-  ca.wsteps = b->n_steps ? c->wsteps.p : nullptr;
+  ca.wsteps = d_wsteps;
   ca.rec_steps = o->rec_steps;
   ca.n_rec = (cf.thin > 0 && S > 0) ? (S + cf.thin - 1) / cf.thin : 0;
   ca.key0 = (uint32_t)cf.seed;
@@ -849,17 +965,18 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   ca.rdnu = rdnu;
   ca.rla = rla;
   ca.kz = o->kz;
-  ca.wflags = c->wflags.p;
+  ca.wflags = d_wflags;
   ca.work = o->work;
   ca.occ = o->occ;
   ca.comp = o->comp;
-  ca.zinit = (b->z_init_offsets && n > 0) ? c->zinit.p : nullptr;
-  ca.zinit_off = (b->z_init_offsets && n > 0) ? c->zinit_off.p : nullptr;
+  ca.zinit = (b->z_init_offsets && n > 0) ? d_zinit : nullptr;
+  ca.zinit_off = (b->z_init_offsets && n > 0) ? d_zinit_off : nullptr;
   ca.refresh_M = cf.refresh_M;
   ca.drift_bound = 1e-3;
   int n_buckets = 0;
   for (int bi = 0; bi < kNumCaps; ++bi) n_buckets += bucket_start[bi + 1] > bucket_start[bi];
-  const bool fan = n_buckets > 1;
+  // the allocation-free variant runs the buckets one after the other on the caller's stream
+  const bool fan = n_buckets > 1 && !noalloc;
   // Side streams: no more than the process has hardware queues (GPU_MAX_HW_QUEUES, HIP's
   // default 4), since streams beyond that share a queue and run one after the other. The
   // buckets go to them largest estimated cost first, each to the least loaded stream (cost
@@ -911,16 +1028,16 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
       if (e != hipSuccess) break;
       ks = c->side[sq];
     }
-    ca.chains = c->chains.p + bucket_start[bi];
+    ca.chains = d_chains + bucket_start[bi];
     ca.n_list = cnt;
     char name[32];
     const int dz = design_of(bi);
     std::snprintf(name, sizeof name, "%s%s_k%d",
                   dz == FSMP_DESIGN_LANE ? "chain_lane" : dz == FSMP_DESIGN_GROUP ? "chain_group" : "chain_group_dm",
                   fp32 ? "_fp32" : "", caps[bi]);
-    ca.dws = dz != FSMP_DESIGN_GROUP ? c->lane_d.p + lane_doff[bi] : nullptr;
-    ca.iws = dz == FSMP_DESIGN_LANE ? c->lane_i.p + lane_ioff[bi] : nullptr;
-    ca.dscr = ca.qdraw ? c->draw_scr.p + draw_off[bi] : nullptr;
+    ca.dws = dz != FSMP_DESIGN_GROUP ? d_lane + lane_doff[bi] : nullptr;
+    ca.iws = dz == FSMP_DESIGN_LANE ? d_lanei + lane_ioff[bi] : nullptr;
+    ca.dscr = ca.qdraw ? d_draw + draw_off[bi] : nullptr;
     e = timed(name, caps[bi], ks, [&](fsmp_timing &t) {
       t.chains = cnt;
       return dz == FSMP_DESIGN_LANE    ? launch_chain_lane(caps[bi], ca, ks, &t.lanes, &t.blocks)
@@ -950,6 +1067,12 @@ extern "C" {
 
 fsmp_status fsmp_sample(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o, void *hip_stream) {
   return sample_impl(c, b, o, hip_stream, nullptr, nullptr, nullptr);
+}
+
+fsmp_status fsmp_sample_noalloc(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o, void *hip_stream) {
+  if (!c) return FSMP_EINVAL;
+  std::lock_guard<std::mutex> lk(g_na_mutex);
+  return sample_impl(c, b, o, hip_stream, nullptr, nullptr, nullptr, true);
 }
 
 fsmp_status fsmp_replay(fsmp_ctx *c, const fsmp_batch *b, const fsmp_logrec *log, double *dnu, double *log_alpha,

@@ -24,7 +24,7 @@ EXPORTS = ("fsmp_create", "fsmp_workspace_bytes", "fsmp_sample", "fsmp_posterior
            "fsmp_server_submit", "fsmp_server_progress", "fsmp_server_result", "fsmp_server_stats",
            "fsmp_server_last_error", "fsmp_server_destroy", "fsmp_set_design", "fsmp_get_design", "fsmp_autotune",
            "fsmp_graph_create", "fsmp_graph_launch", "fsmp_graph_destroy", "fsmp_replay",
-           "fsmp_autotune_steps")
+           "fsmp_autotune_steps", "fsmp_sample_noalloc")
 FSMP_DESIGN_GROUP, FSMP_DESIGN_LANE, FSMP_DESIGN_GROUP_DEVMEM = 0, 1, 2
 
 
@@ -117,6 +117,8 @@ def load(path: Optional[str] = None):
     L.fsmp_workspace_bytes.restype = ctypes.c_size_t
     L.fsmp_sample.argtypes = [ctypes.c_void_p, P(fsmp_batch), P(fsmp_samples), ctypes.c_void_p]
     L.fsmp_sample.restype = ctypes.c_int
+    L.fsmp_sample_noalloc.argtypes = [ctypes.c_void_p, P(fsmp_batch), P(fsmp_samples), ctypes.c_void_p]
+    L.fsmp_sample_noalloc.restype = ctypes.c_int
     L.fsmp_posterior.argtypes = [ctypes.c_void_p, ctypes.c_int64, P(fsmp_samples), P(fsmp_posterior_out),
                                  ctypes.c_void_p]
     L.fsmp_posterior.restype = ctypes.c_int
@@ -432,11 +434,12 @@ class Sampler:
         return dnu, la, out
 
     def sample(self, wave, offsets, lam, kmax=None, g_range=None, t0_init=None, wave_id=None, out=None, kz=None,
-               stream=None, work=False, n_steps=None, occupancy=False, z_init=None):
+               stream=None, work=False, n_steps=None, occupancy=False, z_init=None, noalloc=False):
         """wave: torch float32 device tensor; offsets/lam/kmax/g_range/t0_init/wave_id/n_steps: host numpy
         arrays (n_steps: sweeps per waveform, at most the configured n_steps).  occupancy: also count
         the PEs per grid point over the recorded sweeps (out["occ"]).  z_init: one initial PE list
-        (grid indices) per chain, or None for the empty start."""
+        (grid indices) per chain, or None for the empty start.  noalloc: call fsmp_sample_noalloc
+        (pass `out` to keep the call itself free of allocation)."""
         import torch
         b, keep = self._batch(wave, offsets, lam, kmax, g_range, t0_init, wave_id, n_steps, z_init)
         n = int(b.n_wave)
@@ -449,7 +452,8 @@ class Sampler:
         s = self._samples(out)
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._keep = keep
-        self._check(self.lib.fsmp_sample(self.h, ctypes.byref(b), ctypes.byref(s), ctypes.c_void_p(st.cuda_stream)))
+        fn = self.lib.fsmp_sample_noalloc if noalloc else self.lib.fsmp_sample
+        self._check(fn(self.h, ctypes.byref(b), ctypes.byref(s), ctypes.c_void_p(st.cuda_stream)))
         return out
 
     def posterior(self, n_wave, samples, with_pn=True, stream=None, offsets=None, diagnostics=False, lam=None):
