@@ -74,14 +74,15 @@ def parse():
     ap.add_argument("--chain-steps", type=int, default=0, help="fixed sweeps per chain (no step autotuning)")
     ap.add_argument("--target-mcse", type=float, default=0.02,
                     help="relative batch-means MCSE of N the step autotuner aims at")
-    ap.add_argument("--cpu-wave", type=int, default=1000, help="waveforms in the oracle's timed sample")
+    ap.add_argument("--cpu-wave", type=int, default=6000, help="waveforms in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve", action="store_true", help="only the serving study (rates x precisions)")
     ap.add_argument("--serve-events", type=int, default=48, help="events per serving run")
     ap.add_argument("--serve-rates", default="50,100,150,200,300,2000,5000,10000,20000",
                     help="comma-separated event rates (Hz)")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the FP32, batched, Lucy and MCP legs")
+    ap.add_argument("--legs", default="fp32,batched,lucy,mcp",
+                    help="comma-separated extra legs to run (fp32, batched, lucy, mcp; empty: none)")
     ap.add_argument("--lucy-iter", type=int, default=2000, help="Lucy-Richardson iterations of the init stage (0: skip)")
     ap.add_argument("--no-mcp", action="store_true", help="skip the MCP-PMT mixture-law leg")
     ap.add_argument("--pmc-run", action="store_true",
@@ -91,6 +92,9 @@ def parse():
     ap.add_argument("--issue-summary", nargs=2, metavar=("SQ_DIR_A", "SQ_DIR_B"),
                     help="summarise two rocprofv3 --pmc runs of SQ counters into profiles/")
     ap.add_argument("--step-ms", type=float, default=0.0, help="concurrent step time for --issue-summary")
+    ap.add_argument("--precision-study", type=int, default=0, metavar="N_WAVE",
+                    help="only the precision study: FP64 and FP32+refresh against the oracle on N_WAVE high pile-up "
+                         "waveforms per noise level")
     ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "LAST"),
                     help="per-kernel durations of the last LAST dispatches of a rocprofv3 --kernel-trace run")
     return ap.parse_args()
@@ -401,6 +405,69 @@ def timed_steps(smp, one_step, n, warm):
     return (t1 - t0) * 1e3 / n, kernel_ms
 
 
+def precision_study(fsmp, synth, oracle, n_wave, n_steps=1000, refresh_M=64):
+    """The high pile-up precision study (lambda ~ U[20, 100], charges N(1, 0.35), 1,024 samples)
+    at sigma_eps = 0.05, 0.1, 0.2: per form (FP64, FP32+refresh) the relative error of every
+    proposal's delta-nu against the oracle's extended-precision replay of that chain's log,
+    and the relative errors |m - m_oracle| / max(|m_oracle|, 1) of the posterior means of N,
+    total charge and t0 against the oracle's chains (same seeds), with the share of chains
+    identical to the oracle's and the FP64 re-evaluations per proposal."""
+    import concurrent.futures
+    import torch
+    base = synth.PRESETS["pileup"]
+    rows = []
+    for sig in (0.05, 0.1, 0.2):
+        wl = synth.Workload("pileup", n_wave, base.lengths, "uniform", 20.0, 100.0, phi_kind=base.phi_kind,
+                            tau_rise=base.tau_rise, tau_decay=base.tau_decay, sigma_q=0.35, sigma_eps=sig)
+        b = synth.generate(wl, n_wave=n_wave, seed=41)
+        km = synth.kmax_for(b["lam"])
+        kz = int(km.max())
+        burn = n_steps // 2
+        p = oracle.make_params(ser=wl.ser, sigma_eps=sig, mu_q=wl.mu_q, sigma_q=wl.sigma_q, phi_kind=wl.phi_kind,
+                               tau_rise=wl.tau_rise, tau_decay=wl.tau_decay, t0_min=wl.t0_min, t0_max=wl.t0_max)
+        t = time.perf_counter()
+        o = oracle.run(p, b["wave"], b["offsets"], b["lam"], 1, n_steps, burn, 7, kz, kmax=km,
+                       n_threads=int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count())
+        so = oracle.summarize(o.acc, n_steps, burn, 1)
+        print(f"[precision] sigma_eps={sig}: oracle {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
+        wave = torch.from_numpy(b["wave"]).cuda()
+        for prec in (fsmp.FSMP_FP64, fsmp.FSMP_FP32_REFRESH):
+            smp = fsmp.Sampler(ser=wl.ser, phi_kind=wl.phi_kind, tau_rise=wl.tau_rise, tau_decay=wl.tau_decay,
+                               t0_min=wl.t0_min, t0_max=wl.t0_max, sigma_eps=sig, mu_q=wl.mu_q, sigma_q=wl.sigma_q,
+                               n_steps=n_steps, n_chains=1, burn_in=burn, seed=7, device=0, precision=prec,
+                               refresh_M=refresh_M, record_flags=fsmp.FSMP_REC_LOG)
+            out = smp.sample(wave, b["offsets"], b["lam"], kmax=km, kz=kz, work=True)
+            post = smp.posterior(n_wave, out)
+            torch.cuda.synchronize()
+            logs = fsmp.log_records(out["log"])
+            mean = post["mean"].cpu().numpy()
+            work = out["work"].cpu().numpy()
+
+            def one(c):
+                w = b["wave"][b["offsets"][c]:b["offsets"][c + 1]]
+                d, _, bad = oracle.replay(p, w, b["lam"][c], int(km[c]), 0, 4 * len(w) - 1, c, 7, logs[c],
+                                          tie_eps=1e-9, ext=True)
+                v = (logs[c]["flags"] & 1) != 0
+                return np.abs(logs[c]["dnu"][v] - d[v]) / np.maximum(np.abs(d[v]), 1.0), bad
+            with concurrent.futures.ThreadPoolExecutor(max_workers=16) as ex:
+                rep = list(ex.map(one, range(n_wave)))
+            e = np.concatenate([r[0] for r in rep])
+            row = {"sigma_eps": sig, "form": "fp64" if prec == fsmp.FSMP_FP64 else f"fp32+refresh M={refresh_M}",
+                   "proposals": int(e.size), "dnu_rel_err_max": float(e.max()), "dnu_rel_err_p99": float(np.quantile(e, 0.99)),
+                   "dnu_rel_err_median": float(np.median(e)), "decision_flips": int(sum(r[1] for r in rep)),
+                   "chains_identical": float((out["z"].cpu().numpy() == o.z).all(1).mean()),
+                   "fp64_reevaluations_per_proposal": float(work[:, 4].sum() / max(e.size, 1))}
+            for a, name in enumerate(("N", "Q", "t0")):
+                ref = so[name][0]
+                r = np.abs(mean[:, a] - ref) / np.maximum(np.abs(ref), 1.0)
+                row[f"mean_{name}_rel_err_max"] = float(r.max())
+                row[f"mean_{name}_rel_err_median"] = float(np.median(r))
+            rows.append(row)
+            print(f"[precision] {json.dumps(row)}", file=sys.stderr, flush=True)
+            smp.close()
+    return rows
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -425,6 +492,9 @@ def main():
         res = serving_study(fsmp, synth, [float(r) for r in args.serve_rates.split(",")], args.serve_events)
         print(json.dumps({"serving": res}), flush=True)
         return
+    if args.precision_study:
+        print(json.dumps({"precision_study": precision_study(fsmp, synth, oracle, args.precision_study)}), flush=True)
+        return
 
     wl = synth.PRESETS[args.workload]
     n_wave = args.n_wave or wl.n_wave
@@ -442,7 +512,7 @@ def main():
     wave = torch.from_numpy(b["wave"]).to(dev)
     stream = torch.cuda.current_stream(dev)
 
-    def sampler(precision=fsmp.FSMP_FP64, refresh_M=64, chains=wl.n_chains):
+    def sampler(precision=fsmp.FSMP_FP64, refresh_M=128, chains=wl.n_chains):
         return fsmp.Sampler(ser=wl.ser, phi_kind=wl.phi_kind, tau_rise=wl.tau_rise, tau_decay=wl.tau_decay,
                             t0_min=wl.t0_min, t0_max=wl.t0_max, sigma_eps=wl.sigma_eps, mu_q=wl.mu_q,
                             sigma_q=wl.sigma_q, n_steps=n_steps, n_chains=chains, burn_in=burn, seed=wl.seed,
@@ -529,7 +599,8 @@ def main():
     }
 
     # ---- the FP32+refresh form on the same batch and sweeps: one timed step per refresh_M
-    if not args.no_extra:
+    legs = set(x for x in args.legs.split(",") if x)
+    if "fp32" in legs:
         fp32 = []
         for M in (16, 64, 256):
             s32 = sampler(fsmp.FSMP_FP32_REFRESH, M)
@@ -543,7 +614,7 @@ def main():
         res["fp32_refresh"] = fp32
 
     # ---- the batched workload (100,000 x 1,024 samples, 4 chains x 1,000 sweeps): one timed step
-    if not args.no_extra and wl.name != "batched":
+    if "batched" in legs and wl.name != "batched":
         bw = synth.PRESETS["batched"]
         bb = synth.generate(bw, seed=bw.seed)
         bkm = synth.kmax_for(bb["lam"])
@@ -569,7 +640,7 @@ def main():
     # ---- the initialisation stage: Lucy-Richardson deconvolution of every waveform (fsmp_lucy),
     # timed with events on the stream it runs on; algorithmic flops = the two sums of each
     # iteration, 2 (L_w L_V + (L_w + L_V - 1) L_V) per waveform
-    if not args.no_extra and args.lucy_iter > 0:
+    if "lucy" in legs and args.lucy_iter > 0:
         LV = smp.support_samples()
         smp.lucy(wave, b["offsets"], kmax=km, kz=kz, n_iter=args.lucy_iter, stream=stream)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -589,7 +660,7 @@ def main():
         print(f"[bench] lucy {args.lucy_iter} iterations: {lms:.1f} ms", file=sys.stderr, flush=True)
 
     # ---- the MCP-PMT charge law (the paper's five-Gaussian table) on the same batch and sweeps
-    if not args.no_extra and not args.no_mcp:
+    if "mcp" in legs and not args.no_mcp:
         mix = ([0.041, 0.516, 0.187, 0.195, 0.061], [0.92, 1.98, 3.01, 4.70, 6.79], [0.22, 0.48, 0.80, 1.30, 2.04])
         msmp = fsmp.Sampler(ser=wl.ser, phi_kind=wl.phi_kind, tau_rise=wl.tau_rise, tau_decay=wl.tau_decay,
                             t0_min=wl.t0_min, t0_max=wl.t0_max, sigma_eps=wl.sigma_eps, mu_q=wl.mu_q,

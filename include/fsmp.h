@@ -99,14 +99,21 @@ typedef struct {
  * step 1 / grid_sub samples; jump probabilities J, J, 1 - 2J (Sec. 2.4); t0 random-walk
  * step N(0, t0_step_sd^2) and update shift N(0, shift_sd^2) rounded to the grid.
  * Steps [0, burn_in) are not recorded; accumulators use floor(sqrt(n_steps - burn_in))
- * batches for the batch-means MCSE.  precision: FSMP_FP64 (all FP64) or FSMP_FP32_REFRESH:
- * G^-1 stored in FP32 and updated by its rank-one / rank-two edits (computed in FP64,
- * stored rounded); each proposal's delta-nu is evaluated from it with a two-term residual
- * correction against the exact FP64 G (App. A, eqs. 11-18: the quantities delta^2, u+, omega
- * and x_j of the PE-space form), whose last term bounds the error left; the proposal is
- * re-evaluated from an FP64 rebuild of G^-1 when that bound exceeds 1e-5 max(1, |delta-nu|) or
- * could turn the accept decision, and G^-1 and the charges are rebuilt in FP64 every
- * refresh_M sweeps (0: only at those re-evaluations) and at every recorded charge draw. */
+ * batches for the batch-means MCSE.  Both forms rebuild G^-1 = (A^T A + rho I)^-1 and the
+ * charge means x = G^-1 b from scratch in FP64 every refresh_M sweeps (0: never).
+ * precision: FSMP_FP64 (all FP64; from PE capacity 48 up, in the device-memory design the
+ * kernels run there, with the exact G kept beside G^-1 and the residual s = b - G x of the
+ * charge means recomputed after every accepted move, so that gamma^T G^-1 b and x_j enter
+ * delta-nu as gamma^T x + eta^T s and x_j + h^T s, eta = G^-1 gamma, h = row j of G^-1:
+ * FP64 through an explicit inverse alone leaves x with an error of about kappa(G) eps,
+ * about 1e-8 of delta-nu on pile-up windows at K ~ 100) or
+ * FSMP_FP32_REFRESH: G^-1 stored in FP32 and updated by its edits (computed in FP64, stored
+ * rounded), with the exact G kept in FP64; each proposal's delta-nu is evaluated from the
+ * FP32 G^-1 with a two-term residual correction against G (App. A, eqs. 11-18: the quantities
+ * delta^2, u+, omega and x_j of the PE-space form), whose last term bounds the error left; the
+ * proposal is re-evaluated from an FP64 rebuild of G^-1 when that bound exceeds
+ * 1e-5 max(1, |delta-nu|) or could turn the accept decision, and at every recorded charge
+ * draw. */
 typedef struct {
   double sigma_eps, mu_q, sigma_q;
   int32_t grid_sub;      /* 1..16 */
@@ -196,9 +203,10 @@ typedef struct {
  *                             with the birth on K - 1 PEs), [1] the words an accepted move
  *                             must edit (birth K + 3, death (K-1-j)(K-j) + K(K+1)/2, update
  *                             both), [2] the G^-1 elements this library's proposals read
- *                             (K^2 per K x K mat-vec), [3] the G^-1 elements its accepted edits
- *                             read and write (2 K^2 per edit), [4] FP64 re-evaluations of the
- *                             FP32 form
+ *                             (K^2 per K x K mat-vec, K for a row), [3] the G^-1 and G elements
+ *                             its accepted edits read and write (2 K^2 per edit, K^2 more for
+ *                             the residual of the corrected FP64 form), [4] FP64
+ *                             re-evaluations of the FP32 form
  *   rec_steps             NULL, or [chain] the number of recorded sweeps (after burn-in) of
  *                         the chain; required with per-waveform sweep counts, read by
  *                         fsmp_posterior when present

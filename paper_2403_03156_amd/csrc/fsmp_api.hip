@@ -297,7 +297,7 @@ fsmp_status validate_model(const fsmp_ser *ser, const fsmp_intensity *phi, const
   if (cfg->record_flags & ~(uint32_t)(FSMP_REC_TRACE | FSMP_REC_LOG | FSMP_REC_CHARGE))
     return m = "config: unknown record flag", FSMP_EINVAL;
   if (cfg->precision != FSMP_FP64 && cfg->precision != FSMP_FP32_REFRESH) return m = "config: unknown precision", FSMP_EINVAL;
-  if (cfg->precision == FSMP_FP32_REFRESH && cfg->refresh_M < 0) return m = "config: refresh_M must be >= 0", FSMP_EINVAL;
+  if (cfg->refresh_M < 0) return m = "config: refresh_M must be >= 0", FSMP_EINVAL;
   if (cfg->n_mix < 0 || cfg->n_mix > 8) return m = "config: n_mix must be 0..8", FSMP_EINVAL;
   if (cfg->n_mix > 0) {
     double wsum = 0.0;
@@ -719,11 +719,15 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   auto design_of = [&](int bi) {
     return force ? FSMP_DESIGN_GROUP_DEVMEM : effective_design(c, caps[bi], c->design[bi]);
   };
-  // within a bucket, waveforms in order of lambda (equal lambdas in batch order): neighbouring
-  // lanes then carry chains of similar PE counts, which keeps the lane-per-chain loops
-  // (bounded by the largest K in a wavefront) short
+  // within a bucket, waveforms with per-waveform sweep counts in bins of 250 sweeps, the
+  // longest first, so that the chains of a workgroup end together and the longest start
+  // first; within a bin in order of lambda (equal lambdas in batch order): neighbouring lanes
+  // then carry chains of similar PE counts, which keeps the loops (bounded by the largest K
+  // in a wavefront) short
+  auto sbin = [&](int64_t i) { return b->n_steps ? (b->n_steps[i] + 249) / 250 : 0; };
   for (int64_t i = 0; i < n; ++i) wsorted[i] = i;
   std::sort(wsorted, wsorted + n, [&](int64_t x, int64_t y) {
+    if (sbin(x) != sbin(y)) return sbin(x) > sbin(y);
     return b->lambda[x] < b->lambda[y] || (b->lambda[x] == b->lambda[y] && x < y);
   });
   for (int bi = 0; bi < kNumCaps; ++bi) {

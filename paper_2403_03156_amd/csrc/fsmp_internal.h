@@ -70,8 +70,8 @@ struct ChainArgs {
   // 64 chains (element e of the chain in lane l of tile t at (t * E + e) * 64 + l)
   double *dws;
   int32_t *iws;
-  // precision form (FP32 storage of G^{-1}): FP64 refresh every refresh_M sweeps, drift
-  // flag bound
+  // G^-1 rebuilt in FP64 every refresh_M sweeps (0: never; both forms), and the precision
+  // form's drift flag bound
   int32_t refresh_M;
   double drift_bound;
   // charge draws at recorded steps (optional): outputs [chain][n_rec][kz] and FP64

@@ -392,19 +392,30 @@ __global__ void __launch_bounds__(256) prologue_kernel(PrologueArgs a) {
 
 // ------------------------------------------------------------------ chains
 // LDS block of one chain: H (unless it lives in device memory), x, two scratch vectors (six
-// and b in the FP32 form), the accumulators (kAcc doubles: 12 sums, 3 open batch sums, 5 work
-// counters, then 8 int proposal / accept counts and the current run of N: value, first
-// step), then the int grid indices.  The accumulators live in LDS, updated by the group's
-// first lane, to keep registers free; the N histogram is kept in the output row by run
-// lengths.
+// and b in the FP32 form; b and the residual b - G x in the corrected FP64 form), the
+// accumulators (kAcc doubles: 12 sums, 3 open batch sums, 5 work counters, then 8 int
+// proposal / accept counts and the current run of N: value, first step), then the int grid
+// indices.  The accumulators live in LDS, updated by the group's first lane, to keep
+// registers free; the N histogram is kept in the output row by run lengths.
+//
+// kCorr, the corrected FP64 form (H in device memory, capacities from 48 up): FP64 arithmetic through an explicit inverse leaves x = G^-1 b with an error of about
+// kappa(G) eps, which u+ = beta - gamma^T x and x_j carry into delta-nu magnified by
+// 1 / (sigma_eps^2 delta^2) -- about 1e-8 of delta-nu on pile-up windows at K ~ 100, with or
+// without rebuilds of G^-1.  That form keeps the exact G in device memory and the residual
+// s = b - G x (recomputed after every accepted move), and evaluates
+// gamma^T G^-1 b = gamma^T x + eta^T s and x_j = x_j + h^T s (eta = H gamma, h = row j of H),
+// exact to first order in the error of H; the other quantities (delta^2, omega) need no
+// correction at this precision.
 template <int KCAP, bool HG, bool F32 = false, bool MCP = false>
 struct ChainLayout {
   static constexpr int LD = KCAP;
   static constexpr int kAcc = 25;
+  static constexpr bool kCorr = HG && !F32 && KCAP >= 48;
+  static constexpr bool kKeepG = F32 || kCorr;  // the exact G in device memory, b per PE
   // the FP32 form keeps b (matched filter + rho mu_q per PE) for its residuals and refresh,
   // and the vectors of its corrected proposals; the mixture form the PEs' components after
   // their grid indices
-  static constexpr int kVec = F32 ? 8 : 3;
+  static constexpr int kVec = F32 ? 8 : (kCorr ? 5 : 3);
   static constexpr int kDoubles =
       (HG ? 0 : KCAP * KCAP) + kVec * KCAP + kAcc + (KCAP + 1) / 2 + (MCP ? (KCAP + 1) / 2 : 0);
 };
@@ -451,31 +462,60 @@ __device__ inline void grp_col_update(MT *H, int i, int N, double ai, const doub
   }
 }
 
-// Residuals against the exact Gram matrix G = A^T A + rho I of the PE list zg[0..N), its
-// entries taken from the SER overlap tables, for the rows i owned by this lane of the group:
-//   o1 = t1 - G v1 (t1 the unit vector at u1 when null),  o2 = t2 - G v2.
-// Row `skip` (-1: none) is left out: its outputs are 0, and v1, v2 must be 0 there, so that
-// the products are those of G without row and column `skip`.  Terms in column order.
-template <int LPC>
-__device__ inline void gram_resid2(const ModelDev &md, const double *vt, const double *ov, int Lw, const int *zg, int N,
-                                   int skip, int lane, const double *t1, int u1, const double *v1, const double *t2,
-                                   const double *v2, double *o1, double *o2) {
+// Residuals against the exact Gram matrix G = A^T A + rho I of the PE list (FP64, kept in
+// device memory in the layout of H), for the rows i owned by this lane of the group:
+//   r1 = g1 - G v1 (if v1),  r2 = e_u2 - G v2 (if v2; e_u2 the unit vector at u2),
+//   r3 = t3 - G v3.
+// Loads in chunks of 8 rows as in grp_col_dot, terms in row order.
+template <int LPC, int LD, int HS>
+__device__ inline void gram_resid3(const double *Gm, int N, int lane, const double *g1, const double *v1, int u2,
+                                   const double *v2, const double *t3, const double *v3, double *r1, double *r2,
+                                   double *r3) {
   for (int i = lane; i < N; i += LPC) {
-    if (i == skip) {
-      o1[i] = 0.0;
-      o2[i] = 0.0;
-      continue;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int k0 = 0; k0 < N; k0 += 8) {
+      double g[8], x1[8], x2[8], x3[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        g[u] = Gm[((k0 + u) * LD + i) * HS];
+        x1[u] = v1 ? v1[k0 + u] : 0.0;
+        x2[u] = v2 ? v2[k0 + u] : 0.0;
+        x3[u] = v3[k0 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool in = k0 + u < N;
+        a = in ? a + g[u] * x1[u] : a;
+        b = in ? b + g[u] * x2[u] : b;
+        c = in ? c + g[u] * x3[u] : c;
+      }
     }
-    const int gi = zg[i];
-    double a = 0.0, b = 0.0;
-    for (int k = 0; k < N; ++k) {
-      const double g = overlap(md, vt, ov, gi, zg[k], Lw) + (k == i ? md.rho : 0.0);
-      a += g * v1[k];
-      b += g * v2[k];
-    }
-    o1[i] = (t1 ? t1[i] : (i == u1 ? 1.0 : 0.0)) - a;
-    o2[i] = t2[i] - b;
+    if (v1) r1[i] = g1[i] - a;
+    if (v2) r2[i] = (i == u2 ? 1.0 : 0.0) - b;
+    r3[i] = t3[i] - c;
   }
+}
+
+// s = b - G x against the exact G, for the rows i owned by this lane of the group
+template <int LPC, int LD, int HS>
+__device__ inline void gram_resid_b(const double *Gm, const double *bv, const double *xv, double *rs, int N,
+                                    int lane) {
+  for (int i = lane; i < N; i += LPC) rs[i] = bv[i] - grp_col_dot<LD, HS>(Gm, xv, i, N);
+}
+
+// column i of G (overlap tables, plus the PE's own ridge rho_g on the diagonal) for the PE at
+// grid point g against the list zg[0..N), written as row and column i of Gm by the lanes of
+// the group (g's own entry by the first lane); zg[i] is not read
+template <int LPC, int LD, int HS>
+__device__ inline void gram_set(const ModelDev &md, const double *vt, const double *ov, int Lw, double *Gm,
+                                const int *zg, int N, int i, int g, double rho_g, int lane) {
+  for (int k = lane; k < N; k += LPC) {
+    if (k == i) continue;
+    const double v = overlap(md, vt, ov, g, zg[k], Lw);
+    Gm[(i * LD + k) * HS] = v;
+    Gm[(k * LD + i) * HS] = v;
+  }
+  if (lane == 0) Gm[(i * LD + i) * HS] = overlap(md, vt, ov, g, g, Lw) + rho_g;
 }
 
 template <int W>
@@ -485,20 +525,18 @@ __device__ inline double group_max(double v) {
   return v;
 }
 
-// Precision form, lane groups: rebuild G^{-1} of the current PE list in FP64 into W by
-// bordering (each step is the birth update of the inverse of the leading block, its
-// columns owned by the group's lanes), recompute x = G^{-1} b in FP64 and round W into
-// the FP32 H.  False if a Schur complement is not positive.  `drift` = the largest change
-// of a charge mean, relative to max(1, |x|).  s1, s2 are scratch.
-// G^-1 of the PE list zg[0..N) by bordering, in FP64 into M (device-memory layout of the
-// lane-group kernels): false if a Schur complement is not positive.  s1, s2: scratch.
+// G^-1 of the PE list zg[0..N) by bordering, in FP64 into M (layout of the lane-group
+// kernels; M may hold the old G^-1: only its leading block built so far is read), each step
+// the birth update of the inverse of the leading block, its columns owned by the group's
+// lanes: false if a Schur complement is not positive.  ek: the PEs' mixture components (their
+// own ridge rho_e on the diagonal), or null for the single charge law.  s1, s2: scratch.
 template <int LPC, int LD, int HS>
 __device__ bool grp_build(const ModelDev &md, const double *vt, const double *ov, int Lw, double *M, double *s1,
-                          double *s2, const int *zg, int N, int lane) {
+                          double *s2, const int *zg, int N, int lane, const int *ek = nullptr) {
   for (int k = 0; k < N; ++k) {
     const int gk = zg[k];
     for (int i = lane; i < k; i += LPC) s1[i] = overlap(md, vt, ov, gk, zg[i], Lw);
-    const double d = overlap(md, vt, ov, gk, gk, Lw) + md.rho;
+    const double d = overlap(md, vt, ov, gk, gk, Lw) + (ek ? md.mix_rho[ek[k]] : md.rho);
     WAVE_SYNC();
     double q = 0.0;
     for (int i = lane; i < k; i += LPC) {
@@ -523,6 +561,9 @@ __device__ bool grp_build(const ModelDev &md, const double *vt, const double *ov
   return true;
 }
 
+// Precision form: rebuild G^-1 of the current PE list in FP64 into W, recompute x = G^-1 b in
+// FP64 and round W into the FP32 H.  False if a Schur complement is not positive.  `drift` =
+// the largest change of a charge mean, relative to max(1, |x|).  s1, s2 are scratch.
 template <int LPC, int LD, int HS, typename HT>
 __device__ bool grp_refresh(const ModelDev &md, const double *vt, const double *ov, int Lw, double *W, HT *H,
                             double *xv, const double *bv, double *s1, double *s2, const int *zg, int N, int lane,
@@ -574,21 +615,28 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
   if (slot >= a.n_list) return;
 
   double *cb = smem + md.M * (1 + md.sub) + (KCAP + 2) + (int64_t)(wv * CPW + grp) * CL::kDoubles;
-  // device memory of a tile (the wavefront's chains interleaved element by element): H in
-  // its storage type, then in the FP32 form the FP64 refresh matrix W
+  // device memory of a tile (the wavefront's chains interleaved element by element): H in its
+  // storage type; in the FP32 form then the FP64 refresh matrix W and the exact G (FP64), in
+  // the corrected FP64 form the exact G
+  constexpr bool CORR = CL::kCorr, KEEPG = CL::kKeepG;
   constexpr int64_t kHD = (int64_t)KCAP * LD * CPW * (int64_t)sizeof(HT) / 8;
-  constexpr int64_t kTile = kHD + (F32 ? (int64_t)KCAP * LD * CPW : 0);
+  constexpr int64_t kTile = kHD + (F32 ? 2 : CORR ? 1 : 0) * (int64_t)KCAP * LD * CPW;
   HT *H = HG ? (HT *)(a.dws + tile * kTile) + grp : (HT *)cb;
   double *W = F32 ? a.dws + tile * kTile + kHD + grp : nullptr;
+  double *Gm = F32    ? a.dws + tile * kTile + kHD + (int64_t)KCAP * LD * CPW + grp
+               : CORR ? a.dws + tile * kTile + kHD + grp
+                      : nullptr;
   double *xv = HG ? cb : cb + KCAP * LD;
   double *s1 = xv + KCAP;
   double *s2 = s1 + KCAP;
-  // FP32 form: four more scratch vectors and b of each PE
+  // FP32 form: four more scratch vectors and b of each PE; corrected FP64 form: b and the
+  // residual s = b - G x
   double *s3 = F32 ? s2 + KCAP : nullptr;
   double *s4 = F32 ? s3 + KCAP : nullptr;
   double *s5 = F32 ? s4 + KCAP : nullptr;
   double *s6 = F32 ? s5 + KCAP : nullptr;
-  double *bv = F32 ? s6 + KCAP : nullptr;
+  double *bv = F32 ? s6 + KCAP : CORR ? s2 + KCAP : nullptr;
+  double *rs = CORR ? bv + KCAP : nullptr;
   double *acc = xv + CL::kVec * KCAP;  // [0..11] sums, [12..14] open batch sums, [15..19] work counters
   int *cnt = (int *)(acc + 20);
   int *run = cnt + 8;  // N of the current run among the recorded steps (-1: none yet), its first step
@@ -654,10 +702,17 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         WAVE_SYNC();
         for (int i = lane; i < n0; i += LPC) {
           xv[i] = grp_col_dot<LD, HS>(M, s1, i, n0);
-          if constexpr (F32) {
+          if constexpr (KEEPG) {
             bv[i] = s1[i];
-            for (int k = 0; k < n0; ++k) H[(k * LD + i) * HS] = (HT)W[(k * LD + i) * HS];
+            for (int k = 0; k < n0; ++k) {
+              if constexpr (F32) H[(k * LD + i) * HS] = (HT)W[(k * LD + i) * HS];
+              Gm[(k * LD + i) * HS] = overlap(md, vt, ov, zg[k], zg[i], Lw) + (k == i ? md.rho : 0.0);
+            }
           }
+        }
+        if constexpr (CORR) {
+          WAVE_SYNC();
+          gram_resid_b<LPC, LD, HS>(Gm, bv, xv, rs, n0, lane);
         }
         N = n0;
         double sn = 0.0;
@@ -676,12 +731,27 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
     }
   }
   for (int step = 0; step < n_steps; ++step) {
-    if constexpr (F32) {
-      if (a.refresh_M > 0 && step > 0 && step % a.refresh_M == 0 && N > 0) {
+    if (a.refresh_M > 0 && step > 0 && step % a.refresh_M == 0 && N > 0) {
+      if constexpr (F32) {
         // precision form: FP64 rebuild of G^{-1} every refresh_M sweeps
         double drift;
         if (!grp_refresh<LPC, LD, HS>(md, vt, ov, Lw, W, H, xv, bv, s1, s2, zg, N, lane, drift)) st |= FSMP_ST_FACTOR;
         else if (drift > a.drift_bound) st |= FSMP_ST_DRIFT;
+      } else {
+        // FP64 form: G^-1 rebuilt in place by bordering and x = G^-1 b recomputed, against the
+        // rounding the rank-one and rank-two edits accumulate
+        if (grp_build<LPC, LD, HS>(md, vt, ov, Lw, (double *)H, s1, s2, zg, N, lane, MCP ? ek : nullptr)) {
+          for (int i = lane; i < N; i += LPC) s1[i] = mf[zg[i] - glo] + (MCP ? md.mix_rhom[ek[i]] : md.rhom);
+          WAVE_SYNC();
+          for (int i = lane; i < N; i += LPC) xv[i] = grp_col_dot<LD, HS>((double *)H, s1, i, N);
+          WAVE_SYNC();
+          if constexpr (CORR) {
+            gram_resid_b<LPC, LD, HS>(Gm, bv, xv, rs, N, lane);
+            WAVE_SYNC();
+          }
+        } else {
+          st |= FSMP_ST_FACTOR;
+        }
       }
     }
     // The step's random words and the logs of its three uniforms (Box-Muller radius, t0
@@ -776,7 +846,9 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
     // (deaths, shifts) evaluated with the residual correction
     bool valid = false, need_mv = false, need_dp = false;
     double dnu = 0.0, la = -INFINITY, lpn = 0.0, lpo = 0.0;
-    double delta2 = 1.0, up = 0.0, om = 1.0, xj = 0.0, ej = 0.0, beta = 0.0;
+    // xjp: x_j as stored (the corrected FP64 form evaluates with xj = x_j + h^T s and edits x
+    // with the stored value, which keeps x = H b along the edits)
+    double delta2 = 1.0, up = 0.0, om = 1.0, xj = 0.0, xjp = 0.0, ej = 0.0, beta = 0.0;
     // mixture form: the component of a born or updated PE from word r7 (inverse CDF of the
     // weights); rho, its log, rho mu, rho mu^2 of the new and of the removed / moved PE
     int enew = 0;
@@ -810,7 +882,12 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
           need_dp = true;
         } else {
           om = H[(j * LD + j) * HS];
-          xj = xv[j];
+          xj = xjp = xv[j];
+          if constexpr (CORR) {
+            double xc = 0.0;
+            for (int i = lane; i < N; i += LPC) xc += H[(j * LD + i) * HS] * rs[i];
+            xj += group_sum<LPC>(xc);
+          }
           if constexpr (MCP) {
             lro = md.mix_lrho[ek[j]];
             rm2o = md.mix_rhom2[ek[j]];
@@ -862,15 +939,23 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
       const double d = overlap(md, vt, ov, gnew, gnew, Lw) + rn;
       beta = mf[gnew - glo] + rmn;
       WAVE_SYNC();
-      double q = 0.0, p = 0.0;
+      double q = 0.0, p = 0.0, pc = 0.0, xc = 0.0;
       for (int i = lane; i < N; i += LPC) {
         const double e = grp_col_dot<LD, HS>(M, s1, i, N);
         s2[i] = e;
         q += s1[i] * e;
         p += s1[i] * xv[i];
+        if constexpr (CORR) {
+          pc += e * rs[i];
+          if (move == 3) xc += (double)M[(j * LD + i) * HS] * rs[i];
+        }
       }
       q = group_sum<LPC>(q);
       p = group_sum<LPC>(p);
+      if constexpr (CORR) {
+        p += group_sum<LPC>(pc);
+        if (move == 3) xc = group_sum<LPC>(xc);
+      }
       if (move == 1) {
         delta2 = d - q;
         if (delta2 > 0.0) {
@@ -886,7 +971,8 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
       } else {
         WAVE_SYNC();
         om = (double)M[(j * LD + j) * HS];
-        xj = xv[j];
+        xj = xjp = xv[j];
+        if constexpr (CORR) xj += xc;
         ej = s2[j];
         delta2 = d - (q - ej * ej / om);
         up = beta - (p - ej * xj / om);
@@ -904,19 +990,22 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
       }
     };
     // The FP32 form evaluates a proposal from its FP32 H with a two-term correction against
-    // the exact G, whose entries come from the overlap tables:
-    //   death part (deaths, shifts): h = row j of H, r = e_j - G h, s = b - G x, then
-    //     omega = h_j + h^T r + r^T H r,  x_j = x_j + h^T s + (H r)^T s,  u = h + H r
-    //     (u: G^-1 e_j to second order);
-    //   birth part (births; shifts on the PEs without j, through the inverse of G without row
-    //     and column j, Hj = H - u u^T / omega): gamma, eta = Hj gamma, x~ = x (birth) or
-    //     x - u x_j / omega (shift), r = gamma - G eta, s = b - G x~, then
-    //     q = gamma^T eta + eta^T r + r^T Hj r,  p = gamma^T x~ + eta^T s + (Hj r)^T s,
-    //     v = eta + Hj r;
-    // delta^2 = d - q, u+ = beta - p.  The first correction term cancels the first-order error
-    // of the FP32 inverse exactly; the size of the second bounds what is left (the error
-    // contracts by the factor |I - H G| per term).  bnd is that bound carried into delta-nu
-    // to first order, times four.  Vectors: u in s1, v (or eta) in s3.
+    // the exact G (FP64 in device memory, kept with the list).  For a vector f and its
+    // approximate solve a = H f, the residual r = f - G a and the correction H r, the bilinear
+    // form f'^T G^-1 f is f'^T a + a^T r' + r^T H r' to second order in the error of H (the
+    // first term of the correction cancels the first-order error exactly; the last term is
+    // the size of what is corrected at second order, taken as the bound of what is left, as
+    // the error contracts by |I - H G| per term).  The vectors are gamma (the new position's
+    // overlaps, 0 at j for a shift: births and shifts), e_j (deaths and shifts) and b:
+    //   Qgg = gamma^T G^-1 gamma, Qjg = e_j^T G^-1 gamma, omega = (G^-1)_jj,
+    //   Pg = gamma^T G^-1 b, xj = e_j^T G^-1 b,
+    // from one pass over H (eta = H gamma, h = row j), one over G (r_eta, r_h, s = b - G x)
+    // and one over H again (H r_eta, H r_h).  A shift's birth part is on the PEs without j, by
+    // the identities (G without j)^-1 = (G^-1 - u u^T / omega) there, u = G^-1 e_j:
+    //   delta^2 = d - (Qgg - Qjg^2 / omega),  u+ = beta - (Pg - Qjg xj / omega),
+    // with each bound carried through them.  bnd is the bound of delta-nu to first order, times
+    // four.  Vectors left for the edit: u = h + H r_h in s1, eta + H r_eta (for a shift minus
+    // u Qjg / omega, 0 at j) in s3.
     double bnd = 0.0;
     bool inexact = false;
     auto f32_dnu = [&](double Bom, double Bxj, double Bq, double Bp) {
@@ -945,97 +1034,122 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
     };
     auto f32_eval = [&]() {
       valid = false;
-      double Bom = 0.0, Bxj = 0.0, Bq = 0.0, Bp = 0.0;
-      if (need_dp) {
-        for (int i = lane; i < N; i += LPC) s1[i] = (double)H[(j * LD + i) * HS];
-        WAVE_SYNC();
-        gram_resid2<LPC>(md, vt, ov, Lw, zg, N, -1, lane, nullptr, j, s1, bv, xv, s3, s4);
-        WAVE_SYNC();
-        double a1 = 0.0, a2 = 0.0, c1 = 0.0, c2 = 0.0;
-        for (int i = lane; i < N; i += LPC) {
-          const double hr = grp_col_dot<LD, HS>(H, s3, i, N);
-          a1 += s1[i] * s3[i];
-          a2 += s1[i] * s4[i];
-          c1 += s3[i] * hr;
-          c2 += hr * s4[i];
-          s5[i] = hr;
+      const bool wg = need_mv, wj = need_dp;  // gamma (births, shifts), e_j (deaths, shifts)
+      const int jz = move == 3 ? j : -1;
+      double d = 0.0;
+      if (wg) {
+        for (int i = lane; i < N; i += LPC) s2[i] = (i == jz) ? 0.0 : overlap(md, vt, ov, gnew, zg[i], Lw);
+        d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
+        beta = mf[gnew - glo] + md.rhom;
+      }
+      WAVE_SYNC();
+      // pass 1 over H: eta = H gamma, h = row j; gamma^T eta, gamma^T x
+      double qa = 0.0, pa = 0.0;
+      for (int i = lane; i < N; i += LPC) {
+        if (wg) {
+          const double e = grp_col_dot<LD, HS>(H, s2, i, N);
+          s3[i] = e;
+          qa += s2[i] * e;
+          pa += s2[i] * xv[i];
         }
-        a1 = group_sum<LPC>(a1);
-        a2 = group_sum<LPC>(a2);
-        c1 = group_sum<LPC>(c1);
-        c2 = group_sum<LPC>(c2);
-        WAVE_SYNC();
-        om = s1[j] + a1 + c1;
-        xj = xv[j] + a2 + c2;
-        Bom = fabs(c1);
-        Bxj = fabs(c2);
-        WAVE_SYNC();
-        for (int i = lane; i < N; i += LPC) s1[i] += s5[i];
-        WAVE_SYNC();
+        if (wj) s1[i] = (double)H[(j * LD + i) * HS];
+      }
+      if (wg) {
+        qa = group_sum<LPC>(qa);
+        pa = group_sum<LPC>(pa);
+      }
+      WAVE_SYNC();
+      // the residuals against G: r_eta = gamma - G eta (s5), r_h = e_j - G h (s4), s = b - G x (s6)
+      gram_resid3<LPC, LD, HS>(Gm, N, lane, s2, wg ? s3 : nullptr, j, wj ? s1 : nullptr, bv, xv, s5, s4, s6);
+      WAVE_SYNC();
+      double eta_j = 0.0, h_j = 0.0, x_j = 0.0;
+      if (wj) {
+        eta_j = wg ? s3[j] : 0.0;
+        h_j = s1[j];
+        x_j = xv[j];
+      }
+      // first correction terms
+      double qb = 0.0, pb = 0.0, jb = 0.0, ob = 0.0, xb = 0.0;
+      for (int i = lane; i < N; i += LPC) {
+        if (wg) {
+          qb += s3[i] * s5[i];
+          pb += s3[i] * s6[i];
+        }
+        if (wj) {
+          if (wg) jb += s1[i] * s5[i];
+          ob += s1[i] * s4[i];
+          xb += s1[i] * s6[i];
+        }
+      }
+      if (wg) {
+        qb = group_sum<LPC>(qb);
+        pb = group_sum<LPC>(pb);
+      }
+      if (wj) {
+        if (wg) jb = group_sum<LPC>(jb);
+        ob = group_sum<LPC>(ob);
+        xb = group_sum<LPC>(xb);
+      }
+      // pass 2 over H: H r_eta, H r_h; the second terms, then eta and h corrected in place
+      double qc = 0.0, pc = 0.0, jc = 0.0, oc = 0.0, xc = 0.0;
+      for (int i = lane; i < N; i += LPC) {
+        double te = 0.0, th = 0.0;
+        if (wg) {
+          te = grp_col_dot<LD, HS>(H, s5, i, N);
+          qc += s5[i] * te;
+          pc += te * s6[i];
+        }
+        if (wj) {
+          th = grp_col_dot<LD, HS>(H, s4, i, N);
+          if (wg) jc += s4[i] * te;
+          oc += s4[i] * th;
+          xc += th * s6[i];
+        }
+        if (wg) s3[i] += te;
+        if (wj) s1[i] += th;
+      }
+      double Qgg = 0.0, Pg = 0.0, Qjg = 0.0, Bgg = 0.0, Bp = 0.0, Bjg = 0.0, Bom = 0.0, Bxj = 0.0;
+      if (wg) {
+        qc = group_sum<LPC>(qc);
+        pc = group_sum<LPC>(pc);
+        Qgg = qa + qb + qc;
+        Pg = pa + pb + pc;
+        Bgg = fabs(qc);
+        Bp = fabs(pc);
+      }
+      if (wj) {
+        if (wg) jc = group_sum<LPC>(jc);
+        oc = group_sum<LPC>(oc);
+        xc = group_sum<LPC>(xc);
+        om = h_j + ob + oc;
+        xj = x_j + xb + xc;
+        Qjg = eta_j + jb + jc;
+        Bom = fabs(oc);
+        Bxj = fabs(xc);
+        Bjg = fabs(jc);
         if (!(om > 0.0) || !(Bom < 0.1 * om)) {
           inexact = true;
           return;
         }
       }
-      if (need_mv) {
-        const int jz = move == 3 ? j : -1;
-        for (int i = lane; i < N; i += LPC) s2[i] = (i == jz) ? 0.0 : overlap(md, vt, ov, gnew, zg[i], Lw);
-        const double d = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
-        beta = mf[gnew - glo] + md.rhom;
+      WAVE_SYNC();
+      double Bq = Bgg;
+      if (move == 1) {
+        delta2 = d - Qgg;
+        up = beta - Pg;
+      } else if (move == 3) {
+        const double cj = Qjg / om, cx = xj / om;
+        delta2 = d - (Qgg - Qjg * cj);
+        up = beta - (Pg - Qjg * cx);
+        Bq = Bgg + 2.0 * fabs(cj) * Bjg + cj * cj * Bom;
+        Bp = Bp + fabs(cx) * Bjg + fabs(cj) * Bxj + fabs(cj * cx) * Bom;
+        // v = eta - u Qjg / omega on the PEs without j
+        for (int i = lane; i < N; i += LPC) s3[i] = (i == j) ? 0.0 : s3[i] - s1[i] * cj;
         WAVE_SYNC();
-        double gg = 0.0;
-        for (int i = lane; i < N; i += LPC) {
-          s3[i] = grp_col_dot<LD, HS>(H, s2, i, N);
-          gg += s1[i] * s2[i];
-        }
-        const double *xt = xv;
-        if (move == 3) {
-          gg = group_sum<LPC>(gg);
-          const double cg = gg / om, cx = xj / om;
-          for (int i = lane; i < N; i += LPC) {
-            s3[i] = (i == j) ? 0.0 : s3[i] - s1[i] * cg;
-            s4[i] = (i == j) ? 0.0 : xv[i] - s1[i] * cx;
-          }
-          xt = s4;
-        }
-        WAVE_SYNC();
-        gram_resid2<LPC>(md, vt, ov, Lw, zg, N, jz, lane, s2, -1, s3, bv, xt, s5, s6);
-        WAVE_SYNC();
-        double qa = 0.0, pa = 0.0, qb = 0.0, pb = 0.0, gr = 0.0;
-        for (int i = lane; i < N; i += LPC) {
-          qa += s2[i] * s3[i];
-          pa += s2[i] * xt[i];
-          qb += s3[i] * s5[i];
-          pb += s3[i] * s6[i];
-          gr += s1[i] * s5[i];
-        }
-        qa = group_sum<LPC>(qa);
-        pa = group_sum<LPC>(pa);
-        qb = group_sum<LPC>(qb);
-        pb = group_sum<LPC>(pb);
-        if (move == 3) gr = group_sum<LPC>(gr);
-        WAVE_SYNC();
-        const double cr = move == 3 ? gr / om : 0.0;
-        double qc = 0.0, pc = 0.0;
-        for (int i = lane; i < N; i += LPC) {
-          double t = grp_col_dot<LD, HS>(H, s5, i, N);
-          if (move == 3) t = (i == j) ? 0.0 : t - s1[i] * cr;
-          qc += s5[i] * t;
-          pc += t * s6[i];
-          s2[i] = t;
-        }
-        qc = group_sum<LPC>(qc);
-        pc = group_sum<LPC>(pc);
-        for (int i = lane; i < N; i += LPC) s3[i] += s2[i];
-        WAVE_SYNC();
-        Bq = fabs(qc);
-        Bp = fabs(pc);
-        delta2 = d - (qa + qb + qc);
-        up = beta - (pa + pb + pc);
-        if (!(delta2 > 0.0) || !(Bq < 0.1 * delta2)) {
-          inexact = true;
-          return;
-        }
+      }
+      if (move != 2 && (!(delta2 > 0.0) || !(Bq < 0.1 * delta2))) {
+        inexact = true;
+        return;
       }
       f32_dnu(Bom, Bxj, Bq, Bp);
     };
@@ -1105,10 +1219,11 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
                                   (need_dp ? (double)N : 0.0);
       }
     } else if (need_mv) {
-      if (lane == 0) acc[17] += (double)N * N;
+      // (the corrected form also reads row j of H for a shift's x_j)
+      if (lane == 0) acc[17] += (double)N * N + (CORR && move == 3 ? (double)N : 0.0);
       eval_mv(H);
     } else if (move == 2 && valid && lane == 0) {
-      acc[17] += 1.0;
+      acc[17] += CORR ? (double)N : 1.0;
     }
     // the survey's word count of the proposal (a packed Cholesky factor): birth K(K+1)/2 +
     // 2K + 3, death (K - j)(K - j + 1)/2 + 1, update both (the birth on K - 1 PEs)
@@ -1159,11 +1274,12 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         const double *U = move == 1 ? EV : s1;
         const double *V = shift ? EV : U;
         const double cu = move == 1 ? inv_d2 : -inv_om, cv = shift ? inv_d2 : 0.0;
+        const double xe = CORR ? xjp : xj;
         for (int i = lane; i < N; i += LPC) {
           const double ui = U[i], vi = V[i];
           if (move == 1) xv[i] -= ui * xn;
-          else if (move == 2) xv[i] -= ui * xj * inv_om;
-          else xv[i] = (i == j) ? xn : xv[i] - ui * xj * inv_om - vi * xn;
+          else if (move == 2) xv[i] -= ui * xe * inv_om;
+          else xv[i] = (i == j) ? xn : xv[i] - ui * xe * inv_om - vi * xn;
           grp_col_update<LD, HS, true>(H, i, N, ui, U, cu, vi, V, cv);
           if (move == 1) {
             H[(N * LD + i) * HS] = -ui * inv_d2;
@@ -1171,13 +1287,35 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
           }
         }
         WAVE_SYNC();
+        // the exact G follows the list: the new PE's row and column, or the last PE's moved
+        // into a freed slot (s2 is free once the edit is done)
+        if constexpr (KEEPG) {
+          if (move == 1) {
+            gram_set<LPC, LD, HS>(md, vt, ov, Lw, Gm, zg, N, N, gnew, rn, lane);
+          } else if (move == 3) {
+            gram_set<LPC, LD, HS>(md, vt, ov, Lw, Gm, zg, N, j, gnew, rn, lane);
+          } else if (j != N - 1) {
+            const int last = N - 1;
+            for (int i = lane; i < N; i += LPC) s2[i] = Gm[(last * LD + i) * HS];
+            WAVE_SYNC();
+            const double gd = s2[last];
+            for (int i = lane; i < N; i += LPC) {
+              if (i == j) {
+                Gm[(j * LD + j) * HS] = gd;
+              } else {
+                Gm[(j * LD + i) * HS] = s2[i];
+                Gm[(i * LD + j) * HS] = s2[i];
+              }
+            }
+          }
+        }
         if (move == 1) {
           if (lane == 0) {
             H[(N * LD + N) * HS] = inv_d2;
             zg[N] = gnew;
             if constexpr (MCP) ek[N] = enew;
             xv[N] = xn;
-            if (F32) bv[N] = beta;
+            if (KEEPG) bv[N] = beta;
           }
           N++;
           if (biexp) S_cur += rise_term(md, gnew, t0);
@@ -1200,7 +1338,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
               zg[j] = zg[last];
               if constexpr (MCP) ek[j] = ek[last];
               xv[j] = xv[last];
-              if (F32) bv[j] = bv[last];
+              if (KEEPG) bv[j] = bv[last];
             }
           }
           N--;
@@ -1218,11 +1356,17 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
           if (lane == 0) {
             zg[j] = gnew;
             if constexpr (MCP) ek[j] = enew;
-            if (F32) bv[j] = beta;
+            if (KEEPG) bv[j] = beta;
           }
           if (biexp) S_cur += rise_term(md, gnew, t0) - rise_term(md, gj, t0);
         }
         WAVE_SYNC();
+        // the corrected FP64 form: the residual of the new x against the new G
+        if constexpr (CORR) {
+          gram_resid_b<LPC, LD, HS>(Gm, bv, xv, rs, N, lane);
+          if (lane == 0) acc[18] += (double)N * N;
+          WAVE_SYNC();
+        }
         if (move != 1) {
           if (move == 3 && gnew < gmin) {
             gmin = gnew;
@@ -1703,6 +1847,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
     }
   }
   for (int step = 0; step < n_steps; ++step) {
+    if (a.refresh_M > 0 && step > 0 && step % a.refresh_M == 0 && N > 0) {
+      // G^-1 rebuilt by bordering and x = G^-1 b recomputed, against the rounding the edits
+      // accumulate
+      if (lane_build<KCAP>(md, vt, ov, Lw, Hp, S1, S2, Zp, N)) {
+        for (int i = 0; i < N; ++i) {
+          double xi = 0.0;
+          for (int k = 0; k < N; ++k) xi += Hp[(i * KCAP + k) * 64] * BV(k);
+          XV(i) = xi;
+        }
+      } else {
+        st |= FSMP_ST_FACTOR;
+      }
+    }
     uint32_t r[8];
     philox4x32_10((uint32_t)step, 0u, uid0, uid1, a.key0, a.key1, r);
     philox4x32_10((uint32_t)step, 1u, uid0, uid1, a.key0, a.key1, r + 4);
@@ -2489,10 +2646,19 @@ static const GroupCfg kGroupDM[] = {{16, 4, 4},  {32, 4, 4},   {48, 16, 2},  {64
 static const GroupCfg kGroupDMF32[] = {{16, 4, 2},  {32, 4, 2},   {64, 32, 4},  {96, 16, 2},
                                        {128, 32, 4}, {160, 32, 4}, {192, 32, 2}};
 
+// the vectors of a chain's LDS block (ChainLayout::kVec); the corrected FP64 form (and with it
+// group_dm_ws_doubles' exact G) from capacity 48 up
+static_assert(ChainLayout<48, true>::kCorr && !ChainLayout<32, true>::kCorr && ChainLayout<64, true, false, true>::kCorr,
+              "the host's sizes assume the corrected FP64 form at capacities 48 and up");
+static int chain_vectors(int kcap, bool hg, bool f32, bool mcp) {
+  if (f32) return ChainLayout<64, true, true>::kVec;
+  return (hg && kcap >= 48) ? ChainLayout<64, true>::kVec : ChainLayout<16, true>::kVec;
+}
+
 static size_t chain_lds_bytes(const GroupCfg &g, int M, int sub, bool hg, bool f32 = false, bool mcp = false) {
   const int cpb = g.wpb * (64 / g.lpc);
   const size_t per = (hg ? 0 : (size_t)g.kcap * g.kcap) + (size_t)ChainLayout<16, true, false, false>::kAcc +
-                     (f32 ? ChainLayout<16, true, true>::kVec : ChainLayout<16, true>::kVec) * (size_t)g.kcap +
+                     (size_t)chain_vectors(g.kcap, hg, f32, mcp) * (size_t)g.kcap +
                      ((size_t)g.kcap + 1) / 2 * (mcp ? 2 : 1);
   return sizeof(double) * ((size_t)M * (1 + sub) + (size_t)g.kcap + 2 + (size_t)cpb * per);
 }
@@ -2516,13 +2682,14 @@ bool chain_dm_supported(int kcap, int M, int sub, bool f32, bool mcp) {
   return false;
 }
 
-// H (FP64, or FP32 plus the FP64 refresh matrix) of every chain, in tiles of a wavefront
+// H (FP64, with the exact G from capacity 48 up; or FP32 plus the FP64 refresh matrix and the
+// exact G) of every chain, in tiles of a wavefront
 size_t group_dm_ws_doubles(int kcap, int64_t n_list, bool f32) {
   for (const GroupCfg &g : kGroupDM)
     if (g.kcap == kcap) {
       const int64_t cpw = 64 / g.lpc;
       const size_t k2 = (size_t)kcap * kcap;
-      return (size_t)((n_list + cpw - 1) / cpw) * cpw * (f32 ? k2 / 2 + k2 : k2);
+      return (size_t)((n_list + cpw - 1) / cpw) * cpw * (f32 ? k2 / 2 + 2 * k2 : kcap >= 48 ? 2 * k2 : k2);
     }
   return 0;
 }

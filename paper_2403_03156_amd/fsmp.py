@@ -201,7 +201,7 @@ class Sampler:
     def __init__(self, ser=(8.0, 1.5, 6.0), ser_amp=1.0, ser_support=0, phi_kind=FSMP_PHI_EXP, tau_rise=0.0,
                  tau_decay=20.0, t0_min=50.0, t0_max=100.0, sigma_eps=0.1, mu_q=1.0, sigma_q=0.3, grid_sub=4,
                  jump_J=0.25, t0_step_sd=1.0, shift_sd=1.0, k_max=32, n_steps=2000, n_chains=1, burn_in=None,
-                 thin=1, precision=FSMP_FP64, refresh_M=64, record_flags=0, seed=0, device=0, mix=None):
+                 thin=1, precision=FSMP_FP64, refresh_M=128, record_flags=0, seed=0, device=0, mix=None):
         """mix: None (charge law N(mu_q, sigma_q^2)) or (weights, means, sigmas) of the MCP-PMT
         Gaussian mixture, up to 8 components."""
         self.lib = load()

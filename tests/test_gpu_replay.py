@@ -10,8 +10,10 @@ followed the same path.
 
 On pile-up waveforms nu(z) reaches ~1e6 while delta-nu is 10-40, so the reference there is
 the oracle's extended-precision replay (both nu's from scratch in long double), not the
-FP64 difference recorded in its log.  The long replay (4,000 sweeps at K around 100) shows
-that the FP64 form's incrementally edited G^-1 does not drift beyond that bound.
+FP64 difference recorded in its log (itself up to ~3e-9 off on these windows).  The long
+replay (4,000 sweeps at K around 100) holds the FP64 form to the bound over its whole
+length: there the charge means' residual against the exact G corrects what the explicitly
+inverted G^-1 leaves (about 1e-8 of delta-nu without it, with or without rebuilds).
 """
 import concurrent.futures
 
