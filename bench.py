@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--workload", default="uneven")
     ap.add_argument("--n-wave", type=int, default=0, help="override the workload's waveform count")
     ap.add_argument("--chain-steps", type=int, default=0, help="fixed sweeps per chain (no step autotuning)")
+    ap.add_argument("--trial-steps", type=int, default=100,
+                    help="mean sweeps per chain of the design autotuner's trial (proportional to the tuned counts)")
     ap.add_argument("--target-mcse", type=float, default=0.02,
                     help="relative batch-means MCSE of N the step autotuner aims at")
     ap.add_argument("--cpu-wave", type=int, default=6000, help="waveforms in the oracle's timed sample")
@@ -521,12 +523,12 @@ def main():
     smp = sampler()
     steps, designs = None, None
     if tuned:
-        # set-up, outside the timed region: the kernel design per PE capacity, then the sweeps
-        # per waveform from a pilot run
+        # set-up, outside the timed region: the sweeps per waveform from a pilot run, then the
+        # kernel design per PE capacity for those sweeps
         t_tune = time.time()
-        designs = smp.autotune(wave, b["offsets"], b["lam"], kmax=km, trial_steps=30)
         steps = smp.autotune_steps(wave, b["offsets"], b["lam"], kmax=km, pilot_steps=200,
                                    target_rel_mcse=args.target_mcse, min_steps=500, max_steps=4000)
+        designs = smp.autotune(wave, b["offsets"], b["lam"], kmax=km, trial_steps=args.trial_steps, n_steps=steps)
         torch.cuda.synchronize()
         print(f"[bench] autotuned in {time.time() - t_tune:.1f}s: designs {designs}; sweeps min {steps.min()} "
               f"median {int(np.median(steps))} mean {steps.mean():.0f} max {steps.max()}", file=sys.stderr, flush=True)

@@ -413,23 +413,30 @@ int32_t fsmp_last_timings(const fsmp_ctx *ctx, fsmp_timing *out, int32_t cap);
 fsmp_status fsmp_set_timing(fsmp_ctx *ctx, int32_t enable);
 
 /* ------------------------------------------------------------------ kernel designs
- * Three implementations of the same chains (identical results up to rounding order):
+ * Four implementations of the same chains (identical results up to rounding order):
  * FSMP_DESIGN_GROUP runs one chain per group of lanes with G^{-1} in LDS (PE capacities up
  * to 64); FSMP_DESIGN_LANE runs one chain per lane with G^{-1} interleaved in device
  * memory (capacities 16 and 32); FSMP_DESIGN_GROUP_DEVMEM runs one chain per (narrower)
  * group of lanes with G^{-1} in device memory, interleaved across the chains of a
  * wavefront, and only the vectors in LDS (every capacity, while the SER tables leave room
- * in LDS).  Capacities are 16, 32, 48, 64, 96, 128, 160, 192; a waveform runs in the
- * smallest one >= its kmax.  capacity 0 = every capacity that has the design.
- * FSMP_ENOTSUP if the requested pair does not exist.  The FP32-refresh form and the mixture
- * charge law run FSMP_DESIGN_GROUP_DEVMEM only (the FP32 form runs capacity 48 at 64). */
-enum { FSMP_DESIGN_GROUP = 0, FSMP_DESIGN_LANE = 1, FSMP_DESIGN_GROUP_DEVMEM = 2 };
+ * in LDS); FSMP_DESIGN_GROUP_DEVMEM_WIDE the same with 2-4x the lanes per chain (a whole
+ * wavefront from capacity 64 up; capacities 32-192, FP64 with the single charge law), for
+ * batches whose longest chains set the launch's duration.  Capacities are 16, 32, 48, 64,
+ * 96, 128, 160, 192; a waveform runs in the smallest one >= its kmax.  capacity 0 = every
+ * capacity that has the design.  FSMP_ENOTSUP if the requested pair does not exist.  The
+ * FP32-refresh form and the mixture charge law run FSMP_DESIGN_GROUP_DEVMEM only (the FP32
+ * form runs capacity 48 at 64); replays run FSMP_DESIGN_GROUP_DEVMEM. */
+enum { FSMP_DESIGN_GROUP = 0, FSMP_DESIGN_LANE = 1, FSMP_DESIGN_GROUP_DEVMEM = 2, FSMP_DESIGN_GROUP_DEVMEM_WIDE = 3 };
 fsmp_status fsmp_set_design(fsmp_ctx *ctx, int32_t capacity, int32_t design);
 int32_t fsmp_get_design(const fsmp_ctx *ctx, int32_t capacity);
 
 /* Autotuner: runs the whole batch for trial_steps sweeps once per design, each capacity
  * in that design where it exists (outputs discarded, HIP-event timings of each capacity's
- * launch), then keeps the fastest design per capacity in the context.
+ * launch, the capacities one after the other so that each time is the launch's own), then
+ * keeps the fastest design per capacity in the context.  With per-waveform
+ * sweep counts (batch->n_steps) every waveform's trial keeps its share of them, scaled to a
+ * mean of trial_steps (at least 1), so that the trial weighs a launch's longest chains
+ * against its total work as the full run does.
  * Allocates scratch outputs for the trial and synchronises `hip_stream`.  The FP32-refresh
  * form and the mixture law have one design, which it keeps. */
 fsmp_status fsmp_autotune(fsmp_ctx *ctx, const fsmp_batch *batch, int32_t trial_steps, void *hip_stream);

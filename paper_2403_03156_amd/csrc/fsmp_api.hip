@@ -214,6 +214,7 @@ struct fsmp_ctx {
   hipEvent_t stage_done = nullptr;
   bool stage_pending = false;
   bool timing = false;
+  bool serial = false;  // the autotuner's trials: the buckets one after the other on the call's stream
   hipStream_t capture = nullptr;  // set while fsmp_graph_create captures the kernels
   hipGraph_t captured = nullptr;
   std::vector<fsmp_timing> timings;
@@ -247,7 +248,8 @@ bool finite(double v) { return std::isfinite(v); }
 // whether a kernel design exists for a PE capacity under this model (LDS footprint),
 // precision and charge law: the FP32 form and the mixture law run only in the lane groups
 // with G^-1 in device memory (the FP32 form without capacity 48, which it runs at 64); one
-// lane per chain exists at capacities 16 and 32 (FP64)
+// lane per chain exists at capacities 16 and 32 (FP64); the wide device-memory groups from
+// capacity 32 up (FP64, single charge law)
 bool design_available(const fsmp_ctx *c, int kcap, int design) {
   const bool fp32 = c->cfg.precision == FSMP_FP32_REFRESH;
   const bool mcp = c->cfg.n_mix > 0;
@@ -255,6 +257,8 @@ bool design_available(const fsmp_ctx *c, int kcap, int design) {
     case FSMP_DESIGN_GROUP: return !fp32 && !mcp && chain_kcap_supported(kcap, c->tab.M, c->cfg.grid_sub);
     case FSMP_DESIGN_LANE: return !fp32 && !mcp && (kcap == 16 || kcap == 32);
     case FSMP_DESIGN_GROUP_DEVMEM: return chain_dm_supported(kcap, c->tab.M, c->cfg.grid_sub, fp32, mcp);
+    case FSMP_DESIGN_GROUP_DEVMEM_WIDE:
+      return !fp32 && !mcp && chain_dm_supported(kcap, c->tab.M, c->cfg.grid_sub, false, false, true);
     default: return false;
   }
 }
@@ -450,12 +454,12 @@ fsmp_status fsmp_create(fsmp_ctx **out, const fsmp_ser *ser, const fsmp_intensit
     if (!design_available(c, kCaps[q], c->design[q])) c->design[q] = FSMP_DESIGN_GROUP_DEVMEM;
   if (const char *d = std::getenv("FSMP_CHAIN_DESIGN")) {
     // tuning override: one letter per capacity in kCaps order, g (lane group, H in LDS),
-    // l (lane), d (lane group, H in device memory); a design that does not exist for a
-    // capacity leaves its default
+    // l (lane), d (lane group, H in device memory), w (its wide groups); a design that does
+    // not exist for a capacity leaves its default
     const size_t L = std::strlen(d);
     for (int q = 0; q < kNumCaps && q < (int)L; ++q) {
       const int want = d[q] == 'g' ? FSMP_DESIGN_GROUP : d[q] == 'l' ? FSMP_DESIGN_LANE
-                       : d[q] == 'd' ? FSMP_DESIGN_GROUP_DEVMEM : -1;
+                       : d[q] == 'd' ? FSMP_DESIGN_GROUP_DEVMEM : d[q] == 'w' ? FSMP_DESIGN_GROUP_DEVMEM_WIDE : -1;
       if (want >= 0 && design_available(c, kCaps[q], want)) c->design[q] = want;
     }
   }
@@ -558,8 +562,8 @@ size_t fsmp_workspace_bytes(const fsmp_ctx *c, const fsmp_batch *b) {
     const int dz = effective_design(c, kCaps[q], c->design[q]);
     if (dz == FSMP_DESIGN_LANE)
       bytes += lane_ws_doubles(kCaps[q], cnt[q]) * 8 + lane_ws_ints(kCaps[q], cnt[q]) * 4;
-    else if (dz == FSMP_DESIGN_GROUP_DEVMEM)
-      bytes += group_dm_ws_doubles(kCaps[q], cnt[q], fp32) * 8;
+    else if (dz == FSMP_DESIGN_GROUP_DEVMEM || dz == FSMP_DESIGN_GROUP_DEVMEM_WIDE)
+      bytes += group_dm_ws_doubles(kCaps[q], cnt[q], fp32, dz == FSMP_DESIGN_GROUP_DEVMEM_WIDE) * 8;
     if (cf.record_flags & FSMP_REC_CHARGE) bytes += (size_t)((cnt[q] + 63) / 64 * 64) * kCaps[q] * (kCaps[q] + 1) * 8;
   }
   bytes += (size_t)std::max<int64_t>(tmax + 1, 4 * 4096 + 1) * 16;
@@ -719,12 +723,15 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   auto design_of = [&](int bi) {
     return force ? FSMP_DESIGN_GROUP_DEVMEM : effective_design(c, caps[bi], c->design[bi]);
   };
-  // within a bucket, waveforms with per-waveform sweep counts in bins of 250 sweeps, the
-  // longest first, so that the chains of a workgroup end together and the longest start
-  // first; within a bin in order of lambda (equal lambdas in batch order): neighbouring lanes
-  // then carry chains of similar PE counts, which keeps the loops (bounded by the largest K
-  // in a wavefront) short
-  auto sbin = [&](int64_t i) { return b->n_steps ? (b->n_steps[i] + 249) / 250 : 0; };
+  // within a bucket, waveforms with per-waveform sweep counts in 16 bins of the batch's
+  // largest count, the longest first, so that the chains of a workgroup end together and the
+  // longest start first; within a bin in order of lambda (equal lambdas in batch order):
+  // neighbouring lanes then carry chains of similar PE counts, which keeps the loops (bounded
+  // by the largest K in a wavefront) short
+  int64_t smax = 1;
+  if (b->n_steps)
+    for (int64_t i = 0; i < n; ++i) smax = std::max<int64_t>(smax, b->n_steps[i]);
+  auto sbin = [&](int64_t i) { return b->n_steps ? (int64_t)b->n_steps[i] * 16 / (smax + 1) : 0; };
   for (int64_t i = 0; i < n; ++i) wsorted[i] = i;
   std::sort(wsorted, wsorted + n, [&](int64_t x, int64_t y) {
     if (sbin(x) != sbin(y)) return sbin(x) > sbin(y);
@@ -795,6 +802,7 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     const int dz = design_of(bi);
     const size_t dd = dz == FSMP_DESIGN_LANE ? lane_ws_doubles(caps[bi], cnt)
                       : dz == FSMP_DESIGN_GROUP_DEVMEM ? group_dm_ws_doubles(caps[bi], cnt, fp32)
+                      : dz == FSMP_DESIGN_GROUP_DEVMEM_WIDE ? group_dm_ws_doubles(caps[bi], cnt, fp32, true)
                                                        : 0;
     lane_doff[bi + 1] = lane_doff[bi] + dd;
     lane_ioff[bi + 1] = lane_ioff[bi] + (dz == FSMP_DESIGN_LANE ? lane_ws_ints(caps[bi], cnt) : 0);
@@ -980,7 +988,7 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   int n_buckets = 0;
   for (int bi = 0; bi < kNumCaps; ++bi) n_buckets += bucket_start[bi + 1] > bucket_start[bi];
   // the allocation-free variant runs the buckets one after the other on the caller's stream
-  const bool fan = n_buckets > 1 && !noalloc;
+  const bool fan = n_buckets > 1 && !noalloc && !c->serial;
   // Side streams: no more than the process has hardware queues (GPU_MAX_HW_QUEUES, HIP's
   // default 4), since streams beyond that share a queue and run one after the other. The
   // buckets go to them largest estimated cost first, each to the least loaded stream (cost
@@ -1046,7 +1054,8 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
       t.chains = cnt;
       return dz == FSMP_DESIGN_LANE    ? launch_chain_lane(caps[bi], ca, ks, &t.lanes, &t.blocks)
              : dz == FSMP_DESIGN_GROUP ? launch_chain(caps[bi], ca, ks, &t.lanes, &t.blocks)
-                                       : launch_chain_dm(caps[bi], fp32, ca, ks, &t.lanes, &t.blocks);
+                                       : launch_chain_dm(caps[bi], fp32, dz == FSMP_DESIGN_GROUP_DEVMEM_WIDE, ca, ks,
+                                                         &t.lanes, &t.blocks);
     });
     if (fan) {
       const hipError_t e2 = hipEventRecord(c->join[bi], ks);
@@ -1088,7 +1097,8 @@ fsmp_status fsmp_replay(fsmp_ctx *c, const fsmp_batch *b, const fsmp_logrec *log
 
 fsmp_status fsmp_set_design(fsmp_ctx *c, int32_t capacity, int32_t design) {
   if (!c) return FSMP_EINVAL;
-  if (design != FSMP_DESIGN_GROUP && design != FSMP_DESIGN_LANE && design != FSMP_DESIGN_GROUP_DEVMEM)
+  if (design != FSMP_DESIGN_GROUP && design != FSMP_DESIGN_LANE && design != FSMP_DESIGN_GROUP_DEVMEM &&
+      design != FSMP_DESIGN_GROUP_DEVMEM_WIDE)
     return fail(c, FSMP_EINVAL, "unknown design %d", design);
   bool any = false;
   for (int q = 0; q < kNumCaps; ++q) {
@@ -1123,9 +1133,10 @@ fsmp_status fsmp_autotune(fsmp_ctx *c, const fsmp_batch *b, int32_t trial_steps,
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(c->device);
   // scratch outputs for the trials
-  DevBuf<int32_t> i1, i2, i3, i4, i5;
+  DevBuf<int32_t> i1, i2, i3, i4, i5, i6;
   DevBuf<double> d1, d2, d3;
   hipError_t e = i1.ensure(C);
+  if (e == hipSuccess && b->n_steps) e = i6.ensure(C);
   if (e == hipSuccess) e = i2.ensure((size_t)C * kz);
   if (e == hipSuccess) e = i3.ensure((size_t)C * (kz + 1));
   if (e == hipSuccess) e = i4.ensure((size_t)C * 8);
@@ -1146,16 +1157,38 @@ fsmp_status fsmp_autotune(fsmp_ctx *c, const fsmp_batch *b, int32_t trial_steps,
   o.t0 = d1.p;
   o.charge = d2.p;
   o.acc = d3.p;
+  o.rec_steps = b->n_steps ? i6.p : nullptr;
   o.kz = kz;
+  // with per-waveform sweep counts the trial keeps their proportions, scaled to a mean of
+  // trial_steps, so that it sees what sets a launch's duration in the full run: its longest
+  // chains against its total work
+  fsmp_batch bt = *b;
+  std::vector<int32_t> tsteps;
+  int32_t tmax = trial_steps;
+  if (b->n_steps) {
+    double mean = 0.0;
+    for (int64_t i = 0; i < n; ++i) mean += b->n_steps[i];
+    mean /= (double)n;
+    tsteps.resize(n);
+    tmax = 1;
+    for (int64_t i = 0; i < n; ++i) {
+      tsteps[i] = (int32_t)std::max<double>(1.0, std::llround(b->n_steps[i] * (double)trial_steps / mean));
+      tmax = std::max(tmax, tsteps[i]);
+    }
+    bt.n_steps = tsteps.data();
+  }
   const fsmp_config saved = c->cfg;
   const bool saved_timing = c->timing;
+  // the trials run the buckets one after the other, so that each launch's time is its own
+  // (side by side, each would also carry what the others take from it)
+  c->serial = true;
   int saved_design[kNumCaps];
   std::memcpy(saved_design, c->design, sizeof saved_design);
-  c->cfg.n_steps = trial_steps;
+  c->cfg.n_steps = tmax;
   c->cfg.burn_in = 0;
   c->cfg.record_flags = 0;
   c->timing = true;
-  constexpr int kDesigns = 3;
+  constexpr int kDesigns = 4;
   double ms[kDesigns][kNumCaps];
   fsmp_status st = FSMP_OK;
   for (int d = 0; d < kDesigns && st == FSMP_OK; ++d) {
@@ -1163,7 +1196,7 @@ fsmp_status fsmp_autotune(fsmp_ctx *c, const fsmp_batch *b, int32_t trial_steps,
       ms[d][q] = -1.0;
       c->design[q] = design_available(c, kCaps[q], d) ? d : saved_design[q];
     }
-    st = fsmp_sample(c, b, &o, hip_stream);
+    st = fsmp_sample(c, &bt, &o, hip_stream);
     if (st != FSMP_OK) break;
     std::vector<fsmp_timing> tv(c->timings.size() + 1);
     const int32_t nt = fsmp_last_timings(c, tv.data(), (int32_t)tv.size());
@@ -1173,6 +1206,7 @@ fsmp_status fsmp_autotune(fsmp_ctx *c, const fsmp_batch *b, int32_t trial_steps,
   }
   c->cfg = saved;
   c->timing = saved_timing;
+  c->serial = false;
   std::memcpy(c->design, saved_design, sizeof saved_design);
   // per capacity the fastest of the designs that ran it
   if (st == FSMP_OK)
@@ -1188,6 +1222,7 @@ fsmp_status fsmp_autotune(fsmp_ctx *c, const fsmp_batch *b, int32_t trial_steps,
   i3.release();
   i4.release();
   i5.release();
+  i6.release();
   d1.release();
   d2.release();
   d3.release();

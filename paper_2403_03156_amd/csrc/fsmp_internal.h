@@ -174,11 +174,13 @@ size_t lane_ws_ints(int kcap, int64_t n_list);
 constexpr int kNumCaps = 8;
 constexpr int kCaps[kNumCaps] = {16, 32, 48, 64, 96, 128, 160, 192};
 bool chain_kcap_supported(int kcap, int M, int sub);  // lane-group (LDS) instance exists and fits
-// lane groups with H in device memory (FP64, or FP32 in the precision form): dws must hold
-// group_dm_ws_doubles(kcap, n_list, fp32)
-hipError_t launch_chain_dm(int kcap, bool fp32, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks);
-size_t group_dm_ws_doubles(int kcap, int64_t n_list, bool fp32);
-bool chain_dm_supported(int kcap, int M, int sub, bool fp32, bool mcp = false);
+// lane groups with H in device memory (FP64, or FP32 in the precision form; `wide`: the
+// wider groups, FP64 sampling with the single charge law only): dws must hold
+// group_dm_ws_doubles(kcap, n_list, fp32, wide)
+hipError_t launch_chain_dm(int kcap, bool fp32, bool wide, const ChainArgs &a, hipStream_t st, int32_t *lanes,
+                           int64_t *blocks);
+size_t group_dm_ws_doubles(int kcap, int64_t n_list, bool fp32, bool wide = false);
+bool chain_dm_supported(int kcap, int M, int sub, bool fp32, bool mcp = false, bool wide = false);
 int chain_kcap_for(int kmax);
 
 }  // namespace fsmp

@@ -422,21 +422,21 @@ struct ChainLayout {
 
 // Column i of H owned by one lane: element (k, i) at H[(k * LD + i) * HS] (HS = 1 in LDS;
 // the number of chains of a wavefront in device memory, where the wavefront's chains are
-// interleaved element by element).  Loads go in chunks of 8 rows, issued unconditionally
-// (rows below the capacity, a multiple of 8) with the rows past N dropped by a select,
+// interleaved element by element).  Loads go in chunks of 16 rows, issued unconditionally
+// (rows below the capacity, a multiple of 16) with the rows past N dropped by a select,
 // so a chunk costs one memory round trip; terms are summed in row order.
 template <int LD, int HS, typename MT>
 __device__ inline double grp_col_dot(const MT *H, const double *g, int i, int N) {
   double e = 0.0;
-  for (int k0 = 0; k0 < N; k0 += 8) {
-    double h[8], v[8];
+  for (int k0 = 0; k0 < N; k0 += 16) {
+    double h[16], v[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       h[u] = (double)H[((k0 + u) * LD + i) * HS];
       v[u] = g[k0 + u];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) e = (k0 + u < N) ? e + h[u] * v[u] : e;
+    for (int u = 0; u < 16; ++u) e = (k0 + u < N) ? e + h[u] * v[u] : e;
   }
   return e;
 }
@@ -466,7 +466,7 @@ __device__ inline void grp_col_update(MT *H, int i, int N, double ai, const doub
 // device memory in the layout of H), for the rows i owned by this lane of the group:
 //   r1 = g1 - G v1 (if v1),  r2 = e_u2 - G v2 (if v2; e_u2 the unit vector at u2),
 //   r3 = t3 - G v3.
-// Loads in chunks of 8 rows as in grp_col_dot, terms in row order.
+// Loads in chunks of 8 rows, terms in row order.
 template <int LPC, int LD, int HS>
 __device__ inline void gram_resid3(const double *Gm, int N, int lane, const double *g1, const double *v1, int u2,
                                    const double *v2, const double *t3, const double *v3, double *r1, double *r2,
@@ -592,6 +592,7 @@ template <int KCAP, int LPC, int WPB, bool HG, bool FORCE, bool F32, bool MCP>
 __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu(2))) chain_kernel(ChainArgs a) {
   static_assert(!F32 || (HG && !FORCE), "the FP32 form keeps H in device memory and does not replay");
   static_assert(!MCP || (HG && !FORCE && !F32), "the mixture form runs FP64 with H in device memory");
+  static_assert(KCAP % 16 == 0, "the column loads go in chunks of 16 rows below the capacity");
   using HT = typename std::conditional<F32, float, double>::type;
   constexpr int CPW = kWave / LPC;
   using CL = ChainLayout<KCAP, HG, F32, MCP>;
@@ -2633,18 +2634,25 @@ int chain_kcap_for(int kmax) {
 
 // lane-group instances: PE capacity, lanes per chain, wavefronts per workgroup.  With H
 // in LDS the LDS bounds the chains per CU (one chain per wavefront at capacity 64); with H
-// in device memory each chain keeps only its vectors in LDS, so groups are narrower and a
-// CU holds 8-16x more chains.
+// in device memory each chain keeps only its vectors in LDS, so groups can be narrow and a
+// CU holds 8-16x more chains: the narrow table, for launches that throughput bounds (chains
+// of equal length).  The wide table (FSMP_DESIGN_GROUP_DEVMEM_WIDE) gives each chain 2-4x the
+// lanes, a whole wavefront from capacity 64 up: for launches whose longest chains set their
+// duration (per-waveform sweep counts up to 8x the shortest), where a wider group shortens
+// each of their sweeps (measured on the uneven-window workload: 1.38 s per step narrow, 0.92 s
+// wide from capacity 96 up).
 struct GroupCfg {
   int kcap, lpc, wpb;
 };
 static const GroupCfg kGroup[] = {{16, 16, 4}, {32, 32, 4}, {48, 64, 3}, {64, 64, 4}};
 static const GroupCfg kGroupDM[] = {{16, 4, 4},  {32, 4, 4},   {48, 16, 2},  {64, 32, 4},
                                     {96, 16, 2}, {128, 32, 4}, {160, 32, 4}, {192, 32, 2}};
+static const GroupCfg kGroupDMWide[] = {{32, 16, 4}, {48, 32, 4},  {64, 64, 4},  {96, 64, 4},
+                                        {128, 64, 4}, {160, 64, 4}, {192, 64, 2}};
 // the FP32 form keeps eight vectors per chain in LDS: two wavefronts per workgroup at the
 // capacities of 4-lane groups (at four, capacity 32 would need 168 KB)
-static const GroupCfg kGroupDMF32[] = {{16, 4, 2},  {32, 4, 2},   {64, 32, 4},  {96, 16, 2},
-                                       {128, 32, 4}, {160, 32, 4}, {192, 32, 2}};
+static const GroupCfg kGroupDMF32[] = {{16, 4, 2},  {32, 4, 2},   {64, 32, 4},  {96, 64, 4},
+                                       {128, 64, 4}, {160, 64, 4}, {192, 64, 2}};
 
 // the vectors of a chain's LDS block (ChainLayout::kVec); the corrected FP64 form (and with it
 // group_dm_ws_doubles' exact G) from capacity 48 up
@@ -2669,8 +2677,14 @@ bool chain_kcap_supported(int kcap, int M, int sub) {
   return false;
 }
 
-bool chain_dm_supported(int kcap, int M, int sub, bool f32, bool mcp) {
+bool chain_dm_supported(int kcap, int M, int sub, bool f32, bool mcp, bool wide) {
   if (f32 && mcp) return false;
+  if (wide) {
+    if (f32 || mcp) return false;
+    for (const GroupCfg &g : kGroupDMWide)
+      if (g.kcap == kcap) return chain_lds_bytes(g, M, sub, true, false, false) <= 160 * 1024;
+    return false;
+  }
   if (f32) {
     // no capacity 48: the precision form runs it at 64
     for (const GroupCfg &g : kGroupDMF32)
@@ -2684,10 +2698,14 @@ bool chain_dm_supported(int kcap, int M, int sub, bool f32, bool mcp) {
 
 // H (FP64, with the exact G from capacity 48 up; or FP32 plus the FP64 refresh matrix and the
 // exact G) of every chain, in tiles of a wavefront
-size_t group_dm_ws_doubles(int kcap, int64_t n_list, bool f32) {
-  for (const GroupCfg &g : kGroupDM)
-    if (g.kcap == kcap) {
-      const int64_t cpw = 64 / g.lpc;
+size_t group_dm_ws_doubles(int kcap, int64_t n_list, bool f32, bool wide) {
+  const GroupCfg *t = f32 ? kGroupDMF32 : wide ? kGroupDMWide : kGroupDM;
+  const int nt = f32    ? (int)(sizeof kGroupDMF32 / sizeof *kGroupDMF32)
+                 : wide ? (int)(sizeof kGroupDMWide / sizeof *kGroupDMWide)
+                        : (int)(sizeof kGroupDM / sizeof *kGroupDM);
+  for (int q = 0; q < nt; ++q)
+    if (t[q].kcap == kcap) {
+      const int64_t cpw = 64 / t[q].lpc;
       const size_t k2 = (size_t)kcap * kcap;
       return (size_t)((n_list + cpw - 1) / cpw) * cpw * (f32 ? k2 / 2 + 2 * k2 : kcap >= 48 ? 2 * k2 : k2);
     }
@@ -2723,8 +2741,22 @@ hipError_t launch_chain(int kcap, const ChainArgs &a, hipStream_t st, int32_t *l
   }
 }
 
-// instances must match kGroupDM
-hipError_t launch_chain_dm(int kcap, bool fp32, const ChainArgs &a, hipStream_t st, int32_t *lanes, int64_t *blocks) {
+// instances must match kGroupDM (kGroupDMWide for `wide`, plain FP64 sampling only)
+hipError_t launch_chain_dm(int kcap, bool fp32, bool wide, const ChainArgs &a, hipStream_t st, int32_t *lanes,
+                           int64_t *blocks) {
+  if (wide) {
+    if (a.md.n_mix > 0 || a.force || fp32) return hipErrorInvalidValue;
+    switch (kcap) {
+      case 32: return launch_chain_t<32, 16, 4, true>(a, st, lanes, blocks);
+      case 48: return launch_chain_t<48, 32, 4, true>(a, st, lanes, blocks);
+      case 64: return launch_chain_t<64, 64, 4, true>(a, st, lanes, blocks);
+      case 96: return launch_chain_t<96, 64, 4, true>(a, st, lanes, blocks);
+      case 128: return launch_chain_t<128, 64, 4, true>(a, st, lanes, blocks);
+      case 160: return launch_chain_t<160, 64, 4, true>(a, st, lanes, blocks);
+      case 192: return launch_chain_t<192, 64, 2, true>(a, st, lanes, blocks);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (a.md.n_mix > 0) {
     if (a.force || fp32) return hipErrorInvalidValue;
     switch (kcap) {
@@ -2758,10 +2790,10 @@ hipError_t launch_chain_dm(int kcap, bool fp32, const ChainArgs &a, hipStream_t 
       case 16: return launch_chain_t<16, 4, 2, true, false, true>(a, st, lanes, blocks);
       case 32: return launch_chain_t<32, 4, 2, true, false, true>(a, st, lanes, blocks);
       case 64: return launch_chain_t<64, 32, 4, true, false, true>(a, st, lanes, blocks);
-      case 96: return launch_chain_t<96, 16, 2, true, false, true>(a, st, lanes, blocks);
-      case 128: return launch_chain_t<128, 32, 4, true, false, true>(a, st, lanes, blocks);
-      case 160: return launch_chain_t<160, 32, 4, true, false, true>(a, st, lanes, blocks);
-      case 192: return launch_chain_t<192, 32, 2, true, false, true>(a, st, lanes, blocks);
+      case 96: return launch_chain_t<96, 64, 4, true, false, true>(a, st, lanes, blocks);
+      case 128: return launch_chain_t<128, 64, 4, true, false, true>(a, st, lanes, blocks);
+      case 160: return launch_chain_t<160, 64, 4, true, false, true>(a, st, lanes, blocks);
+      case 192: return launch_chain_t<192, 64, 2, true, false, true>(a, st, lanes, blocks);
       default: return hipErrorInvalidValue;
     }
   }

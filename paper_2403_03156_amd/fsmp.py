@@ -25,7 +25,7 @@ EXPORTS = ("fsmp_create", "fsmp_workspace_bytes", "fsmp_sample", "fsmp_posterior
            "fsmp_server_last_error", "fsmp_server_destroy", "fsmp_set_design", "fsmp_get_design", "fsmp_autotune",
            "fsmp_graph_create", "fsmp_graph_launch", "fsmp_graph_destroy", "fsmp_replay",
            "fsmp_autotune_steps", "fsmp_sample_noalloc")
-FSMP_DESIGN_GROUP, FSMP_DESIGN_LANE, FSMP_DESIGN_GROUP_DEVMEM = 0, 1, 2
+FSMP_DESIGN_GROUP, FSMP_DESIGN_LANE, FSMP_DESIGN_GROUP_DEVMEM, FSMP_DESIGN_GROUP_DEVMEM_WIDE = 0, 1, 2, 3
 
 
 class fsmp_ser(ctypes.Structure):
@@ -384,9 +384,10 @@ class Sampler:
     def get_design(self, capacity):
         return self.lib.fsmp_get_design(self.h, capacity)
 
-    def autotune(self, wave, offsets, lam, kmax=None, trial_steps=50, stream=None):
+    def autotune(self, wave, offsets, lam, kmax=None, trial_steps=50, stream=None, n_steps=None):
+        """fsmp_autotune; n_steps: the per-waveform sweep counts the run will use, if any."""
         import torch
-        b, keep = self._batch(wave, offsets, lam, kmax)
+        b, keep = self._batch(wave, offsets, lam, kmax, n_steps=n_steps)
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._check(self.lib.fsmp_autotune(self.h, ctypes.byref(b), trial_steps, ctypes.c_void_p(st.cuda_stream)))
         return {c: self.get_design(c) for c in (16, 32, 48, 64, 96, 128, 160, 192)}

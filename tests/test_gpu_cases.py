@@ -58,13 +58,14 @@ def _gpu_and_oracle(wl, b, km, n_steps, burn, n_chains, seed, design=None, g_ran
 
 
 # FSMP_CHAIN_DESIGN: one letter per PE capacity (16, 32, 48, 64, 96, 128, 160, 192):
-# g lane group with H in LDS, l one lane per chain, d lane group with H in device memory
+# g lane group with H in LDS, l one lane per chain, d lane group with H in device memory,
+# w its wide lane groups
 @pytest.mark.parametrize("design", [
     pytest.param("llllllll", marks=pytest.mark.skip(
         reason="forcing one lane per chain at every capacity faulted the GPU (capacity 48, cause not found; "
                "a bounds-checked CPU build of the kernel is clean on this case); the capacity-48 lane "
                "instance is removed and this case stays off the GPU")),
-    "gggggggg", "dddddddd"])
+    "gggggggg", "dddddddd", "dwwwwwww"])
 def test_designs_agree_with_oracle(design):
     wl = synth.PRESETS["batched"]
     b = synth.generate(wl, n_wave=40, seed=11)
@@ -86,7 +87,7 @@ def test_lane_design_at_its_capacities():
     assert len(parted) == 0, parted
 
 
-@pytest.mark.parametrize("design", [None, "dddddddd"])
+@pytest.mark.parametrize("design", [None, "dddddddd", "dwwwwwww"])
 def test_large_capacities_pileup(design):
     wl = synth.PRESETS["pileup"]
     lam = np.array([20.0, 28.0, 48.0, 60.0, 75.0, 90.0, 100.0, 100.0])

@@ -78,8 +78,12 @@ def test_set_design_validation():
     assert [smp.get_design(c) for c in synth.KCAPS] == [0, 0, 0, 0] + before[4:]
     smp.set_design(0, fsmp.FSMP_DESIGN_GROUP_DEVMEM)
     assert [smp.get_design(c) for c in synth.KCAPS] == [2] * 8
+    smp.set_design(0, fsmp.FSMP_DESIGN_GROUP_DEVMEM_WIDE)  # the wide groups exist from capacity 32 up
+    assert [smp.get_design(c) for c in synth.KCAPS] == [2] + [3] * 7
     with pytest.raises(RuntimeError):
-        smp.set_design(16, 3)
+        smp.set_design(16, fsmp.FSMP_DESIGN_GROUP_DEVMEM_WIDE)
+    with pytest.raises(RuntimeError):
+        smp.set_design(16, 4)
 
 
 def test_autotune_keeps_results_correct():
@@ -90,7 +94,8 @@ def test_autotune_keeps_results_correct():
     before = {c: smp.get_design(c) for c in synth.KCAPS}
     designs = smp.autotune(wave, b["offsets"], b["lam"], kmax=km, trial_steps=40)
     print(f"[autotune] {before} -> {designs}", flush=True)
-    assert all(designs[c] in (fsmp.FSMP_DESIGN_GROUP, fsmp.FSMP_DESIGN_GROUP_DEVMEM) for c in (48, 64))  # no lane
+    assert all(designs[c] in (fsmp.FSMP_DESIGN_GROUP, fsmp.FSMP_DESIGN_GROUP_DEVMEM, fsmp.FSMP_DESIGN_GROUP_DEVMEM_WIDE)
+               for c in (48, 64))  # no lane
 
     assert all(designs[c] == before[c] for c in (96, 128, 160, 192))                # not in the batch: untouched
     # a sub-batch in the tuned designs against the oracle

@@ -18,15 +18,22 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def test_per_waveform_steps_match_oracle():
+@pytest.mark.parametrize("tuned", [False, True])
+def test_per_waveform_steps_match_oracle(tuned):
+    # tuned: the kernel designs from fsmp_autotune with the same sweep counts (its trial keeps
+    # their proportions), which may pick any design per capacity, the wide groups included
     wl = synth.PRESETS["batched"]
     n, C, n_steps, burn = 60, 2, 600, 300
     b = synth.generate(wl, n_wave=n, seed=91)
     km = synth.kmax_for(b["lam"])
     kz = int(km.max())
     steps = np.random.default_rng(3).choice([200, 351, 600, 457], size=n).astype(np.int32)
-    print(f"[case] per-waveform steps n={n} chains={C} steps={sorted(set(steps.tolist()))}", flush=True)
+    print(f"[case] per-waveform steps n={n} chains={C} steps={sorted(set(steps.tolist()))} tuned={tuned}", flush=True)
     smp = gpu_sampler(wl, n_steps, burn, C, 12)
+    if tuned:
+        designs = smp.autotune(torch.from_numpy(b["wave"]).cuda(), b["offsets"], b["lam"], kmax=km, trial_steps=20,
+                               n_steps=steps)
+        print(f"[autotune] {designs}", flush=True)
     out = smp.sample(torch.from_numpy(b["wave"]).cuda(), b["offsets"], b["lam"], kmax=km, kz=kz, n_steps=steps)
     post = smp.posterior(n, out)
     torch.cuda.synchronize()
