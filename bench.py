@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--workload", default="uneven")
     ap.add_argument("--n-wave", type=int, default=0, help="override the workload's waveform count")
     ap.add_argument("--chain-steps", type=int, default=0, help="fixed sweeps per chain (no step autotuning)")
+    ap.add_argument("--refresh", type=int, default=-1,
+                    help="FP64 form: rebuild G^-1 from scratch every this many sweeps (-1: the sampler's default)")
     ap.add_argument("--trial-steps", type=int, default=100,
                     help="mean sweeps per chain of the design autotuner's trial (proportional to the tuned counts)")
     ap.add_argument("--target-mcse", type=float, default=0.02,
@@ -514,7 +516,9 @@ def main():
     wave = torch.from_numpy(b["wave"]).to(dev)
     stream = torch.cuda.current_stream(dev)
 
-    def sampler(precision=fsmp.FSMP_FP64, refresh_M=128, chains=wl.n_chains):
+    def sampler(precision=fsmp.FSMP_FP64, refresh_M=None, chains=wl.n_chains):
+        if refresh_M is None:
+            refresh_M = args.refresh if args.refresh >= 0 else fsmp.Sampler.default_refresh(precision)
         return fsmp.Sampler(ser=wl.ser, phi_kind=wl.phi_kind, tau_rise=wl.tau_rise, tau_decay=wl.tau_decay,
                             t0_min=wl.t0_min, t0_max=wl.t0_max, sigma_eps=wl.sigma_eps, mu_q=wl.mu_q,
                             sigma_q=wl.sigma_q, n_steps=n_steps, n_chains=chains, burn_in=burn, seed=wl.seed,
@@ -574,7 +578,13 @@ def main():
                 "lds": {"peak_read_measured_GBps": lds_r / 1e9, "peak_write_measured_GBps": lds_w / 1e9,
                         "frac_of_read_peak": achieved / lds_r,
                         "peak_nominal_GBps": 256 * 128 * CLOCK_HZ / 1e9},
-                "impl_bytes_per_launch": 8.0 * (wsel[:, 2].sum() + wsel[:, 3].sum())}
+                "impl_bytes_per_launch": 8.0 * (wsel[:, 2].sum() + wsel[:, 3].sum()),
+                # every chain launch: its time in the step, the algorithmic bytes (packed factor) and
+                # the G^-1 / G elements the implementation reads and writes, per launch
+                "by_kernel": {name: {"ms": avg[name],
+                                     "alg_bytes": algorithmic_bytes(work[chain_kcap == chains_of[name]]),
+                                     "impl_bytes": 8.0 * float(work[chain_kcap == chains_of[name]][:, 2:4].sum())}
+                              for name in sorted(chains_of, key=lambda k: -avg[k])}}
     print(f"[bench] kernels (mean ms): {json.dumps(avg)}", file=sys.stderr, flush=True)
     res = {
         "metric": "waveforms/s and MCMC steps/s at matched posterior accuracy; p99 event latency",

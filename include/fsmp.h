@@ -100,7 +100,8 @@ typedef struct {
  * step N(0, t0_step_sd^2) and update shift N(0, shift_sd^2) rounded to the grid.
  * Steps [0, burn_in) are not recorded; accumulators use floor(sqrt(n_steps - burn_in))
  * batches for the batch-means MCSE.  Both forms rebuild G^-1 = (A^T A + rho I)^-1 and the
- * charge means x = G^-1 b from scratch in FP64 every refresh_M sweeps (0: never).
+ * charge means x = G^-1 b from scratch in FP64 every refresh_M sweeps (0: never), except the
+ * FP64 form's corrected kernels below, which need no rebuild.
  * precision: FSMP_FP64 (all FP64; from PE capacity 48 up, in the device-memory design the
  * kernels run there, with the exact G kept beside G^-1 and the residual s = b - G x of the
  * charge means recomputed after every accepted move, so that gamma^T G^-1 b and x_j enter

@@ -738,18 +738,16 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         double drift;
         if (!grp_refresh<LPC, LD, HS>(md, vt, ov, Lw, W, H, xv, bv, s1, s2, zg, N, lane, drift)) st |= FSMP_ST_FACTOR;
         else if (drift > a.drift_bound) st |= FSMP_ST_DRIFT;
-      } else {
+      } else if constexpr (!CORR) {
         // FP64 form: G^-1 rebuilt in place by bordering and x = G^-1 b recomputed, against the
-        // rounding the rank-one and rank-two edits accumulate
+        // rounding the rank-one and rank-two edits accumulate (the corrected form needs none:
+        // the residual against the exact G takes up what the edits leave in x, and over 4,000
+        // sweeps at K ~ 100 its delta-nu is as close to the exact one without rebuilds as with)
         if (grp_build<LPC, LD, HS>(md, vt, ov, Lw, (double *)H, s1, s2, zg, N, lane, MCP ? ek : nullptr)) {
           for (int i = lane; i < N; i += LPC) s1[i] = mf[zg[i] - glo] + (MCP ? md.mix_rhom[ek[i]] : md.rhom);
           WAVE_SYNC();
           for (int i = lane; i < N; i += LPC) xv[i] = grp_col_dot<LD, HS>((double *)H, s1, i, N);
           WAVE_SYNC();
-          if constexpr (CORR) {
-            gram_resid_b<LPC, LD, HS>(Gm, bv, xv, rs, N, lane);
-            WAVE_SYNC();
-          }
         } else {
           st |= FSMP_ST_FACTOR;
         }

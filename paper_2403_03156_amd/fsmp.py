@@ -198,12 +198,19 @@ def fsmp_create(ser: fsmp_ser, phi: fsmp_intensity, cfg: fsmp_config, device: in
 class Sampler:
     """Owns one fsmp_ctx; ``sample`` takes a device waveform tensor and host metadata."""
 
+    @staticmethod
+    def default_refresh(precision):
+        """FP64 rebuilds of G^-1 every this many sweeps by default: 128 in both forms."""
+        return 128
+
     def __init__(self, ser=(8.0, 1.5, 6.0), ser_amp=1.0, ser_support=0, phi_kind=FSMP_PHI_EXP, tau_rise=0.0,
                  tau_decay=20.0, t0_min=50.0, t0_max=100.0, sigma_eps=0.1, mu_q=1.0, sigma_q=0.3, grid_sub=4,
                  jump_J=0.25, t0_step_sd=1.0, shift_sd=1.0, k_max=32, n_steps=2000, n_chains=1, burn_in=None,
-                 thin=1, precision=FSMP_FP64, refresh_M=128, record_flags=0, seed=0, device=0, mix=None):
+                 thin=1, precision=FSMP_FP64, refresh_M=None, record_flags=0, seed=0, device=0, mix=None):
         """mix: None (charge law N(mu_q, sigma_q^2)) or (weights, means, sigmas) of the MCP-PMT
-        Gaussian mixture, up to 8 components."""
+        Gaussian mixture, up to 8 components.  refresh_M: None for default_refresh(precision)."""
+        if refresh_M is None:
+            refresh_M = self.default_refresh(precision)
         self.lib = load()
         self.ser = fsmp_ser(ser[0], ser[1], ser[2], ser_amp, ser_support)
         self.phi = fsmp_intensity(phi_kind, tau_rise, tau_decay, t0_min, t0_max)
