@@ -280,6 +280,16 @@ def recorded_traffic(workload, kernel):
     return t["kernels"][kernel]["hbm_bytes"]
 
 
+def step_traffic(workload, kernels, ms_per_step):
+    """HBM bytes of a step from the recorded counters (every kernel of the step, the posterior
+    included), and their rate over the step against the HBM peak; None if any is missing"""
+    per = [recorded_traffic(workload, k) for k in list(kernels) + ["posterior"]]
+    if any(v is None for v in per):
+        return None
+    tot = float(sum(per))
+    return {"hbm_bytes": tot, "GBps": tot / (ms_per_step / 1e3) / 1e9, "frac": tot / (ms_per_step / 1e3) / PEAK_HBM}
+
+
 def serving_run(fsmp, synth, pool, rate, n_events, precision, seed=0, n_streams=4, max_batch_wave=20000):
     """Poisson arrivals of trigger events (500-2000 channels drawn from a pool of synthetic
     channels, 1,024 samples each) submitted to the serving loop as they arrive; latency
@@ -451,14 +461,24 @@ def precision_study(fsmp, synth, oracle, n_wave, n_steps=1000, refresh_M=64):
                 w = b["wave"][b["offsets"][c]:b["offsets"][c + 1]]
                 d, _, bad = oracle.replay(p, w, b["lam"][c], int(km[c]), 0, 4 * len(w) - 1, c, 7, logs[c],
                                           tie_eps=1e-9, ext=True)
+                # the oracle's own FP64 (two nu's from scratch) along the same path
+                d64, _, _ = oracle.replay(p, w, b["lam"][c], int(km[c]), 0, 4 * len(w) - 1, c, 7, logs[c],
+                                          tie_eps=1e-9, ext=False)
                 v = (logs[c]["flags"] & 1) != 0
-                return np.abs(logs[c]["dnu"][v] - d[v]) / np.maximum(np.abs(d[v]), 1.0), bad
+                den = np.maximum(np.abs(d[v]), 1.0)
+                return np.abs(logs[c]["dnu"][v] - d[v]) / den, bad, np.abs(d64[v] - d[v]) / den
             with concurrent.futures.ThreadPoolExecutor(max_workers=16) as ex:
                 rep = list(ex.map(one, range(n_wave)))
             e = np.concatenate([r[0] for r in rep])
+            caps = np.asarray(synth.KCAPS)[np.searchsorted(synth.KCAPS, km)]
+            by_cap = {int(k): float(np.concatenate([rep[c][0] for c in range(n_wave) if caps[c] == k] +
+                                                   [np.zeros(1)]).max()) for k in sorted(set(caps.tolist()))}
             row = {"sigma_eps": sig, "form": "fp64" if prec == fsmp.FSMP_FP64 else f"fp32+refresh M={refresh_M}",
                    "proposals": int(e.size), "dnu_rel_err_max": float(e.max()), "dnu_rel_err_p99": float(np.quantile(e, 0.99)),
-                   "dnu_rel_err_median": float(np.median(e)), "decision_flips": int(sum(r[1] for r in rep)),
+                   "dnu_rel_err_median": float(np.median(e)), "dnu_rel_err_max_by_capacity": by_cap,
+                   "oracle_fp64_dnu_rel_err_max": float(np.concatenate([r[2] for r in rep]).max()),
+                   "oracle_fp64_dnu_rel_err_p99": float(np.quantile(np.concatenate([r[2] for r in rep]), 0.99)),
+                   "decision_flips": int(sum(r[1] for r in rep)),
                    "chains_identical": float((out["z"].cpu().numpy() == o.z).all(1).mean()),
                    "fp64_reevaluations_per_proposal": float(work[:, 4].sum() / max(e.size, 1))}
             for a, name in enumerate(("N", "Q", "t0")):
@@ -579,6 +599,9 @@ def main():
                         "frac_of_read_peak": achieved / lds_r,
                         "peak_nominal_GBps": 256 * 128 * CLOCK_HZ / 1e9},
                 "impl_bytes_per_launch": 8.0 * (wsel[:, 2].sum() + wsel[:, 3].sum()),
+                # the counters' HBM bytes of every kernel of the step (while the kernel source is the
+                # one they were taken with) over the step's time: the whole step against HBM
+                "step_traffic": step_traffic(args.workload, list(avg), ms_per_step),
                 # every chain launch: its time in the step, the algorithmic bytes (packed factor) and
                 # the G^-1 / G elements the implementation reads and writes, per launch
                 "by_kernel": {name: {"ms": avg[name],
