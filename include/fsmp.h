@@ -157,7 +157,17 @@ typedef struct {
  * n_chains + 1 offsets from 0.  Each list holds at most the waveform's kmax PEs, each inside
  * the waveform's T where phi(g / grid_sub - t0_init) > 0, and needs lambda > 0; G^-1 and
  * the charges of the list are built before the first sweep, which draws no random numbers
- * for it (a chain's stream is the same as from the empty list). */
+ * for it (a chain's stream is the same as from the empty list).
+ * Why the per-waveform metadata is host memory (the waveforms are device memory): the host
+ * validates it (ranges, T inside the window, start lists against the prior) and uses it to
+ * plan the call -- the capacity bucket of every waveform, the chain order within a bucket
+ * (sweep-count bins, then lambda), the workspace size -- before any launch, so it would
+ * read it back from the device otherwise.  fsmp_sample copies the planned arrays (24-40
+ * bytes per waveform, 12 MB for 250,000 waveforms) to the device on the caller's stream
+ * through the context's pinned staging buffer: that copy is part of the call and of any
+ * time measured around it (its stream order keeps it ahead of the kernels; the call does
+ * not wait for it, but reuses the staging buffer only once the previous call's copy has
+ * finished).  fsmp_sample_noalloc copies from the caller's host memory directly. */
 typedef struct {
   int64_t n_wave;
   const float *wave;
