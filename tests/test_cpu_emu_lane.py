@@ -1,0 +1,131 @@
+"""The library's host path and its one-lane-per-chain kernel run on the CPU, under
+AddressSanitizer, and agree with the oracle (no GPU needed).
+
+The sources are compiled with g++ against a CPU stand-in for the HIP runtime
+(tests/cpu_emu/hip/hip_runtime.h: device memory is host memory, a kernel launch runs its
+blocks one after the other with one OS thread per GPU thread).  fsmp_sample is called from a
+small driver exactly as a caller would, so every host step of the call (batch checks, the
+capacity buckets, the workspace layout, the prologue kernel and the chain launches) runs over
+buffers that AddressSanitizer watches, each device buffer its own allocation of the size the
+library asks for: an access outside any of them, in host or kernel code, ends the run with a
+report.  Only the lane design can run here (the lane-group kernels need the wavefront's
+cross-lane operations), so the batches hold waveforms of PE capacity 16 and 32."""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_03156_amd import fsmp, synth
+from tests.cpu_emu import build_emu
+from tests.fsmp_cases import compare_chains, oracle_params
+
+pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+
+LANE_AT_16_AND_32 = [fsmp.FSMP_DESIGN_LANE] * 2 + [fsmp.FSMP_DESIGN_GROUP_DEVMEM] * 6
+
+
+def _subset(b, keep):
+    off = b["offsets"]
+    parts = [b["wave"][off[i]:off[i + 1]] for i in keep]
+    new_off = np.concatenate([[0], np.cumsum([len(p) for p in parts])]).astype(np.int64)
+    return np.concatenate(parts).astype(np.float32), new_off, b["lam"][keep].astype(np.float64)
+
+
+def _run_emu(tmp, wl, wave, offsets, lam, km, n_steps, burn, n_chains, seed, design, record_flags=0, thin=1,
+             g_range=None, t0_init=None):
+    ser = fsmp.fsmp_ser(*wl.ser, 1.0, 0)
+    phi = fsmp.fsmp_intensity(wl.phi_kind, wl.tau_rise, wl.tau_decay, wl.t0_min, wl.t0_max)
+    cfg = fsmp.fsmp_config(wl.sigma_eps, wl.mu_q, wl.sigma_q, 4, 0.25, 1.0, 1.0, 64, n_steps, n_chains, burn, thin,
+                           fsmp.FSMP_FP64, 128, record_flags, seed)
+    for name, s in (("ser", ser), ("intensity", phi), ("config", cfg)):
+        with open(os.path.join(tmp, name + ".bin"), "wb") as f:
+            f.write(bytes(s))
+    kz = int(km.max())
+    with open(os.path.join(tmp, "kz.txt"), "w") as f:
+        f.write(f"{kz}\n")
+    with open(os.path.join(tmp, "design.txt"), "w") as f:
+        f.write(" ".join(str(d) for d in design) + "\n")
+    wave.astype(np.float32).tofile(os.path.join(tmp, "wave.f32"))
+    offsets.astype(np.int64).tofile(os.path.join(tmp, "offsets.i64"))
+    lam.astype(np.float64).tofile(os.path.join(tmp, "lam.f64"))
+    km.astype(np.int32).tofile(os.path.join(tmp, "kmax.i32"))
+    if g_range is not None:
+        np.ascontiguousarray(g_range, dtype=np.int32).tofile(os.path.join(tmp, "g_range.i32"))
+    if t0_init is not None:
+        np.ascontiguousarray(t0_init, dtype=np.float64).tofile(os.path.join(tmp, "t0_init.f64"))
+    exe = build_emu.build()
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:halt_on_error=1")
+    r = subprocess.run([exe, tmp], env=env, capture_output=True, text=True, timeout=900)
+    assert r.returncode == 0, f"emulated fsmp_sample failed ({r.returncode}):\n{r.stdout[-2000:]}\n{r.stderr[:6000]}"
+    C = len(lam) * n_chains
+    n_rec = -(-(n_steps - burn) // thin)
+
+    def rd(name, dt, shape):
+        return np.fromfile(os.path.join(tmp, name), dtype=dt).reshape(shape)
+    g = {"n_pe": rd("n_pe.i32", np.int32, (C,)), "t0": rd("t0.f64", np.float64, (C,)),
+         "z": rd("z.i32", np.int32, (C, kz)), "charge": rd("charge.f64", np.float64, (C, kz)),
+         "acc": rd("acc.f64", np.float64, (C, 12)), "nhist": rd("nhist.i32", np.int32, (C, kz + 1)),
+         "counts": rd("counts.i32", np.int32, (C, 8)), "status": rd("status.u32", np.uint32, (C,))}
+    if record_flags & fsmp.FSMP_REC_LOG:
+        g["log"] = rd("log.bin", fsmp.LOGREC_DTYPE, (C, n_steps))
+    if record_flags & fsmp.FSMP_REC_TRACE:
+        g["trace"] = rd("trace.f64", np.float64, (C, n_rec, 3))
+    if record_flags & fsmp.FSMP_REC_CHARGE:
+        g["qdraw"] = rd("qdraw.f64", np.float64, (C, n_rec, kz))
+        g["zdraw"] = rd("zdraw.i32", np.int32, (C, n_rec, kz))
+    return g
+
+
+def test_lane_design_on_the_cpu_under_asan(tmp_path):
+    wl = synth.PRESETS["batched"]
+    b = synth.generate(wl, n_wave=40, seed=11)
+    km_all = synth.kmax_for(b["lam"])
+    keep = np.where(km_all <= 32)[0]
+    assert len(keep) >= 20 and (km_all[keep] > 16).any() and (km_all[keep] <= 16).any()
+    wave, offsets, lam = _subset(b, keep)
+    km = km_all[keep].astype(np.int32)
+    n_steps, burn, n_chains, seed = 300, 150, 2, 4
+    g = _run_emu(str(tmp_path), wl, wave, offsets, lam, km, n_steps, burn, n_chains, seed, LANE_AT_16_AND_32)
+    o = oracle.run(oracle_params(wl), wave, offsets, lam, n_chains, n_steps, burn, seed, int(km.max()), kmax=km)
+    parted = compare_chains(g, o)
+    assert len(parted) == 0, parted
+    assert (g["counts"][:, 3] > 0).mean() > 0.5
+
+
+def test_lane_design_edges_and_records_on_the_cpu_under_asan(tmp_path):
+    # ragged windows down to one sample, lambda = 0, a non-finite sample, K_max = 1, an empty
+    # and a custom solution space, a t0 start, with the proposal log, the trace and the charge
+    # draws recorded
+    wl = synth.PRESETS["plain"]
+    lengths = np.array([1, 2, 5, 17, 40, 96, 97, 256, 300, 64, 256, 256, 256, 256])
+    lam = np.array([1.0, 2.0, 3.0, 2.5, 4.0, 3.0, 3.0, 4.0, 5.0, 0.0, 3.0, 3.0, 3.0, 3.0])
+    b = synth.generate(wl, n_wave=len(lengths), seed=5, lam=lam, lengths=lengths)
+    b["wave"][b["offsets"][11] + 7] = np.nan
+    km = synth.kmax_for(b["lam"]).astype(np.int32)
+    km[12] = 1
+    assert km.max() <= 32
+    g_range = np.stack([np.zeros(len(lengths)), 4 * lengths - 1], 1).astype(np.int32)
+    g_range[13] = [500, 499]
+    g_range[8] = [300, 700]
+    t0_init = np.full(len(lengths), 75.0)
+    t0_init[3] = 51.25
+    n_steps, burn, n_chains, seed, thin = 240, 80, 2, 8, 7
+    flags = fsmp.FSMP_REC_LOG | fsmp.FSMP_REC_TRACE | fsmp.FSMP_REC_CHARGE
+    g = _run_emu(str(tmp_path), wl, b["wave"], b["offsets"], b["lam"], km, n_steps, burn, n_chains, seed,
+                 LANE_AT_16_AND_32, record_flags=flags, thin=thin, g_range=g_range, t0_init=t0_init)
+    o = oracle.run(oracle_params(wl), b["wave"], b["offsets"], b["lam"], n_chains, n_steps, burn, seed,
+                   int(km.max()), kmax=km, g_range=g_range, t0_init=t0_init, log=True, thin=thin, charges=True)
+    parted = compare_chains(g, o)
+    assert len(parted) == 0, parted
+    assert g["status"][11 * n_chains] & fsmp.FSMP_ST_NONFINITE
+    assert g["status"][13 * n_chains] & fsmp.FSMP_ST_EMPTY_T
+    for f in ("move", "flags", "j", "g"):
+        np.testing.assert_array_equal(g["log"][f], o.log[f])
+    np.testing.assert_allclose(g["log"]["t0"], o.log["t0"], rtol=1e-9, atol=1e-9)
+    np.testing.assert_array_equal(g["zdraw"], o.zdraw)
+    np.testing.assert_allclose(g["trace"], o.trace, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(g["qdraw"], o.qdraw, rtol=1e-8, atol=1e-9, equal_nan=True)
+    assert (o.zdraw >= 0).sum() > 0
