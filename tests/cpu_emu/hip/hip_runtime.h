@@ -8,6 +8,9 @@
 // may run here.
 #pragma once
 #include <barrier>
+#if defined(__SANITIZE_ADDRESS__)
+#include <sanitizer/asan_interface.h>
+#endif
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
@@ -176,11 +179,37 @@ inline hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipErrorN
 inline hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
 inline hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
 
+// the kernels' dynamic LDS (each launch's blocks run one at a time, so one array per name);
+// declared in the library's namespaces, where the kernels' block-scope declarations find them.
+// A launch poisons each array beyond the bytes it asked for, so that AddressSanitizer reports
+// an LDS access past the launch's size.
+namespace fsmp {
+namespace {
+constexpr size_t emu_lds_bytes = 160 * 1024;
+alignas(16) double vt[emu_lds_bytes / 8];
+alignas(16) double smem[emu_lds_bytes / 8];
+alignas(16) double lds[emu_lds_bytes / 8];
+}  // namespace
+}  // namespace fsmp
+
+inline void emu_lds_limit(size_t bytes) {
+#if defined(__SANITIZE_ADDRESS__)
+  for (double *a : {fsmp::vt, fsmp::smem, fsmp::lds}) {
+    __asan_unpoison_memory_region(a, fsmp::emu_lds_bytes);
+    if (bytes < fsmp::emu_lds_bytes) __asan_poison_memory_region((char *)a + bytes, fsmp::emu_lds_bytes - bytes);
+  }
+#else
+  (void)bytes;
+#endif
+}
+
 // a launch: the blocks one after the other, one thread per GPU thread of a block; a thread
 // that returns leaves the block's barrier
 template <typename... KA, typename... A>
-void emu_launch(void (*k)(KA...), dim3 g, dim3 b, size_t, A... args) {
+void emu_launch(void (*k)(KA...), dim3 g, dim3 b, size_t lds_bytes, A... args) {
   if (g.y != 1 || g.z != 1 || b.y != 1 || b.z != 1) emu_unreachable("a multi-dimensional launch");
+  if (lds_bytes > fsmp::emu_lds_bytes) emu_unreachable("a launch asking for more than 160 KiB of LDS");
+  emu_lds_limit(lds_bytes);
   for (unsigned bx = 0; bx < g.x; ++bx) {
     std::barrier<> bar((std::ptrdiff_t)b.x);
     emu_or_acc[0] = emu_or_acc[1] = 0;
@@ -200,15 +229,7 @@ void emu_launch(void (*k)(KA...), dim3 g, dim3 b, size_t, A... args) {
       });
     for (auto &x : th) x.join();
   }
+  emu_lds_limit(fsmp::emu_lds_bytes);
 }
 #define hipLaunchKernelGGL(K, G, B, L, S, ...) emu_launch(K, dim3(G), dim3(B), (size_t)(L), __VA_ARGS__)
 
-// the kernels' dynamic LDS (each launch's blocks run one at a time, so one array per name);
-// declared in the library's namespaces, where the kernels' block-scope declarations find them
-namespace fsmp {
-namespace {
-alignas(16) double vt[160 * 1024 / 8];
-alignas(16) double smem[160 * 1024 / 8];
-alignas(16) double lds[160 * 1024 / 8];
-}  // namespace
-}  // namespace fsmp

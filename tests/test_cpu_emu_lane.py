@@ -7,8 +7,8 @@ blocks one after the other with one OS thread per GPU thread).  fsmp_sample is c
 small driver exactly as a caller would, so every host step of the call (batch checks, the
 capacity buckets, the workspace layout, the prologue kernel and the chain launches) runs over
 buffers that AddressSanitizer watches, each device buffer its own allocation of the size the
-library asks for: an access outside any of them, in host or kernel code, ends the run with a
-report.  Only the lane design can run here (the lane-group kernels need the wavefront's
+library asks for and each launch's LDS the size it asks for: an access outside any of them, in
+host or kernel code, ends the run with a report.  Only the lane design can run here (the lane-group kernels need the wavefront's
 cross-lane operations), so the batches hold waveforms of PE capacity 16 and 32."""
 import os
 import shutil
@@ -57,7 +57,10 @@ def _run_emu(tmp, wl, wave, offsets, lam, km, n_steps, burn, n_chains, seed, des
     if t0_init is not None:
         np.ascontiguousarray(t0_init, dtype=np.float64).tofile(os.path.join(tmp, "t0_init.f64"))
     exe = build_emu.build()
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:halt_on_error=1")
+    # every allocation starts filled with 0xbe bytes (an index read before it is written is
+    # then far out of range), as device memory holds whatever an earlier kernel left
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:malloc_fill_byte=190:"
+                                        "max_malloc_fill_size=4294967296")
     r = subprocess.run([exe, tmp], env=env, capture_output=True, text=True, timeout=900)
     assert r.returncode == 0, f"emulated fsmp_sample failed ({r.returncode}):\n{r.stdout[-2000:]}\n{r.stderr[:6000]}"
     C = len(lam) * n_chains
