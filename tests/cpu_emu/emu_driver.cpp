@@ -1,5 +1,5 @@
 // Runs fsmp_sample of the library built for the CPU emulation (hip/hip_runtime.h here) on a
-// batch written by tests/test_cpu_emu_lane.py, and writes the chains' outputs.  Test
+// batch written by tests/test_cpu_emu.py, and writes the chains' outputs.  Test
 // infrastructure only.  Files in the directory argv[1] (raw little-endian):
 //   ser.bin, intensity.bin, config.bin   fsmp_ser, fsmp_intensity, fsmp_config as in fsmp.h
 //   design.txt                           one design per PE capacity (8 integers)

@@ -1,11 +1,15 @@
 // CPU emulation of the part of the HIP runtime and device language the library's sources
-// use, for running the one-lane-per-chain kernel and the prologue through the library's own
-// host code on the CPU, under AddressSanitizer (tests/test_cpu_emu_lane.py).  Test
-// infrastructure only: "device" memory is host memory, copies are synchronous, streams and
-// events do nothing, and a kernel launch runs its blocks one after the other with one OS
-// thread per GPU thread (a std::barrier for __syncthreads).  The cross-lane operations of
-// the lane-group kernels (shuffles, DPP, ballot) abort if reached: only kernels without them
-// may run here.
+// use, for running the library's kernels through its own host code on the CPU, under
+// AddressSanitizer (tests/test_cpu_emu.py).  Test infrastructure only: "device" memory is
+// host memory, copies are synchronous, streams and events do nothing, and a kernel launch runs
+// its blocks one after the other with one OS thread per GPU thread.  Barriers: a std::barrier
+// per block for __syncthreads and one per wavefront of 64 threads for the wavefront barrier.
+// Cross-lane operations (shuffles, the DPP patterns the kernels use, ballot) go through a
+// per-wavefront exchange: each lane writes its value to its slot, the wavefront passes its
+// barrier, each lane reads the slot of its source lane, and the wavefront passes its barrier
+// again.  A lane's phases pair with those of the other lanes of its wavefront whatever code
+// they run, so lanes of different chains of one wavefront may take different branches, as
+// long as every exchange reads a lane of the same chain (all the kernels' do).
 #pragma once
 #include <barrier>
 #if defined(__SANITIZE_ADDRESS__)
@@ -16,7 +20,9 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
+#include <memory>
 #include <thread>
 #include <vector>
 
@@ -38,6 +44,9 @@ struct emu_idx {
 inline thread_local emu_idx emu_threadIdx{0, 0, 0}, emu_blockIdx{0, 0, 0}, emu_blockDim{1, 1, 1},
     emu_gridDim{1, 1, 1};
 inline thread_local std::barrier<> *emu_bar = nullptr;
+inline thread_local std::barrier<> *emu_wbar = nullptr;  // the thread's wavefront barrier
+inline thread_local uint64_t *emu_xbuf = nullptr;        // its wavefront's exchange slots [64]
+inline thread_local int emu_lane = 0;                    // its lane in the wavefront
 inline thread_local int emu_or_gen = 0;
 inline int emu_or_acc[2];
 #define threadIdx emu_threadIdx
@@ -46,7 +55,7 @@ inline int emu_or_acc[2];
 #define gridDim emu_gridDim
 
 [[noreturn]] inline void emu_unreachable(const char *what) {
-  std::fprintf(stderr, "cpu emulation: %s reached (a lane-group kernel ran)\n", what);
+  std::fprintf(stderr, "cpu emulation: %s reached\n", what);
   std::abort();
 }
 
@@ -60,18 +69,62 @@ inline int __syncthreads_or(int v) {
   emu_bar->arrive_and_wait();
   return r;
 }
-template <typename T>
-T __shfl(T, int, int = 64) {
-  emu_unreachable("__shfl");
+// one exchange phase: write this lane's bits, read lane src's (0..63)
+inline uint64_t emu_exchange(uint64_t mine, int src) {
+  emu_xbuf[emu_lane] = mine;
+  emu_wbar->arrive_and_wait();
+  const uint64_t r = emu_xbuf[src & 63];
+  emu_wbar->arrive_and_wait();
+  return r;
 }
 template <typename T>
-T __shfl_xor(T, int, int = 64) {
-  emu_unreachable("__shfl_xor");
+uint64_t emu_bits(T v) {
+  static_assert(sizeof(T) <= 8, "exchange of at most 64 bits");
+  uint64_t u = 0;
+  std::memcpy(&u, &v, sizeof(T));
+  return u;
 }
-inline unsigned long long __ballot(int) { emu_unreachable("__ballot"); }
-#define __builtin_amdgcn_update_dpp(...) (emu_unreachable("DPP"), 0)
+template <typename T>
+T emu_from_bits(uint64_t u) {
+  T v;
+  std::memcpy(&v, &u, sizeof(T));
+  return v;
+}
+// HIP's definitions: __shfl reads lane src + the first lane of the caller's width segment;
+// __shfl_xor reads lane ^ mask, or the caller's own value if that leaves its segment
+template <typename T>
+T __shfl(T v, int src, int width = 64) {
+  const int index = src + (emu_lane & ~(width - 1));
+  return emu_from_bits<T>(emu_exchange(emu_bits(v), index));
+}
+template <typename T>
+T __shfl_xor(T v, int mask, int width = 64) {
+  int index = emu_lane ^ mask;
+  if (index >= ((emu_lane + width) & ~(width - 1))) index = emu_lane;
+  return emu_from_bits<T>(emu_exchange(emu_bits(v), index));
+}
+inline unsigned long long __ballot(int pred) {
+  emu_xbuf[emu_lane] = pred ? 1u : 0u;
+  emu_wbar->arrive_and_wait();
+  unsigned long long m = 0;
+  for (int l = 0; l < 64; ++l) m |= (unsigned long long)(emu_xbuf[l] != 0) << l;
+  emu_wbar->arrive_and_wait();
+  return m;
+}
+// DPP moves: quad_perm, row_ror:1..15 (lane i of a row of 16 reads lane i - n), row_newbcast:k;
+// every source lane exists for these, so old, the masks and bound_ctrl do not matter
+inline int emu_update_dpp(int old, int src, int ctrl, int, int, bool) {
+  (void)old;
+  int from;
+  if (ctrl >= 0 && ctrl <= 0xFF) from = (emu_lane & ~3) | ((ctrl >> (2 * (emu_lane & 3))) & 3);
+  else if (ctrl >= 0x121 && ctrl <= 0x12F) from = (emu_lane & ~15) | (((emu_lane & 15) - (ctrl & 15)) & 15);
+  else if (ctrl >= 0x150 && ctrl <= 0x15F) from = (emu_lane & ~15) | (ctrl & 15);
+  else emu_unreachable("a DPP control the emulation does not model");
+  return emu_from_bits<int>(emu_exchange(emu_bits(src), from));
+}
+#define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) emu_update_dpp((old), (src), (ctrl), (rm), (bm), (bc))
 #define __builtin_amdgcn_fence(...) ((void)0)
-#define __builtin_amdgcn_wave_barrier() ((void)0)
+#define __builtin_amdgcn_wave_barrier() emu_wbar->arrive_and_wait()
 inline int __double2loint(double v) {
   long long u;
   std::memcpy(&u, &v, 8);
@@ -210,8 +263,13 @@ void emu_launch(void (*k)(KA...), dim3 g, dim3 b, size_t lds_bytes, A... args) {
   if (g.y != 1 || g.z != 1 || b.y != 1 || b.z != 1) emu_unreachable("a multi-dimensional launch");
   if (lds_bytes > fsmp::emu_lds_bytes) emu_unreachable("a launch asking for more than 160 KiB of LDS");
   emu_lds_limit(lds_bytes);
+  const unsigned n_waves = (b.x + 63) / 64;
   for (unsigned bx = 0; bx < g.x; ++bx) {
     std::barrier<> bar((std::ptrdiff_t)b.x);
+    std::vector<std::unique_ptr<std::barrier<>>> wbar;
+    std::vector<uint64_t> xbuf(64 * n_waves, 0);
+    for (unsigned w = 0; w < n_waves; ++w)
+      wbar.emplace_back(new std::barrier<>((std::ptrdiff_t)std::min(64u, b.x - 64 * w)));
     emu_or_acc[0] = emu_or_acc[1] = 0;
     std::vector<std::thread> th;
     th.reserve(b.x);
@@ -222,10 +280,17 @@ void emu_launch(void (*k)(KA...), dim3 g, dim3 b, size_t lds_bytes, A... args) {
         emu_blockDim = {b.x, 1, 1};
         emu_gridDim = {g.x, 1, 1};
         emu_bar = &bar;
+        emu_wbar = wbar[t / 64].get();
+        emu_xbuf = xbuf.data() + 64 * (t / 64);
+        emu_lane = (int)(t % 64);
         emu_or_gen = 0;
         k(args...);
+        // a lane that has left reads as 0 in a ballot and no longer holds up its wavefront
+        emu_xbuf[emu_lane] = 0;
+        emu_wbar->arrive_and_drop();
         bar.arrive_and_drop();
         emu_bar = nullptr;
+        emu_wbar = nullptr;
       });
     for (auto &x : th) x.join();
   }

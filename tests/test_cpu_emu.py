@@ -8,8 +8,9 @@ small driver exactly as a caller would, so every host step of the call (batch ch
 capacity buckets, the workspace layout, the prologue kernel and the chain launches) runs over
 buffers that AddressSanitizer watches, each device buffer its own allocation of the size the
 library asks for and each launch's LDS the size it asks for: an access outside any of them, in
-host or kernel code, ends the run with a report.  Only the lane design can run here (the lane-group kernels need the wavefront's
-cross-lane operations), so the batches hold waveforms of PE capacity 16 and 32."""
+host or kernel code, ends the run with a report.  The lane-group kernels run there too: their shuffles, DPP moves, ballots and
+wavefront barriers go through a per-wavefront exchange, so the device-memory designs (narrow
+and wide lane groups) are checked the same way, up to capacity 160."""
 import os
 import shutil
 import subprocess
@@ -132,3 +133,24 @@ def test_lane_design_edges_and_records_on_the_cpu_under_asan(tmp_path):
     np.testing.assert_allclose(g["trace"], o.trace, rtol=1e-9, atol=1e-9)
     np.testing.assert_allclose(g["qdraw"], o.qdraw, rtol=1e-8, atol=1e-9, equal_nan=True)
     assert (o.zdraw >= 0).sum() > 0
+
+
+@pytest.mark.parametrize("design", ["narrow", "wide"])
+def test_device_memory_groups_on_the_cpu_under_asan(tmp_path, design):
+    # pile-up waveforms at capacities 48-160: lane groups with G^-1 (and the exact G of the
+    # corrected form) in device memory, narrow groups or the wide ones (one chain per
+    # wavefront from capacity 64 up)
+    wl = synth.PRESETS["pileup"]
+    lam = np.array([20.0, 45.0, 60.0, 80.0, 100.0])
+    b = synth.generate(wl, n_wave=len(lam), seed=9, lam=lam)
+    km = synth.kmax_for(b["lam"]).astype(np.int32)
+    assert set(km.tolist()) >= {48, 96, 128, 160}
+    d = fsmp.FSMP_DESIGN_GROUP_DEVMEM if design == "narrow" else fsmp.FSMP_DESIGN_GROUP_DEVMEM_WIDE
+    n_steps, burn, n_chains, seed = 60, 30, 2, 4
+    g = _run_emu(str(tmp_path), wl, b["wave"], b["offsets"], b["lam"], km, n_steps, burn, n_chains, seed,
+                 [fsmp.FSMP_DESIGN_GROUP_DEVMEM] + [d] * 7)
+    o = oracle.run(oracle_params(wl), b["wave"], b["offsets"], b["lam"], n_chains, n_steps, burn, seed,
+                   int(km.max()), kmax=km)
+    parted = compare_chains(g, o)
+    assert len(parted) == 0, parted
+    assert (g["n_pe"] > 5).all()
