@@ -334,9 +334,10 @@ size_t fsmp_workspace_bytes(const fsmp_ctx *ctx, const fsmp_batch *batch);
  * write `out`.  Validates every host array first (FSMP_EINVAL, nothing enqueued); returns
  * FSMP_ENOTSUP if a kmax exceeds 192 or the SER support does not fit a kernel.  The work is
  * enqueued on `hip_stream` (a hipStream_t; NULL = the null stream) and is complete when that
- * stream is: the PE-capacity buckets of the batch run concurrently on the context's own
- * side streams (at most GPU_MAX_HW_QUEUES of them, default 4), forked from and joined back
- * into `hip_stream` with events.  The calls of one context share its workspace: give them
+ * stream is: the PE-capacity buckets of the batch run concurrently, on `hip_stream` and on
+ * the context's own side streams (GPU_MAX_HW_QUEUES lanes in all, default 4), forked from and
+ * joined back into `hip_stream` with events; buckets are dealt to the lanes by estimated cost
+ * (after fsmp_autotune, its trial times of the chosen designs).  The calls of one context share its workspace: give them
  * one stream, or order their streams, so that two calls never run on the device at once. */
 fsmp_status fsmp_sample(fsmp_ctx *ctx, const fsmp_batch *batch, const fsmp_samples *out, void *hip_stream);
 
@@ -370,7 +371,8 @@ fsmp_status fsmp_sample_noalloc(fsmp_ctx *ctx, const fsmp_batch *batch, const fs
  * [chain][cfg.n_steps]) receive what the kernel computes for each evaluated proposal; 0
  * and -inf for steps not evaluated (not flagged valid, malformed, or invalid here, e.g. a
  * Schur complement that is not positive).  Runs the lane-group kernels with G^-1 in
- * device memory at every capacity, FP64 form only (FSMP_ENOTSUP otherwise).  `out`
+ * device memory at every capacity (the wide ones where the context has chosen them at
+ * capacity 64 and up), FP64 form only (FSMP_ENOTSUP otherwise).  `out`
  * receives the final state and accumulators as in fsmp_sample.  Errors as fsmp_sample. */
 fsmp_status fsmp_replay(fsmp_ctx *ctx, const fsmp_batch *batch, const fsmp_logrec *log, double *dnu,
                         double *log_alpha, const fsmp_samples *out, void *hip_stream);
@@ -436,7 +438,8 @@ fsmp_status fsmp_set_timing(fsmp_ctx *ctx, int32_t enable);
  * 96, 128, 160, 192; a waveform runs in the smallest one >= its kmax.  capacity 0 = every
  * capacity that has the design.  FSMP_ENOTSUP if the requested pair does not exist.  The
  * FP32-refresh form and the mixture charge law run FSMP_DESIGN_GROUP_DEVMEM only (the FP32
- * form runs capacity 48 at 64); replays run FSMP_DESIGN_GROUP_DEVMEM. */
+ * form runs capacity 48 at 64); replays run FSMP_DESIGN_GROUP_DEVMEM, or
+ * FSMP_DESIGN_GROUP_DEVMEM_WIDE where the context has it at capacity 64 and up. */
 enum { FSMP_DESIGN_GROUP = 0, FSMP_DESIGN_LANE = 1, FSMP_DESIGN_GROUP_DEVMEM = 2, FSMP_DESIGN_GROUP_DEVMEM_WIDE = 3 };
 fsmp_status fsmp_set_design(fsmp_ctx *ctx, int32_t capacity, int32_t design);
 int32_t fsmp_get_design(const fsmp_ctx *ctx, int32_t capacity);

@@ -215,13 +215,17 @@ struct fsmp_ctx {
   bool stage_pending = false;
   bool timing = false;
   bool serial = false;  // the autotuner's trials: the buckets one after the other on the call's stream
+  // per PE capacity the autotuner's trial time (ms) of the design it chose, and that design
+  // (-1: none); fsmp_sample takes them as the buckets' costs when it deals them to streams
+  double tuned_ms[kNumCaps] = {-1, -1, -1, -1, -1, -1, -1, -1};
+  int tuned_design[kNumCaps] = {-1, -1, -1, -1, -1, -1, -1, -1};
   hipStream_t capture = nullptr;  // set while fsmp_graph_create captures the kernels
   hipGraph_t captured = nullptr;
   std::vector<fsmp_timing> timings;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timing_events;
   std::vector<hipEvent_t> evpool;
-  // capacity buckets run concurrently: each on its own stream, forked from and joined
-  // back into the caller's stream with events
+  // capacity buckets run concurrently: on the caller's stream and on side streams forked
+  // from and joined back into it with events
   hipStream_t side[kNumCaps] = {};
   hipEvent_t fork = nullptr, join[kNumCaps] = {};
   // this device's copy of the allocation-free variant's scratch array (null if its address
@@ -721,7 +725,11 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   int64_t bucket_start[kNumCaps + 1] = {0};
   const bool fp32 = cf.precision == FSMP_FP32_REFRESH;
   auto design_of = [&](int bi) {
-    return force ? FSMP_DESIGN_GROUP_DEVMEM : effective_design(c, caps[bi], c->design[bi]);
+    const int dz = effective_design(c, caps[bi], c->design[bi]);
+    // a replay runs the device-memory groups: the wide ones where the context has chosen them
+    // at capacity 64 and up, else the narrow ones
+    if (force) return dz == FSMP_DESIGN_GROUP_DEVMEM_WIDE && caps[bi] >= 64 ? dz : FSMP_DESIGN_GROUP_DEVMEM;
+    return dz;
   };
   // within a bucket, waveforms with per-waveform sweep counts in 16 bins of the batch's
   // largest count, the longest first, so that the chains of a workgroup end together and the
@@ -989,42 +997,56 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
   for (int bi = 0; bi < kNumCaps; ++bi) n_buckets += bucket_start[bi + 1] > bucket_start[bi];
   // the allocation-free variant runs the buckets one after the other on the caller's stream
   const bool fan = n_buckets > 1 && !noalloc && !c->serial;
-  // Side streams: no more than the process has hardware queues (GPU_MAX_HW_QUEUES, HIP's
-  // default 4), since streams beyond that share a queue and run one after the other. The
-  // buckets go to them largest estimated cost first, each to the least loaded stream (cost
-  // = chains x a per-capacity weight, the measured time of one sweep of one chain relative
-  // to capacity 16); a stream runs its buckets in capacity order.
-  int side_of[kNumCaps] = {};
+  // Lanes of concurrent work: the caller's stream and up to GPU_MAX_HW_QUEUES - 1 side
+  // streams (the process has that many hardware queues, HIP's default 4; the caller's stream
+  // holds one, and streams beyond them would share a queue and run one after the other). The
+  // buckets go to the lanes largest estimated cost first, each to the least loaded lane; a
+  // lane runs its buckets in capacity order. A bucket's cost is the autotuner's trial time of
+  // its design when the context has one for every bucket of the call, else its chains' sweeps
+  // times a per-capacity weight (the measured time of one sweep of one chain relative to
+  // capacity 16).
+  int lane_of[kNumCaps] = {};
+  int n_lanes = 1;
   if (fan) {
-    int n_side = 4;
+    int n_queues = 4;
     if (const char *q = std::getenv("GPU_MAX_HW_QUEUES")) {
       const int v = std::atoi(q);
-      if (v > 0) n_side = v;
+      if (v > 0) n_queues = v;
     }
-    if (n_side > n_buckets) n_side = n_buckets;
-    if (n_side > kNumCaps) n_side = kNumCaps;
+    n_lanes = std::min(std::min(n_queues, n_buckets), kNumCaps);
     static const double kWeight[kNumCaps] = {1.0, 3.8, 5.4, 8.8, 16.0, 25.0, 35.0, 45.0};
+    double cost[kNumCaps] = {};
+    bool tuned = true;
+    for (int bi = 0; bi < kNumCaps; ++bi)
+      if (bucket_start[bi + 1] > bucket_start[bi] &&
+          !(c->tuned_ms[bi] > 0.0 && c->tuned_design[bi] == design_of(bi)))
+        tuned = false;
+    for (int bi = 0; bi < kNumCaps; ++bi) {
+      if (tuned) {
+        cost[bi] = bucket_start[bi + 1] > bucket_start[bi] ? c->tuned_ms[bi] : 0.0;
+        continue;
+      }
+      double sweeps = 0.0;
+      for (int64_t k = bucket_start[bi]; k < bucket_start[bi + 1]; ++k)
+        sweeps += b->n_steps ? (double)b->n_steps[order[k] / cf.n_chains] : (double)cf.n_steps;
+      cost[bi] = sweeps * kWeight[bi];
+    }
     double load[kNumCaps] = {};
     bool done[kNumCaps] = {};
     for (int r = 0; r < n_buckets; ++r) {
       int best = -1;
-      double bc = -1.0;
-      for (int bi = 0; bi < kNumCaps; ++bi) {
-        const double cost = (double)(bucket_start[bi + 1] - bucket_start[bi]) * kWeight[bi];
-        if (!done[bi] && bucket_start[bi + 1] > bucket_start[bi] && cost > bc) {
-          bc = cost;
-          best = bi;
-        }
-      }
-      int sq = 0;
-      for (int k = 1; k < n_side; ++k)
-        if (load[k] < load[sq]) sq = k;
-      side_of[best] = sq;
-      load[sq] += bc;
+      for (int bi = 0; bi < kNumCaps; ++bi)
+        if (!done[bi] && bucket_start[bi + 1] > bucket_start[bi] && (best < 0 || cost[bi] > cost[best])) best = bi;
+      int ln = 0;
+      for (int k = 1; k < n_lanes; ++k)
+        if (load[k] < load[ln]) ln = k;
+      lane_of[best] = ln;
+      load[ln] += cost[best];
       done[best] = true;
     }
   }
-  if (fan && e == hipSuccess) {
+  const bool fork_join = fan && n_lanes > 1;
+  if (fork_join && e == hipSuccess) {
     if (!c->fork) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(c->fork, st);
   }
@@ -1032,8 +1054,10 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
     const int64_t cnt = bucket_start[bi + 1] - bucket_start[bi];
     if (cnt == 0) continue;
     hipStream_t ks = st;
-    if (fan) {
-      const int sq = side_of[bi];
+    // lane 0 is the caller's stream, lane k > 0 side stream k - 1
+    const bool side = fork_join && lane_of[bi] > 0;
+    if (side) {
+      const int sq = lane_of[bi] - 1;
       if (!c->side[sq]) e = hipStreamCreateWithFlags(&c->side[sq], hipStreamNonBlocking);
       if (e == hipSuccess && !c->join[bi]) e = hipEventCreateWithFlags(&c->join[bi], hipEventDisableTiming);
       if (e == hipSuccess) e = hipStreamWaitEvent(c->side[sq], c->fork, 0);
@@ -1057,12 +1081,15 @@ fsmp_status sample_impl(fsmp_ctx *c, const fsmp_batch *b, const fsmp_samples *o,
                                        : launch_chain_dm(caps[bi], fp32, dz == FSMP_DESIGN_GROUP_DEVMEM_WIDE, ca, ks,
                                                          &t.lanes, &t.blocks);
     });
-    if (fan) {
+    if (side) {
       const hipError_t e2 = hipEventRecord(c->join[bi], ks);
-      const hipError_t e3 = e2 == hipSuccess ? hipStreamWaitEvent(st, c->join[bi], 0) : e2;
-      if (e == hipSuccess) e = e3;
+      if (e == hipSuccess) e = e2;
     }
   }
+  // the caller's stream waits for the side lanes after its own buckets are enqueued
+  if (fork_join)
+    for (int bi = 0; bi < kNumCaps && e == hipSuccess; ++bi)
+      if (bucket_start[bi + 1] > bucket_start[bi] && lane_of[bi] > 0) e = hipStreamWaitEvent(st, c->join[bi], 0);
   if (c->capture) {
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(c->capture, &g);
@@ -1215,6 +1242,8 @@ fsmp_status fsmp_autotune(fsmp_ctx *c, const fsmp_batch *b, int32_t trial_steps,
       for (int d = 0; d < kDesigns; ++d)
         if (ms[d][q] >= 0.0 && (best < 0 || ms[d][q] < ms[best][q])) best = d;
       if (best >= 0) c->design[q] = best;
+      c->tuned_design[q] = best;
+      c->tuned_ms[q] = best >= 0 ? ms[best][q] : -1.0;
     }
   (void)hipStreamSynchronize((hipStream_t)hip_stream);
   i1.release();

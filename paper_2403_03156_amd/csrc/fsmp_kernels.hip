@@ -2743,7 +2743,18 @@ hipError_t launch_chain(int kcap, const ChainArgs &a, hipStream_t st, int32_t *l
 hipError_t launch_chain_dm(int kcap, bool fp32, bool wide, const ChainArgs &a, hipStream_t st, int32_t *lanes,
                            int64_t *blocks) {
   if (wide) {
-    if (a.md.n_mix > 0 || a.force || fp32) return hipErrorInvalidValue;
+    if (a.md.n_mix > 0 || fp32) return hipErrorInvalidValue;
+    if (a.force) {
+      // replay with the wide groups, capacities from 64 up
+      switch (kcap) {
+        case 64: return launch_chain_t<64, 64, 4, true, true>(a, st, lanes, blocks);
+        case 96: return launch_chain_t<96, 64, 4, true, true>(a, st, lanes, blocks);
+        case 128: return launch_chain_t<128, 64, 4, true, true>(a, st, lanes, blocks);
+        case 160: return launch_chain_t<160, 64, 4, true, true>(a, st, lanes, blocks);
+        case 192: return launch_chain_t<192, 64, 2, true, true>(a, st, lanes, blocks);
+        default: return hipErrorInvalidValue;
+      }
+    }
     switch (kcap) {
       case 32: return launch_chain_t<32, 16, 4, true>(a, st, lanes, blocks);
       case 48: return launch_chain_t<48, 32, 4, true>(a, st, lanes, blocks);

@@ -146,11 +146,19 @@ def test_device_memory_groups_on_the_cpu_under_asan(tmp_path, design):
     km = synth.kmax_for(b["lam"]).astype(np.int32)
     assert set(km.tolist()) >= {48, 96, 128, 160}
     d = fsmp.FSMP_DESIGN_GROUP_DEVMEM if design == "narrow" else fsmp.FSMP_DESIGN_GROUP_DEVMEM_WIDE
-    n_steps, burn, n_chains, seed = 60, 30, 2, 4
+    n_steps, burn, n_chains, seed, thin = 60, 30, 2, 4, 7
+    flags = fsmp.FSMP_REC_LOG | fsmp.FSMP_REC_TRACE | fsmp.FSMP_REC_CHARGE
     g = _run_emu(str(tmp_path), wl, b["wave"], b["offsets"], b["lam"], km, n_steps, burn, n_chains, seed,
-                 [fsmp.FSMP_DESIGN_GROUP_DEVMEM] + [d] * 7)
+                 [fsmp.FSMP_DESIGN_GROUP_DEVMEM] + [d] * 7, record_flags=flags, thin=thin)
     o = oracle.run(oracle_params(wl), b["wave"], b["offsets"], b["lam"], n_chains, n_steps, burn, seed,
-                   int(km.max()), kmax=km)
+                   int(km.max()), kmax=km, log=True, thin=thin, charges=True)
     parted = compare_chains(g, o)
     assert len(parted) == 0, parted
     assert (g["n_pe"] > 5).all()
+    for f in ("move", "flags", "j", "g"):
+        np.testing.assert_array_equal(g["log"][f], o.log[f])
+    v = (o.log["flags"] & 1) != 0
+    np.testing.assert_allclose(g["log"]["dnu"][v], o.log["dnu"][v], rtol=1e-8, atol=1e-8)
+    np.testing.assert_array_equal(g["zdraw"], o.zdraw)
+    np.testing.assert_allclose(g["trace"], o.trace, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(g["qdraw"], o.qdraw, rtol=1e-7, atol=1e-8, equal_nan=True)

@@ -77,7 +77,7 @@ def test_charge_draws_high_capacity():
                         tau_rise=base.tau_rise, tau_decay=base.tau_decay, sigma_q=0.35, sigma_eps=0.1)
     b = synth.generate(wl, n_wave=6, seed=5)
     km = synth.kmax_for(b["lam"])
-    for design in (None, fsmp.FSMP_DESIGN_GROUP_DEVMEM):
+    for design in (None, fsmp.FSMP_DESIGN_GROUP_DEVMEM, fsmp.FSMP_DESIGN_GROUP_DEVMEM_WIDE):
         g, o, parted = _run(wl, b, km, 160, 80, 20, 3, design=design)
         _check_identical_chains(g, o, parted, rtol=1e-7, atol=1e-8)
 

@@ -44,13 +44,19 @@ def _ext_reference(p, b, km, log, n_chains, seed):
     return np.stack([r[0] for r in res]), np.stack([r[1] for r in res])
 
 
-def _replay_oracle_log(wl, b, km, n_steps, n_chains, seed, extended=False):
+def _replay_oracle_log(wl, b, km, n_steps, n_chains, seed, extended=False, wide=False):
+    """wide: the wide lane groups (one chain per wavefront) from capacity 64 up, else the
+    narrow ones"""
     kz = int(km.max())
-    print(f"[case] replay {wl.name} n={len(km)} caps={sorted(set(km.tolist()))} steps={n_steps}", flush=True)
+    print(f"[case] replay {wl.name} n={len(km)} caps={sorted(set(km.tolist()))} steps={n_steps} wide={wide}",
+          flush=True)
     p = oracle_params(wl)
     o = oracle.run(p, b["wave"], b["offsets"], b["lam"], n_chains, n_steps, n_steps // 2, seed, kz, kmax=km,
                    log=True)
     smp = gpu_sampler(wl, n_steps, n_steps // 2, n_chains, seed)
+    if wide:
+        for cap in (64, 96, 128, 160, 192):
+            smp.set_design(cap, fsmp.FSMP_DESIGN_GROUP_DEVMEM_WIDE)
     dnu, la, out = smp.replay(torch.from_numpy(b["wave"]).cuda(), b["offsets"], b["lam"], o.log, kmax=km, kz=kz)
     torch.cuda.synchronize()
     dnu, la = dnu.cpu().numpy(), la.cpu().numpy()
@@ -83,16 +89,18 @@ def test_replay_oracle_log_batched():
     _replay_oracle_log(wl, b, km, 300, 2, 21)
 
 
-def test_replay_oracle_log_high_capacity():
+@pytest.mark.parametrize("wide", [False, True])
+def test_replay_oracle_log_high_capacity(wide):
     wl = synth.PRESETS["pileup"]
     lam = np.array([20.0, 45.0, 60.0, 80.0, 100.0])
     b = synth.generate(wl, n_wave=len(lam), seed=9, lam=lam)
     km = synth.kmax_for(b["lam"])
     assert km.max() >= 128
-    _replay_oracle_log(wl, b, km, 250, 1, 4, extended=True)
+    _replay_oracle_log(wl, b, km, 250, 1, 4, extended=True, wide=wide)
 
 
-def test_replay_long_chains_high_capacity():
+@pytest.mark.parametrize("wide", [False, True])
+def test_replay_long_chains_high_capacity(wide):
     # 4,000 sweeps at K ~ 90-110: the FP64 form edits G^-1 by rank-one / rank-two updates the
     # whole way; its delta-nu must stay within the bound to the last sweep
     wl = synth.PRESETS["pileup"]
@@ -100,7 +108,7 @@ def test_replay_long_chains_high_capacity():
     b = synth.generate(wl, n_wave=len(lam), seed=13, lam=lam)
     km = synth.kmax_for(b["lam"])
     assert km.min() >= 128
-    o, err = _replay_oracle_log(wl, b, km, 4000, 1, 8, extended=True)
+    o, err = _replay_oracle_log(wl, b, km, 4000, 1, 8, extended=True, wide=wide)
     assert o.N.min() >= 80
     valid = (o.log["flags"] & 1) != 0
     late = np.zeros_like(valid)

@@ -1,11 +1,12 @@
 """Side streams of the capacity buckets (needs an MI355X).
 
-fsmp_sample deals the PE-capacity buckets of a call to at most GPU_MAX_HW_QUEUES side
-streams (the library reads the variable at every call; HIP's own queue count is fixed at
-start-up and is not changed here). The stream a bucket runs on, and which buckets share a
-stream, must not change a single output. A batch of the uneven workload (seven buckets)
-is sampled with one, two, three and eight side streams and compared with the default four,
-output by output and bit for bit.
+fsmp_sample deals the PE-capacity buckets of a call to at most GPU_MAX_HW_QUEUES lanes, the
+caller's stream and side streams (the library reads the variable at every call; HIP's own
+queue count is fixed at start-up and is not changed here). The stream a bucket runs on, and
+which buckets share a stream, must not change a single output. A batch of the uneven workload
+(seven buckets) is sampled with one, two, three and eight lanes and compared with the default
+four, output by output and bit for bit; and after the design autotuner (whose trial times
+then set the buckets' costs) with one lane and with the default.
 """
 import numpy as np
 import pytest
@@ -41,12 +42,32 @@ def test_outputs_do_not_depend_on_side_streams(queues, monkeypatch):
     assert len(set(km.tolist())) >= 6
     if "ref" not in _REF:
         monkeypatch.delenv("GPU_MAX_HW_QUEUES", raising=False)
-        print(f"[case] side streams default caps={sorted(set(km.tolist()))}", flush=True)
+        print(f"[case] lanes default caps={sorted(set(km.tolist()))}", flush=True)
         _REF["ref"] = _run(wl, b, km)
     monkeypatch.setenv("GPU_MAX_HW_QUEUES", queues)
-    print(f"[case] side streams {queues}", flush=True)
+    print(f"[case] lanes {queues}", flush=True)
     g = _run(wl, b, km)
     ref = _REF["ref"]
     for k, v in ref.items():
         if isinstance(v, np.ndarray):
-            np.testing.assert_array_equal(g[k], v, err_msg=f"{k} with {queues} side streams")
+            np.testing.assert_array_equal(g[k], v, err_msg=f"{k} with {queues} lanes")
+
+
+def test_tuned_costs_do_not_change_outputs(monkeypatch):
+    wl, b, km = _batch()
+    smp = gpu_sampler(wl, 200, 100, 2, 13)
+    wave = torch.from_numpy(b["wave"]).cuda()
+    print("[case] lanes after the design autotuner", flush=True)
+    smp.autotune(wave, b["offsets"], b["lam"], kmax=km, trial_steps=20)
+    res = {}
+    for queues in ("1", None):
+        if queues is None:
+            monkeypatch.delenv("GPU_MAX_HW_QUEUES", raising=False)
+        else:
+            monkeypatch.setenv("GPU_MAX_HW_QUEUES", queues)
+        out = smp.sample(wave, b["offsets"], b["lam"], kmax=km, kz=int(km.max()))
+        torch.cuda.synchronize()
+        res[queues] = to_host(out)
+    for k, v in res["1"].items():
+        if isinstance(v, np.ndarray):
+            np.testing.assert_array_equal(res[None][k], v, err_msg=k)
