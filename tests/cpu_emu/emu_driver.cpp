@@ -2,12 +2,14 @@
 // batch written by tests/test_cpu_emu.py, and writes the chains' outputs.  Test
 // infrastructure only.  Files in the directory argv[1] (raw little-endian):
 //   ser.bin, intensity.bin, config.bin   fsmp_ser, fsmp_intensity, fsmp_config as in fsmp.h
-//   design.txt                           one design per PE capacity (8 integers)
+//   design.txt                           one design per PE capacity (8 integers, -1: the default)
 //   kz.txt                               the output row length
-//   wave.f32, offsets.i64, lam.f64, kmax.i32, and when present g_range.i32, t0_init.f64
+//   wave.f32, offsets.i64, lam.f64, kmax.i32, and when present g_range.i32, t0_init.f64,
+//   noalloc (empty: call fsmp_sample_noalloc instead of fsmp_sample)
 // and written there: n_pe.i32, t0.f64, z.i32, charge.f64, acc.f64, nhist.i32, counts.i32,
-// status.u32, work.f64, rec_steps.i32, and as the configuration's record flags ask, log.bin
-// (fsmp_logrec per chain and step), trace.f64, qdraw.f64, zdraw.i32.
+// status.u32, work.f64, rec_steps.i32, comp.i32 (with a mixture charge law), and as the
+// configuration's record flags ask, log.bin (fsmp_logrec per chain and step), trace.f64,
+// qdraw.f64, zdraw.i32.
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -93,7 +95,7 @@ int main(int argc, char **argv) {
   }
   static const int caps[8] = {16, 32, 48, 64, 96, 128, 160, 192};
   for (int q = 0; q < 8; ++q)
-    if (fsmp_set_design(ctx, caps[q], design[q]) != FSMP_OK) {
+    if (design[q] >= 0 && fsmp_set_design(ctx, caps[q], design[q]) != FSMP_OK) {
       std::fprintf(stderr, "set_design %d %d: %s\n", caps[q], design[q], fsmp_last_error(ctx));
       return 1;
     }
@@ -105,7 +107,7 @@ int main(int argc, char **argv) {
   std::vector<fsmp_logrec> log((size_t)C * cfg.n_steps);
   const int64_t n_rec = cfg.thin > 0 ? (cfg.n_steps - cfg.burn_in + cfg.thin - 1) / cfg.thin : 0;
   std::vector<double> trace((size_t)C * n_rec * 3), qdraw((size_t)C * n_rec * kz), work((size_t)C * 5);
-  std::vector<int32_t> zdraw((size_t)C * n_rec * kz), rec_steps(C);
+  std::vector<int32_t> zdraw((size_t)C * n_rec * kz), rec_steps(C), comp((size_t)C * kz);
   fsmp_batch b{};
   b.n_wave = n;
   b.wave = wave.data();
@@ -129,8 +131,10 @@ int main(int argc, char **argv) {
   o.zdraw = (cfg.record_flags & FSMP_REC_CHARGE) ? zdraw.data() : nullptr;
   o.work = work.data();
   o.rec_steps = rec_steps.data();
+  o.comp = cfg.n_mix > 0 ? comp.data() : nullptr;
   o.kz = kz;
-  if (fsmp_sample(ctx, &b, &o, nullptr) != FSMP_OK) {
+  const bool noalloc = exists(d + "noalloc");
+  if ((noalloc ? fsmp_sample_noalloc(ctx, &b, &o, nullptr) : fsmp_sample(ctx, &b, &o, nullptr)) != FSMP_OK) {
     std::fprintf(stderr, "sample: %s\n", fsmp_last_error(ctx));
     return 1;
   }
@@ -149,6 +153,7 @@ int main(int argc, char **argv) {
   if (o.zdraw) spit(d + "zdraw.i32", zdraw);
   spit(d + "work.f64", work);
   spit(d + "rec_steps.i32", rec_steps);
+  if (o.comp) spit(d + "comp.i32", comp);
   std::printf("cpu emulation: %lld waveforms x %d chains x %d sweeps done\n", (long long)n, cfg.n_chains,
               cfg.n_steps);
   return 0;

@@ -36,11 +36,17 @@ def _subset(b, keep):
 
 
 def _run_emu(tmp, wl, wave, offsets, lam, km, n_steps, burn, n_chains, seed, design, record_flags=0, thin=1,
-             g_range=None, t0_init=None):
+             g_range=None, t0_init=None, precision=fsmp.FSMP_FP64, mix=None, noalloc=False):
     ser = fsmp.fsmp_ser(*wl.ser, 1.0, 0)
     phi = fsmp.fsmp_intensity(wl.phi_kind, wl.tau_rise, wl.tau_decay, wl.t0_min, wl.t0_max)
-    cfg = fsmp.fsmp_config(wl.sigma_eps, wl.mu_q, wl.sigma_q, 4, 0.25, 1.0, 1.0, 64, n_steps, n_chains, burn, thin,
-                           fsmp.FSMP_FP64, 128, record_flags, seed)
+    cfg = fsmp.fsmp_config(wl.sigma_eps, wl.mu_q, wl.sigma_q, 4, 0.25, 1.0, 1.0, 192, n_steps, n_chains, burn, thin,
+                           precision, 128 if precision == fsmp.FSMP_FP64 else 64, record_flags, seed)
+    if mix is not None:
+        cfg.n_mix = len(mix[0])
+        for i in range(cfg.n_mix):
+            cfg.mix_weight[i], cfg.mix_mu[i], cfg.mix_sigma[i] = mix[0][i], mix[1][i], mix[2][i]
+    if noalloc:
+        open(os.path.join(tmp, "noalloc"), "w").close()
     for name, s in (("ser", ser), ("intensity", phi), ("config", cfg)):
         with open(os.path.join(tmp, name + ".bin"), "wb") as f:
             f.write(bytes(s))
@@ -80,6 +86,8 @@ def _run_emu(tmp, wl, wave, offsets, lam, km, n_steps, burn, n_chains, seed, des
     if record_flags & fsmp.FSMP_REC_CHARGE:
         g["qdraw"] = rd("qdraw.f64", np.float64, (C, n_rec, kz))
         g["zdraw"] = rd("zdraw.i32", np.int32, (C, n_rec, kz))
+    if mix is not None:
+        g["comp"] = rd("comp.i32", np.int32, (C, kz))
     return g
 
 
@@ -162,3 +170,40 @@ def test_device_memory_groups_on_the_cpu_under_asan(tmp_path, design):
     np.testing.assert_array_equal(g["zdraw"], o.zdraw)
     np.testing.assert_allclose(g["trace"], o.trace, rtol=1e-9, atol=1e-9)
     np.testing.assert_allclose(g["qdraw"], o.qdraw, rtol=1e-7, atol=1e-8, equal_nan=True)
+
+
+# the five-Gaussian MCP-PMT charge law (weights, means, sigmas in units of the SER amplitude)
+MIX = ([0.041, 0.516, 0.187, 0.195, 0.061], [0.92, 1.98, 3.01, 4.70, 6.79], [0.22, 0.48, 0.80, 1.30, 2.04])
+
+
+@pytest.mark.parametrize("form", ["fp32_refresh", "mixture", "noalloc"])
+def test_other_forms_on_the_cpu_under_asan(tmp_path, form):
+    # the FP32-refresh form, the mixture charge law and the allocation-free entry point (its
+    # static scratch array and host tables), on the device-memory groups at capacities 16-64
+    wl = synth.PRESETS["batched"]
+    b = synth.generate(wl, n_wave=12, seed=12)
+    km = synth.kmax_for(b["lam"]).astype(np.int32)
+    assert len(set(km.tolist())) >= 3
+    n_steps, burn, n_chains, seed = 80, 40, 2, 6
+    p = oracle_params(wl)
+    kw = {}
+    if form == "fp32_refresh":
+        kw["precision"] = fsmp.FSMP_FP32_REFRESH
+    elif form == "mixture":
+        kw["mix"] = MIX
+        p.n_mix = len(MIX[0])
+        for i in range(p.n_mix):
+            p.mix_w[i], p.mix_mu[i], p.mix_sigma[i] = MIX[0][i], MIX[1][i], MIX[2][i]
+    else:
+        kw["noalloc"] = True
+    # (the FP32 form has no capacity-48 instance: its waveforms run at 64)
+    design = [fsmp.FSMP_DESIGN_GROUP_DEVMEM] * 8
+    if form == "fp32_refresh":
+        design[2] = -1
+    g = _run_emu(str(tmp_path), wl, b["wave"], b["offsets"], b["lam"], km, n_steps, burn, n_chains, seed, design,
+                 **kw)
+    o = oracle.run(p, b["wave"], b["offsets"], b["lam"], n_chains, n_steps, burn, seed, int(km.max()), kmax=km)
+    parted = compare_chains(g, o, tol=1e-7 if form == "fp32_refresh" else 1e-9)
+    assert len(parted) == 0, parted
+    if form == "mixture":
+        np.testing.assert_array_equal(g["comp"], o.e)
