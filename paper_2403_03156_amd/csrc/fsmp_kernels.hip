@@ -1224,7 +1224,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
     } else if (move == 2 && valid && lane == 0) {
       acc[17] += CORR ? (double)N : 1.0;
     }
-    // the survey's word count of the proposal (a packed Cholesky factor): birth K(K+1)/2 +
+    // the word count of the proposal in a packed Cholesky factor: birth K(K+1)/2 +
     // 2K + 3, death (K - j)(K - j + 1)/2 + 1, update both (the birth on K - 1 PEs)
     if (lane == 0 && (valid || need_mv || need_dp)) {
       const double K = N, r = N - j;
@@ -1241,7 +1241,7 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
       // an accepted zero shift changes nothing (unless it changes the PE's component)
       const bool shift = move == 3 && (sh != 0 || (MCP && enew != ek[j]));
       if (lane == 0) {
-        // the survey's word count of the edit (packed factor): birth K + 3, death
+        // the word count of the edit in a packed Cholesky factor: birth K + 3, death
         // (K - 1 - j)(K - j) + K(K + 1)/2, update both; and the G^-1 elements this kernel reads
         // and writes in its rank-one or rank-two edit
         const double K = N, r = N - j;
@@ -1961,7 +1961,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
       for (int i = 0; i < N; ++i) G1(i) = (i == j) ? 0.0 : overlap(md, vt, ov, gnew, ZG(i), Lw);
       dself = overlap(md, vt, ov, gnew, gnew, Lw) + md.rho;
       beta = mf[gnew - glo] + md.rhom;
-      // the survey's word count of the proposal (packed factor), and the G^-1 elements read
+      // the word count of the proposal in a packed Cholesky factor, and the G^-1 elements read
       {
         const double K = N, r = N - j;
         wk0 += move == 1 ? K * (K + 1) / 2 + 2 * K + 3 : r * (r + 1) / 2 + 1 + (K - 1) * K / 2 + 2 * (K - 1) + 3;
