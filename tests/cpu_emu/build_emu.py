@@ -18,9 +18,9 @@ FLAGS = ["-std=c++20", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-point
          "-Wno-attributes", "-Wno-unused-variable", "-Wno-unused-function"]
 
 
-def _hash():
+def _hash(csrc):
     h = hashlib.sha256()
-    for f in [os.path.join(CSRC, s) for s in SOURCES + HEADERS] + [os.path.join(INCLUDE, "fsmp.h"),
+    for f in [os.path.join(csrc, s) for s in SOURCES + HEADERS] + [os.path.join(INCLUDE, "fsmp.h"),
                                                                    os.path.join(HERE, "hip", "hip_runtime.h"),
                                                                    os.path.join(HERE, "emu_driver.cpp")]:
         h.update(open(f, "rb").read())
@@ -28,32 +28,33 @@ def _hash():
     return h.hexdigest()[:16]
 
 
-def build(verbose=False):
-    """Path of the emulation driver, compiled if the sources changed."""
-    tag = _hash()
-    exe = os.path.join(BUILD, f"emu_driver_{tag}")
+def build(verbose=False, csrc=CSRC, build_dir=BUILD):
+    """Path of the emulation driver, compiled if the sources changed (csrc: the directory of
+    the library's sources, build_dir: where to build, emptied first)."""
+    tag = _hash(csrc)
+    exe = os.path.join(build_dir, f"emu_driver_{tag}")
     if os.path.exists(exe):
         return exe
-    if os.path.isdir(BUILD):
-        shutil.rmtree(BUILD)
-    src = os.path.join(BUILD, "src", "csrc")
+    if os.path.isdir(build_dir):
+        shutil.rmtree(build_dir)
+    src = os.path.join(build_dir, "src", "csrc")
     os.makedirs(src)
-    os.makedirs(os.path.join(BUILD, "include"))
+    os.makedirs(os.path.join(build_dir, "include"))
     # the sources include "../../include/fsmp.h" relative to their own directory
-    shutil.copy(os.path.join(INCLUDE, "fsmp.h"), os.path.join(BUILD, "include", "fsmp.h"))
+    shutil.copy(os.path.join(INCLUDE, "fsmp.h"), os.path.join(build_dir, "include", "fsmp.h"))
     for h in HEADERS:
-        shutil.copy(os.path.join(CSRC, h), os.path.join(src, h))
+        shutil.copy(os.path.join(csrc, h), os.path.join(src, h))
     objs = []
     jobs = []
     for s in SOURCES:
         cpp = os.path.join(src, s.replace(".hip", ".cpp"))
-        shutil.copy(os.path.join(CSRC, s), cpp)
+        shutil.copy(os.path.join(csrc, s), cpp)
         obj = cpp[:-4] + ".o"
         cmd = ["g++", *FLAGS, "-I", HERE, "-c", cpp, "-o", obj]
         jobs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT))
         objs.append(obj)
-    drv = os.path.join(BUILD, "emu_driver.o")
-    jobs.append(subprocess.Popen(["g++", *FLAGS, "-I", HERE, "-I", os.path.join(BUILD, "include"), "-c",
+    drv = os.path.join(build_dir, "emu_driver.o")
+    jobs.append(subprocess.Popen(["g++", *FLAGS, "-I", HERE, "-I", os.path.join(build_dir, "include"), "-c",
                                   os.path.join(HERE, "emu_driver.cpp"), "-o", drv],
                                  stdout=subprocess.PIPE, stderr=subprocess.STDOUT))
     for j in jobs:

@@ -36,7 +36,8 @@ def _subset(b, keep):
 
 
 def _run_emu(tmp, wl, wave, offsets, lam, km, n_steps, burn, n_chains, seed, design, record_flags=0, thin=1,
-             g_range=None, t0_init=None, precision=fsmp.FSMP_FP64, mix=None, noalloc=False):
+             g_range=None, t0_init=None, precision=fsmp.FSMP_FP64, mix=None, noalloc=False, exe=None,
+             expect_ok=True):
     ser = fsmp.fsmp_ser(*wl.ser, 1.0, 0)
     phi = fsmp.fsmp_intensity(wl.phi_kind, wl.tau_rise, wl.tau_decay, wl.t0_min, wl.t0_max)
     cfg = fsmp.fsmp_config(wl.sigma_eps, wl.mu_q, wl.sigma_q, 4, 0.25, 1.0, 1.0, 192, n_steps, n_chains, burn, thin,
@@ -63,12 +64,14 @@ def _run_emu(tmp, wl, wave, offsets, lam, km, n_steps, burn, n_chains, seed, des
         np.ascontiguousarray(g_range, dtype=np.int32).tofile(os.path.join(tmp, "g_range.i32"))
     if t0_init is not None:
         np.ascontiguousarray(t0_init, dtype=np.float64).tofile(os.path.join(tmp, "t0_init.f64"))
-    exe = build_emu.build()
+    exe = exe or build_emu.build()
     # every allocation starts filled with 0xbe bytes (an index read before it is written is
     # then far out of range), as device memory holds whatever an earlier kernel left
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:malloc_fill_byte=190:"
                                         "max_malloc_fill_size=4294967296")
     r = subprocess.run([exe, tmp], env=env, capture_output=True, text=True, timeout=900)
+    if not expect_ok:
+        return r
     assert r.returncode == 0, f"emulated fsmp_sample failed ({r.returncode}):\n{r.stdout[-2000:]}\n{r.stderr[:6000]}"
     C = len(lam) * n_chains
     n_rec = -(-(n_steps - burn) // thin)
@@ -207,3 +210,29 @@ def test_other_forms_on_the_cpu_under_asan(tmp_path, form):
     assert len(parted) == 0, parted
     if form == "mixture":
         np.testing.assert_array_equal(g["comp"], o.e)
+
+
+def test_the_harness_reports_a_planted_overrun(tmp_path):
+    # the harness itself: a copy of the sources with one read planted past the end of a
+    # device buffer in the lane kernel must stop with AddressSanitizer's report at that kernel
+    csrc = tmp_path / "csrc"
+    shutil.copytree(build_emu.CSRC, csrc)
+    k = csrc / "fsmp_kernels.hip"
+    src = k.read_text()
+    at = src.index("chain_lane_kernel(ChainArgs a)")
+    old = "const int kmax = a.kmax[w];"
+    j = src.index(old, at)
+    k.write_text(src[:j] + "const int kmax = a.kmax[w + 3 * a.n_list];" + src[j + len(old):])
+    # (built where later runs find it: the build is cached by the sources' hash)
+    exe = build_emu.build(csrc=str(csrc), build_dir=os.path.join(build_emu.BUILD, "planted"))
+    wl = synth.PRESETS["batched"]
+    b = synth.generate(wl, n_wave=40, seed=11)
+    km_all = synth.kmax_for(b["lam"])
+    keep = np.where(km_all <= 32)[0]
+    wave, offsets, lam = _subset(b, keep)
+    run = tmp_path / "run"
+    run.mkdir()
+    r = _run_emu(str(run), wl, wave, offsets, lam, km_all[keep].astype(np.int32), 20, 10, 2, 4, LANE_AT_16_AND_32,
+                 exe=exe, expect_ok=False)
+    assert r.returncode != 0
+    assert "AddressSanitizer: heap-buffer-overflow" in r.stderr and "chain_lane_kernel" in r.stderr, r.stderr[:3000]
