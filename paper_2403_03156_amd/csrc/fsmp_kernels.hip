@@ -100,6 +100,13 @@ __device__ inline double dpp_move(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// v of lane L of the wavefront, in scalar registers
+__device__ inline double lane_value(double v, int L) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), L);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), L);
+  return __hiloint2double(hi, lo);
+}
+
 // The value of lane K of the caller's group of W lanes (groups aligned to W, every lane of
 // the group active): a DPP broadcast inside a quad (W = 4: quad_perm [K, K, K, K]) or a row
 // (W = 16: row_newbcast:K), else a lane permute from lane base + K
@@ -107,6 +114,7 @@ template <int W, int K>
 __device__ inline double group_bcast(double v, int base) {
   if constexpr (W == 4) return dpp_move<K * 0x55>(v);
   else if constexpr (W == 16) return dpp_move<0x150 + K>(v);
+  else if constexpr (W == kWave) return lane_value(v, K);
   else return __shfl(v, base + K, kWave);
 }
 template <int W, int K>
@@ -187,6 +195,15 @@ __device__ inline double phi_total_group(const ModelDev &md, double t0, int glo,
 // the same as with lane permutes for every offset.
 template <int W>
 __device__ inline double group_sum(double v) {
+  if constexpr (W == kWave) {
+    // a whole wavefront: the rows of 16 lanes by DPP, then their four sums from lanes 0, 16,
+    // 32 and 48 into scalar registers, added in that order
+    v += dpp_move<0x128>(v);  // row_ror:8
+    v += dpp_move<0x124>(v);  // row_ror:4
+    v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]: xor 2
+    v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]: xor 1
+    return ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
+  }
 #pragma unroll
   for (int o = W / 2; o >= 16; o >>= 1) v += __shfl_xor(v, o, W);
   if constexpr (W >= 16) {
@@ -608,7 +625,10 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
   for (int i = threadIdx.x; i < KCAP + 2; i += blockDim.x) lgn[i] = log((double)i);
   __syncthreads();
 
-  const int wv = threadIdx.x / kWave, l64 = threadIdx.x % kWave;
+  // the wavefront's index is the same in all its lanes: taken from the first, it and what
+  // follows from it (the tile, and with one chain per wavefront the chain and its waveform's
+  // parameters) are held in scalar registers, which keeps those kernels free of spills
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)), l64 = threadIdx.x % kWave;
   const int grp = l64 / LPC, lane = l64 % LPC;
   const int gbase = grp * LPC;  // the group's first lane in the wavefront
   const int64_t tile = (int64_t)blockIdx.x * WPB + wv;

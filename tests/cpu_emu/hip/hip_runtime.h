@@ -4,7 +4,7 @@
 // host memory, copies are synchronous, streams and events do nothing, and a kernel launch runs
 // its blocks one after the other with one OS thread per GPU thread.  Barriers: a std::barrier
 // per block for __syncthreads and one per wavefront of 64 threads for the wavefront barrier.
-// Cross-lane operations (shuffles, the DPP patterns the kernels use, ballot) go through a
+// Cross-lane operations (shuffles, the DPP patterns the kernels use, ballot, lane reads) go through a
 // per-wavefront exchange: each lane writes its value to its slot, the wavefront passes its
 // barrier, each lane reads the slot of its source lane, and the wavefront passes its barrier
 // again.  A lane's phases pair with those of the other lanes of its wavefront whatever code
@@ -123,6 +123,12 @@ inline int emu_update_dpp(int old, int src, int ctrl, int, int, bool) {
   return emu_from_bits<int>(emu_exchange(emu_bits(src), from));
 }
 #define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) emu_update_dpp((old), (src), (ctrl), (rm), (bm), (bc))
+// the value of the wavefront's first active lane (the kernels take it where every lane is active)
+inline int emu_readfirstlane(int v) { return emu_from_bits<int>(emu_exchange(emu_bits(v), 0)); }
+#define __builtin_amdgcn_readfirstlane(v) emu_readfirstlane((v))
+// the value of lane L of the wavefront
+inline int emu_readlane(int v, int L) { return emu_from_bits<int>(emu_exchange(emu_bits(v), L)); }
+#define __builtin_amdgcn_readlane(v, L) emu_readlane((v), (L))
 #define __builtin_amdgcn_fence(...) ((void)0)
 #define __builtin_amdgcn_wave_barrier() emu_wbar->arrive_and_wait()
 inline int __double2loint(double v) {
