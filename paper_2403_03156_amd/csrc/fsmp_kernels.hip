@@ -439,21 +439,24 @@ struct ChainLayout {
 
 // Column i of H owned by one lane: element (k, i) at H[(k * LD + i) * HS] (HS = 1 in LDS;
 // the number of chains of a wavefront in device memory, where the wavefront's chains are
-// interleaved element by element).  Loads go in chunks of 16 rows, issued unconditionally
-// (rows below the capacity, a multiple of 16) with the rows past N dropped by a select,
-// so a chunk costs one memory round trip; terms are summed in row order.
+// interleaved element by element).  Loads go in chunks of 16 rows with one chain per
+// wavefront and of 8 with several (whose kernels are short of registers: the smaller chunk
+// keeps their spills down), issued unconditionally (rows below the capacity, a multiple of
+// 16) with the rows past N dropped by a select, so a chunk costs one memory round trip;
+// terms are summed in row order.
 template <int LD, int HS, typename MT>
 __device__ inline double grp_col_dot(const MT *H, const double *g, int i, int N) {
+  constexpr int RC = HS > 1 ? 8 : 16;
   double e = 0.0;
-  for (int k0 = 0; k0 < N; k0 += 16) {
-    double h[16], v[16];
+  for (int k0 = 0; k0 < N; k0 += RC) {
+    double h[RC], v[RC];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < RC; ++u) {
       h[u] = (double)H[((k0 + u) * LD + i) * HS];
       v[u] = g[k0 + u];
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) e = (k0 + u < N) ? e + h[u] * v[u] : e;
+    for (int u = 0; u < RC; ++u) e = (k0 + u < N) ? e + h[u] * v[u] : e;
   }
   return e;
 }
