@@ -109,7 +109,8 @@ __device__ inline double lane_value(double v, int L) {
 
 // The value of lane K of the caller's group of W lanes (groups aligned to W, every lane of
 // the group active): a DPP broadcast inside a quad (W = 4: quad_perm [K, K, K, K]) or a row
-// (W = 16: row_newbcast:K), else a lane permute from lane base + K
+// (W = 16: row_newbcast:K), a lane read into scalar registers for a whole wavefront, else a
+// lane permute from lane base + K
 template <int W, int K>
 __device__ inline double group_bcast(double v, int base) {
   if constexpr (W == 4) return dpp_move<K * 0x55>(v);
@@ -121,6 +122,7 @@ template <int W, int K>
 __device__ inline uint32_t group_bcast(uint32_t v, int base) {
   if constexpr (W == 4) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, K * 0x55, 0xF, 0xF, false);
   else if constexpr (W == 16) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + K, 0xF, 0xF, false);
+  else if constexpr (W == kWave) return (uint32_t)__builtin_amdgcn_readlane((int)v, K);
   else return (uint32_t)__shfl((int)v, base + K, kWave);
 }
 
