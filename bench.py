@@ -127,7 +127,14 @@ def kernel_label(name):
 
 
 def source_hash():
-    return hashlib.sha256(open(KSRC, "rb").read()).hexdigest()
+    """SHA-256 of the kernel source with its comments and blank space removed: what the
+    compiled kernels depend on, so that a comment edit keeps recorded counters valid"""
+    import re
+    text = open(KSRC).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    text = " ".join(text.split())
+    return hashlib.sha256(text.encode()).hexdigest()
 
 
 def pmc_summary(fdir, wdir, workload):

@@ -194,7 +194,9 @@ __device__ inline double phi_total_group(const ModelDev &md, double t0, int glo,
 // rest are DPP moves inside a row of 16: xor 8 is a rotation of the row by 8, xor 4 after it
 // a rotation by 4 (the values then depend only on the lane index mod 8, where a rotation by
 // 4 and xor 4 agree), xor 2 and xor 1 quad permutations.  The pairs, and so the sums, are
-// the same as with lane permutes for every offset.
+// the same as with lane permutes for every offset.  A whole wavefront (W = 64) sums its four
+// rows of 16 so and adds the row sums, read from lanes 0, 16, 32 and 48 into scalar
+// registers, in that order (no lane permutes, and the result is a scalar).
 template <int W>
 __device__ inline double group_sum(double v) {
   if constexpr (W == kWave) {
