@@ -129,10 +129,10 @@ def tie_at(p, lam, glo, ghi, uid, seed, ga, ob, s, t0_init, z_init=()):
 
 
 def assert_partings_explained(parted, p, b, lam, n_chains, seed, gpu_logs, ora_logs, kmax, g_range=None,
-                              t0_init=None, wave_id=None, tie=TIE):
+                              t0_init=None, wave_id=None, tie=TIE, z_init=None):
     """every chain in `parted` (chain index wave * n_chains + chain) must part at a near-tie;
     gpu_logs / ora_logs: a function of the list of parted chains giving their logs (rows in the
-    order of the list)"""
+    order of the list); z_init: the chains' start lists, or None"""
     parted = [int(c) for c in parted]
     if not parted:
         return
@@ -147,7 +147,8 @@ def assert_partings_explained(parted, p, b, lam, n_chains, seed, gpu_logs, ora_l
         uid = wid * n_chains + c % n_chains
         s = first_difference(gl[row], ol[row])
         assert s is not None, f"chain {c}: results differ but the proposal logs agree"
-        kind, margin = tie_at(p, float(lam[i]), glo, ghi, uid, seed, gl[row], ol[row], s, t0i)
+        kind, margin = tie_at(p, float(lam[i]), glo, ghi, uid, seed, gl[row], ol[row], s, t0i,
+                              z_init=() if z_init is None else tuple(z_init[c]))
         print(f"[parting] chain {c} (waveform {i}) parts at step {s}: {kind}, margin {margin:.2e}", flush=True)
         assert margin < tie, f"chain {c}: parts at step {s} ({kind}) with margin {margin:.2e}, not a near-tie"
 
@@ -155,28 +156,29 @@ def assert_partings_explained(parted, p, b, lam, n_chains, seed, gpu_logs, ora_l
 def gpu_log_runner(make_sampler, kz):
     """rerun function for rerun_logs: make_sampler(record_flags) builds the sampler of the test
     with the proposal log switched on"""
-    def run(wave, off, lam, km, gr, ti, wid):
+    def run(wave, off, lam, km, gr, ti, wid, z0=None):
         import torch
         from paper_2403_03156_amd import fsmp
         smp = make_sampler(fsmp.FSMP_REC_LOG)
         out = smp.sample(torch.from_numpy(np.ascontiguousarray(wave)).cuda(), off, lam, kmax=km, kz=kz, g_range=gr,
-                         t0_init=ti, wave_id=wid)
+                         t0_init=ti, wave_id=wid, z_init=z0)
         torch.cuda.synchronize()
         return fsmp.log_records(out["log"])
     return run
 
 
 def oracle_log_runner(p, n_chains, n_steps, burn, seed, kz):
-    def run(wave, off, lam, km, gr, ti, wid):
+    def run(wave, off, lam, km, gr, ti, wid, z0=None):
         return oracle.run(p, wave, off, lam, n_chains, n_steps, burn, seed, kz, kmax=km, g_range=gr, t0_init=ti,
-                          wave_id=wid, log=True).log
+                          wave_id=wid, log=True, z_init=z0).log
     return run
 
 
 def check_partings(parted, p, b, lam, kmax, n_chains, n_steps, burn, seed, kz, make_sampler, g_range=None,
-                   t0_init=None, wave_id=None):
+                   t0_init=None, wave_id=None, z_init=None):
     """every parted chain of a run must part at a near-tie (see tie_at); the parted chains'
-    waveforms are rerun on both sides with proposal logs"""
+    waveforms are rerun on both sides with proposal logs (z_init: the chains' start lists,
+    one per chain, or None)"""
     if len(parted) == 0:
         return
     ids = np.arange(len(lam), dtype=np.uint64) if wave_id is None else np.asarray(wave_id, np.uint64)
@@ -189,7 +191,8 @@ def check_partings(parted, p, b, lam, kmax, n_chains, n_steps, burn, seed, kz, m
         gr = None if g_range is None else np.asarray(g_range)[sel]
         ti = None if t0_init is None else np.asarray(t0_init)[sel]
         rows = [waves.index(int(c) // n_chains) * n_chains + int(c) % n_chains for c in chains]
-        return (wave, off, np.asarray(lam)[sel], np.asarray(kmax)[sel], gr, ti, ids[sel]), rows
+        z0 = None if z_init is None else [list(z_init[i * n_chains + ch]) for i in waves for ch in range(n_chains)]
+        return (wave, off, np.asarray(lam)[sel], np.asarray(kmax)[sel], gr, ti, ids[sel], z0), rows
 
     run_g = gpu_log_runner(make_sampler, kz)
     run_o = oracle_log_runner(p, n_chains, n_steps, burn, seed, kz)
@@ -202,4 +205,4 @@ def check_partings(parted, p, b, lam, kmax, n_chains, n_steps, burn, seed, kz, m
         args, rows = sub_batch(chains)
         return run_o(*args)[rows]
     assert_partings_explained(parted, p, b, lam, n_chains, seed, gl, ol, kmax, g_range=g_range, t0_init=t0_init,
-                              wave_id=ids)
+                              wave_id=ids, z_init=z_init)

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from paper_2403_03156_amd import fsmp, synth
-from tests.fsmp_cases import compare_chains, gpu_sampler, oracle_params, to_host
+from tests.fsmp_cases import check_partings, compare_chains, gpu_sampler, oracle_params, to_host
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -38,7 +38,7 @@ def _starts(wl, b, km, n_chains, seed, max_len=None):
 
 
 @pytest.mark.parametrize("design", [None, fsmp.FSMP_DESIGN_GROUP, fsmp.FSMP_DESIGN_LANE,
-                                    fsmp.FSMP_DESIGN_GROUP_DEVMEM])
+                                    fsmp.FSMP_DESIGN_GROUP_DEVMEM, fsmp.FSMP_DESIGN_GROUP_DEVMEM_WIDE])
 def test_started_chains_match_oracle(design):
     wl = synth.PRESETS["batched"]
     n, C, n_steps, burn = 60, 2, 300, 150
@@ -54,7 +54,13 @@ def test_started_chains_match_oracle(design):
     o = oracle.run(oracle_params(wl), b["wave"], b["offsets"], b["lam"], C, n_steps, burn, 23, kz, kmax=km, z_init=z0)
     parted = compare_chains(g, o)
     print(f"[init] {len(parted)} of {n * C} chains parted", flush=True)
-    assert len(parted) <= 0.1 * n * C, parted
+
+    def make(flags):
+        m = gpu_sampler(wl, n_steps, burn, C, 23, record_flags=flags)
+        if design is not None:
+            m.set_design(0, design)
+        return m
+    check_partings(parted, oracle_params(wl), b, b["lam"], km, C, n_steps, burn, 23, kz, make, z_init=z0)
 
 
 def test_long_start_lists_high_capacity():
@@ -73,7 +79,8 @@ def test_long_start_lists_high_capacity():
     o = oracle.run(oracle_params(wl), b["wave"], b["offsets"], b["lam"], 1, 150, 75, 8, int(km.max()), kmax=km,
                    z_init=z0)
     parted = compare_chains(g, o, tol=1e-7)
-    assert len(parted) <= 1, parted
+    check_partings(parted, oracle_params(wl), b, b["lam"], km, 1, 150, 75, 8, int(km.max()),
+                   lambda flags: gpu_sampler(wl, 150, 75, 1, 8, record_flags=flags), z_init=z0)
 
 
 @pytest.mark.parametrize("preset", ["batched", "pileup"])

@@ -16,7 +16,7 @@ import pytest
 import oracle
 from oracle import lucy
 from paper_2403_03156_amd import synth
-from tests.fsmp_cases import compare_chains, gpu_sampler, oracle_params, to_host
+from tests.fsmp_cases import check_partings, compare_chains, gpu_sampler, oracle_params, to_host
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -156,4 +156,8 @@ def test_sampling_from_the_deconvolution():
                    z_init=zo)
     parted = compare_chains(g, o)
     print(f"[lucy] sampling from the deconvolution: {len(parted)} of {n * C} chains parted", flush=True)
-    assert len(parted) <= 0.1 * n * C
+    gr = np.array([r["g_range"] for r in ref], np.int32)
+    ti = np.array([r["t0"] for r in ref])
+    check_partings(parted, oracle_params(wl), b, b["lam"], km, C, n_steps, burn, 29, kz,
+                   lambda flags: gpu_sampler(wl, n_steps, burn, C, 29, record_flags=flags), g_range=gr, t0_init=ti,
+                   z_init=zo)
