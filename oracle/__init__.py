@@ -118,7 +118,8 @@ def lib():
         L.ora_charge_normals.argtypes = [_u64, _u64, _i32, _i32, _vp]
         L.ora_charge_normals.restype = None
         L.ora_run.restype = ctypes.c_int
-        L.ora_replay.argtypes = [_P(Params), _vp, _i32, _d, _i32, _i32, _i32, _u64, _u64, _i32, _vp, _vp, _vp, _d, _i32]
+        L.ora_replay.argtypes = [_P(Params), _vp, _i32, _d, _i32, _i32, _i32, _u64, _u64, _i32, _vp, _vp, _vp, _d, _i32,
+                                 _vp, _i32]
         L.ora_replay.restype = _i64
         _lib = L
     return _lib
@@ -265,9 +266,10 @@ def charge_normals(uid, seed, step, K):
     return xi[:K]
 
 
-def replay(p: Params, w, lam, kmax, glo, ghi, uid, seed, rec, tie_eps=1e-9, ext=False):
+def replay(p: Params, w, lam, kmax, glo, ghi, uid, seed, rec, tie_eps=1e-9, ext=False, z_init=None):
     """Recompute delta-nu / log-alpha along a recorded log of one chain.  ext: delta-nu as the
     difference of two from-scratch nu's in extended precision (long double), else in FP64.
+    z_init: None (empty start) or the chain's initial PE list (grid indices), as `run` takes it.
 
     Returns (dnu_ref, la_ref, n_decision_mismatches)."""
     w = np.ascontiguousarray(w, dtype=np.float32)
@@ -275,8 +277,9 @@ def replay(p: Params, w, lam, kmax, glo, ghi, uid, seed, rec, tie_eps=1e-9, ext=
     n = len(rec)
     dnu = np.zeros(n, np.float64)
     la = np.zeros(n, np.float64)
+    z0 = np.ascontiguousarray(z_init if z_init is not None else [], dtype=np.int32)
     bad = lib().ora_replay(ctypes.byref(p), _ptr(w), len(w), lam, kmax, glo, ghi, uid, seed, n, _ptr(rec),
-                           _ptr(dnu), _ptr(la), tie_eps, 1 if ext else 0)
+                           _ptr(dnu), _ptr(la), tie_eps, 1 if ext else 0, _ptr(z0) if len(z0) else None, len(z0))
     return dnu, la, int(bad)
 
 

@@ -952,11 +952,13 @@ int ora_run(const ora_params *p, int64_t n_wave, const float *wave, const int64_
  * index, the new grid point, the t0 after the MH half-step and the recorded
  * accept decision), recompute delta-nu and log alpha from scratch for every
  * valid proposal, and re-derive the accept decision from this oracle's own
- * Philox stream.  Returns the number of steps whose decision differs
- * although |log U - log alpha| > tie_eps. */
+ * Philox stream.  z0[0 .. n0) is the chain's initial PE list (n0 = 0: empty
+ * start).  Returns the number of steps whose decision differs although
+ * |log U - log alpha| > tie_eps, or -1 when n0 exceeds kmax. */
 int64_t ora_replay(const ora_params *p, const float *w, int32_t Lw, double lambda0, int32_t kmax, int32_t glo,
                    int32_t ghi, uint64_t uid, uint64_t seed, int32_t n_steps, const ora_logrec *rec, double *dnu_ref,
-                   double *la_ref, double tie_eps, int32_t ext) {
+                   double *la_ref, double tie_eps, int32_t ext, const int32_t *z0, int32_t n0) {
+  if (n0 < 0 || n0 > kmax) return -1;
   ora_table t;
   table_init(&t, p);
   ora_ctx c;
@@ -969,6 +971,13 @@ int64_t ora_replay(const ora_params *p, const float *w, int32_t Lw, double lambd
   long double nu_cur_ext = 0.0L, nu_new_ext = 0.0L;
   int64_t bad = 0;
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  /* a chain started from a given PE sequence (as ora_run starts it): its nu from scratch */
+  if (n0 > 0) {
+    memcpy(z, z0, sizeof(int32_t) * n0);
+    N = n0;
+    if (nu_of(&c, z, NULL, N, &nu_cur, NULL)) bad++;
+    if (ext && nu_of_ext(&c, z, N, &nu_cur_ext)) bad++;
+  }
   for (int32_t step = 0; step < n_steps; ++step) {
     const ora_logrec *lr = &rec[step];
     double t0 = lr->t0;

@@ -1,5 +1,7 @@
 """Shared set-up for the parity tests: one workload description drives both the HIP
 path (through the C ABI binding) and the oracle, with identical seeded inputs."""
+import concurrent.futures
+
 import numpy as np
 
 import oracle
@@ -206,3 +208,17 @@ def check_partings(parted, p, b, lam, kmax, n_chains, n_steps, burn, seed, kz, m
         return run_o(*args)[rows]
     assert_partings_explained(parted, p, b, lam, n_chains, seed, gl, ol, kmax, g_range=g_range, t0_init=t0_init,
                               wave_id=ids, z_init=z_init)
+
+
+def ext_reference(p, b, km, log, n_chains, seed, z_init=None):
+    """delta-nu and log-alpha along the log from the oracle's extended-precision replay (the
+    chains replayed side by side on the host cores; z_init: the chains' start lists or None)"""
+    def one(c):
+        i = c // n_chains
+        w = b["wave"][b["offsets"][i]:b["offsets"][i + 1]]
+        return oracle.replay(p, w, b["lam"][i], int(km[i]), 0, 4 * len(w) - 1, c, seed, log[c], ext=True,
+                             z_init=None if z_init is None else z_init[c])
+    with concurrent.futures.ThreadPoolExecutor(max_workers=8) as ex:
+        res = list(ex.map(one, range(log.shape[0])))
+    assert all(r[2] == 0 for r in res)
+    return np.stack([r[0] for r in res]), np.stack([r[1] for r in res])

@@ -15,33 +15,17 @@ replay (4,000 sweeps at K around 100) holds the FP64 form to the bound over its 
 length: there the charge means' residual against the exact G corrects what the explicitly
 inverted G^-1 leaves (about 1e-8 of delta-nu without it, with or without rebuilds).
 """
-import concurrent.futures
-
 import numpy as np
 import pytest
 
 import oracle
 from paper_2403_03156_amd import fsmp, synth
-from tests.fsmp_cases import gpu_sampler, oracle_params
+from tests.fsmp_cases import ext_reference, gpu_sampler, oracle_params
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-9
-
-
-def _ext_reference(p, b, km, log, n_chains, seed):
-    """delta-nu and log-alpha along the log from the oracle's extended-precision replay (the
-    chains replayed side by side on the host cores)"""
-    def one(c):
-        i = c // n_chains
-        w = b["wave"][b["offsets"][i]:b["offsets"][i + 1]]
-        d, la, bad = oracle.replay(p, w, b["lam"][i], int(km[i]), 0, 4 * len(w) - 1, c, seed, log[c], ext=True)
-        return d, la, bad
-    with concurrent.futures.ThreadPoolExecutor(max_workers=8) as ex:
-        res = list(ex.map(one, range(log.shape[0])))
-    assert all(r[2] == 0 for r in res)
-    return np.stack([r[0] for r in res]), np.stack([r[1] for r in res])
 
 
 def _replay_oracle_log(wl, b, km, n_steps, n_chains, seed, extended=False, wide=False):
@@ -62,7 +46,7 @@ def _replay_oracle_log(wl, b, km, n_steps, n_chains, seed, extended=False, wide=
     dnu, la = dnu.cpu().numpy(), la.cpu().numpy()
     valid = (o.log["flags"] & 1) != 0
     if extended:
-        ref_d, ref_a = _ext_reference(p, b, km, o.log, n_chains, seed)
+        ref_d, ref_a = ext_reference(p, b, km, o.log, n_chains, seed)
         e64 = np.abs(o.log["dnu"][valid] - ref_d[valid]) / np.maximum(np.abs(ref_d[valid]), 1.0)
         print(f"[replay] the oracle's own FP64 delta-nu against the extended one: max rel err {e64.max():.2e}",
               flush=True)

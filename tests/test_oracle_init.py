@@ -81,3 +81,42 @@ def test_start_is_the_state():
         np.testing.assert_allclose(r.x[0][:len(z)], x, rtol=1e-9, atol=1e-12)
         checked += 1
     assert checked >= 10
+
+
+def test_replay_from_start_list():
+    # the replay started from a chain's start list follows that chain's own run: its FP64
+    # delta-nu equals the logged one and every accept decision is re-derived; from the empty
+    # list the same log is not the chain's (the deaths name PEs the empty start lacks)
+    from paper_2403_03156_amd import synth
+    p = oracle.make_params()
+    b = synth.generate(synth.PRESETS["plain"], n_wave=3, seed=5)
+    off = b["offsets"]
+    kz, C, seed = 16, 2, 12
+    rng = np.random.default_rng(4)
+    starts = []
+    for i in range(3):
+        L = int(off[i + 1] - off[i])
+        for _ in range(C):
+            starts.append(sorted(rng.integers(40, p.sub * L - 1, size=int(rng.integers(2, 6))).tolist()))
+    r = oracle.run(p, b["wave"], off, b["lam"], C, 300, 150, seed, kz, z_init=starts, log=True)
+    differs = 0
+    for i in range(3):
+        w = b["wave"][off[i]:off[i + 1]]
+        for ch in range(C):
+            row = i * C + ch
+            rec = r.log[row]
+            valid = (rec["flags"] & 1) != 0
+            assert valid.sum() > 100
+            args = (p, w, b["lam"][i], kz, 0, 4 * len(w) - 1, row, seed, rec)
+            dnu, la, bad = oracle.replay(*args, z_init=starts[row])
+            assert bad == 0
+            np.testing.assert_array_equal(dnu[valid], rec["dnu"][valid])
+            dx, _, badx = oracle.replay(*args, z_init=starts[row], ext=True)
+            assert badx == 0
+            np.testing.assert_allclose(dx[valid], rec["dnu"][valid], rtol=1e-9, atol=1e-9)
+            d0, _, bad0 = oracle.replay(*args)
+            differs += bad0 > 0 or not np.array_equal(d0[valid], rec["dnu"][valid])
+    assert differs == 3 * C
+    # more PEs than kmax is refused
+    w = b["wave"][off[0]:off[1]]
+    assert oracle.replay(p, w, b["lam"][0], 3, 0, 4 * len(w) - 1, 0, seed, r.log[0], z_init=starts[0] + [50] * 4)[2] == -1
