@@ -81,8 +81,10 @@ def parse():
     ap.add_argument("--cpu-wave", type=int, default=6000, help="waveforms in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve", action="store_true", help="only the serving study (rates x precisions)")
-    ap.add_argument("--serve-events", type=int, default=48, help="events per serving run")
-    ap.add_argument("--serve-rates", default="50,100,150,200,300,2000,5000,10000,20000",
+    ap.add_argument("--serve-events", type=int, default=160,
+                    help="events per serving run (enough that one event's drain after the last arrival is a "
+                         "few percent of the arrival window at the sustainable rates)")
+    ap.add_argument("--serve-rates", default="50,100,150,200,250,300,350,400,2000,5000,10000,20000",
                     help="comma-separated event rates (Hz)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--legs", default="fp32,batched,lucy,mcp",
@@ -300,10 +302,13 @@ def step_traffic(workload, kernels, ms_per_step):
 def serving_run(fsmp, synth, pool, rate, n_events, precision, seed=0, n_streams=4, max_batch_wave=20000):
     """Poisson arrivals of trigger events (500-2000 channels drawn from a pool of synthetic
     channels, 1,024 samples each) submitted to the serving loop as they arrive; latency
-    percentiles, throughput, and whether the rate is sustained (served at the offered rate
-    without a growing queue: the last third of the events waits at most 1.5x as long as
-    the first third)."""
+    percentiles, throughput, and whether the rate is sustained: the run ends within 5% of the
+    last arrival plus the median latency (a server that keeps pace drains one event after the
+    last arrival), and the queue does not grow (the last third of the events waits at most
+    1.5x as long as the first third).  The arrival window is about 1.5 s (n_events to
+    3 n_events events), so an overload of a few percent shows as a growing latency."""
     wl = synth.PRESETS["serving"]
+    n_events = int(np.clip(round(rate * 1.5), n_events, 3 * n_events))
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, n_events)
     arrive = np.cumsum(gaps) - gaps[0]
@@ -346,9 +351,10 @@ def serving_run(fsmp, synth, pool, rate, n_events, precision, seed=0, n_streams=
     third = max(1, n_events // 3)
     served = waves / t_end
     offered = waves / max(arrive[-1], 1e-9)
-    sustained = bool(served >= 0.95 * offered and l[-third:].mean() <= 1.5 * l[:third].mean())
+    sustained = bool(t_end <= 1.05 * (arrive[-1] + np.percentile(l, 50)) and l[-third:].mean() <= 1.5 * l[:third].mean())
     return {"rate_hz": rate, "events": n_events, "waveforms": waves, "precision": "fp32+refresh" if precision else "fp64",
             "p50_ms": float(np.percentile(l, 50) * 1e3), "p99_ms": float(np.percentile(l, 99) * 1e3),
+            "arrival_window_ms": float(arrive[-1] * 1e3), "drain_ms": float((t_end - arrive[-1]) * 1e3),
             "mean_ms_first_third": float(l[:third].mean() * 1e3), "mean_ms_last_third": float(l[-third:].mean() * 1e3),
             "waveforms_per_s": served, "offered_waveforms_per_s": offered, "sustained": sustained}
 

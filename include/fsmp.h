@@ -433,12 +433,13 @@ fsmp_status fsmp_set_timing(fsmp_ctx *ctx, int32_t enable);
  * group of lanes with G^{-1} in device memory, interleaved across the chains of a
  * wavefront, and only the vectors in LDS (every capacity, while the SER tables leave room
  * in LDS); FSMP_DESIGN_GROUP_DEVMEM_WIDE the same with 2-4x the lanes per chain (a whole
- * wavefront from capacity 64 up; capacities 32-192, FP64 with the single charge law), for
- * batches whose longest chains set the launch's duration.  Capacities are 16, 32, 48, 64,
- * 96, 128, 160, 192; a waveform runs in the smallest one >= its kmax.  capacity 0 = every
- * capacity that has the design.  FSMP_ENOTSUP if the requested pair does not exist.  The
- * FP32-refresh form and the mixture charge law run FSMP_DESIGN_GROUP_DEVMEM only (the FP32
- * form runs capacity 48 at 64); replays run FSMP_DESIGN_GROUP_DEVMEM, or
+ * wavefront from capacity 64 up; capacities 32-192 in FP64 with the single charge law, 16
+ * and 32 in the FP32-refresh form, 16 lanes per chain), for batches whose longest chains
+ * set the launch's duration.  Capacities are 16, 32, 48, 64, 96, 128, 160, 192; a waveform
+ * runs in the smallest one >= its kmax.  capacity 0 = every capacity that has the design.
+ * FSMP_ENOTSUP if the requested pair does not exist.  The FP32-refresh form runs
+ * FSMP_DESIGN_GROUP_DEVMEM and its wide groups (capacity 48 at 64); the mixture charge law
+ * FSMP_DESIGN_GROUP_DEVMEM only; replays run FSMP_DESIGN_GROUP_DEVMEM, or
  * FSMP_DESIGN_GROUP_DEVMEM_WIDE where the context has it at capacity 64 and up. */
 enum { FSMP_DESIGN_GROUP = 0, FSMP_DESIGN_LANE = 1, FSMP_DESIGN_GROUP_DEVMEM = 2, FSMP_DESIGN_GROUP_DEVMEM_WIDE = 3 };
 fsmp_status fsmp_set_design(fsmp_ctx *ctx, int32_t capacity, int32_t design);

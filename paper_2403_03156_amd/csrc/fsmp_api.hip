@@ -262,7 +262,7 @@ bool design_available(const fsmp_ctx *c, int kcap, int design) {
     case FSMP_DESIGN_LANE: return !fp32 && !mcp && (kcap == 16 || kcap == 32);
     case FSMP_DESIGN_GROUP_DEVMEM: return chain_dm_supported(kcap, c->tab.M, c->cfg.grid_sub, fp32, mcp);
     case FSMP_DESIGN_GROUP_DEVMEM_WIDE:
-      return !fp32 && !mcp && chain_dm_supported(kcap, c->tab.M, c->cfg.grid_sub, false, false, true);
+      return !mcp && chain_dm_supported(kcap, c->tab.M, c->cfg.grid_sub, fp32, false, true);
     default: return false;
   }
 }

@@ -2678,6 +2678,10 @@ static const GroupCfg kGroupDMWide[] = {{32, 16, 4}, {48, 32, 4},  {64, 64, 4}, 
 // capacities of 4-lane groups (at four, capacity 32 would need 168 KB)
 static const GroupCfg kGroupDMF32[] = {{16, 4, 2},  {32, 4, 2},   {64, 32, 4},  {96, 64, 4},
                                        {128, 64, 4}, {160, 64, 4}, {192, 64, 2}};
+// its wide groups: 16 lanes per chain at the two smallest capacities (a quarter of the sweep
+// latency of the 4-lane groups, which matters where one event's chains finish together);
+// from capacity 64 up its groups are already 32-64 lanes wide
+static const GroupCfg kGroupDMF32Wide[] = {{16, 16, 4}, {32, 16, 4}};
 
 // the vectors of a chain's LDS block (ChainLayout::kVec); the corrected FP64 form (and with it
 // group_dm_ws_doubles' exact G) from capacity 48 up
@@ -2704,8 +2708,13 @@ bool chain_kcap_supported(int kcap, int M, int sub) {
 
 bool chain_dm_supported(int kcap, int M, int sub, bool f32, bool mcp, bool wide) {
   if (f32 && mcp) return false;
+  if (wide && f32) {
+    for (const GroupCfg &g : kGroupDMF32Wide)
+      if (g.kcap == kcap) return chain_lds_bytes(g, M, sub, true, true, false) <= 160 * 1024;
+    return false;
+  }
   if (wide) {
-    if (f32 || mcp) return false;
+    if (mcp) return false;
     for (const GroupCfg &g : kGroupDMWide)
       if (g.kcap == kcap) return chain_lds_bytes(g, M, sub, true, false, false) <= 160 * 1024;
     return false;
@@ -2724,8 +2733,9 @@ bool chain_dm_supported(int kcap, int M, int sub, bool f32, bool mcp, bool wide)
 // H (FP64, with the exact G from capacity 48 up; or FP32 plus the FP64 refresh matrix and the
 // exact G) of every chain, in tiles of a wavefront
 size_t group_dm_ws_doubles(int kcap, int64_t n_list, bool f32, bool wide) {
-  const GroupCfg *t = f32 ? kGroupDMF32 : wide ? kGroupDMWide : kGroupDM;
-  const int nt = f32    ? (int)(sizeof kGroupDMF32 / sizeof *kGroupDMF32)
+  const GroupCfg *t = f32 ? (wide ? kGroupDMF32Wide : kGroupDMF32) : wide ? kGroupDMWide : kGroupDM;
+  const int nt = f32    ? (wide ? (int)(sizeof kGroupDMF32Wide / sizeof *kGroupDMF32Wide)
+                                : (int)(sizeof kGroupDMF32 / sizeof *kGroupDMF32))
                  : wide ? (int)(sizeof kGroupDMWide / sizeof *kGroupDMWide)
                         : (int)(sizeof kGroupDM / sizeof *kGroupDM);
   for (int q = 0; q < nt; ++q)
@@ -2766,11 +2776,20 @@ hipError_t launch_chain(int kcap, const ChainArgs &a, hipStream_t st, int32_t *l
   }
 }
 
-// instances must match kGroupDM (kGroupDMWide for `wide`, plain FP64 sampling only)
+// instances must match kGroupDM (kGroupDMWide for `wide`, kGroupDMF32 and kGroupDMF32Wide for
+// the FP32 form; no wide groups for the mixture law)
 hipError_t launch_chain_dm(int kcap, bool fp32, bool wide, const ChainArgs &a, hipStream_t st, int32_t *lanes,
                            int64_t *blocks) {
+  if (wide && fp32) {
+    if (a.md.n_mix > 0 || a.force) return hipErrorInvalidValue;
+    switch (kcap) {
+      case 16: return launch_chain_t<16, 16, 4, true, false, true>(a, st, lanes, blocks);
+      case 32: return launch_chain_t<32, 16, 4, true, false, true>(a, st, lanes, blocks);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (wide) {
-    if (a.md.n_mix > 0 || fp32) return hipErrorInvalidValue;
+    if (a.md.n_mix > 0) return hipErrorInvalidValue;
     if (a.force) {
       // replay with the wide groups, capacities from 64 up
       switch (kcap) {

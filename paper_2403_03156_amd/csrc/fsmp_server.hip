@@ -298,8 +298,15 @@ fsmp_status fsmp_server_create(fsmp_server **out, const fsmp_ser *ser, const fsm
     }
     // latency: the lane-group kernels finish a sweep in microseconds; one lane per chain
     // with its state in device memory needs many memory round trips per sweep.  The FP32
-    // form has lane groups with G^-1 in device memory only.
-    (void)fsmp_set_design(sl->ctx, 0, cfg->precision == FSMP_FP32_REFRESH ? FSMP_DESIGN_GROUP_DEVMEM : FSMP_DESIGN_GROUP);
+    // form has lane groups with G^-1 in device memory only: its wide groups (16 lanes per
+    // chain at capacities 16 and 32, the narrow ones above, which are 32-64 lanes wide
+    // from capacity 64 up).
+    if (cfg->precision == FSMP_FP32_REFRESH) {
+      (void)fsmp_set_design(sl->ctx, 0, FSMP_DESIGN_GROUP_DEVMEM);
+      (void)fsmp_set_design(sl->ctx, 0, FSMP_DESIGN_GROUP_DEVMEM_WIDE);
+    } else {
+      (void)fsmp_set_design(sl->ctx, 0, FSMP_DESIGN_GROUP);
+    }
     (void)hipSetDevice(device);
     if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl->done, hipEventDisableTiming) != hipSuccess) {

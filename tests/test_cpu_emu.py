@@ -179,10 +179,11 @@ def test_device_memory_groups_on_the_cpu_under_asan(tmp_path, design):
 MIX = ([0.041, 0.516, 0.187, 0.195, 0.061], [0.92, 1.98, 3.01, 4.70, 6.79], [0.22, 0.48, 0.80, 1.30, 2.04])
 
 
-@pytest.mark.parametrize("form", ["fp32_refresh", "mixture", "noalloc"])
+@pytest.mark.parametrize("form", ["fp32_refresh", "fp32_refresh_wide", "mixture", "noalloc"])
 def test_other_forms_on_the_cpu_under_asan(tmp_path, form):
-    # the FP32-refresh form, the mixture charge law and the allocation-free entry point (its
-    # static scratch array and host tables), on the device-memory groups at capacities 16-64
+    # the FP32-refresh form (narrow groups, or its wide groups at capacities 16 and 32), the
+    # mixture charge law and the allocation-free entry point (its static scratch array and
+    # host tables), on the device-memory groups at capacities 16-64
     wl = synth.PRESETS["batched"]
     b = synth.generate(wl, n_wave=12, seed=12)
     km = synth.kmax_for(b["lam"]).astype(np.int32)
@@ -190,7 +191,7 @@ def test_other_forms_on_the_cpu_under_asan(tmp_path, form):
     n_steps, burn, n_chains, seed = 80, 40, 2, 6
     p = oracle_params(wl)
     kw = {}
-    if form == "fp32_refresh":
+    if form.startswith("fp32_refresh"):
         kw["precision"] = fsmp.FSMP_FP32_REFRESH
     elif form == "mixture":
         kw["mix"] = MIX
@@ -201,12 +202,14 @@ def test_other_forms_on_the_cpu_under_asan(tmp_path, form):
         kw["noalloc"] = True
     # (the FP32 form has no capacity-48 instance: its waveforms run at 64)
     design = [fsmp.FSMP_DESIGN_GROUP_DEVMEM] * 8
-    if form == "fp32_refresh":
+    if form.startswith("fp32_refresh"):
         design[2] = -1
+    if form == "fp32_refresh_wide":
+        design[0] = design[1] = fsmp.FSMP_DESIGN_GROUP_DEVMEM_WIDE
     g = _run_emu(str(tmp_path), wl, b["wave"], b["offsets"], b["lam"], km, n_steps, burn, n_chains, seed, design,
                  **kw)
     o = oracle.run(p, b["wave"], b["offsets"], b["lam"], n_chains, n_steps, burn, seed, int(km.max()), kmax=km)
-    parted = compare_chains(g, o, tol=1e-7 if form == "fp32_refresh" else 1e-9)
+    parted = compare_chains(g, o, tol=1e-7 if form.startswith("fp32_refresh") else 1e-9)
     assert len(parted) == 0, parted
     if form == "mixture":
         np.testing.assert_array_equal(g["comp"], o.e)
