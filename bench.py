@@ -305,8 +305,9 @@ def serving_run(fsmp, synth, pool, rate, n_events, precision, seed=0, n_streams=
     percentiles, throughput, and whether the rate is sustained: the run ends within 5% of the
     last arrival plus the median latency (a server that keeps pace drains one event after the
     last arrival), and the queue does not grow (the last third of the events waits at most
-    1.5x as long as the first third).  The arrival window is about 1.5 s (n_events to
-    3 n_events events), so an overload of a few percent shows as a growing latency."""
+    1.25x as long as the first third, plus 20 ms for the jitter of short waits).  The arrival
+    window is about 1.5 s (n_events to 3 n_events events), so an overload of a few percent
+    shows as a growing latency."""
     wl = synth.PRESETS["serving"]
     n_events = int(np.clip(round(rate * 1.5), n_events, 3 * n_events))
     rng = np.random.default_rng(seed)
@@ -351,7 +352,8 @@ def serving_run(fsmp, synth, pool, rate, n_events, precision, seed=0, n_streams=
     third = max(1, n_events // 3)
     served = waves / t_end
     offered = waves / max(arrive[-1], 1e-9)
-    sustained = bool(t_end <= 1.05 * (arrive[-1] + np.percentile(l, 50)) and l[-third:].mean() <= 1.5 * l[:third].mean())
+    sustained = bool(t_end <= 1.05 * (arrive[-1] + np.percentile(l, 50))
+                     and l[-third:].mean() <= 1.25 * l[:third].mean() + 0.020)
     return {"rate_hz": rate, "events": n_events, "waveforms": waves, "precision": "fp32+refresh" if precision else "fp64",
             "p50_ms": float(np.percentile(l, 50) * 1e3), "p99_ms": float(np.percentile(l, 99) * 1e3),
             "arrival_window_ms": float(arrive[-1] * 1e3), "drain_ms": float((t_end - arrive[-1]) * 1e3),
