@@ -758,6 +758,10 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
       WAVE_SYNC();
     }
   }
+  // with one chain per wavefront, lane l keeps the random values of sweep 64 m + l
+  constexpr bool kStash = LPC == kWave;
+  uint32_t st_r3 = 0, st_r4 = 0, st_r5 = 0, st_r7 = 0;
+  double st_l2 = 0.0, st_l6 = 0.0, st_xt = 0.0, st_xs = 0.0;
   for (int step = 0; step < n_steps; ++step) {
     if (a.refresh_M > 0 && step > 0 && step % a.refresh_M == 0 && N > 0) {
       if constexpr (F32) {
@@ -787,24 +791,59 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
     // computing all of it in every lane, with a third of the VALU work)
     static_assert(LPC >= 4, "a chain's group needs at least three lanes");
     uint32_t r[8];
-    double lg0, lg2, lg6;  // log u01(r0), log u01(r2), log u01(r6)
-    {
-      const int base = gbase;
-      uint32_t q[4];
-      philox4x32_10((uint32_t)step, (uint32_t)(lane & 1), uid0, uid1, a.key0, a.key1, q);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        r[u] = group_bcast<LPC, 0>(q[u], base);
-        r[4 + u] = group_bcast<LPC, 1>(q[u], base);
+    double lg2, lg6;      // log u01(r2), log u01(r6)
+    double xi_t0, xi_sh;  // the Box-Muller pair of (r0, r1)
+    if constexpr (kStash) {
+      // one chain per wavefront: every 64 sweeps each lane makes the random values of one of
+      // the next 64 (both Philox blocks, the three logs, the Box-Muller pair), the same
+      // functions of the same words as below, so the same values; a sweep reads its own by
+      // lane reads, off the sweep's dependent path
+      const int sl = step & (kWave - 1);
+      if (sl == 0) {
+        uint32_t q0[4], q1[4];
+        philox4x32_10((uint32_t)(step + lane), 0u, uid0, uid1, a.key0, a.key1, q0);
+        philox4x32_10((uint32_t)(step + lane), 1u, uid0, uid1, a.key0, a.key1, q1);
+        const double R = sqrt(-2.0 * log(u01(q0[0])));
+        const double th = 2.0 * M_PI * u01(q0[1]);
+        st_xt = R * cos(th);
+        st_xs = R * sin(th);
+        st_l2 = log(u01(q0[2]));
+        st_l6 = log(u01(q1[2]));
+        st_r3 = q0[3];
+        st_r4 = q1[0];
+        st_r5 = q1[1];
+        st_r7 = q1[3];
       }
-      const double lv = log(u01(lane == 0 ? r[0] : lane == 1 ? r[2] : r[6]));
-      lg0 = group_bcast<LPC, 0>(lv, base);
-      lg2 = group_bcast<LPC, 1>(lv, base);
-      lg6 = group_bcast<LPC, 2>(lv, base);
+      r[0] = r[1] = r[2] = r[6] = 0u;  // consumed by the values above
+      r[3] = (uint32_t)__builtin_amdgcn_readlane((int)st_r3, sl);
+      r[4] = (uint32_t)__builtin_amdgcn_readlane((int)st_r4, sl);
+      r[5] = (uint32_t)__builtin_amdgcn_readlane((int)st_r5, sl);
+      r[7] = (uint32_t)__builtin_amdgcn_readlane((int)st_r7, sl);
+      lg2 = lane_value(st_l2, sl);
+      lg6 = lane_value(st_l6, sl);
+      xi_t0 = lane_value(st_xt, sl);
+      xi_sh = lane_value(st_xs, sl);
+    } else {
+      double lg0;  // log u01(r0)
+      {
+        const int base = gbase;
+        uint32_t q[4];
+        philox4x32_10((uint32_t)step, (uint32_t)(lane & 1), uid0, uid1, a.key0, a.key1, q);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          r[u] = group_bcast<LPC, 0>(q[u], base);
+          r[4 + u] = group_bcast<LPC, 1>(q[u], base);
+        }
+        const double lv = log(u01(lane == 0 ? r[0] : lane == 1 ? r[2] : r[6]));
+        lg0 = group_bcast<LPC, 0>(lv, base);
+        lg2 = group_bcast<LPC, 1>(lv, base);
+        lg6 = group_bcast<LPC, 2>(lv, base);
+      }
+      const double R = sqrt(-2.0 * lg0);
+      const double th = 2.0 * M_PI * u01(r[1]);
+      xi_t0 = R * cos(th);
+      xi_sh = R * sin(th);
     }
-    const double R = sqrt(-2.0 * lg0);
-    const double th = 2.0 * M_PI * u01(r[1]);
-    const double xi_t0 = R * cos(th), xi_sh = R * sin(th);
 
     // ---- Gibbs half-step 1: t0 by Metropolis-Hastings
     const double t0p = t0 + md.t0_sd * xi_t0;
