@@ -2,7 +2,8 @@
 
 * fsmp_graph_*: a captured batch replays to bit-identical outputs, several times, with
   eager sampling on the same context, output clearing and synchronisations between the
-  replays;
+  replays (FP64 with the default designs; the FP32-refresh form with its wide groups at
+  capacities 16 and 32);
 * fsmp_set_design / fsmp_autotune: the chosen design per PE capacity is one that exists,
   and a batch run with the tuned designs still agrees with the oracle.
 """
@@ -25,12 +26,22 @@ def _batch(n, seed, preset="batched"):
     return wl, b, synth.kmax_for(b["lam"])
 
 
-def test_graph_replays_equal_eager():
+@pytest.mark.parametrize("form", ["fp64", "fp32_wide"])
+def test_graph_replays_equal_eager(form):
     wl, b, km = _batch(96, 41)
     _, b2, km2 = _batch(40, 42)
     kz = int(km.max())
-    print(f"[case] graph replay n=96 kz={kz} caps={sorted(set(km.tolist()))}", flush=True)
-    smp = gpu_sampler(wl, 200, 100, 2, 9)
+    print(f"[case] graph replay {form} n=96 kz={kz} caps={sorted(set(km.tolist()))}", flush=True)
+    if form == "fp64":
+        smp = gpu_sampler(wl, 200, 100, 2, 9)
+    else:
+        smp = fsmp.Sampler(ser=wl.ser, phi_kind=wl.phi_kind, tau_rise=wl.tau_rise, tau_decay=wl.tau_decay,
+                           t0_min=wl.t0_min, t0_max=wl.t0_max, sigma_eps=wl.sigma_eps, mu_q=wl.mu_q,
+                           sigma_q=wl.sigma_q, n_steps=200, n_chains=2, burn_in=100, seed=9,
+                           precision=fsmp.FSMP_FP32_REFRESH, refresh_M=64)
+        for cap in (16, 32):
+            smp.set_design(cap, fsmp.FSMP_DESIGN_GROUP_DEVMEM_WIDE)
+        assert {16, 32} <= set(km.tolist())
     wave = torch.from_numpy(b["wave"]).cuda()
     ref = to_host(smp.sample(wave, b["offsets"], b["lam"], kmax=km, kz=kz))
     g, out = smp.graph(wave, b["offsets"], b["lam"], kmax=km, kz=kz)
