@@ -97,6 +97,28 @@ def test_set_design_validation():
         smp.set_design(16, 4)
 
 
+def test_set_design_validation_fp32():
+    # the FP32-refresh form: device-memory groups only; its wide groups at capacities 16 and 32
+    wl, _, _ = _batch(2, 1)
+    smp = fsmp.Sampler(ser=wl.ser, phi_kind=wl.phi_kind, tau_rise=wl.tau_rise, tau_decay=wl.tau_decay,
+                       t0_min=wl.t0_min, t0_max=wl.t0_max, sigma_eps=wl.sigma_eps, mu_q=wl.mu_q,
+                       sigma_q=wl.sigma_q, n_steps=10, n_chains=1, burn_in=5, seed=1,
+                       precision=fsmp.FSMP_FP32_REFRESH)
+    for cap in synth.KCAPS:
+        for d in (fsmp.FSMP_DESIGN_GROUP, fsmp.FSMP_DESIGN_LANE):
+            with pytest.raises(RuntimeError):
+                smp.set_design(cap, d)
+    for cap in (16, 32):
+        smp.set_design(cap, fsmp.FSMP_DESIGN_GROUP_DEVMEM_WIDE)
+        assert smp.get_design(cap) == fsmp.FSMP_DESIGN_GROUP_DEVMEM_WIDE
+    for cap in (48, 64, 96, 128, 160, 192):
+        with pytest.raises(RuntimeError):
+            smp.set_design(cap, fsmp.FSMP_DESIGN_GROUP_DEVMEM_WIDE)
+    smp.set_design(0, fsmp.FSMP_DESIGN_GROUP_DEVMEM)
+    smp.set_design(0, fsmp.FSMP_DESIGN_GROUP_DEVMEM_WIDE)  # every capacity that has it; the rest keep theirs
+    assert [smp.get_design(c) for c in synth.KCAPS] == [3, 3] + [2] * 6
+
+
 def test_autotune_keeps_results_correct():
     wl, b, km = _batch(400, 51)
     kz = int(km.max())
