@@ -434,6 +434,28 @@ def timed_steps(smp, one_step, n, warm):
     return (t1 - t0) * 1e3 / n, kernel_ms
 
 
+def serial_kernel_ms(smp, one_step):
+    """one untimed step with the capacity buckets one after another on the caller's stream
+    (the library takes its lane count from GPU_MAX_HW_QUEUES on each call; the HIP runtime
+    read it once at start-up and keeps its queues): the HIP-event time of every launch alone"""
+    import torch
+    prev = os.environ.get("GPU_MAX_HW_QUEUES")
+    os.environ["GPU_MAX_HW_QUEUES"] = "1"
+    try:
+        torch.cuda.synchronize()
+        smp.set_timing(True)
+        one_step()
+        res = {t["name"]: float(t["ms"]) for t in smp.last_timings()}
+        torch.cuda.synchronize()
+    finally:
+        smp.set_timing(False)
+        if prev is None:
+            del os.environ["GPU_MAX_HW_QUEUES"]
+        else:
+            os.environ["GPU_MAX_HW_QUEUES"] = prev
+    return res
+
+
 def precision_study(fsmp, synth, oracle, n_wave, n_steps=1000, refresh_M=64):
     """The high pile-up precision study (lambda ~ U[20, 100], charges N(1, 0.35), 1,024 samples)
     at sigma_eps = 0.05, 0.1, 0.2: per form (FP64, FP32+refresh) the relative error of every
@@ -623,7 +645,15 @@ def main():
                                      "alg_bytes": algorithmic_bytes(work[chain_kcap == chains_of[name]]),
                                      "impl_bytes": 8.0 * float(work[chain_kcap == chains_of[name]][:, 2:4].sum())}
                               for name in sorted(chains_of, key=lambda k: -avg[k])}}
-    print(f"[bench] kernels (mean ms): {json.dumps(avg)}", file=sys.stderr, flush=True)
+    # the same kernel with the chip to itself (the step's launches one after another, one
+    # untimed step after the timed ones): over the concurrent duration above, a launch's
+    # fraction falls as more launches share the chip
+    alone = serial_kernel_ms(smp, one_step)
+    if dom in alone:
+        roofline["alone"] = {"kernel_ms": alone[dom], "achieved": nbytes / (alone[dom] / 1e3) / 1e9,
+                             "frac": nbytes / (alone[dom] / 1e3) / PEAK_HBM,
+                             "by_kernel_ms": {k: alone[k] for k in sorted(chains_of, key=lambda k: -avg[k]) if k in alone}}
+    print(f"[bench] kernels (mean ms): {json.dumps(avg)}; alone: {json.dumps(alone)}", file=sys.stderr, flush=True)
     res = {
         "metric": "waveforms/s and MCMC steps/s at matched posterior accuracy; p99 event latency",
         "value": wps,
