@@ -87,6 +87,10 @@ def parse():
     ap.add_argument("--serve-rates", default="50,100,150,200,250,300,350,400,2000,5000,10000,20000",
                     help="comma-separated event rates (Hz)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--hw-queues", type=int, default=8,
+                    help="hardware queues the process asks HIP for (GPU_MAX_HW_QUEUES, read once when the "
+                         "runtime starts; HIP's default is 4): with 8 every capacity bucket of a step runs on a "
+                         "lane of its own; 0 leaves the environment as it is")
     ap.add_argument("--legs", default="fp32,batched,lucy,mcp",
                     help="comma-separated extra legs to run (fp32, batched, lucy, mcp; empty: none)")
     ap.add_argument("--lucy-iter", type=int, default=2000, help="Lucy-Richardson iterations of the init stage (0: skip)")
@@ -531,6 +535,9 @@ def precision_study(fsmp, synth, oracle, n_wave, n_steps=1000, refresh_M=64):
 
 def main():
     args = parse()
+    if args.hw_queues > 0:
+        # before anything starts the HIP runtime; the library sizes its lanes from the same variable
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               f"(the sampler has no cross-GPU path: waveforms are independent)", file=sys.stderr)
@@ -613,6 +620,7 @@ def main():
         print("[bench] counter run done", file=sys.stderr, flush=True)
         return
 
+    alone = serial_kernel_ms(smp, one_step)
     ms_per_step, kernel_ms = timed_steps(smp, one_step, args.steps, args.warmup)
     print("[bench] timed steps done", file=sys.stderr, flush=True)
     wps = n_wave / (ms_per_step / 1e3)
@@ -646,9 +654,8 @@ def main():
                                      "impl_bytes": 8.0 * float(work[chain_kcap == chains_of[name]][:, 2:4].sum())}
                               for name in sorted(chains_of, key=lambda k: -avg[k])}}
     # the same kernel with the chip to itself (the step's launches one after another, one
-    # untimed step after the timed ones): over the concurrent duration above, a launch's
+    # untimed step before the timed ones): over the concurrent duration above, a launch's
     # fraction falls as more launches share the chip
-    alone = serial_kernel_ms(smp, one_step)
     if dom in alone:
         roofline["alone"] = {"kernel_ms": alone[dom], "achieved": nbytes / (alone[dom] / 1e3) / 1e9,
                              "frac": nbytes / (alone[dom] / 1e3) / PEAK_HBM,
