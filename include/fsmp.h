@@ -335,9 +335,12 @@ size_t fsmp_workspace_bytes(const fsmp_ctx *ctx, const fsmp_batch *batch);
  * FSMP_ENOTSUP if a kmax exceeds 192 or the SER support does not fit a kernel.  The work is
  * enqueued on `hip_stream` (a hipStream_t; NULL = the null stream) and is complete when that
  * stream is: the PE-capacity buckets of the batch run concurrently, on `hip_stream` and on
- * the context's own side streams (GPU_MAX_HW_QUEUES lanes in all, default 4), forked from and
- * joined back into `hip_stream` with events; buckets are dealt to the lanes by estimated cost
- * (after fsmp_autotune, its trial times of the chosen designs).  The calls of one context share its workspace: give them
+ * the context's own side streams (GPU_MAX_HW_QUEUES lanes in all, default 4, read at each
+ * call; HIP reads the same variable once when it starts, and each lane needs a hardware queue
+ * of its own, so a process that sets it to 8 before HIP starts runs every bucket on a lane of
+ * its own), forked from and joined back into `hip_stream` with events; with fewer lanes than
+ * buckets, buckets are dealt to the lanes by estimated cost (after fsmp_autotune, its trial
+ * times of the chosen designs).  The calls of one context share its workspace: give them
  * one stream, or order their streams, so that two calls never run on the device at once. */
 fsmp_status fsmp_sample(fsmp_ctx *ctx, const fsmp_batch *batch, const fsmp_samples *out, void *hip_stream);
 
