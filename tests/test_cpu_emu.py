@@ -10,7 +10,8 @@ buffers that AddressSanitizer watches, each device buffer its own allocation of 
 library asks for and each launch's LDS the size it asks for: an access outside any of them, in
 host or kernel code, ends the run with a report.  The lane-group kernels run there too: their shuffles, DPP moves, ballots and
 wavefront barriers go through a per-wavefront exchange, so the device-memory designs (narrow
-and wide lane groups) are checked the same way, up to capacity 160."""
+and wide lane groups, up to capacity 160) and the lane groups with G^-1 in LDS (16-48) are
+checked the same way."""
 import os
 import shutil
 import subprocess
@@ -173,6 +174,25 @@ def test_device_memory_groups_on_the_cpu_under_asan(tmp_path, design):
     np.testing.assert_array_equal(g["zdraw"], o.zdraw)
     np.testing.assert_allclose(g["trace"], o.trace, rtol=1e-9, atol=1e-9)
     np.testing.assert_allclose(g["qdraw"], o.qdraw, rtol=1e-7, atol=1e-8, equal_nan=True)
+
+
+def test_lds_groups_on_the_cpu_under_asan(tmp_path):
+    # lane groups with G^-1 in LDS at capacities 16-64 (one chain per wavefront at 48 and 64,
+    # where each lane makes the random values of one of the next 64 sweeps): 80 sweeps, so
+    # the values of a second block of 64 are made and read too
+    wl = synth.PRESETS["batched"]
+    b = synth.generate(wl, n_wave=16, seed=14)
+    km = synth.kmax_for(b["lam"]).astype(np.int32)
+    assert {16, 32} <= set(km.tolist()) and km.max() <= 64
+    n_steps, burn, n_chains, seed = 80, 40, 2, 8
+    g = _run_emu(str(tmp_path), wl, b["wave"], b["offsets"], b["lam"], km, n_steps, burn, n_chains, seed,
+                 [fsmp.FSMP_DESIGN_GROUP] * 4 + [-1] * 4, record_flags=fsmp.FSMP_REC_LOG)
+    o = oracle.run(oracle_params(wl), b["wave"], b["offsets"], b["lam"], n_chains, n_steps, burn, seed,
+                   int(km.max()), kmax=km, log=True)
+    parted = compare_chains(g, o)
+    assert len(parted) == 0, parted
+    for f in ("move", "flags", "j", "g"):
+        np.testing.assert_array_equal(g["log"][f], o.log[f])
 
 
 # the five-Gaussian MCP-PMT charge law (weights, means, sigmas in units of the SER amplitude)
