@@ -22,6 +22,8 @@
 // counter = (step, block, uid lo, uid hi).  Words of one step: r0,r1 Box-Muller pair
 // (t0 step, update shift), r2 t0 accept, r3 move, r4 (r5) index or 53-bit birth
 // uniform, r6 jump accept, r7 the mixture component of a born or updated PE (MCP-PMT law).
+// Where a chain owns a whole wavefront, its lanes make these values 64 sweeps at a time,
+// lane l those of sweep 64 m + l, and each sweep reads its own by lane reads.
 
 #include <math.h>
 
