@@ -22,8 +22,9 @@
 // counter = (step, block, uid lo, uid hi).  Words of one step: r0,r1 Box-Muller pair
 // (t0 step, update shift), r2 t0 accept, r3 move, r4 (r5) index or 53-bit birth
 // uniform, r6 jump accept, r7 the mixture component of a born or updated PE (MCP-PMT law).
-// Where a chain owns a whole wavefront, its lanes make these values 64 sweeps at a time,
-// lane l those of sweep 64 m + l, and each sweep reads its own by lane reads.
+// Where a chain owns a whole wavefront (and in the FP64 form's 32-lane groups), its lanes
+// make these values LPC sweeps at a time, lane l of its group those of sweep LPC m + l, and
+// each sweep reads its own by lane reads.
 
 #include <math.h>
 
@@ -107,6 +108,25 @@ __device__ inline double lane_value(double v, int L) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), L);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), L);
   return __hiloint2double(hi, lo);
+}
+
+// v of lane L of the caller's group of W lanes (group index grp; W >= 16, so at most four
+// groups): one lane read per group, the caller's own picked by a select
+template <int W>
+__device__ inline uint32_t group_lane_u32(uint32_t v, int L, int grp) {
+  uint32_t out = (uint32_t)__builtin_amdgcn_readlane((int)v, L);
+#pragma unroll
+  for (int g = 1; g < kWave / W; ++g) {
+    const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)v, g * W + L);
+    out = grp == g ? x : out;
+  }
+  return out;
+}
+template <int W>
+__device__ inline double group_lane(double v, int L, int grp) {
+  const uint32_t lo = group_lane_u32<W>((uint32_t)__double2loint(v), L, grp);
+  const uint32_t hi = group_lane_u32<W>((uint32_t)__double2hiint(v), L, grp);
+  return __hiloint2double((int)hi, (int)lo);
 }
 
 // The value of lane K of the caller's group of W lanes (groups aligned to W, every lane of
@@ -760,8 +780,9 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
       WAVE_SYNC();
     }
   }
-  // with one chain per wavefront, lane l keeps the random values of sweep 64 m + l
-  constexpr bool kStash = LPC == kWave;
+  // with one chain per wavefront, or in the FP64 form's 32-lane groups, lane l of a chain's
+  // group keeps the random values of its sweep LPC m + l
+  constexpr bool kStash = LPC == kWave || (LPC == 32 && !F32 && !MCP);
   uint32_t st_r3 = 0, st_r4 = 0, st_r5 = 0, st_r7 = 0;
   double st_l2 = 0.0, st_l6 = 0.0, st_xt = 0.0, st_xs = 0.0;
   for (int step = 0; step < n_steps; ++step) {
@@ -796,11 +817,12 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
     double lg2, lg6;      // log u01(r2), log u01(r6)
     double xi_t0, xi_sh;  // the Box-Muller pair of (r0, r1)
     if constexpr (kStash) {
-      // one chain per wavefront: every 64 sweeps each lane makes the random values of one of
-      // the next 64 (both Philox blocks, the three logs, the Box-Muller pair), the same
-      // functions of the same words as below, so the same values; a sweep reads its own by
-      // lane reads, off the sweep's dependent path
-      const int sl = step & (kWave - 1);
+      // every LPC sweeps each lane of a chain's group makes the random values of one of the
+      // group's next LPC sweeps (both Philox blocks, the three logs, the Box-Muller pair), the
+      // same functions of the same words as below, so the same values; a sweep reads its own
+      // by lane reads (one per group of the wavefront, its own picked), off the sweep's
+      // dependent path
+      const int sl = step & (LPC - 1);
       if (sl == 0) {
         uint32_t q0[4], q1[4];
         philox4x32_10((uint32_t)(step + lane), 0u, uid0, uid1, a.key0, a.key1, q0);
@@ -817,14 +839,14 @@ __global__ void __launch_bounds__(kWave *WPB) __attribute__((amdgpu_waves_per_eu
         st_r7 = q1[3];
       }
       r[0] = r[1] = r[2] = r[6] = 0u;  // consumed by the values above
-      r[3] = (uint32_t)__builtin_amdgcn_readlane((int)st_r3, sl);
-      r[4] = (uint32_t)__builtin_amdgcn_readlane((int)st_r4, sl);
-      r[5] = (uint32_t)__builtin_amdgcn_readlane((int)st_r5, sl);
-      r[7] = (uint32_t)__builtin_amdgcn_readlane((int)st_r7, sl);
-      lg2 = lane_value(st_l2, sl);
-      lg6 = lane_value(st_l6, sl);
-      xi_t0 = lane_value(st_xt, sl);
-      xi_sh = lane_value(st_xs, sl);
+      r[3] = group_lane_u32<LPC>(st_r3, sl, grp);
+      r[4] = group_lane_u32<LPC>(st_r4, sl, grp);
+      r[5] = group_lane_u32<LPC>(st_r5, sl, grp);
+      r[7] = group_lane_u32<LPC>(st_r7, sl, grp);
+      lg2 = group_lane<LPC>(st_l2, sl, grp);
+      lg6 = group_lane<LPC>(st_l6, sl, grp);
+      xi_t0 = group_lane<LPC>(st_xt, sl, grp);
+      xi_sh = group_lane<LPC>(st_xs, sl, grp);
     } else {
       double lg0;  // log u01(r0)
       {
