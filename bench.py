@@ -306,10 +306,10 @@ def step_traffic(workload, kernels, ms_per_step):
 def serving_run(fsmp, synth, pool, rate, n_events, precision, seed=0, n_streams=4, max_batch_wave=20000):
     """Poisson arrivals of trigger events (500-2000 channels drawn from a pool of synthetic
     channels, 1,024 samples each) submitted to the serving loop as they arrive; latency
-    percentiles, throughput, and whether the rate is sustained: the run ends within 5% of the
-    last arrival plus the median latency (a server that keeps pace drains one event after the
-    last arrival), and the queue does not grow (the last third of the events waits at most
-    1.25x as long as the first third, plus 20 ms for the jitter of short waits).  The arrival
+    percentiles, throughput, and whether the run kept pace: it ends within 5% of the last
+    arrival plus the median latency (a server that keeps pace drains one event after the last
+    arrival), and the queue does not grow (the last third of the events waits at most 1.25x
+    as long as the first third, plus 20 ms for the jitter of short waits).  The arrival
     window is about 1.5 s (n_events to 3 n_events events), so an overload of a few percent
     shows as a growing latency."""
     wl = synth.PRESETS["serving"]
@@ -356,13 +356,13 @@ def serving_run(fsmp, synth, pool, rate, n_events, precision, seed=0, n_streams=
     third = max(1, n_events // 3)
     served = waves / t_end
     offered = waves / max(arrive[-1], 1e-9)
-    sustained = bool(t_end <= 1.05 * (arrive[-1] + np.percentile(l, 50))
-                     and l[-third:].mean() <= 1.25 * l[:third].mean() + 0.020)
+    keeps_pace = bool(t_end <= 1.05 * (arrive[-1] + np.percentile(l, 50))
+                      and l[-third:].mean() <= 1.25 * l[:third].mean() + 0.020)
     return {"rate_hz": rate, "events": n_events, "waveforms": waves, "precision": "fp32+refresh" if precision else "fp64",
             "p50_ms": float(np.percentile(l, 50) * 1e3), "p99_ms": float(np.percentile(l, 99) * 1e3),
             "arrival_window_ms": float(arrive[-1] * 1e3), "drain_ms": float((t_end - arrive[-1]) * 1e3),
             "mean_ms_first_third": float(l[:third].mean() * 1e3), "mean_ms_last_third": float(l[-third:].mean() * 1e3),
-            "waveforms_per_s": served, "offered_waveforms_per_s": offered, "sustained": sustained}
+            "waveforms_per_s": served, "offered_waveforms_per_s": offered, "keeps_pace": keeps_pace}
 
 
 def serving_pool(synth, n=20000, seed=5):
@@ -372,18 +372,27 @@ def serving_pool(synth, n=20000, seed=5):
 
 
 def serving_study(fsmp, synth, rates, n_events):
-    """both precision forms over the rates; per form the largest sustained rate and the p50 /
-    p99 latency there"""
+    """both precision forms over the rates; per form the saturation throughput (the most
+    waveforms/s any of its runs served), and the largest sustained rate with the p50 / p99
+    latency there.  A rate is sustained if its run kept pace (serving_run) and it offers at
+    most 95% of the saturation throughput: a queue fed faster than it is served grows without
+    bound, however slowly that shows within one run."""
     pool = serving_pool(synth)
-    runs, best = [], {}
+    runs, best, sat = [], {}, {}
     for prec in (fsmp.FSMP_FP64, fsmp.FSMP_FP32_REFRESH):
+        mine = []
         for rate in rates:
             r = serving_run(fsmp, synth, pool, rate, n_events, prec)
             print(f"[bench] serving {json.dumps(r)}", file=sys.stderr, flush=True)
-            runs.append(r)
+            mine.append(r)
+        top = max(r["waveforms_per_s"] for r in mine)
+        for r in mine:
+            r["sustained"] = bool(r["keeps_pace"] and r["offered_waveforms_per_s"] <= 0.95 * top)
             if r["sustained"] and r["rate_hz"] > best.get(r["precision"], {}).get("rate_hz", -1):
                 best[r["precision"]] = {k: r[k] for k in ("rate_hz", "p50_ms", "p99_ms", "waveforms_per_s")}
-    return {"runs": runs, "largest_sustained": best}
+        sat[mine[0]["precision"]] = top
+        runs += mine
+    return {"runs": runs, "saturation_waveforms_per_s": sat, "largest_sustained": best}
 
 
 def cpu_model():
